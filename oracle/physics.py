@@ -1,0 +1,199 @@
+"""Pointwise physics in entropy variables (oracle).
+
+Every function accepts complex arrays (so that the element Jacobian can be
+taken by complex step) and broadcasts over leading axes.  The state vector
+has m = d + 2 components; the last axis of ``v`` / ``u`` is the component.
+
+References to the paper:
+
+* conservation variables, inviscid flux F and the perfect-gas pressure:
+  the compressible Euler section (flux equation and the EOS after it);
+* viscous flux G, Newtonian stress with beta = 0 and Fourier heat flux with
+  kappa = c_p mu / Pr: the compressible Navier-Stokes section;
+* entropy pair H = -rho s, F_H = -rho s V with s = log(p / rho^gamma) - s0
+  and the entropy variables v(u): the section on entropy pairs and
+  symmetrization (the map equation there);
+* G in entropy variables, G(v, q) = G(u(v), grad u) with grad u = A0(v) q:
+  the NS hybridized DG section;
+* trace flux f_hat = 1/2 (F(v_hat) + F(v)).n + 1/2 sigma (v - v_hat): the
+  numerical flux equation of the Euler hybridized DG section;
+* symmetric Lax-Friedrichs stabilization sigma = lambda_max(v*) A0(v*) with
+  v* = v_hat: its definition in the stability section and the choice stated
+  at the start of the numerical examples;
+* viscous trace flux g_hat = G(v_hat, q).n: second option of the viscous
+  numerical flux equations, the one used in the numerical examples.
+
+Gas constant R = 1 (T = p / rho), c_v = 1/(gamma-1), c_p = gamma/(gamma-1),
+s0 = 0.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def abs_cs(x):
+    """|x| continued analytically for complex step; derivative +1 at 0."""
+    return np.where(np.real(x) >= 0, x, -x)
+
+
+def split_v(v):
+    m = v.shape[-1]
+    return v[..., 0], v[..., 1:m - 1], v[..., m - 1]
+
+
+def prim_of_v(v, gamma):
+    """Density, velocity (..., d) and pressure from entropy variables."""
+    v1, w, vm = split_v(v)
+    s = gamma - v1 + (w * w).sum(-1) / (2.0 * vm)
+    rho = ((gamma - 1.0) / (-vm) * np.exp(-s)) ** (1.0 / (gamma - 1.0))
+    p = (gamma - 1.0) * rho / (-vm)
+    V = -w / vm[..., None]
+    return rho, V, p
+
+
+def u_of_v(v, gamma):
+    """Conservation variables u(v) (inverse of the entropy-variable map)."""
+    rho, V, p = prim_of_v(v, gamma)
+    rE = p / (gamma - 1.0) + 0.5 * rho * (V * V).sum(-1)
+    return np.concatenate([rho[..., None], rho[..., None] * V, rE[..., None]], axis=-1)
+
+
+def prim_of_u(u, gamma):
+    m = u.shape[-1]
+    rho = u[..., 0]
+    V = u[..., 1:m - 1] / rho[..., None]
+    p = (gamma - 1.0) * (u[..., m - 1] - 0.5 * rho * (V * V).sum(-1))
+    return rho, V, p
+
+
+def u_of_prim(rho, V, p, gamma):
+    rE = p / (gamma - 1.0) + 0.5 * rho * (V * V).sum(-1)
+    return np.concatenate([rho[..., None], rho[..., None] * V, rE[..., None]], axis=-1)
+
+
+def v_of_u(u, gamma):
+    """Entropy variables from the paper's closed form for H = -rho s (s0 = 0)."""
+    m = u.shape[-1]
+    rho, V, p = prim_of_u(u, gamma)
+    s = np.log(p / rho ** gamma)
+    rE = u[..., m - 1]
+    v1 = (gamma - 1.0) * (-s / (gamma - 1.0) + (gamma + 1.0) / (gamma - 1.0) - rE / p)
+    w = (gamma - 1.0) * u[..., 1:m - 1] / p[..., None]
+    vm = -(gamma - 1.0) * rho / p
+    return np.concatenate([v1[..., None], w, vm[..., None]], axis=-1)
+
+
+def v_of_prim(rho, V, p, gamma):
+    return v_of_u(u_of_prim(rho, V, p, gamma), gamma)
+
+
+def entropy_pair(v, gamma):
+    """Generalized entropy H = -rho s and entropy flux F_H = -rho s V."""
+    rho, V, p = prim_of_v(v, gamma)
+    s = np.log(p / rho ** gamma)
+    H = -rho * s
+    return H, H[..., None] * V
+
+
+def A0(v, gamma):
+    """Closed form of dU/dV for H = -rho s (symmetric positive definite).
+
+    The paper defers the expression to its reference on symmetrization; this
+    is that matrix written with E = rho E / rho, H_t = E + p / rho and
+    c^2 = gamma p / rho, scaled by 1/(gamma - 1).  Pinned in tests against the
+    complex-step derivative of ``u_of_v``.
+    """
+    rho, V, p = prim_of_v(v, gamma)
+    d = V.shape[-1]
+    m = d + 2
+    E = p / ((gamma - 1.0) * rho) + 0.5 * (V * V).sum(-1)
+    Ht = E + p / rho
+    c2 = gamma * p / rho
+    out = np.zeros(v.shape[:-1] + (m, m), dtype=np.result_type(v, float))
+    out[..., 0, 0] = rho
+    out[..., 0, 1:m - 1] = rho[..., None] * V
+    out[..., 1:m - 1, 0] = rho[..., None] * V
+    out[..., 0, m - 1] = rho * E
+    out[..., m - 1, 0] = rho * E
+    out[..., 1:m - 1, 1:m - 1] = rho[..., None, None] * V[..., :, None] * V[..., None, :] \
+        + p[..., None, None] * np.eye(d)
+    out[..., 1:m - 1, m - 1] = (rho * Ht)[..., None] * V
+    out[..., m - 1, 1:m - 1] = (rho * Ht)[..., None] * V
+    out[..., m - 1, m - 1] = rho * Ht * Ht - c2 * p / (gamma - 1.0)
+    return out / (gamma - 1.0)
+
+
+def flux_F(v, gamma):
+    """Inviscid flux F(u(v)), shape (..., m, d)."""
+    rho, V, p = prim_of_v(v, gamma)
+    d = V.shape[-1]
+    m = d + 2
+    rE = p / (gamma - 1.0) + 0.5 * rho * (V * V).sum(-1)
+    F = np.zeros(v.shape[:-1] + (m, d), dtype=np.result_type(v, float))
+    F[..., 0, :] = rho[..., None] * V
+    F[..., 1:m - 1, :] = rho[..., None, None] * V[..., :, None] * V[..., None, :] \
+        + p[..., None, None] * np.eye(d)
+    F[..., m - 1, :] = V * (rE + p)[..., None]
+    return F
+
+
+def flux_G(v, q, gamma, mu, Pr):
+    """Viscous flux G(v, q), shape (..., m, d); q has shape (..., m, d).
+
+    grad u = A0(v) q per direction, then velocity and temperature gradients
+    from grad u, stress tau with beta = 0 and heat flux f = -kappa grad T.
+    """
+    rho, V, p = prim_of_v(v, gamma)
+    d = V.shape[-1]
+    m = d + 2
+    gu = np.einsum("...ab,...bk->...ak", A0(v, gamma), q)        # (..., m, d)
+    grho = gu[..., 0, :]
+    gV = (gu[..., 1:m - 1, :] - V[..., :, None] * grho[..., None, :]) / rho[..., None, None]
+    gp = (gamma - 1.0) * (gu[..., m - 1, :] - np.einsum("...i,...ik->...k", V, gu[..., 1:m - 1, :])
+                          + 0.5 * (V * V).sum(-1)[..., None] * grho)
+    T = p / rho
+    gT = (gp - T[..., None] * grho) / rho[..., None]
+    div = np.einsum("...ii->...", gV)
+    tau = mu * (gV + np.swapaxes(gV, -1, -2) - (2.0 / 3.0) * div[..., None, None] * np.eye(d))
+    kappa = gamma / (gamma - 1.0) * mu / Pr
+    f = -kappa * gT
+    G = np.zeros(v.shape[:-1] + (m, d), dtype=np.result_type(v, q, float))
+    G[..., 1:m - 1, :] = -tau
+    G[..., m - 1, :] = -(np.einsum("...i,...ij->...j", V, tau) - f)
+    return G
+
+
+def lam_max(v, n, gamma):
+    """Largest |eigenvalue| of A_n: |V.n| + c (n unit)."""
+    rho, V, p = prim_of_v(v, gamma)
+    vn = (V * n).sum(-1)
+    return abs_cs(vn) + np.sqrt(gamma * p / rho)
+
+
+def sigma_slf(vh, n, gamma):
+    """Symmetric Lax-Friedrichs stabilization lambda_max(v_hat) A0(v_hat)."""
+    return lam_max(vh, n, gamma)[..., None, None] * A0(vh, gamma)
+
+
+def fhat(vh, v, n, gamma):
+    """Inviscid trace flux with sigma_SLF evaluated at v* = v_hat."""
+    Fn = np.einsum("...cj,...j->...c", flux_F(vh, gamma) + flux_F(v, gamma), n)
+    sig = sigma_slf(vh, n, gamma)
+    return 0.5 * Fn + 0.5 * np.einsum("...ab,...b->...a", sig, v - vh)
+
+
+def ghat(vh, q, n, gamma, mu, Pr):
+    """Viscous trace flux G(v_hat, q).n."""
+    return np.einsum("...cj,...j->...c", flux_G(vh, q, gamma, mu, Pr), n)
+
+
+def jac_cs(f, x, h=1e-30):
+    """Complex-step Jacobian of f at real x: (..., out, in)."""
+    x = np.asarray(x, dtype=complex)
+    n = x.shape[-1]
+    cols = []
+    for i in range(n):
+        xp = x.copy()
+        xp[..., i] += 1j * h
+        cols.append(np.imag(f(xp)) / h)
+    return np.stack(cols, axis=-1)

@@ -1,0 +1,145 @@
+"""Pins of the oracle's pointwise physics.
+
+* U <-> V round trip and the closed-form A0 against the complex-step dU/dV
+  (entropy variables of the section on entropy pairs and symmetrization);
+* symmetrization: A0 SPD, A_n A0 symmetric (the stability section's notation);
+* Lemma 1 / Corollary 3 (jump entropy identity) pointwise;
+* the dissipation identity of the viscous flux written with grad v
+  (the paper's identity for q^T K q in terms of Phi / T and |grad T|^2),
+  with T and V gradients taken from q directly, not through A0;
+* complex step against central finite differences.
+"""
+import numpy as np
+import pytest
+
+from oracle import physics as P
+
+GAM = 1.4
+
+
+def _states(rng, n, d):
+    rho = rng.uniform(0.3, 3.0, n)
+    V = rng.normal(size=(n, d)) * rng.uniform(0.1, 2.0, (n, 1))
+    p = rng.uniform(0.3, 5.0, n)
+    return rho, V, p
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_round_trip_and_A0(d):
+    rng = np.random.default_rng(10 + d)
+    rho, V, p = _states(rng, 50, d)
+    u = P.u_of_prim(rho, V, p, GAM)
+    v = P.v_of_u(u, GAM)
+    assert np.abs(P.u_of_v(v, GAM) - u).max() <= 1e-14 * np.abs(u).max()
+    # printed closed form of v (section on entropy pairs): v_m = -(gamma-1) rho / p
+    assert np.allclose(v[:, -1], -(GAM - 1) * rho / p, rtol=1e-15)
+    assert np.allclose(v[:, 1:-1], (GAM - 1) * rho[:, None] * V / p[:, None], rtol=1e-14)
+    J = P.jac_cs(lambda x: P.u_of_v(x, GAM), v)
+    A0 = P.A0(v, GAM)
+    assert np.abs(J - A0).max() <= 1e-14 * np.abs(J).max()
+    assert np.abs(A0 - np.swapaxes(A0, 1, 2)).max() <= 1e-14 * np.abs(A0).max()
+    assert np.all(np.linalg.eigvalsh(A0) > 0)
+    # A0 times dv/du is the identity
+    dvdu = P.jac_cs(lambda x: P.v_of_u(x, GAM), u)
+    assert np.abs(np.einsum("nab,nbc->nac", A0, dvdu) - np.eye(d + 2)).max() < 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_symmetrized_flux_jacobian(d):
+    rng = np.random.default_rng(20 + d)
+    rho, V, p = _states(rng, 30, d)
+    v = P.v_of_prim(rho, V, p, GAM)
+    n = rng.normal(size=(30, d))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    An = P.jac_cs(lambda x: np.einsum("...cj,...j->...c", P.flux_F(x, GAM), n), v)
+    assert np.abs(An - np.swapaxes(An, 1, 2)).max() <= 1e-13 * np.abs(An).max()
+    # lambda_max is the spectral radius of A_n = dF_n/du
+    Au = P.jac_cs(lambda x: np.einsum("...cj,...j->...c", P.flux_F(P.v_of_u(x, GAM), GAM), n),
+                  P.u_of_v(v, GAM))
+    rad = np.abs(np.linalg.eigvals(Au)).max(1)
+    assert np.allclose(rad, np.real(P.lam_max(v, n, GAM)), rtol=1e-10)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_entropy_flux_identity(d):
+    # dF_H/dv = v^T dF/dv (the identity defining the entropy pair, written in v)
+    rng = np.random.default_rng(30 + d)
+    rho, V, p = _states(rng, 20, d)
+    v = P.v_of_prim(rho, V, p, GAM)
+    for j in range(d):
+        dFH = P.jac_cs(lambda x: P.entropy_pair(x, GAM)[1][..., j][..., None], v)[:, 0]
+        dF = P.jac_cs(lambda x: P.flux_F(x, GAM)[..., j], v)
+        assert np.abs(dFH - np.einsum("na,nab->nb", v, dF)).max() < 1e-12 * np.abs(dFH).max()
+
+
+def _gauss01(nq):
+    x, w = np.polynomial.legendre.leggauss(nq)
+    return 0.5 * (x + 1), 0.5 * w
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_lemma1_jump_entropy_identity(d):
+    """-[F_H.n] + 1/2 (v1+v2)^T [F_n] = 1/2 dv^T Sigma(v1,v2;n) dv, straight path."""
+    rng = np.random.default_rng(40 + d)
+    th, wt = _gauss01(200)
+    for _ in range(20):
+        r1, V1, p1 = _states(rng, 1, d)
+        r2, V2, p2 = _states(rng, 1, d)
+        v1, v2 = P.v_of_prim(r1, V1, p1, GAM)[0], P.v_of_prim(r2, V2, p2, GAM)[0]
+        n = rng.normal(size=d)
+        n /= np.linalg.norm(n)
+        Fn = lambda x: np.einsum("...cj,j->...c", P.flux_F(x, GAM), n)
+        FHn = lambda x: P.entropy_pair(x, GAM)[1] @ n
+        dv = v2 - v1
+        path = v1[None, :] + th[:, None] * dv[None, :]
+        An = P.jac_cs(Fn, path)
+        Sigma = np.einsum("t,tab->ab", wt * (1 - 2 * th), An)
+        lhs = -(FHn(v2[None])[0] - FHn(v1[None])[0]) + 0.5 * (v1 + v2) @ (Fn(v2[None])[0] - Fn(v1[None])[0])
+        rhs = 0.5 * dv @ Sigma @ dv
+        scale = abs(FHn(v2[None])[0]) + abs(FHn(v1[None])[0]) + abs(rhs)
+        assert abs(lhs - rhs) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_viscous_dissipation_identity(d):
+    """-sum q:G(v,q) = (gamma-1) (Phi/T + kappa |grad T|^2 / T^2) with q = grad v."""
+    rng = np.random.default_rng(50 + d)
+    mu, Pr = 0.37, 0.72
+    rho, V, p = _states(rng, 40, d)
+    v = P.v_of_prim(rho, V, p, GAM)
+    q = rng.normal(size=(40, d + 2, d))
+    G = P.flux_G(v, q, GAM, mu, Pr)
+    lhs = -(q * G).sum((1, 2))
+    # primitive gradients straight from grad v: T = -(gamma-1)/v_m, V = -w / v_m
+    vm, w = v[:, -1], v[:, 1:-1]
+    T = -(GAM - 1) / vm
+    gT = (GAM - 1) * q[:, -1, :] / vm[:, None] ** 2
+    gV = -q[:, 1:-1, :] / vm[:, None, None] + w[:, :, None] * q[:, -1, None, :] / vm[:, None, None] ** 2
+    div = np.einsum("nii->n", gV)
+    tau = mu * (gV + gV.transpose(0, 2, 1) - 2.0 / 3.0 * div[:, None, None] * np.eye(d))
+    Phi = (tau * gV).sum((1, 2))
+    kappa = GAM / (GAM - 1) * mu / Pr
+    rhs = (GAM - 1) * (Phi / T + kappa * (gT ** 2).sum(1) / T ** 2)
+    assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(rhs).max()
+    # G is linear in q and annihilates the mass row
+    assert np.abs(G[:, 0, :]).max() == 0.0
+    G2 = P.flux_G(v, 2.0 * q, GAM, mu, Pr)
+    assert np.allclose(G2, 2 * G, rtol=1e-14, atol=0)
+
+
+def test_complex_step_matches_finite_differences():
+    rng = np.random.default_rng(60)
+    rho, V, p = _states(rng, 5, 3)
+    v = P.v_of_prim(rho, V, p, GAM)
+    n = np.array([0.3, -0.5, 0.81])
+    n /= np.linalg.norm(n)
+    vh = v + 0.01 * rng.normal(size=v.shape) * np.abs(v)
+    f = lambda x: P.fhat(x, v, n, GAM)
+    Jc = P.jac_cs(f, vh)
+    Jf = np.empty_like(Jc)
+    for i in range(5):
+        h = 1e-6 * max(1.0, abs(vh[0, i]))
+        e = np.zeros(5)
+        e[i] = h
+        Jf[:, :, i] = (f(vh + e) - f(vh - e)) / (2 * h)
+    assert np.abs(Jc - Jf).max() <= 1e-6 * np.abs(Jc).max()

@@ -1,0 +1,50 @@
+"""Input generators: the paper's analytic states and mesh conformity."""
+import numpy as np
+
+from workloads import configs as C
+from workloads import fields as F
+from workloads import meshes as M
+
+
+def test_shu_vortex_radial_equilibrium():
+    """dp/dr = rho u_theta^2 / r holds with the squared Mach number in the density law."""
+    f = F.ShuVortex(psi=5.0, mach=0.5, L=0.1, center=(0.5, 0.5))
+    r = np.linspace(0.005, 0.3, 50)
+    x = np.stack([0.5 + r, 0.5 + 0 * r])
+    prim, grad = f.prim_and_grad(x)
+    rho, vx, vy, p = prim
+    dpdr = grad[3, 0]                     # along +x from the centre
+    # relative to the uniform stream, the swirl is vy at these points
+    assert np.allclose(dpdr, rho * vy ** 2 / r, rtol=1e-10, atol=1e-12)
+
+
+def test_tgv_initial_state():
+    f = F.TaylorGreen(mach=0.1)
+    x = np.random.default_rng(0).uniform(0, 2 * np.pi, (3, 20))
+    prim, grad = f.prim_and_grad(x)
+    assert np.allclose(prim[0], 1.0)
+    assert np.allclose(f.p0, 1 / (1.4 * 0.01))
+    # incompressible initial velocity: div V = 0
+    assert np.abs(grad[1, 0] + grad[2, 1] + grad[3, 2]).max() < 1e-13
+
+
+def test_periodic_fields_are_periodic():
+    wl = C.ns3d_hex(n=2)
+    nf = wl.noisy_field()
+    x = np.random.default_rng(1).uniform(0, 2 * np.pi, (3, 10))
+    a = nf.prim(x.astype(complex))
+    b = nf.prim((x + 2 * np.pi * np.array([1, 0, 0])[:, None]).astype(complex))
+    assert np.allclose(a, b, rtol=1e-12)
+
+
+def test_meshes_conforming_and_counts():
+    m = M.hex_cube(4, 0.05, 0)
+    tmap, nt = M.trace_map(m, 2, "hdg")
+    assert nt == 3 * 64 * 9                     # 3 faces per periodic hex
+    counts = np.bincount(tmap.ravel(), minlength=nt)
+    assert np.all(counts == 2)                  # every HDG trace node seen by two elements
+    nb, nbf = M.face_neighbors(m, 2)
+    assert np.all(nb >= 0)
+    t = M.tri_square(8, 0.1, 1)
+    tm, nt = M.trace_map(t, 2, "hdg")
+    assert nt == 208 * 3 and t.boundary.sum() == 32
