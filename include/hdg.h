@@ -1,0 +1,178 @@
+/*
+ * hdg.h -- C ABI of the entropy-variable hybridized DG hot path on MI355X (gfx950).
+ *
+ * Method: Fernandez, Nguyen & Peraire, "Entropy-stable hybridized discontinuous
+ * Galerkin methods for the compressible Euler and Navier-Stokes equations".
+ * For every element the library evaluates, at volume and face quadrature points,
+ * the residual of the hybridized DG weak forms in entropy variables (section on
+ * the Euler discretization: element and trace equations; section on the
+ * Navier-Stokes discretization: gradient, element and trace equations) and its
+ * exact Newton Jacobian, factors the dense local block and forms the Schur
+ * complement onto the trace unknowns (the local elimination noted after both
+ * weak forms: only v_hat is globally coupled).  Numerical flux: the inviscid
+ * trace flux f_hat = 1/2 (F(v_hat) + F(v)).n + 1/2 sigma (v - v_hat) with the
+ * symmetric Lax-Friedrichs matrix sigma = lambda_max(v_hat) A0(v_hat), and the
+ * viscous trace flux g_hat = G(v_hat, q).n -- the choices of the paper's
+ * numerical examples.
+ *
+ * Conventions (all arrays are plain contiguous memory):
+ *   m = dim + 2 components.  Element e has Np nodes, nf faces, Nfp nodes per face.
+ *   Local unknowns x_K (length n):  v at [c*Np + a], then q at
+ *     [m*Np + (c*dim + j)*Np + a]          (n = m*Np Euler, m*Np*(1+dim) NS)
+ *   Element trace unknowns (length k = nf*m*Nfp): [f*(m*Nfp) + c*Nfp + b].
+ *   Global fields are structure-of-arrays:
+ *     v     [m][E*Np]       entropy variables at element nodes, node e*Np + a
+ *     q     [m*dim][E*Np]   gradient unknowns, row c*dim + j
+ *     vhat  [m][n_trace]    trace unknowns at global trace nodes
+ *   Per-element matrices are column-major and element-major:
+ *     S [E][k][k], g [E][k], Y [E][k][n] (n x k column-major), z [E][n].
+ *   Element node order: tensor Gauss-Lobatto lattice, x fastest (quad/hex);
+ *   equispaced barycentric lattice, k outer / j / i inner (tri/tet).  Local face
+ *   f: xi=-1,+1, eta=-1,+1, zeta=-1,+1 (quad/hex); opposite vertex f (tri/tet).
+ *   Face node b is the b-th element node (ascending) on that face.
+ *   Quadrature: Gauss-Legendre with p+2 points per direction (collapsed on
+ *   simplices).  Gas constant R = 1, c_v = 1/(gamma-1), s0 = 0, beta = 0.
+ *
+ * Memory: every device buffer is owned by the caller.  The plan keeps host
+ * copies of the mesh tables; after hdg_plan_bind_workspace it also uses the
+ * caller's workspace (tables at its start, per-element scratch after).
+ * Calls are asynchronous on the given stream; errors detected on the host are
+ * returned immediately, errors detected on the device land in the per-element
+ * status array (HDG_ENONPHYS, HDG_ESINGULAR).
+ * Thread safety: one plan must not be used by overlapping calls (the bound
+ * workspace is shared scratch).
+ */
+#ifndef HDG_H_
+#define HDG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HDG_OK = 0,
+  HDG_EINVAL = -1,        /* bad argument: null pointer, size mismatch, det J <= 0 */
+  HDG_EUNSUPPORTED = -2,  /* element type / order / dimension not built */
+  HDG_ENONPHYS = -3,      /* v_m >= 0 or non-finite state at a quadrature point */
+  HDG_ESINGULAR = -4,     /* zero pivot in the local LU */
+  HDG_EHIP = -5,          /* HIP runtime error (see hdg_last_error) */
+  HDG_ENOMEM = -6         /* workspace smaller than hdg_plan_workspace_bytes */
+};
+
+enum { HDG_TRI = 0, HDG_QUAD = 1, HDG_TET = 2, HDG_HEX = 3 };
+enum { HDG_FP64 = 0, HDG_FP32 = 1, HDG_BF16 = 2 };
+
+typedef struct hdg_plan hdg_plan;
+
+/* Physical parameters (Euler / Navier-Stokes sections; numerical examples for
+ * beta = 0).  alpha is the mass coefficient of a backward-Euler / DIRK stage:
+ * the element equation gets alpha (u(v_h) - u*, w); alpha = 0 is steady. */
+typedef struct {
+  int viscous;     /* 0 Euler, 1 Navier-Stokes */
+  double gamma;
+  double mu;       /* constant dynamic viscosity */
+  double Pr;
+  double alpha;
+} hdg_phys;
+
+/* Mesh description, host memory, read once by hdg_plan_create. */
+typedef struct {
+  int elem_type;           /* HDG_TRI .. HDG_HEX */
+  int order;               /* polynomial degree p (1..4) */
+  int n_elem;
+  const double *elem_xyz;  /* [n_elem][n_vertices][dim]: straight-sided or multilinear */
+  const int32_t *face_bc;  /* [n_elem][nf]: 0 flux face, 1 Dirichlet-trace face; NULL: all 0 */
+  const int32_t *trace_map;/* [n_elem][nf][Nfp] global trace node; encodes HDG/EDG/IEDG */
+  int n_trace;             /* number of global trace nodes */
+} hdg_mesh;
+
+typedef struct {
+  int chunk_elems;         /* elements per internal wave (0: all) */
+  int precision;           /* HDG_FP64 (others reserved) */
+} hdg_opts;
+
+typedef struct {
+  int dim, m, Np, nf, Nfp, Nq, Nfq;
+  int n, k;                /* local and element-trace block sizes */
+  int n_pad, k_pad;        /* internal padded sizes */
+  int n_elem, n_trace, chunk_elems;
+} hdg_dims;
+
+/* Create a plan: builds reference tables and element geometry on the host.
+ * Returns HDG_EINVAL for bad sizes or a non-positive Jacobian, HDG_EUNSUPPORTED
+ * for an order outside 1..4. */
+int hdg_plan_create(hdg_plan **plan, const hdg_mesh *mesh, const hdg_phys *phys, const hdg_opts *opts);
+void hdg_plan_destroy(hdg_plan *plan);
+int hdg_plan_dims(const hdg_plan *plan, hdg_dims *out);
+
+/* Bytes of device workspace the plan needs (tables + per-chunk scratch). */
+int hdg_plan_workspace_bytes(const hdg_plan *plan, size_t *bytes);
+
+/* Bind caller-owned device workspace (>= hdg_plan_workspace_bytes, 256-byte
+ * aligned) and upload the tables into it (synchronous on `stream`). */
+int hdg_plan_bind_workspace(hdg_plan *plan, void *dev_ptr, size_t bytes, void *stream);
+
+/* Physical coordinates of the element nodes x[dim][E*Np] and of the global
+ * trace nodes xt[dim][n_trace] (device pointers, either may be NULL). */
+int hdg_node_coords(const hdg_plan *plan, double *x, double *xt, void *stream);
+
+/* Workload preparation (entropy-variable section): from primitives
+ * prim[m][N] = (rho, V_1..V_dim, p) and optional gradients grad[m][dim][N]
+ * compute v[m][N] = v(u(prim)), q[m*dim][N] = dv/dprim . grad (NULL-able),
+ * u[m][N] = conservation variables (NULL-able).  Device pointers. */
+int hdg_prepare_state(const hdg_plan *plan, int N, const double *prim, const double *grad,
+                      double *v, double *q, double *u, void *stream);
+
+/* Residual and Jacobian blocks of every element (no condensation), compact
+ * column-major: A [E][n][n], B [E][k][n] (n x k), C [E][n][k] (k x n),
+ * D [E][k][k], R_loc [E][n], R_tr [E][k].  Inputs as in hdg_assemble_condense.
+ * Any output may be NULL.  Meant for inspection and tests. */
+int hdg_assemble(hdg_plan *plan, const double *v, const double *q, const double *vhat,
+                 const double *u_star, const double *v_bc,
+                 double *A, double *B, double *C, double *D, double *R_loc, double *R_tr,
+                 int32_t *elem_status, void *stream);
+
+/* The hot path.  For every element: residual R_loc, R_tr and Jacobian blocks
+ * [A B; C D] of the Newton system [A B; C D][dx; dlambda] = -[R_loc; R_tr],
+ * LU of A with partial pivoting, and
+ *     Y = A^-1 B,  z = A^-1 R_loc,  S = D - C Y,  g = -R_tr + C z.
+ * v, vhat required; q required iff viscous; u_star [m][E*Np] nodal u* of the
+ * mass term (NULL: u* = 0, needs alpha == 0 to be meaningful); v_bc [m][n_trace]
+ * Dirichlet data read on Dirichlet-trace faces (NULL: zero).  Outputs S, g, Y, z
+ * required; R_loc, R_tr optional copies of the element residuals.
+ * elem_status [E] (required) receives HDG_OK or a device-side error code. */
+int hdg_assemble_condense(hdg_plan *plan, const double *v, const double *q, const double *vhat,
+                          const double *u_star, const double *v_bc,
+                          double *S, double *g, double *Y, double *z,
+                          double *R_loc, double *R_tr, int32_t *elem_status, void *stream);
+
+/* Local back-solve after the global trace update (same passage):
+ *   dx_K = -z_K - Y_K P_K dlambda,   P_K the trace-map gather.
+ * dvhat [m][n_trace]; outputs dv [m][E*Np] and (NS) dq [m*dim][E*Np] in the
+ * global SoA layout (dq may be NULL for Euler). */
+int hdg_backsolve(hdg_plan *plan, const double *Y, const double *z, const double *dvhat,
+                  double *dv, double *dq, void *stream);
+
+/* Condensed trace operator y = sum_K P_K^T S_K P_K x on [m][n_trace] vectors
+ * (overwrites y).  HDG, EDG and IEDG differ only in the trace map (the paper's
+ * remark that the three schemes differ only in the trace unknowns). */
+int hdg_trace_matvec(hdg_plan *plan, const double *S, const double *x, double *y, void *stream);
+
+/* Right-hand side of the condensed system r = sum_K P_K^T g_K ([m][n_trace]). */
+int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
+
+/* Device self-check of the FP64 matrix-core operand layout the dense kernels
+ * rely on (one 16x16x4 product against a scalar loop); *max_err receives the
+ * largest absolute difference (0 expected).  Allocates 8 bytes of device memory. */
+int hdg_selftest(double *max_err);
+
+/* Last host-side error message of the calling thread. */
+const char *hdg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDG_H_ */

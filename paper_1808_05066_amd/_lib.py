@@ -1,0 +1,94 @@
+"""ctypes declarations of the C ABI in include/hdg.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libhdg.so")
+HEADER = os.path.join(HERE, "..", "include", "hdg.h")
+
+HDG_OK, HDG_EINVAL, HDG_EUNSUPPORTED, HDG_ENONPHYS, HDG_ESINGULAR, HDG_EHIP, HDG_ENOMEM = 0, -1, -2, -3, -4, -5, -6
+ERROR_NAMES = {0: "HDG_OK", -1: "HDG_EINVAL", -2: "HDG_EUNSUPPORTED", -3: "HDG_ENONPHYS",
+               -4: "HDG_ESINGULAR", -5: "HDG_EHIP", -6: "HDG_ENOMEM"}
+ETYPES = {"tri": 0, "quad": 1, "tet": 2, "hex": 3}
+
+
+class hdg_phys(ctypes.Structure):
+    _fields_ = [("viscous", ctypes.c_int), ("gamma", ctypes.c_double), ("mu", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class hdg_mesh(ctypes.Structure):
+    _fields_ = [("elem_type", ctypes.c_int), ("order", ctypes.c_int), ("n_elem", ctypes.c_int),
+                ("elem_xyz", ctypes.c_void_p), ("face_bc", ctypes.c_void_p),
+                ("trace_map", ctypes.c_void_p), ("n_trace", ctypes.c_int)]
+
+
+class hdg_opts(ctypes.Structure):
+    _fields_ = [("chunk_elems", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class hdg_dims(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int) for n in ("dim", "m", "Np", "nf", "Nfp", "Nq", "Nfq", "n", "k", "n_pad",
+                                             "k_pad", "n_elem", "n_trace", "chunk_elems")]
+
+
+P = ctypes.c_void_p
+I = ctypes.c_int
+SIGNATURES = {
+    "hdg_plan_create": (I, [ctypes.POINTER(P), ctypes.POINTER(hdg_mesh), ctypes.POINTER(hdg_phys),
+                            ctypes.POINTER(hdg_opts)]),
+    "hdg_plan_destroy": (None, [P]),
+    "hdg_plan_dims": (I, [P, ctypes.POINTER(hdg_dims)]),
+    "hdg_plan_workspace_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_plan_bind_workspace": (I, [P, P, ctypes.c_size_t, P]),
+    "hdg_node_coords": (I, [P, P, P, P]),
+    "hdg_prepare_state": (I, [P, I, P, P, P, P, P, P]),
+    "hdg_assemble": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
+    "hdg_assemble_condense": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
+    "hdg_backsolve": (I, [P, P, P, P, P, P, P]),
+    "hdg_trace_matvec": (I, [P, P, P, P, P]),
+    "hdg_trace_rhs": (I, [P, P, P, P]),
+    "hdg_selftest": (I, [ctypes.POINTER(ctypes.c_double)]),
+    "hdg_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def header_symbols():
+    """Function names declared in include/hdg.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hdg_[a-z_]+)\s*\(", txt)))
+
+
+def load():
+    """Load libhdg.so; raises if it was not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libhdg.so not found at %s; build it with "
+                           "`python paper_1808_05066_amd/build.py`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class HdgError(RuntimeError):
+    def __init__(self, code, where):
+        msg = load().hdg_last_error().decode(errors="replace")
+        super().__init__("%s failed with %s: %s" % (where, ERROR_NAMES.get(code, code), msg))
+        self.code = code
+
+
+def check(code, where):
+    if code != HDG_OK:
+        raise HdgError(code, where)

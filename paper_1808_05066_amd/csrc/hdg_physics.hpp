@@ -1,0 +1,209 @@
+// Pointwise physics in entropy variables, device side.
+//
+// Written once over a scalar type T that is either double or Dual (value plus
+// one directional derivative): a pass with Dual seeded along one input
+// direction yields that column of the pointwise Jacobian exactly (forward-mode
+// differentiation), so the element Jacobian needs no hand-derived second
+// derivatives of u(v).
+//
+// Paper sections used: perfect-gas Euler flux and pressure (Euler section);
+// Newtonian stress with beta = 0 and Fourier heat flux, kappa = c_p mu / Pr
+// (Navier-Stokes section); entropy variables of H = -rho s (entropy pairs
+// section); inviscid trace flux and the symmetric Lax-Friedrichs matrix with
+// v* = v_hat (numerical-flux equation and its definition in the stability
+// section, choice stated in the numerical examples); viscous trace flux
+// G(v_hat, q).n.  R = 1 so T = p / rho = -(gamma-1)/v_m, c_v = 1/(gamma-1).
+// Viscous gradients are taken straight from q ~ grad v:
+//   grad T = (gamma-1) grad v_m / v_m^2,  grad V_i = -grad w_i / v_m + w_i grad v_m / v_m^2.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace hdg {
+
+struct Dual {
+  double v, d;
+};
+
+__host__ __device__ inline Dual mk(double v, double d) { return Dual{v, d}; }
+__host__ __device__ inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__host__ __device__ inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__host__ __device__ inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+__host__ __device__ inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__host__ __device__ inline Dual operator/(Dual a, Dual b) {
+  double r = 1.0 / b.v;
+  double q = a.v * r;
+  return {q, (a.d - q * b.d) * r};
+}
+__host__ __device__ inline Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+__host__ __device__ inline Dual operator+(double b, Dual a) { return {a.v + b, a.d}; }
+__host__ __device__ inline Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
+__host__ __device__ inline Dual operator-(double b, Dual a) { return {b - a.v, -a.d}; }
+__host__ __device__ inline Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+__host__ __device__ inline Dual operator*(double b, Dual a) { return {a.v * b, a.d * b}; }
+__host__ __device__ inline Dual operator/(Dual a, double b) { return {a.v / b, a.d / b}; }
+__host__ __device__ inline Dual operator/(double a, Dual b) {
+  double q = a / b.v;
+  return {q, -q * b.d / b.v};
+}
+
+__device__ inline double dexp(double x) { return exp(x); }
+__device__ inline Dual dexp(Dual x) {
+  double e = exp(x.v);
+  return {e, e * x.d};
+}
+__device__ inline double dpow(double x, double a) { return pow(x, a); }
+__device__ inline Dual dpow(Dual x, double a) {
+  double y = pow(x.v, a);
+  return {y, a * y / x.v * x.d};
+}
+__device__ inline double dlog(double x) { return log(x); }
+__device__ inline Dual dlog(Dual x) { return {log(x.v), x.d / x.v}; }
+__device__ inline double dsqrt(double x) { return sqrt(x); }
+__device__ inline Dual dsqrt(Dual x) {
+  double s = sqrt(x.v);
+  return {s, 0.5 * x.d / s};
+}
+// |x| with derivative +1 at x = 0
+__device__ inline double dabs(double x) { return x >= 0.0 ? x : -x; }
+__device__ inline Dual dabs(Dual x) { return x.v >= 0.0 ? x : -x; }
+__device__ inline double val(double x) { return x; }
+__device__ inline double val(Dual x) { return x.v; }
+__device__ inline double der(double) { return 0.0; }
+__device__ inline double der(Dual x) { return x.d; }
+
+template <typename T>
+__device__ inline T cst(double x) { return T(x); }
+template <>
+__device__ inline Dual cst<Dual>(double x) { return Dual{x, 0.0}; }
+
+// Primitive state from entropy variables (inverse of the entropy-variable map).
+template <int D, typename T>
+struct Prim {
+  T rho, p, V[D], vm, w[D];
+};
+
+template <int D, typename T>
+__device__ inline Prim<D, T> prim_of_v(const T *v, double gam) {
+  Prim<D, T> s;
+  const T vm = v[D + 1];
+  T ww = cst<T>(0.0);
+  for (int i = 0; i < D; ++i) {
+    s.w[i] = v[1 + i];
+    ww = ww + v[1 + i] * v[1 + i];
+  }
+  s.vm = vm;
+  // physical entropy s = gamma - v1 + |w|^2 / (2 v_m); rho^(gamma-1) = (gamma-1)/(-v_m) e^{-s}
+  T sent = gam - v[0] + ww / (2.0 * vm);
+  s.rho = dpow((gam - 1.0) / (-vm) * dexp(-sent), 1.0 / (gam - 1.0));
+  s.p = (gam - 1.0) * s.rho / (-vm);
+  for (int i = 0; i < D; ++i) s.V[i] = -s.w[i] / vm;
+  return s;
+}
+
+template <int D, typename T>
+__device__ inline void u_of_prim(const Prim<D, T> &s, double gam, T *u) {
+  T kin = cst<T>(0.0);
+  for (int i = 0; i < D; ++i) kin = kin + s.V[i] * s.V[i];
+  u[0] = s.rho;
+  for (int i = 0; i < D; ++i) u[1 + i] = s.rho * s.V[i];
+  u[D + 1] = s.p / (gam - 1.0) + 0.5 * s.rho * kin;
+}
+
+// Inviscid flux along n (n == nullptr: all directions into F[c*D + j]).
+template <int D, typename T>
+__device__ inline void flux_F(const Prim<D, T> &s, double gam, T *F) {
+  T kin = cst<T>(0.0);
+  for (int i = 0; i < D; ++i) kin = kin + s.V[i] * s.V[i];
+  T H = s.p / (gam - 1.0) + 0.5 * s.rho * kin + s.p;   // rho E + p
+  for (int j = 0; j < D; ++j) {
+    F[0 * D + j] = s.rho * s.V[j];
+    for (int i = 0; i < D; ++i) F[(1 + i) * D + j] = s.rho * s.V[i] * s.V[j] + (i == j ? s.p : cst<T>(0.0));
+    F[(D + 1) * D + j] = s.V[j] * H;
+  }
+}
+
+// Viscous flux G[c*D + j] from the state and q[c*D + k] (q of scalar type Q).
+template <int D, typename T, typename Q>
+__device__ inline void flux_G(const Prim<D, T> &s, const Q *q, double gam, double mu, double Pr, T *G) {
+  const T vm2 = s.vm * s.vm;
+  T gT[D], gV[D][D];
+  for (int k = 0; k < D; ++k) gT[k] = (gam - 1.0) * q[(D + 1) * D + k] / vm2;
+  for (int i = 0; i < D; ++i)
+    for (int k = 0; k < D; ++k) gV[i][k] = s.w[i] * q[(D + 1) * D + k] / vm2 - q[(1 + i) * D + k] / s.vm;
+  T div = cst<T>(0.0);
+  for (int i = 0; i < D; ++i) div = div + gV[i][i];
+  const double kappa = gam / (gam - 1.0) * mu / Pr;
+  for (int j = 0; j < D; ++j) {
+    G[0 * D + j] = cst<T>(0.0);
+    T vt = cst<T>(0.0);
+    for (int i = 0; i < D; ++i) {
+      T tau = mu * (gV[i][j] + gV[j][i]);
+      if (i == j) tau = tau - (2.0 / 3.0) * mu * div;
+      G[(1 + i) * D + j] = -tau;
+      vt = vt + s.V[i] * tau;
+    }
+    G[(D + 1) * D + j] = -vt - kappa * gT[j];
+  }
+}
+
+// dU/dV in closed form (symmetric), from the primitive state.
+template <int D, typename T>
+__device__ inline void A0_of_prim(const Prim<D, T> &s, double gam, T *A) {
+  const int M = D + 2;
+  T kin = cst<T>(0.0);
+  for (int i = 0; i < D; ++i) kin = kin + s.V[i] * s.V[i];
+  const double g1 = 1.0 / (gam - 1.0);
+  T E = s.p / ((gam - 1.0) * s.rho) + 0.5 * kin;
+  T Ht = E + s.p / s.rho;
+  T c2 = gam * s.p / s.rho;
+  A[0] = s.rho * g1;
+  for (int i = 0; i < D; ++i) {
+    A[0 * M + 1 + i] = s.rho * s.V[i] * g1;
+    A[(1 + i) * M + 0] = A[0 * M + 1 + i];
+    for (int k = 0; k < D; ++k)
+      A[(1 + i) * M + 1 + k] = (s.rho * s.V[i] * s.V[k] + (i == k ? s.p : cst<T>(0.0))) * g1;
+    A[(1 + i) * M + M - 1] = s.rho * Ht * s.V[i] * g1;
+    A[(M - 1) * M + 1 + i] = A[(1 + i) * M + M - 1];
+  }
+  A[0 * M + M - 1] = s.rho * E * g1;
+  A[(M - 1) * M + 0] = A[0 * M + M - 1];
+  A[(M - 1) * M + M - 1] = (s.rho * Ht * Ht - c2 * s.p * g1) * g1;
+}
+
+// Trace flux f_hat + g_hat at one face point.  vh: trace state (type T),
+// F_n(v) of the element state precomputed (double), dv = v - v_hat evaluated
+// inside, q (type Q) the element gradient unknowns (ignored if !visc).
+template <int D, typename T, typename Q>
+__device__ inline void trace_flux(const T *vh, const double *v, const double *Fnv, const Q *q,
+                                  const double *n, double gam, double mu, double Pr, bool visc,
+                                  T *out) {
+  const int M = D + 2;
+  Prim<D, T> s = prim_of_v<D, T>(vh, gam);
+  T F[M * D];
+  flux_F<D, T>(s, gam, F);
+  T A[M * M];
+  A0_of_prim<D, T>(s, gam, A);
+  T vn = cst<T>(0.0);
+  for (int j = 0; j < D; ++j) vn = vn + s.V[j] * n[j];
+  T lam = dabs(vn) + dsqrt(gam * s.p / s.rho);
+  T dv[M];
+  for (int c = 0; c < M; ++c) dv[c] = v[c] - vh[c];
+  for (int c = 0; c < M; ++c) {
+    T fn = cst<T>(0.0);
+    for (int j = 0; j < D; ++j) fn = fn + F[c * D + j] * n[j];
+    T sd = cst<T>(0.0);
+    for (int e = 0; e < M; ++e) sd = sd + A[c * M + e] * dv[e];
+    out[c] = 0.5 * (fn + Fnv[c]) + 0.5 * lam * sd;
+  }
+  if (visc) {
+    T G[M * D];
+    flux_G<D, T, Q>(s, q, gam, mu, Pr, G);
+    for (int c = 0; c < M; ++c) {
+      T gn = cst<T>(0.0);
+      for (int j = 0; j < D; ++j) gn = gn + G[c * D + j] * n[j];
+      out[c] = out[c] + gn;
+    }
+  }
+}
+
+}  // namespace hdg

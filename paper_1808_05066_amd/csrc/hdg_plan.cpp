@@ -1,0 +1,467 @@
+// C ABI: plan creation, workspace binding and the entry points of hdg.h.
+#include "hdg_plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return HDG_EHIP;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int roundup(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+using namespace hdg;
+
+extern "C" const char *hdg_last_error(void) { return g_err.c_str(); }
+
+extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_phys *phys,
+                               const hdg_opts *opts) {
+  if (!out || !mesh || !phys) return fail(HDG_EINVAL, "null argument");
+  *out = nullptr;
+  if (mesh->n_elem <= 0 || !mesh->elem_xyz || !mesh->trace_map || mesh->n_trace <= 0)
+    return fail(HDG_EINVAL, "mesh: n_elem, elem_xyz, trace_map and n_trace are required");
+  if (mesh->order < 1 || mesh->order > 4) return fail(HDG_EUNSUPPORTED, "order must be 1..4");
+  if (mesh->elem_type < 0 || mesh->elem_type > 3) return fail(HDG_EUNSUPPORTED, "unknown element type");
+  if (!(phys->gamma > 1.0) || phys->mu < 0.0 || (phys->viscous && !(phys->Pr > 0.0)) || phys->alpha < 0.0)
+    return fail(HDG_EINVAL, "physical parameters out of range");
+  if (opts && opts->precision != HDG_FP64) return fail(HDG_EUNSUPPORTED, "only HDG_FP64 is built");
+
+  Plan *P = new Plan();
+  std::string err = build_ref_tables(mesh->elem_type, mesh->order, P->ref);
+  if (!err.empty()) {
+    delete P;
+    return fail(HDG_EUNSUPPORTED, err);
+  }
+  const RefTables &R = P->ref;
+  const int d = R.dim, E = mesh->n_elem, M = R.m;
+  P->phys = *phys;
+  P->n_elem = E;
+  P->n_trace = mesh->n_trace;
+  P->chunk = (opts && opts->chunk_elems > 0) ? std::min(opts->chunk_elems, E) : E;
+
+  // trace map / face flags
+  P->tmap.assign(mesh->trace_map, mesh->trace_map + (size_t)E * R.nf * R.Nfp);
+  for (int t : P->tmap)
+    if (t < 0 || t >= mesh->n_trace) {
+      delete P;
+      return fail(HDG_EINVAL, "trace_map entry out of range");
+    }
+  P->face_bc.assign((size_t)E * R.nf, 0);
+  if (mesh->face_bc)
+    for (size_t i = 0; i < P->face_bc.size(); ++i) P->face_bc[i] = mesh->face_bc[i] ? 1 : 0;
+  P->node_face.assign(R.Np * R.nf, -1);
+  for (int f = 0; f < R.nf; ++f)
+    for (int b = 0; b < R.Nfp; ++b) P->node_face[R.fnodes[f * R.Nfp + b] * R.nf + f] = b;
+
+  // geometry at quadrature points and node coordinates
+  P->geo_vol.assign((size_t)E * R.Nq * (1 + d * d), 0.0);
+  P->geo_face.assign((size_t)E * R.nf * R.Nfq * (1 + d), 0.0);
+  P->node_x.assign((size_t)d * E * R.Np, 0.0);
+  P->trace_x.assign((size_t)d * mesh->n_trace, 0.0);
+  std::vector<double> Nv(R.nv), dNv(R.nv * d);
+  for (int e = 0; e < E; ++e) {
+    const double *X = mesh->elem_xyz + (size_t)e * R.nv * d;
+    auto jac = [&](const double *xi, double J[3][3], double *x) {
+      vertex_shape(R.etype, d, xi, Nv.data(), dNv.data());
+      for (int i = 0; i < d; ++i) {
+        if (x) x[i] = 0.0;
+        for (int r = 0; r < d; ++r) J[i][r] = 0.0;
+      }
+      for (int v = 0; v < R.nv; ++v)
+        for (int i = 0; i < d; ++i) {
+          if (x) x[i] += Nv[v] * X[v * d + i];
+          for (int r = 0; r < d; ++r) J[i][r] += dNv[v * d + r] * X[v * d + i];
+        }
+    };
+    auto inv = [&](double J[3][3], double Ji[3][3]) -> double {
+      if (d == 2) {
+        double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        Ji[0][0] = J[1][1] / det;
+        Ji[0][1] = -J[0][1] / det;
+        Ji[1][0] = -J[1][0] / det;
+        Ji[1][1] = J[0][0] / det;
+        return det;
+      }
+      double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+      Ji[0][0] = c00 / det;
+      Ji[1][0] = c01 / det;
+      Ji[2][0] = c02 / det;
+      Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+      Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+      Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+      Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+      Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+      Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+      return det;
+    };
+    double J[3][3], Ji[3][3];
+    for (int q = 0; q < R.Nq; ++q) {
+      jac(&R.xq[q * d], J, nullptr);
+      double det = inv(J, Ji);  // Ji[r][i] = dxi_r / dx_i
+      if (!(det > 0.0)) {
+        delete P;
+        return fail(HDG_EINVAL, "element with non-positive Jacobian determinant");
+      }
+      double *g = &P->geo_vol[((size_t)e * R.Nq + q) * (1 + d * d)];
+      g[0] = R.wq[q] * det;
+      for (int r = 0; r < d; ++r)
+        for (int j = 0; j < d; ++j) g[1 + r * d + j] = Ji[r][j];
+    }
+    for (int f = 0; f < R.nf; ++f)
+      for (int q = 0; q < R.Nfq; ++q) {
+        jac(&R.fxi[(f * R.Nfq + q) * d], J, nullptr);
+        double det = inv(J, Ji);
+        if (!(det > 0.0)) {
+          delete P;
+          return fail(HDG_EINVAL, "element with non-positive Jacobian determinant");
+        }
+        // Nanson: n dS = det J  J^-T n_ref dS_ref
+        double a[3] = {0, 0, 0}, nrm = 0.0;
+        for (int i = 0; i < d; ++i) {
+          for (int r = 0; r < d; ++r) a[i] += Ji[r][i] * R.fnref[f * d + r];
+          a[i] *= det;
+          nrm += a[i] * a[i];
+        }
+        nrm = std::sqrt(nrm);
+        double *g = &P->geo_face[(((size_t)e * R.nf + f) * R.Nfq + q) * (1 + d)];
+        g[0] = R.fw[f * R.Nfq + q] * nrm;
+        for (int i = 0; i < d; ++i) g[1 + i] = a[i] / nrm;
+      }
+    for (int a = 0; a < R.Np; ++a) {
+      double x[3];
+      jac(&R.nodes[a * d], J, x);
+      for (int i = 0; i < d; ++i) P->node_x[(size_t)i * E * R.Np + (size_t)e * R.Np + a] = x[i];
+    }
+    for (int f = 0; f < R.nf; ++f)
+      for (int b = 0; b < R.Nfp; ++b) {
+        int a = R.fnodes[f * R.Nfp + b];
+        int t = P->tmap[((size_t)e * R.nf + f) * R.Nfp + b];
+        for (int i = 0; i < d; ++i)
+          P->trace_x[(size_t)i * mesh->n_trace + t] = P->node_x[(size_t)i * E * R.Np + (size_t)e * R.Np + a];
+      }
+  }
+
+  // descriptor
+  DevPlan &D = P->dp;
+  D.dim = d;
+  D.m = M;
+  D.Np = R.Np;
+  D.nf = R.nf;
+  D.Nfp = R.Nfp;
+  D.Nq = R.Nq;
+  D.Nfq = R.Nfq;
+  D.viscous = phys->viscous ? 1 : 0;
+  D.n = M * R.Np * (D.viscous ? (1 + d) : 1);
+  D.k = R.nf * M * R.Nfp;
+  D.n_pad = roundup(D.n, 16);
+  D.k_pad = roundup(D.k, 16);
+  D.kx = D.k_pad + 16;
+  D.n_elem = E;
+  D.n_trace = mesh->n_trace;
+  D.gamma = phys->gamma;
+  D.mu = phys->mu;
+  D.Pr = phys->Pr;
+  D.alpha = phys->alpha;
+  if (D.n_pad > 1024) {
+    delete P;
+    return fail(HDG_EUNSUPPORTED, "local block larger than 1024 is not built in this version");
+  }
+  PointLayout &L = D.L;
+  int o = 0;
+  L.Mv = o; o += M * M;
+  L.Kv = o; o += M * d * M;
+  L.Kq = o; o += D.viscous ? M * d * M * d : 0;
+  L.Fr = o; o += M * d;
+  L.Wu = o; o += M;
+  L.Wq = o; o += D.viscous ? M * d : 0;
+  L.v = o; o += M;
+  L.WJ = o; o += d * d;
+  L.W = o; o += 1;
+  L.size = o;
+  o = 0;
+  L.fFv = o; o += M * M;
+  L.fFq = o; o += D.viscous ? M * M * d : 0;
+  L.fFh = o; o += M * M;
+  L.fFf = o; o += M;
+  L.fWn = o; o += d;
+  L.fvh = o; o += M;
+  L.fFd = o; o += M;
+  L.fW = o; o += 1;
+  L.fsize = o;
+  *out = reinterpret_cast<hdg_plan *>(P);
+  return HDG_OK;
+}
+
+extern "C" void hdg_plan_destroy(hdg_plan *plan) { delete reinterpret_cast<Plan *>(plan); }
+
+extern "C" int hdg_plan_dims(const hdg_plan *plan, hdg_dims *o) {
+  if (!plan || !o) return fail(HDG_EINVAL, "null argument");
+  const Plan *P = reinterpret_cast<const Plan *>(plan);
+  const DevPlan &D = P->dp;
+  o->dim = D.dim; o->m = D.m; o->Np = D.Np; o->nf = D.nf; o->Nfp = D.Nfp; o->Nq = D.Nq; o->Nfq = D.Nfq;
+  o->n = D.n; o->k = D.k; o->n_pad = D.n_pad; o->k_pad = D.k_pad;
+  o->n_elem = P->n_elem; o->n_trace = P->n_trace; o->chunk_elems = P->chunk;
+  return HDG_OK;
+}
+
+namespace {
+
+struct Layout {
+  size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x, tables_end;
+  size_t pv, pf, A, X, C, D, Rt, ipiv, total;
+};
+
+Layout layout(const Plan *P) {
+  const RefTables &R = P->ref;
+  const DevPlan &D = P->dp;
+  const size_t E = P->n_elem, ch = P->chunk;
+  Layout l{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  l.phi = take(R.phi.size() * 8);
+  l.dphi = take(R.dphi.size() * 8);
+  l.fphi = take(R.fphi.size() * 8);
+  l.fnodes = take(R.fnodes.size() * 4);
+  l.node_face = take(P->node_face.size() * 4);
+  l.geo_vol = take(P->geo_vol.size() * 8);
+  l.geo_face = take(P->geo_face.size() * 8);
+  l.tmap = take(P->tmap.size() * 4);
+  l.face_bc = take(E * R.nf * 4);
+  l.node_x = take(P->node_x.size() * 8);
+  l.trace_x = take(P->trace_x.size() * 8);
+  l.tables_end = o;
+  l.pv = take(ch * D.Nq * D.L.size * 8);
+  l.pf = take(ch * D.nf * D.Nfq * D.L.fsize * 8);
+  l.A = take(ch * (size_t)D.n_pad * D.n_pad * 8);
+  l.X = take(ch * (size_t)D.kx * D.n_pad * 8);
+  l.C = take(ch * (size_t)D.n_pad * D.k_pad * 8);
+  l.D = take(ch * (size_t)D.k_pad * D.k_pad * 8);
+  l.Rt = take(ch * (size_t)D.k_pad * 8);
+  l.ipiv = take(ch * (size_t)D.n_pad * 4);
+  l.total = o;
+  return l;
+}
+
+Plan *checked(hdg_plan *plan) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P) {
+    g_err = "null plan";
+    return nullptr;
+  }
+  if (!P->bound) {
+    g_err = "workspace not bound";
+    return nullptr;
+  }
+  return P;
+}
+
+}  // namespace
+
+extern "C" int hdg_plan_workspace_bytes(const hdg_plan *plan, size_t *bytes) {
+  if (!plan || !bytes) return fail(HDG_EINVAL, "null argument");
+  *bytes = layout(reinterpret_cast<const Plan *>(plan)).total;
+  return HDG_OK;
+}
+
+extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !dev) return fail(HDG_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(dev) & 255) return fail(HDG_EINVAL, "workspace must be 256-byte aligned");
+  Layout l = layout(P);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "workspace smaller than hdg_plan_workspace_bytes");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(dev);
+  const RefTables &R = P->ref;
+  auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    return hipMemcpyAsync(base + off, src, n, hipMemcpyHostToDevice, s);
+  };
+  hipError_t e = hipSuccess;
+  if (!e) e = up(l.phi, R.phi.data(), R.phi.size() * 8);
+  if (!e) e = up(l.dphi, R.dphi.data(), R.dphi.size() * 8);
+  if (!e) e = up(l.fphi, R.fphi.data(), R.fphi.size() * 8);
+  if (!e) e = up(l.fnodes, R.fnodes.data(), R.fnodes.size() * 4);
+  if (!e) e = up(l.node_face, P->node_face.data(), P->node_face.size() * 4);
+  if (!e) e = up(l.geo_vol, P->geo_vol.data(), P->geo_vol.size() * 8);
+  if (!e) e = up(l.geo_face, P->geo_face.data(), P->geo_face.size() * 8);
+  if (!e) e = up(l.tmap, P->tmap.data(), P->tmap.size() * 4);
+  if (!e) e = up(l.face_bc, P->face_bc.data(), P->face_bc.size() * 4);
+  if (!e) e = up(l.node_x, P->node_x.data(), P->node_x.size() * 8);
+  if (!e) e = up(l.trace_x, P->trace_x.data(), P->trace_x.size() * 8);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "bind_workspace upload");
+  DevPlan &D = P->dp;
+  D.phi = reinterpret_cast<const double *>(base + l.phi);
+  D.dphi = reinterpret_cast<const double *>(base + l.dphi);
+  D.fphi = reinterpret_cast<const double *>(base + l.fphi);
+  D.fnodes = reinterpret_cast<const int *>(base + l.fnodes);
+  D.node_face = reinterpret_cast<const int *>(base + l.node_face);
+  D.geo_vol = reinterpret_cast<const double *>(base + l.geo_vol);
+  D.geo_face = reinterpret_cast<const double *>(base + l.geo_face);
+  D.tmap = reinterpret_cast<const int *>(base + l.tmap);
+  D.face_bc = reinterpret_cast<const int *>(base + l.face_bc);
+  D.node_x = reinterpret_cast<const double *>(base + l.node_x);
+  D.trace_x = reinterpret_cast<const double *>(base + l.trace_x);
+  D.pv = reinterpret_cast<double *>(base + l.pv);
+  D.pf = reinterpret_cast<double *>(base + l.pf);
+  D.A = reinterpret_cast<double *>(base + l.A);
+  D.X = reinterpret_cast<double *>(base + l.X);
+  D.C = reinterpret_cast<double *>(base + l.C);
+  D.D = reinterpret_cast<double *>(base + l.D);
+  D.Rt = reinterpret_cast<double *>(base + l.Rt);
+  D.ipiv = reinterpret_cast<int *>(base + l.ipiv);
+  P->ws = dev;
+  P->ws_bytes = bytes;
+  P->bound = true;
+  return HDG_OK;
+}
+
+extern "C" int hdg_node_coords(const hdg_plan *plan, double *x, double *xt, void *stream) {
+  const Plan *P = checked(const_cast<hdg_plan *>(plan));
+  if (!P) return HDG_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (x) e = hipMemcpyAsync(x, P->dp.node_x, P->node_x.size() * 8, hipMemcpyDeviceToDevice, s);
+  if (!e && xt) e = hipMemcpyAsync(xt, P->dp.trace_x, P->trace_x.size() * 8, hipMemcpyDeviceToDevice, s);
+  if (e) return hip_fail(e, "node_coords");
+  return HDG_OK;
+}
+
+extern "C" int hdg_prepare_state(const hdg_plan *plan, int N, const double *prim, const double *grad,
+                                 double *v, double *q, double *u, void *stream) {
+  const Plan *P = reinterpret_cast<const Plan *>(plan);
+  if (!P || !prim || !v || N < 0) return fail(HDG_EINVAL, "null argument");
+  if (q && !grad) return fail(HDG_EINVAL, "q requested without gradients");
+  hipError_t e = launch_prepare_state(P->dp, N, prim, grad, v, q, u, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "prepare_state");
+  return HDG_OK;
+}
+
+namespace {
+
+int run_front(Plan *P, const double *v, const double *q, const double *vhat, const double *ustar,
+              const double *vbc, int32_t *status, int e0, int ec, hipStream_t s) {
+  hipError_t e = launch_points(P->dp, e0, ec, v, q, vhat, ustar, vbc, status, s);
+  if (!e) e = launch_contract(P->dp, e0, ec, s);
+  if (e) return hip_fail(e, "assemble");
+  return HDG_OK;
+}
+
+int check_inputs(const Plan *P, const double *v, const double *q, const double *vhat,
+                 const double *ustar, int32_t *status) {
+  if (!v || !vhat || !status) return fail(HDG_EINVAL, "v, vhat and elem_status are required");
+  if (P->dp.viscous && !q) return fail(HDG_EINVAL, "q is required for Navier-Stokes");
+  (void)ustar;
+  return HDG_OK;
+}
+
+}  // namespace
+
+extern "C" int hdg_assemble(hdg_plan *plan, const double *v, const double *q, const double *vhat,
+                            const double *ustar, const double *vbc, double *A, double *B, double *C,
+                            double *D, double *Rloc, double *Rtr, int32_t *status, void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  int rc = check_inputs(P, v, q, vhat, ustar, status);
+  if (rc) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_fill_int(status, P->n_elem, HDG_OK, s);
+  if (e) return hip_fail(e, "status init");
+  for (int e0 = 0; e0 < P->n_elem; e0 += P->chunk) {
+    int ec = std::min(P->chunk, P->n_elem - e0);
+    rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s);
+    if (rc) return rc;
+    e = launch_export_blocks(P->dp, e0, ec, A, B, C, D, Rloc, Rtr, s);
+    if (e) return hip_fail(e, "export");
+  }
+  return HDG_OK;
+}
+
+extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const double *q,
+                                     const double *vhat, const double *ustar, const double *vbc,
+                                     double *S, double *g, double *Y, double *z, double *Rloc,
+                                     double *Rtr, int32_t *status, void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  int rc = check_inputs(P, v, q, vhat, ustar, status);
+  if (rc) return rc;
+  if (!S || !g || !Y || !z) return fail(HDG_EINVAL, "S, g, Y and z are required");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_fill_int(status, P->n_elem, HDG_OK, s);
+  if (e) return hip_fail(e, "status init");
+  for (int e0 = 0; e0 < P->n_elem; e0 += P->chunk) {
+    int ec = std::min(P->chunk, P->n_elem - e0);
+    rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s);
+    if (rc) return rc;
+    e = launch_copy_resid(P->dp, e0, ec, Rloc, Rtr, s);
+    if (!e) e = launch_lu(P->dp, ec, status + e0, s);
+    if (!e) e = launch_solve(P->dp, ec, s);
+    if (!e) e = launch_schur(P->dp, e0, ec, S, g, Y, z, Rloc, Rtr, s);
+    if (e) return hip_fail(e, "condense");
+  }
+  return HDG_OK;
+}
+
+extern "C" int hdg_backsolve(hdg_plan *plan, const double *Y, const double *z, const double *dvhat,
+                             double *dv, double *dq, void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  if (!Y || !z || !dvhat || !dv) return fail(HDG_EINVAL, "Y, z, dvhat and dv are required");
+  if (P->dp.viscous && !dq) return fail(HDG_EINVAL, "dq is required for Navier-Stokes");
+  hipError_t e = launch_backsolve(P->dp, Y, z, dvhat, dv, dq, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "backsolve");
+  return HDG_OK;
+}
+
+extern "C" int hdg_trace_matvec(hdg_plan *plan, const double *S, const double *x, double *y, void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  if (!S || !x || !y) return fail(HDG_EINVAL, "S, x and y are required");
+  if (x == y) return fail(HDG_EINVAL, "x and y must not alias");
+  hipError_t e = launch_trace_matvec(P->dp, S, x, y, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "trace_matvec");
+  return HDG_OK;
+}
+
+extern "C" int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  if (!g || !r) return fail(HDG_EINVAL, "g and r are required");
+  hipError_t e = launch_trace_rhs(P->dp, g, r, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "trace_rhs");
+  return HDG_OK;
+}
+
+extern "C" int hdg_selftest(double *max_err) {
+  if (!max_err) return fail(HDG_EINVAL, "null argument");
+  double *d = nullptr;
+  hipError_t e = hipMalloc(&d, sizeof(double));
+  if (!e) e = launch_mfma_selftest(d, nullptr);
+  if (!e) e = hipMemcpy(max_err, d, sizeof(double), hipMemcpyDeviceToHost);
+  if (d) (void)hipFree(d);
+  if (e) return hip_fail(e, "selftest");
+  return HDG_OK;
+}

@@ -1,0 +1,86 @@
+// Plan: host-built tables, device descriptor passed to the kernels, launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hdg.h"
+#include "hdg_tables.hpp"
+
+namespace hdg {
+
+// Offsets (in doubles) of the pointwise data written per volume / face point.
+struct PointLayout {
+  int Mv, Kv, Kq, Fr, Wu, Wq, v, WJ, W, size;       // volume
+  int fFv, fFq, fFh, fFf, fWn, fvh, fFd, fW, fsize;   // face
+};
+
+// Everything a kernel needs; passed by value.
+struct DevPlan {
+  int dim, m, Np, nf, Nfp, Nq, Nfq, n, k, n_pad, k_pad, kx, viscous, n_elem, n_trace;
+  double gamma, mu, Pr, alpha;
+  PointLayout L;
+  // tables (device)
+  const double *phi;       // [Nq][Np]
+  const double *dphi;      // [dim][Nq][Np]
+  const double *fphi;      // [nf][Nfq][Nfp]
+  const int *fnodes;       // [nf][Nfp]
+  const int *node_face;    // [Np][nf]: position of the node on face f, or -1
+  const double *geo_vol;   // [E][Nq][1 + dim*dim]: W, dxi_r/dx_j
+  const double *geo_face;  // [E][nf][Nfq][1 + dim]: W_f, n
+  const int *tmap;         // [E][nf][Nfp]
+  const int *face_bc;      // [E][nf]
+  const double *node_x;    // [dim][E*Np]
+  const double *trace_x;   // [dim][n_trace]
+  // per-chunk scratch (device)
+  double *pv;              // [chunk][Nq][L.size]
+  double *pf;              // [chunk][nf][Nfq][L.fsize]
+  double *A;               // [chunk][n_pad][n_pad]       column-major
+  double *X;               // [chunk][kx][n_pad]          [B | R_loc | 0] then [Y | z]
+  double *C;               // [chunk][n_pad][k_pad]       column-major k_pad x n_pad
+  double *D;               // [chunk][k_pad][k_pad]
+  double *Rt;              // [chunk][k_pad]
+  int *ipiv;               // [chunk][n_pad]
+};
+
+struct Plan {
+  RefTables ref;
+  DevPlan dp{};
+  hdg_phys phys{};
+  int n_elem = 0, n_trace = 0, chunk = 0;
+  // host copies
+  std::vector<double> geo_vol, geo_face, node_x, trace_x;
+  std::vector<int> tmap, face_bc, node_face;
+  // workspace
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t off_tables_end = 0;
+  bool bound = false;
+};
+
+// kernel launchers (hdg_assemble.hip / hdg_dense.hip / hdg_trace.hip)
+hipError_t launch_fill_int(int32_t *p, int n, int val, hipStream_t s);
+hipError_t launch_fill_double(double *p, size_t n, double val, hipStream_t s);
+hipError_t launch_points(const DevPlan &P, int e0, int ec, const double *v, const double *q,
+                         const double *vhat, const double *ustar, const double *vbc,
+                         int32_t *status, hipStream_t s);
+hipError_t launch_contract(const DevPlan &P, int e0, int ec, hipStream_t s);
+hipError_t launch_lu(const DevPlan &P, int ec, int32_t *status, hipStream_t s);
+hipError_t launch_solve(const DevPlan &P, int ec, hipStream_t s);
+hipError_t launch_schur(const DevPlan &P, int e0, int ec, double *S, double *g, double *Y,
+                        double *z, double *Rloc, double *Rtr, hipStream_t s);
+hipError_t launch_copy_resid(const DevPlan &P, int e0, int ec, double *Rloc, double *Rtr, hipStream_t s);
+hipError_t launch_mfma_selftest(double *out, hipStream_t s);
+hipError_t launch_export_blocks(const DevPlan &P, int e0, int ec, double *A, double *B, double *C,
+                                double *D, double *Rloc, double *Rtr, hipStream_t s);
+hipError_t launch_backsolve(const DevPlan &P, const double *Y, const double *z, const double *dvhat,
+                            double *dv, double *dq, hipStream_t s);
+hipError_t launch_trace_matvec(const DevPlan &P, const double *S, const double *x, double *y,
+                               hipStream_t s);
+hipError_t launch_trace_rhs(const DevPlan &P, const double *g, double *r, hipStream_t s);
+hipError_t launch_prepare_state(const DevPlan &P, int N, const double *prim, const double *grad,
+                                double *v, double *q, double *u, hipStream_t s);
+
+}  // namespace hdg

@@ -1,0 +1,157 @@
+"""Thin Python binding of the C ABI.  Torch provides device memory and streams.
+
+Every step of the hot path runs in libhdg.so; this module only allocates
+tensors, passes pointers and checks return codes.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import check
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """One mesh (single element type and order) with bound device workspace.
+
+    elem_xyz: (E, nv, d) float64 vertex coordinates; trace_map: (E, nf, Nfp)
+    int32; face_bc: (E, nf) int32 (1 = Dirichlet-trace face) or None.
+    """
+
+    def __init__(self, etype, order, elem_xyz, trace_map, n_trace, face_bc=None, *, viscous=False,
+                 gamma=1.4, mu=0.0, Pr=0.72, alpha=0.0, chunk_elems=0, device="cuda"):
+        torch = _torch()
+        self.lib = _lib.load()
+        self._xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
+        self._tmap = np.ascontiguousarray(trace_map, dtype=np.int32)
+        self._fbc = None if face_bc is None else np.ascontiguousarray(face_bc, dtype=np.int32)
+        mesh = _lib.hdg_mesh(_lib.ETYPES[etype] if isinstance(etype, str) else int(etype), int(order),
+                             int(self._xyz.shape[0]), self._xyz.ctypes.data,
+                             None if self._fbc is None else self._fbc.ctypes.data,
+                             self._tmap.ctypes.data, int(n_trace))
+        phys = _lib.hdg_phys(int(bool(viscous)), float(gamma), float(mu), float(Pr), float(alpha))
+        opts = _lib.hdg_opts(int(chunk_elems), 0)
+        h = ctypes.c_void_p()
+        check(self.lib.hdg_plan_create(ctypes.byref(h), ctypes.byref(mesh), ctypes.byref(phys),
+                                       ctypes.byref(opts)), "hdg_plan_create")
+        self.h = h
+        d = _lib.hdg_dims()
+        check(self.lib.hdg_plan_dims(h, ctypes.byref(d)), "hdg_plan_dims")
+        self.dims = {f: getattr(d, f) for f, _ in _lib.hdg_dims._fields_}
+        for key, val in self.dims.items():
+            setattr(self, key, val)
+        self.viscous = bool(viscous)
+        self.device = torch.device(device)
+        nb = ctypes.c_size_t()
+        check(self.lib.hdg_plan_workspace_bytes(h, ctypes.byref(nb)), "hdg_plan_workspace_bytes")
+        self.workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = ctypes.c_void_p(self.workspace.data_ptr() + off)
+        check(self.lib.hdg_plan_bind_workspace(h, self._ws_ptr, ctypes.c_size_t(nb.value), _stream()),
+              "hdg_plan_bind_workspace")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.hdg_plan_destroy(h)
+            self.h = None
+
+    # -- helpers -------------------------------------------------------------
+    def _empty(self, *shape, dtype=None):
+        torch = _torch()
+        return torch.empty(*shape, dtype=torch.float64 if dtype is None else dtype, device=self.device)
+
+    @property
+    def n_nodes(self):
+        return self.n_elem * self.Np
+
+    def node_coords(self):
+        x = self._empty(self.dim, self.n_nodes)
+        xt = self._empty(self.dim, self.n_trace)
+        check(self.lib.hdg_node_coords(self.h, _ptr(x), _ptr(xt), _stream()), "hdg_node_coords")
+        return x, xt
+
+    def prepare_state(self, prim, grad=None, want_u=False):
+        N = prim.shape[1]
+        v = self._empty(self.m, N)
+        q = self._empty(self.m * self.dim, N) if grad is not None else None
+        u = self._empty(self.m, N) if want_u else None
+        check(self.lib.hdg_prepare_state(self.h, N, _ptr(prim), _ptr(grad), _ptr(v), _ptr(q), _ptr(u),
+                                         _stream()), "hdg_prepare_state")
+        return v, q, u
+
+    def assemble(self, v, q, vhat, ustar=None, vbc=None):
+        E, n, k = self.n_elem, self.n, self.k
+        out = dict(A=self._empty(E, n, n), B=self._empty(E, k, n), C=self._empty(E, n, k),
+                   D=self._empty(E, k, k), R_loc=self._empty(E, n), R_tr=self._empty(E, k))
+        torch = _torch()
+        status = torch.empty(E, dtype=torch.int32, device=self.device)
+        check(self.lib.hdg_assemble(self.h, _ptr(v), _ptr(q), _ptr(vhat), _ptr(ustar), _ptr(vbc),
+                                    _ptr(out["A"]), _ptr(out["B"]), _ptr(out["C"]), _ptr(out["D"]),
+                                    _ptr(out["R_loc"]), _ptr(out["R_tr"]), _ptr(status), _stream()),
+              "hdg_assemble")
+        out["status"] = status
+        return out
+
+    def alloc_outputs(self, residuals=False):
+        """Output tensors of assemble_condense (column-major blocks as (E, cols, rows))."""
+        torch = _torch()
+        E, n, k = self.n_elem, self.n, self.k
+        out = dict(S=self._empty(E, k, k), g=self._empty(E, k), Y=self._empty(E, k, n), z=self._empty(E, n),
+                   status=torch.empty(E, dtype=torch.int32, device=self.device))
+        if residuals:
+            out["R_loc"] = self._empty(E, n)
+            out["R_tr"] = self._empty(E, k)
+        return out
+
+    def assemble_condense(self, v, q, vhat, ustar=None, vbc=None, out=None, residuals=False):
+        if out is None:
+            out = self.alloc_outputs(residuals)
+        check(self.lib.hdg_assemble_condense(
+            self.h, _ptr(v), _ptr(q), _ptr(vhat), _ptr(ustar), _ptr(vbc), _ptr(out["S"]), _ptr(out["g"]),
+            _ptr(out["Y"]), _ptr(out["z"]), _ptr(out.get("R_loc")), _ptr(out.get("R_tr")), _ptr(out["status"]),
+            _stream()), "hdg_assemble_condense")
+        return out
+
+    def backsolve(self, Y, z, dvhat):
+        dv = self._empty(self.m, self.n_nodes)
+        dq = self._empty(self.m * self.dim, self.n_nodes) if self.viscous else None
+        check(self.lib.hdg_backsolve(self.h, _ptr(Y), _ptr(z), _ptr(dvhat), _ptr(dv), _ptr(dq), _stream()),
+              "hdg_backsolve")
+        return dv, dq
+
+    def trace_matvec(self, S, x, y=None):
+        if y is None:
+            y = self._empty(self.m, self.n_trace)
+        check(self.lib.hdg_trace_matvec(self.h, _ptr(S), _ptr(x), _ptr(y), _stream()), "hdg_trace_matvec")
+        return y
+
+    def trace_rhs(self, g, r=None):
+        if r is None:
+            r = self._empty(self.m, self.n_trace)
+        check(self.lib.hdg_trace_rhs(self.h, _ptr(g), _ptr(r), _stream()), "hdg_trace_rhs")
+        return r
+
+
+def selftest():
+    """Largest error of the device matrix-core layout self-check."""
+    lib = _lib.load()
+    e = ctypes.c_double(-1.0)
+    check(lib.hdg_selftest(ctypes.byref(e)), "hdg_selftest")
+    return e.value

@@ -1,0 +1,111 @@
+"""Shared helpers for GPU parity tests: oracle inputs and GPU plans of a workload."""
+import numpy as np
+
+from oracle import hdg as ohdg
+from oracle import state as ostate
+from workloads import configs as C
+
+
+def oracle_disc(wl, nquad=None):
+    return ohdg.Discretization(wl.mesh, wl.p, ohdg.Phys(wl.gamma, wl.mu, wl.Pr, wl.alpha, wl.viscous),
+                               wl.tmap, wl.n_trace, wl.face_bc, nquad)
+
+
+def oracle_case(wl):
+    disc = oracle_disc(wl)
+    return disc, ostate.oracle_inputs(wl, disc)
+
+
+def gpu_plan(wl, chunk_elems=0):
+    from paper_1808_05066_amd.hdg import Plan
+    return Plan(wl.mesh.etype, wl.p, wl.mesh.elem_xyz, wl.tmap, wl.n_trace, wl.face_bc, viscous=wl.viscous,
+                gamma=wl.gamma, mu=wl.mu, Pr=wl.Pr, alpha=wl.alpha, chunk_elems=chunk_elems)
+
+
+def to_dev(inp):
+    import torch
+    out = {}
+    for key in ("v", "q", "vhat", "ustar", "vbc"):
+        a = inp.get(key)
+        out[key] = None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return out
+
+
+def rel_err_per_elem(gpu, ref):
+    """max over elements of ||gpu - ref||_F / ||ref||_F (elements along axis 0)."""
+    g = np.asarray(gpu).reshape(gpu.shape[0], -1)
+    r = np.asarray(ref).reshape(ref.shape[0], -1)
+    num = np.linalg.norm(g - r, axis=1)
+    den = np.linalg.norm(r, axis=1)
+    return float(np.max(num / np.where(den > 0, den, 1.0)))
+
+
+def colmajor(mats):
+    """Stack (rows x cols) numpy matrices into the (E, cols, rows) column-major layout."""
+    return np.stack([np.asarray(M).T for M in mats])
+
+
+SMALL_CASES = {
+    "euler2d_tri_p2": lambda: C.euler2d_tri_p2(),
+    "euler2d_tri_p2_periodic_edg": lambda: C.euler2d_tri_p2(n=4, periodic=True, scheme="edg"),
+    "ns2d_tri_p2": lambda: C.ns2d_tri(n=3, p=2),
+    "ns2d_tri_p3": lambda: C.ns2d_tri(n=2, p=3),
+    "ns3d_hex_p1": lambda: C.ns3d_hex(n=3, p=1),
+    "ns3d_hex_p2": lambda: C.ns3d_hex(n=2, p=2),
+    "euler3d_hex_p2": lambda: C.euler3d_hex(n=2, p=2),
+}
+
+
+def residual_term_scale(disc, e, x, lam, ustar=None):
+    """Norm of the element residual with every quadrature contribution in absolute value.
+
+    R_loc is a sum of volume and face contributions that nearly cancel for
+    states close to a discrete steady state; its floating-point error is
+    bounded by eps times this sum of magnitudes, so parity of R_loc is stated
+    relative to it.
+    """
+    from oracle import physics as ph
+    G = disc.geom(e)
+    m, d, Np, Nfp, nf = disc.m, disc.d, disc.Np, disc.Nfp, disc.nf
+    gam, P = disc.phys.gamma, disc.phys
+    vN = x[:m * Np].reshape(m, Np)
+    qN = x[m * Np:].reshape(m, d, Np) if P.viscous else None
+    LN = lam.reshape(nf, m, Nfp)
+    phi, gphi, W = disc.ref.phi, G.gphi, np.abs(G.W)
+    vq = phi @ vN.T
+    flux = np.abs(ph.flux_F(vq, gam))
+    if P.viscous:
+        qq = np.einsum("qa,cja->qcj", phi, qN)
+        flux = flux + np.abs(ph.flux_G(vq, qq, gam, P.mu, P.Pr))
+    Tv = np.einsum("q,qcj,qaj->ca", W, flux, np.abs(gphi))
+    if P.alpha:
+        us = 0.0 if ustar is None else np.abs(phi @ ustar.T)
+        Tv = Tv + P.alpha * np.einsum("q,qc,qa->ca", W, np.abs(ph.u_of_v(vq, gam)) + us, np.abs(phi))
+    if P.viscous:
+        Tq = np.einsum("q,qcj,qa->cja", W, np.abs(qq), np.abs(phi)) + \
+            np.einsum("q,qc,qaj->cja", W, np.abs(vq), np.abs(gphi))
+    for f in range(nf):
+        F = G.faces[f]
+        vf = F["phi"] @ vN.T
+        vhf = F["psi"] @ LN[f].T
+        tf = np.abs(0.5 * np.einsum("qcj,qj->qc", ph.flux_F(vhf, gam) + ph.flux_F(vf, gam), F["n"])) + \
+            np.abs(0.5 * np.einsum("qab,qb->qa", ph.sigma_slf(vhf, F["n"], gam), vf - vhf))
+        if P.viscous:
+            qf = np.einsum("qa,cja->qcj", F["phi"], qN)
+            tf = tf + np.abs(ph.ghat(vhf, qf, F["n"], gam, P.mu, P.Pr))
+            Tq = Tq + np.einsum("q,qc,qj,qa->cja", np.abs(F["W"]), np.abs(vhf), np.abs(F["n"]), np.abs(F["phi"]))
+        Tv = Tv + np.einsum("q,qc,qa->ca", np.abs(F["W"]), tf, np.abs(F["phi"]))
+    out = Tv.reshape(-1)
+    if P.viscous:
+        out = np.concatenate([out, Tq.reshape(-1)])
+    return float(np.linalg.norm(out))
+
+
+def rloc_err(disc, inp, gpu_R, ref_R):
+    """max over elements of ||R_gpu - R_oracle|| / (sum-of-magnitudes scale)."""
+    worst = 0.0
+    for e in range(gpu_R.shape[0]):
+        x, lam, us, _ = disc.elem_inputs(e, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
+        s = residual_term_scale(disc, e, x, lam, us)
+        worst = max(worst, float(np.linalg.norm(gpu_R[e] - ref_R[e])) / s)
+    return worst

@@ -1,0 +1,154 @@
+"""GPU path vs the FP64 oracle, element by element, through the C ABI.
+
+Bar (FP64 path): per element ||X_gpu - X_oracle||_F / ||X_oracle||_F <= 1e-12 for
+the pure evaluations R_tr, A, B, C, D and for the condensed outputs S, g, Y, z;
+max over elements.  R_loc nearly cancels (states close to a discrete steady
+state), so its error is measured against the sum of magnitudes of its
+quadrature contributions (cases.residual_term_scale), also at 1e-12.
+"""
+import numpy as np
+import pytest
+
+from oracle import hdg as ohdg
+from oracle import state as ostate
+
+from cases import SMALL_CASES, colmajor, gpu_plan, oracle_case, rel_err_per_elem, rloc_err, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def test_mfma_layout_selftest(torch):
+    from paper_1808_05066_amd.hdg import selftest
+    assert selftest() == 0.0
+
+
+_cache = {}
+
+
+def _case(name):
+    if name not in _cache:
+        wl = SMALL_CASES[name]()
+        disc, inp = oracle_case(wl)
+        blocks = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"],
+                                        keep_blocks=True)
+        _cache[name] = (wl, disc, inp, blocks)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+def test_assemble_blocks_match_oracle(torch, name):
+    wl, disc, inp, blocks = _case(name)
+    print("case", name, flush=True)
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().max()) == 0
+    errs = {
+        "R_loc": rloc_err(disc, inp, out["R_loc"].cpu().numpy(), np.stack([b["R_loc"] for b in blocks])),
+        "R_tr": rel_err_per_elem(out["R_tr"].cpu().numpy(), np.stack([b["R_tr"] for b in blocks])),
+        "A": rel_err_per_elem(out["A"].cpu().numpy(), colmajor([b["A"] for b in blocks])),
+        "B": rel_err_per_elem(out["B"].cpu().numpy(), colmajor([b["B"] for b in blocks])),
+        "C": rel_err_per_elem(out["C"].cpu().numpy(), colmajor([b["C"] for b in blocks])),
+        "D": rel_err_per_elem(out["D"].cpu().numpy(), colmajor([b["D"] for b in blocks])),
+    }
+    print(name, errs)
+    for key, err in errs.items():
+        assert err <= TOL, (key, err)
+
+
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+@pytest.mark.parametrize("chunk", [0, 3])
+def test_condense_matches_oracle(torch, name, chunk):
+    wl, disc, inp, blocks = _case(name)
+    print("case", name, "chunk", chunk, flush=True)
+    plan = gpu_plan(wl, chunk_elems=chunk)
+    d = to_dev(inp)
+    out = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], residuals=True)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().max()) == 0
+    errs = {
+        "S": rel_err_per_elem(out["S"].cpu().numpy(), colmajor([b["S"] for b in blocks])),
+        "Y": rel_err_per_elem(out["Y"].cpu().numpy(), colmajor([b["Y"] for b in blocks])),
+        "g": rel_err_per_elem(out["g"].cpu().numpy(), np.stack([b["g"] for b in blocks])),
+        "z": rel_err_per_elem(out["z"].cpu().numpy(), np.stack([b["z"] for b in blocks])),
+        "R_loc": rloc_err(disc, inp, out["R_loc"].cpu().numpy(), np.stack([b["R_loc"] for b in blocks])),
+        "R_tr": rel_err_per_elem(out["R_tr"].cpu().numpy(), np.stack([b["R_tr"] for b in blocks])),
+    }
+    print(name, errs)
+    for key, err in errs.items():
+        assert err <= TOL, (key, err)
+
+
+@pytest.mark.parametrize("name", ["euler2d_tri_p2", "ns2d_tri_p2", "ns3d_hex_p1"])
+def test_trace_operator_backsolve_and_brute_force(torch, name):
+    """Condensed solve with GPU S, g + GPU back-solve == oracle brute-force full solve."""
+    import scipy.sparse.linalg as spla
+    wl, disc, inp, blocks = _case(name)
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    out = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    S = out["S"].cpu().numpy()
+    g = out["g"].cpu().numpy()
+    m, nt = disc.m, wl.n_trace
+    # matrix-free operator and right-hand side vs the oracle's
+    x = np.random.default_rng(3).normal(size=(m, nt))
+    y = plan.trace_matvec(out["S"], torch.from_numpy(x).cuda()).cpu().numpy()
+    y_ref = ohdg.trace_matvec(disc, [b["S"] for b in blocks], x.reshape(-1)).reshape(m, nt)
+    assert np.linalg.norm(y - y_ref) <= 1e-12 * np.linalg.norm(y_ref)
+    r = plan.trace_rhs(out["g"]).cpu().numpy()
+    r_ref = ohdg.trace_rhs(disc, [b["g"] for b in blocks]).reshape(m, nt)
+    assert np.linalg.norm(r - r_ref) <= 1e-12 * np.linalg.norm(r_ref)
+    # global solve on the host from the GPU blocks, then GPU back-solve
+    K = ohdg.trace_matrix(disc, [Si.T for Si in S]).tocsc()
+    dl = spla.spsolve(K, r.reshape(-1))
+    dv, dq = plan.backsolve(out["Y"], out["z"], torch.from_numpy(dl.reshape(m, nt).copy()).cuda())
+    bx, bl = ohdg.brute_force_solve(disc, blocks)
+    assert np.linalg.norm(dl - bl) <= 1e-10 * np.linalg.norm(bl)
+    dv = dv.cpu().numpy()
+    Np = disc.Np
+    for e in range(0, wl.mesh.n_elem, max(1, wl.mesh.n_elem // 7)):
+        ref = bx[e]
+        got = dv[:, e * Np:(e + 1) * Np].reshape(-1)
+        if wl.viscous:
+            got = np.concatenate([got, dq.cpu().numpy()[:, e * Np:(e + 1) * Np].reshape(-1)])
+        assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", ["euler2d_tri_p2", "ns3d_hex_p2"])
+def test_prepare_state_and_node_coords(torch, name):
+    wl, disc, inp, _ = _case(name)
+    plan = gpu_plan(wl)
+    x, xt = plan.node_coords()
+    assert np.allclose(x.cpu().numpy(), inp["xn"], rtol=0, atol=1e-14 * np.abs(inp["xn"]).max())
+    assert np.allclose(xt.cpu().numpy(), inp["xt"], rtol=0, atol=1e-14 * np.abs(inp["xt"]).max())
+    prim = torch.from_numpy(inp["prim"]).cuda()
+    grad = torch.from_numpy(inp["grad"]).cuda() if inp["grad"] is not None else None
+    v, q, u = plan.prepare_state(prim, grad, want_u=True)
+    v_ref, q_ref = ostate.entropy_state(inp["prim"], inp["grad"], wl.gamma)
+    assert np.abs(v.cpu().numpy() - v_ref).max() <= 1e-13 * np.abs(v_ref).max()
+    if q is not None:
+        assert np.abs(q.cpu().numpy() - q_ref).max() <= 1e-12 * np.abs(q_ref).max()
+    u_ref = ostate.conservative_state(inp["prim"], wl.gamma)
+    assert np.abs(u.cpu().numpy() - u_ref).max() <= 1e-14 * np.abs(u_ref).max()
+
+
+def test_nonphysical_state_is_flagged(torch):
+    wl, disc, inp, _ = _case("euler2d_tri_p2")
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    bad = 17
+    d["v"][-1, bad * disc.Np:(bad + 1) * disc.Np] = 0.5       # v_m >= 0: not a physical state
+    out = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    st = out["status"].cpu().numpy()
+    assert st[bad] == -3
+    assert np.count_nonzero(st) == 1
