@@ -1,0 +1,195 @@
+#!/usr/bin/env python
+"""Throughput of the entropy-variable hybridized DG hot path on one MI355X.
+
+A step is one pass of the hot path over the whole mesh:
+  hdg_assemble_condense  (pointwise physics + Jacobians, block assembly,
+                          LU, triangular solves, Schur complement)
+  hdg_trace_rhs          (condensed right-hand side)
+  hdg_trace_matvec       (one application of the condensed trace operator)
+  hdg_backsolve          (local back-solve with the right-hand side as the
+                          trace update; the global solve is not part of a step)
+Inputs are resident in HBM before the timed region.  The value is elements per
+second of whole steps.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from workloads import configs as C  # noqa: E402
+
+METRIC = "elem/s local Jacobian+static condensation; FP64 vs mixed-prec at 1e-10 resid"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "ns3d_hex_p2_16": ("3D Navier-Stokes, 16^3 periodic trilinear hexes on [0,2pi]^3 (jitter 5%), p=2, "
+                       "Re=1600, Pr=0.72, Mach 0.1 Taylor-Green + 2% noise, DIRK(3,3) stage mass term",
+                       lambda: C.ns3d_hex(n=16, p=2)),
+    "euler2d_tri_p2_8": ("2D Euler, unit square 8x8 split into 128 triangles (jitter 10%), p=2, Shu vortex "
+                         "+ 1% noise, Dirichlet-trace boundary", lambda: C.euler2d_tri_p2()),
+}
+
+
+def flops_per_elem(n, k, Np, Nq, m, d, viscous):
+    """Algorithmic flops of each phase for one element (dense formulas)."""
+    slots = m * m + m * d * m + (m * d * m * d + d * d + 1 if viscous else 0)
+    return {
+        "contract": 2.0 * Nq * Np * Np * slots,
+        "lu": 2.0 * n ** 3 / 3.0,
+        "solve": 2.0 * n * n * (k + 1),
+        "schur": 2.0 * k * n * (k + 1),
+    }
+
+
+def prepare_inputs(plan, wl, torch):
+    x, xt = plan.node_coords()
+    s = wl.sample(x.cpu().numpy(), xt.cpu().numpy())
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    v, q, _ = plan.prepare_state(dev(s["prim"]), dev(s["grad"]) if wl.viscous else None)
+    vhat, _, _ = plan.prepare_state(dev(s["prim_hat"]))
+    _, _, ustar = plan.prepare_state(dev(s["prim_star"]), want_u=True)
+    vbc = None
+    if np.any(wl.face_bc):
+        vbc, _, _ = plan.prepare_state(dev(s["prim_bc"]))
+    torch.cuda.synchronize()
+    return dict(v=v, q=q, vhat=vhat, ustar=ustar, vbc=vbc)
+
+
+def cpu_baseline(wl, seconds_budget=20.0):
+    """Time the FP64 oracle on a bounded element sample of the same workload (1 BLAS thread)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hdg as ohdg
+    from oracle import state as ostate
+    disc = ohdg.Discretization(wl.mesh, wl.p, ohdg.Phys(wl.gamma, wl.mu, wl.Pr, wl.alpha, wl.viscous),
+                               wl.tmap, wl.n_trace, wl.face_bc)
+    inp = ostate.oracle_inputs_fast(wl, disc)
+    rng = np.random.default_rng(0)
+    order = rng.permutation(wl.mesh.n_elem)
+    done, t_used = 0, 0.0
+    with threadpool_limits(limits=1):
+        while t_used < seconds_budget and done < wl.mesh.n_elem:
+            e = int(order[done])
+            t0 = time.perf_counter()
+            ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"], elems=[e])
+            t_used += time.perf_counter() - t0
+            done += 1
+    return {"value": done / t_used, "unit": "elem/s", "cores": 1, "kind": "oracle",
+            "sample": "%d seeded-random elements of the same mesh, residual + complex-step Jacobian + "
+                      "LAPACK condensation, 1 BLAS thread, %.1f s" % (done, t_used)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ns3d_hex_p2_16", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the per-element work shards by element partition; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_1808_05066_amd.hdg import Plan
+
+    desc, make = WORKLOADS[args.workload]
+    wl = make()
+    print("[bench] workload %s: %d elements, building plan" % (args.workload, wl.mesh.n_elem),
+          file=sys.stderr, flush=True)
+    plan = Plan(wl.mesh.etype, wl.p, wl.mesh.elem_xyz, wl.tmap, wl.n_trace, wl.face_bc, viscous=wl.viscous,
+                gamma=wl.gamma, mu=wl.mu, Pr=wl.Pr, alpha=wl.alpha)
+    inp = prepare_inputs(plan, wl, torch)
+    out = plan.alloc_outputs()
+    E, n, k = plan.n_elem, plan.n, plan.k
+    r = torch.empty(plan.m, plan.n_trace, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(r)
+    dv = torch.empty(plan.m, plan.n_nodes, dtype=torch.float64, device="cuda")
+    dq = torch.empty(plan.m * plan.dim, plan.n_nodes, dtype=torch.float64, device="cuda") if wl.viscous else None
+
+    def step():
+        plan.assemble_condense(inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"], out=out)
+        plan.trace_rhs(out["g"], r)
+        plan.trace_matvec(out["S"], r, y)
+        plan.backsolve(out["Y"], out["z"], r, dv, dq)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    bad = int((out["status"] != 0).sum())
+    if bad:
+        print("[bench] %d elements reported a non-OK status" % bad, file=sys.stderr)
+        sys.exit(1)
+    print("[bench] warmup done, timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = E / (ms / 1e3)
+
+    # per-kernel durations from HIP events recorded by the library on the launch stream
+    plan.set_timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ph = plan.phase_times()
+    plan.set_timing(False)
+    avg = {name: (t / c if c else 0.0) for name, (t, c) in ph.items()}
+    fl = flops_per_elem(n, k, plan.Np, plan.Nq, plan.m, plan.dim, wl.viscous)
+    fl["condense"] = fl["lu"] + fl["solve"] + fl["schur"]
+    dom = max(avg, key=avg.get)
+    if dom in fl and dom != "contract":
+        achieved = fl[dom] * E / (avg[dom] / 1e3) / 1e12
+        roof = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "flops_per_elem": fl[dom], "elems_per_launch": E, "avg_ms": avg[dom]}
+    else:
+        achieved = fl.get(dom, 0.0) * E / (avg[dom] / 1e3) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "flops_per_elem": fl.get(dom), "elems_per_launch": E, "avg_ms": avg[dom]}
+    dense = fl["condense"]
+    dense_ms = sum(avg[p] for p in ("lu", "solve", "schur", "condense"))
+    cond_ms = avg["points"] + avg["contract"] + dense_ms
+    res = {
+        "metric": METRIC, "value": value, "unit": "elem/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "elements": E, "n": n, "k": k,
+                   "p": wl.p, "precision": "fp64"},
+        "roofline": roof,
+        "phase_ms": {p: round(v, 4) for p, v in avg.items()},
+        "condense_elem_per_s": E / (cond_ms / 1e3),
+        "dense_tflops": dense * E / (dense_ms / 1e3) / 1e12,
+        "condensed_GBps": E * (k * k + k) * 8 / (cond_ms / 1e3) / 1e9,
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

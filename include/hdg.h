@@ -89,9 +89,14 @@ typedef struct {
   int n_trace;             /* number of global trace nodes */
 } hdg_mesh;
 
+enum { HDG_FLAG_SPLIT_DENSE = 1 };
+
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */
   int precision;           /* HDG_FP64 (others reserved) */
+  int flags;               /* HDG_FLAG_SPLIT_DENSE: separate LU / solve / Schur kernels
+                              instead of the fused left-looking one (default when its
+                              LDS block fits, n_pad <= 576) */
 } hdg_opts;
 
 typedef struct {
@@ -163,6 +168,16 @@ int hdg_trace_matvec(hdg_plan *plan, const double *S, const double *x, double *y
 
 /* Right-hand side of the condensed system r = sum_K P_K^T g_K ([m][n_trace]). */
 int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
+
+/* Optional per-phase timing with HIP events recorded on the call's stream
+ * around each kernel group: 0 points (pointwise physics), 1 contract (block
+ * assembly), 2 LU, 3 triangular solves, 4 Schur product (split dense path),
+ * 5 back-solve, 6 trace operator, 7 trace right-hand side, 8 fused
+ * condensation (LU + solves + Schur in one kernel).  Enabling resets the
+ * totals; hdg_plan_phase_times returns accumulated milliseconds and call
+ * counts (n >= 9 entries) and synchronizes on the last recorded events. */
+int hdg_plan_set_timing(hdg_plan *plan, int enable);
+int hdg_plan_phase_times(hdg_plan *plan, double *ms, long *calls, int n);
 
 /* Device self-check of the FP64 matrix-core operand layout the dense kernels
  * rely on (one 16x16x4 product against a scalar loop); *max_err receives the

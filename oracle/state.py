@@ -50,3 +50,32 @@ def oracle_inputs(wl, disc):
     ustar = conservative_state(s["prim_star"], wl.gamma)
     vbc, _ = entropy_state(s["prim_bc"], None, wl.gamma)
     return dict(v=v, q=q, vhat=vhat, ustar=ustar, vbc=vbc, xn=xn, xt=xt, **s)
+
+
+def node_coords(disc):
+    """(d, E*Np) element node coordinates via the oracle's vertex maps (all elements at once)."""
+    from .geometry import shape_functions
+    N, _ = shape_functions(disc.ref.etype, disc.ref.nodes)          # (Np, nv)
+    x = np.einsum("av,evi->eai", N, disc.mesh.elem_xyz)             # (E, Np, d)
+    return x.reshape(-1, disc.d).T.copy()
+
+
+def trace_coords(disc, xn):
+    """(d, n_trace) trace node coordinates from the element node coordinates."""
+    X = np.full((disc.d, disc.n_trace), np.nan)
+    fn = np.stack(disc.ref.face_nodes)                               # (nf, Nfp)
+    idx = (np.arange(disc.mesh.n_elem)[:, None, None] * disc.Np + fn[None]).reshape(-1)
+    X[:, disc.tmap.reshape(-1)] = xn[:, idx]
+    return X
+
+
+def oracle_inputs_fast(wl, disc):
+    """oracle_inputs without per-element geometry objects (large meshes)."""
+    xn = node_coords(disc)
+    xt = trace_coords(disc, xn)
+    s = wl.sample(xn, xt)
+    v, q = entropy_state(s["prim"], s["grad"], wl.gamma)
+    vhat, _ = entropy_state(s["prim_hat"], None, wl.gamma)
+    ustar = conservative_state(s["prim_star"], wl.gamma)
+    vbc, _ = entropy_state(s["prim_bc"], None, wl.gamma)
+    return dict(v=v, q=q, vhat=vhat, ustar=ustar, vbc=vbc, xn=xn, xt=xt, **s)

@@ -13,6 +13,8 @@ HDG_OK, HDG_EINVAL, HDG_EUNSUPPORTED, HDG_ENONPHYS, HDG_ESINGULAR, HDG_EHIP, HDG
 ERROR_NAMES = {0: "HDG_OK", -1: "HDG_EINVAL", -2: "HDG_EUNSUPPORTED", -3: "HDG_ENONPHYS",
                -4: "HDG_ESINGULAR", -5: "HDG_EHIP", -6: "HDG_ENOMEM"}
 ETYPES = {"tri": 0, "quad": 1, "tet": 2, "hex": 3}
+PHASES = ["points", "contract", "lu", "solve", "schur", "backsolve", "matvec", "rhs", "condense"]
+FLAG_SPLIT_DENSE = 1
 
 
 class hdg_phys(ctypes.Structure):
@@ -27,7 +29,7 @@ class hdg_mesh(ctypes.Structure):
 
 
 class hdg_opts(ctypes.Structure):
-    _fields_ = [("chunk_elems", ctypes.c_int), ("precision", ctypes.c_int)]
+    _fields_ = [("chunk_elems", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int)]
 
 
 class hdg_dims(ctypes.Structure):
@@ -52,6 +54,8 @@ SIGNATURES = {
     "hdg_trace_matvec": (I, [P, P, P, P, P]),
     "hdg_trace_rhs": (I, [P, P, P, P]),
     "hdg_selftest": (I, [ctypes.POINTER(ctypes.c_double)]),
+    "hdg_plan_set_timing": (I, [P, I]),
+    "hdg_plan_phase_times": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long), I]),
     "hdg_last_error": (ctypes.c_char_p, []),
 }
 

@@ -172,9 +172,9 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   D.viscous = phys->viscous ? 1 : 0;
   D.n = M * R.Np * (D.viscous ? (1 + d) : 1);
   D.k = R.nf * M * R.Nfp;
-  D.n_pad = roundup(D.n, 16);
+  D.n_pad = roundup(D.n, 32);
   D.k_pad = roundup(D.k, 16);
-  D.kx = D.k_pad + 16;
+  D.kx = roundup(D.k_pad + 1, 32);
   D.n_elem = E;
   D.n_trace = mesh->n_trace;
   D.gamma = phys->gamma;
@@ -185,6 +185,9 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
     delete P;
     return fail(HDG_EUNSUPPORTED, "local block larger than 1024 is not built in this version");
   }
+  // fused left-looking condensation when its 32-column LDS block fits
+  P->fused = condense_lds_bytes(D.n_pad) <= 160 * 1024;
+  if (opts && (opts->flags & HDG_FLAG_SPLIT_DENSE)) P->fused = false;
   PointLayout &L = D.L;
   int o = 0;
   L.Mv = o; o += M * M;
@@ -211,7 +214,45 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   return HDG_OK;
 }
 
-extern "C" void hdg_plan_destroy(hdg_plan *plan) { delete reinterpret_cast<Plan *>(plan); }
+extern "C" void hdg_plan_destroy(hdg_plan *plan) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P) return;
+  for (int i = 0; i < PH_COUNT; ++i)
+    for (int j = 0; j < 2; ++j)
+      if (P->ev[i][j]) (void)hipEventDestroy(P->ev[i][j]);
+  delete P;
+}
+
+extern "C" int hdg_plan_set_timing(hdg_plan *plan, int enable) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P) return fail(HDG_EINVAL, "null plan");
+  P->timing = enable != 0;
+  for (int i = 0; i < PH_COUNT; ++i) {
+    P->phase_ms[i] = 0.0;
+    P->phase_calls[i] = 0;
+    P->ev_pending[i] = false;
+  }
+  return HDG_OK;
+}
+
+extern "C" int hdg_plan_phase_times(hdg_plan *plan, double *ms, long *calls, int n) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !ms || n < PH_COUNT) return fail(HDG_EINVAL, "null argument or n < phase count");
+  for (int i = 0; i < PH_COUNT; ++i) {
+    if (P->ev_pending[i]) {
+      hipError_t e = hipEventSynchronize(P->ev[i][1]);
+      float t = 0.f;
+      if (!e) e = hipEventElapsedTime(&t, P->ev[i][0], P->ev[i][1]);
+      if (e) return hip_fail(e, "phase_times");
+      P->phase_ms[i] += t;
+      P->phase_calls[i] += 1;
+      P->ev_pending[i] = false;
+    }
+    ms[i] = P->phase_ms[i];
+    if (calls) calls[i] = P->phase_calls[i];
+  }
+  return HDG_OK;
+}
 
 extern "C" int hdg_plan_dims(const hdg_plan *plan, hdg_dims *o) {
   if (!plan || !o) return fail(HDG_EINVAL, "null argument");
@@ -362,10 +403,42 @@ extern "C" int hdg_prepare_state(const hdg_plan *plan, int N, const double *prim
 
 namespace {
 
+// Accumulate the elapsed time of the previous launch of a phase (events are
+// reused, so the previous interval is read before recording a new one).
+hipError_t phase_begin(Plan *P, int ph, hipStream_t s) {
+  if (!P->timing) return hipSuccess;
+  hipError_t e = hipSuccess;
+  if (!P->ev[ph][0]) {
+    e = hipEventCreate(&P->ev[ph][0]);
+    if (!e) e = hipEventCreate(&P->ev[ph][1]);
+    if (e) return e;
+  }
+  if (P->ev_pending[ph]) {
+    e = hipEventSynchronize(P->ev[ph][1]);
+    float ms = 0.f;
+    if (!e) e = hipEventElapsedTime(&ms, P->ev[ph][0], P->ev[ph][1]);
+    if (e) return e;
+    P->phase_ms[ph] += ms;
+    P->phase_calls[ph] += 1;
+    P->ev_pending[ph] = false;
+  }
+  return hipEventRecord(P->ev[ph][0], s);
+}
+
+hipError_t phase_end(Plan *P, int ph, hipStream_t s) {
+  if (!P->timing) return hipSuccess;
+  P->ev_pending[ph] = true;
+  return hipEventRecord(P->ev[ph][1], s);
+}
+
 int run_front(Plan *P, const double *v, const double *q, const double *vhat, const double *ustar,
               const double *vbc, int32_t *status, int e0, int ec, hipStream_t s) {
-  hipError_t e = launch_points(P->dp, e0, ec, v, q, vhat, ustar, vbc, status, s);
+  hipError_t e = phase_begin(P, PH_POINTS, s);
+  if (!e) e = launch_points(P->dp, e0, ec, v, q, vhat, ustar, vbc, status, s);
+  if (!e) e = phase_end(P, PH_POINTS, s);
+  if (!e) e = phase_begin(P, PH_CONTRACT, s);
   if (!e) e = launch_contract(P->dp, e0, ec, s);
+  if (!e) e = phase_end(P, PH_CONTRACT, s);
   if (e) return hip_fail(e, "assemble");
   return HDG_OK;
 }
@@ -417,9 +490,22 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
     rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s);
     if (rc) return rc;
     e = launch_copy_resid(P->dp, e0, ec, Rloc, Rtr, s);
+    if (!e && P->fused) {
+      e = phase_begin(P, PH_CONDENSE, s);
+      if (!e) e = launch_condense(P->dp, e0, ec, status + e0, S, g, Y, z, s);
+      if (!e) e = phase_end(P, PH_CONDENSE, s);
+      if (e) return hip_fail(e, "condense");
+      continue;
+    }
+    if (!e) e = phase_begin(P, PH_LU, s);
     if (!e) e = launch_lu(P->dp, ec, status + e0, s);
+    if (!e) e = phase_end(P, PH_LU, s);
+    if (!e) e = phase_begin(P, PH_SOLVE, s);
     if (!e) e = launch_solve(P->dp, ec, s);
+    if (!e) e = phase_end(P, PH_SOLVE, s);
+    if (!e) e = phase_begin(P, PH_SCHUR, s);
     if (!e) e = launch_schur(P->dp, e0, ec, S, g, Y, z, Rloc, Rtr, s);
+    if (!e) e = phase_end(P, PH_SCHUR, s);
     if (e) return hip_fail(e, "condense");
   }
   return HDG_OK;
@@ -431,7 +517,10 @@ extern "C" int hdg_backsolve(hdg_plan *plan, const double *Y, const double *z, c
   if (!P) return HDG_EINVAL;
   if (!Y || !z || !dvhat || !dv) return fail(HDG_EINVAL, "Y, z, dvhat and dv are required");
   if (P->dp.viscous && !dq) return fail(HDG_EINVAL, "dq is required for Navier-Stokes");
-  hipError_t e = launch_backsolve(P->dp, Y, z, dvhat, dv, dq, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = phase_begin(P, PH_BACKSOLVE, s);
+  if (!e) e = launch_backsolve(P->dp, Y, z, dvhat, dv, dq, s);
+  if (!e) e = phase_end(P, PH_BACKSOLVE, s);
   if (e) return hip_fail(e, "backsolve");
   return HDG_OK;
 }
@@ -441,7 +530,10 @@ extern "C" int hdg_trace_matvec(hdg_plan *plan, const double *S, const double *x
   if (!P) return HDG_EINVAL;
   if (!S || !x || !y) return fail(HDG_EINVAL, "S, x and y are required");
   if (x == y) return fail(HDG_EINVAL, "x and y must not alias");
-  hipError_t e = launch_trace_matvec(P->dp, S, x, y, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = phase_begin(P, PH_MATVEC, s);
+  if (!e) e = launch_trace_matvec(P->dp, S, x, y, s);
+  if (!e) e = phase_end(P, PH_MATVEC, s);
   if (e) return hip_fail(e, "trace_matvec");
   return HDG_OK;
 }
@@ -450,7 +542,10 @@ extern "C" int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *s
   Plan *P = checked(plan);
   if (!P) return HDG_EINVAL;
   if (!g || !r) return fail(HDG_EINVAL, "g and r are required");
-  hipError_t e = launch_trace_rhs(P->dp, g, r, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = phase_begin(P, PH_RHS, s);
+  if (!e) e = launch_trace_rhs(P->dp, g, r, s);
+  if (!e) e = phase_end(P, PH_RHS, s);
   if (e) return hip_fail(e, "trace_rhs");
   return HDG_OK;
 }

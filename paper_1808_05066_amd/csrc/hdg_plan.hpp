@@ -45,8 +45,17 @@ struct DevPlan {
   int *ipiv;               // [chunk][n_pad]
 };
 
+// Phases timed with HIP events when phase timing is enabled.
+enum Phase { PH_POINTS = 0, PH_CONTRACT, PH_LU, PH_SOLVE, PH_SCHUR, PH_BACKSOLVE, PH_MATVEC, PH_RHS, PH_CONDENSE, PH_COUNT };
+
 struct Plan {
   RefTables ref;
+  bool timing = false;
+  bool fused = true;
+  hipEvent_t ev[PH_COUNT][2] = {};
+  bool ev_pending[PH_COUNT] = {};
+  double phase_ms[PH_COUNT] = {};
+  long phase_calls[PH_COUNT] = {};
   DevPlan dp{};
   hdg_phys phys{};
   int n_elem = 0, n_trace = 0, chunk = 0;
@@ -73,6 +82,9 @@ hipError_t launch_schur(const DevPlan &P, int e0, int ec, double *S, double *g, 
                         double *z, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_copy_resid(const DevPlan &P, int e0, int ec, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_mfma_selftest(double *out, hipStream_t s);
+size_t condense_lds_bytes(int np);
+hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
+                           double *z, hipStream_t s);
 hipError_t launch_export_blocks(const DevPlan &P, int e0, int ec, double *A, double *B, double *C,
                                 double *D, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_backsolve(const DevPlan &P, const double *Y, const double *z, const double *dvhat,

@@ -35,7 +35,7 @@ class Plan:
     """
 
     def __init__(self, etype, order, elem_xyz, trace_map, n_trace, face_bc=None, *, viscous=False,
-                 gamma=1.4, mu=0.0, Pr=0.72, alpha=0.0, chunk_elems=0, device="cuda"):
+                 gamma=1.4, mu=0.0, Pr=0.72, alpha=0.0, chunk_elems=0, split_dense=False, device="cuda"):
         torch = _torch()
         self.lib = _lib.load()
         self._xyz = np.ascontiguousarray(elem_xyz, dtype=np.float64)
@@ -46,7 +46,7 @@ class Plan:
                              None if self._fbc is None else self._fbc.ctypes.data,
                              self._tmap.ctypes.data, int(n_trace))
         phys = _lib.hdg_phys(int(bool(viscous)), float(gamma), float(mu), float(Pr), float(alpha))
-        opts = _lib.hdg_opts(int(chunk_elems), 0)
+        opts = _lib.hdg_opts(int(chunk_elems), 0, _lib.FLAG_SPLIT_DENSE if split_dense else 0)
         h = ctypes.c_void_p()
         check(self.lib.hdg_plan_create(ctypes.byref(h), ctypes.byref(mesh), ctypes.byref(phys),
                                        ctypes.byref(opts)), "hdg_plan_create")
@@ -129,9 +129,11 @@ class Plan:
             _stream()), "hdg_assemble_condense")
         return out
 
-    def backsolve(self, Y, z, dvhat):
-        dv = self._empty(self.m, self.n_nodes)
-        dq = self._empty(self.m * self.dim, self.n_nodes) if self.viscous else None
+    def backsolve(self, Y, z, dvhat, dv=None, dq=None):
+        if dv is None:
+            dv = self._empty(self.m, self.n_nodes)
+        if dq is None and self.viscous:
+            dq = self._empty(self.m * self.dim, self.n_nodes)
         check(self.lib.hdg_backsolve(self.h, _ptr(Y), _ptr(z), _ptr(dvhat), _ptr(dv), _ptr(dq), _stream()),
               "hdg_backsolve")
         return dv, dq
@@ -141,6 +143,17 @@ class Plan:
             y = self._empty(self.m, self.n_trace)
         check(self.lib.hdg_trace_matvec(self.h, _ptr(S), _ptr(x), _ptr(y), _stream()), "hdg_trace_matvec")
         return y
+
+    def set_timing(self, enable=True):
+        check(self.lib.hdg_plan_set_timing(self.h, int(bool(enable))), "hdg_plan_set_timing")
+
+    def phase_times(self):
+        """{phase: (total ms, calls)} accumulated since timing was enabled."""
+        n = len(_lib.PHASES)
+        ms = (ctypes.c_double * n)()
+        calls = (ctypes.c_long * n)()
+        check(self.lib.hdg_plan_phase_times(self.h, ms, calls, n), "hdg_plan_phase_times")
+        return {name: (ms[i], calls[i]) for i, name in enumerate(_lib.PHASES)}
 
     def trace_rhs(self, g, r=None):
         if r is None:

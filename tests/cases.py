@@ -16,10 +16,11 @@ def oracle_case(wl):
     return disc, ostate.oracle_inputs(wl, disc)
 
 
-def gpu_plan(wl, chunk_elems=0):
+def gpu_plan(wl, chunk_elems=0, split_dense=False):
     from paper_1808_05066_amd.hdg import Plan
     return Plan(wl.mesh.etype, wl.p, wl.mesh.elem_xyz, wl.tmap, wl.n_trace, wl.face_bc, viscous=wl.viscous,
-                gamma=wl.gamma, mu=wl.mu, Pr=wl.Pr, alpha=wl.alpha, chunk_elems=chunk_elems)
+                gamma=wl.gamma, mu=wl.mu, Pr=wl.Pr, alpha=wl.alpha, chunk_elems=chunk_elems,
+                split_dense=split_dense)
 
 
 def to_dev(inp):
@@ -109,3 +110,15 @@ def rloc_err(disc, inp, gpu_R, ref_R):
         s = residual_term_scale(disc, e, x, lam, us)
         worst = max(worst, float(np.linalg.norm(gpu_R[e] - ref_R[e])) / s)
     return worst
+
+
+def z_backward_err(disc, inp, e, A, R_loc, z_gpu):
+    """||A z_gpu - R_loc|| over the summation scale of R_loc (element e, oracle A and R_loc).
+
+    z = A^-1 R_loc inherits the cancellation of R_loc; two correct FP64 codes agree
+    on z only to the rounding of R_loc amplified by A^-1, so z is judged by how
+    well it solves A z = R_loc measured in R_loc's own scale.
+    """
+    x, lam, us, _ = disc.elem_inputs(e, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
+    s = residual_term_scale(disc, e, x, lam, us)
+    return float(np.linalg.norm(A @ z_gpu - R_loc)) / s

@@ -34,7 +34,7 @@ def _create(lib, wl, **kw):
                          kw.get("n_elem", wl.mesh.n_elem), xyz.ctypes.data, fbc.ctypes.data, tm.ctypes.data,
                          kw.get("n_trace", wl.n_trace))
     phys = _lib.hdg_phys(int(wl.viscous), kw.get("gamma", wl.gamma), wl.mu, wl.Pr, wl.alpha)
-    opts = _lib.hdg_opts(kw.get("chunk", 0), kw.get("precision", 0))
+    opts = _lib.hdg_opts(kw.get("chunk", 0), kw.get("precision", 0), 0)
     h = ctypes.c_void_p()
     rc = lib.hdg_plan_create(ctypes.byref(h), ctypes.byref(mesh), ctypes.byref(phys), ctypes.byref(opts))
     return rc, h, (xyz, tm, fbc)
