@@ -94,9 +94,11 @@ enum { HDG_FLAG_SPLIT_DENSE = 1 };
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */
   int precision;           /* HDG_FP64 (others reserved) */
-  int flags;               /* HDG_FLAG_SPLIT_DENSE: separate LU / solve / Schur kernels
-                              instead of the fused left-looking one (default when its
-                              LDS block fits, n_pad <= 576) */
+  int flags;               /* HDG_FLAG_SPLIT_DENSE: the reference kernel variants (VALU
+                              block contraction; separate LU / solve / Schur kernels)
+                              instead of the matrix-core contraction and the fused
+                              left-looking condensation used by default when their LDS
+                              working sets fit */
 } hdg_opts;
 
 typedef struct {

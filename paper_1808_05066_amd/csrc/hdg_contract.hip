@@ -1,0 +1,336 @@
+// Element block assembly on matrix cores (volume) plus face-local products.
+//
+// Volume part of the element rows (weak forms of the element equation):
+//   A[(c,a),(g,b)] = sum_qp T[(g,c,a), qp] phi_b(qp),  column group g = c' (v columns)
+//   or g = m + s (q columns), with
+//   T = W alpha A0_{c c'} phi_a + sum_r Kv_{c r c'} dphi_{r a}     (g < m)
+//   T = sum_r Kq_{c r s} dphi_{r a}                                 (g >= m)
+// is a GEMM with M = (groups x m x Np) rows, K = N_q, N = Np, run on FP64 MFMA
+// with the basis tables and a 4-point slice of the pointwise coefficients
+// staged in LDS.  Face f contributes small products
+//   T_f[(.,.), ia, ib] = sum_fq coef(fq) psi_ia(fq) psi_ib(fq)
+// that are formed once and scattered into A (added), B, C and D; the gradient
+// rows (mass and divergence matrices) are formed once and copied per component.
+#include "hdg_plan.hpp"
+
+namespace hdg {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;
+
+__device__ inline d4 mfma4(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int D, bool VISC, int NCT>
+__global__ __launch_bounds__(NT) void k_contract_mfma(DevPlan P, int e0, int ec) {
+  constexpr int M = D + 2;
+  constexpr int G = VISC ? M + M * D : M;   // column groups
+  constexpr int RT = (NCT == 1) ? 16 : 8;   // row tiles per wave per pass
+  extern __shared__ double lds[];
+  const int el = blockIdx.x, e = e0 + el;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int Np = P.Np, Nq = P.Nq, nf = P.nf, Nfp = P.Nfp, Nfq = P.Nfq;
+  const int Nq4 = (Nq + 3) & ~3;
+  const int np = P.n_pad, kp = P.k_pad, kx = P.kx;
+  const PointLayout L = P.L;
+  double *A = P.A + (size_t)el * np * np;
+  double *X = P.X + (size_t)el * kx * np;
+  double *Cm = P.C + (size_t)el * np * kp;
+  double *Dm = P.D + (size_t)el * kp * kp;
+  double *Rt = P.Rt + (size_t)el * kp;
+  const double *pv = P.pv + (size_t)el * Nq * L.size;
+  const double *pf = P.pf + (size_t)el * nf * Nfq * L.fsize;
+  const int *fnodes = P.fnodes;
+  const int *fbc = P.face_bc + (size_t)e * nf;
+
+  // LDS: basis tables (zero-padded to Nq4 points, 16*NCT basis functions)
+  const int NB = 16 * NCT;
+  double *sphi = lds;                          // [Nq4][NB]
+  double *sdphi = sphi + Nq4 * NB;             // [D][Nq4][NB]
+  double *work = sdphi + D * Nq4 * NB;         // shared scratch
+  for (int t = tid; t < (1 + D) * Nq4 * NB; t += NT) {
+    const int b = t % NB, qp = (t / NB) % Nq4, r = t / (NB * Nq4);
+    double val = 0.0;
+    if (b < Np && qp < Nq) val = (r == 0) ? P.phi[qp * Np + b] : P.dphi[((size_t)(r - 1) * Nq + qp) * Np + b];
+    sphi[t] = val;
+  }
+  // zero fill: q rows and padding of A, X, C, D, R_tr
+  const int nv = M * Np;
+  for (size_t i = tid; i < (size_t)np * np; i += NT) {
+    const int col = (int)(i / np), row = (int)(i % np);
+    if (row >= nv || col >= P.n) A[i] = (row == col && row >= P.n) ? 1.0 : 0.0;
+  }
+  for (size_t i = tid; i < (size_t)kx * np; i += NT) X[i] = 0.0;
+  for (size_t i = tid; i < (size_t)np * kp; i += NT) Cm[i] = 0.0;
+  for (size_t i = tid; i < (size_t)kp * kp; i += NT) Dm[i] = 0.0;
+  for (int i = tid; i < kp; i += NT) Rt[i] = 0.0;
+  __syncthreads();
+
+  // ---- volume GEMM on MFMA
+  const int nrows = G * M * Np;
+  const int ntiles = (nrows + 15) / 16;
+  constexpr int CS = M * M + M * D * M + (VISC ? M * D * M * D : 0);  // coefficients per point
+  double *coef = work;                                                // [4][CS]
+  for (int base = 0; base < ntiles; base += 4 * RT) {
+    d4 acc[RT][NCT];
+#pragma unroll
+    for (int u = 0; u < RT; ++u)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < Nq4; q0 += 4) {
+      __syncthreads();
+      for (int t = tid; t < 4 * CS; t += NT) {
+        const int j = t % CS, qq = t / CS;
+        double val = 0.0;
+        if (q0 + qq < Nq) {
+          const double *w = pv + (size_t)(q0 + qq) * L.size;
+          if (j < M * M) val = w[L.Mv + j];
+          else if (j < M * M + M * D * M) val = w[L.Kv + (j - M * M)];
+          else val = w[L.Kq + (j - M * M - M * D * M)];
+        }
+        coef[t] = val;
+      }
+      __syncthreads();
+      const int qp = q0 + lk;
+      const double *cq = coef + lk * CS;
+#pragma unroll
+      for (int u = 0; u < RT; ++u) {
+        const int tile = base + wave * RT + u;
+        const int rho = tile * 16 + li;
+        double tval = 0.0;
+        if (tile < ntiles && rho < nrows) {
+          const int a = rho % Np, c = (rho / Np) % M, g = rho / (Np * M);
+          if (g < M) {
+            tval = cq[c * M + g] * sphi[qp * NB + a];
+#pragma unroll
+            for (int r = 0; r < D; ++r) tval += cq[M * M + (c * D + r) * M + g] * sdphi[(r * Nq4 + qp) * NB + a];
+          } else {
+            const int s = g - M;
+#pragma unroll
+            for (int r = 0; r < D; ++r)
+              tval += cq[M * M + M * D * M + (c * D + r) * (M * D) + s] * sdphi[(r * Nq4 + qp) * NB + a];
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = mfma4(tval, sphi[qp * NB + ct * 16 + li], acc[u][ct]);
+      }
+    }
+    // write the tiles: rows rho = (g, c, a), columns b
+#pragma unroll
+    for (int u = 0; u < RT; ++u) {
+      const int tile = base + wave * RT + u;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rho = tile * 16 + lk + 4 * r;
+        if (tile >= ntiles || rho >= nrows) continue;
+        const int a = rho % Np, c = (rho / Np) % M, g = rho / (Np * M);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const int b = ct * 16 + li;
+          if (b < Np) A[(size_t)(g * Np + b) * np + c * Np + a] = acc[u][ct][r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- gradient rows: G_j[a][b] = sum W dphi_j,a phi_b (physical), M[a][b] = sum W phi_a phi_b
+  if (VISC) {
+    double *gm = work;   // [(D+1)][Np][Np]
+    for (int t = tid; t < (D + 1) * Np * Np; t += NT) {
+      const int b = t % Np, a = (t / Np) % Np, j = t / (Np * Np);
+      double acc = 0.0;
+      for (int qp = 0; qp < Nq; ++qp) {
+        const double *w = pv + (size_t)qp * L.size;
+        if (j < D) {
+          double ta = 0.0;
+#pragma unroll
+          for (int r = 0; r < D; ++r) ta += w[L.WJ + r * D + j] * sdphi[(r * Nq4 + qp) * NB + a];
+          acc += ta * sphi[qp * NB + b];
+        } else {
+          acc += w[L.W] * sphi[qp * NB + a] * sphi[qp * NB + b];
+        }
+      }
+      gm[t] = acc;
+    }
+    __syncthreads();
+    for (int t = tid; t < M * D * Np * Np; t += NT) {
+      const int a = t % Np, b = (t / Np) % Np, cj = t / (Np * Np);
+      const int c = cj / D, j = cj % D;
+      const int row = nv + cj * Np + a;
+      A[(size_t)(c * Np + b) * np + row] = gm[(j * Np + a) * Np + b];
+      A[(size_t)(nv + cj * Np + b) * np + row] = gm[(D * Np + a) * Np + b];
+    }
+    __syncthreads();
+  }
+
+  // ---- element residual rows (column k_pad of X): volume parts
+  double *R = X + (size_t)kp * np;
+  for (int t = tid; t < M * Np; t += NT) {
+    const int a = t % Np, c = t / Np;
+    double acc = 0.0;
+    for (int qp = 0; qp < Nq; ++qp) {
+      const double *w = pv + (size_t)qp * L.size;
+      double ta = w[L.Wu + c] * sphi[qp * NB + a];
+#pragma unroll
+      for (int r = 0; r < D; ++r) ta += w[L.Fr + c * D + r] * sdphi[(r * Nq4 + qp) * NB + a];
+      acc += ta;
+    }
+    R[c * Np + a] = acc;
+  }
+  if (VISC) {
+    for (int t = tid; t < M * D * Np; t += NT) {
+      const int a = t % Np, cj = t / Np, c = cj / D, j = cj % D;
+      double acc = 0.0;
+      for (int qp = 0; qp < Nq; ++qp) {
+        const double *w = pv + (size_t)qp * L.size;
+        double ta = 0.0;
+#pragma unroll
+        for (int r = 0; r < D; ++r) ta += w[L.WJ + r * D + j] * sdphi[(r * Nq4 + qp) * NB + a];
+        acc += w[L.Wq + c * D + j] * sphi[qp * NB + a] + w[L.v + c] * ta;
+      }
+      R[nv + cj * Np + a] = acc;
+    }
+  }
+  __syncthreads();
+
+  // ---- faces, one at a time (A entries of edge nodes receive several faces)
+  const int MF = M * Nfp;
+  const int NP2 = Nfp * Nfp;
+  double *spf = work;                           // [Nfq][fsize]
+  double *spp = spf + Nfq * L.fsize;            // [Nfq][Nfp][Nfp]
+  double *sps = spp + Nfq * NP2;                // [Nfq][Nfp]
+  for (int f = 0; f < nf; ++f) {
+    const double *pff = pf + (size_t)f * Nfq * L.fsize;
+    for (int t = tid; t < Nfq * L.fsize; t += NT) spf[t] = pff[t];
+    const double *fp = P.fphi + (size_t)f * Nfq * Nfp;
+    for (int t = tid; t < Nfq * NP2; t += NT) {
+      const int ib = t % Nfp, ia = (t / Nfp) % Nfp, fq = t / NP2;
+      spp[t] = fp[fq * Nfp + ia] * fp[fq * Nfp + ib];
+    }
+    for (int t = tid; t < Nfq * Nfp; t += NT) sps[t] = fp[t];
+    __syncthreads();
+    const bool dir = fbc[f] != 0;
+    const int *fn = fnodes + f * Nfp;
+    // (c, c') blocks: A_vv += Tv, C_v = Tv (flux faces), B_v = Th, D = Th or mass
+    for (int t = tid; t < M * M * NP2; t += NT) {
+      const int ib = t % Nfp, ia = (t / Nfp) % Nfp, cc = t / NP2;
+      const int c = cc / M, cp = cc % M;
+      double tv = 0.0, th = 0.0, tw = 0.0;
+      for (int fq = 0; fq < Nfq; ++fq) {
+        const double pp = spp[fq * NP2 + ia * Nfp + ib];
+        const double *w = spf + fq * L.fsize;
+        tv += w[L.fFv + c * M + cp] * pp;
+        th += w[L.fFh + c * M + cp] * pp;
+        tw += w[L.fW] * pp;
+      }
+      const int a = fn[ia], b = fn[ib];
+      A[(size_t)(cp * Np + b) * np + c * Np + a] += tv;
+      X[(size_t)(f * MF + cp * Nfp + ib) * np + c * Np + a] = th;
+      Dm[(size_t)(f * MF + cp * Nfp + ib) * kp + f * MF + c * Nfp + ia] = dir ? (c == cp ? tw : 0.0) : th;
+      if (!dir) Cm[(size_t)(cp * Np + a) * kp + f * MF + c * Nfp + ib] = tv;
+    }
+    if (VISC) {
+      // (c, s) blocks: A_vq += Tq, C_q = Tq (flux faces)
+      for (int t = tid; t < M * M * D * NP2; t += NT) {
+        const int ib = t % Nfp, ia = (t / Nfp) % Nfp, cs = t / NP2;
+        const int c = cs / (M * D), s = cs % (M * D);
+        double tq = 0.0;
+        for (int fq = 0; fq < Nfq; ++fq)
+          tq += spf[fq * L.fsize + L.fFq + c * (M * D) + s] * spp[fq * NP2 + ia * Nfp + ib];
+        const int a = fn[ia], b = fn[ib];
+        A[(size_t)(nv + s * Np + b) * np + c * Np + a] += tq;
+        if (!dir) Cm[(size_t)(nv + s * Np + a) * kp + f * MF + c * Nfp + ib] = tq;
+      }
+      // B_q[(c, j, a), (f, c, b)] = -sum W n_j psi_a psi_b
+      for (int t = tid; t < D * NP2; t += NT) {
+        const int ib = t % Nfp, ia = (t / Nfp) % Nfp, j = t / NP2;
+        double tn = 0.0;
+        for (int fq = 0; fq < Nfq; ++fq) tn += spf[fq * L.fsize + L.fWn + j] * spp[fq * NP2 + ia * Nfp + ib];
+        for (int c = 0; c < M; ++c)
+          X[(size_t)(f * MF + c * Nfp + ib) * np + nv + (c * D + j) * Np + fn[ia]] = -tn;
+      }
+    }
+    // residual face terms
+    for (int t = tid; t < M * Nfp; t += NT) {
+      const int ia = t % Nfp, c = t / Nfp;
+      double rv = 0.0, rt = 0.0;
+      for (int fq = 0; fq < Nfq; ++fq) {
+        const double *w = spf + fq * L.fsize;
+        const double ps = sps[fq * Nfp + ia];
+        rv += w[L.fFf + c] * ps;
+        rt += (dir ? w[L.fFd + c] : w[L.fFf + c]) * ps;
+      }
+      R[c * Np + fn[ia]] += rv;
+      Rt[f * MF + c * Nfp + ia] = rt;
+    }
+    if (VISC) {
+      for (int t = tid; t < M * D * Nfp; t += NT) {
+        const int ia = t % Nfp, cj = t / Nfp, c = cj / D, j = cj % D;
+        double rq = 0.0;
+        for (int fq = 0; fq < Nfq; ++fq) {
+          const double *w = spf + fq * L.fsize;
+          rq += w[L.fWn + j] * w[L.fvh + c] * sps[fq * Nfp + ia];
+        }
+        R[nv + cj * Np + fn[ia]] -= rq;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int D, bool VISC, int NCT>
+size_t lds_bytes_t(const DevPlan &P) {
+  constexpr int M = D + 2;
+  const int Nq4 = (P.Nq + 3) & ~3;
+  const int NB = 16 * NCT;
+  const size_t tables = (size_t)(1 + D) * Nq4 * NB;
+  const size_t cs = (size_t)(M * M + M * D * M + (VISC ? M * D * M * D : 0));
+  size_t work = 4 * cs;
+  if (VISC) work = work > (size_t)(D + 1) * P.Np * P.Np ? work : (size_t)(D + 1) * P.Np * P.Np;
+  const size_t facew = (size_t)P.Nfq * P.L.fsize + (size_t)P.Nfq * P.Nfp * P.Nfp + (size_t)P.Nfq * P.Nfp;
+  if (facew > work) work = facew;
+  return (tables + work) * sizeof(double);
+}
+
+template <int D, bool VISC, int NCT>
+hipError_t launch_t(const DevPlan &P, int e0, int ec, hipStream_t s) {
+  const size_t lds = lds_bytes_t<D, VISC, NCT>(P);
+  hipError_t e = hipFuncSetAttribute((const void *)k_contract_mfma<D, VISC, NCT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e) return e;
+  hipLaunchKernelGGL((k_contract_mfma<D, VISC, NCT>), dim3(ec), dim3(NT), lds, s, P, e0, ec);
+  return hipGetLastError();
+}
+
+template <int D, bool VISC>
+size_t lds_for(const DevPlan &P) {
+  return P.Np <= 16 ? lds_bytes_t<D, VISC, 1>(P) : lds_bytes_t<D, VISC, 2>(P);
+}
+
+}  // namespace
+
+bool contract_mfma_supported(const DevPlan &P) {
+  if (P.Np > 32) return false;
+  size_t lds = 0;
+  if (P.dim == 2) lds = P.viscous ? lds_for<2, true>(P) : lds_for<2, false>(P);
+  else lds = P.viscous ? lds_for<3, true>(P) : lds_for<3, false>(P);
+  return lds <= 160 * 1024;
+}
+
+hipError_t launch_contract_mfma(const DevPlan &P, int e0, int ec, hipStream_t s) {
+  const bool one = P.Np <= 16;
+  if (P.dim == 2) {
+    if (P.viscous) return one ? launch_t<2, true, 1>(P, e0, ec, s) : launch_t<2, true, 2>(P, e0, ec, s);
+    return one ? launch_t<2, false, 1>(P, e0, ec, s) : launch_t<2, false, 2>(P, e0, ec, s);
+  }
+  if (P.viscous) return one ? launch_t<3, true, 1>(P, e0, ec, s) : launch_t<3, true, 2>(P, e0, ec, s);
+  return one ? launch_t<3, false, 1>(P, e0, ec, s) : launch_t<3, false, 2>(P, e0, ec, s);
+}
+
+}  // namespace hdg

@@ -210,6 +210,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   L.fFd = o; o += M;
   L.fW = o; o += 1;
   L.fsize = o;
+  P->contract_mfma = contract_mfma_supported(D) && !(opts && (opts->flags & HDG_FLAG_SPLIT_DENSE));
   *out = reinterpret_cast<hdg_plan *>(P);
   return HDG_OK;
 }
@@ -437,7 +438,7 @@ int run_front(Plan *P, const double *v, const double *q, const double *vhat, con
   if (!e) e = launch_points(P->dp, e0, ec, v, q, vhat, ustar, vbc, status, s);
   if (!e) e = phase_end(P, PH_POINTS, s);
   if (!e) e = phase_begin(P, PH_CONTRACT, s);
-  if (!e) e = launch_contract(P->dp, e0, ec, s);
+  if (!e) e = P->contract_mfma ? launch_contract_mfma(P->dp, e0, ec, s) : launch_contract(P->dp, e0, ec, s);
   if (!e) e = phase_end(P, PH_CONTRACT, s);
   if (e) return hip_fail(e, "assemble");
   return HDG_OK;

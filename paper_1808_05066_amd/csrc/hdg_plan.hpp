@@ -52,6 +52,7 @@ struct Plan {
   RefTables ref;
   bool timing = false;
   bool fused = true;
+  bool contract_mfma = true;
   hipEvent_t ev[PH_COUNT][2] = {};
   bool ev_pending[PH_COUNT] = {};
   double phase_ms[PH_COUNT] = {};
@@ -83,6 +84,8 @@ hipError_t launch_schur(const DevPlan &P, int e0, int ec, double *S, double *g, 
 hipError_t launch_copy_resid(const DevPlan &P, int e0, int ec, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_mfma_selftest(double *out, hipStream_t s);
 size_t condense_lds_bytes(int np);
+bool contract_mfma_supported(const DevPlan &P);
+hipError_t launch_contract_mfma(const DevPlan &P, int e0, int ec, hipStream_t s);
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s);
 hipError_t launch_export_blocks(const DevPlan &P, int e0, int ec, double *A, double *B, double *C,
