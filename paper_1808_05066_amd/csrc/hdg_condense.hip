@@ -34,10 +34,11 @@ __device__ inline d4 mfma4(double a, double b, d4 c) {
 
 struct Lds {
   double *blk;   // [np][BS]
-  double *tri;   // [W][BS]
+  double *prow;  // [W] pivot row
+  double *tmp;   // [W] displaced row
   int *perm;     // [np]
-  double *redv;  // [NW]
-  int *redi;     // [NW]
+  double *redv;  // [2][NW]
+  int *redi;     // [2][NW]
 };
 
 // blk[i][c] = M[(c0 + c) * ld + perm[i]]  (gathered through the permutation)
@@ -55,37 +56,56 @@ __device__ inline void store_block(const Lds &s, double *M, int ld, int c0, int 
   }
 }
 
-// Stage the 32 x 32 diagonal block of the stored factors at rows / columns p0.
-__device__ inline void stage_tri(const Lds &s, const double *A, int ld, int p0) {
-  for (int t = threadIdx.x; t < W * W; t += NT) {
-    const int kk = t / W, i = t - kk * W;
-    s.tri[i * BS + kk] = A[(size_t)(p0 + kk) * ld + s.perm[p0 + i]];
+// Rows p0..p0+31 of the block <- Inv * rows, Inv the stored inverse of the unit-lower
+// (L) or upper (U) 32 x 32 diagonal block of the factors; four waves each form one
+// 16 x 16 tile on MFMA, then write back after a barrier.
+__device__ inline void inv_apply(const Lds &s, const double *Inv, int p0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int ti = wave & 1, tj = (wave >> 1) & 1;
+  if (wave < 4) {
+    double a[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) a[kk] = Inv[(4 * kk + lk) * W + ti * 16 + li];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) acc = mfma4(a[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
+  }
+  __syncthreads();
+  if (wave < 4) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s.blk[(p0 + ti * 16 + lk + 4 * r) * BS + tj * 16 + li] = acc[r];
   }
 }
 
-// Rows p0..p0+31 of the block <- L_pp^-1 (unit lower) or U_pp^-1 (upper) times them.
-template <bool LOWER>
-__device__ inline void tri_solve(const Lds &s, int p0) {
-  const int tid = threadIdx.x;
-  if (tid < W) {
-    double x[W];
+// Inverses of the diagonal 32 x 32 blocks of the freshly factored panel (block rows
+// j0..j0+31): wave 0 inverts the unit-lower part, wave 1 the upper part; column c
+// of each inverse is solved by lane c.  Stored column-major (32 x 32) in Linv / Uinv.
+__device__ inline void invert_diag(const Lds &s, int j0, double *Linv, double *Uinv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane >= W || wave > 1) return;
+  const int c = lane;
+  double x[W];
+  if (wave == 0) {
 #pragma unroll
-    for (int i = 0; i < W; ++i) x[i] = s.blk[(p0 + i) * BS + tid];
-    if (LOWER) {
+    for (int i = 0; i < W; ++i) x[i] = (i == c) ? 1.0 : 0.0;
 #pragma unroll
-      for (int kk = 0; kk < W; ++kk)
+    for (int kk = 0; kk < W; ++kk)
 #pragma unroll
-        for (int i = kk + 1; i < W; ++i) x[i] -= s.tri[i * BS + kk] * x[kk];
-    } else {
+      for (int i = kk + 1; i < W; ++i) x[i] -= s.blk[(j0 + i) * BS + kk] * x[kk];
 #pragma unroll
-      for (int kk = W - 1; kk >= 0; --kk) {
-        x[kk] /= s.tri[kk * BS + kk];
+    for (int i = 0; i < W; ++i) Linv[c * W + i] = x[i];
+  } else {
 #pragma unroll
-        for (int i = 0; i < kk; ++i) x[i] -= s.tri[i * BS + kk] * x[kk];
-      }
+    for (int i = 0; i < W; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int kk = W - 1; kk >= 0; --kk) {
+      x[kk] /= s.blk[(j0 + kk) * BS + kk];
+#pragma unroll
+      for (int i = 0; i < kk; ++i) x[i] -= s.blk[(j0 + i) * BS + kk] * x[kk];
     }
 #pragma unroll
-    for (int i = 0; i < W; ++i) s.blk[(p0 + i) * BS + tid] = x[i];
+    for (int i = 0; i < W; ++i) Uinv[c * W + i] = x[i];
   }
 }
 
@@ -95,12 +115,22 @@ __device__ inline void gemm_update(const Lds &s, const double *M, int ld, int p0
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ntile = (r_hi - r_lo) / 16;
-  for (int t = wave; t < ntile; t += NW) {
-    const int r0 = r_lo + t * 16;
-    const size_t grow = (size_t)s.perm[r0 + li];
-    double a[8];
+  const double *Mp = M + (size_t)(p0 + lk) * ld;
+  double a[8], an[8];
+  int t = wave;
+  if (t < ntile) {
+    const size_t grow = (size_t)s.perm[r_lo + t * 16 + li];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) a[kk] = -M[(size_t)(p0 + 4 * kk + lk) * ld + grow];
+    for (int kk = 0; kk < 8; ++kk) a[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
+  }
+  for (; t < ntile; t += NW) {
+    const int r0 = r_lo + t * 16;
+    const int tn = t + NW;
+    if (tn < ntile) {
+      const size_t grow = (size_t)s.perm[r_lo + tn * 16 + li];
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) an[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
+    }
     d4 c0, c1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -118,77 +148,183 @@ __device__ inline void gemm_update(const Lds &s, const double *M, int ld, int p0
       s.blk[(r0 + lk + 4 * r) * BS + li] = c0[r];
       s.blk[(r0 + lk + 4 * r) * BS + 16 + li] = c1[r];
     }
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
   }
 }
 
-// Unblocked LU with partial pivoting of block rows j0..np-1 (block columns 0..31).
-__device__ inline bool panel_factor(const Lds &s, int j0, int np) {
+// LU with partial pivoting of block rows j0..np-1 (block columns 0..31), in four
+// sub-panels of 8 columns.  Inside a sub-panel thread t keeps the 8 entries of
+// row j0+t in registers (rows beyond j0+NT, present only when np - j0 > NT,
+// stay in LDS); per column the pivot is found by wave shuffles plus one
+// exchange through LDS, the pivot row is published and whole rows are swapped
+// in LDS: two barriers per column.  After a sub-panel, its 8 pivot rows are
+// solved against the remaining columns (unit-lower 8 x 8) and the rows below
+// receive the rank-8 update.
+constexpr int SPW = 8;   // sub-panel width
+
+__device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, double *tmprow) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r0 = j0 + tid, r1 = j0 + tid + NT;
+  const bool has0 = r0 < np, has1 = r1 < np;
+  double *y0 = s.blk + (size_t)r0 * BS;
+  double *y1 = s.blk + (size_t)r1 * BS;
   bool singular = false;
-  for (int jj = 0; jj < W; ++jj) {
-    const int r = j0 + jj;
-    double best = -1.0;
-    int bi = r;
-    for (int i = r + tid; i < np; i += NT) {
-      const double a = fabs(s.blk[i * BS + jj]);
-      if (a > best) {
-        best = a;
-        bi = i;
-      }
-    }
+  for (int cs = 0; cs < W; cs += SPW) {
+    double x0[SPW];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
+    for (int c = 0; c < SPW; ++c) x0[c] = has0 ? y0[cs + c] : 0.0;
+    for (int jj = 0; jj < SPW; ++jj) {
+      const int col = cs + jj;
+      const int r = j0 + col;
+      double v0 = 0.0;
+#pragma unroll
+      for (int c = 0; c < SPW; ++c)
+        if (c == jj) v0 = x0[c];
+      double best = -1.0;
+      int bi = np;
+      if (has0 && r0 >= r) {
+        best = fabs(v0);
+        bi = r0;
+      }
+      if (has1) {
+        const double v1 = fabs(y1[col]);
+        if (v1 > best) {
+          best = v1;
+          bi = r1;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      double *rv = s.redv + (col & 1) * NW;
+      int *ri = s.redi + (col & 1) * NW;
+      if (lane == 0) {
+        rv[wave] = best;
+        ri[wave] = bi;
+      }
+      __syncthreads();
+      best = rv[0];
+      bi = ri[0];
+#pragma unroll
+      for (int w2 = 1; w2 < NW; ++w2) {
+        const double ob = rv[w2];
+        const int oi = ri[w2];
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      const bool zero = !(best > 0.0);
+      singular |= zero;
+      const int piv = zero ? r : bi;
+      // pivot row entries of this sub-panel -> prow; if rows move, the register
+      // part of row r -> tmprow and the LDS columns outside the sub-panel swap.
+      if (has0 && r0 == piv) {
+#pragma unroll
+        for (int c = 0; c < SPW; ++c) prow[c] = x0[c];
+      }
+      if (has1 && r1 == piv) {
+#pragma unroll
+        for (int c = 0; c < SPW; ++c) prow[c] = y1[cs + c];
+      }
+      if (piv != r) {
+        if (has0 && r0 == r) {
+#pragma unroll
+          for (int c = 0; c < SPW; ++c) tmprow[c] = x0[c];
+        }
+        if (tid < W && (tid < cs || tid >= cs + SPW)) {
+          const double t0 = s.blk[r * BS + tid];
+          s.blk[r * BS + tid] = s.blk[piv * BS + tid];
+          s.blk[piv * BS + tid] = t0;
+        }
+        if (tid == W) {
+          const int t0 = s.perm[r];
+          s.perm[r] = s.perm[piv];
+          s.perm[piv] = t0;
+        }
+      }
+      __syncthreads();
+      if (piv != r) {
+        if (has0 && r0 == piv) {
+#pragma unroll
+          for (int c = 0; c < SPW; ++c) x0[c] = tmprow[c];
+        } else if (has0 && r0 == r) {
+#pragma unroll
+          for (int c = 0; c < SPW; ++c) x0[c] = prow[c];
+        }
+        if (has1 && r1 == piv) {
+#pragma unroll
+          for (int c = 0; c < SPW; ++c) y1[cs + c] = tmprow[c];
+        }
+      }
+      if (!zero) {
+        const double inv = 1.0 / prow[jj];
+        if (has0 && r0 > r) {
+          double l0 = 0.0;
+#pragma unroll
+          for (int c = 0; c < SPW; ++c)
+            if (c == jj) l0 = x0[c] * inv;
+#pragma unroll
+          for (int c = 0; c < SPW; ++c) {
+            if (c == jj) x0[c] = l0;
+            else if (c > jj) x0[c] -= l0 * prow[c];
+          }
+        }
+        if (has1) {
+          const double l1 = y1[col] * inv;
+          y1[col] = l1;
+          for (int c = jj + 1; c < SPW; ++c) y1[cs + c] -= l1 * prow[c];
+        }
       }
     }
-    if (lane == 0) {
-      s.redv[wave] = best;
-      s.redi[wave] = bi;
+    if (has0) {
+#pragma unroll
+      for (int c = 0; c < SPW; ++c) y0[cs + c] = x0[c];
     }
     __syncthreads();
-    best = s.redv[0];
-    bi = s.redi[0];
-    for (int w2 = 1; w2 < NW; ++w2) {
-      const double ob = s.redv[w2];
-      const int oi = s.redi[w2];
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
+    if (cs + SPW < W) {
+      // pivot rows j0+cs..j0+cs+7 of the remaining columns: unit-lower 8 x 8 solve
+      const int rp = j0 + cs;
+      if (tid < W - cs - SPW) {
+        const int c = cs + SPW + tid;
+        double u[SPW];
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) u[i] = s.blk[(rp + i) * BS + c];
+#pragma unroll
+        for (int k = 0; k < SPW; ++k)
+#pragma unroll
+          for (int i = k + 1; i < SPW; ++i) u[i] -= s.blk[(rp + i) * BS + cs + k] * u[k];
+#pragma unroll
+        for (int i = 0; i < SPW; ++i) s.blk[(rp + i) * BS + c] = u[i];
       }
-    }
-    const bool zero = !(best > 0.0);
-    singular |= zero;
-    if (!zero && bi != r) {
-      if (tid < W) {
-        const double t0 = s.blk[r * BS + tid];
-        s.blk[r * BS + tid] = s.blk[bi * BS + tid];
-        s.blk[bi * BS + tid] = t0;
-      } else if (tid == W) {
-        const int t0 = s.perm[r];
-        s.perm[r] = s.perm[bi];
-        s.perm[bi] = t0;
+      __syncthreads();
+      // rank-8 update of the rows below
+      for (int i = rp + SPW + tid; i < np; i += NT) {
+        double l[SPW];
+#pragma unroll
+        for (int k = 0; k < SPW; ++k) l[k] = s.blk[i * BS + cs + k];
+        for (int c = cs + SPW; c < W; ++c) {
+          double acc = s.blk[i * BS + c];
+#pragma unroll
+          for (int k = 0; k < SPW; ++k) acc -= l[k] * s.blk[(rp + k) * BS + c];
+          s.blk[i * BS + c] = acc;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    if (!zero) {
-      const double inv = 1.0 / s.blk[r * BS + jj];
-      for (int i = r + 1 + tid; i < np; i += NT) {
-        const double l = s.blk[i * BS + jj] * inv;
-        s.blk[i * BS + jj] = l;
-        for (int c = jj + 1; c < W; ++c) s.blk[i * BS + c] -= l * s.blk[r * BS + c];
-      }
-    }
-    __syncthreads();
   }
   return singular;
 }
 
 __global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *status, double *S, double *g,
-                                                 double *Y, double *z) {
+                                                 double *Y, double *z, double *inv) {
   extern __shared__ double smem[];
   const int el = blockIdx.x, e = e0 + el;
   const int np = P.n_pad, kp = P.k_pad, kx = P.kx, n = P.n, k = P.k;
@@ -199,10 +335,13 @@ __global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *sta
   const double *Rt = P.Rt + (size_t)el * kp;
   Lds s;
   s.blk = smem;
-  s.tri = s.blk + (size_t)np * BS;
-  s.perm = reinterpret_cast<int *>(s.tri + W * BS);
+  s.prow = s.blk + (size_t)np * BS;
+  s.tmp = s.prow + W;
+  s.perm = reinterpret_cast<int *>(s.tmp + W);
   s.redv = reinterpret_cast<double *>(s.perm + np);
-  s.redi = reinterpret_cast<int *>(s.redv + NW);
+  s.redi = reinterpret_cast<int *>(s.redv + 2 * NW);
+  // inverses of the diagonal blocks: [nJ][2][W][W] per element
+  double *Ie = inv + (size_t)el * (np / W) * 2 * W * W;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nJ = np / W;
@@ -218,14 +357,14 @@ __global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *sta
     __syncthreads();
     for (int Pp = 0; Pp < J; ++Pp) {
       const int p0 = Pp * W;
-      stage_tri(s, A, np, p0);
-      __syncthreads();
-      tri_solve<true>(s, p0);
+      inv_apply(s, Ie + (size_t)Pp * 2 * W * W, p0);
       __syncthreads();
       gemm_update(s, A, np, p0, p0 + W, np);
       __syncthreads();
     }
-    singular |= panel_factor(s, j0, np);
+    singular |= panel_factor(s, j0, np, s.prow, s.tmp);
+    __syncthreads();
+    invert_diag(s, j0, Ie + (size_t)J * 2 * W * W, Ie + (size_t)J * 2 * W * W + W * W);
     store_block(s, A, np, j0, np);
     __syncthreads();
   }
@@ -240,18 +379,14 @@ __global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *sta
     __syncthreads();
     for (int Pp = 0; Pp < nJ; ++Pp) {
       const int p0 = Pp * W;
-      stage_tri(s, A, np, p0);
-      __syncthreads();
-      tri_solve<true>(s, p0);
+      inv_apply(s, Ie + (size_t)Pp * 2 * W * W, p0);
       __syncthreads();
       if (p0 + W < np) gemm_update(s, A, np, p0, p0 + W, np);
       __syncthreads();
     }
     for (int Pp = nJ - 1; Pp >= 0; --Pp) {
       const int p0 = Pp * W;
-      stage_tri(s, A, np, p0);
-      __syncthreads();
-      tri_solve<false>(s, p0);
+      inv_apply(s, Ie + (size_t)Pp * 2 * W * W + W * W, p0);
       __syncthreads();
       if (p0 > 0) gemm_update(s, A, np, p0, 0, p0);
       __syncthreads();
@@ -267,16 +402,23 @@ __global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *sta
     for (int t = wave; t < ntr; t += NW) {
       const int r0 = t * 16;
       d4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
-      for (int kb = 0; kb < np; kb += 32) {
-        double a[8];
+      const double *Cr = C + (size_t)lk * kp + r0 + li;
+      double a[8], an[8];
 #pragma unroll
-        for (int kk = 0; kk < 8; ++kk) a[kk] = C[(size_t)(kb + 4 * kk + lk) * kp + r0 + li];
+      for (int kk = 0; kk < 8; ++kk) a[kk] = Cr[(size_t)(4 * kk) * kp];
+      for (int kb = 0; kb < np; kb += 32) {
+        if (kb + 32 < np) {
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) an[kk] = Cr[(size_t)(kb + 32 + 4 * kk) * kp];
+        }
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
           const double *brow = s.blk + (kb + 4 * kk + lk) * BS;
           a0 = mfma4(a[kk], brow[li], a0);
           a1 = mfma4(a[kk], brow[16 + li], a1);
         }
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -297,16 +439,19 @@ __global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *sta
 }  // namespace
 
 size_t condense_lds_bytes(int np) {
-  return ((size_t)np * BS + (size_t)W * BS) * sizeof(double) + (size_t)np * sizeof(int) +
-         NW * (sizeof(double) + sizeof(int));
+  return ((size_t)np * BS + 2 * W) * sizeof(double) + (size_t)np * sizeof(int) +
+         2 * NW * (sizeof(double) + sizeof(int));
 }
+
+size_t condense_inv_doubles(int np) { return (size_t)(np / W) * 2 * W * W; }
 
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s) {
+  double *inv = P.inv;
   const size_t lds = condense_lds_bytes(P.n_pad);
   hipError_t e = hipFuncSetAttribute((const void *)k_condense, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e) return e;
-  hipLaunchKernelGGL(k_condense, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z);
+  hipLaunchKernelGGL(k_condense, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, inv);
   return hipGetLastError();
 }
 

@@ -269,7 +269,7 @@ namespace {
 
 struct Layout {
   size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x, tables_end;
-  size_t pv, pf, A, X, C, D, Rt, ipiv, total;
+  size_t pv, pf, A, X, C, D, Rt, ipiv, inv, total;
 };
 
 Layout layout(const Plan *P) {
@@ -303,6 +303,7 @@ Layout layout(const Plan *P) {
   l.D = take(ch * (size_t)D.k_pad * D.k_pad * 8);
   l.Rt = take(ch * (size_t)D.k_pad * 8);
   l.ipiv = take(ch * (size_t)D.n_pad * 4);
+  l.inv = take(P->fused ? ch * condense_inv_doubles(D.n_pad) * 8 : 0);
   l.total = o;
   return l;
 }
@@ -375,6 +376,7 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   D.D = reinterpret_cast<double *>(base + l.D);
   D.Rt = reinterpret_cast<double *>(base + l.Rt);
   D.ipiv = reinterpret_cast<int *>(base + l.ipiv);
+  D.inv = reinterpret_cast<double *>(base + l.inv);
   P->ws = dev;
   P->ws_bytes = bytes;
   P->bound = true;

@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hdg.h"
+#include "hdg.h"
 #include "hdg_tables.hpp"
 
 namespace hdg {
@@ -43,6 +43,7 @@ struct DevPlan {
   double *D;               // [chunk][k_pad][k_pad]
   double *Rt;              // [chunk][k_pad]
   int *ipiv;               // [chunk][n_pad]
+  double *inv;             // [chunk][n_pad/32][2][32][32] inverses of diagonal factor blocks
 };
 
 // Phases timed with HIP events when phase timing is enabled.
@@ -84,6 +85,7 @@ hipError_t launch_schur(const DevPlan &P, int e0, int ec, double *S, double *g, 
 hipError_t launch_copy_resid(const DevPlan &P, int e0, int ec, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_mfma_selftest(double *out, hipStream_t s);
 size_t condense_lds_bytes(int np);
+size_t condense_inv_doubles(int np);
 bool contract_mfma_supported(const DevPlan &P);
 hipError_t launch_contract_mfma(const DevPlan &P, int e0, int ec, hipStream_t s);
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
