@@ -171,6 +171,55 @@ int hdg_trace_matvec(hdg_plan *plan, const double *S, const double *x, double *y
 /* Right-hand side of the condensed system r = sum_K P_K^T g_K ([m][n_trace]). */
 int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
 
+/* ---- Global trace solve --------------------------------------------------
+ * The paper leaves the linear solver of the condensed system open; this
+ * library solves  K dlambda = r,  K = sum_K P_K^T S_K P_K  (the trace operator
+ * above), with restarted GMRES, right-preconditioned:
+ *   precond 0: none;
+ *   precond 1: block Jacobi on the diagonal blocks of K.  A block holds the
+ *     unknowns of one mesh face (all components, face nodes in ascending
+ *     trace-node order) when every trace node lies on exactly one face (HDG),
+ *     else the m x m block of one trace node (EDG / IEDG, where faces share
+ *     nodes).
+ * Arnoldi uses classical Gram-Schmidt with one reorthogonalization pass; every
+ * vector operation runs on the device, the (restart+1) x restart Hessenberg
+ * matrix and its Givens rotations on the host (one stream synchronization per
+ * iteration).  Stopping test: ||r - K x|| <= tol ||r||, checked on the true
+ * residual at every restart and on return. */
+typedef struct {
+  int restart;    /* Krylov dimension per cycle (>= 1; 50 in the benchmarks) */
+  int maxit;      /* total Arnoldi steps allowed */
+  double tol;     /* relative residual target (> 0) */
+  int precond;    /* 0 none, 1 block Jacobi */
+} hdg_solve_opts;
+
+typedef struct {
+  int iterations;       /* Arnoldi steps taken */
+  int converged;        /* 1 if the returned x meets tol */
+  double rel_residual;  /* true ||r - K x|| / ||r|| of the returned x */
+  double solve_ms;      /* host wall time of hdg_trace_solve */
+} hdg_solve_info;
+
+/* Bytes of caller-owned device workspace for the solver (block inverses,
+ * restart+1 Krylov vectors, reduction scratch); 256-byte aligned pointer. */
+int hdg_solver_workspace_bytes(const hdg_plan *plan, const hdg_solve_opts *opts, size_t *bytes);
+
+/* Assemble the block-Jacobi blocks of K from S [E][k][k] and invert them (LU
+ * with partial pivoting) into `work`.  Synchronizes `stream`; HDG_ESINGULAR if
+ * a block has a zero pivot.  Required before precond 1 is used. */
+int hdg_precond_setup(hdg_plan *plan, const double *S, void *work, size_t bytes,
+                      const hdg_solve_opts *opts, void *stream);
+
+/* z = M^-1 r with the blocks from hdg_precond_setup; r, z [m][n_trace]. */
+int hdg_precond_apply(hdg_plan *plan, void *work, size_t bytes, const hdg_solve_opts *opts,
+                      const double *r, double *z, void *stream);
+
+/* Solve K x = rhs (x overwritten, initial guess 0).  Device pointers S, rhs,
+ * x, work; `info` on the host.  Returns HDG_OK also when tol is not reached
+ * within maxit (info->converged = 0). */
+int hdg_trace_solve(hdg_plan *plan, const double *S, const double *rhs, double *x, void *work,
+                    size_t bytes, const hdg_solve_opts *opts, hdg_solve_info *info, void *stream);
+
 /* Optional per-phase timing with HIP events recorded on the call's stream
  * around each kernel group: 0 points (pointwise physics), 1 contract (block
  * assembly), 2 LU, 3 triangular solves, 4 Schur product (split dense path),

@@ -32,6 +32,16 @@ class hdg_opts(ctypes.Structure):
     _fields_ = [("chunk_elems", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int)]
 
 
+class hdg_solve_opts(ctypes.Structure):
+    _fields_ = [("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("tol", ctypes.c_double),
+                ("precond", ctypes.c_int)]
+
+
+class hdg_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("solve_ms", ctypes.c_double)]
+
+
 class hdg_dims(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("dim", "m", "Np", "nf", "Nfp", "Nq", "Nfq", "n", "k", "n_pad",
                                              "k_pad", "n_elem", "n_trace", "chunk_elems")]
@@ -53,6 +63,11 @@ SIGNATURES = {
     "hdg_backsolve": (I, [P, P, P, P, P, P, P]),
     "hdg_trace_matvec": (I, [P, P, P, P, P]),
     "hdg_trace_rhs": (I, [P, P, P, P]),
+    "hdg_solver_workspace_bytes": (I, [P, ctypes.POINTER(hdg_solve_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_precond_setup": (I, [P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),
+    "hdg_precond_apply": (I, [P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P, P, P]),
+    "hdg_trace_solve": (I, [P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts),
+                            ctypes.POINTER(hdg_solve_info), P]),
     "hdg_selftest": (I, [ctypes.POINTER(ctypes.c_double)]),
     "hdg_plan_set_timing": (I, [P, I]),
     "hdg_plan_phase_times": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long), I]),

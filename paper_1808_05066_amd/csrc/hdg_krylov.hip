@@ -1,0 +1,277 @@
+// Kernels of the global trace solve: block-Jacobi assembly, inversion and
+// application on the condensed operator sum_K P_K^T S_K P_K, and the vector
+// kernels of restarted GMRES (multi-dot with a two-stage reduction,
+// multi-AXPY, scaling, linear combinations).  The paper does not describe its
+// linear solver; GMRES with a block-Jacobi preconditioner is this library's.
+#include "hdg_plan.hpp"
+
+namespace hdg {
+
+namespace {
+
+constexpr int RB = 256;   // reduction block size
+
+// Face blocks: unknowns of one mesh face (HDG), ordered (c, p) -> c*Nfp + p with p
+// the position of the trace node in the block's node list.  Each block sums the
+// face-diagonal part of S of its (at most two) adjacent elements.
+__global__ void k_bj_assemble_face(DevPlan P, const double *__restrict__ S, double *B) {
+  const int blk = blockIdx.x;
+  const int M = P.m, Nfp = P.Nfp, k = P.k, bs = M * Nfp;
+  double *Bb = B + (size_t)blk * bs * bs;
+  for (int t = threadIdx.x; t < bs * bs; t += blockDim.x) {
+    const int row = t % bs, col = t / bs;
+    const int c = row / Nfp, p = row % Nfp, c2 = col / Nfp, p2 = col % Nfp;
+    double acc = 0.0;
+    for (int q = 0; q < 2; ++q) {
+      const int e = P.bj_ce[blk * 2 + q];
+      if (e < 0) continue;
+      const int f = P.bj_cf[blk * 2 + q];
+      const int *loc = P.bj_loc + ((size_t)blk * 2 + q) * Nfp;
+      const int i = f * M * Nfp + c * Nfp + loc[p];
+      const int j = f * M * Nfp + c2 * Nfp + loc[p2];
+      acc += S[(size_t)e * k * k + (size_t)j * k + i];
+    }
+    Bb[(size_t)col * bs + row] = acc;
+  }
+}
+
+// Point blocks (m x m per trace node): every pair of element trace rows that map
+// to the same node adds its entry (FP64 atomics; used when faces share nodes).
+__global__ void k_bj_assemble_point(DevPlan P, const double *__restrict__ S, double *B) {
+  const int e = blockIdx.x;
+  const int M = P.m, Nfp = P.Nfp, k = P.k;
+  const int *tm = P.tmap + (size_t)e * P.nf * Nfp;
+  for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+    const int i = t % k, j = t / k;
+    const int bi = i % Nfp, fi = i / (M * Nfp), ci = (i / Nfp) % M;
+    const int bj = j % Nfp, fj = j / (M * Nfp), cj = (j / Nfp) % M;
+    const int ni = tm[fi * Nfp + bi], nj = tm[fj * Nfp + bj];
+    if (ni != nj) continue;
+    atomicAdd(&B[(size_t)ni * M * M + cj * M + ci], S[(size_t)e * k * k + (size_t)j * k + i]);
+  }
+}
+
+// In-place inverse of each bs x bs block (column-major) by LU with partial
+// pivoting in LDS followed by solves against the identity.
+__global__ void k_block_invert(double *B, int bs, int32_t *bad) {
+  extern __shared__ double a[];   // [bs][bs+1] column-major with padding, then pivots
+  const int blk = blockIdx.x;
+  const int ld = bs + 1;
+  double *Bb = B + (size_t)blk * bs * bs;
+  int *piv = reinterpret_cast<int *>(a + (size_t)bs * ld);
+  __shared__ int s_p;
+  __shared__ int s_zero;
+  for (int t = threadIdx.x; t < bs * bs; t += blockDim.x) a[(t / bs) * ld + t % bs] = Bb[t];
+  if (threadIdx.x == 0) s_zero = 0;
+  __syncthreads();
+  for (int j = 0; j < bs; ++j) {
+    if (threadIdx.x == 0) {
+      int p = j;
+      double best = fabs(a[j * ld + j]);
+      for (int i = j + 1; i < bs; ++i) {
+        const double v = fabs(a[j * ld + i]);
+        if (v > best) {
+          best = v;
+          p = i;
+        }
+      }
+      if (!(best > 0.0)) s_zero = 1;
+      s_p = p;
+      piv[j] = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != j)
+      for (int c = threadIdx.x; c < bs; c += blockDim.x) {
+        const double t0 = a[c * ld + j];
+        a[c * ld + j] = a[c * ld + p];
+        a[c * ld + p] = t0;
+      }
+    __syncthreads();
+    const double d = a[j * ld + j];
+    if (d != 0.0) {
+      for (int i = j + 1 + threadIdx.x; i < bs; i += blockDim.x) a[j * ld + i] /= d;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < (bs - j - 1) * (bs - j - 1); t += blockDim.x) {
+      const int i = j + 1 + t % (bs - j - 1), c = j + 1 + t / (bs - j - 1);
+      a[c * ld + i] -= a[j * ld + i] * a[c * ld + j];
+    }
+    __syncthreads();
+  }
+  // column c of the inverse: solve L U x = P e_c
+  for (int c = threadIdx.x; c < bs; c += blockDim.x) {
+    double *x = Bb + (size_t)c * bs;
+    for (int i = 0; i < bs; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+    for (int j = 0; j < bs; ++j) {
+      const int p = piv[j];
+      if (p != j) {
+        const double t0 = x[j];
+        x[j] = x[p];
+        x[p] = t0;
+      }
+    }
+    for (int j = 0; j < bs; ++j)
+      for (int i = j + 1; i < bs; ++i) x[i] -= a[j * ld + i] * x[j];
+    for (int j = bs - 1; j >= 0; --j) {
+      x[j] /= a[j * ld + j];
+      for (int i = 0; i < j; ++i) x[i] -= a[j * ld + i] * x[j];
+    }
+  }
+  if (threadIdx.x == 0 && s_zero) atomicAdd(bad, 1);
+}
+
+// z = blockdiag(Binv) r on [m][n_trace] vectors.
+__global__ void k_block_apply(DevPlan P, const double *__restrict__ Binv, const double *__restrict__ r, double *z,
+                              int bs, int nodes_per_blk) {
+  extern __shared__ double rv[];
+  const int blk = blockIdx.x;
+  const int *nodes = P.bj_nodes + (size_t)blk * nodes_per_blk;
+  const size_t NT_ = (size_t)P.n_trace;
+  for (int i = threadIdx.x; i < bs; i += blockDim.x) {
+    const int c = i / nodes_per_blk, p = i % nodes_per_blk;
+    rv[i] = r[c * NT_ + nodes[p]];
+  }
+  __syncthreads();
+  const double *Bb = Binv + (size_t)blk * bs * bs;
+  for (int i = threadIdx.x; i < bs; i += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < bs; ++j) acc += Bb[(size_t)j * bs + i] * rv[j];
+    const int c = i / nodes_per_blk, p = i % nodes_per_blk;
+    z[c * NT_ + nodes[p]] = acc;
+  }
+}
+
+// partial[b][i] = sum over this block's slice of V[i][:] * w[:], i < nv
+__global__ void k_multidot(const double *__restrict__ V, size_t ldv, int nv, const double *__restrict__ w, size_t N,
+                           double *partial) {
+  __shared__ double red[RB];
+  const size_t per = (N + gridDim.x - 1) / gridDim.x;
+  const size_t lo = blockIdx.x * per, hi = lo + per < N ? lo + per : N;
+  for (int i = 0; i < nv; ++i) {
+    double acc = 0.0;
+    const double *Vi = V + (size_t)i * ldv;
+    for (size_t t = lo + threadIdx.x; t < hi; t += RB) acc += Vi[t] * w[t];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = RB / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nv + i] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_reduce_partial(const double *__restrict__ partial, int nb, int nv, double *out) {
+  const int i = blockIdx.x;
+  __shared__ double red[RB];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RB) acc += partial[(size_t)b * nv + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = RB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = red[0];
+}
+
+// w -= sum_i h[i] V[i], and accumulate h into hacc (if given)
+__global__ void k_multiaxpy(const double *__restrict__ V, size_t ldv, int nv, const double *__restrict__ h, double *w,
+                            size_t N) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  double acc = w[t];
+  for (int i = 0; i < nv; ++i) acc -= h[i] * V[(size_t)i * ldv + t];
+  w[t] = acc;
+}
+
+// out = sum_i y[i] V[i]
+__global__ void k_lincomb(const double *__restrict__ V, size_t ldv, int nv, const double *__restrict__ y, double *out,
+                          size_t N) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  double acc = 0.0;
+  for (int i = 0; i < nv; ++i) acc += y[i] * V[(size_t)i * ldv + t];
+  out[t] = acc;
+}
+
+// out = alpha * x + beta * y  (y may be null for beta = 0)
+__global__ void k_axpby(double alpha, const double *__restrict__ x, double beta, const double *__restrict__ y,
+                        double *out, size_t N) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  out[t] = alpha * x[t] + (y ? beta * y[t] : 0.0);
+}
+
+// out = x / s[0]   (s on the device)
+__global__ void k_scale_by(const double *__restrict__ x, const double *__restrict__ s, double *out, size_t N) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  out[t] = x[t] / s[0];
+}
+
+}  // namespace
+
+hipError_t launch_bj_assemble(const DevPlan &P, const double *S, double *B, hipStream_t s) {
+  if (P.bj_face) {
+    hipLaunchKernelGGL(k_bj_assemble_face, dim3(P.bj_nblk), dim3(256), 0, s, P, S, B);
+  } else {
+    hipError_t e = launch_fill_double(B, (size_t)P.bj_nblk * P.m * P.m, 0.0, s);
+    if (e) return e;
+    hipLaunchKernelGGL(k_bj_assemble_point, dim3(P.n_elem), dim3(256), 0, s, P, S, B);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_invert(const DevPlan &P, double *B, int32_t *bad, hipStream_t s) {
+  const int bs = P.bj_bs;
+  const size_t lds = (size_t)bs * (bs + 1) * sizeof(double) + (size_t)bs * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void *)k_block_invert, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e) return e;
+  hipLaunchKernelGGL(k_block_invert, dim3(P.bj_nblk), dim3(128), lds, s, B, bs, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_apply(const DevPlan &P, const double *Binv, const double *r, double *z, hipStream_t s) {
+  const int bs = P.bj_bs;
+  const int npb = P.bj_face ? P.Nfp : 1;
+  hipLaunchKernelGGL(k_block_apply, dim3(P.bj_nblk), dim3(bs <= 64 ? 64 : 128), bs * sizeof(double), s, P, Binv, r,
+                     z, bs, npb);
+  return hipGetLastError();
+}
+
+hipError_t launch_multidot(const double *V, size_t ldv, int nv, const double *w, size_t N, double *partial, int nb,
+                           double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(RB), 0, s, V, ldv, nv, w, N, partial);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nv), dim3(RB), 0, s, partial, nb, nv, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy(const double *V, size_t ldv, int nv, const double *h, double *w, size_t N,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_multiaxpy, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, V, ldv, nv, h, w, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_lincomb(const double *V, size_t ldv, int nv, const double *y, double *out, size_t N,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, V, ldv, nv, y, out, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double alpha, const double *x, double beta, const double *y, double *out, size_t N,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, alpha, x, beta, y, out, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_by(const double *x, const double *sc, double *out, size_t N, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_by, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, x, sc, out, N);
+  return hipGetLastError();
+}
+
+}  // namespace hdg

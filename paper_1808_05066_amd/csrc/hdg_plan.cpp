@@ -3,12 +3,16 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace hdg {
 
 int fail(int code, const std::string &msg) {
   g_err = msg;
@@ -19,6 +23,10 @@ int hip_fail(hipError_t e, const char *where) {
   g_err = std::string(where) + ": " + hipGetErrorString(e);
   return HDG_EHIP;
 }
+
+}  // namespace hdg
+
+namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -160,6 +168,70 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
       }
   }
 
+  // block-Jacobi structure: one block per face when every trace node lies on
+  // exactly one face (HDG), otherwise one m x m block per trace node
+  {
+    std::map<std::vector<int>, int> keys;
+    std::vector<std::vector<int>> nodes_of;
+    std::vector<std::vector<std::pair<int, int>>> contrib;
+    std::vector<int> owner(mesh->n_trace, -1);
+    bool face_ok = true;
+    for (int e = 0; e < E && face_ok; ++e)
+      for (int f = 0; f < R.nf && face_ok; ++f) {
+        std::vector<int> key(&P->tmap[((size_t)e * R.nf + f) * R.Nfp], &P->tmap[((size_t)e * R.nf + f) * R.Nfp] + R.Nfp);
+        std::sort(key.begin(), key.end());
+        if (std::adjacent_find(key.begin(), key.end()) != key.end()) face_ok = false;
+        auto it = keys.find(key);
+        int id;
+        if (it == keys.end()) {
+          id = (int)nodes_of.size();
+          keys[key] = id;
+          nodes_of.push_back(key);
+          contrib.emplace_back();
+          for (int t : key) {
+            if (owner[t] >= 0) face_ok = false;
+            owner[t] = id;
+          }
+        } else {
+          id = it->second;
+        }
+        contrib[id].push_back({e, f});
+        if (contrib[id].size() > 2) face_ok = false;
+      }
+    for (int t = 0; t < mesh->n_trace && face_ok; ++t)
+      if (owner[t] < 0) face_ok = false;
+    P->dp.bj_face = face_ok ? 1 : 0;
+    if (face_ok) {
+      const int nb = (int)nodes_of.size();
+      P->dp.bj_nblk = nb;
+      P->dp.bj_bs = M * R.Nfp;
+      P->bj_nodes.resize((size_t)nb * R.Nfp);
+      P->bj_ce.assign((size_t)nb * 2, -1);
+      P->bj_cf.assign((size_t)nb * 2, -1);
+      P->bj_loc.assign((size_t)nb * 2 * R.Nfp, 0);
+      for (int b = 0; b < nb; ++b) {
+        for (int p = 0; p < R.Nfp; ++p) P->bj_nodes[(size_t)b * R.Nfp + p] = nodes_of[b][p];
+        for (size_t q = 0; q < contrib[b].size(); ++q) {
+          const int e = contrib[b][q].first, f = contrib[b][q].second;
+          P->bj_ce[b * 2 + q] = e;
+          P->bj_cf[b * 2 + q] = f;
+          for (int p = 0; p < R.Nfp; ++p)
+            for (int bb = 0; bb < R.Nfp; ++bb)
+              if (P->tmap[((size_t)e * R.nf + f) * R.Nfp + bb] == nodes_of[b][p])
+                P->bj_loc[((size_t)b * 2 + q) * R.Nfp + p] = bb;
+        }
+      }
+    } else {
+      P->dp.bj_nblk = mesh->n_trace;
+      P->dp.bj_bs = M;
+      P->bj_nodes.resize(mesh->n_trace);
+      for (int t = 0; t < mesh->n_trace; ++t) P->bj_nodes[t] = t;
+      P->bj_ce.assign(2, -1);
+      P->bj_cf.assign(2, -1);
+      P->bj_loc.assign(2, 0);
+    }
+  }
+
   // descriptor
   DevPlan &D = P->dp;
   D.dim = d;
@@ -268,7 +340,8 @@ extern "C" int hdg_plan_dims(const hdg_plan *plan, hdg_dims *o) {
 namespace {
 
 struct Layout {
-  size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x, tables_end;
+  size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x;
+  size_t bj_nodes, bj_ce, bj_cf, bj_loc, tables_end;
   size_t pv, pf, A, X, C, D, Rt, ipiv, inv, total;
 };
 
@@ -294,6 +367,10 @@ Layout layout(const Plan *P) {
   l.face_bc = take(E * R.nf * 4);
   l.node_x = take(P->node_x.size() * 8);
   l.trace_x = take(P->trace_x.size() * 8);
+  l.bj_nodes = take(P->bj_nodes.size() * 4);
+  l.bj_ce = take(P->bj_ce.size() * 4);
+  l.bj_cf = take(P->bj_cf.size() * 4);
+  l.bj_loc = take(P->bj_loc.size() * 4);
   l.tables_end = o;
   l.pv = take(ch * D.Nq * D.L.size * 8);
   l.pf = take(ch * D.nf * D.Nfq * D.L.fsize * 8);
@@ -354,6 +431,10 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   if (!e) e = up(l.face_bc, P->face_bc.data(), P->face_bc.size() * 4);
   if (!e) e = up(l.node_x, P->node_x.data(), P->node_x.size() * 8);
   if (!e) e = up(l.trace_x, P->trace_x.data(), P->trace_x.size() * 8);
+  if (!e) e = up(l.bj_nodes, P->bj_nodes.data(), P->bj_nodes.size() * 4);
+  if (!e) e = up(l.bj_ce, P->bj_ce.data(), P->bj_ce.size() * 4);
+  if (!e) e = up(l.bj_cf, P->bj_cf.data(), P->bj_cf.size() * 4);
+  if (!e) e = up(l.bj_loc, P->bj_loc.data(), P->bj_loc.size() * 4);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(e, "bind_workspace upload");
   DevPlan &D = P->dp;
@@ -368,6 +449,10 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   D.face_bc = reinterpret_cast<const int *>(base + l.face_bc);
   D.node_x = reinterpret_cast<const double *>(base + l.node_x);
   D.trace_x = reinterpret_cast<const double *>(base + l.trace_x);
+  D.bj_nodes = reinterpret_cast<const int *>(base + l.bj_nodes);
+  D.bj_ce = reinterpret_cast<const int *>(base + l.bj_ce);
+  D.bj_cf = reinterpret_cast<const int *>(base + l.bj_cf);
+  D.bj_loc = reinterpret_cast<const int *>(base + l.bj_loc);
   D.pv = reinterpret_cast<double *>(base + l.pv);
   D.pf = reinterpret_cast<double *>(base + l.pf);
   D.A = reinterpret_cast<double *>(base + l.A);

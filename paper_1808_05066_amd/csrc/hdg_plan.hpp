@@ -44,6 +44,13 @@ struct DevPlan {
   double *Rt;              // [chunk][k_pad]
   int *ipiv;               // [chunk][n_pad]
   double *inv;             // [chunk][n_pad/32][2][32][32] inverses of diagonal factor blocks
+  // block-Jacobi structure of the condensed operator
+  int bj_face;             // 1: one block per mesh face (HDG), 0: one m x m block per trace node
+  int bj_nblk, bj_bs;
+  const int *bj_nodes;     // [nblk][nodes per block] global trace nodes (sorted)
+  const int *bj_ce;        // [nblk][2] contributing elements (-1: none)   (face blocks)
+  const int *bj_cf;        // [nblk][2] their local faces
+  const int *bj_loc;       // [nblk][2][Nfp] local face node of each block position
 };
 
 // Phases timed with HIP events when phase timing is enabled.
@@ -64,12 +71,17 @@ struct Plan {
   // host copies
   std::vector<double> geo_vol, geo_face, node_x, trace_x;
   std::vector<int> tmap, face_bc, node_face;
+  std::vector<int> bj_nodes, bj_ce, bj_cf, bj_loc;
   // workspace
   void *ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_tables_end = 0;
   bool bound = false;
 };
+
+// error channel of hdg_last_error(): records the message, returns the code
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *where);
 
 // kernel launchers (hdg_assemble.hip / hdg_dense.hip / hdg_trace.hip)
 hipError_t launch_fill_int(int32_t *p, int n, int val, hipStream_t s);
@@ -90,6 +102,18 @@ bool contract_mfma_supported(const DevPlan &P);
 hipError_t launch_contract_mfma(const DevPlan &P, int e0, int ec, hipStream_t s);
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s);
+hipError_t launch_bj_assemble(const DevPlan &P, const double *S, double *B, hipStream_t s);
+hipError_t launch_block_invert(const DevPlan &P, double *B, int32_t *bad, hipStream_t s);
+hipError_t launch_block_apply(const DevPlan &P, const double *Binv, const double *r, double *z, hipStream_t s);
+hipError_t launch_multidot(const double *V, size_t ldv, int nv, const double *w, size_t N, double *partial, int nb,
+                           double *out, hipStream_t s);
+hipError_t launch_multiaxpy(const double *V, size_t ldv, int nv, const double *h, double *w, size_t N,
+                            hipStream_t s);
+hipError_t launch_lincomb(const double *V, size_t ldv, int nv, const double *y, double *out, size_t N,
+                          hipStream_t s);
+hipError_t launch_axpby(double alpha, const double *x, double beta, const double *y, double *out, size_t N,
+                        hipStream_t s);
+hipError_t launch_scale_by(const double *x, const double *sc, double *out, size_t N, hipStream_t s);
 hipError_t launch_export_blocks(const DevPlan &P, int e0, int ec, double *A, double *B, double *C,
                                 double *D, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_backsolve(const DevPlan &P, const double *Y, const double *z, const double *dvhat,

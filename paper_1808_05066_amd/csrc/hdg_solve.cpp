@@ -1,0 +1,220 @@
+// Global trace solve: restarted GMRES with right preconditioning on the
+// condensed operator sum_K P_K^T S_K P_K, driven from the host.  Every vector
+// operation runs on the device; only the Hessenberg column crosses to the host
+// (one synchronization per Arnoldi step).  Arnoldi uses classical Gram-Schmidt
+// with one reorthogonalization pass.  The block-Jacobi inverses live at the
+// start of the solver workspace, written by hdg_precond_setup.
+#include <chrono>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "hdg_plan.hpp"
+
+using namespace hdg;
+
+namespace {
+
+constexpr int NB_RED = 256;
+
+struct SolveLayout {
+  size_t binv, V, w, z, u, partial, scal, bad, total;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+SolveLayout solve_layout(const Plan *P, int restart) {
+  const size_t N = (size_t)P->dp.m * P->n_trace;
+  SolveLayout l{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t r = o;
+    o = a256(o + b);
+    return r;
+  };
+  l.binv = take((size_t)P->dp.bj_nblk * P->dp.bj_bs * P->dp.bj_bs * 8);
+  l.V = take((size_t)(restart + 1) * N * 8);
+  l.w = take(N * 8);
+  l.z = take(N * 8);
+  l.u = take(N * 8);
+  l.partial = take((size_t)NB_RED * (restart + 2) * 8);
+  l.scal = take((size_t)(3 * (restart + 2) + 8) * 8);
+  l.bad = take(64);
+  l.total = o;
+  return l;
+}
+
+}  // namespace
+
+extern "C" int hdg_solver_workspace_bytes(const hdg_plan *plan, const hdg_solve_opts *opts, size_t *bytes) {
+  const Plan *P = reinterpret_cast<const Plan *>(plan);
+  if (!P || !opts || !bytes || opts->restart < 1) return fail(HDG_EINVAL, "bad argument");
+  *bytes = solve_layout(P, opts->restart).total;
+  return HDG_OK;
+}
+
+extern "C" int hdg_precond_setup(hdg_plan *plan, const double *S, void *work, size_t bytes,
+                                 const hdg_solve_opts *opts, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !S || !work || !opts) return fail(HDG_EINVAL, "bad argument or unbound plan");
+  SolveLayout l = solve_layout(P, opts->restart);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(work);
+  double *B = reinterpret_cast<double *>(base + l.binv);
+  int32_t *bad = reinterpret_cast<int32_t *>(base + l.bad);
+  hipError_t e = launch_fill_int(bad, 1, 0, s);
+  if (!e) e = launch_bj_assemble(P->dp, S, B, s);
+  if (!e) e = launch_block_invert(P->dp, B, bad, s);
+  int32_t hbad = 0;
+  if (!e) e = hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "precond_setup");
+  if (hbad) return fail(HDG_ESINGULAR, "singular block-Jacobi block");
+  return HDG_OK;
+}
+
+extern "C" int hdg_precond_apply(hdg_plan *plan, void *work, size_t bytes, const hdg_solve_opts *opts,
+                                 const double *r, double *z, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !work || !opts || !r || !z) return fail(HDG_EINVAL, "bad argument");
+  SolveLayout l = solve_layout(P, opts->restart);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
+  const double *B = reinterpret_cast<const double *>(static_cast<char *>(work) + l.binv);
+  hipError_t e = launch_block_apply(P->dp, B, r, z, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "precond_apply");
+  return HDG_OK;
+}
+
+extern "C" int hdg_trace_solve(hdg_plan *plan, const double *S, const double *rhs, double *x, void *work,
+                               size_t bytes, const hdg_solve_opts *opts, hdg_solve_info *info, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !S || !rhs || !x || !work || !opts || !info) return fail(HDG_EINVAL, "bad argument");
+  const int m = opts->restart;
+  if (m < 1 || opts->maxit < 1 || !(opts->tol > 0.0)) return fail(HDG_EINVAL, "bad solver options");
+  SolveLayout l = solve_layout(P, m);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
+  auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(work);
+  const size_t N = (size_t)P->dp.m * P->n_trace;
+  const double *B = reinterpret_cast<const double *>(base + l.binv);
+  double *V = reinterpret_cast<double *>(base + l.V);
+  double *w = reinterpret_cast<double *>(base + l.w);
+  double *z = reinterpret_cast<double *>(base + l.z);
+  double *u = reinterpret_cast<double *>(base + l.u);
+  double *partial = reinterpret_cast<double *>(base + l.partial);
+  double *dh = reinterpret_cast<double *>(base + l.scal);
+  double *dh2 = dh + (m + 2);
+  double *dy = dh2 + (m + 2);
+  double *dn = dy + (m + 2);
+  const bool pre = opts->precond != 0;
+  hipError_t e = hipSuccess;
+
+  auto prec = [&](const double *in, double *out) -> hipError_t {
+    if (pre) return launch_block_apply(P->dp, B, in, out, s);
+    return hipMemcpyAsync(out, in, N * 8, hipMemcpyDeviceToDevice, s);
+  };
+  auto matvec = [&](const double *in, double *out) -> hipError_t {
+    return launch_trace_matvec(P->dp, S, in, out, s);
+  };
+  auto norm = [&](const double *v, double &out) -> hipError_t {
+    hipError_t ee = launch_multidot(v, N, 1, v, N, partial, NB_RED, dn, s);
+    double h = 0.0;
+    if (!ee) ee = hipMemcpyAsync(&h, dn, 8, hipMemcpyDeviceToHost, s);
+    if (!ee) ee = hipStreamSynchronize(s);
+    out = std::sqrt(h);
+    return ee;
+  };
+
+  double bnorm = 0.0;
+  e = launch_fill_double(x, N, 0.0, s);
+  if (!e) e = norm(rhs, bnorm);
+  if (e) return hip_fail(e, "trace_solve");
+  info->iterations = 0;
+  info->converged = 0;
+  info->rel_residual = 0.0;
+  info->solve_ms = 0.0;
+  if (bnorm == 0.0) {
+    info->converged = 1;
+    return HDG_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hh(m + 2), hh2(m + 2), y(m);
+  int it = 0;
+  double relres = 1.0;
+  while (it < opts->maxit) {
+    // r = rhs - K x  -> V0
+    e = matvec(x, w);
+    if (!e) e = launch_axpby(1.0, rhs, -1.0, w, V, N, s);
+    double beta = 0.0;
+    if (!e) e = norm(V, beta);
+    if (e) return hip_fail(e, "trace_solve");
+    relres = beta / bnorm;
+    if (relres <= opts->tol) break;
+    e = launch_axpby(1.0 / beta, V, 0.0, nullptr, V, N, s);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double *Vj = V + (size_t)j * N;
+      if (!e) e = prec(Vj, z);
+      if (!e) e = matvec(z, w);
+      if (!e) e = launch_multidot(V, N, j + 1, w, N, partial, NB_RED, dh, s);
+      if (!e) e = launch_multiaxpy(V, N, j + 1, dh, w, N, s);
+      if (!e) e = launch_multidot(V, N, j + 1, w, N, partial, NB_RED, dh2, s);
+      if (!e) e = launch_multiaxpy(V, N, j + 1, dh2, w, N, s);
+      if (!e) e = launch_multidot(w, N, 1, w, N, partial, NB_RED, dn, s);
+      if (!e) e = hipMemcpyAsync(hh.data(), dh, (j + 1) * 8, hipMemcpyDeviceToHost, s);
+      if (!e) e = hipMemcpyAsync(hh2.data(), dh2, (j + 1) * 8, hipMemcpyDeviceToHost, s);
+      double nrm2 = 0.0;
+      if (!e) e = hipMemcpyAsync(&nrm2, dn, 8, hipMemcpyDeviceToHost, s);
+      if (!e) e = hipStreamSynchronize(s);
+      if (e) return hip_fail(e, "trace_solve");
+      const double hn = std::sqrt(nrm2);
+      double *col = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh2[i];
+      col[j + 1] = hn;
+      if (hn > 0.0) e = launch_axpby(1.0 / hn, w, 0.0, nullptr, V + (size_t)(j + 1) * N, N, s);
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = std::hypot(col[j], col[j + 1]);
+      cs[j] = col[j] / den;
+      sn[j] = col[j + 1] / den;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      jend = j + 1;
+      relres = std::fabs(g[j + 1]) / bnorm;
+      if (relres <= opts->tol || it >= opts->maxit || hn == 0.0) break;
+    }
+    // y = H^-1 g (upper triangular), x += M^-1 V y
+    for (int i = jend - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int k2 = i + 1; k2 < jend; ++k2) acc -= H[(size_t)k2 * (m + 1) + i] * y[k2];
+      y[i] = acc / H[(size_t)i * (m + 1) + i];
+    }
+    if (!e) e = hipMemcpyAsync(dy, y.data(), jend * 8, hipMemcpyHostToDevice, s);
+    if (!e) e = launch_lincomb(V, N, jend, dy, u, N, s);
+    if (!e) e = prec(u, z);
+    if (!e) e = launch_axpby(1.0, x, 1.0, z, x, N, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return hip_fail(e, "trace_solve");
+    // the next cycle starts from the true residual, which confirms convergence
+  }
+  // true residual
+  double rn = 0.0;
+  e = matvec(x, w);
+  if (!e) e = launch_axpby(1.0, rhs, -1.0, w, w, N, s);
+  if (!e) e = norm(w, rn);
+  if (e) return hip_fail(e, "trace_solve");
+  info->iterations = it;
+  info->rel_residual = rn / bnorm;
+  info->converged = info->rel_residual <= opts->tol ? 1 : 0;
+  info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return HDG_OK;
+}

@@ -162,6 +162,50 @@ class Plan:
         return r
 
 
+class TraceSolver:
+    """Restarted GMRES on the condensed trace system of one plan.
+
+    precond: "none" or "block_jacobi".  setup(S) builds the preconditioner
+    from the Schur blocks; solve(S, rhs) returns (x, info dict).
+    """
+
+    PRECONDS = {"none": 0, "block_jacobi": 1}
+
+    def __init__(self, plan, restart=50, maxit=2000, tol=1e-10, precond="block_jacobi"):
+        torch = _torch()
+        self.plan = plan
+        self.opts = _lib.hdg_solve_opts(int(restart), int(maxit), float(tol), self.PRECONDS[precond])
+        nb = ctypes.c_size_t()
+        check(plan.lib.hdg_solver_workspace_bytes(plan.h, ctypes.byref(self.opts), ctypes.byref(nb)),
+              "hdg_solver_workspace_bytes")
+        self.nbytes = int(nb.value)
+        self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=plan.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ptr = ctypes.c_void_p(self.workspace.data_ptr() + off)
+
+    def setup(self, S):
+        if self.opts.precond:
+            check(self.plan.lib.hdg_precond_setup(self.plan.h, _ptr(S), self._ptr, ctypes.c_size_t(self.nbytes),
+                                                  ctypes.byref(self.opts), _stream()), "hdg_precond_setup")
+
+    def apply(self, r, z=None):
+        if z is None:
+            z = self.plan._empty(self.plan.m, self.plan.n_trace)
+        check(self.plan.lib.hdg_precond_apply(self.plan.h, self._ptr, ctypes.c_size_t(self.nbytes),
+                                              ctypes.byref(self.opts), _ptr(r), _ptr(z), _stream()),
+              "hdg_precond_apply")
+        return z
+
+    def solve(self, S, rhs, x=None):
+        if x is None:
+            x = self.plan._empty(self.plan.m, self.plan.n_trace)
+        info = _lib.hdg_solve_info()
+        check(self.plan.lib.hdg_trace_solve(self.plan.h, _ptr(S), _ptr(rhs), _ptr(x), self._ptr,
+                                            ctypes.c_size_t(self.nbytes), ctypes.byref(self.opts),
+                                            ctypes.byref(info), _stream()), "hdg_trace_solve")
+        return x, {f: getattr(info, f) for f, _ in _lib.hdg_solve_info._fields_}
+
+
 def selftest():
     """Largest error of the device matrix-core layout self-check."""
     lib = _lib.load()

@@ -49,6 +49,7 @@ def colmajor(mats):
 SMALL_CASES = {
     "euler2d_tri_p2": lambda: C.euler2d_tri_p2(),
     "euler2d_tri_p2_periodic_edg": lambda: C.euler2d_tri_p2(n=4, periodic=True, scheme="edg"),
+    "euler2d_tri_p2_iedg": lambda: C.euler2d_tri_p2(n=4, scheme="iedg"),
     "ns2d_tri_p2": lambda: C.ns2d_tri(n=3, p=2),
     "ns2d_tri_p3": lambda: C.ns2d_tri(n=2, p=3),
     "ns3d_hex_p1": lambda: C.ns3d_hex(n=3, p=1),

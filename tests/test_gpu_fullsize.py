@@ -26,7 +26,8 @@ def torch():
     return t
 
 
-def test_ns3d_hex_p2_16_sampled(torch):
+@pytest.fixture(scope="module")
+def full(torch):
     wl = C.ns3d_hex(n=16, p=2)
     disc = oracle_disc(wl)
     inp = ostate.oracle_inputs_fast(wl, disc)
@@ -36,6 +37,11 @@ def test_ns3d_hex_p2_16_sampled(torch):
     print("full-size run: %d elements" % wl.mesh.n_elem, flush=True)
     out = plan.assemble_condense(dev["v"], dev["q"], dev["vhat"], dev["ustar"], None, residuals=True)
     torch.cuda.synchronize()
+    return wl, disc, inp, plan, out
+
+
+def test_ns3d_hex_p2_16_sampled(torch, full):
+    wl, disc, inp, plan, out = full
     assert int((out["status"] != 0).sum()) == 0
     E = wl.mesh.n_elem
     rng = np.random.default_rng(2024)
@@ -56,3 +62,53 @@ def test_ns3d_hex_p2_16_sampled(torch):
         print("element", e, errs, flush=True)
         for key, err in errs.items():
             assert err <= TOL, (e, key, err)
+
+
+def test_ns3d_hex_p2_16_trace_solve(torch, full):
+    """GMRES(50) + block Jacobi on the full condensed system.
+
+    Sampled check of the preconditioner: the face block shared by elements
+    (e, f) and its neighbour, assembled from the oracle's S of both elements,
+    must be inverted by the GPU apply of a vector supported on that face
+    (backward error ||B_o z - r|| <= 1e-12 cond-free scale ||B_o|| ||z||).
+    The solve must reach its tolerance on the true residual, recomputed here
+    with the (parity-tested) trace operator.
+    """
+    from paper_1808_05066_amd.hdg import TraceSolver
+    wl, disc, inp, plan, out = full
+    m, nt, Nfp = disc.m, wl.n_trace, disc.Nfp
+    ts = TraceSolver(plan, restart=50, maxit=1000, tol=1e-10, precond="block_jacobi")
+    ts.setup(out["S"])
+    # sampled face blocks
+    rng = np.random.default_rng(11)
+    for e, f in ((0, 0), (wl.mesh.n_elem - 1, disc.nf - 1), (int(rng.integers(wl.mesh.n_elem)), 2)):
+        nodes = np.sort(wl.tmap[e, f])
+        owners = [(e2, f2) for e2 in range(wl.mesh.n_elem) for f2 in range(disc.nf)
+                  if np.array_equal(np.sort(wl.tmap[e2, f2]), nodes)]
+        assert 1 <= len(owners) <= 2
+        ref = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], None,
+                                     elems=[o[0] for o in owners])
+        gidx = (np.arange(m)[:, None] * nt + nodes[None, :]).reshape(-1)
+        B = np.zeros((m * Nfp, m * Nfp))
+        for (e2, f2), r2 in zip(owners, ref):
+            idx = ohdg.element_trace_index(disc, e2)
+            pos = {int(t): i for i, t in enumerate(idx)}
+            loc = np.array([pos[int(t)] for t in gidx])
+            B += r2["S"][np.ix_(loc, loc)]
+        rvec = np.zeros(m * nt)
+        rvec[gidx] = rng.normal(size=gidx.size)
+        z = ts.apply(torch.from_numpy(rvec.reshape(m, nt)).cuda()).cpu().numpy().reshape(-1)
+        zg = z[gidx]
+        back = np.linalg.norm(B @ zg - rvec[gidx]) / (np.linalg.norm(B) * np.linalg.norm(zg))
+        print("face block", e, f, owners, "backward", back, flush=True)
+        assert back <= 1e-12
+        mask = np.ones(m * nt, bool)
+        mask[gidx] = False
+        assert np.all(z[mask] == 0.0)
+    rhs = plan.trace_rhs(out["g"])
+    x, info = ts.solve(out["S"], rhs)
+    print("full-size GMRES", info, flush=True)
+    assert info["converged"] == 1
+    y = plan.trace_matvec(out["S"], x)
+    res = float(torch.linalg.norm(rhs - y) / torch.linalg.norm(rhs))
+    assert res <= 1.01e-10
