@@ -93,7 +93,7 @@ enum { HDG_FLAG_SPLIT_DENSE = 1 };
 
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */
-  int precision;           /* HDG_FP64 (others reserved) */
+  int precision;           /* HDG_FP64; the FP32 path has its own entry points below */
   int flags;               /* HDG_FLAG_SPLIT_DENSE: the reference kernel variants (VALU
                               block contraction; separate LU / solve / Schur kernels)
                               instead of the matrix-core contraction and the fused
@@ -191,6 +191,8 @@ typedef struct {
   int maxit;      /* total Arnoldi steps allowed */
   double tol;     /* relative residual target (> 0) */
   int precond;    /* 0 none, 1 block Jacobi */
+  int s_dtype;    /* element type of S: HDG_FP64 (double) or HDG_FP32 (float, the
+                     mixed-precision path); vectors and arithmetic stay FP64 */
 } hdg_solve_opts;
 
 typedef struct {
@@ -207,7 +209,7 @@ int hdg_solver_workspace_bytes(const hdg_plan *plan, const hdg_solve_opts *opts,
 /* Assemble the block-Jacobi blocks of K from S [E][k][k] and invert them (LU
  * with partial pivoting) into `work`.  Synchronizes `stream`; HDG_ESINGULAR if
  * a block has a zero pivot.  Required before precond 1 is used. */
-int hdg_precond_setup(hdg_plan *plan, const double *S, void *work, size_t bytes,
+int hdg_precond_setup(hdg_plan *plan, const void *S, void *work, size_t bytes,
                       const hdg_solve_opts *opts, void *stream);
 
 /* z = M^-1 r with the blocks from hdg_precond_setup; r, z [m][n_trace]. */
@@ -217,16 +219,83 @@ int hdg_precond_apply(hdg_plan *plan, void *work, size_t bytes, const hdg_solve_
 /* Solve K x = rhs (x overwritten, initial guess 0).  Device pointers S, rhs,
  * x, work; `info` on the host.  Returns HDG_OK also when tol is not reached
  * within maxit (info->converged = 0). */
-int hdg_trace_solve(hdg_plan *plan, const double *S, const double *rhs, double *x, void *work,
+int hdg_trace_solve(hdg_plan *plan, const void *S, const double *rhs, double *x, void *work,
                     size_t bytes, const hdg_solve_opts *opts, hdg_solve_info *info, void *stream);
+
+/* ---- Mixed precision ------------------------------------------------------
+ * Low-precision condensation with FP64 refinement of the full Newton linear
+ * system  J delta = -R,  J = [A B; C D] coupled through the traces.
+ *
+ * hdg_assemble_condense_lp: as hdg_assemble_condense (points, residuals and
+ * block contraction in FP64), then per element the symmetric power-of-two
+ * scaling A_hat = D A D, d_i = 2^-round(log2 sqrt|a_ii|), LU with partial
+ * pivoting of A_hat in FP32 on the FP32 matrix cores (FP32 accumulation), and
+ *   Y = D A_hat^-1 D B,  z = D A_hat^-1 D R_loc,  S = D - C Y,  g = -R_tr + C z
+ * with FP32 arithmetic.  S [E][k][k] and Y [E][k][n] are written as float
+ * (column-major as in the FP64 path), g and z as double (low-precision values).
+ * `factors` (hdg_lp_factor_bytes) receives per element the FP32 factors,
+ * pivots, scaling and diagonal-block inverses for hdg_lp_solve; R_loc [E][n]
+ * and R_tr [E][k] (FP64 residuals) are optional but needed by the refinement.
+ * HDG_EUNSUPPORTED when the FP32 working block does not fit in LDS. */
+int hdg_lp_factor_bytes(const hdg_plan *plan, size_t *bytes);
+int hdg_assemble_condense_lp(hdg_plan *plan, const double *v, const double *q, const double *vhat,
+                             const double *u_star, const double *v_bc, float *S, double *g, float *Y,
+                             double *z, float *factors, double *R_loc, double *R_tr, int32_t *elem_status,
+                             void *stream);
+
+/* x_K = A_lp,K^-1 r_K for every element from the stored FP32 factors (FP64
+ * vectors and arithmetic); r, x [E][n] element-local, must not alias. */
+int hdg_lp_solve(hdg_plan *plan, const float *factors, const double *r, double *x, void *stream);
+
+/* Matrix-free FP64 action of the element Newton matrices:
+ *   y_loc,K = A_K dx_K + B_K P_K dlam,   y_tr,K = C_K dx_K + D_K P_K dlam
+ * from the quadrature-point Jacobians (no element matrix is formed).
+ * dx, y_loc [E][n]; dlam [m][n_trace]; y_tr [E][k] (element-local trace rows;
+ * hdg_trace_rhs assembles them).  The pointwise data are recomputed from the
+ * state (v, q, vhat, u_star, v_bc as in hdg_assemble_condense) unless
+ * reuse_points != 0 and the plan processes all elements in one chunk, in which
+ * case those of the last call on this plan are used (caller guarantees the
+ * state is unchanged). */
+int hdg_jacobian_apply(hdg_plan *plan, const double *v, const double *q, const double *vhat,
+                       const double *u_star, const double *v_bc, int reuse_points, const double *dx,
+                       const double *dlam, double *y_loc, double *y_tr, int32_t *elem_status, void *stream);
+
+typedef struct {
+  int max_outer;          /* refinement steps allowed */
+  double tol;             /* target ||J delta + R|| / ||R|| (FP64, full system) */
+  int reuse_points;       /* passed to hdg_jacobian_apply */
+  hdg_solve_opts gmres;   /* inner solve on the FP32 condensed system (s_dtype forced FP32) */
+} hdg_refine_opts;
+
+typedef struct {
+  int outer_iterations, gmres_iterations, converged;
+  double rel_residual;    /* ||J delta + R|| / ||R|| of the returned delta */
+  double total_ms, gmres_ms;
+  double history[16];     /* relative residual after each refinement step */
+} hdg_refine_info;
+
+int hdg_refine_workspace_bytes(const hdg_plan *plan, const hdg_refine_opts *opts, size_t *bytes);
+
+/* Outer refinement: delta = 0; repeat  c = J_lp^-1 r  (hdg_lp_solve, FP64
+ * action of C, GMRES on the FP32 Schur system, back-solve with FP32 Y),
+ * delta += c,  r = -R - J delta (hdg_jacobian_apply)  until the relative
+ * residual reaches tol.  Outputs dx [E][n] (element-local) and dlam
+ * [m][n_trace] with J (dx, dlam) = -(R_loc, sum_K P^T R_tr). */
+int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q, const double *vhat,
+                     const double *u_star, const double *v_bc, const float *S, const float *Y,
+                     const float *factors, const double *R_loc, const double *R_tr, double *dx,
+                     double *dlam, void *work, size_t bytes, const hdg_refine_opts *opts,
+                     hdg_refine_info *info, int32_t *elem_status, void *stream);
 
 /* Optional per-phase timing with HIP events recorded on the call's stream
  * around each kernel group: 0 points (pointwise physics), 1 contract (block
  * assembly), 2 LU, 3 triangular solves, 4 Schur product (split dense path),
  * 5 back-solve, 6 trace operator, 7 trace right-hand side, 8 fused
- * condensation (LU + solves + Schur in one kernel).  Enabling resets the
- * totals; hdg_plan_phase_times returns accumulated milliseconds and call
- * counts (n >= 9 entries) and synchronizes on the last recorded events. */
+ * condensation (LU + solves + Schur in one kernel), 9 low-precision fused
+ * condensation, 10 low-precision local solve, 11 matrix-free Jacobian action.
+ * Enabling resets the totals; hdg_plan_phase_times returns accumulated
+ * milliseconds and call counts (up to n entries) and synchronizes on the last
+ * recorded events. */
 int hdg_plan_set_timing(hdg_plan *plan, int enable);
 int hdg_plan_phase_times(hdg_plan *plan, double *ms, long *calls, int n);
 

@@ -9,11 +9,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "lib", "libhdg.so")
 HEADER = os.path.join(HERE, "..", "include", "hdg.h")
 
+HDG_FP64, HDG_FP32, HDG_BF16 = 0, 1, 2
 HDG_OK, HDG_EINVAL, HDG_EUNSUPPORTED, HDG_ENONPHYS, HDG_ESINGULAR, HDG_EHIP, HDG_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 ERROR_NAMES = {0: "HDG_OK", -1: "HDG_EINVAL", -2: "HDG_EUNSUPPORTED", -3: "HDG_ENONPHYS",
                -4: "HDG_ESINGULAR", -5: "HDG_EHIP", -6: "HDG_ENOMEM"}
 ETYPES = {"tri": 0, "quad": 1, "tet": 2, "hex": 3}
-PHASES = ["points", "contract", "lu", "solve", "schur", "backsolve", "matvec", "rhs", "condense"]
+PHASES = ["points", "contract", "lu", "solve", "schur", "backsolve", "matvec", "rhs", "condense", "condense_lp",
+          "lp_solve", "jvp"]
 FLAG_SPLIT_DENSE = 1
 
 
@@ -34,7 +36,18 @@ class hdg_opts(ctypes.Structure):
 
 class hdg_solve_opts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("maxit", ctypes.c_int), ("tol", ctypes.c_double),
-                ("precond", ctypes.c_int)]
+                ("precond", ctypes.c_int), ("s_dtype", ctypes.c_int)]
+
+
+class hdg_refine_opts(ctypes.Structure):
+    _fields_ = [("max_outer", ctypes.c_int), ("tol", ctypes.c_double), ("reuse_points", ctypes.c_int),
+                ("gmres", hdg_solve_opts)]
+
+
+class hdg_refine_info(ctypes.Structure):
+    _fields_ = [("outer_iterations", ctypes.c_int), ("gmres_iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("total_ms", ctypes.c_double), ("gmres_ms", ctypes.c_double),
+                ("history", ctypes.c_double * 16)]
 
 
 class hdg_solve_info(ctypes.Structure):
@@ -68,6 +81,13 @@ SIGNATURES = {
     "hdg_precond_apply": (I, [P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P, P, P]),
     "hdg_trace_solve": (I, [P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts),
                             ctypes.POINTER(hdg_solve_info), P]),
+    "hdg_lp_factor_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_assemble_condense_lp": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
+    "hdg_lp_solve": (I, [P, P, P, P, P]),
+    "hdg_jacobian_apply": (I, [P, P, P, P, P, P, I, P, P, P, P, P, P]),
+    "hdg_refine_workspace_bytes": (I, [P, ctypes.POINTER(hdg_refine_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_refine_solve": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t,
+                             ctypes.POINTER(hdg_refine_opts), ctypes.POINTER(hdg_refine_info), P, P]),
     "hdg_selftest": (I, [ctypes.POINTER(ctypes.c_double)]),
     "hdg_plan_set_timing": (I, [P, I]),
     "hdg_plan_phase_times": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long), I]),

@@ -15,6 +15,14 @@
 // * Right-hand sides [B | R_loc] in blocks of 32 columns: permutation gather,
 //   forward and backward substitution against the stored factors, then the
 //   Schur product C * Y_block straight from LDS into S and g.
+//
+// The same kernel, instantiated for FP32, is the low-precision factorization of
+// the mixed-precision path: the FP64 blocks are symmetrically scaled by powers
+// of two, D A D with d_i = 2^-round(log2 sqrt|a_ii|) (exact in binary), rounded
+// to FP32 on their way into LDS, factored and solved on the FP32 matrix cores
+// (FP32 accumulation); Y = D Y_hat and z = D z_hat are unscaled on output and
+// the factors, pivots, scales and diagonal-block inverses are kept for the
+// refinement solves.
 #include "hdg_plan.hpp"
 
 namespace hdg {
@@ -22,34 +30,68 @@ namespace hdg {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int W = 32;        // block width
-constexpr int BS = W + 1;    // LDS row stride of the block (doubles)
+constexpr int BS = W + 1;    // LDS row stride of the block (elements)
 constexpr int NT = 512;      // threads per workgroup (8 wave64)
 constexpr int NW = NT / 64;
 
-__device__ inline d4 mfma4(double a, double b, d4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+// Matrix-core tile 16 x 16 x 4 per element type.  Operands: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator r of lane l holds
+// C[row(l / 16, r)][l % 16] with the row map below (measured on gfx950: the
+// FP64 and FP32 instructions distribute rows differently).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4 acc;
+  __device__ static inline acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef f4 acc;
+  __device__ static inline acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lk, int r) { return 4 * lk + r; }
+};
 
+template <typename T>
 struct Lds {
-  double *blk;   // [np][BS]
-  double *prow;  // [W] pivot row
-  double *tmp;   // [W] displaced row
+  T *blk;        // [np][BS]
+  T *prow;       // [W] pivot row
+  T *tmp;        // [W] displaced row
   int *perm;     // [np]
-  double *redv;  // [2][NW]
+  T *redv;       // [2][NW]
   int *redi;     // [2][NW]
+  double *dsc;   // [np] symmetric scaling (low-precision path only)
 };
 
 // blk[i][c] = M[(c0 + c) * ld + perm[i]]  (gathered through the permutation)
-__device__ inline void load_block(const Lds &s, const double *M, int ld, int c0, int np) {
+template <typename T>
+__device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, int np) {
   for (int t = threadIdx.x; t < np * W; t += NT) {
     const int c = t / np, i = t - c * np;
     s.blk[i * BS + c] = M[(size_t)(c0 + c) * ld + s.perm[i]];
   }
 }
 
-__device__ inline void store_block(const Lds &s, double *M, int ld, int c0, int np) {
+// Low-precision load of FP64 columns: blk[i][c] = d_row * M[c0+c][perm[i]] * d_col
+// (colscale false: right-hand sides, rows scaled only).
+template <typename T>
+__device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int ld, int c0, int np, bool colscale) {
+  for (int t = threadIdx.x; t < np * W; t += NT) {
+    const int c = t / np, i = t - c * np;
+    const int pi = s.perm[i];
+    double x = M[(size_t)(c0 + c) * ld + pi] * s.dsc[pi];
+    if (colscale) x *= s.dsc[c0 + c];
+    s.blk[i * BS + c] = (T)x;
+  }
+}
+
+template <typename T>
+__device__ inline void store_block(const Lds<T> &s, T *M, int ld, int c0, int np) {
   for (int t = threadIdx.x; t < np * W; t += NT) {
     const int c = t / np, i = t - c * np;
     M[(size_t)(c0 + c) * ld + s.perm[i]] = s.blk[i * BS + c];
@@ -59,36 +101,39 @@ __device__ inline void store_block(const Lds &s, double *M, int ld, int c0, int 
 // Rows p0..p0+31 of the block <- Inv * rows, Inv the stored inverse of the unit-lower
 // (L) or upper (U) 32 x 32 diagonal block of the factors; four waves each form one
 // 16 x 16 tile on MFMA, then write back after a barrier.
-__device__ inline void inv_apply(const Lds &s, const double *Inv, int p0) {
+template <typename T>
+__device__ inline void inv_apply(const Lds<T> &s, const T *Inv, int p0) {
+  typedef Mfma<T> MF;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  typename MF::acc acc = {0, 0, 0, 0};
   const int ti = wave & 1, tj = (wave >> 1) & 1;
   if (wave < 4) {
-    double a[8];
+    T a[8];
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) a[kk] = Inv[(4 * kk + lk) * W + ti * 16 + li];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) acc = mfma4(a[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
+    for (int kk = 0; kk < 8; ++kk) acc = MF::op(a[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
   }
   __syncthreads();
   if (wave < 4) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) s.blk[(p0 + ti * 16 + lk + 4 * r) * BS + tj * 16 + li] = acc[r];
+    for (int r = 0; r < 4; ++r) s.blk[(p0 + ti * 16 + MF::row(lk, r)) * BS + tj * 16 + li] = acc[r];
   }
 }
 
 // Inverses of the diagonal 32 x 32 blocks of the freshly factored panel (block rows
 // j0..j0+31): wave 0 inverts the unit-lower part, wave 1 the upper part; column c
 // of each inverse is solved by lane c.  Stored column-major (32 x 32) in Linv / Uinv.
-__device__ inline void invert_diag(const Lds &s, int j0, double *Linv, double *Uinv) {
+template <typename T>
+__device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane >= W || wave > 1) return;
   const int c = lane;
-  double x[W];
+  T x[W];
   if (wave == 0) {
 #pragma unroll
-    for (int i = 0; i < W; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+    for (int i = 0; i < W; ++i) x[i] = (i == c) ? T(1) : T(0);
 #pragma unroll
     for (int kk = 0; kk < W; ++kk)
 #pragma unroll
@@ -97,7 +142,7 @@ __device__ inline void invert_diag(const Lds &s, int j0, double *Linv, double *U
     for (int i = 0; i < W; ++i) Linv[c * W + i] = x[i];
   } else {
 #pragma unroll
-    for (int i = 0; i < W; ++i) x[i] = (i == c) ? 1.0 : 0.0;
+    for (int i = 0; i < W; ++i) x[i] = (i == c) ? T(1) : T(0);
 #pragma unroll
     for (int kk = W - 1; kk >= 0; --kk) {
       x[kk] /= s.blk[(j0 + kk) * BS + kk];
@@ -111,12 +156,14 @@ __device__ inline void invert_diag(const Lds &s, int j0, double *Linv, double *U
 
 // blk[r][:] -= sum_kk M[(p0+kk) * ld + perm[r]] * blk[p0+kk][:]  for rows r in [r_lo, r_hi)
 // (r_lo, r_hi multiples of 16, disjoint from p0..p0+31).
-__device__ inline void gemm_update(const Lds &s, const double *M, int ld, int p0, int r_lo, int r_hi) {
+template <typename T>
+__device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, int r_lo, int r_hi) {
+  typedef Mfma<T> MF;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ntile = (r_hi - r_lo) / 16;
-  const double *Mp = M + (size_t)(p0 + lk) * ld;
-  double a[8], an[8];
+  const T *Mp = M + (size_t)(p0 + lk) * ld;
+  T a[8], an[8];
   int t = wave;
   if (t < ntile) {
     const size_t grow = (size_t)s.perm[r_lo + t * 16 + li];
@@ -131,22 +178,22 @@ __device__ inline void gemm_update(const Lds &s, const double *M, int ld, int p0
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) an[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
     }
-    d4 c0, c1;
+    typename MF::acc c0, c1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      c0[r] = s.blk[(r0 + lk + 4 * r) * BS + li];
-      c1[r] = s.blk[(r0 + lk + 4 * r) * BS + 16 + li];
+      c0[r] = s.blk[(r0 + MF::row(lk, r)) * BS + li];
+      c1[r] = s.blk[(r0 + MF::row(lk, r)) * BS + 16 + li];
     }
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
-      const double *brow = s.blk + (p0 + 4 * kk + lk) * BS;
-      c0 = mfma4(a[kk], brow[li], c0);
-      c1 = mfma4(a[kk], brow[16 + li], c1);
+      const T *brow = s.blk + (p0 + 4 * kk + lk) * BS;
+      c0 = MF::op(a[kk], brow[li], c0);
+      c1 = MF::op(a[kk], brow[16 + li], c1);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      s.blk[(r0 + lk + 4 * r) * BS + li] = c0[r];
-      s.blk[(r0 + lk + 4 * r) * BS + 16 + li] = c1[r];
+      s.blk[(r0 + MF::row(lk, r)) * BS + li] = c0[r];
+      s.blk[(r0 + MF::row(lk, r)) * BS + 16 + li] = c1[r];
     }
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
@@ -163,32 +210,33 @@ __device__ inline void gemm_update(const Lds &s, const double *M, int ld, int p0
 // receive the rank-8 update.
 constexpr int SPW = 8;   // sub-panel width
 
-__device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, double *tmprow) {
+template <typename T>
+__device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T *tmprow) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = j0 + tid, r1 = j0 + tid + NT;
   const bool has0 = r0 < np, has1 = r1 < np;
-  double *y0 = s.blk + (size_t)r0 * BS;
-  double *y1 = s.blk + (size_t)r1 * BS;
+  T *y0 = s.blk + (size_t)r0 * BS;
+  T *y1 = s.blk + (size_t)r1 * BS;
   bool singular = false;
   for (int cs = 0; cs < W; cs += SPW) {
-    double x0[SPW];
+    T x0[SPW];
 #pragma unroll
-    for (int c = 0; c < SPW; ++c) x0[c] = has0 ? y0[cs + c] : 0.0;
+    for (int c = 0; c < SPW; ++c) x0[c] = has0 ? y0[cs + c] : T(0);
     for (int jj = 0; jj < SPW; ++jj) {
       const int col = cs + jj;
       const int r = j0 + col;
-      double v0 = 0.0;
+      T v0 = T(0);
 #pragma unroll
       for (int c = 0; c < SPW; ++c)
         if (c == jj) v0 = x0[c];
-      double best = -1.0;
+      T best = T(-1);
       int bi = np;
       if (has0 && r0 >= r) {
         best = fabs(v0);
         bi = r0;
       }
       if (has1) {
-        const double v1 = fabs(y1[col]);
+        const T v1 = fabs(y1[col]);
         if (v1 > best) {
           best = v1;
           bi = r1;
@@ -196,14 +244,14 @@ __device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, 
       }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
+        const T ob = __shfl_xor(best, off, 64);
         const int oi = __shfl_xor(bi, off, 64);
         if (ob > best || (ob == best && oi < bi)) {
           best = ob;
           bi = oi;
         }
       }
-      double *rv = s.redv + (col & 1) * NW;
+      T *rv = s.redv + (col & 1) * NW;
       int *ri = s.redi + (col & 1) * NW;
       if (lane == 0) {
         rv[wave] = best;
@@ -214,14 +262,14 @@ __device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, 
       bi = ri[0];
 #pragma unroll
       for (int w2 = 1; w2 < NW; ++w2) {
-        const double ob = rv[w2];
+        const T ob = rv[w2];
         const int oi = ri[w2];
         if (ob > best || (ob == best && oi < bi)) {
           best = ob;
           bi = oi;
         }
       }
-      const bool zero = !(best > 0.0);
+      const bool zero = !(best > T(0));
       singular |= zero;
       const int piv = zero ? r : bi;
       // pivot row entries of this sub-panel -> prow; if rows move, the register
@@ -240,7 +288,7 @@ __device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, 
           for (int c = 0; c < SPW; ++c) tmprow[c] = x0[c];
         }
         if (tid < W && (tid < cs || tid >= cs + SPW)) {
-          const double t0 = s.blk[r * BS + tid];
+          const T t0 = s.blk[r * BS + tid];
           s.blk[r * BS + tid] = s.blk[piv * BS + tid];
           s.blk[piv * BS + tid] = t0;
         }
@@ -265,9 +313,9 @@ __device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, 
         }
       }
       if (!zero) {
-        const double inv = 1.0 / prow[jj];
+        const T inv = T(1) / prow[jj];
         if (has0 && r0 > r) {
-          double l0 = 0.0;
+          T l0 = T(0);
 #pragma unroll
           for (int c = 0; c < SPW; ++c)
             if (c == jj) l0 = x0[c] * inv;
@@ -278,7 +326,7 @@ __device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, 
           }
         }
         if (has1) {
-          const double l1 = y1[col] * inv;
+          const T l1 = y1[col] * inv;
           y1[col] = l1;
           for (int c = jj + 1; c < SPW; ++c) y1[cs + c] -= l1 * prow[c];
         }
@@ -294,7 +342,7 @@ __device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, 
       const int rp = j0 + cs;
       if (tid < W - cs - SPW) {
         const int c = cs + SPW + tid;
-        double u[SPW];
+        T u[SPW];
 #pragma unroll
         for (int i = 0; i < SPW; ++i) u[i] = s.blk[(rp + i) * BS + c];
 #pragma unroll
@@ -307,11 +355,11 @@ __device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, 
       __syncthreads();
       // rank-8 update of the rows below
       for (int i = rp + SPW + tid; i < np; i += NT) {
-        double l[SPW];
+        T l[SPW];
 #pragma unroll
         for (int k = 0; k < SPW; ++k) l[k] = s.blk[i * BS + cs + k];
         for (int c = cs + SPW; c < W; ++c) {
-          double acc = s.blk[i * BS + c];
+          T acc = s.blk[i * BS + c];
 #pragma unroll
           for (int k = 0; k < SPW; ++k) acc -= l[k] * s.blk[(rp + k) * BS + c];
           s.blk[i * BS + c] = acc;
@@ -323,72 +371,148 @@ __device__ inline bool panel_factor(const Lds &s, int j0, int np, double *prow, 
   return singular;
 }
 
-__global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *status, double *S, double *g,
-                                                 double *Y, double *z, double *inv) {
+// LDS carve-up of k_condense_t (byte offsets, 16-byte aligned parts).
+struct LdsLayout {
+  size_t blk, prow, tmp, perm, redv, redi, dsc, total;
+};
+
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
+
+__host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp) {
+  LdsLayout L;
+  size_t o = 0;
+  L.blk = o;
+  o = al16(o + (size_t)np * BS * tsize);
+  L.prow = o;
+  o = al16(o + W * tsize);
+  L.tmp = o;
+  o = al16(o + W * tsize);
+  L.perm = o;
+  o = al16(o + (size_t)np * sizeof(int));
+  L.redv = o;
+  o = al16(o + 2 * NW * tsize);
+  L.redi = o;
+  o = al16(o + 2 * NW * sizeof(int));
+  L.dsc = o;
+  o = al16(o + (lp ? (size_t)np * sizeof(double) : 0));
+  L.total = o;
+  return L;
+}
+
+// Per-element record of the low-precision factorization (floats):
+//   F [np][np] factors at original row index | Inv [np/W][2][W][W] |
+//   perm [np] (int) | dsc [np] (symmetric scaling, powers of two)
+__host__ __device__ inline size_t lp_rec_floats(int np) {
+  return (size_t)np * np + (size_t)(np / W) * 2 * W * W + 2 * (size_t)np;
+}
+
+// T = double, LP = false: FP64 condensation, factors overwrite the A scratch.
+// T = float,  LP = true : scaled FP32 condensation, factors to the record `fac`.
+template <typename T, bool LP>
+__global__ __launch_bounds__(NT) void k_condense_t(DevPlan P, int e0, int32_t *status, T *S, double *g, T *Y,
+                                                   double *z, T *inv, float *fac) {
+  typedef Mfma<T> MF;
   extern __shared__ double smem[];
   const int el = blockIdx.x, e = e0 + el;
   const int np = P.n_pad, kp = P.k_pad, kx = P.kx, n = P.n, k = P.k;
-  double *A = P.A + (size_t)el * np * np;
+  double *A64 = P.A + (size_t)el * np * np;
   const double *X = P.X + (size_t)el * kx * np;
   const double *C = P.C + (size_t)el * np * kp;
   const double *Dm = P.D + (size_t)el * kp * kp;
   const double *Rt = P.Rt + (size_t)el * kp;
-  Lds s;
-  s.blk = smem;
-  s.prow = s.blk + (size_t)np * BS;
-  s.tmp = s.prow + W;
-  s.perm = reinterpret_cast<int *>(s.tmp + W);
-  s.redv = reinterpret_cast<double *>(s.perm + np);
-  s.redi = reinterpret_cast<int *>(s.redv + 2 * NW);
-  // inverses of the diagonal blocks: [nJ][2][W][W] per element
-  double *Ie = inv + (size_t)el * (np / W) * 2 * W * W;
+  char *sm = reinterpret_cast<char *>(smem);
+  const LdsLayout Lo = lds_layout(np, sizeof(T), LP);
+  Lds<T> s;
+  s.blk = reinterpret_cast<T *>(sm + Lo.blk);
+  s.prow = reinterpret_cast<T *>(sm + Lo.prow);
+  s.tmp = reinterpret_cast<T *>(sm + Lo.tmp);
+  s.perm = reinterpret_cast<int *>(sm + Lo.perm);
+  s.redv = reinterpret_cast<T *>(sm + Lo.redv);
+  s.redi = reinterpret_cast<int *>(sm + Lo.redi);
+  s.dsc = LP ? reinterpret_cast<double *>(sm + Lo.dsc) : nullptr;
+  // factor storage and inverses of the diagonal blocks ([nJ][2][W][W])
+  T *Fm;
+  T *Ie;
+  float *rec = nullptr;
+  if constexpr (LP) {
+    rec = fac + (size_t)e * lp_rec_floats(np);
+    Fm = rec;
+    Ie = rec + (size_t)np * np;
+  } else {
+    Fm = A64;
+    Ie = inv + (size_t)el * (np / W) * 2 * W * W;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nJ = np / W;
 
-  for (int i = tid; i < np; i += NT) s.perm[i] = i;
+  for (int i = tid; i < np; i += NT) {
+    s.perm[i] = i;
+    if constexpr (LP) {
+      const double a = fabs(A64[(size_t)i * np + i]);
+      s.dsc[i] = (a > 0.0 && a < 1e300) ? exp2(-rint(0.5 * log2(a))) : 1.0;
+    }
+  }
   __syncthreads();
   bool singular = false;
 
   // ---- LU, left-looking over 32-column blocks
   for (int J = 0; J < nJ; ++J) {
     const int j0 = J * W;
-    load_block(s, A, np, j0, np);
+    if constexpr (LP) load_block_scaled(s, A64, np, j0, np, true);
+    else load_block(s, A64, np, j0, np);
     __syncthreads();
     for (int Pp = 0; Pp < J; ++Pp) {
       const int p0 = Pp * W;
       inv_apply(s, Ie + (size_t)Pp * 2 * W * W, p0);
       __syncthreads();
-      gemm_update(s, A, np, p0, p0 + W, np);
+      gemm_update(s, Fm, np, p0, p0 + W, np);
       __syncthreads();
     }
     singular |= panel_factor(s, j0, np, s.prow, s.tmp);
     __syncthreads();
     invert_diag(s, j0, Ie + (size_t)J * 2 * W * W, Ie + (size_t)J * 2 * W * W + W * W);
-    store_block(s, A, np, j0, np);
+    store_block(s, Fm, np, j0, np);
     __syncthreads();
+  }
+  if constexpr (LP) {
+    int *rp = reinterpret_cast<int *>(rec + (size_t)np * np + (size_t)nJ * 2 * W * W);
+    float *rd = reinterpret_cast<float *>(rp + np);
+    for (int i = tid; i < np; i += NT) {
+      rp[i] = s.perm[i];
+      rd[i] = (float)s.dsc[i];
+    }
   }
 
   // ---- right-hand sides, 32 columns at a time, then the Schur product
-  double *Se = S + (size_t)e * k * k;
+  T *Se = S + (size_t)e * k * k;
   double *ge = g + (size_t)e * k;
-  double *Ye = Y + (size_t)e * n * k;
+  T *Ye = Y + (size_t)e * n * k;
   const int ntr = kp / 16;
   for (int c0 = 0; c0 < kx; c0 += W) {
-    load_block(s, X, np, c0, np);
+    if constexpr (LP) load_block_scaled(s, X, np, c0, np, false);
+    else load_block(s, X, np, c0, np);
     __syncthreads();
     for (int Pp = 0; Pp < nJ; ++Pp) {
       const int p0 = Pp * W;
       inv_apply(s, Ie + (size_t)Pp * 2 * W * W, p0);
       __syncthreads();
-      if (p0 + W < np) gemm_update(s, A, np, p0, p0 + W, np);
+      if (p0 + W < np) gemm_update(s, Fm, np, p0, p0 + W, np);
       __syncthreads();
     }
     for (int Pp = nJ - 1; Pp >= 0; --Pp) {
       const int p0 = Pp * W;
       inv_apply(s, Ie + (size_t)Pp * 2 * W * W + W * W, p0);
       __syncthreads();
-      if (p0 > 0) gemm_update(s, A, np, p0, 0, p0);
+      if (p0 > 0) gemm_update(s, Fm, np, p0, 0, p0);
+      __syncthreads();
+    }
+    if constexpr (LP) {
+      // undo the column scaling: Y = D Y_hat, z = D z_hat
+      for (int t = tid; t < np * W; t += NT) {
+        const int c = t / np, i = t - c * np;
+        s.blk[i * BS + c] = (T)((double)s.blk[i * BS + c] * s.dsc[i]);
+      }
       __syncthreads();
     }
     // outputs Y, z (compact)
@@ -396,39 +520,39 @@ __global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *sta
       const int c = t / n, i = t - c * n;
       const int col = c0 + c;
       if (col < k) Ye[(size_t)col * n + i] = s.blk[i * BS + c];
-      else if (col == kp) z[(size_t)e * n + i] = s.blk[i * BS + c];
+      else if (col == kp) z[(size_t)e * n + i] = (double)s.blk[i * BS + c];
     }
     // T = C * block (k_pad x 32): S = D - T, g = -R_tr + T
     for (int t = wave; t < ntr; t += NW) {
       const int r0 = t * 16;
-      d4 a0 = {0.0, 0.0, 0.0, 0.0}, a1 = {0.0, 0.0, 0.0, 0.0};
+      typename MF::acc a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
       const double *Cr = C + (size_t)lk * kp + r0 + li;
-      double a[8], an[8];
+      T a[8], an[8];
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) a[kk] = Cr[(size_t)(4 * kk) * kp];
+      for (int kk = 0; kk < 8; ++kk) a[kk] = (T)Cr[(size_t)(4 * kk) * kp];
       for (int kb = 0; kb < np; kb += 32) {
         if (kb + 32 < np) {
 #pragma unroll
-          for (int kk = 0; kk < 8; ++kk) an[kk] = Cr[(size_t)(kb + 32 + 4 * kk) * kp];
+          for (int kk = 0; kk < 8; ++kk) an[kk] = (T)Cr[(size_t)(kb + 32 + 4 * kk) * kp];
         }
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
-          const double *brow = s.blk + (kb + 4 * kk + lk) * BS;
-          a0 = mfma4(a[kk], brow[li], a0);
-          a1 = mfma4(a[kk], brow[16 + li], a1);
+          const T *brow = s.blk + (kb + 4 * kk + lk) * BS;
+          a0 = MF::op(a[kk], brow[li], a0);
+          a1 = MF::op(a[kk], brow[16 + li], a1);
         }
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = r0 + lk + 4 * r;
+        const int row = r0 + MF::row(lk, r);
         if (row >= k) continue;
         const int col0 = c0 + li, col1 = c0 + 16 + li;
-        if (col0 < k) Se[(size_t)col0 * k + row] = Dm[(size_t)col0 * kp + row] - a0[r];
-        else if (col0 == kp) ge[row] = -Rt[row] + a0[r];
-        if (col1 < k) Se[(size_t)col1 * k + row] = Dm[(size_t)col1 * kp + row] - a1[r];
-        else if (col1 == kp) ge[row] = -Rt[row] + a1[r];
+        if (col0 < k) Se[(size_t)col0 * k + row] = (T)(Dm[(size_t)col0 * kp + row] - (double)a0[r]);
+        else if (col0 == kp) ge[row] = -Rt[row] + (double)a0[r];
+        if (col1 < k) Se[(size_t)col1 * k + row] = (T)(Dm[(size_t)col1 * kp + row] - (double)a1[r]);
+        else if (col1 == kp) ge[row] = -Rt[row] + (double)a1[r];
       }
     }
     __syncthreads();
@@ -436,22 +560,115 @@ __global__ __launch_bounds__(NT) void k_condense(DevPlan P, int e0, int32_t *sta
   if (singular && tid == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
 }
 
+// x = A_lp^-1 r per element from the low-precision record: y = P D r, forward
+// substitution (unit L) and backward substitution (U) over W-column blocks
+// with the stored diagonal-block inverses, x = D y.  Vectors and arithmetic in
+// FP64, factors read as FP32; rows are visited in their stored (original)
+// order so every factor column is read contiguously.  One workgroup per element.
+constexpr int SB = 256;
+
+__global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, const float *__restrict__ fac,
+                                                 const double *__restrict__ r, double *x) {
+  extern __shared__ double sm2[];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int nJ = np / W;
+  double *y = sm2;                                   // [np] by pivot position
+  double *t32 = y + np;                              // [W]
+  int *ipos = reinterpret_cast<int *>(t32 + W);      // [np] position of original row o
+  const float *rec = fac + (size_t)e * lp_rec_floats(np);
+  const float *F = rec;
+  const float *Inv = rec + (size_t)np * np;
+  const int *perm = reinterpret_cast<const int *>(Inv + (size_t)nJ * 2 * W * W);
+  const float *dsc = reinterpret_cast<const float *>(perm + np);
+  const double *re = r + (size_t)e * n;
+  for (int i = tid; i < np; i += SB) {
+    const int o = perm[i];
+    ipos[o] = i;
+    y[i] = o < n ? (double)dsc[o] * re[o] : 0.0;
+  }
+  __syncthreads();
+  // forward: unit lower
+  for (int J = 0; J < nJ; ++J) {
+    const int j0 = J * W;
+    const float *Li = Inv + (size_t)J * 2 * W * W;
+    if (tid < W) {
+      double acc = 0.0;
+      for (int c = 0; c < W; ++c) acc += (double)Li[c * W + tid] * y[j0 + c];
+      t32[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < W) y[j0 + tid] = t32[tid];
+    __syncthreads();
+    for (int o = tid; o < np; o += SB) {
+      const int i = ipos[o];
+      if (i < j0 + W) continue;
+      double acc = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < W; ++c) acc += (double)F[(size_t)(j0 + c) * np + o] * y[j0 + c];
+      y[i] -= acc;
+    }
+    __syncthreads();
+  }
+  // backward: upper
+  for (int J = nJ - 1; J >= 0; --J) {
+    const int j0 = J * W;
+    const float *Ui = Inv + (size_t)J * 2 * W * W + W * W;
+    if (tid < W) {
+      double acc = 0.0;
+      for (int c = 0; c < W; ++c) acc += (double)Ui[c * W + tid] * y[j0 + c];
+      t32[tid] = acc;
+    }
+    __syncthreads();
+    if (tid < W) y[j0 + tid] = t32[tid];
+    __syncthreads();
+    if (j0 > 0) {
+      for (int o = tid; o < np; o += SB) {
+        const int i = ipos[o];
+        if (i >= j0) continue;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < W; ++c) acc += (double)F[(size_t)(j0 + c) * np + o] * y[j0 + c];
+        y[i] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += SB) x[(size_t)e * n + i] = (double)dsc[i] * y[i];
+}
+
 }  // namespace
 
-size_t condense_lds_bytes(int np) {
-  return ((size_t)np * BS + 2 * W) * sizeof(double) + (size_t)np * sizeof(int) +
-         2 * NW * (sizeof(double) + sizeof(int));
-}
+size_t condense_lds_bytes(int np) { return lds_layout(np, sizeof(double), false).total; }
+
+size_t condense_lds_bytes_lp(int np) { return lds_layout(np, sizeof(float), true).total; }
 
 size_t condense_inv_doubles(int np) { return (size_t)(np / W) * 2 * W * W; }
 
+size_t lp_record_bytes(int np) { return lp_rec_floats(np) * sizeof(float); }
+
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s) {
-  double *inv = P.inv;
   const size_t lds = condense_lds_bytes(P.n_pad);
-  hipError_t e = hipFuncSetAttribute((const void *)k_condense, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  auto *kern = k_condense_t<double, false>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e) return e;
-  hipLaunchKernelGGL(k_condense, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, inv);
+  hipLaunchKernelGGL(kern, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, P.inv, (float *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
+                              double *z, float *fac, hipStream_t s) {
+  const size_t lds = condense_lds_bytes_lp(P.n_pad);
+  auto *kern = k_condense_t<float, true>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e) return e;
+  hipLaunchKernelGGL(kern, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, (float *)nullptr, fac);
+  return hipGetLastError();
+}
+
+hipError_t launch_lp_solve(const DevPlan &P, const float *fac, const double *r, double *x, hipStream_t s) {
+  const size_t lds = (size_t)(P.n_pad + W) * sizeof(double) + (size_t)P.n_pad * sizeof(int);
+  hipLaunchKernelGGL(k_lp_solve, dim3(P.n_elem), dim3(SB), lds, s, P.n, P.n_pad, fac, r, x);
   return hipGetLastError();
 }
 

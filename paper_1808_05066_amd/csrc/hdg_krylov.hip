@@ -14,7 +14,8 @@ constexpr int RB = 256;   // reduction block size
 // Face blocks: unknowns of one mesh face (HDG), ordered (c, p) -> c*Nfp + p with p
 // the position of the trace node in the block's node list.  Each block sums the
 // face-diagonal part of S of its (at most two) adjacent elements.
-__global__ void k_bj_assemble_face(DevPlan P, const double *__restrict__ S, double *B) {
+template <typename T>
+__global__ void k_bj_assemble_face(DevPlan P, const T *__restrict__ S, double *B) {
   const int blk = blockIdx.x;
   const int M = P.m, Nfp = P.Nfp, k = P.k, bs = M * Nfp;
   double *Bb = B + (size_t)blk * bs * bs;
@@ -29,7 +30,7 @@ __global__ void k_bj_assemble_face(DevPlan P, const double *__restrict__ S, doub
       const int *loc = P.bj_loc + ((size_t)blk * 2 + q) * Nfp;
       const int i = f * M * Nfp + c * Nfp + loc[p];
       const int j = f * M * Nfp + c2 * Nfp + loc[p2];
-      acc += S[(size_t)e * k * k + (size_t)j * k + i];
+      acc += (double)S[(size_t)e * k * k + (size_t)j * k + i];
     }
     Bb[(size_t)col * bs + row] = acc;
   }
@@ -37,7 +38,8 @@ __global__ void k_bj_assemble_face(DevPlan P, const double *__restrict__ S, doub
 
 // Point blocks (m x m per trace node): every pair of element trace rows that map
 // to the same node adds its entry (FP64 atomics; used when faces share nodes).
-__global__ void k_bj_assemble_point(DevPlan P, const double *__restrict__ S, double *B) {
+template <typename T>
+__global__ void k_bj_assemble_point(DevPlan P, const T *__restrict__ S, double *B) {
   const int e = blockIdx.x;
   const int M = P.m, Nfp = P.Nfp, k = P.k;
   const int *tm = P.tmap + (size_t)e * P.nf * Nfp;
@@ -47,7 +49,7 @@ __global__ void k_bj_assemble_point(DevPlan P, const double *__restrict__ S, dou
     const int bj = j % Nfp, fj = j / (M * Nfp), cj = (j / Nfp) % M;
     const int ni = tm[fi * Nfp + bi], nj = tm[fj * Nfp + bj];
     if (ni != nj) continue;
-    atomicAdd(&B[(size_t)ni * M * M + cj * M + ci], S[(size_t)e * k * k + (size_t)j * k + i]);
+    atomicAdd(&B[(size_t)ni * M * M + cj * M + ci], (double)S[(size_t)e * k * k + (size_t)j * k + i]);
   }
 }
 
@@ -214,15 +216,24 @@ __global__ void k_scale_by(const double *__restrict__ x, const double *__restric
 
 }  // namespace
 
-hipError_t launch_bj_assemble(const DevPlan &P, const double *S, double *B, hipStream_t s) {
+template <typename T>
+hipError_t launch_bj_assemble_t(const DevPlan &P, const T *S, double *B, hipStream_t s) {
   if (P.bj_face) {
-    hipLaunchKernelGGL(k_bj_assemble_face, dim3(P.bj_nblk), dim3(256), 0, s, P, S, B);
+    hipLaunchKernelGGL(k_bj_assemble_face<T>, dim3(P.bj_nblk), dim3(256), 0, s, P, S, B);
   } else {
     hipError_t e = launch_fill_double(B, (size_t)P.bj_nblk * P.m * P.m, 0.0, s);
     if (e) return e;
-    hipLaunchKernelGGL(k_bj_assemble_point, dim3(P.n_elem), dim3(256), 0, s, P, S, B);
+    hipLaunchKernelGGL(k_bj_assemble_point<T>, dim3(P.n_elem), dim3(256), 0, s, P, S, B);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_bj_assemble(const DevPlan &P, const double *S, double *B, hipStream_t s) {
+  return launch_bj_assemble_t<double>(P, S, B, s);
+}
+
+hipError_t launch_bj_assemble_f32(const DevPlan &P, const float *S, double *B, hipStream_t s) {
+  return launch_bj_assemble_t<float>(P, S, B, s);
 }
 
 hipError_t launch_block_invert(const DevPlan &P, double *B, int32_t *bad, hipStream_t s) {

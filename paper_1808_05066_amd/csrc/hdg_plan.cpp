@@ -385,6 +385,10 @@ Layout layout(const Plan *P) {
   return l;
 }
 
+}  // namespace
+
+namespace hdg {
+
 Plan *checked(hdg_plan *plan) {
   Plan *P = reinterpret_cast<Plan *>(plan);
   if (!P) {
@@ -397,6 +401,10 @@ Plan *checked(hdg_plan *plan) {
   }
   return P;
 }
+
+}  // namespace hdg
+
+namespace {
 
 }  // namespace
 
@@ -489,7 +497,7 @@ extern "C" int hdg_prepare_state(const hdg_plan *plan, int N, const double *prim
   return HDG_OK;
 }
 
-namespace {
+namespace hdg {
 
 // Accumulate the elapsed time of the previous launch of a phase (events are
 // reused, so the previous interval is read before recording a new one).
@@ -539,7 +547,7 @@ int check_inputs(const Plan *P, const double *v, const double *q, const double *
   return HDG_OK;
 }
 
-}  // namespace
+}  // namespace hdg
 
 extern "C" int hdg_assemble(hdg_plan *plan, const double *v, const double *q, const double *vhat,
                             const double *ustar, const double *vbc, double *A, double *B, double *C,

@@ -54,7 +54,10 @@ struct DevPlan {
 };
 
 // Phases timed with HIP events when phase timing is enabled.
-enum Phase { PH_POINTS = 0, PH_CONTRACT, PH_LU, PH_SOLVE, PH_SCHUR, PH_BACKSOLVE, PH_MATVEC, PH_RHS, PH_CONDENSE, PH_COUNT };
+enum Phase {
+  PH_POINTS = 0, PH_CONTRACT, PH_LU, PH_SOLVE, PH_SCHUR, PH_BACKSOLVE, PH_MATVEC, PH_RHS, PH_CONDENSE,
+  PH_CONDENSE_LP, PH_LP_SOLVE, PH_JVP, PH_COUNT
+};
 
 struct Plan {
   RefTables ref;
@@ -79,6 +82,15 @@ struct Plan {
   bool bound = false;
 };
 
+// plan helpers shared by the entry-point sources (hdg_plan.cpp)
+Plan *checked(hdg_plan *plan);   // null or unbound plan -> nullptr with the error recorded
+hipError_t phase_begin(Plan *P, int ph, hipStream_t s);
+hipError_t phase_end(Plan *P, int ph, hipStream_t s);
+int run_front(Plan *P, const double *v, const double *q, const double *vhat, const double *ustar,
+              const double *vbc, int32_t *status, int e0, int ec, hipStream_t s);
+int check_inputs(const Plan *P, const double *v, const double *q, const double *vhat, const double *ustar,
+                 int32_t *status);
+
 // error channel of hdg_last_error(): records the message, returns the code
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);
@@ -97,6 +109,17 @@ hipError_t launch_schur(const DevPlan &P, int e0, int ec, double *S, double *g, 
 hipError_t launch_copy_resid(const DevPlan &P, int e0, int ec, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_mfma_selftest(double *out, hipStream_t s);
 size_t condense_lds_bytes(int np);
+size_t condense_lds_bytes_lp(int np);
+size_t lp_record_bytes(int np);
+hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
+                              double *z, float *fac, hipStream_t s);
+hipError_t launch_lp_solve(const DevPlan &P, const float *fac, const double *r, double *x, hipStream_t s);
+hipError_t launch_jvp(const DevPlan &P, int e0, int ec, const double *dx, const double *dlam, double *yloc,
+                      double *ytr, hipStream_t s);
+hipError_t launch_trace_matvec_f32(const DevPlan &P, const float *S, const double *x, double *y, hipStream_t s);
+hipError_t launch_backsolve_local_f32(const DevPlan &P, const float *Y, const double *a, const double *dvhat,
+                                      double *out, hipStream_t s);
+hipError_t launch_bj_assemble_f32(const DevPlan &P, const float *S, double *B, hipStream_t s);
 size_t condense_inv_doubles(int np);
 bool contract_mfma_supported(const DevPlan &P);
 hipError_t launch_contract_mfma(const DevPlan &P, int e0, int ec, hipStream_t s);

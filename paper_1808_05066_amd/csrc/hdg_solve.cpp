@@ -53,10 +53,11 @@ extern "C" int hdg_solver_workspace_bytes(const hdg_plan *plan, const hdg_solve_
   return HDG_OK;
 }
 
-extern "C" int hdg_precond_setup(hdg_plan *plan, const double *S, void *work, size_t bytes,
+extern "C" int hdg_precond_setup(hdg_plan *plan, const void *S, void *work, size_t bytes,
                                  const hdg_solve_opts *opts, void *stream) {
   Plan *P = reinterpret_cast<Plan *>(plan);
   if (!P || !P->bound || !S || !work || !opts) return fail(HDG_EINVAL, "bad argument or unbound plan");
+  if (opts->s_dtype != HDG_FP64 && opts->s_dtype != HDG_FP32) return fail(HDG_EINVAL, "s_dtype must be FP64 or FP32");
   SolveLayout l = solve_layout(P, opts->restart);
   if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -64,7 +65,9 @@ extern "C" int hdg_precond_setup(hdg_plan *plan, const double *S, void *work, si
   double *B = reinterpret_cast<double *>(base + l.binv);
   int32_t *bad = reinterpret_cast<int32_t *>(base + l.bad);
   hipError_t e = launch_fill_int(bad, 1, 0, s);
-  if (!e) e = launch_bj_assemble(P->dp, S, B, s);
+  if (!e)
+    e = opts->s_dtype == HDG_FP32 ? launch_bj_assemble_f32(P->dp, static_cast<const float *>(S), B, s)
+                                  : launch_bj_assemble(P->dp, static_cast<const double *>(S), B, s);
   if (!e) e = launch_block_invert(P->dp, B, bad, s);
   int32_t hbad = 0;
   if (!e) e = hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s);
@@ -86,12 +89,13 @@ extern "C" int hdg_precond_apply(hdg_plan *plan, void *work, size_t bytes, const
   return HDG_OK;
 }
 
-extern "C" int hdg_trace_solve(hdg_plan *plan, const double *S, const double *rhs, double *x, void *work,
+extern "C" int hdg_trace_solve(hdg_plan *plan, const void *S, const double *rhs, double *x, void *work,
                                size_t bytes, const hdg_solve_opts *opts, hdg_solve_info *info, void *stream) {
   Plan *P = reinterpret_cast<Plan *>(plan);
   if (!P || !P->bound || !S || !rhs || !x || !work || !opts || !info) return fail(HDG_EINVAL, "bad argument");
   const int m = opts->restart;
-  if (m < 1 || opts->maxit < 1 || !(opts->tol > 0.0)) return fail(HDG_EINVAL, "bad solver options");
+  if (m < 1 || opts->maxit < 1 || !(opts->tol > 0.0) || (opts->s_dtype != HDG_FP64 && opts->s_dtype != HDG_FP32))
+    return fail(HDG_EINVAL, "bad solver options");
   SolveLayout l = solve_layout(P, m);
   if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
   auto t0 = std::chrono::steady_clock::now();
@@ -116,7 +120,8 @@ extern "C" int hdg_trace_solve(hdg_plan *plan, const double *S, const double *rh
     return hipMemcpyAsync(out, in, N * 8, hipMemcpyDeviceToDevice, s);
   };
   auto matvec = [&](const double *in, double *out) -> hipError_t {
-    return launch_trace_matvec(P->dp, S, in, out, s);
+    if (opts->s_dtype == HDG_FP32) return launch_trace_matvec_f32(P->dp, static_cast<const float *>(S), in, out, s);
+    return launch_trace_matvec(P->dp, static_cast<const double *>(S), in, out, s);
   };
   auto norm = [&](const double *v, double &out) -> hipError_t {
     hipError_t ee = launch_multidot(v, N, 1, v, N, partial, NB_RED, dn, s);

@@ -44,18 +44,38 @@ __global__ __launch_bounds__(BLK) void k_backsolve(DevPlan P, const double *__re
   }
 }
 
-__global__ __launch_bounds__(BLK) void k_trace_matvec(DevPlan P, const double *__restrict__ S,
+// out[e] = a[e] - Y_e P_e dlambda on element-local vectors [E][n] (refinement
+// loop of the mixed-precision path; Y in FP64 or FP32, arithmetic in FP64).
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_backsolve_local(DevPlan P, const T *__restrict__ Y,
+                                                          const double *__restrict__ a,
+                                                          const double *__restrict__ dvhat, double *out) {
+  extern __shared__ double xl[];
+  const int e = blockIdx.x;
+  const int n = P.n, k = P.k;
+  gather_trace(P, e, dvhat, xl);
+  __syncthreads();
+  const T *Ye = Y + (size_t)e * n * k;
+  for (int row = threadIdx.x; row < n; row += BLK) {
+    double acc = a[(size_t)e * n + row];
+    for (int col = 0; col < k; ++col) acc -= (double)Ye[(size_t)col * n + row] * xl[col];
+    out[(size_t)e * n + row] = acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_trace_matvec(DevPlan P, const T *__restrict__ S,
                                                        const double *__restrict__ x, double *y) {
   extern __shared__ double xl[];
   const int e = blockIdx.x;
   const int k = P.k, Nfp = P.Nfp, M = P.m, nf = P.nf;
   gather_trace(P, e, x, xl);
   __syncthreads();
-  const double *Se = S + (size_t)e * k * k;
+  const T *Se = S + (size_t)e * k * k;
   const int *tm = P.tmap + (size_t)e * nf * Nfp;
   for (int row = threadIdx.x; row < k; row += BLK) {
     double acc = 0.0;
-    for (int col = 0; col < k; ++col) acc += Se[(size_t)col * k + row] * xl[col];
+    for (int col = 0; col < k; ++col) acc += (double)Se[(size_t)col * k + row] * xl[col];
     const int b = row % Nfp, c = (row / Nfp) % M, f = row / (Nfp * M);
     atomicAdd(&y[(size_t)c * P.n_trace + tm[f * Nfp + b]], acc);
   }
@@ -129,7 +149,21 @@ hipError_t launch_backsolve(const DevPlan &P, const double *Y, const double *z, 
 hipError_t launch_trace_matvec(const DevPlan &P, const double *S, const double *x, double *y, hipStream_t s) {
   hipError_t e = launch_fill_double(y, (size_t)P.m * P.n_trace, 0.0, s);
   if (e) return e;
-  hipLaunchKernelGGL(k_trace_matvec, dim3(P.n_elem), dim3(BLK), P.k * sizeof(double), s, P, S, x, y);
+  hipLaunchKernelGGL(k_trace_matvec<double>, dim3(P.n_elem), dim3(BLK), P.k * sizeof(double), s, P, S, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_matvec_f32(const DevPlan &P, const float *S, const double *x, double *y, hipStream_t s) {
+  hipError_t e = launch_fill_double(y, (size_t)P.m * P.n_trace, 0.0, s);
+  if (e) return e;
+  hipLaunchKernelGGL(k_trace_matvec<float>, dim3(P.n_elem), dim3(BLK), P.k * sizeof(double), s, P, S, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_backsolve_local_f32(const DevPlan &P, const float *Y, const double *a, const double *dvhat,
+                                      double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve_local<float>, dim3(P.n_elem), dim3(BLK), P.k * sizeof(double), s, P, Y, a, dvhat,
+                     out);
   return hipGetLastError();
 }
 

@@ -155,6 +155,80 @@ class Plan:
         check(self.lib.hdg_plan_phase_times(self.h, ms, calls, n), "hdg_plan_phase_times")
         return {name: (ms[i], calls[i]) for i, name in enumerate(_lib.PHASES)}
 
+    # -- mixed precision -----------------------------------------------------
+    def lp_factor_bytes(self):
+        nb = ctypes.c_size_t()
+        check(self.lib.hdg_lp_factor_bytes(self.h, ctypes.byref(nb)), "hdg_lp_factor_bytes")
+        return int(nb.value)
+
+    def alloc_outputs_lp(self, residuals=True):
+        """Outputs of assemble_condense_lp: FP32 S, Y; FP64 g, z; FP32 factor records."""
+        torch = _torch()
+        E, n, k = self.n_elem, self.n, self.k
+        f32 = torch.float32
+        out = dict(S=self._empty(E, k, k, dtype=f32), g=self._empty(E, k), Y=self._empty(E, k, n, dtype=f32),
+                   z=self._empty(E, n), factors=self._empty(self.lp_factor_bytes() // 4, dtype=f32),
+                   status=torch.empty(E, dtype=torch.int32, device=self.device))
+        if residuals:
+            out["R_loc"] = self._empty(E, n)
+            out["R_tr"] = self._empty(E, k)
+        return out
+
+    def assemble_condense_lp(self, v, q, vhat, ustar=None, vbc=None, out=None, residuals=True):
+        if out is None:
+            out = self.alloc_outputs_lp(residuals)
+        check(self.lib.hdg_assemble_condense_lp(
+            self.h, _ptr(v), _ptr(q), _ptr(vhat), _ptr(ustar), _ptr(vbc), _ptr(out["S"]), _ptr(out["g"]),
+            _ptr(out["Y"]), _ptr(out["z"]), _ptr(out["factors"]), _ptr(out.get("R_loc")), _ptr(out.get("R_tr")),
+            _ptr(out["status"]), _stream()), "hdg_assemble_condense_lp")
+        return out
+
+    def lp_solve(self, factors, r, x=None):
+        if x is None:
+            x = self._empty(self.n_elem, self.n)
+        check(self.lib.hdg_lp_solve(self.h, _ptr(factors), _ptr(r), _ptr(x), _stream()), "hdg_lp_solve")
+        return x
+
+    def jacobian_apply(self, v, q, vhat, dx, dlam, ustar=None, vbc=None, reuse_points=False, y_loc=None,
+                       y_tr=None, status=None):
+        torch = _torch()
+        if y_loc is None:
+            y_loc = self._empty(self.n_elem, self.n)
+        if y_tr is None:
+            y_tr = self._empty(self.n_elem, self.k)
+        if status is None:
+            status = torch.zeros(self.n_elem, dtype=torch.int32, device=self.device)
+        check(self.lib.hdg_jacobian_apply(self.h, _ptr(v), _ptr(q), _ptr(vhat), _ptr(ustar), _ptr(vbc),
+                                          int(bool(reuse_points)), _ptr(dx), _ptr(dlam), _ptr(y_loc), _ptr(y_tr),
+                                          _ptr(status), _stream()), "hdg_jacobian_apply")
+        return y_loc, y_tr
+
+    def refine_solve(self, v, q, vhat, lp, ustar=None, vbc=None, tol=1e-10, max_outer=10, reuse_points=False,
+                     gmres_restart=50, gmres_maxit=2000, gmres_tol=1e-6, precond="block_jacobi"):
+        """Outer FP64 refinement of the full Newton system with the low-precision outputs `lp`.
+
+        Returns (dx [E][n], dlam [m][n_trace], info dict)."""
+        torch = _torch()
+        go = _lib.hdg_solve_opts(int(gmres_restart), int(gmres_maxit), float(gmres_tol),
+                                 TraceSolver.PRECONDS[precond], _lib.HDG_FP32)
+        opts = _lib.hdg_refine_opts(int(max_outer), float(tol), int(bool(reuse_points)), go)
+        nb = ctypes.c_size_t()
+        check(self.lib.hdg_refine_workspace_bytes(self.h, ctypes.byref(opts), ctypes.byref(nb)),
+              "hdg_refine_workspace_bytes")
+        work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        wp = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        dx = self._empty(self.n_elem, self.n)
+        dlam = self._empty(self.m, self.n_trace)
+        info = _lib.hdg_refine_info()
+        status = torch.zeros(self.n_elem, dtype=torch.int32, device=self.device)
+        check(self.lib.hdg_refine_solve(self.h, _ptr(v), _ptr(q), _ptr(vhat), _ptr(ustar), _ptr(vbc), _ptr(lp["S"]),
+                                        _ptr(lp["Y"]), _ptr(lp["factors"]), _ptr(lp["R_loc"]), _ptr(lp["R_tr"]),
+                                        _ptr(dx), _ptr(dlam), wp, ctypes.c_size_t(nb.value), ctypes.byref(opts),
+                                        ctypes.byref(info), _ptr(status), _stream()), "hdg_refine_solve")
+        res = {f: getattr(info, f) for f, _ in _lib.hdg_refine_info._fields_ if f != "history"}
+        res["history"] = [info.history[i] for i in range(min(16, info.outer_iterations))]
+        return dx, dlam, res
+
     def trace_rhs(self, g, r=None):
         if r is None:
             r = self._empty(self.m, self.n_trace)
@@ -171,10 +245,11 @@ class TraceSolver:
 
     PRECONDS = {"none": 0, "block_jacobi": 1}
 
-    def __init__(self, plan, restart=50, maxit=2000, tol=1e-10, precond="block_jacobi"):
+    def __init__(self, plan, restart=50, maxit=2000, tol=1e-10, precond="block_jacobi", s_dtype="fp64"):
         torch = _torch()
         self.plan = plan
-        self.opts = _lib.hdg_solve_opts(int(restart), int(maxit), float(tol), self.PRECONDS[precond])
+        self.opts = _lib.hdg_solve_opts(int(restart), int(maxit), float(tol), self.PRECONDS[precond],
+                                        {"fp64": _lib.HDG_FP64, "fp32": _lib.HDG_FP32}[s_dtype])
         nb = ctypes.c_size_t()
         check(plan.lib.hdg_solver_workspace_bytes(plan.h, ctypes.byref(self.opts), ctypes.byref(nb)),
               "hdg_solver_workspace_bytes")
