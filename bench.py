@@ -89,6 +89,72 @@ def cpu_baseline(wl, seconds_budget=20.0):
                       "LAPACK condensation, 1 BLAS thread, %.1f s" % (done, t_used)}
 
 
+def _timed(fn, reps, torch):
+    """Median milliseconds of fn() over reps runs, HIP events on the current stream."""
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
+def bench_mixed(plan, inp, out64, E, fp64_cond_ms, torch):
+    """FP32 condensation + FP64 refinement of the full Newton system to 1e-10.
+
+    Mixed elem/s = E / (t_factor_lp + n_ref * t_refine_local): t_factor_lp the
+    low-precision assemble + condense, t_refine_local the per-step local work
+    of the refinement (FP32 local solves, matrix-free FP64 Jacobian actions,
+    back-solve, norms; host wall time of the loop minus its GMRES time), n_ref
+    the refinement steps to reach the tolerance.  GMRES time is reported apart.
+    """
+    lp = plan.alloc_outputs_lp()
+    args = (inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
+    plan.assemble_condense_lp(*args, out=lp)
+    torch.cuda.synchronize()
+    if int((lp["status"] != 0).sum()):
+        return {"error": "non-OK element status in the low-precision path"}
+    t_lp = _timed(lambda: plan.assemble_condense_lp(*args, out=lp), 5, torch)
+    plan.assemble_condense(*args, out=out64)
+    plan.assemble_condense_lp(*args, out=lp)
+    torch.cuda.synchronize()
+    dx, dlam, info = plan.refine_solve(*args[:3], lp, ustar=inp["ustar"], vbc=inp["vbc"], tol=1e-10,
+                                       max_outer=10, reuse_points=True, gmres_restart=50, gmres_tol=1e-8)
+    n_ref = max(1, info["outer_iterations"])
+    t_local = (info["total_ms"] - info["gmres_ms"]) / n_ref
+    value = E / ((t_lp + n_ref * t_local) / 1e3)
+
+    def rel(a, b):
+        a = a.double()
+        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+    errs = {"S": rel(lp["S"], out64["S"]), "Y": rel(lp["Y"], out64["Y"]), "g": rel(lp["g"], out64["g"]),
+            "z": rel(lp["z"], out64["z"])}
+    return {"value": value, "unit": "elem/s", "dtype": "f32 condensation + f64 refinement",
+            "speedup_vs_fp64": value / (E / (fp64_cond_ms / 1e3)),
+            "t_factor_lp_ms": t_lp, "refine_steps": info["outer_iterations"], "t_refine_local_ms": t_local,
+            "refine_rel_residual": info["rel_residual"], "refine_history": info["history"],
+            "gmres_iterations": info["gmres_iterations"], "gmres_ms": info["gmres_ms"],
+            "converged": info["converged"], "rel_err_vs_fp64_gpu": errs}
+
+
+def bench_solve(plan, out, rhs, torch):
+    """GMRES(50) + block Jacobi to 1e-10 on the FP64 condensed system (outside the timed step)."""
+    from paper_1808_05066_amd.hdg import TraceSolver
+    ts = TraceSolver(plan, restart=50, maxit=2000, tol=1e-10, precond="block_jacobi")
+    ts.setup(out["S"])
+    plan.trace_rhs(out["g"], rhs)
+    t_setup = _timed(lambda: ts.setup(out["S"]), 3, torch)
+    x, info = ts.solve(out["S"], rhs)
+    torch.cuda.synchronize()
+    return {"restart": 50, "precond": "block_jacobi", "tol": 1e-10, "iterations": info["iterations"],
+            "rel_residual": info["rel_residual"], "converged": info["converged"], "solve_ms": info["solve_ms"],
+            "setup_ms": t_setup, "unknowns": plan.m * plan.n_trace}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +163,8 @@ def main():
     ap.add_argument("--workload", default="ns3d_hex_p2_16", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurement")
+    ap.add_argument("--no-solve", action="store_true", help="skip the GMRES measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -185,6 +253,12 @@ def main():
         "condensed_GBps": E * (k * k + k) * 8 / (cond_ms / 1e3) / 1e9,
         "wall_s_timed": wall,
     }
+    if not args.no_mixed:
+        print("[bench] mixed-precision path", file=sys.stderr, flush=True)
+        res["mixed"] = bench_mixed(plan, inp, out, E, cond_ms, torch)
+    if not args.no_solve:
+        print("[bench] global trace solve", file=sys.stderr, flush=True)
+        res["trace_solve"] = bench_solve(plan, out, r, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

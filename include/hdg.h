@@ -270,7 +270,7 @@ typedef struct {
 typedef struct {
   int outer_iterations, gmres_iterations, converged;
   double rel_residual;    /* ||J delta + R|| / ||R|| of the returned delta */
-  double total_ms, gmres_ms;
+  double total_ms, gmres_ms;   /* host wall time: whole call; global solves incl. preconditioner setup */
   double history[16];     /* relative residual after each refinement step */
 } hdg_refine_info;
 

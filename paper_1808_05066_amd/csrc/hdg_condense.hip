@@ -408,9 +408,10 @@ __host__ __device__ inline size_t lp_rec_floats(int np) {
 
 // T = double, LP = false: FP64 condensation, factors overwrite the A scratch.
 // T = float,  LP = true : scaled FP32 condensation, factors to the record `fac`.
+// One workgroup per element (blockIdx.x = element of the chunk).
 template <typename T, bool LP>
-__global__ __launch_bounds__(NT) void k_condense_t(DevPlan P, int e0, int32_t *status, T *S, double *g, T *Y,
-                                                   double *z, T *inv, float *fac) {
+__device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t *status, T *S, double *g, T *Y,
+                                              double *z, T *inv, float *fac) {
   typedef Mfma<T> MF;
   extern __shared__ double smem[];
   const int el = blockIdx.x, e = e0 + el;
@@ -560,6 +561,18 @@ __global__ __launch_bounds__(NT) void k_condense_t(DevPlan P, int e0, int32_t *s
   if (singular && tid == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
 }
 
+__global__ __launch_bounds__(NT) void k_condense_f64(DevPlan P, int e0, int32_t *status, double *S, double *g,
+                                                     double *Y, double *z, double *inv) {
+  condense_body<double, false>(P, e0, status, S, g, Y, z, inv, nullptr);
+}
+
+// Two workgroups per CU (the FP32 working block takes half the LDS): registers
+// are capped so that 16 waves fit.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_condense_f32(
+    DevPlan P, int e0, int32_t *status, float *S, double *g, float *Y, double *z, float *fac) {
+  condense_body<float, true>(P, e0, status, S, g, Y, z, nullptr, fac);
+}
+
 // x = A_lp^-1 r per element from the low-precision record: y = P D r, forward
 // substitution (unit L) and backward substitution (U) over W-column blocks
 // with the stored diagonal-block inverses, x = D y.  Vectors and arithmetic in
@@ -649,20 +662,20 @@ size_t lp_record_bytes(int np) { return lp_rec_floats(np) * sizeof(float); }
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s) {
   const size_t lds = condense_lds_bytes(P.n_pad);
-  auto *kern = k_condense_t<double, false>;
-  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute((const void *)k_condense_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
   if (e) return e;
-  hipLaunchKernelGGL(kern, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, P.inv, (float *)nullptr);
+  hipLaunchKernelGGL(k_condense_f64, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, P.inv);
   return hipGetLastError();
 }
 
 hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
                               double *z, float *fac, hipStream_t s) {
   const size_t lds = condense_lds_bytes_lp(P.n_pad);
-  auto *kern = k_condense_t<float, true>;
-  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = hipFuncSetAttribute((const void *)k_condense_f32, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
   if (e) return e;
-  hipLaunchKernelGGL(kern, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, (float *)nullptr, fac);
+  hipLaunchKernelGGL(k_condense_f32, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, fac);
   return hipGetLastError();
 }
 

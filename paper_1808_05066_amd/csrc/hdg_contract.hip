@@ -19,7 +19,7 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int NT = 256;
+constexpr int NT = 1024;   // 16 waves: the block tables keep one workgroup per CU
 
 __device__ inline d4 mfma4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -29,7 +29,7 @@ template <int D, bool VISC, int NCT>
 __global__ __launch_bounds__(NT) void k_contract_mfma(DevPlan P, int e0, int ec) {
   constexpr int M = D + 2;
   constexpr int G = VISC ? M + M * D : M;   // column groups
-  constexpr int RT = (NCT == 1) ? 16 : 8;   // row tiles per wave per pass
+  constexpr int RT = (NCT == 1) ? 8 : 4;    // row tiles per wave per pass
   extern __shared__ double lds[];
   const int el = blockIdx.x, e = e0 + el;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(NT) void k_contract_mfma(DevPlan P, int e0, int ec)
   const int ntiles = (nrows + 15) / 16;
   constexpr int CS = M * M + M * D * M + (VISC ? M * D * M * D : 0);  // coefficients per point
   double *coef = work;                                                // [4][CS]
-  for (int base = 0; base < ntiles; base += 4 * RT) {
+  for (int base = 0; base < ntiles; base += (NT / 64) * RT) {
     d4 acc[RT][NCT];
 #pragma unroll
     for (int u = 0; u < RT; ++u)

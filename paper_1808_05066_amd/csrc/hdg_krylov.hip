@@ -53,74 +53,76 @@ __global__ void k_bj_assemble_point(DevPlan P, const T *__restrict__ S, double *
   }
 }
 
-// In-place inverse of each bs x bs block (column-major) by LU with partial
-// pivoting in LDS followed by solves against the identity.
-__global__ void k_block_invert(double *B, int bs, int32_t *bad) {
-  extern __shared__ double a[];   // [bs][bs+1] column-major with padding, then pivots
-  const int blk = blockIdx.x;
-  const int ld = bs + 1;
+// In-place inverse of each bs x bs block (column-major): Gauss-Jordan with
+// partial pivoting on [B | I] held in LDS, every thread of the workgroup
+// updating entries of the augmented matrix at each elimination step.
+constexpr int BI = 256;
+
+__global__ __launch_bounds__(BI) void k_block_invert(double *B, int bs, int32_t *bad) {
+  extern __shared__ double aug[];   // [2 bs][bs + 1] column-major, then the multiplier column [bs]
+  const int blk = blockIdx.x, tid = threadIdx.x;
+  const int ld = bs + 1, nc = 2 * bs;
   double *Bb = B + (size_t)blk * bs * bs;
-  int *piv = reinterpret_cast<int *>(a + (size_t)bs * ld);
+  double *mul = aug + (size_t)nc * ld;
   __shared__ int s_p;
   __shared__ int s_zero;
-  for (int t = threadIdx.x; t < bs * bs; t += blockDim.x) a[(t / bs) * ld + t % bs] = Bb[t];
-  if (threadIdx.x == 0) s_zero = 0;
+  for (int t = tid; t < nc * bs; t += BI) {
+    const int c = t / bs, i = t - c * bs;
+    aug[c * ld + i] = c < bs ? Bb[(size_t)c * bs + i] : (c - bs == i ? 1.0 : 0.0);
+  }
+  if (tid == 0) s_zero = 0;
   __syncthreads();
   for (int j = 0; j < bs; ++j) {
-    if (threadIdx.x == 0) {
-      int p = j;
-      double best = fabs(a[j * ld + j]);
-      for (int i = j + 1; i < bs; ++i) {
-        const double v = fabs(a[j * ld + i]);
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = j;
+      for (int i = j + tid; i < bs; i += 64) {
+        const double v = fabs(aug[j * ld + i]);
         if (v > best) {
           best = v;
-          p = i;
+          bi = i;
         }
       }
-      if (!(best > 0.0)) s_zero = 1;
-      s_p = p;
-      piv[j] = p;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_p = bi;
+        if (!(best > 0.0)) s_zero = 1;
+      }
     }
     __syncthreads();
     const int p = s_p;
     if (p != j)
-      for (int c = threadIdx.x; c < bs; c += blockDim.x) {
-        const double t0 = a[c * ld + j];
-        a[c * ld + j] = a[c * ld + p];
-        a[c * ld + p] = t0;
+      for (int c = tid; c < nc; c += BI) {
+        const double t0 = aug[c * ld + j];
+        aug[c * ld + j] = aug[c * ld + p];
+        aug[c * ld + p] = t0;
       }
     __syncthreads();
-    const double d = a[j * ld + j];
-    if (d != 0.0) {
-      for (int i = j + 1 + threadIdx.x; i < bs; i += blockDim.x) a[j * ld + i] /= d;
-    }
+    const double d = aug[j * ld + j];
+    const double inv = d != 0.0 ? 1.0 / d : 0.0;
+    for (int i = tid; i < bs; i += BI) mul[i] = (i == j) ? 0.0 : aug[j * ld + i];
     __syncthreads();
-    for (int t = threadIdx.x; t < (bs - j - 1) * (bs - j - 1); t += blockDim.x) {
-      const int i = j + 1 + t % (bs - j - 1), c = j + 1 + t / (bs - j - 1);
-      a[c * ld + i] -= a[j * ld + i] * a[c * ld + j];
+    for (int c = tid; c < nc; c += BI) aug[c * ld + j] *= inv;
+    __syncthreads();
+    for (int t = tid; t < nc * bs; t += BI) {
+      const int c = t / bs, i = t - c * bs;
+      if (i != j) aug[c * ld + i] -= mul[i] * aug[c * ld + j];
     }
     __syncthreads();
   }
-  // column c of the inverse: solve L U x = P e_c
-  for (int c = threadIdx.x; c < bs; c += blockDim.x) {
-    double *x = Bb + (size_t)c * bs;
-    for (int i = 0; i < bs; ++i) x[i] = (i == c) ? 1.0 : 0.0;
-    for (int j = 0; j < bs; ++j) {
-      const int p = piv[j];
-      if (p != j) {
-        const double t0 = x[j];
-        x[j] = x[p];
-        x[p] = t0;
-      }
-    }
-    for (int j = 0; j < bs; ++j)
-      for (int i = j + 1; i < bs; ++i) x[i] -= a[j * ld + i] * x[j];
-    for (int j = bs - 1; j >= 0; --j) {
-      x[j] /= a[j * ld + j];
-      for (int i = 0; i < j; ++i) x[i] -= a[j * ld + i] * x[j];
-    }
+  for (int t = tid; t < bs * bs; t += BI) {
+    const int c = t / bs, i = t - c * bs;
+    Bb[(size_t)c * bs + i] = aug[(bs + c) * ld + i];
   }
-  if (threadIdx.x == 0 && s_zero) atomicAdd(bad, 1);
+  if (tid == 0 && s_zero) atomicAdd(bad, 1);
 }
 
 // z = blockdiag(Binv) r on [m][n_trace] vectors.
@@ -238,10 +240,10 @@ hipError_t launch_bj_assemble_f32(const DevPlan &P, const float *S, double *B, h
 
 hipError_t launch_block_invert(const DevPlan &P, double *B, int32_t *bad, hipStream_t s) {
   const int bs = P.bj_bs;
-  const size_t lds = (size_t)bs * (bs + 1) * sizeof(double) + (size_t)bs * sizeof(int);
+  const size_t lds = ((size_t)2 * bs * (bs + 1) + bs) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void *)k_block_invert, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e) return e;
-  hipLaunchKernelGGL(k_block_invert, dim3(P.bj_nblk), dim3(128), lds, s, B, bs, bad);
+  hipLaunchKernelGGL(k_block_invert, dim3(P.bj_nblk), dim3(BI), lds, s, B, bs, bad);
   return hipGetLastError();
 }
 

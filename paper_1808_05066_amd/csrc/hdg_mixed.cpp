@@ -223,8 +223,12 @@ extern "C" int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q
   for (int i = 0; i < 16; ++i) info->history[i] = 0.0;
   if (Rn == 0.0) return HDG_OK;
 
-  rc = hdg_precond_setup(plan, S, swork, sb, &go, stream);
-  if (rc) return rc;
+  {
+    auto g0 = std::chrono::steady_clock::now();
+    rc = hdg_precond_setup(plan, S, swork, sb, &go, stream);
+    if (rc) return rc;
+    gmres_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - g0).count();
+  }
   for (int it = 0; it < opts->max_outer; ++it) {
     // low-precision correction
     rc = hdg_lp_solve(plan, factors, rloc, zh, stream);
