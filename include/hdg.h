@@ -113,6 +113,9 @@ typedef struct {
  * for an order outside 1..4. */
 int hdg_plan_create(hdg_plan **plan, const hdg_mesh *mesh, const hdg_phys *phys, const hdg_opts *opts);
 void hdg_plan_destroy(hdg_plan *plan);
+/* Replace gamma, mu, Pr and alpha of a plan (the viscous flag must not change);
+ * takes effect at the next call. */
+int hdg_plan_set_phys(hdg_plan *plan, const hdg_phys *phys);
 int hdg_plan_dims(const hdg_plan *plan, hdg_dims *out);
 
 /* Bytes of device workspace the plan needs (tables + per-chunk scratch). */
@@ -221,6 +224,50 @@ int hdg_precond_apply(hdg_plan *plan, void *work, size_t bytes, const hdg_solve_
  * within maxit (info->converged = 0). */
 int hdg_trace_solve(hdg_plan *plan, const void *S, const double *rhs, double *x, void *work,
                     size_t bytes, const hdg_solve_opts *opts, hdg_solve_info *info, void *stream);
+
+/* ---- Learned block-Jacobi correction ---------------------------------------
+ * Not in the paper.  A small network rescales every block-Jacobi inverse B_F:
+ *   M_F^-1 = diag(e^a) B_F diag(e^b),  (a_i, b_i) = 0.5 tanh(o_i),
+ *   o_i = W3 tanh(W2 tanh(W1 f_i + b1) + b2) + b3   (16 -> 32 -> 32 -> 2, FP32)
+ * with f_i 16 features of block row i (log10 |D_ii| and ||D_i,:|| of the
+ * assembled block, log10 of the coupling of the row to other blocks and its
+ * ratio to the row norm, one-hot component, node position on the face, local
+ * Mach number, log10 p and log10 rho of the trace state, a constant 1; logs
+ * scaled by 1/4).  Rows are in block order (block F, position i -> F*bs + i,
+ * i = c * nodes_per_block + p); N_rows = m * n_trace.  Parameters (float,
+ * hdg_learn_nparams of them): W1[32][16] b1[32] W2[32][32] b2[32] W3[2][32] b3[2].
+ * Training loss over random vectors x_v with w_v = K x_v:
+ *   L = sum_v ||x_v - M^-1 w_v||^2 / x2,  x2 = sum_v ||x_v||^2,
+ * minimized with Adam (beta 0.9, 0.999, eps 1e-8).  All pointers device. */
+int hdg_learn_nparams(void);
+
+/* Block-Jacobi setup as hdg_precond_setup (inverses into `work`) plus the
+ * features feat [N_rows][16] from S (type per opts->s_dtype) and vhat [m][n_trace]. */
+int hdg_learn_setup(hdg_plan *plan, const void *S, const double *vhat, float *feat, void *work, size_t bytes,
+                    const hdg_solve_opts *opts, void *stream);
+/* out [N_rows][2] = network outputs o. */
+int hdg_learn_forward(hdg_plan *plan, const float *theta, const float *feat, float *out, void *stream);
+/* Rescale the inverses held in `work` with the outputs; hdg_trace_solve with
+ * precond 1 then applies the learned preconditioner (same cost as block Jacobi). */
+int hdg_learn_apply(hdg_plan *plan, const float *out, void *work, size_t bytes, const hdg_solve_opts *opts,
+                    void *stream);
+/* Loss (into *loss, device double) and dL/do [N_rows][2] for nvec vectors X, Wv
+ * [nvec][m][n_trace] with the UNSCALED inverses in `work`. */
+int hdg_learn_loss_grad(hdg_plan *plan, const void *work, size_t bytes, const hdg_solve_opts *opts,
+                        const float *out, const double *X, const double *Wv, int nvec, double x2, float *dO,
+                        double *loss, void *stream);
+/* Floats of scratch for hdg_learn_backward. */
+int hdg_learn_scratch_floats(const hdg_plan *plan, size_t *n);
+/* grad [nparams] = dL/dtheta from dO (recomputes the forward pass). */
+int hdg_learn_backward(hdg_plan *plan, const float *theta, const float *feat, const float *dO, float *grad,
+                       float *scratch, void *stream);
+/* One Adam step (t >= 1) on theta with moments m, v. */
+int hdg_learn_adam(float *theta, const float *grad, float *m, float *v, int t, float lr, void *stream);
+/* forward + loss_grad + backward + adam. */
+int hdg_learn_train_step(hdg_plan *plan, float *theta, float *m, float *v, int t, float lr, const float *feat,
+                         const void *work, size_t bytes, const hdg_solve_opts *opts, const double *X,
+                         const double *Wv, int nvec, double x2, float *out, float *dO, float *grad, float *scratch,
+                         double *loss, void *stream);
 
 /* ---- Mixed precision ------------------------------------------------------
  * Low-precision condensation with FP64 refinement of the full Newton linear

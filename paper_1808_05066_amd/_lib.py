@@ -66,6 +66,7 @@ SIGNATURES = {
     "hdg_plan_create": (I, [ctypes.POINTER(P), ctypes.POINTER(hdg_mesh), ctypes.POINTER(hdg_phys),
                             ctypes.POINTER(hdg_opts)]),
     "hdg_plan_destroy": (None, [P]),
+    "hdg_plan_set_phys": (I, [P, ctypes.POINTER(hdg_phys)]),
     "hdg_plan_dims": (I, [P, ctypes.POINTER(hdg_dims)]),
     "hdg_plan_workspace_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
     "hdg_plan_bind_workspace": (I, [P, P, ctypes.c_size_t, P]),
@@ -88,6 +89,17 @@ SIGNATURES = {
     "hdg_refine_workspace_bytes": (I, [P, ctypes.POINTER(hdg_refine_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "hdg_refine_solve": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t,
                              ctypes.POINTER(hdg_refine_opts), ctypes.POINTER(hdg_refine_info), P, P]),
+    "hdg_learn_nparams": (I, []),
+    "hdg_learn_setup": (I, [P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),
+    "hdg_learn_forward": (I, [P, P, P, P, P]),
+    "hdg_learn_apply": (I, [P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),
+    "hdg_learn_loss_grad": (I, [P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P, P, P, I,
+                                ctypes.c_double, P, P, P]),
+    "hdg_learn_scratch_floats": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_learn_backward": (I, [P, P, P, P, P, P, P]),
+    "hdg_learn_adam": (I, [P, P, P, P, I, ctypes.c_float, P]),
+    "hdg_learn_train_step": (I, [P, P, P, P, I, ctypes.c_float, P, P, ctypes.c_size_t,
+                                 ctypes.POINTER(hdg_solve_opts), P, P, I, ctypes.c_double, P, P, P, P, P, P]),
     "hdg_selftest": (I, [ctypes.POINTER(ctypes.c_double)]),
     "hdg_plan_set_timing": (I, [P, I]),
     "hdg_plan_phase_times": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long), I]),

@@ -1,0 +1,362 @@
+// Learned correction of the block-Jacobi preconditioner (not in the paper).
+//
+// Every block-Jacobi inverse B_F of the condensed operator is rescaled as
+//   M_F^-1 = diag(e^a) B_F diag(e^b),   (a_i, b_i) = 0.5 tanh(o_i),
+// o_i = MLP(features of unknown i): 16 -> 32 (tanh) -> 32 (tanh) -> 2, FP32.
+// Training minimizes L = sum_v ||x_v - M^-1 K x_v||^2 / sum_v ||x_v||^2 over
+// random vectors with Adam; these kernels are the features, the network's
+// forward and backward passes, the loss gradient and the Adam update.
+//
+// Parameter vector (float): W1[32][16] b1[32] W2[32][32] b2[32] W3[2][32] b3[2].
+// Rows are block rows: block F, position i -> F*bs + i, i = c*npb + p.
+#include "hdg_physics.hpp"
+#include "hdg_plan.hpp"
+
+namespace hdg {
+
+namespace {
+
+constexpr int NF = 16, NH = 32, NO = 2;
+constexpr int OW1 = 0, OB1 = OW1 + NH * NF, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
+              OB3 = OW3 + NO * NH, NPAR = OB3 + NO;
+constexpr float LOGS = 0.25f;   // scale of log10 features
+
+__device__ inline int npb_of(const DevPlan &P) { return P.bj_face ? P.Nfp : 1; }
+
+// features of every row from the assembled (not yet inverted) diagonal blocks
+// and the trace state; columns 2 and 3 are completed by k_feat_finish.
+template <int D>
+__global__ void k_feat_block(DevPlan P, const double *__restrict__ Bd, const double *__restrict__ vhat,
+                             float *feat) {
+  constexpr int M = D + 2;
+  const int blk = blockIdx.x;
+  const int bs = P.bj_bs, npb = npb_of(P);
+  const double *Bb = Bd + (size_t)blk * bs * bs;
+  for (int i = threadIdx.x; i < bs; i += blockDim.x) {
+    const int c = i / npb, p = i % npb;
+    const int t = P.bj_nodes[(size_t)blk * npb + p];
+    double rn = 0.0;
+    for (int j = 0; j < bs; ++j) rn += Bb[(size_t)j * bs + i] * Bb[(size_t)j * bs + i];
+    float f[NF];
+    for (int q = 0; q < NF; ++q) f[q] = 0.f;
+    f[0] = LOGS * (float)log10(fabs(Bb[(size_t)i * bs + i]) + 1e-300);
+    f[1] = LOGS * (float)log10(sqrt(rn) + 1e-300);
+    if (c < 5) f[4 + c] = 1.f;
+    if (P.bj_face) {
+      const int e = P.bj_ce[blk * 2], fc = P.bj_cf[blk * 2];
+      const int bb = P.bj_loc[((size_t)blk * 2) * P.Nfp + p];
+      const int a = P.fnodes[fc * P.Nfp + bb];
+      int nfc = 0;
+      for (int ff = 0; ff < P.nf; ++ff) nfc += P.node_face[a * P.nf + ff] >= 0;
+      f[9 + (nfc >= 3 ? 2 : nfc - 1)] = 1.f;
+      (void)e;
+    }
+    double vv[M];
+    for (int cc = 0; cc < M; ++cc) vv[cc] = vhat[(size_t)cc * P.n_trace + t];
+    if (vv[M - 1] < 0.0) {
+      Prim<D, double> s = prim_of_v<D, double>(vv, P.gamma);
+      double v2 = 0.0;
+      for (int j = 0; j < D; ++j) v2 += s.V[j] * s.V[j];
+      f[12] = (float)sqrt(v2 / (P.gamma * s.p / s.rho));
+      f[13] = LOGS * (float)log10(s.p);
+      f[14] = LOGS * (float)log10(s.rho);
+    }
+    f[15] = 1.f;
+    float *o = feat + ((size_t)blk * bs + i) * NF;
+    for (int q = 0; q < NF; ++q) o[q] = f[q];
+  }
+}
+
+// coupling^2 of every global row: squared entries of the element Schur rows in
+// columns whose trace node lies outside the row's block
+template <typename T>
+__global__ void k_feat_coupling(DevPlan P, const T *__restrict__ S, const int *__restrict__ tpos, double *coup) {
+  const int e = blockIdx.x;
+  const int k = P.k, Nfp = P.Nfp, M = P.m, nf = P.nf, npb = npb_of(P), bs = P.bj_bs;
+  const int *tm = P.tmap + (size_t)e * nf * Nfp;
+  const T *Se = S + (size_t)e * k * k;
+  for (int l = threadIdx.x; l < k; l += blockDim.x) {
+    const int b = l % Nfp, c = (l / Nfp) % M, f = l / (Nfp * M);
+    const int tp = tpos[tm[f * Nfp + b]];
+    const int blk = tp / npb, p = tp % npb;
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const int bj = j % Nfp, fj = j / (Nfp * M);
+      if (tpos[tm[fj * Nfp + bj]] / npb == blk) continue;
+      const double s = (double)Se[(size_t)j * k + l];
+      acc += s * s;
+    }
+    atomicAdd(&coup[(size_t)blk * bs + c * npb + p], acc);
+  }
+}
+
+__global__ void k_feat_finish(const double *__restrict__ coup, float *feat, size_t N) {
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  const float lc = LOGS * (float)log10(sqrt(coup[r]) + 1e-300);
+  feat[r * NF + 2] = lc;
+  feat[r * NF + 3] = lc - feat[r * NF + 1];
+}
+
+__device__ inline void mlp_fwd_row(const float *th, const float *x, float *h1, float *h2, float *o) {
+  for (int j = 0; j < NH; ++j) {
+    float s = th[OB1 + j];
+#pragma unroll
+    for (int i = 0; i < NF; ++i) s += th[OW1 + j * NF + i] * x[i];
+    h1[j] = tanhf(s);
+  }
+  for (int j = 0; j < NH; ++j) {
+    float s = th[OB2 + j];
+#pragma unroll 8
+    for (int i = 0; i < NH; ++i) s += th[OW2 + j * NH + i] * h1[i];
+    h2[j] = tanhf(s);
+  }
+  for (int j = 0; j < NO; ++j) {
+    float s = th[OB3 + j];
+#pragma unroll 8
+    for (int i = 0; i < NH; ++i) s += th[OW3 + j * NH + i] * h2[i];
+    o[j] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ theta, const float *__restrict__ feat,
+                                                 size_t N, float *out) {
+  __shared__ float th[NPAR];
+  for (int i = threadIdx.x; i < NPAR; i += blockDim.x) th[i] = theta[i];
+  __syncthreads();
+  const size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  float x[NF], h1[NH], h2[NH], o[NO];
+  for (int i = 0; i < NF; ++i) x[i] = feat[r * NF + i];
+  mlp_fwd_row(th, x, h1, h2, o);
+  out[r * 2] = o[0];
+  out[r * 2 + 1] = o[1];
+}
+
+// Loss and dL/do per block: y = e^a (B (e^b w)), r = x - y over nvec vectors.
+__global__ void k_precond_grad(DevPlan P, const double *__restrict__ Binv, const float *__restrict__ o,
+                               const double *__restrict__ X, const double *__restrict__ Wv, int nvec, double x2,
+                               float *dO, double *loss) {
+  extern __shared__ double sm[];
+  const int blk = blockIdx.x, bs = P.bj_bs, npb = npb_of(P);
+  const size_t NT = (size_t)P.n_trace, NV = (size_t)P.m * NT;
+  double *ea = sm, *eb = ea + bs, *ew = eb + bs, *dy = ew + bs, *red = dy + bs;
+  const double *Bb = Binv + (size_t)blk * bs * bs;
+  const int tid = threadIdx.x;
+  double ga = 0.0, gb = 0.0, lsum = 0.0;
+  int gidx = -1;
+  double ta = 0.0, tb = 0.0;
+  if (tid < bs) {
+    const size_t r = (size_t)blk * bs + tid;
+    ta = tanh((double)o[r * 2]);
+    tb = tanh((double)o[r * 2 + 1]);
+    ea[tid] = exp(0.5 * ta);
+    eb[tid] = exp(0.5 * tb);
+    const int c = tid / npb, p = tid % npb;
+    gidx = (int)(c * NT) + P.bj_nodes[(size_t)blk * npb + p];
+  }
+  for (int v = 0; v < nvec; ++v) {
+    __syncthreads();
+    double xv = 0.0;
+    if (tid < bs) {
+      ew[tid] = eb[tid] * Wv[(size_t)v * NV + gidx];
+      xv = X[(size_t)v * NV + gidx];
+    }
+    __syncthreads();
+    double y = 0.0;
+    if (tid < bs) {
+      double u = 0.0;
+      for (int j = 0; j < bs; ++j) u += Bb[(size_t)j * bs + tid] * ew[j];
+      y = ea[tid] * u;
+      const double r = xv - y;
+      lsum += r * r;
+      const double d = -2.0 * r / x2;
+      ga += d * y;
+      dy[tid] = ea[tid] * d;
+    }
+    __syncthreads();
+    if (tid < bs) {
+      double t = 0.0;
+      for (int i = 0; i < bs; ++i) t += Bb[(size_t)tid * bs + i] * dy[i];
+      gb += t * ew[tid];
+    }
+  }
+  if (tid < bs) {
+    const size_t r = (size_t)blk * bs + tid;
+    dO[r * 2] = (float)(ga * 0.5 * (1.0 - ta * ta));
+    dO[r * 2 + 1] = (float)(gb * 0.5 * (1.0 - tb * tb));
+  }
+  // block sum of the loss
+  red[tid] = lsum;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) atomicAdd(loss, red[0] / x2);
+}
+
+// Backward: 64 rows per workgroup; activations and deltas in LDS, then every
+// thread accumulates its share of the parameters over the rows.
+constexpr int BR = 64;
+
+__global__ __launch_bounds__(BR) void k_mlp_bwd(const float *__restrict__ theta, const float *__restrict__ feat,
+                                                const float *__restrict__ dO, size_t N, float *partial) {
+  __shared__ float th[NPAR];
+  __shared__ float sx[BR][NF + 1], sh1[BR][NH + 1], sh2[BR][NH + 1], sd1[BR][NH + 1], sd2[BR][NH + 1],
+      so[BR][NO];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NPAR; i += BR) th[i] = theta[i];
+  __syncthreads();
+  const size_t r = (size_t)blockIdx.x * BR + tid;
+  float x[NF], h1[NH], h2[NH], o[NO], g[NO];
+  if (r < N) {
+    for (int i = 0; i < NF; ++i) x[i] = feat[r * NF + i];
+    g[0] = dO[r * 2];
+    g[1] = dO[r * 2 + 1];
+  } else {
+    for (int i = 0; i < NF; ++i) x[i] = 0.f;
+    g[0] = g[1] = 0.f;
+  }
+  mlp_fwd_row(th, x, h1, h2, o);
+  float d2[NH], d1[NH];
+  for (int j = 0; j < NH; ++j) {
+    float s = 0.f;
+    for (int q = 0; q < NO; ++q) s += g[q] * th[OW3 + q * NH + j];
+    d2[j] = s * (1.f - h2[j] * h2[j]);
+  }
+  for (int j = 0; j < NH; ++j) {
+    float s = 0.f;
+    for (int q = 0; q < NH; ++q) s += d2[q] * th[OW2 + q * NH + j];
+    d1[j] = s * (1.f - h1[j] * h1[j]);
+  }
+  for (int i = 0; i < NF; ++i) sx[tid][i] = x[i];
+  for (int j = 0; j < NH; ++j) {
+    sh1[tid][j] = h1[j];
+    sh2[tid][j] = h2[j];
+    sd1[tid][j] = d1[j];
+    sd2[tid][j] = d2[j];
+  }
+  so[tid][0] = g[0];
+  so[tid][1] = g[1];
+  __syncthreads();
+  float *out = partial + (size_t)blockIdx.x * NPAR;
+  for (int p = tid; p < NPAR; p += BR) {
+    float acc = 0.f;
+    if (p < OB1) {
+      const int j = (p - OW1) / NF, i = (p - OW1) % NF;
+      for (int q = 0; q < BR; ++q) acc += sd1[q][j] * sx[q][i];
+    } else if (p < OW2) {
+      const int j = p - OB1;
+      for (int q = 0; q < BR; ++q) acc += sd1[q][j];
+    } else if (p < OB2) {
+      const int j = (p - OW2) / NH, i = (p - OW2) % NH;
+      for (int q = 0; q < BR; ++q) acc += sd2[q][j] * sh1[q][i];
+    } else if (p < OW3) {
+      const int j = p - OB2;
+      for (int q = 0; q < BR; ++q) acc += sd2[q][j];
+    } else if (p < OB3) {
+      const int j = (p - OW3) / NH, i = (p - OW3) % NH;
+      for (int q = 0; q < BR; ++q) acc += so[q][j] * sh2[q][i];
+    } else {
+      const int j = p - OB3;
+      for (int q = 0; q < BR; ++q) acc += so[q][j];
+    }
+    out[p] = acc;
+  }
+}
+
+// out[p] = sum_b partial[b][p]  (FP64 accumulation)
+__global__ void k_reduce_cols(const float *__restrict__ partial, int nb, float *out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPAR) return;
+  double acc = 0.0;
+  for (int b = 0; b < nb; ++b) acc += partial[(size_t)b * NPAR + p];
+  out[p] = (float)acc;
+}
+
+__global__ void k_adam(float *theta, const float *__restrict__ g, float *m, float *v, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPAR) return;
+  const float mm = b1 * m[p] + (1.f - b1) * g[p];
+  const float vv = b2 * v[p] + (1.f - b2) * g[p] * g[p];
+  m[p] = mm;
+  v[p] = vv;
+  theta[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+__global__ void k_scale_blocks(DevPlan P, double *B, const float *__restrict__ o) {
+  const int blk = blockIdx.x, bs = P.bj_bs;
+  double *Bb = B + (size_t)blk * bs * bs;
+  const float *ob = o + (size_t)blk * bs * 2;
+  for (int t = threadIdx.x; t < bs * bs; t += blockDim.x) {
+    const int i = t % bs, j = t / bs;
+    Bb[t] *= exp(0.5 * tanh((double)ob[i * 2]) + 0.5 * tanh((double)ob[j * 2 + 1]));
+  }
+}
+
+}  // namespace
+
+int learn_nparams() { return NPAR; }
+
+hipError_t launch_feat(const DevPlan &P, const double *Bd, const void *S, int s_f32, const double *vhat,
+                       const int *tpos, double *coup, float *feat, hipStream_t s) {
+  const size_t N = (size_t)P.bj_nblk * P.bj_bs;
+  if (P.dim == 2) hipLaunchKernelGGL(k_feat_block<2>, dim3(P.bj_nblk), dim3(64), 0, s, P, Bd, vhat, feat);
+  else hipLaunchKernelGGL(k_feat_block<3>, dim3(P.bj_nblk), dim3(64), 0, s, P, Bd, vhat, feat);
+  hipError_t e = hipGetLastError();
+  if (!e) e = launch_fill_double(coup, N, 0.0, s);
+  if (e) return e;
+  if (s_f32)
+    hipLaunchKernelGGL(k_feat_coupling<float>, dim3(P.n_elem), dim3(256), 0, s, P, static_cast<const float *>(S),
+                       tpos, coup);
+  else
+    hipLaunchKernelGGL(k_feat_coupling<double>, dim3(P.n_elem), dim3(256), 0, s, P,
+                       static_cast<const double *>(S), tpos, coup);
+  e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_feat_finish, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, coup, feat, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_fwd(const float *theta, const float *feat, size_t N, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, theta, feat, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_grad(const DevPlan &P, const double *Binv, const float *o, const double *X,
+                               const double *Wv, int nvec, double x2, float *dO, double *loss, hipStream_t s) {
+  const int bs = P.bj_bs;
+  const int nt = bs <= 64 ? 64 : (bs <= 128 ? 128 : 256);
+  if (bs > 256) return hipErrorInvalidValue;
+  const size_t lds = ((size_t)4 * bs + nt) * sizeof(double);
+  hipLaunchKernelGGL(k_precond_grad, dim3(P.bj_nblk), dim3(nt), lds, s, P, Binv, o, X, Wv, nvec, x2, dO, loss);
+  return hipGetLastError();
+}
+
+size_t learn_partial_floats(size_t N) { return ((N + BR - 1) / BR) * NPAR; }
+
+hipError_t launch_mlp_bwd(const float *theta, const float *feat, const float *dO, size_t N, float *partial,
+                          float *grad, hipStream_t s) {
+  const unsigned nb = (unsigned)((N + BR - 1) / BR);
+  hipLaunchKernelGGL(k_mlp_bwd, dim3(nb), dim3(BR), 0, s, theta, feat, dO, N, partial);
+  hipError_t e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_reduce_cols, dim3((NPAR + 255) / 256), dim3(256), 0, s, partial, (int)nb, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *theta, const float *g, float *m, float *v, int t, float lr, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  hipLaunchKernelGGL(k_adam, dim3((NPAR + 255) / 256), dim3(256), 0, s, theta, g, m, v, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_blocks(const DevPlan &P, double *B, const float *o, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_blocks, dim3(P.bj_nblk), dim3(256), 0, s, P, B, o);
+  return hipGetLastError();
+}
+
+}  // namespace hdg

@@ -201,6 +201,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
     for (int t = 0; t < mesh->n_trace && face_ok; ++t)
       if (owner[t] < 0) face_ok = false;
     P->dp.bj_face = face_ok ? 1 : 0;
+    P->bj_tpos.assign(mesh->n_trace, 0);
     if (face_ok) {
       const int nb = (int)nodes_of.size();
       P->dp.bj_nblk = nb;
@@ -210,7 +211,10 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
       P->bj_cf.assign((size_t)nb * 2, -1);
       P->bj_loc.assign((size_t)nb * 2 * R.Nfp, 0);
       for (int b = 0; b < nb; ++b) {
-        for (int p = 0; p < R.Nfp; ++p) P->bj_nodes[(size_t)b * R.Nfp + p] = nodes_of[b][p];
+        for (int p = 0; p < R.Nfp; ++p) {
+          P->bj_nodes[(size_t)b * R.Nfp + p] = nodes_of[b][p];
+          P->bj_tpos[nodes_of[b][p]] = b * R.Nfp + p;
+        }
         for (size_t q = 0; q < contrib[b].size(); ++q) {
           const int e = contrib[b][q].first, f = contrib[b][q].second;
           P->bj_ce[b * 2 + q] = e;
@@ -225,7 +229,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
       P->dp.bj_nblk = mesh->n_trace;
       P->dp.bj_bs = M;
       P->bj_nodes.resize(mesh->n_trace);
-      for (int t = 0; t < mesh->n_trace; ++t) P->bj_nodes[t] = t;
+      for (int t = 0; t < mesh->n_trace; ++t) P->bj_nodes[t] = P->bj_tpos[t] = t;
       P->bj_ce.assign(2, -1);
       P->bj_cf.assign(2, -1);
       P->bj_loc.assign(2, 0);
@@ -287,6 +291,20 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   return HDG_OK;
 }
 
+extern "C" int hdg_plan_set_phys(hdg_plan *plan, const hdg_phys *phys) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !phys) return fail(HDG_EINVAL, "null argument");
+  if ((phys->viscous != 0) != (P->dp.viscous != 0)) return fail(HDG_EINVAL, "viscous flag cannot change");
+  if (!(phys->gamma > 1.0) || phys->mu < 0.0 || (phys->viscous && !(phys->Pr > 0.0)) || phys->alpha < 0.0)
+    return fail(HDG_EINVAL, "physical parameters out of range");
+  P->phys = *phys;
+  P->dp.gamma = phys->gamma;
+  P->dp.mu = phys->mu;
+  P->dp.Pr = phys->Pr;
+  P->dp.alpha = phys->alpha;
+  return HDG_OK;
+}
+
 extern "C" void hdg_plan_destroy(hdg_plan *plan) {
   Plan *P = reinterpret_cast<Plan *>(plan);
   if (!P) return;
@@ -341,7 +359,7 @@ namespace {
 
 struct Layout {
   size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x;
-  size_t bj_nodes, bj_ce, bj_cf, bj_loc, tables_end;
+  size_t bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos, tables_end;
   size_t pv, pf, A, X, C, D, Rt, ipiv, inv, total;
 };
 
@@ -371,6 +389,7 @@ Layout layout(const Plan *P) {
   l.bj_ce = take(P->bj_ce.size() * 4);
   l.bj_cf = take(P->bj_cf.size() * 4);
   l.bj_loc = take(P->bj_loc.size() * 4);
+  l.bj_tpos = take(P->bj_tpos.size() * 4);
   l.tables_end = o;
   l.pv = take(ch * D.Nq * D.L.size * 8);
   l.pf = take(ch * D.nf * D.Nfq * D.L.fsize * 8);
@@ -443,6 +462,7 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   if (!e) e = up(l.bj_ce, P->bj_ce.data(), P->bj_ce.size() * 4);
   if (!e) e = up(l.bj_cf, P->bj_cf.data(), P->bj_cf.size() * 4);
   if (!e) e = up(l.bj_loc, P->bj_loc.data(), P->bj_loc.size() * 4);
+  if (!e) e = up(l.bj_tpos, P->bj_tpos.data(), P->bj_tpos.size() * 4);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(e, "bind_workspace upload");
   DevPlan &D = P->dp;
@@ -461,6 +481,7 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   D.bj_ce = reinterpret_cast<const int *>(base + l.bj_ce);
   D.bj_cf = reinterpret_cast<const int *>(base + l.bj_cf);
   D.bj_loc = reinterpret_cast<const int *>(base + l.bj_loc);
+  D.bj_tpos = reinterpret_cast<const int *>(base + l.bj_tpos);
   D.pv = reinterpret_cast<double *>(base + l.pv);
   D.pf = reinterpret_cast<double *>(base + l.pf);
   D.A = reinterpret_cast<double *>(base + l.A);

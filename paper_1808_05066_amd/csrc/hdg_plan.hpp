@@ -51,6 +51,7 @@ struct DevPlan {
   const int *bj_ce;        // [nblk][2] contributing elements (-1: none)   (face blocks)
   const int *bj_cf;        // [nblk][2] their local faces
   const int *bj_loc;       // [nblk][2][Nfp] local face node of each block position
+  const int *bj_tpos;      // [n_trace] block * (nodes per block) + position of each trace node
 };
 
 // Phases timed with HIP events when phase timing is enabled.
@@ -74,7 +75,7 @@ struct Plan {
   // host copies
   std::vector<double> geo_vol, geo_face, node_x, trace_x;
   std::vector<int> tmap, face_bc, node_face;
-  std::vector<int> bj_nodes, bj_ce, bj_cf, bj_loc;
+  std::vector<int> bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos;
   // workspace
   void *ws = nullptr;
   size_t ws_bytes = 0;
@@ -90,6 +91,19 @@ int run_front(Plan *P, const double *v, const double *q, const double *vhat, con
               const double *vbc, int32_t *status, int e0, int ec, hipStream_t s);
 int check_inputs(const Plan *P, const double *v, const double *q, const double *vhat, const double *ustar,
                  int32_t *status);
+
+// learned block-Jacobi correction (hdg_learn.hip)
+int learn_nparams();
+size_t learn_partial_floats(size_t N);
+hipError_t launch_feat(const DevPlan &P, const double *Bd, const void *S, int s_f32, const double *vhat,
+                       const int *tpos, double *coup, float *feat, hipStream_t s);
+hipError_t launch_mlp_fwd(const float *theta, const float *feat, size_t N, float *out, hipStream_t s);
+hipError_t launch_precond_grad(const DevPlan &P, const double *Binv, const float *o, const double *X,
+                               const double *Wv, int nvec, double x2, float *dO, double *loss, hipStream_t s);
+hipError_t launch_mlp_bwd(const float *theta, const float *feat, const float *dO, size_t N, float *partial,
+                          float *grad, hipStream_t s);
+hipError_t launch_adam(float *theta, const float *g, float *m, float *v, int t, float lr, hipStream_t s);
+hipError_t launch_scale_blocks(const DevPlan &P, double *B, const float *o, hipStream_t s);
 
 // error channel of hdg_last_error(): records the message, returns the code
 int fail(int code, const std::string &msg);

@@ -223,3 +223,106 @@ extern "C" int hdg_trace_solve(hdg_plan *plan, const void *S, const double *rhs,
   info->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return HDG_OK;
 }
+
+// ---- learned block-Jacobi correction ---------------------------------------
+
+extern "C" int hdg_learn_nparams(void) { return learn_nparams(); }
+
+extern "C" int hdg_learn_setup(hdg_plan *plan, const void *S, const double *vhat, float *feat, void *work,
+                               size_t bytes, const hdg_solve_opts *opts, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !S || !vhat || !feat || !work || !opts) return fail(HDG_EINVAL, "bad argument");
+  if (opts->s_dtype != HDG_FP64 && opts->s_dtype != HDG_FP32) return fail(HDG_EINVAL, "s_dtype must be FP64 or FP32");
+  SolveLayout l = solve_layout(P, opts->restart);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(work);
+  double *B = reinterpret_cast<double *>(base + l.binv);
+  double *coup = reinterpret_cast<double *>(base + l.V);   // Krylov space reused as scratch
+  int32_t *bad = reinterpret_cast<int32_t *>(base + l.bad);
+  const bool f32 = opts->s_dtype == HDG_FP32;
+  hipError_t e = launch_fill_int(bad, 1, 0, s);
+  if (!e)
+    e = f32 ? launch_bj_assemble_f32(P->dp, static_cast<const float *>(S), B, s)
+            : launch_bj_assemble(P->dp, static_cast<const double *>(S), B, s);
+  if (!e) e = launch_feat(P->dp, B, S, f32 ? 1 : 0, vhat, P->dp.bj_tpos, coup, feat, s);
+  if (!e) e = launch_block_invert(P->dp, B, bad, s);
+  int32_t hbad = 0;
+  if (!e) e = hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "learn_setup");
+  if (hbad) return fail(HDG_ESINGULAR, "singular block-Jacobi block");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_forward(hdg_plan *plan, const float *theta, const float *feat, float *out, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !theta || !feat || !out) return fail(HDG_EINVAL, "bad argument");
+  const size_t N = (size_t)P->dp.bj_nblk * P->dp.bj_bs;
+  hipError_t e = launch_mlp_fwd(theta, feat, N, out, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "learn_forward");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_apply(hdg_plan *plan, const float *out, void *work, size_t bytes,
+                               const hdg_solve_opts *opts, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !out || !work || !opts) return fail(HDG_EINVAL, "bad argument");
+  SolveLayout l = solve_layout(P, opts->restart);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
+  double *B = reinterpret_cast<double *>(static_cast<char *>(work) + l.binv);
+  hipError_t e = launch_scale_blocks(P->dp, B, out, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "learn_apply");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_loss_grad(hdg_plan *plan, const void *work, size_t bytes, const hdg_solve_opts *opts,
+                                   const float *out, const double *X, const double *Wv, int nvec, double x2,
+                                   float *dO, double *loss, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !work || !opts || !out || !X || !Wv || !dO || !loss || nvec < 1 || !(x2 > 0.0))
+    return fail(HDG_EINVAL, "bad argument");
+  SolveLayout l = solve_layout(P, opts->restart);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const double *B = reinterpret_cast<const double *>(static_cast<const char *>(work) + l.binv);
+  hipError_t e = launch_fill_double(loss, 1, 0.0, s);
+  if (!e) e = launch_precond_grad(P->dp, B, out, X, Wv, nvec, x2, dO, loss, s);
+  if (e) return hip_fail(e, "learn_loss_grad");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_scratch_floats(const hdg_plan *plan, size_t *n) {
+  const Plan *P = reinterpret_cast<const Plan *>(plan);
+  if (!P || !n) return fail(HDG_EINVAL, "bad argument");
+  *n = learn_partial_floats((size_t)P->dp.bj_nblk * P->dp.bj_bs);
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_backward(hdg_plan *plan, const float *theta, const float *feat, const float *dO,
+                                  float *grad, float *scratch, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !theta || !feat || !dO || !grad || !scratch) return fail(HDG_EINVAL, "bad argument");
+  const size_t N = (size_t)P->dp.bj_nblk * P->dp.bj_bs;
+  hipError_t e = launch_mlp_bwd(theta, feat, dO, N, scratch, grad, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "learn_backward");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_adam(float *theta, const float *grad, float *m, float *v, int t, float lr, void *stream) {
+  if (!theta || !grad || !m || !v || t < 1) return fail(HDG_EINVAL, "bad argument");
+  hipError_t e = launch_adam(theta, grad, m, v, t, lr, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "learn_adam");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_train_step(hdg_plan *plan, float *theta, float *m, float *v, int t, float lr,
+                                    const float *feat, const void *work, size_t bytes, const hdg_solve_opts *opts,
+                                    const double *X, const double *Wv, int nvec, double x2, float *out, float *dO,
+                                    float *grad, float *scratch, double *loss, void *stream) {
+  int rc = hdg_learn_forward(plan, theta, feat, out, stream);
+  if (!rc) rc = hdg_learn_loss_grad(plan, work, bytes, opts, out, X, Wv, nvec, x2, dO, loss, stream);
+  if (!rc) rc = hdg_learn_backward(plan, theta, feat, dO, grad, scratch, stream);
+  if (!rc) rc = hdg_learn_adam(theta, grad, m, v, t, lr, stream);
+  return rc;
+}

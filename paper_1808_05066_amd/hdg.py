@@ -66,6 +66,10 @@ class Plan:
         check(self.lib.hdg_plan_bind_workspace(h, self._ws_ptr, ctypes.c_size_t(nb.value), _stream()),
               "hdg_plan_bind_workspace")
 
+    def set_phys(self, gamma=1.4, mu=0.0, Pr=0.72, alpha=0.0):
+        phys = _lib.hdg_phys(int(self.viscous), float(gamma), float(mu), float(Pr), float(alpha))
+        check(self.lib.hdg_plan_set_phys(self.h, ctypes.byref(phys)), "hdg_plan_set_phys")
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h is not None and h.value:
@@ -279,6 +283,82 @@ class TraceSolver:
                                             ctypes.c_size_t(self.nbytes), ctypes.byref(self.opts),
                                             ctypes.byref(info), _stream()), "hdg_trace_solve")
         return x, {f: getattr(info, f) for f, _ in _lib.hdg_solve_info._fields_}
+
+
+class LearnedPrecond:
+    """Learned rescaling of the block-Jacobi inverses of one TraceSolver (see include/hdg.h).
+
+    setup(S, vhat) computes the features and the plain block-Jacobi inverses;
+    apply(theta) rescales the inverses with the network's outputs, after which
+    the solver's preconditioner is the learned one.  train_step() runs one Adam
+    step of the network on (X, W = K X) with the unscaled inverses.
+    """
+
+    def __init__(self, solver):
+        torch = _torch()
+        self.ts = solver
+        self.plan = solver.plan
+        lib = self.plan.lib
+        self.nparams = lib.hdg_learn_nparams()
+        self.N = self.plan.m * self.plan.n_trace
+        dev = self.plan.device
+        self.feat = torch.empty(self.N, 16, dtype=torch.float32, device=dev)
+        self.out = torch.zeros(self.N, 2, dtype=torch.float32, device=dev)
+        self.dO = torch.empty(self.N, 2, dtype=torch.float32, device=dev)
+        self.grad = torch.empty(self.nparams, dtype=torch.float32, device=dev)
+        n = ctypes.c_size_t()
+        check(lib.hdg_learn_scratch_floats(self.plan.h, ctypes.byref(n)), "hdg_learn_scratch_floats")
+        self.scratch = torch.empty(int(n.value), dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def _w(self):
+        return self.ts._ptr, ctypes.c_size_t(self.ts.nbytes), ctypes.byref(self.ts.opts)
+
+    def setup(self, S, vhat):
+        w, nb, op = self._w()
+        check(self.plan.lib.hdg_learn_setup(self.plan.h, _ptr(S), _ptr(vhat), _ptr(self.feat), w, nb, op,
+                                            _stream()), "hdg_learn_setup")
+
+    def forward(self, theta):
+        check(self.plan.lib.hdg_learn_forward(self.plan.h, _ptr(theta), _ptr(self.feat), _ptr(self.out),
+                                              _stream()), "hdg_learn_forward")
+        return self.out
+
+    def apply(self, theta):
+        self.forward(theta)
+        w, nb, op = self._w()
+        check(self.plan.lib.hdg_learn_apply(self.plan.h, _ptr(self.out), w, nb, op, _stream()), "hdg_learn_apply")
+
+    def loss_grad(self, X, Wv, out=None):
+        out = self.out if out is None else out
+        w, nb, op = self._w()
+        x2 = float((X * X).sum())
+        check(self.plan.lib.hdg_learn_loss_grad(self.plan.h, w, nb, op, _ptr(out), _ptr(X), _ptr(Wv), X.shape[0],
+                                                x2, _ptr(self.dO), _ptr(self.loss), _stream()),
+              "hdg_learn_loss_grad")
+        return self.loss, self.dO
+
+    def backward(self, theta, dO=None):
+        dO = self.dO if dO is None else dO
+        check(self.plan.lib.hdg_learn_backward(self.plan.h, _ptr(theta), _ptr(self.feat), _ptr(dO),
+                                               _ptr(self.grad), _ptr(self.scratch), _stream()), "hdg_learn_backward")
+        return self.grad
+
+    def train_step(self, theta, m, v, t, lr, X, Wv, x2):
+        w, nb, op = self._w()
+        check(self.plan.lib.hdg_learn_train_step(self.plan.h, _ptr(theta), _ptr(m), _ptr(v), int(t),
+                                                 ctypes.c_float(lr), _ptr(self.feat), w, nb, op, _ptr(X), _ptr(Wv),
+                                                 X.shape[0], float(x2), _ptr(self.out), _ptr(self.dO),
+                                                 _ptr(self.grad), _ptr(self.scratch), _ptr(self.loss), _stream()),
+              "hdg_learn_train_step")
+        return self.loss
+
+
+def adam(theta, grad, m, v, t, lr):
+    """One device Adam step (the library's kernel)."""
+    lib = _lib.load()
+    check(lib.hdg_learn_adam(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), int(t), ctypes.c_float(lr), _stream()),
+          "hdg_learn_adam")
 
 
 def selftest():
