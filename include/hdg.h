@@ -89,7 +89,7 @@ typedef struct {
   int n_trace;             /* number of global trace nodes */
 } hdg_mesh;
 
-enum { HDG_FLAG_SPLIT_DENSE = 1 };
+enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2 };
 
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */

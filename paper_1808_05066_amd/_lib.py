@@ -17,6 +17,7 @@ ETYPES = {"tri": 0, "quad": 1, "tet": 2, "hex": 3}
 PHASES = ["points", "contract", "lu", "solve", "schur", "backsolve", "matvec", "rhs", "condense", "condense_lp",
           "lp_solve", "jvp"]
 FLAG_SPLIT_DENSE = 1
+FLAG_NARROW_BLOCK = 2
 
 
 class hdg_phys(ctypes.Structure):

@@ -32,8 +32,9 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int W = 32;        // block width
-constexpr int BS = W + 1;    // LDS row stride of the block (elements)
+// Block width W (32, or 16 where a 32-column block does not fit in LDS); the
+// LDS row stride of the block is W + 1 elements.
+constexpr int WMAX = 32;
 constexpr int NT = 512;      // threads per workgroup (8 wave64)
 constexpr int NW = NT / 64;
 
@@ -69,8 +70,9 @@ struct Lds {
 };
 
 // blk[i][c] = M[(c0 + c) * ld + perm[i]]  (gathered through the permutation)
-template <typename T>
+template <typename T, int W>
 __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, int np) {
+  constexpr int BS = W + 1;
   for (int t = threadIdx.x; t < np * W; t += NT) {
     const int c = t / np, i = t - c * np;
     s.blk[i * BS + c] = M[(size_t)(c0 + c) * ld + s.perm[i]];
@@ -79,8 +81,9 @@ __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, i
 
 // Low-precision load of FP64 columns: blk[i][c] = d_row * M[c0+c][perm[i]] * d_col
 // (colscale false: right-hand sides, rows scaled only).
-template <typename T>
+template <typename T, int W>
 __device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int ld, int c0, int np, bool colscale) {
+  constexpr int BS = W + 1;
   for (int t = threadIdx.x; t < np * W; t += NT) {
     const int c = t / np, i = t - c * np;
     const int pi = s.perm[i];
@@ -90,43 +93,46 @@ __device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int l
   }
 }
 
-template <typename T>
+template <typename T, int W>
 __device__ inline void store_block(const Lds<T> &s, T *M, int ld, int c0, int np) {
+  constexpr int BS = W + 1;
   for (int t = threadIdx.x; t < np * W; t += NT) {
     const int c = t / np, i = t - c * np;
     M[(size_t)(c0 + c) * ld + s.perm[i]] = s.blk[i * BS + c];
   }
 }
 
-// Rows p0..p0+31 of the block <- Inv * rows, Inv the stored inverse of the unit-lower
-// (L) or upper (U) 32 x 32 diagonal block of the factors; four waves each form one
-// 16 x 16 tile on MFMA, then write back after a barrier.
-template <typename T>
+// Rows p0..p0+W-1 of the block <- Inv * rows, Inv the stored inverse of the
+// unit-lower (L) or upper (U) W x W diagonal block of the factors; (W/16)^2 waves
+// each form one 16 x 16 tile on MFMA, then write back after a barrier.
+template <typename T, int W>
 __device__ inline void inv_apply(const Lds<T> &s, const T *Inv, int p0) {
   typedef Mfma<T> MF;
+  constexpr int BS = W + 1, TW = W / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   typename MF::acc acc = {0, 0, 0, 0};
-  const int ti = wave & 1, tj = (wave >> 1) & 1;
-  if (wave < 4) {
-    T a[8];
+  const int ti = wave % TW, tj = wave / TW;
+  if (wave < TW * TW) {
+    T a[W / 4];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) a[kk] = Inv[(4 * kk + lk) * W + ti * 16 + li];
+    for (int kk = 0; kk < W / 4; ++kk) a[kk] = Inv[(4 * kk + lk) * W + ti * 16 + li];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) acc = MF::op(a[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
+    for (int kk = 0; kk < W / 4; ++kk) acc = MF::op(a[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
   }
   __syncthreads();
-  if (wave < 4) {
+  if (wave < TW * TW) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) s.blk[(p0 + ti * 16 + MF::row(lk, r)) * BS + tj * 16 + li] = acc[r];
   }
 }
 
-// Inverses of the diagonal 32 x 32 blocks of the freshly factored panel (block rows
-// j0..j0+31): wave 0 inverts the unit-lower part, wave 1 the upper part; column c
-// of each inverse is solved by lane c.  Stored column-major (32 x 32) in Linv / Uinv.
-template <typename T>
+// Inverses of the diagonal W x W blocks of the freshly factored panel (block rows
+// j0..j0+W-1): wave 0 inverts the unit-lower part, wave 1 the upper part; column c
+// of each inverse is solved by lane c.  Stored column-major (W x W) in Linv / Uinv.
+template <typename T, int W>
 __device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
+  constexpr int BS = W + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane >= W || wave > 1) return;
   const int c = lane;
@@ -155,20 +161,21 @@ __device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
 }
 
 // blk[r][:] -= sum_kk M[(p0+kk) * ld + perm[r]] * blk[p0+kk][:]  for rows r in [r_lo, r_hi)
-// (r_lo, r_hi multiples of 16, disjoint from p0..p0+31).
-template <typename T>
+// (r_lo, r_hi multiples of 16, disjoint from p0..p0+W-1).
+template <typename T, int W>
 __device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, int r_lo, int r_hi) {
   typedef Mfma<T> MF;
+  constexpr int BS = W + 1, TW = W / 16, KS = W / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int ntile = (r_hi - r_lo) / 16;
   const T *Mp = M + (size_t)(p0 + lk) * ld;
-  T a[8], an[8];
+  T a[KS], an[KS];
   int t = wave;
   if (t < ntile) {
     const size_t grow = (size_t)s.perm[r_lo + t * 16 + li];
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) a[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
+    for (int kk = 0; kk < KS; ++kk) a[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
   }
   for (; t < ntile; t += NW) {
     const int r0 = r_lo + t * 16;
@@ -176,47 +183,44 @@ __device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, 
     if (tn < ntile) {
       const size_t grow = (size_t)s.perm[r_lo + tn * 16 + li];
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) an[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
+      for (int kk = 0; kk < KS; ++kk) an[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
     }
-    typename MF::acc c0, c1;
+    typename MF::acc c[TW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      c0[r] = s.blk[(r0 + MF::row(lk, r)) * BS + li];
-      c1[r] = s.blk[(r0 + MF::row(lk, r)) * BS + 16 + li];
-    }
+    for (int q = 0; q < TW; ++q)
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) {
+      for (int r = 0; r < 4; ++r) c[q][r] = s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
       const T *brow = s.blk + (p0 + 4 * kk + lk) * BS;
-      c0 = MF::op(a[kk], brow[li], c0);
-      c1 = MF::op(a[kk], brow[16 + li], c1);
+#pragma unroll
+      for (int q = 0; q < TW; ++q) c[q] = MF::op(a[kk], brow[q * 16 + li], c[q]);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      s.blk[(r0 + MF::row(lk, r)) * BS + li] = c0[r];
-      s.blk[(r0 + MF::row(lk, r)) * BS + 16 + li] = c1[r];
-    }
+    for (int q = 0; q < TW; ++q)
 #pragma unroll
-    for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
+      for (int r = 0; r < 4; ++r) s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li] = c[q][r];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) a[kk] = an[kk];
   }
 }
 
-// LU with partial pivoting of block rows j0..np-1 (block columns 0..31), in four
+// LU with partial pivoting of block rows j0..np-1 (block columns 0..W-1), in
 // sub-panels of 8 columns.  Inside a sub-panel thread t keeps the 8 entries of
-// row j0+t in registers (rows beyond j0+NT, present only when np - j0 > NT,
-// stay in LDS); per column the pivot is found by wave shuffles plus one
+// row j0+t in registers (its rows j0+t+NT, j0+t+2NT, ... stay in LDS); per column the pivot is found by wave shuffles plus one
 // exchange through LDS, the pivot row is published and whole rows are swapped
 // in LDS: two barriers per column.  After a sub-panel, its 8 pivot rows are
 // solved against the remaining columns (unit-lower 8 x 8) and the rows below
 // receive the rank-8 update.
 constexpr int SPW = 8;   // sub-panel width
 
-template <typename T>
+template <typename T, int W>
 __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T *tmprow) {
+  constexpr int BS = W + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r0 = j0 + tid, r1 = j0 + tid + NT;
-  const bool has0 = r0 < np, has1 = r1 < np;
+  const int r0 = j0 + tid, r1 = j0 + tid + NT;   // rows r1, r1 + NT, ... stay in LDS
+  const bool has0 = r0 < np;
   T *y0 = s.blk + (size_t)r0 * BS;
-  T *y1 = s.blk + (size_t)r1 * BS;
   bool singular = false;
   for (int cs = 0; cs < W; cs += SPW) {
     T x0[SPW];
@@ -235,11 +239,11 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
         best = fabs(v0);
         bi = r0;
       }
-      if (has1) {
-        const T v1 = fabs(y1[col]);
+      for (int rr = r1; rr < np; rr += NT) {
+        const T v1 = fabs(s.blk[(size_t)rr * BS + col]);
         if (v1 > best) {
           best = v1;
-          bi = r1;
+          bi = rr;
         }
       }
 #pragma unroll
@@ -278,9 +282,10 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
 #pragma unroll
         for (int c = 0; c < SPW; ++c) prow[c] = x0[c];
       }
-      if (has1 && r1 == piv) {
+      const bool own_lds = piv >= r1 && (piv - r1) % NT == 0;   // this thread's LDS row
+      if (own_lds) {
 #pragma unroll
-        for (int c = 0; c < SPW; ++c) prow[c] = y1[cs + c];
+        for (int c = 0; c < SPW; ++c) prow[c] = s.blk[(size_t)piv * BS + cs + c];
       }
       if (piv != r) {
         if (has0 && r0 == r) {
@@ -307,9 +312,9 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
 #pragma unroll
           for (int c = 0; c < SPW; ++c) x0[c] = prow[c];
         }
-        if (has1 && r1 == piv) {
+        if (own_lds) {
 #pragma unroll
-          for (int c = 0; c < SPW; ++c) y1[cs + c] = tmprow[c];
+          for (int c = 0; c < SPW; ++c) s.blk[(size_t)piv * BS + cs + c] = tmprow[c];
         }
       }
       if (!zero) {
@@ -325,7 +330,8 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
             else if (c > jj) x0[c] -= l0 * prow[c];
           }
         }
-        if (has1) {
+        for (int rr = r1; rr < np; rr += NT) {
+          T *y1 = s.blk + (size_t)rr * BS;
           const T l1 = y1[col] * inv;
           y1[col] = l1;
           for (int c = jj + 1; c < SPW; ++c) y1[cs + c] -= l1 * prow[c];
@@ -378,11 +384,11 @@ struct LdsLayout {
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
 
-__host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp) {
+__host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp, int W) {
   LdsLayout L;
   size_t o = 0;
   L.blk = o;
-  o = al16(o + (size_t)np * BS * tsize);
+  o = al16(o + (size_t)np * (W + 1) * tsize);
   L.prow = o;
   o = al16(o + W * tsize);
   L.tmp = o;
@@ -400,19 +406,19 @@ __host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp) {
 }
 
 // Per-element record of the low-precision factorization (floats):
-//   F [np][np] factors at original row index | Inv [np/W][2][W][W] |
-//   perm [np] (int) | dsc [np] (symmetric scaling, powers of two)
-__host__ __device__ inline size_t lp_rec_floats(int np) {
-  return (size_t)np * np + (size_t)(np / W) * 2 * W * W + 2 * (size_t)np;
-}
+//   F [np][np] factors at original row index | Inv [np/W][2][W][W] (space for
+//   W = 32) | perm [np] (int) | dsc [np] (symmetric scaling, powers of two)
+__host__ __device__ inline size_t rec_perm_off(int np) { return (size_t)np * np + 2 * (size_t)np * WMAX; }
+__host__ __device__ inline size_t lp_rec_floats(int np) { return rec_perm_off(np) + 2 * (size_t)np; }
 
 // T = double, LP = false: FP64 condensation, factors overwrite the A scratch.
 // T = float,  LP = true : scaled FP32 condensation, factors to the record `fac`.
 // One workgroup per element (blockIdx.x = element of the chunk).
-template <typename T, bool LP>
+template <typename T, bool LP, int W>
 __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t *status, T *S, double *g, T *Y,
                                               double *z, T *inv, float *fac) {
   typedef Mfma<T> MF;
+  constexpr int BS = W + 1, TW = W / 16;
   extern __shared__ double smem[];
   const int el = blockIdx.x, e = e0 + el;
   const int np = P.n_pad, kp = P.k_pad, kx = P.kx, n = P.n, k = P.k;
@@ -422,7 +428,7 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
   const double *Dm = P.D + (size_t)el * kp * kp;
   const double *Rt = P.Rt + (size_t)el * kp;
   char *sm = reinterpret_cast<char *>(smem);
-  const LdsLayout Lo = lds_layout(np, sizeof(T), LP);
+  const LdsLayout Lo = lds_layout(np, sizeof(T), LP, W);
   Lds<T> s;
   s.blk = reinterpret_cast<T *>(sm + Lo.blk);
   s.prow = reinterpret_cast<T *>(sm + Lo.prow);
@@ -441,7 +447,7 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
     Ie = rec + (size_t)np * np;
   } else {
     Fm = A64;
-    Ie = inv + (size_t)el * (np / W) * 2 * W * W;
+    Ie = inv + (size_t)el * 2 * np * WMAX;
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
@@ -457,27 +463,27 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
   __syncthreads();
   bool singular = false;
 
-  // ---- LU, left-looking over 32-column blocks
+  // ---- LU, left-looking over W-column blocks
   for (int J = 0; J < nJ; ++J) {
     const int j0 = J * W;
-    if constexpr (LP) load_block_scaled(s, A64, np, j0, np, true);
-    else load_block(s, A64, np, j0, np);
+    if constexpr (LP) load_block_scaled<T, W>(s, A64, np, j0, np, true);
+    else load_block<T, W>(s, A64, np, j0, np);
     __syncthreads();
     for (int Pp = 0; Pp < J; ++Pp) {
       const int p0 = Pp * W;
-      inv_apply(s, Ie + (size_t)Pp * 2 * W * W, p0);
+      inv_apply<T, W>(s, Ie + (size_t)Pp * 2 * W * W, p0);
       __syncthreads();
-      gemm_update(s, Fm, np, p0, p0 + W, np);
+      gemm_update<T, W>(s, Fm, np, p0, p0 + W, np);
       __syncthreads();
     }
-    singular |= panel_factor(s, j0, np, s.prow, s.tmp);
+    singular |= panel_factor<T, W>(s, j0, np, s.prow, s.tmp);
     __syncthreads();
-    invert_diag(s, j0, Ie + (size_t)J * 2 * W * W, Ie + (size_t)J * 2 * W * W + W * W);
-    store_block(s, Fm, np, j0, np);
+    invert_diag<T, W>(s, j0, Ie + (size_t)J * 2 * W * W, Ie + (size_t)J * 2 * W * W + W * W);
+    store_block<T, W>(s, Fm, np, j0, np);
     __syncthreads();
   }
   if constexpr (LP) {
-    int *rp = reinterpret_cast<int *>(rec + (size_t)np * np + (size_t)nJ * 2 * W * W);
+    int *rp = reinterpret_cast<int *>(rec + rec_perm_off(np));
     float *rd = reinterpret_cast<float *>(rp + np);
     for (int i = tid; i < np; i += NT) {
       rp[i] = s.perm[i];
@@ -491,21 +497,21 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
   T *Ye = Y + (size_t)e * n * k;
   const int ntr = kp / 16;
   for (int c0 = 0; c0 < kx; c0 += W) {
-    if constexpr (LP) load_block_scaled(s, X, np, c0, np, false);
-    else load_block(s, X, np, c0, np);
+    if constexpr (LP) load_block_scaled<T, W>(s, X, np, c0, np, false);
+    else load_block<T, W>(s, X, np, c0, np);
     __syncthreads();
     for (int Pp = 0; Pp < nJ; ++Pp) {
       const int p0 = Pp * W;
-      inv_apply(s, Ie + (size_t)Pp * 2 * W * W, p0);
+      inv_apply<T, W>(s, Ie + (size_t)Pp * 2 * W * W, p0);
       __syncthreads();
-      if (p0 + W < np) gemm_update(s, Fm, np, p0, p0 + W, np);
+      if (p0 + W < np) gemm_update<T, W>(s, Fm, np, p0, p0 + W, np);
       __syncthreads();
     }
     for (int Pp = nJ - 1; Pp >= 0; --Pp) {
       const int p0 = Pp * W;
-      inv_apply(s, Ie + (size_t)Pp * 2 * W * W + W * W, p0);
+      inv_apply<T, W>(s, Ie + (size_t)Pp * 2 * W * W + W * W, p0);
       __syncthreads();
-      if (p0 > 0) gemm_update(s, Fm, np, p0, 0, p0);
+      if (p0 > 0) gemm_update<T, W>(s, Fm, np, p0, 0, p0);
       __syncthreads();
     }
     if constexpr (LP) {
@@ -523,10 +529,12 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
       if (col < k) Ye[(size_t)col * n + i] = s.blk[i * BS + c];
       else if (col == kp) z[(size_t)e * n + i] = (double)s.blk[i * BS + c];
     }
-    // T = C * block (k_pad x 32): S = D - T, g = -R_tr + T
+    // T = C * block (k_pad x W): S = D - T, g = -R_tr + T
     for (int t = wave; t < ntr; t += NW) {
       const int r0 = t * 16;
-      typename MF::acc a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+      typename MF::acc acc[TW];
+#pragma unroll
+      for (int q = 0; q < TW; ++q) acc[q] = typename MF::acc{0, 0, 0, 0};
       const double *Cr = C + (size_t)lk * kp + r0 + li;
       T a[8], an[8];
 #pragma unroll
@@ -539,8 +547,8 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
           const T *brow = s.blk + (kb + 4 * kk + lk) * BS;
-          a0 = MF::op(a[kk], brow[li], a0);
-          a1 = MF::op(a[kk], brow[16 + li], a1);
+#pragma unroll
+          for (int q = 0; q < TW; ++q) acc[q] = MF::op(a[kk], brow[q * 16 + li], acc[q]);
         }
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
@@ -549,11 +557,12 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
       for (int r = 0; r < 4; ++r) {
         const int row = r0 + MF::row(lk, r);
         if (row >= k) continue;
-        const int col0 = c0 + li, col1 = c0 + 16 + li;
-        if (col0 < k) Se[(size_t)col0 * k + row] = (T)(Dm[(size_t)col0 * kp + row] - (double)a0[r]);
-        else if (col0 == kp) ge[row] = -Rt[row] + (double)a0[r];
-        if (col1 < k) Se[(size_t)col1 * k + row] = (T)(Dm[(size_t)col1 * kp + row] - (double)a1[r]);
-        else if (col1 == kp) ge[row] = -Rt[row] + (double)a1[r];
+#pragma unroll
+        for (int q = 0; q < TW; ++q) {
+          const int col = c0 + q * 16 + li;
+          if (col < k) Se[(size_t)col * k + row] = (T)(Dm[(size_t)col * kp + row] - (double)acc[q][r]);
+          else if (col == kp) ge[row] = -Rt[row] + (double)acc[q][r];
+        }
       }
     }
     __syncthreads();
@@ -561,16 +570,23 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
   if (singular && tid == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
 }
 
-__global__ __launch_bounds__(NT) void k_condense_f64(DevPlan P, int e0, int32_t *status, double *S, double *g,
-                                                     double *Y, double *z, double *inv) {
-  condense_body<double, false>(P, e0, status, S, g, Y, z, inv, nullptr);
+__global__ __launch_bounds__(NT) void k_condense_f64_w32(DevPlan P, int e0, int32_t *status, double *S, double *g,
+                                                         double *Y, double *z, double *inv) {
+  condense_body<double, false, 32>(P, e0, status, S, g, Y, z, inv, nullptr);
 }
 
-// Two workgroups per CU (the FP32 working block takes half the LDS): registers
-// are capped so that 16 waves fit.
+// 16-column blocks take half the LDS: two workgroups per CU with capped registers.
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_condense_f64_w16(
+    DevPlan P, int e0, int32_t *status, double *S, double *g, double *Y, double *z, double *inv) {
+  condense_body<double, false, 16>(P, e0, status, S, g, Y, z, inv, nullptr);
+}
+
+// Two workgroups per CU where the FP32 working block fits twice in LDS:
+// registers are capped so that 16 waves fit.
+template <int W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_condense_f32(
     DevPlan P, int e0, int32_t *status, float *S, double *g, float *Y, double *z, float *fac) {
-  condense_body<float, true>(P, e0, status, S, g, Y, z, nullptr, fac);
+  condense_body<float, true, W>(P, e0, status, S, g, Y, z, nullptr, fac);
 }
 
 // x = A_lp^-1 r per element from the low-precision record: y = P D r, forward
@@ -580,7 +596,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 // order so every factor column is read contiguously.  One workgroup per element.
 constexpr int SB = 256;
 
-__global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, const float *__restrict__ fac,
+__global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, int W, const float *__restrict__ fac,
                                                  const double *__restrict__ r, double *x) {
   extern __shared__ double sm2[];
   const int e = blockIdx.x, tid = threadIdx.x;
@@ -591,7 +607,7 @@ __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, const float *__r
   const float *rec = fac + (size_t)e * lp_rec_floats(np);
   const float *F = rec;
   const float *Inv = rec + (size_t)np * np;
-  const int *perm = reinterpret_cast<const int *>(Inv + (size_t)nJ * 2 * W * W);
+  const int *perm = reinterpret_cast<const int *>(rec + rec_perm_off(np));
   const float *dsc = reinterpret_cast<const float *>(perm + np);
   const double *re = r + (size_t)e * n;
   for (int i = tid; i < np; i += SB) {
@@ -651,37 +667,50 @@ __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, const float *__r
 
 }  // namespace
 
-size_t condense_lds_bytes(int np) { return lds_layout(np, sizeof(double), false).total; }
+int condense_width(int np, bool lp) {
+  const size_t cap = 160 * 1024;
+  const size_t ts = lp ? sizeof(float) : sizeof(double);
+  if (lds_layout(np, ts, lp, 32).total <= cap) return 32;
+  if (lds_layout(np, ts, lp, 16).total <= cap) return 16;
+  return 0;
+}
 
-size_t condense_lds_bytes_lp(int np) { return lds_layout(np, sizeof(float), true).total; }
+size_t condense_lds_bytes(int np, int w) { return lds_layout(np, sizeof(double), false, w).total; }
 
-size_t condense_inv_doubles(int np) { return (size_t)(np / W) * 2 * W * W; }
+size_t condense_lds_bytes_lp(int np, int w) { return lds_layout(np, sizeof(float), true, w).total; }
+
+size_t condense_inv_doubles(int np) { return 2 * (size_t)np * WMAX; }
 
 size_t lp_record_bytes(int np) { return lp_rec_floats(np) * sizeof(float); }
 
+template <typename K, typename... Args>
+hipError_t launch_dyn(K kern, int ec, size_t lds, hipStream_t s, Args... args) {
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e) return e;
+  hipLaunchKernelGGL(kern, dim3(ec), dim3(NT), lds, s, args...);
+  return hipGetLastError();
+}
+
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s) {
-  const size_t lds = condense_lds_bytes(P.n_pad);
-  hipError_t e = hipFuncSetAttribute((const void *)k_condense_f64, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e) return e;
-  hipLaunchKernelGGL(k_condense_f64, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, P.inv);
-  return hipGetLastError();
+  const size_t lds = condense_lds_bytes(P.n_pad, P.cw);
+  if (P.cw == 32) return launch_dyn(k_condense_f64_w32, ec, lds, s, P, e0, status, S, g, Y, z, P.inv);
+  if (P.cw == 16) return launch_dyn(k_condense_f64_w16, ec, lds, s, P, e0, status, S, g, Y, z, P.inv);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
                               double *z, float *fac, hipStream_t s) {
-  const size_t lds = condense_lds_bytes_lp(P.n_pad);
-  hipError_t e = hipFuncSetAttribute((const void *)k_condense_f32, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e) return e;
-  hipLaunchKernelGGL(k_condense_f32, dim3(ec), dim3(NT), lds, s, P, e0, status, S, g, Y, z, fac);
-  return hipGetLastError();
+  const size_t lds = condense_lds_bytes_lp(P.n_pad, P.cw_lp);
+  if (P.cw_lp == 32) return launch_dyn(k_condense_f32<32>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
+  if (P.cw_lp == 16) return launch_dyn(k_condense_f32<16>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_lp_solve(const DevPlan &P, const float *fac, const double *r, double *x, hipStream_t s) {
-  const size_t lds = (size_t)(P.n_pad + W) * sizeof(double) + (size_t)P.n_pad * sizeof(int);
-  hipLaunchKernelGGL(k_lp_solve, dim3(P.n_elem), dim3(SB), lds, s, P.n, P.n_pad, fac, r, x);
+  const int w = P.cw_lp;
+  const size_t lds = (size_t)(P.n_pad + w) * sizeof(double) + (size_t)P.n_pad * sizeof(int);
+  hipLaunchKernelGGL(k_lp_solve, dim3(P.n_elem), dim3(SB), lds, s, P.n, P.n_pad, w, fac, r, x);
   return hipGetLastError();
 }
 

@@ -306,8 +306,10 @@ __global__ void k_copy_resid(DevPlan P, int e0, double *Rl, double *Rtr) {
 
 }  // namespace
 
+size_t lu_lds_bytes(int np) { return (size_t)np * PS * sizeof(double); }
+
 hipError_t launch_lu(const DevPlan &P, int ec, int32_t *status, hipStream_t s) {
-  const size_t lds = (size_t)P.n_pad * PS * sizeof(double);
+  const size_t lds = lu_lds_bytes(P.n_pad);
   hipError_t e = hipFuncSetAttribute((const void *)k_lu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e) return e;
   hipLaunchKernelGGL(k_lu, dim3(ec), dim3(BLK), lds, s, P, status);

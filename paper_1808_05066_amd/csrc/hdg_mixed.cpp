@@ -51,7 +51,7 @@ RefineLayout refine_layout(const Plan *P, size_t solver_bytes) {
   return l;
 }
 
-bool lp_supported(const Plan *P) { return condense_lds_bytes_lp(P->dp.n_pad) <= 160 * 1024; }
+bool lp_supported(const Plan *P) { return P->dp.cw_lp != 0; }
 
 }  // namespace
 

@@ -257,13 +257,20 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   D.mu = phys->mu;
   D.Pr = phys->Pr;
   D.alpha = phys->alpha;
-  if (D.n_pad > 1024) {
-    delete P;
-    return fail(HDG_EUNSUPPORTED, "local block larger than 1024 is not built in this version");
+  // fused left-looking condensation when its 32- or 16-column LDS block fits
+  D.cw = condense_width(D.n_pad, false);
+  D.cw_lp = condense_width(D.n_pad, true);
+  if (opts && (opts->flags & HDG_FLAG_NARROW_BLOCK)) {
+    if (D.cw) D.cw = 16;
+    if (D.cw_lp) D.cw_lp = 16;
   }
-  // fused left-looking condensation when its 32-column LDS block fits
-  P->fused = condense_lds_bytes(D.n_pad) <= 160 * 1024;
+  P->fused = D.cw != 0;
   if (opts && (opts->flags & HDG_FLAG_SPLIT_DENSE)) P->fused = false;
+  P->split_ok = lu_lds_bytes(D.n_pad) <= 160 * 1024;
+  if (!P->fused && !P->split_ok && !D.cw_lp) {
+    delete P;
+    return fail(HDG_EUNSUPPORTED, "local block too large for every condensation kernel");
+  }
   PointLayout &L = D.L;
   int o = 0;
   L.Mv = o; o += M * M;
@@ -607,6 +614,7 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
     rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s);
     if (rc) return rc;
     e = launch_copy_resid(P->dp, e0, ec, Rloc, Rtr, s);
+    if (!e && !P->fused && !P->split_ok) return fail(HDG_EUNSUPPORTED, "FP64 condensation: local block too large");
     if (!e && P->fused) {
       e = phase_begin(P, PH_CONDENSE, s);
       if (!e) e = launch_condense(P->dp, e0, ec, status + e0, S, g, Y, z, s);

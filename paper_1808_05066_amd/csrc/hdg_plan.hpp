@@ -20,6 +20,7 @@ struct PointLayout {
 // Everything a kernel needs; passed by value.
 struct DevPlan {
   int dim, m, Np, nf, Nfp, Nq, Nfq, n, k, n_pad, k_pad, kx, viscous, n_elem, n_trace;
+  int cw, cw_lp;           // column-block width of the fused FP64 / FP32 condensation (0: not available)
   double gamma, mu, Pr, alpha;
   PointLayout L;
   // tables (device)
@@ -64,6 +65,7 @@ struct Plan {
   RefTables ref;
   bool timing = false;
   bool fused = true;
+  bool split_ok = true;     // separate LU / solve / Schur kernels fit (LDS of the LU panel)
   bool contract_mfma = true;
   hipEvent_t ev[PH_COUNT][2] = {};
   bool ev_pending[PH_COUNT] = {};
@@ -117,13 +119,15 @@ hipError_t launch_points(const DevPlan &P, int e0, int ec, const double *v, cons
                          int32_t *status, hipStream_t s);
 hipError_t launch_contract(const DevPlan &P, int e0, int ec, hipStream_t s);
 hipError_t launch_lu(const DevPlan &P, int ec, int32_t *status, hipStream_t s);
+size_t lu_lds_bytes(int np);
 hipError_t launch_solve(const DevPlan &P, int ec, hipStream_t s);
 hipError_t launch_schur(const DevPlan &P, int e0, int ec, double *S, double *g, double *Y,
                         double *z, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_copy_resid(const DevPlan &P, int e0, int ec, double *Rloc, double *Rtr, hipStream_t s);
 hipError_t launch_mfma_selftest(double *out, hipStream_t s);
-size_t condense_lds_bytes(int np);
-size_t condense_lds_bytes_lp(int np);
+int condense_width(int np, bool lp);
+size_t condense_lds_bytes(int np, int w);
+size_t condense_lds_bytes_lp(int np, int w);
 size_t lp_record_bytes(int np);
 hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
                               double *z, float *fac, hipStream_t s);

@@ -84,11 +84,11 @@ def test_jacobian_apply_matches_oracle_blocks(torch, name):
     assert np.array_equal(yl2.cpu().numpy(), yl) and np.array_equal(yt2.cpu().numpy(), yt)
 
 
-@pytest.mark.parametrize("name", CASES)
-def test_lp_condensation_error_report(torch, name):
+@pytest.mark.parametrize("name,narrow", [(c, False) for c in CASES] + [("ns3d_hex_p2", True)])
+def test_lp_condensation_error_report(torch, name, narrow):
     wl, disc, inp, blocks = _case(name)
-    print("case", name, flush=True)
-    plan = gpu_plan(wl)
+    print("case", name, "narrow", narrow, flush=True)
+    plan = gpu_plan(wl, narrow_block=narrow)
     d = to_dev(inp)
     lp = plan.assemble_condense_lp(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
     torch.cuda.synchronize()

@@ -70,11 +70,12 @@ def test_assemble_blocks_match_oracle(torch, name):
 
 
 @pytest.mark.parametrize("name", list(SMALL_CASES))
-@pytest.mark.parametrize("chunk,split", [(0, False), (3, False), (0, True)])
-def test_condense_matches_oracle(torch, name, chunk, split):
+@pytest.mark.parametrize("chunk,split,narrow", [(0, False, False), (3, False, False), (0, True, False),
+                                                (0, False, True)])
+def test_condense_matches_oracle(torch, name, chunk, split, narrow):
     wl, disc, inp, blocks = _case(name)
-    print("case", name, "chunk", chunk, "split", split, flush=True)
-    plan = gpu_plan(wl, chunk_elems=chunk, split_dense=split)
+    print("case", name, "chunk", chunk, "split", split, "narrow", narrow, flush=True)
+    plan = gpu_plan(wl, chunk_elems=chunk, split_dense=split, narrow_block=narrow)
     d = to_dev(inp)
     out = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], residuals=True)
     torch.cuda.synchronize()
