@@ -174,6 +174,57 @@ int hdg_trace_matvec(hdg_plan *plan, const double *S, const double *x, double *y
 /* Right-hand side of the condensed system r = sum_K P_K^T g_K ([m][n_trace]). */
 int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
 
+/* ---- Kernel tuning ---------------------------------------------------------
+ * Launch shapes of one plan (0 leaves a field unchanged): workgroup size of
+ * the block contraction (256, 512, 1024 threads) and column-block width of
+ * the fused FP64 / FP32 condensation (32 or 16; must fit in LDS).  The
+ * autotuner (paper_1808_05066_amd/autotune.py) sweeps these per (n, k, dtype)
+ * and caches the fastest in JSON.  Set before building a batch. */
+typedef struct {
+  int contract_threads;
+  int condense_width;
+  int condense_width_lp;
+} hdg_tuning;
+
+int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t);
+int hdg_plan_get_tuning(const hdg_plan *plan, hdg_tuning *t);
+
+/* ---- Batches ----------------------------------------------------------------
+ * Several plans (element types / orders with uneven n, k, e.g. tetrahedra of
+ * orders 1..4 next to hexahedra) condensed in ONE persistent launch: each
+ * workgroup takes (plan, element) items from a queue in decreasing order of
+ * block cost (order 0, longest processing time first) or plan order
+ * (order 1) until the queue is empty.  Every plan must be bound, use the
+ * fused condensation and process all its elements in one chunk; its
+ * pointwise and contraction kernels run first, per plan.  The whole sequence
+ * can be captured in a hipGraph and replayed.  The batch copies the plans'
+ * descriptors at bind time: set tunings before binding. */
+typedef struct hdg_batch hdg_batch;
+
+typedef struct {            /* per plan, device pointers as in hdg_assemble_condense */
+  const double *v, *q, *vhat, *u_star, *v_bc;
+  double *S, *g, *Y, *z;
+  int32_t *elem_status;
+} hdg_batch_io;
+
+int hdg_batch_create(hdg_batch **batch, hdg_plan *const *plans, int n_plans, int order);
+void hdg_batch_destroy(hdg_batch *batch);
+/* Caller-owned device workspace (descriptors, queue, counter). */
+int hdg_batch_workspace_bytes(const hdg_batch *batch, size_t *bytes);
+int hdg_batch_bind_workspace(hdg_batch *batch, void *dev_ptr, size_t bytes, void *stream);
+/* Persistent grid size (default: number of compute units). */
+int hdg_batch_set_groups(hdg_batch *batch, int groups);
+/* Inputs / outputs of every plan (array of n_plans); synchronous upload. */
+int hdg_batch_set_io(hdg_batch *batch, const hdg_batch_io *io, void *stream);
+/* Run once: per plan status reset + pointwise + contraction, then the
+ * persistent condensation of all items. */
+int hdg_batch_run(hdg_batch *batch, void *stream);
+/* Capture the sequence of hdg_batch_run in a graph (after one eager run on the
+ * same stream); hdg_batch_replay launches it.  Phase timing must be off. */
+int hdg_batch_capture(hdg_batch *batch, void *stream);
+int hdg_batch_replay(hdg_batch *batch, void *stream);
+int hdg_batch_info(const hdg_batch *batch, int *n_items, int *groups, size_t *lds_bytes);
+
 /* ---- Global trace solve --------------------------------------------------
  * The paper leaves the linear solver of the condensed system open; this
  * library solves  K dlambda = r,  K = sum_K P_K^T S_K P_K  (the trace operator

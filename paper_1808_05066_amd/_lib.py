@@ -56,6 +56,16 @@ class hdg_solve_info(ctypes.Structure):
                 ("solve_ms", ctypes.c_double)]
 
 
+class hdg_tuning(ctypes.Structure):
+    _fields_ = [("contract_threads", ctypes.c_int), ("condense_width", ctypes.c_int),
+                ("condense_width_lp", ctypes.c_int)]
+
+
+class hdg_batch_io(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("v", "q", "vhat", "u_star", "v_bc", "S", "g", "Y", "z",
+                                                "elem_status")]
+
+
 class hdg_dims(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int) for n in ("dim", "m", "Np", "nf", "Nfp", "Nq", "Nfq", "n", "k", "n_pad",
                                              "k_pad", "n_elem", "n_trace", "chunk_elems")]
@@ -101,6 +111,18 @@ SIGNATURES = {
     "hdg_learn_adam": (I, [P, P, P, P, I, ctypes.c_float, P]),
     "hdg_learn_train_step": (I, [P, P, P, P, I, ctypes.c_float, P, P, ctypes.c_size_t,
                                  ctypes.POINTER(hdg_solve_opts), P, P, I, ctypes.c_double, P, P, P, P, P, P]),
+    "hdg_plan_set_tuning": (I, [P, ctypes.POINTER(hdg_tuning)]),
+    "hdg_plan_get_tuning": (I, [P, ctypes.POINTER(hdg_tuning)]),
+    "hdg_batch_create": (I, [ctypes.POINTER(P), ctypes.POINTER(P), I, I]),
+    "hdg_batch_destroy": (None, [P]),
+    "hdg_batch_workspace_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_batch_bind_workspace": (I, [P, P, ctypes.c_size_t, P]),
+    "hdg_batch_set_groups": (I, [P, I]),
+    "hdg_batch_set_io": (I, [P, ctypes.POINTER(hdg_batch_io), P]),
+    "hdg_batch_run": (I, [P, P]),
+    "hdg_batch_capture": (I, [P, P]),
+    "hdg_batch_replay": (I, [P, P]),
+    "hdg_batch_info": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_size_t)]),
     "hdg_selftest": (I, [ctypes.POINTER(ctypes.c_double)]),
     "hdg_plan_set_timing": (I, [P, I]),
     "hdg_plan_phase_times": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long), I]),

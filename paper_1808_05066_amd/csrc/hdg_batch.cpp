@@ -1,0 +1,270 @@
+// Batches of plans (element types and orders with uneven block sizes)
+// condensed in one persistent launch, and hipGraph capture of the whole
+// assemble + condense sequence of a batch.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "hdg_plan.hpp"
+
+using namespace hdg;
+
+namespace hdg {
+size_t batch_item_args_bytes();
+hipError_t launch_condense_batch(const DevPlan *plans_dev, const void *io_dev, const int *queue, int n_items,
+                                 int *counter, int n_groups, size_t lds, hipStream_t s);
+}  // namespace hdg
+
+namespace {
+
+struct ItemArgs {   // device layout of the per-plan outputs read by the persistent kernel
+  double *S, *g, *Y, *z;
+  int32_t *status;
+};
+
+struct Batch {
+  std::vector<Plan *> plans;
+  std::vector<int> queue;
+  size_t lds = 0;
+  int groups = 0;
+  bool bound = false;
+  DevPlan *d_plans = nullptr;
+  ItemArgs *d_io = nullptr;
+  int *d_queue = nullptr;
+  int *d_counter = nullptr;
+  std::vector<hdg_batch_io> io;
+  bool io_set = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct BatchLayout {
+  size_t plans, io, queue, counter, total;
+};
+
+BatchLayout batch_layout(const Batch *B) {
+  BatchLayout l{};
+  size_t o = 0;
+  l.plans = o;
+  o = a256(o + B->plans.size() * sizeof(DevPlan));
+  l.io = o;
+  o = a256(o + B->plans.size() * sizeof(ItemArgs));
+  l.queue = o;
+  o = a256(o + B->queue.size() * sizeof(int));
+  l.counter = o;
+  o = a256(o + 64);
+  l.total = o;
+  return l;
+}
+
+void drop_graph(Batch *B) {
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  B->exec = nullptr;
+  B->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" int hdg_batch_create(hdg_batch **out, hdg_plan *const *plans, int n_plans, int order) {
+  if (!out || !plans || n_plans < 1 || n_plans > 127) return fail(HDG_EINVAL, "need 1..127 plans");
+  if (batch_item_args_bytes() != sizeof(ItemArgs)) return fail(HDG_EINVAL, "internal layout mismatch");
+  *out = nullptr;
+  Batch *B = new Batch;
+  struct Item {
+    double cost;
+    int plan, el;
+  };
+  std::vector<Item> items;
+  for (int i = 0; i < n_plans; ++i) {
+    Plan *P = reinterpret_cast<Plan *>(plans[i]);
+    if (!P || !P->bound || !P->fused || P->chunk < P->n_elem || P->n_elem >= (1 << 24)) {
+      delete B;
+      return fail(HDG_EINVAL, "batch plans must be bound, fused and process all elements in one chunk");
+    }
+    B->plans.push_back(P);
+    B->lds = std::max(B->lds, condense_lds_bytes(P->dp.n_pad, P->dp.cw));
+    const double np = P->dp.n_pad, kp = P->dp.k_pad;
+    const double cost = np * np * np / 3.0 + np * np * kp + np * kp * kp;   // LU + solves + Schur
+    for (int e = 0; e < P->n_elem; ++e) items.push_back({cost, i, e});
+  }
+  if (order == 0)   // longest processing time first
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  for (const Item &it : items) B->queue.push_back((it.plan << 24) | it.el);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) cus = 256;
+  B->groups = std::max(1, std::min<int>(cus, (int)B->queue.size()));
+  *out = reinterpret_cast<hdg_batch *>(B);
+  return HDG_OK;
+}
+
+extern "C" void hdg_batch_destroy(hdg_batch *batch) {
+  Batch *B = reinterpret_cast<Batch *>(batch);
+  if (!B) return;
+  drop_graph(B);
+  delete B;
+}
+
+extern "C" int hdg_batch_workspace_bytes(const hdg_batch *batch, size_t *bytes) {
+  const Batch *B = reinterpret_cast<const Batch *>(batch);
+  if (!B || !bytes) return fail(HDG_EINVAL, "bad argument");
+  *bytes = batch_layout(B).total;
+  return HDG_OK;
+}
+
+extern "C" int hdg_batch_bind_workspace(hdg_batch *batch, void *ptr, size_t bytes, void *stream) {
+  Batch *B = reinterpret_cast<Batch *>(batch);
+  if (!B || !ptr) return fail(HDG_EINVAL, "bad argument");
+  const BatchLayout l = batch_layout(B);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "batch workspace too small");
+  char *base = static_cast<char *>(ptr);
+  B->d_plans = reinterpret_cast<DevPlan *>(base + l.plans);
+  B->d_io = reinterpret_cast<ItemArgs *>(base + l.io);
+  B->d_queue = reinterpret_cast<int *>(base + l.queue);
+  B->d_counter = reinterpret_cast<int *>(base + l.counter);
+  std::vector<DevPlan> dp;
+  for (Plan *P : B->plans) dp.push_back(P->dp);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(B->d_plans, dp.data(), dp.size() * sizeof(DevPlan), hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(B->d_queue, B->queue.data(), B->queue.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "batch_bind");
+  B->bound = true;
+  drop_graph(B);
+  return HDG_OK;
+}
+
+extern "C" int hdg_batch_set_groups(hdg_batch *batch, int groups) {
+  Batch *B = reinterpret_cast<Batch *>(batch);
+  if (!B || groups < 1) return fail(HDG_EINVAL, "bad argument");
+  B->groups = std::min<int>(groups, (int)B->queue.size());
+  drop_graph(B);
+  return HDG_OK;
+}
+
+extern "C" int hdg_batch_set_io(hdg_batch *batch, const hdg_batch_io *io, void *stream) {
+  Batch *B = reinterpret_cast<Batch *>(batch);
+  if (!B || !B->bound || !io) return fail(HDG_EINVAL, "bad argument or unbound batch");
+  std::vector<ItemArgs> args;
+  for (size_t i = 0; i < B->plans.size(); ++i) {
+    const hdg_batch_io &a = io[i];
+    if (!a.v || !a.vhat || !a.S || !a.g || !a.Y || !a.z || !a.elem_status || (B->plans[i]->dp.viscous && !a.q))
+      return fail(HDG_EINVAL, "batch io: v, vhat, S, g, Y, z, elem_status (and q for Navier-Stokes) required");
+    args.push_back({a.S, a.g, a.Y, a.z, a.elem_status});
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(B->d_io, args.data(), args.size() * sizeof(ItemArgs), hipMemcpyHostToDevice, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "batch_set_io");
+  B->io.assign(io, io + B->plans.size());
+  B->io_set = true;
+  drop_graph(B);
+  return HDG_OK;
+}
+
+namespace {
+int batch_sequence(Batch *B, hipStream_t s) {
+  for (size_t i = 0; i < B->plans.size(); ++i) {
+    Plan *P = B->plans[i];
+    const hdg_batch_io &a = B->io[i];
+    hipError_t e = launch_fill_int(a.elem_status, P->n_elem, HDG_OK, s);
+    if (e) return hip_fail(e, "batch status init");
+    int rc = run_front(P, a.v, a.q, a.vhat, a.u_star, a.v_bc, a.elem_status, 0, P->n_elem, s);
+    if (rc) return rc;
+  }
+  hipError_t e = launch_fill_int(B->d_counter, 1, 0, s);
+  if (!e)
+    e = launch_condense_batch(B->d_plans, B->d_io, B->d_queue, (int)B->queue.size(), B->d_counter, B->groups, B->lds,
+                              s);
+  if (e) return hip_fail(e, "batch condense");
+  return HDG_OK;
+}
+}  // namespace
+
+extern "C" int hdg_batch_run(hdg_batch *batch, void *stream) {
+  Batch *B = reinterpret_cast<Batch *>(batch);
+  if (!B || !B->bound || !B->io_set) return fail(HDG_EINVAL, "batch not bound or io not set");
+  return batch_sequence(B, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int hdg_batch_capture(hdg_batch *batch, void *stream) {
+  Batch *B = reinterpret_cast<Batch *>(batch);
+  if (!B || !B->bound || !B->io_set) return fail(HDG_EINVAL, "batch not bound or io not set");
+  for (Plan *P : B->plans)
+    if (P->timing) return fail(HDG_EINVAL, "disable phase timing before capturing a graph");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // one eager pass sets every kernel attribute outside the capture
+  int rc = batch_sequence(B, s);
+  if (rc) return rc;
+  drop_graph(B);
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e) return hip_fail(e, "begin capture");
+  rc = batch_sequence(B, s);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e) return hip_fail(e, "end capture");
+  B->graph = g;
+  e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+  if (e) {
+    drop_graph(B);
+    return hip_fail(e, "graph instantiate");
+  }
+  return HDG_OK;
+}
+
+extern "C" int hdg_batch_replay(hdg_batch *batch, void *stream) {
+  Batch *B = reinterpret_cast<Batch *>(batch);
+  if (!B || !B->exec) return fail(HDG_EINVAL, "no captured graph");
+  hipError_t e = hipGraphLaunch(B->exec, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "graph launch");
+  return HDG_OK;
+}
+
+extern "C" int hdg_batch_info(const hdg_batch *batch, int *n_items, int *groups, size_t *lds) {
+  const Batch *B = reinterpret_cast<const Batch *>(batch);
+  if (!B) return fail(HDG_EINVAL, "bad argument");
+  if (n_items) *n_items = (int)B->queue.size();
+  if (groups) *groups = B->groups;
+  if (lds) *lds = B->lds;
+  return HDG_OK;
+}
+
+extern "C" int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !t) return fail(HDG_EINVAL, "bad argument");
+  if (t->contract_threads) {
+    if (t->contract_threads != 256 && t->contract_threads != 512 && t->contract_threads != 1024)
+      return fail(HDG_EINVAL, "contract_threads must be 256, 512 or 1024");
+    P->dp.contract_threads = t->contract_threads;
+  }
+  if (t->condense_width) {
+    if (t->condense_width != 16 && t->condense_width != 32) return fail(HDG_EINVAL, "condense_width must be 16 or 32");
+    if (condense_lds_bytes(P->dp.n_pad, t->condense_width) > 160 * 1024)
+      return fail(HDG_EUNSUPPORTED, "condense_width does not fit in LDS for this block size");
+    if (!P->fused) return fail(HDG_EINVAL, "plan uses the separate LU / solve / Schur kernels");
+    P->dp.cw = t->condense_width;
+  }
+  if (t->condense_width_lp) {
+    if (t->condense_width_lp != 16 && t->condense_width_lp != 32)
+      return fail(HDG_EINVAL, "condense_width_lp must be 16 or 32");
+    if (condense_lds_bytes_lp(P->dp.n_pad, t->condense_width_lp) > 160 * 1024)
+      return fail(HDG_EUNSUPPORTED, "condense_width_lp does not fit in LDS for this block size");
+    P->dp.cw_lp = t->condense_width_lp;
+  }
+  return HDG_OK;
+}
+
+extern "C" int hdg_plan_get_tuning(const hdg_plan *plan, hdg_tuning *t) {
+  const Plan *P = reinterpret_cast<const Plan *>(plan);
+  if (!P || !t) return fail(HDG_EINVAL, "bad argument");
+  t->contract_threads = P->dp.contract_threads;
+  t->condense_width = P->fused ? P->dp.cw : 0;
+  t->condense_width_lp = P->dp.cw_lp;
+  return HDG_OK;
+}

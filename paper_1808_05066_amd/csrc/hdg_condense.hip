@@ -415,12 +415,12 @@ __host__ __device__ inline size_t lp_rec_floats(int np) { return rec_perm_off(np
 // T = float,  LP = true : scaled FP32 condensation, factors to the record `fac`.
 // One workgroup per element (blockIdx.x = element of the chunk).
 template <typename T, bool LP, int W>
-__device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t *status, T *S, double *g, T *Y,
-                                              double *z, T *inv, float *fac) {
+__device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, int32_t *status, T *S, double *g,
+                                              T *Y, double *z, T *inv, float *fac) {
   typedef Mfma<T> MF;
   constexpr int BS = W + 1, TW = W / 16;
   extern __shared__ double smem[];
-  const int el = blockIdx.x, e = e0 + el;
+  const int e = e0 + el;
   const int np = P.n_pad, kp = P.k_pad, kx = P.kx, n = P.n, k = P.k;
   double *A64 = P.A + (size_t)el * np * np;
   const double *X = P.X + (size_t)el * kx * np;
@@ -572,13 +572,13 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int32_t 
 
 __global__ __launch_bounds__(NT) void k_condense_f64_w32(DevPlan P, int e0, int32_t *status, double *S, double *g,
                                                          double *Y, double *z, double *inv) {
-  condense_body<double, false, 32>(P, e0, status, S, g, Y, z, inv, nullptr);
+  condense_body<double, false, 32>(P, e0, blockIdx.x, status, S, g, Y, z, inv, nullptr);
 }
 
 // 16-column blocks take half the LDS: two workgroups per CU with capped registers.
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_condense_f64_w16(
     DevPlan P, int e0, int32_t *status, double *S, double *g, double *Y, double *z, double *inv) {
-  condense_body<double, false, 16>(P, e0, status, S, g, Y, z, inv, nullptr);
+  condense_body<double, false, 16>(P, e0, blockIdx.x, status, S, g, Y, z, inv, nullptr);
 }
 
 // Two workgroups per CU where the FP32 working block fits twice in LDS:
@@ -586,7 +586,38 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 template <int W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_condense_f32(
     DevPlan P, int e0, int32_t *status, float *S, double *g, float *Y, double *z, float *fac) {
-  condense_body<float, true, W>(P, e0, status, S, g, Y, z, nullptr, fac);
+  condense_body<float, true, W>(P, e0, blockIdx.x, status, S, g, Y, z, nullptr, fac);
+}
+
+// Persistent condensation over a batch of plans (element types / orders with
+// uneven n, k): every workgroup takes work items from a queue ordered by
+// decreasing block size (longest processing time first) until it is empty.
+// Item i = (plan index, element) packed as plan << 24 | element.
+struct BatchItemArgs {
+  double *S, *g, *Y, *z;
+  int32_t *status;
+};
+
+__global__ __launch_bounds__(NT) void k_condense_batch(const DevPlan *__restrict__ plans,
+                                                       const BatchItemArgs *__restrict__ io,
+                                                       const int *__restrict__ queue, int n_items, int *counter) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const int code = queue[it];
+    const int pi = code >> 24, el = code & 0xFFFFFF;
+    const DevPlan &P = plans[pi];
+    const BatchItemArgs &a = io[pi];
+    if (P.cw == 32)
+      condense_body<double, false, 32>(P, 0, el, a.status, a.S, a.g, a.Y, a.z, P.inv, nullptr);
+    else
+      condense_body<double, false, 16>(P, 0, el, a.status, a.S, a.g, a.Y, a.z, P.inv, nullptr);
+    __syncthreads();
+  }
 }
 
 // x = A_lp^-1 r per element from the low-precision record: y = P D r, forward
@@ -685,7 +716,7 @@ size_t lp_record_bytes(int np) { return lp_rec_floats(np) * sizeof(float); }
 
 template <typename K, typename... Args>
 hipError_t launch_dyn(K kern, int ec, size_t lds, hipStream_t s, Args... args) {
-  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = set_dyn_lds((const void *)kern, lds);
   if (e) return e;
   hipLaunchKernelGGL(kern, dim3(ec), dim3(NT), lds, s, args...);
   return hipGetLastError();
@@ -705,6 +736,17 @@ hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status,
   if (P.cw_lp == 32) return launch_dyn(k_condense_f32<32>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
   if (P.cw_lp == 16) return launch_dyn(k_condense_f32<16>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
   return hipErrorInvalidValue;
+}
+
+size_t batch_item_args_bytes() { return sizeof(BatchItemArgs); }
+
+hipError_t launch_condense_batch(const DevPlan *plans_dev, const void *io_dev, const int *queue, int n_items,
+                                 int *counter, int n_groups, size_t lds, hipStream_t s) {
+  hipError_t e = set_dyn_lds((const void *)k_condense_batch, lds);
+  if (e) return e;
+  hipLaunchKernelGGL(k_condense_batch, dim3(n_groups), dim3(NT), lds, s, plans_dev,
+                     static_cast<const BatchItemArgs *>(io_dev), queue, n_items, counter);
+  return hipGetLastError();
 }
 
 hipError_t launch_lp_solve(const DevPlan &P, const float *fac, const double *r, double *x, hipStream_t s) {

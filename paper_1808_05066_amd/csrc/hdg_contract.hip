@@ -19,17 +19,18 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int NT = 1024;   // 16 waves: the block tables keep one workgroup per CU
 
 __device__ inline d4 mfma4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-template <int D, bool VISC, int NCT>
-__global__ __launch_bounds__(NT) void k_contract_mfma(DevPlan P, int e0, int ec) {
+// NTH threads per workgroup (256, 512 or 1024; chosen per plan, default 1024).
+template <int D, bool VISC, int NCT, int NTH>
+__global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec) {
+  constexpr int NT = NTH;
   constexpr int M = D + 2;
   constexpr int G = VISC ? M + M * D : M;   // column groups
-  constexpr int RT = (NCT == 1) ? 8 : 4;    // row tiles per wave per pass
+  constexpr int RT = (NCT == 1) ? (NTH >= 1024 ? 8 : 16) : (NTH >= 1024 ? 4 : 8);   // row tiles per wave per pass
   extern __shared__ double lds[];
   const int el = blockIdx.x, e = e0 + el;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -298,14 +299,20 @@ size_t lds_bytes_t(const DevPlan &P) {
   return (tables + work) * sizeof(double);
 }
 
+template <int D, bool VISC, int NCT, int NTH>
+hipError_t launch_nt(const DevPlan &P, int e0, int ec, hipStream_t s) {
+  const size_t lds = lds_bytes_t<D, VISC, NCT>(P);
+  hipError_t e = set_dyn_lds((const void *)k_contract_mfma<D, VISC, NCT, NTH>, lds);
+  if (e) return e;
+  hipLaunchKernelGGL((k_contract_mfma<D, VISC, NCT, NTH>), dim3(ec), dim3(NTH), lds, s, P, e0, ec);
+  return hipGetLastError();
+}
+
 template <int D, bool VISC, int NCT>
 hipError_t launch_t(const DevPlan &P, int e0, int ec, hipStream_t s) {
-  const size_t lds = lds_bytes_t<D, VISC, NCT>(P);
-  hipError_t e = hipFuncSetAttribute((const void *)k_contract_mfma<D, VISC, NCT>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e) return e;
-  hipLaunchKernelGGL((k_contract_mfma<D, VISC, NCT>), dim3(ec), dim3(NT), lds, s, P, e0, ec);
-  return hipGetLastError();
+  if (P.contract_threads == 256) return launch_nt<D, VISC, NCT, 256>(P, e0, ec, s);
+  if (P.contract_threads == 512) return launch_nt<D, VISC, NCT, 512>(P, e0, ec, s);
+  return launch_nt<D, VISC, NCT, 1024>(P, e0, ec, s);
 }
 
 template <int D, bool VISC>

@@ -310,7 +310,7 @@ size_t lu_lds_bytes(int np) { return (size_t)np * PS * sizeof(double); }
 
 hipError_t launch_lu(const DevPlan &P, int ec, int32_t *status, hipStream_t s) {
   const size_t lds = lu_lds_bytes(P.n_pad);
-  hipError_t e = hipFuncSetAttribute((const void *)k_lu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = set_dyn_lds((const void *)k_lu, lds);
   if (e) return e;
   hipLaunchKernelGGL(k_lu, dim3(ec), dim3(BLK), lds, s, P, status);
   return hipGetLastError();

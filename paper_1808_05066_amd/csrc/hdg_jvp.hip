@@ -180,8 +180,7 @@ hipError_t launch_jvp_t(const DevPlan &P, int e0, int ec, const double *dx, cons
   constexpr int PV = M + MD + (VISC ? MD * D + MD : 0);
   const size_t lds = ((size_t)P.n + P.k + (size_t)P.Nq * PV + (size_t)P.nf * P.Nfq * 2 * M) * sizeof(double);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute((const void *)k_jvp<D, VISC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  hipError_t e = set_dyn_lds((const void *)k_jvp<D, VISC>, lds);
   if (e) return e;
   hipLaunchKernelGGL((k_jvp<D, VISC>), dim3(ec), dim3(JB), lds, s, P, e0, dx, dlam, yloc, ytr);
   return hipGetLastError();

@@ -241,7 +241,7 @@ hipError_t launch_bj_assemble_f32(const DevPlan &P, const float *S, double *B, h
 hipError_t launch_block_invert(const DevPlan &P, double *B, int32_t *bad, hipStream_t s) {
   const int bs = P.bj_bs;
   const size_t lds = ((size_t)2 * bs * (bs + 1) + bs) * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void *)k_block_invert, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = set_dyn_lds((const void *)k_block_invert, lds);
   if (e) return e;
   hipLaunchKernelGGL(k_block_invert, dim3(P.bj_nblk), dim3(BI), lds, s, B, bs, bad);
   return hipGetLastError();

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <vector>
 #include <cstdio>
 #include <cstring>
@@ -264,6 +265,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
     if (D.cw) D.cw = 16;
     if (D.cw_lp) D.cw_lp = 16;
   }
+  D.contract_threads = 1024;
   P->fused = D.cw != 0;
   if (opts && (opts->flags & HDG_FLAG_SPLIT_DENSE)) P->fused = false;
   P->split_ok = lu_lds_bytes(D.n_pad) <= 160 * 1024;
@@ -414,6 +416,20 @@ Layout layout(const Plan *P) {
 }  // namespace
 
 namespace hdg {
+
+hipError_t set_dyn_lds(const void *kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void *>, size_t> done;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t &have = done[{dev, kernel}];
+  if (bytes <= have) return hipSuccess;
+  e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (!e) have = bytes;
+  return e;
+}
 
 Plan *checked(hdg_plan *plan) {
   Plan *P = reinterpret_cast<Plan *>(plan);

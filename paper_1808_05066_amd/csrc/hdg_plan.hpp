@@ -21,6 +21,7 @@ struct PointLayout {
 struct DevPlan {
   int dim, m, Np, nf, Nfp, Nq, Nfq, n, k, n_pad, k_pad, kx, viscous, n_elem, n_trace;
   int cw, cw_lp;           // column-block width of the fused FP64 / FP32 condensation (0: not available)
+  int contract_threads;    // workgroup size of the block contraction (256, 512, 1024)
   double gamma, mu, Pr, alpha;
   PointLayout L;
   // tables (device)
@@ -106,6 +107,10 @@ hipError_t launch_mlp_bwd(const float *theta, const float *feat, const float *dO
                           float *grad, hipStream_t s);
 hipError_t launch_adam(float *theta, const float *g, float *m, float *v, int t, float lr, hipStream_t s);
 hipError_t launch_scale_blocks(const DevPlan &P, double *B, const float *o, hipStream_t s);
+
+// Raise a kernel's dynamic-LDS limit once (cached per kernel): the attribute
+// call is not repeated inside stream capture.
+hipError_t set_dyn_lds(const void *kernel, size_t bytes);
 
 // error channel of hdg_last_error(): records the message, returns the code
 int fail(int code, const std::string &msg);

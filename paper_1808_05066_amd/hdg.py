@@ -72,6 +72,15 @@ class Plan:
         phys = _lib.hdg_phys(int(self.viscous), float(gamma), float(mu), float(Pr), float(alpha))
         check(self.lib.hdg_plan_set_phys(self.h, ctypes.byref(phys)), "hdg_plan_set_phys")
 
+    def tuning(self):
+        t = _lib.hdg_tuning()
+        check(self.lib.hdg_plan_get_tuning(self.h, ctypes.byref(t)), "hdg_plan_get_tuning")
+        return {f: getattr(t, f) for f, _ in _lib.hdg_tuning._fields_}
+
+    def set_tuning(self, contract_threads=0, condense_width=0, condense_width_lp=0):
+        t = _lib.hdg_tuning(int(contract_threads), int(condense_width), int(condense_width_lp))
+        check(self.lib.hdg_plan_set_tuning(self.h, ctypes.byref(t)), "hdg_plan_set_tuning")
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h is not None and h.value:
@@ -361,6 +370,74 @@ def adam(theta, grad, m, v, t, lr):
     lib = _lib.load()
     check(lib.hdg_learn_adam(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), int(t), ctypes.c_float(lr), _stream()),
           "hdg_learn_adam")
+
+
+class Batch:
+    """Persistent condensation of several plans in one launch, optionally replayed from a hipGraph.
+
+    io: list (one per plan) of dicts with v, q, vhat, ustar, vbc and outputs S, g, Y, z, status.
+    order: "lpt" (largest blocks first) or "plan".
+    """
+
+    def __init__(self, plans, order="lpt"):
+        torch = _torch()
+        self.lib = _lib.load()
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.h.value for p in self.plans])
+        h = ctypes.c_void_p()
+        check(self.lib.hdg_batch_create(ctypes.byref(h), arr, len(self.plans), 0 if order == "lpt" else 1),
+              "hdg_batch_create")
+        self.h = h
+        nb = ctypes.c_size_t()
+        check(self.lib.hdg_batch_workspace_bytes(h, ctypes.byref(nb)), "hdg_batch_workspace_bytes")
+        self.workspace = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.plans[0].device)
+        ptr = ctypes.c_void_p(self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256)
+        check(self.lib.hdg_batch_bind_workspace(h, ptr, ctypes.c_size_t(nb.value), _stream()),
+              "hdg_batch_bind_workspace")
+        self._io = None
+
+    def info(self):
+        n, g, lds = ctypes.c_int(), ctypes.c_int(), ctypes.c_size_t()
+        check(self.lib.hdg_batch_info(self.h, ctypes.byref(n), ctypes.byref(g), ctypes.byref(lds)), "hdg_batch_info")
+        return {"items": n.value, "groups": g.value, "lds_bytes": lds.value}
+
+    def set_groups(self, groups):
+        check(self.lib.hdg_batch_set_groups(self.h, int(groups)), "hdg_batch_set_groups")
+
+    def set_io(self, io):
+        arr = (_lib.hdg_batch_io * len(io))()
+        for i, d in enumerate(io):
+            arr[i] = _lib.hdg_batch_io(*[None if d.get(k) is None else d[k].data_ptr()
+                                         for k in ("v", "q", "vhat", "ustar", "vbc", "S", "g", "Y", "z",
+                                                   "status")])
+        self._io = io
+        check(self.lib.hdg_batch_set_io(self.h, arr, _stream()), "hdg_batch_set_io")
+
+    def run(self):
+        check(self.lib.hdg_batch_run(self.h, _stream()), "hdg_batch_run")
+
+    def capture(self):
+        """Capture on a stream of its own (the default stream cannot be captured)."""
+        torch = _torch()
+        self._gstream = torch.cuda.Stream()
+        self._gstream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self._gstream):
+            check(self.lib.hdg_batch_capture(self.h, _stream()), "hdg_batch_capture")
+        torch.cuda.current_stream().wait_stream(self._gstream)
+
+    def replay(self):
+        torch = _torch()
+        s = self._gstream
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            check(self.lib.hdg_batch_replay(self.h, _stream()), "hdg_batch_replay")
+        torch.cuda.current_stream().wait_stream(s)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.hdg_batch_destroy(h)
+            self.h = None
 
 
 def selftest():

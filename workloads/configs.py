@@ -132,3 +132,48 @@ def ns2d_tri(n=3, p=2, eps=0.02, jitter=0.1, mach=0.3, re=100.0, config_id=7, al
                              p0 + 0.25 * (np.cos(2 * X) + np.cos(2 * Y))])
     return Workload("ns2d_tri_p%d_%dx%d" % (p, n, n), config_id, mesh, p, "hdg", 1.4, 1.0 / re, 0.72,
                     alpha, True, TG2(), eps, 1.0, face_bc)
+
+
+def ns3d_tet(n=2, p=2, eps=0.02, jitter=0.05, mach=0.3, re=1.0e4, config_id=8, alpha=None):
+    """Periodic Kuhn tetrahedra (6 per cube) with the Taylor-Green state."""
+    mesh = M.kuhn_tets(n, jitter, seed=[config_id, 0], periodic=True)
+    face_bc = np.zeros((mesh.n_elem, 4), dtype=np.int32)
+    fld = F.TaylorGreen(mach=mach)
+    a = 1.0 / (DIRK33_AII * TGV_DT) if alpha is None else alpha
+    return Workload("ns3d_tet_p%d_%d^3x6" % (p, n), config_id, mesh, p, "hdg", 1.4, 1.0 / re, 0.72, a, True, fld,
+                    eps, 1.0, face_bc)
+
+
+def mixed_batch(n_tet=15, n_hex=16, orders=(1, 2, 3, 4), jitter=0.05, eps=0.02, re=1.0e4, config_id=3,
+                with_hex=True):
+    """Mixed batch of Navier-Stokes elements for one persistent launch.
+
+    n_tet^3 x 6 periodic Kuhn tetrahedra (15 -> 20,250) with the order of each
+    element drawn uniformly from `orders` (seed [config_id, 4]), plus the
+    n_hex^3 periodic p = 2 hex mesh (16 -> 4,096); Taylor-Green velocity with
+    the background pressure of a Mach number per octant, M ~ U(0.1, 0.8)
+    (seed [config_id, 6]); Re = 1e4, Pr = 0.72, DIRK stage mass term.  Each
+    element uses a trace space of its own order, so the batch is one workload
+    per order: the tetrahedra of order p form a sub-mesh whose faces towards
+    elements of another order are Dirichlet-trace faces (v_bc from the clean
+    state).  Returns a list of Workloads.
+    """
+    rng = np.random.default_rng([config_id, 4])
+    tets = M.kuhn_tets(n_tet, jitter, seed=[config_id, 0], periodic=True)
+    pk = np.asarray(orders)[rng.integers(0, len(orders), size=tets.n_elem)]
+    machs = np.random.default_rng([config_id, 6]).uniform(0.1, 0.8, size=8)
+    fld = F.OctantTaylorGreen(machs)
+    a = 1.0 / (DIRK33_AII * TGV_DT)
+    out = []
+    for p in orders:
+        sel = np.nonzero(pk == p)[0]
+        if len(sel) == 0:
+            continue
+        sub = M.subset_mesh(tets, sel)
+        out.append(Workload("mixed_tet_p%d" % p, config_id, sub, int(p), "hdg", 1.4, 1.0 / re, 0.72, a, True, fld,
+                            eps, 1.0, sub.boundary.astype(np.int32)))
+    if with_hex:
+        hexes = M.hex_cube(n_hex, jitter, seed=[config_id, 5], periodic=True)
+        out.append(Workload("mixed_hex_p2", config_id, hexes, 2, "hdg", 1.4, 1.0 / re, 0.72, a, True, fld, eps, 1.0,
+                            np.zeros((hexes.n_elem, 6), dtype=np.int32)))
+    return out

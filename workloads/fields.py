@@ -99,6 +99,36 @@ class TaylorGreen(Field):
         return np.stack([rho, vx, vy, vz, p])
 
 
+class OctantTaylorGreen(TaylorGreen):
+    """Taylor-Green velocity with a background pressure set by a Mach number per octant.
+
+    Octant o = 4 b_z + 2 b_y + b_x with b = 1 on (pi L, 2 pi L) of an axis.  The
+    squared octant Mach numbers are blended with the periodic, analytic
+    indicator s(x) = (1 - tanh(sin(x / L) / delta)) / 2 per axis (delta = 0.5)
+    and the background pressure is 1 / (gamma M^2(x)): the entropy variable
+    v_m is proportional to M^2, so it varies smoothly between the octant values
+    and high-order interpolation stays physical (a pressure jump of up to
+    (0.8 / 0.1)^2 would not).
+    """
+
+    def __init__(self, machs, rho0=1.0, v0=1.0, L=1.0, gamma=1.4, delta=0.5):
+        super().__init__(mach=float(np.min(machs)), rho0=rho0, v0=v0, L=L, gamma=gamma)
+        self.machs = np.asarray(machs, float)
+        self.delta = delta
+
+    def prim(self, x):
+        base = super().prim(x)
+        s = [0.5 * (1.0 - np.tanh(np.sin(x[a] / self.L) / self.delta)) for a in range(3)]
+        m2 = 0.0
+        for o in range(8):
+            w = 1.0
+            for a in range(3):
+                w = w * (s[a] if (o >> a) & 1 else 1.0 - s[a])
+            m2 = m2 + w * self.machs[o] ** 2
+        p0 = self.rho0 * self.v0 ** 2 / (self.gamma * m2)
+        return np.concatenate([base[:4], (base[4] - self.p0 + p0)[None]])
+
+
 class SmoothNoise(Field):
     """base * (1 + eps*eta) for rho and p; V + eps*vref*eta for velocity.
 

@@ -361,3 +361,20 @@ def face_neighbors(mesh: Mesh, p: int = 1):
     nb[a], nbf[a] = b // nf, b % nf
     nb[b], nbf[b] = a // nf, a % nf
     return nb.reshape(E, nf), nbf.reshape(E, nf)
+
+
+def subset_mesh(mesh: Mesh, elems) -> Mesh:
+    """The elements `elems` of `mesh` as a mesh of their own.
+
+    Faces whose neighbour is not in the subset become boundary faces; the
+    lattice period is kept, so faces matched across a periodic boundary stay
+    matched.
+    """
+    elems = np.asarray(elems, dtype=np.int64)
+    nb, _ = face_neighbors(mesh)
+    inside = np.zeros(mesh.n_elem, dtype=bool)
+    inside[elems] = True
+    nbs = nb[elems]
+    bnd = mesh.boundary[elems] | (nbs < 0) | ~inside[np.maximum(nbs, 0)]
+    return Mesh(mesh.etype, mesh.elem_xyz[elems].copy(), mesh.elem_lat[elems].copy(), mesh.period, bnd, mesh.h,
+                mesh.extent, mesh.length, dict(mesh.info, subset=len(elems)))
