@@ -52,17 +52,8 @@ def flops_per_elem(n, k, Np, Nq, m, d, viscous):
 
 
 def prepare_inputs(plan, wl, torch):
-    x, xt = plan.node_coords()
-    s = wl.sample(x.cpu().numpy(), xt.cpu().numpy())
-    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    v, q, _ = plan.prepare_state(dev(s["prim"]), dev(s["grad"]) if wl.viscous else None)
-    vhat, _, _ = plan.prepare_state(dev(s["prim_hat"]))
-    _, _, ustar = plan.prepare_state(dev(s["prim_star"]), want_u=True)
-    vbc = None
-    if np.any(wl.face_bc):
-        vbc, _, _ = plan.prepare_state(dev(s["prim_bc"]))
-    torch.cuda.synchronize()
-    return dict(v=v, q=q, vhat=vhat, ustar=ustar, vbc=vbc)
+    from paper_1808_05066_amd.inputs import device_inputs
+    return device_inputs(plan, wl)
 
 
 def cpu_baseline(wl, seconds_budget=20.0):
@@ -141,6 +132,66 @@ def bench_mixed(plan, inp, out64, E, fp64_cond_ms, torch):
             "converged": info["converged"], "rel_err_vs_fp64_gpu": errs}
 
 
+def bench_batch(torch, tune=True):
+    """Mixed batch: 20,250 Kuhn tetrahedra with orders drawn from {1,2,3,4} plus 4,096 p = 2 hexes (NS).
+
+    Times the per-plan launches one after another, the persistent batched
+    launch (largest blocks first, and plan order) and its hipGraph replay.
+    """
+    from paper_1808_05066_amd import autotune
+    from paper_1808_05066_amd.hdg import Batch
+    from paper_1808_05066_amd.inputs import device_inputs, plan_for
+    groups = C.mixed_batch()
+    plans, io, flops = [], [], 0.0
+    for wl in groups:
+        pl = plan_for(wl)
+        inp = device_inputs(pl, wl)
+        if tune:
+            autotune.apply(pl)
+        o = pl.alloc_outputs()
+        plans.append(pl)
+        io.append(dict(v=inp["v"], q=inp["q"], vhat=inp["vhat"], ustar=inp["ustar"], vbc=inp["vbc"], **o))
+        fl = flops_per_elem(pl.n, pl.k, pl.Np, pl.Nq, pl.m, pl.dim, True)
+        flops += (fl["lu"] + fl["solve"] + fl["schur"]) * pl.n_elem
+    E = sum(pl.n_elem for pl in plans)
+
+    def sequential():
+        for pl, d in zip(plans, io):
+            pl.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], out=d)
+
+    res = {"elements": E, "groups": [{"name": wl.name, "elements": pl.n_elem, "n": pl.n, "k": pl.k,
+                                      "tuning": pl.tuning()} for wl, pl in zip(groups, plans)],
+           "dense_flop": flops}
+    res["sequential_ms"] = _timed(sequential, 3, torch)
+    for order in ("lpt", "plan"):
+        b = Batch(plans, order=order)
+        b.set_io(io)
+        res["batch_%s_ms" % order] = _timed(b.run, 3, torch)
+        if order == "lpt":
+            b.capture()
+            res["graph_replay_ms"] = _timed(b.replay, 3, torch)
+            bad = sum(int((d["status"] != 0).sum()) for d in io)
+            res["bad_elements"] = bad
+        del b
+    best = min(res["batch_lpt_ms"], res["graph_replay_ms"])
+    res["value"] = E / (best / 1e3)
+    res["unit"] = "elem/s"
+    res["dense_tflops"] = flops / (best / 1e3) / 1e12
+    return res
+
+
+def bench_learned(torch):
+    """Held-out 24^3 p = 2 system: GMRES(50) to 1e-10 with plain and learned block Jacobi."""
+    ck = os.path.join(ROOT, "paper_1808_05066_amd", "data", "learned_bj.npz")
+    if not os.path.exists(ck):
+        return {"error": "no trained checkpoint"}
+    from paper_1808_05066_amd import learn
+    z = np.load(ck, allow_pickle=False)
+    rows = learn.evaluate(z["theta"], n=24, seeds=(learn.HELDOUT_SEED0 + 50,),
+                          log=lambda s: print(s, file=sys.stderr, flush=True))
+    return {"checkpoint": "paper_1808_05066_amd/data/learned_bj.npz", "heldout": rows}
+
+
 def bench_solve(plan, out, rhs, torch):
     """GMRES(50) + block Jacobi to 1e-10 on the FP64 condensed system (outside the timed step)."""
     from paper_1808_05066_amd.hdg import TraceSolver
@@ -165,6 +216,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurement")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the mixed-batch measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -259,6 +312,14 @@ def main():
     if not args.no_solve:
         print("[bench] global trace solve", file=sys.stderr, flush=True)
         res["trace_solve"] = bench_solve(plan, out, r, torch)
+    if not args.no_learned:
+        print("[bench] learned preconditioner on a held-out system", file=sys.stderr, flush=True)
+        res["learned_precond"] = bench_learned(torch)
+    if not args.no_batch:
+        del out, inp, plan
+        torch.cuda.empty_cache()
+        print("[bench] mixed tetrahedron/hexahedron batch", file=sys.stderr, flush=True)
+        res["batch"] = bench_batch(torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
