@@ -206,6 +206,44 @@ def bench_solve(plan, out, rhs, torch):
             "setup_ms": t_setup, "unknowns": plan.m * plan.n_trace}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "condense_ns3d_hex_p2_16_traffic.md")
+
+
+def kernel_source_hash():
+    """Hash of the condensation kernel source: HBM counters taken on another version do not apply."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1808_05066_amd", "csrc", "hdg_condense.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the condensation kernel from the committed counter summary, or None.
+
+    The summary holds a line `traffic-json: {...}` with the source hash the
+    counters were taken on; a different current hash means the kernel changed.
+    """
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic-json:"):
+            d = json.loads(line.split(":", 1)[1])
+            if d.get("source_hash") != kernel_source_hash():
+                return None
+            return d
+    return None
+
+
+def copy_calibration(torch, nbytes=1 << 30):
+    """A plain device copy of known size, run under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE."""
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +256,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-batch measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -227,6 +267,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     from paper_1808_05066_amd.hdg import Plan
 
     desc, make = WORKLOADS[args.workload]
@@ -290,6 +333,11 @@ def main():
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                 "flops_per_elem": fl.get(dom), "elems_per_launch": E, "avg_ms": avg[dom]}
+    tr = measured_traffic() if dom == "condense" else None
+    if tr is not None:
+        roof["traffic"] = tr["bytes_per_launch"] * E / tr["elements_per_launch"]
+        roof["traffic_unit"] = "bytes"
+        roof["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
     dense = fl["condense"]
     dense_ms = sum(avg[p] for p in ("lu", "solve", "schur", "condense"))
     cond_ms = avg["points"] + avg["contract"] + dense_ms

@@ -10,8 +10,9 @@
 // * LU (left-looking): block J is gathered through the current row permutation,
 //   updated by all previous blocks (unit-lower triangle solves and MFMA
 //   updates), then factored in LDS with partial pivoting.  Factored columns are
-//   stored at their ORIGINAL row index, so later row interchanges only touch the
-//   permutation vector, never stored columns.
+//   stored in pivot-position order; a row interchange in a later panel is also
+//   applied to the stored columns of the earlier panels (as LAPACK's laswp),
+//   which keeps every later read of the factors contiguous.
 // * Right-hand sides [B | R_loc] in blocks of 32 columns: permutation gather,
 //   forward and backward substitution against the stored factors, then the
 //   Schur product C * Y_block straight from LDS into S and g.
@@ -93,12 +94,13 @@ __device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int l
   }
 }
 
+// factored block -> M at pivot position (row i of the block is position i)
 template <typename T, int W>
 __device__ inline void store_block(const Lds<T> &s, T *M, int ld, int c0, int np) {
   constexpr int BS = W + 1;
   for (int t = threadIdx.x; t < np * W; t += NT) {
     const int c = t / np, i = t - c * np;
-    M[(size_t)(c0 + c) * ld + s.perm[i]] = s.blk[i * BS + c];
+    M[(size_t)(c0 + c) * ld + i] = s.blk[i * BS + c];
   }
 }
 
@@ -160,7 +162,8 @@ __device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
   }
 }
 
-// blk[r][:] -= sum_kk M[(p0+kk) * ld + perm[r]] * blk[p0+kk][:]  for rows r in [r_lo, r_hi)
+// blk[r][:] -= sum_kk M[(p0+kk) * ld + r] * blk[p0+kk][:]  for rows r in [r_lo, r_hi)
+// (stored factors are in pivot-position order, so the loads are contiguous)
 // (r_lo, r_hi multiples of 16, disjoint from p0..p0+W-1).
 template <typename T, int W>
 __device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, int r_lo, int r_hi) {
@@ -173,7 +176,7 @@ __device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, 
   T a[KS], an[KS];
   int t = wave;
   if (t < ntile) {
-    const size_t grow = (size_t)s.perm[r_lo + t * 16 + li];
+    const size_t grow = (size_t)(r_lo + t * 16 + li);
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) a[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
   }
@@ -181,7 +184,7 @@ __device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, 
     const int r0 = r_lo + t * 16;
     const int tn = t + NW;
     if (tn < ntile) {
-      const size_t grow = (size_t)s.perm[r_lo + tn * 16 + li];
+      const size_t grow = (size_t)(r_lo + tn * 16 + li);
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) an[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
     }
@@ -215,7 +218,7 @@ __device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, 
 constexpr int SPW = 8;   // sub-panel width
 
 template <typename T, int W>
-__device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T *tmprow) {
+__device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T *tmprow, T *Fm, int ld) {
   constexpr int BS = W + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = j0 + tid, r1 = j0 + tid + NT;   // rows r1, r1 + NT, ... stay in LDS
@@ -301,6 +304,13 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
           const int t0 = s.perm[r];
           s.perm[r] = s.perm[piv];
           s.perm[piv] = t0;
+        }
+        // the interchange also applies to the stored columns of the earlier panels
+        for (int c = tid; c < j0; c += NT) {
+          T *col = Fm + (size_t)c * ld;
+          const T t0 = col[r];
+          col[r] = col[piv];
+          col[piv] = t0;
         }
       }
       __syncthreads();
@@ -406,7 +416,7 @@ __host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp, i
 }
 
 // Per-element record of the low-precision factorization (floats):
-//   F [np][np] factors at original row index | Inv [np/W][2][W][W] (space for
+//   F [np][np] factors in pivot-position order | Inv [np/W][2][W][W] (space for
 //   W = 32) | perm [np] (int) | dsc [np] (symmetric scaling, powers of two)
 __host__ __device__ inline size_t rec_perm_off(int np) { return (size_t)np * np + 2 * (size_t)np * WMAX; }
 __host__ __device__ inline size_t lp_rec_floats(int np) { return rec_perm_off(np) + 2 * (size_t)np; }
@@ -476,7 +486,7 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
       gemm_update<T, W>(s, Fm, np, p0, p0 + W, np);
       __syncthreads();
     }
-    singular |= panel_factor<T, W>(s, j0, np, s.prow, s.tmp);
+    singular |= panel_factor<T, W>(s, j0, np, s.prow, s.tmp, Fm, np);
     __syncthreads();
     invert_diag<T, W>(s, j0, Ie + (size_t)J * 2 * W * W, Ie + (size_t)J * 2 * W * W + W * W);
     store_block<T, W>(s, Fm, np, j0, np);
@@ -623,8 +633,8 @@ __global__ __launch_bounds__(NT) void k_condense_batch(const DevPlan *__restrict
 // x = A_lp^-1 r per element from the low-precision record: y = P D r, forward
 // substitution (unit L) and backward substitution (U) over W-column blocks
 // with the stored diagonal-block inverses, x = D y.  Vectors and arithmetic in
-// FP64, factors read as FP32; rows are visited in their stored (original)
-// order so every factor column is read contiguously.  One workgroup per element.
+// FP64, factors read as FP32 (stored in pivot-position order, so every factor
+// column is read contiguously).  One workgroup per element.
 constexpr int SB = 256;
 
 __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, int W, const float *__restrict__ fac,
@@ -634,7 +644,6 @@ __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, int W, const flo
   const int nJ = np / W;
   double *y = sm2;                                   // [np] by pivot position
   double *t32 = y + np;                              // [W]
-  int *ipos = reinterpret_cast<int *>(t32 + W);      // [np] position of original row o
   const float *rec = fac + (size_t)e * lp_rec_floats(np);
   const float *F = rec;
   const float *Inv = rec + (size_t)np * np;
@@ -643,7 +652,6 @@ __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, int W, const flo
   const double *re = r + (size_t)e * n;
   for (int i = tid; i < np; i += SB) {
     const int o = perm[i];
-    ipos[o] = i;
     y[i] = o < n ? (double)dsc[o] * re[o] : 0.0;
   }
   __syncthreads();
@@ -659,12 +667,10 @@ __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, int W, const flo
     __syncthreads();
     if (tid < W) y[j0 + tid] = t32[tid];
     __syncthreads();
-    for (int o = tid; o < np; o += SB) {
-      const int i = ipos[o];
-      if (i < j0 + W) continue;
+    for (int i = j0 + W + tid; i < np; i += SB) {
       double acc = 0.0;
 #pragma unroll 8
-      for (int c = 0; c < W; ++c) acc += (double)F[(size_t)(j0 + c) * np + o] * y[j0 + c];
+      for (int c = 0; c < W; ++c) acc += (double)F[(size_t)(j0 + c) * np + i] * y[j0 + c];
       y[i] -= acc;
     }
     __syncthreads();
@@ -681,15 +687,11 @@ __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, int W, const flo
     __syncthreads();
     if (tid < W) y[j0 + tid] = t32[tid];
     __syncthreads();
-    if (j0 > 0) {
-      for (int o = tid; o < np; o += SB) {
-        const int i = ipos[o];
-        if (i >= j0) continue;
-        double acc = 0.0;
+    for (int i = tid; i < j0; i += SB) {
+      double acc = 0.0;
 #pragma unroll 8
-        for (int c = 0; c < W; ++c) acc += (double)F[(size_t)(j0 + c) * np + o] * y[j0 + c];
-        y[i] -= acc;
-      }
+      for (int c = 0; c < W; ++c) acc += (double)F[(size_t)(j0 + c) * np + i] * y[j0 + c];
+      y[i] -= acc;
     }
     __syncthreads();
   }
