@@ -104,11 +104,45 @@ __device__ inline void store_block(const Lds<T> &s, T *M, int ld, int c0, int np
   }
 }
 
-// Rows p0..p0+W-1 of the block <- Inv * rows, Inv the stored inverse of the
-// unit-lower (L) or upper (U) W x W diagonal block of the factors; (W/16)^2 waves
-// each form one 16 x 16 tile on MFMA, then write back after a barrier.
+// One step "apply diagonal-block inverse, then update the other rows" of a
+// blocked triangular sweep.  Both global operands of a step (the W x W inverse
+// and the first row tile of the factor panel) are loaded one step ahead into
+// registers, so their latency overlaps the previous step.
+struct Step {
+  int inv;          // offset of the W x W inverse in the inverse table (-1: no step)
+  int p0;           // first row / factor column of the diagonal block
+  int r_lo, r_hi;   // rows updated by the panel p0..p0+W-1 (empty if r_lo >= r_hi)
+};
+
 template <typename T, int W>
-__device__ inline void inv_apply(const Lds<T> &s, const T *Inv, int p0) {
+__device__ inline void load_inv(T (&ia)[W / 4], const T *Ie, const Step &st) {
+  constexpr int TW = W / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  if (st.inv < 0 || wave >= TW * TW) return;
+  const T *Inv = Ie + st.inv;
+  const int ti = wave % TW;
+#pragma unroll
+  for (int kk = 0; kk < W / 4; ++kk) ia[kk] = Inv[(4 * kk + lk) * W + ti * 16 + li];
+}
+
+template <typename T, int W>
+__device__ inline void load_tile(T (&a)[W / 4], const T *M, int ld, const Step &st) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  if (st.inv < 0 || st.r_lo + wave * 16 >= st.r_hi) return;
+  const T *Mp = M + (size_t)(st.p0 + lk) * ld;
+  const size_t grow = (size_t)(st.r_lo + wave * 16 + li);
+#pragma unroll
+  for (int kk = 0; kk < W / 4; ++kk) a[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
+}
+
+// Rows p0..p0+W-1 of the block <- Inv * rows, Inv (preloaded in ia) the stored
+// inverse of the unit-lower (L) or upper (U) W x W diagonal block of the factors;
+// (W/16)^2 waves each form one 16 x 16 tile on MFMA, then write back after a
+// barrier.  The inverse of the next step is loaded into ia meanwhile.
+template <typename T, int W>
+__device__ inline void inv_apply(const Lds<T> &s, T (&ia)[W / 4], int p0, const T *Ie, const Step &next) {
   typedef Mfma<T> MF;
   constexpr int BS = W + 1, TW = W / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -116,12 +150,10 @@ __device__ inline void inv_apply(const Lds<T> &s, const T *Inv, int p0) {
   typename MF::acc acc = {0, 0, 0, 0};
   const int ti = wave % TW, tj = wave / TW;
   if (wave < TW * TW) {
-    T a[W / 4];
 #pragma unroll
-    for (int kk = 0; kk < W / 4; ++kk) a[kk] = Inv[(4 * kk + lk) * W + ti * 16 + li];
-#pragma unroll
-    for (int kk = 0; kk < W / 4; ++kk) acc = MF::op(a[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
+    for (int kk = 0; kk < W / 4; ++kk) acc = MF::op(ia[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
   }
+  load_inv<T, W>(ia, Ie, next);
   __syncthreads();
   if (wave < TW * TW) {
 #pragma unroll
@@ -163,24 +195,22 @@ __device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
 }
 
 // blk[r][:] -= sum_kk M[(p0+kk) * ld + r] * blk[p0+kk][:]  for rows r in [r_lo, r_hi)
-// (stored factors are in pivot-position order, so the loads are contiguous)
-// (r_lo, r_hi multiples of 16, disjoint from p0..p0+W-1).
+// (stored factors are in pivot-position order, so the loads are contiguous;
+// r_lo, r_hi multiples of 16, disjoint from p0..p0+W-1).  The wave's first tile
+// arrives preloaded in a; the first tile of the next step is loaded into a at
+// the end.
 template <typename T, int W>
-__device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, int r_lo, int r_hi) {
+__device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, int ld, const Step &st,
+                                   const Step &next) {
   typedef Mfma<T> MF;
   constexpr int BS = W + 1, TW = W / 16, KS = W / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int ntile = (r_hi - r_lo) / 16;
+  const int p0 = st.p0, r_lo = st.r_lo;
+  const int ntile = st.r_hi > r_lo ? (st.r_hi - r_lo) / 16 : 0;
   const T *Mp = M + (size_t)(p0 + lk) * ld;
-  T a[KS], an[KS];
-  int t = wave;
-  if (t < ntile) {
-    const size_t grow = (size_t)(r_lo + t * 16 + li);
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) a[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
-  }
-  for (; t < ntile; t += NW) {
+  T an[KS];
+  for (int t = wave; t < ntile; t += NW) {
     const int r0 = r_lo + t * 16;
     const int tn = t + NW;
     if (tn < ntile) {
@@ -205,6 +235,25 @@ __device__ inline void gemm_update(const Lds<T> &s, const T *M, int ld, int p0, 
       for (int r = 0; r < 4; ++r) s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li] = c[q][r];
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) a[kk] = an[kk];
+  }
+  load_tile<T, W>(a, M, ld, next);
+}
+
+// A sequence of steps: spec(i) for i in [0, count), each applied with its
+// operands loaded one step ahead.
+template <typename T, int W, typename Spec>
+__device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int ld, int count, Spec spec) {
+  T ia[W / 4], a[W / 4];
+  Step cur = spec(0);
+  load_inv<T, W>(ia, Ie, cur);
+  load_tile<T, W>(a, Fm, ld, cur);
+  for (int i = 0; i < count; ++i) {
+    const Step nxt = (i + 1 < count) ? spec(i + 1) : Step{-1, 0, 0, 0};
+    inv_apply<T, W>(s, ia, cur.p0, Ie, nxt);
+    __syncthreads();
+    gemm_update<T, W>(s, a, Fm, ld, cur, nxt);
+    __syncthreads();
+    cur = nxt;
   }
 }
 
@@ -479,13 +528,8 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
     if constexpr (LP) load_block_scaled<T, W>(s, A64, np, j0, np, true);
     else load_block<T, W>(s, A64, np, j0, np);
     __syncthreads();
-    for (int Pp = 0; Pp < J; ++Pp) {
-      const int p0 = Pp * W;
-      inv_apply<T, W>(s, Ie + (size_t)Pp * 2 * W * W, p0);
-      __syncthreads();
-      gemm_update<T, W>(s, Fm, np, p0, p0 + W, np);
-      __syncthreads();
-    }
+    if (J > 0)
+      run_steps<T, W>(s, Ie, Fm, np, J, [&](int i) { return Step{i * 2 * W * W, i * W, i * W + W, np}; });
     singular |= panel_factor<T, W>(s, j0, np, s.prow, s.tmp, Fm, np);
     __syncthreads();
     invert_diag<T, W>(s, j0, Ie + (size_t)J * 2 * W * W, Ie + (size_t)J * 2 * W * W + W * W);
@@ -510,20 +554,12 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
     if constexpr (LP) load_block_scaled<T, W>(s, X, np, c0, np, false);
     else load_block<T, W>(s, X, np, c0, np);
     __syncthreads();
-    for (int Pp = 0; Pp < nJ; ++Pp) {
-      const int p0 = Pp * W;
-      inv_apply<T, W>(s, Ie + (size_t)Pp * 2 * W * W, p0);
-      __syncthreads();
-      if (p0 + W < np) gemm_update<T, W>(s, Fm, np, p0, p0 + W, np);
-      __syncthreads();
-    }
-    for (int Pp = nJ - 1; Pp >= 0; --Pp) {
-      const int p0 = Pp * W;
-      inv_apply<T, W>(s, Ie + (size_t)Pp * 2 * W * W + W * W, p0);
-      __syncthreads();
-      if (p0 > 0) gemm_update<T, W>(s, Fm, np, p0, 0, p0);
-      __syncthreads();
-    }
+    // forward (unit lower) then backward (upper) sweep as one pipelined sequence
+    run_steps<T, W>(s, Ie, Fm, np, 2 * nJ, [&](int i) {
+      if (i < nJ) return Step{i * 2 * W * W, i * W, i * W + W, np};
+      const int P = 2 * nJ - 1 - i;
+      return Step{P * 2 * W * W + W * W, P * W, 0, P * W};
+    });
     if constexpr (LP) {
       // undo the column scaling: Y = D Y_hat, z = D z_hat
       for (int t = tid; t < np * W; t += NT) {
