@@ -18,6 +18,8 @@ import pytest
 
 from oracle import hdg as ohdg
 
+from workloads import configs as C
+
 from cases import SMALL_CASES, gpu_plan, oracle_case, to_dev
 
 pytestmark = pytest.mark.gpu
@@ -150,3 +152,41 @@ def test_refinement_reaches_full_system_tolerance(torch, name):
     fwd = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(name, "forward error vs oracle", fwd)
     assert fwd <= 1e-4
+
+
+def test_large_block_p3_hex_fp32_and_refinement(torch):
+    """n = 1280 (p = 3 hexes, the per-GPU shape of the 32^3 mesh): no FP64 kernel fits in LDS, the FP32
+    condensation runs with 16-column blocks; sampled outputs against the oracle and the refined solve."""
+    from paper_1808_05066_amd import _lib
+    wl = C.ns3d_hex(n=2, p=3, eps=0.05, jitter=0.05)
+    disc, inp = oracle_case(wl)
+    plan = gpu_plan(wl)
+    assert plan.tuning()["condense_width_lp"] == 16
+    d = to_dev(inp)
+    with pytest.raises(_lib.HdgError):
+        plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    lp = plan.assemble_condense_lp(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    torch.cuda.synchronize()
+    assert int(lp["status"].abs().max()) == 0
+    ref = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"], elems=[0],
+                                 keep_blocks=True)[0]
+    errs = {"S": np.linalg.norm(lp["S"][0].cpu().numpy().astype(np.float64).T - ref["S"]) / np.linalg.norm(ref["S"]),
+            "Y": np.linalg.norm(lp["Y"][0].cpu().numpy().astype(np.float64).T - ref["Y"]) / np.linalg.norm(ref["Y"]),
+            "g": np.linalg.norm(lp["g"][0].cpu().numpy() - ref["g"]) / np.linalg.norm(ref["g"])}
+    print("p=3 hex FP32 errors vs oracle", errs)
+    for k, e in errs.items():
+        assert e <= 1e-3, (k, e)
+    # matrix-free FP64 Jacobian of element 0 against the oracle blocks
+    rng = np.random.default_rng(31)
+    dx = rng.normal(size=(wl.mesh.n_elem, disc.n))
+    dlam = rng.normal(size=(disc.m, wl.n_trace))
+    yl, yt = plan.jacobian_apply(d["v"], d["q"], d["vhat"], torch.from_numpy(dx).cuda(),
+                                 torch.from_numpy(dlam).cuda(), ustar=d["ustar"], vbc=d["vbc"])
+    lam0 = dlam.reshape(-1)[ohdg.element_trace_index(disc, 0)]
+    ol = ref["A"] @ dx[0] + ref["B"] @ lam0
+    sl = np.abs(ref["A"]) @ np.abs(dx[0]) + np.abs(ref["B"]) @ np.abs(lam0)
+    assert np.linalg.norm(yl[0].cpu().numpy() - ol) / np.linalg.norm(sl) <= 1e-12
+    dxs, dls, info = plan.refine_solve(d["v"], d["q"], d["vhat"], lp, ustar=d["ustar"], vbc=d["vbc"], tol=1e-10,
+                                       max_outer=12, gmres_tol=1e-8)
+    print("p=3 hex refinement", info)
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
