@@ -24,13 +24,54 @@ __device__ inline d4 mfma4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Quadrature points per staged chunk of the basis tables: all of them when the
+// (1 + D) tables of NB columns fit in 64 KB, else the largest multiple of 4 that does.
+template <int D, int NCT>
+__host__ __device__ inline int table_chunk(int Nq4) {
+  const int per_point = (1 + D) * 16 * NCT * 8;
+  int qc = (64 * 1024 / per_point) & ~3;
+  return qc >= Nq4 ? Nq4 : qc;
+}
+
+// Dynamic LDS of the kernel in doubles: the larger of the volume phase (staged
+// tables + a 4-point coefficient slice), the gradient phase (tables if resident +
+// at least one Np x Np matrix) and the face phase.
+template <int D, bool VISC, int NCT>
+__host__ __device__ inline size_t contract_lds_doubles(int Np, int Nq, int Nfq, int Nfp, int fsize) {
+  constexpr int M = D + 2;
+  const int Nq4 = (Nq + 3) & ~3;
+  const int QC = table_chunk<D, NCT>(Nq4);
+  const size_t tables = (size_t)(1 + D) * QC * 16 * NCT;
+  const size_t cs = (size_t)(M * M + M * D * M + (VISC ? M * D * M * D : 0));
+  size_t total = tables + 4 * cs;
+  const size_t facew = (size_t)Nfq * fsize + (size_t)Nfq * Nfp * Nfp + (size_t)Nfq * Nfp;
+  if (facew > total) total = facew;
+  if (VISC) {
+    const size_t held = QC >= Nq4 ? tables : 0;
+    if (held + (size_t)Np * Np > total) total = held + (size_t)Np * Np;
+  }
+  return total;
+}
+
+// Gradient and mass matrices formed per pass (as many as fit in the LDS beside
+// resident tables).
+template <int D, bool VISC, int NCT>
+__host__ __device__ inline int grad_group(int Np, int Nq, int Nfq, int Nfp, int fsize) {
+  const int Nq4 = (Nq + 3) & ~3;
+  const int QC = table_chunk<D, NCT>(Nq4);
+  const size_t held = QC >= Nq4 ? (size_t)(1 + D) * QC * 16 * NCT : 0;
+  const size_t avail = contract_lds_doubles<D, VISC, NCT>(Np, Nq, Nfq, Nfp, fsize) - held;
+  const size_t jg = avail / ((size_t)Np * Np);
+  return jg > (size_t)(D + 1) ? D + 1 : (int)jg;
+}
+
 // NTH threads per workgroup (256, 512 or 1024; chosen per plan, default 1024).
 template <int D, bool VISC, int NCT, int NTH>
 __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec) {
   constexpr int NT = NTH;
   constexpr int M = D + 2;
   constexpr int G = VISC ? M + M * D : M;   // column groups
-  constexpr int RT = (NCT == 1) ? (NTH >= 1024 ? 8 : 16) : (NTH >= 1024 ? 4 : 8);   // row tiles per wave per pass
+  constexpr int RT = (NCT == 1) ? (NTH >= 1024 ? 8 : 16) : (NCT == 2 ? (NTH >= 1024 ? 4 : 8) : (NTH >= 1024 ? 2 : 4));
   extern __shared__ double lds[];
   const int el = blockIdx.x, e = e0 + el;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -49,17 +90,28 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   const int *fnodes = P.fnodes;
   const int *fbc = P.face_bc + (size_t)e * nf;
 
-  // LDS: basis tables (zero-padded to Nq4 points, 16*NCT basis functions)
+  // LDS: basis tables of QC quadrature points at a time (zero-padded, 16*NCT basis
+  // functions).  When all Nq4 points fit (QC == Nq4) the tables stay resident for
+  // the later phases; otherwise those phases read the global tables.
   const int NB = 16 * NCT;
-  double *sphi = lds;                          // [Nq4][NB]
-  double *sdphi = sphi + Nq4 * NB;             // [D][Nq4][NB]
-  double *work = sdphi + D * Nq4 * NB;         // shared scratch
-  for (int t = tid; t < (1 + D) * Nq4 * NB; t += NT) {
-    const int b = t % NB, qp = (t / NB) % Nq4, r = t / (NB * Nq4);
-    double val = 0.0;
-    if (b < Np && qp < Nq) val = (r == 0) ? P.phi[qp * Np + b] : P.dphi[((size_t)(r - 1) * Nq + qp) * Np + b];
-    sphi[t] = val;
-  }
+  const int QC = table_chunk<D, NCT>(Nq4);
+  const bool resident = QC >= Nq4;
+  double *sphi = lds;                          // [QC][NB]
+  double *sdphi = sphi + QC * NB;              // [D][QC][NB]
+  double *work = sdphi + D * QC * NB;          // shared scratch
+  auto stage = [&](int qc) {
+    for (int t = tid; t < (1 + D) * QC * NB; t += NT) {
+      const int b = t % NB, qq = (t / NB) % QC, r = t / (NB * QC), qp = qc + qq;
+      double val = 0.0;
+      if (b < Np && qp < Nq) val = (r == 0) ? P.phi[qp * Np + b] : P.dphi[((size_t)(r - 1) * Nq + qp) * Np + b];
+      sphi[t] = val;
+    }
+  };
+  auto PHI = [&](int qp, int a) { return resident ? sphi[qp * NB + a] : P.phi[qp * Np + a]; };
+  auto DPHI = [&](int r, int qp, int a) {
+    return resident ? sdphi[(r * QC + qp) * NB + a] : P.dphi[((size_t)r * Nq + qp) * Np + a];
+  };
+  if (resident) stage(0);
   // zero fill: q rows and padding of A, X, C, D, R_tr
   const int nv = M * Np;
   for (size_t i = tid; i < (size_t)np * np; i += NT) {
@@ -84,6 +136,10 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = d4{0.0, 0.0, 0.0, 0.0};
     for (int q0 = 0; q0 < Nq4; q0 += 4) {
+      if (!resident && q0 % QC == 0) {
+        __syncthreads();
+        stage(q0);
+      }
       __syncthreads();
       for (int t = tid; t < 4 * CS; t += NT) {
         const int j = t % CS, qq = t / CS;
@@ -98,6 +154,7 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
       }
       __syncthreads();
       const int qp = q0 + lk;
+      const int ql = resident ? qp : qp % QC;   // row of the staged tables
       const double *cq = coef + lk * CS;
 #pragma unroll
       for (int u = 0; u < RT; ++u) {
@@ -107,18 +164,18 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
         if (tile < ntiles && rho < nrows) {
           const int a = rho % Np, c = (rho / Np) % M, g = rho / (Np * M);
           if (g < M) {
-            tval = cq[c * M + g] * sphi[qp * NB + a];
+            tval = cq[c * M + g] * sphi[ql * NB + a];
 #pragma unroll
-            for (int r = 0; r < D; ++r) tval += cq[M * M + (c * D + r) * M + g] * sdphi[(r * Nq4 + qp) * NB + a];
+            for (int r = 0; r < D; ++r) tval += cq[M * M + (c * D + r) * M + g] * sdphi[(r * QC + ql) * NB + a];
           } else {
             const int s = g - M;
 #pragma unroll
             for (int r = 0; r < D; ++r)
-              tval += cq[M * M + M * D * M + (c * D + r) * (M * D) + s] * sdphi[(r * Nq4 + qp) * NB + a];
+              tval += cq[M * M + M * D * M + (c * D + r) * (M * D) + s] * sdphi[(r * QC + ql) * NB + a];
           }
         }
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = mfma4(tval, sphi[qp * NB + ct * 16 + li], acc[u][ct]);
+        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = mfma4(tval, sphi[ql * NB + ct * 16 + li], acc[u][ct]);
       }
     }
     // write the tiles: rows rho = (g, c, a), columns b
@@ -140,34 +197,46 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   }
   __syncthreads();
 
-  // ---- gradient rows: G_j[a][b] = sum W dphi_j,a phi_b (physical), M[a][b] = sum W phi_a phi_b
+  // ---- gradient rows: G_j[a][b] = sum W dphi_j,a phi_b (physical), M[a][b] = sum W phi_a phi_b,
+  // one matrix at a time (j = 0..D-1 gradients, j = D mass)
   if (VISC) {
-    double *gm = work;   // [(D+1)][Np][Np]
-    for (int t = tid; t < (D + 1) * Np * Np; t += NT) {
-      const int b = t % Np, a = (t / Np) % Np, j = t / (Np * Np);
-      double acc = 0.0;
-      for (int qp = 0; qp < Nq; ++qp) {
-        const double *w = pv + (size_t)qp * L.size;
-        if (j < D) {
-          double ta = 0.0;
+    const int JG = grad_group<D, VISC, NCT>(Np, Nq, Nfq, Nfp, L.fsize);
+    double *gm = resident ? work : lds;   // [JG][Np][Np]
+    for (int j0 = 0; j0 <= D; j0 += JG) {
+      const int nj = (D + 1 - j0) < JG ? (D + 1 - j0) : JG;
+      for (int t = tid; t < nj * Np * Np; t += NT) {
+        const int b = t % Np, a = (t / Np) % Np, j = j0 + t / (Np * Np);
+        double acc = 0.0;
+        for (int qp = 0; qp < Nq; ++qp) {
+          const double *w = pv + (size_t)qp * L.size;
+          if (j < D) {
+            double ta = 0.0;
 #pragma unroll
-          for (int r = 0; r < D; ++r) ta += w[L.WJ + r * D + j] * sdphi[(r * Nq4 + qp) * NB + a];
-          acc += ta * sphi[qp * NB + b];
+            for (int r = 0; r < D; ++r) ta += w[L.WJ + r * D + j] * DPHI(r, qp, a);
+            acc += ta * PHI(qp, b);
+          } else {
+            acc += w[L.W] * PHI(qp, a) * PHI(qp, b);
+          }
+        }
+        gm[t] = acc;
+      }
+      __syncthreads();
+      // G_j into the (q_j, v) block, the mass matrix into every (q_j, q_j) block
+      for (int t = tid; t < M * nj * Np * Np; t += NT) {
+        const int a = t % Np, b = (t / Np) % Np, jl = (t / (Np * Np)) % nj, c = t / (nj * Np * Np);
+        const int j = j0 + jl;
+        const double val = gm[(jl * Np + a) * Np + b];
+        if (j < D) {
+          A[(size_t)(c * Np + b) * np + nv + (c * D + j) * Np + a] = val;
         } else {
-          acc += w[L.W] * sphi[qp * NB + a] * sphi[qp * NB + b];
+          for (int jj = 0; jj < D; ++jj) {
+            const int cj = c * D + jj;
+            A[(size_t)(nv + cj * Np + b) * np + nv + cj * Np + a] = val;
+          }
         }
       }
-      gm[t] = acc;
+      __syncthreads();
     }
-    __syncthreads();
-    for (int t = tid; t < M * D * Np * Np; t += NT) {
-      const int a = t % Np, b = (t / Np) % Np, cj = t / (Np * Np);
-      const int c = cj / D, j = cj % D;
-      const int row = nv + cj * Np + a;
-      A[(size_t)(c * Np + b) * np + row] = gm[(j * Np + a) * Np + b];
-      A[(size_t)(nv + cj * Np + b) * np + row] = gm[(D * Np + a) * Np + b];
-    }
-    __syncthreads();
   }
 
   // ---- element residual rows (column k_pad of X): volume parts
@@ -177,9 +246,9 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
     double acc = 0.0;
     for (int qp = 0; qp < Nq; ++qp) {
       const double *w = pv + (size_t)qp * L.size;
-      double ta = w[L.Wu + c] * sphi[qp * NB + a];
+      double ta = w[L.Wu + c] * PHI(qp, a);
 #pragma unroll
-      for (int r = 0; r < D; ++r) ta += w[L.Fr + c * D + r] * sdphi[(r * Nq4 + qp) * NB + a];
+      for (int r = 0; r < D; ++r) ta += w[L.Fr + c * D + r] * DPHI(r, qp, a);
       acc += ta;
     }
     R[c * Np + a] = acc;
@@ -192,8 +261,8 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
         const double *w = pv + (size_t)qp * L.size;
         double ta = 0.0;
 #pragma unroll
-        for (int r = 0; r < D; ++r) ta += w[L.WJ + r * D + j] * sdphi[(r * Nq4 + qp) * NB + a];
-        acc += w[L.Wq + c * D + j] * sphi[qp * NB + a] + w[L.v + c] * ta;
+        for (int r = 0; r < D; ++r) ta += w[L.WJ + r * D + j] * DPHI(r, qp, a);
+        acc += w[L.Wq + c * D + j] * PHI(qp, a) + w[L.v + c] * ta;
       }
       R[nv + cj * Np + a] = acc;
     }
@@ -203,7 +272,7 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   // ---- faces, one at a time (A entries of edge nodes receive several faces)
   const int MF = M * Nfp;
   const int NP2 = Nfp * Nfp;
-  double *spf = work;                           // [Nfq][fsize]
+  double *spf = lds;                            // [Nfq][fsize] (tables no longer needed)
   double *spp = spf + Nfq * L.fsize;            // [Nfq][Nfp][Nfp]
   double *sps = spp + Nfq * NP2;                // [Nfq][Nfp]
   for (int f = 0; f < nf; ++f) {
@@ -287,16 +356,7 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
 
 template <int D, bool VISC, int NCT>
 size_t lds_bytes_t(const DevPlan &P) {
-  constexpr int M = D + 2;
-  const int Nq4 = (P.Nq + 3) & ~3;
-  const int NB = 16 * NCT;
-  const size_t tables = (size_t)(1 + D) * Nq4 * NB;
-  const size_t cs = (size_t)(M * M + M * D * M + (VISC ? M * D * M * D : 0));
-  size_t work = 4 * cs;
-  if (VISC) work = work > (size_t)(D + 1) * P.Np * P.Np ? work : (size_t)(D + 1) * P.Np * P.Np;
-  const size_t facew = (size_t)P.Nfq * P.L.fsize + (size_t)P.Nfq * P.Nfp * P.Nfp + (size_t)P.Nfq * P.Nfp;
-  if (facew > work) work = facew;
-  return (tables + work) * sizeof(double);
+  return contract_lds_doubles<D, VISC, NCT>(P.Np, P.Nq, P.Nfq, P.Nfp, P.L.fsize) * sizeof(double);
 }
 
 template <int D, bool VISC, int NCT, int NTH>
@@ -317,13 +377,24 @@ hipError_t launch_t(const DevPlan &P, int e0, int ec, hipStream_t s) {
 
 template <int D, bool VISC>
 size_t lds_for(const DevPlan &P) {
-  return P.Np <= 16 ? lds_bytes_t<D, VISC, 1>(P) : lds_bytes_t<D, VISC, 2>(P);
+  if (P.Np <= 16) return lds_bytes_t<D, VISC, 1>(P);
+  if (P.Np <= 32) return lds_bytes_t<D, VISC, 2>(P);
+  if (P.Np <= 48) return lds_bytes_t<D, VISC, 3>(P);
+  return lds_bytes_t<D, VISC, 4>(P);
+}
+
+template <int D, bool VISC>
+hipError_t launch_dv(const DevPlan &P, int e0, int ec, hipStream_t s) {
+  if (P.Np <= 16) return launch_t<D, VISC, 1>(P, e0, ec, s);
+  if (P.Np <= 32) return launch_t<D, VISC, 2>(P, e0, ec, s);
+  if (P.Np <= 48) return launch_t<D, VISC, 3>(P, e0, ec, s);
+  return launch_t<D, VISC, 4>(P, e0, ec, s);
 }
 
 }  // namespace
 
 bool contract_mfma_supported(const DevPlan &P) {
-  if (P.Np > 32) return false;
+  if (P.Np > 64) return false;
   size_t lds = 0;
   if (P.dim == 2) lds = P.viscous ? lds_for<2, true>(P) : lds_for<2, false>(P);
   else lds = P.viscous ? lds_for<3, true>(P) : lds_for<3, false>(P);
@@ -331,13 +402,8 @@ bool contract_mfma_supported(const DevPlan &P) {
 }
 
 hipError_t launch_contract_mfma(const DevPlan &P, int e0, int ec, hipStream_t s) {
-  const bool one = P.Np <= 16;
-  if (P.dim == 2) {
-    if (P.viscous) return one ? launch_t<2, true, 1>(P, e0, ec, s) : launch_t<2, true, 2>(P, e0, ec, s);
-    return one ? launch_t<2, false, 1>(P, e0, ec, s) : launch_t<2, false, 2>(P, e0, ec, s);
-  }
-  if (P.viscous) return one ? launch_t<3, true, 1>(P, e0, ec, s) : launch_t<3, true, 2>(P, e0, ec, s);
-  return one ? launch_t<3, false, 1>(P, e0, ec, s) : launch_t<3, false, 2>(P, e0, ec, s);
+  if (P.dim == 2) return P.viscous ? launch_dv<2, true>(P, e0, ec, s) : launch_dv<2, false>(P, e0, ec, s);
+  return P.viscous ? launch_dv<3, true>(P, e0, ec, s) : launch_dv<3, false>(P, e0, ec, s);
 }
 
 }  // namespace hdg
