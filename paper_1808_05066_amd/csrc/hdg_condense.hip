@@ -10,9 +10,10 @@
 // * LU (left-looking): block J is gathered through the current row permutation,
 //   updated by all previous blocks (unit-lower triangle solves and MFMA
 //   updates), then factored in LDS with partial pivoting.  Factored columns are
-//   stored in pivot-position order; a row interchange in a later panel is also
-//   applied to the stored columns of the earlier panels (as LAPACK's laswp),
-//   which keeps every later read of the factors contiguous.
+//   stored in pivot-position order; the row interchanges of a later panel are
+//   also applied to the stored columns of the earlier panels (as LAPACK's laswp,
+//   once per panel as one row movement), which keeps every later read of the
+//   factors contiguous.
 // * Right-hand sides [B | R_loc] in blocks of 32 columns: permutation gather,
 //   forward and backward substitution against the stored factors, then the
 //   Schur product C * Y_block straight from LDS into S and g.
@@ -62,21 +63,43 @@ template <> struct Mfma<float> {
 template <typename T>
 struct Lds {
   T *blk;        // [np][BS]
-  T *prow;       // [W] pivot row
-  T *tmp;        // [W] displaced row
+  T *crow;       // [2][NW + 1][8] pivot candidate rows and diagonal row, by column parity
   int *perm;     // [np]
   T *redv;       // [2][NW]
   int *redi;     // [2][NW]
   double *dsc;   // [np] symmetric scaling (low-precision path only)
+  int *invb;     // [np] original row -> position before the current panel
+  int *mvx;      // [2W] positions changed by the panel's interchanges
+  int *mvy;      // [2W] position each of them takes its value from
+  int *mvn;      // [1] number of changed positions
 };
 
-// blk[i][c] = M[(c0 + c) * ld + perm[i]]  (gathered through the permutation)
+// blk[i][c] = M[(c0 + c) * ld + perm[i]]  (gathered through the permutation;
+// each thread keeps LU loads in flight before writing them to LDS)
+constexpr int LU = 8;
+
 template <typename T, int W>
 __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, int np) {
   constexpr int BS = W + 1;
-  for (int t = threadIdx.x; t < np * W; t += NT) {
-    const int c = t / np, i = t - c * np;
-    s.blk[i * BS + c] = M[(size_t)(c0 + c) * ld + s.perm[i]];
+  const int total = np * W;
+  for (int t0 = threadIdx.x; t0 < total; t0 += LU * NT) {
+    T v[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int t = t0 + u * NT;
+      if (t < total) {
+        const int c = t / np, i = t - c * np;
+        v[u] = M[(size_t)(c0 + c) * ld + s.perm[i]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int t = t0 + u * NT;
+      if (t < total) {
+        const int c = t / np, i = t - c * np;
+        s.blk[i * BS + c] = v[u];
+      }
+    }
   }
 }
 
@@ -85,12 +108,27 @@ __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, i
 template <typename T, int W>
 __device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int ld, int c0, int np, bool colscale) {
   constexpr int BS = W + 1;
-  for (int t = threadIdx.x; t < np * W; t += NT) {
-    const int c = t / np, i = t - c * np;
-    const int pi = s.perm[i];
-    double x = M[(size_t)(c0 + c) * ld + pi] * s.dsc[pi];
-    if (colscale) x *= s.dsc[c0 + c];
-    s.blk[i * BS + c] = (T)x;
+  const int total = np * W;
+  for (int t0 = threadIdx.x; t0 < total; t0 += LU * NT) {
+    double v[LU];
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int t = t0 + u * NT;
+      if (t < total) {
+        const int c = t / np, i = t - c * np;
+        v[u] = M[(size_t)(c0 + c) * ld + s.perm[i]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < LU; ++u) {
+      const int t = t0 + u * NT;
+      if (t < total) {
+        const int c = t / np, i = t - c * np;
+        double x = v[u] * s.dsc[s.perm[i]];
+        if (colscale) x *= s.dsc[c0 + c];
+        s.blk[i * BS + c] = (T)x;
+      }
+    }
   }
 }
 
@@ -257,17 +295,70 @@ __device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int 
   }
 }
 
+// Wave-wide reductions on the DPP network: within each row of 16 lanes by quad
+// permutations and row rotations (every lane ends with its row's result), then
+// across the four rows by reading lanes 0, 16, 32, 48.  All 64 lanes must be active.
+template <int CTRL>
+__device__ inline int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline double dpp_val(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)dpp_i32<CTRL>((int)(unsigned)u);
+  const unsigned hi = (unsigned)dpp_i32<CTRL>((int)(unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+template <int CTRL>
+__device__ inline float dpp_val(float v) {
+  return __builtin_bit_cast(float, dpp_i32<CTRL>(__builtin_bit_cast(int, v)));
+}
+__device__ inline double lane_val(double v, int l) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ inline float lane_val(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+constexpr int DPP_QUAD_1032 = 0xB1, DPP_QUAD_2301 = 0x4E, DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR8 = 0x128;
+
+template <typename T>
+__device__ inline T wave_max(T v) {
+  v = fmax(v, dpp_val<DPP_QUAD_1032>(v));
+  v = fmax(v, dpp_val<DPP_QUAD_2301>(v));
+  v = fmax(v, dpp_val<DPP_ROW_ROR4>(v));
+  v = fmax(v, dpp_val<DPP_ROW_ROR8>(v));
+  return fmax(fmax(lane_val(v, 0), lane_val(v, 16)), fmax(lane_val(v, 32), lane_val(v, 48)));
+}
+__device__ inline int wave_min(int v) {
+  v = min(v, dpp_i32<DPP_QUAD_1032>(v));
+  v = min(v, dpp_i32<DPP_QUAD_2301>(v));
+  v = min(v, dpp_i32<DPP_ROW_ROR4>(v));
+  v = min(v, dpp_i32<DPP_ROW_ROR8>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
 // LU with partial pivoting of block rows j0..np-1 (block columns 0..W-1), in
 // sub-panels of 8 columns.  Inside a sub-panel thread t keeps the 8 entries of
-// row j0+t in registers (its rows j0+t+NT, j0+t+2NT, ... stay in LDS); per column the pivot is found by wave shuffles plus one
-// exchange through LDS, the pivot row is published and whole rows are swapped
-// in LDS: two barriers per column.  After a sub-panel, its 8 pivot rows are
-// solved against the remaining columns (unit-lower 8 x 8) and the rows below
-// receive the rank-8 update.
+// row j0+t in registers (its rows j0+t+NT, j0+t+2NT, ... stay in LDS).  One
+// barrier per column: each wave reduces its pivot candidates (largest magnitude,
+// lowest row among equal ones) on the DPP network and publishes the winner's
+// value, row index and 8 sub-panel entries, next to the entries of the diagonal
+// row; after the barrier every wave reduces the NW winners the same way and
+// applies the interchange and the rank-1 update to its own rows (the interchanges
+// of the columns outside the sub-panel and of perm wait for the sub-panel's
+// end, where they are applied as one row movement).  The publication slots are
+// double-buffered by column parity, so the next column's writes cannot overtake
+// this column's reads.  After a sub-panel, its 8 pivot rows are solved against
+// the remaining columns (unit-lower 8 x 8) and the rows below receive the
+// rank-8 update.
 constexpr int SPW = 8;   // sub-panel width
 
 template <typename T, int W>
-__device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T *tmprow, T *Fm, int ld) {
+__device__ inline bool panel_factor(const Lds<T> &s, int j0, int np) {
   constexpr int BS = W + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = j0 + tid, r1 = j0 + tid + NT;   // rows r1, r1 + NT, ... stay in LDS
@@ -276,19 +367,20 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
   bool singular = false;
   for (int cs = 0; cs < W; cs += SPW) {
     T x0[SPW];
+    int pivs[SPW];
 #pragma unroll
     for (int c = 0; c < SPW; ++c) x0[c] = has0 ? y0[cs + c] : T(0);
+#pragma unroll
     for (int jj = 0; jj < SPW; ++jj) {
       const int col = cs + jj;
-      const int r = j0 + col;
-      T v0 = T(0);
-#pragma unroll
-      for (int c = 0; c < SPW; ++c)
-        if (c == jj) v0 = x0[c];
+      const int r = j0 + col;   // diagonal row, always thread col's register row
+      const int b = jj & 1;
+      T *crow = s.crow + b * (NW + 1) * SPW;   // [NW candidate rows | diagonal row][SPW]
+      // this thread's candidate
       T best = T(-1);
       int bi = np;
       if (has0 && r0 >= r) {
-        best = fabs(v0);
+        best = fabs(x0[jj]);
         bi = r0;
       }
       for (int rr = r1; rr < np; rr += NT) {
@@ -298,103 +390,108 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
           bi = rr;
         }
       }
+      const T wm = wave_max(best);
+      const int wi = wave_min(best == wm ? bi : INT_MAX);
+      if (best >= T(0) && best == wm && bi == wi) {
+        T v[SPW];
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const T ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
+        for (int c = 0; c < SPW; ++c) v[c] = (bi == r0) ? x0[c] : s.blk[(size_t)bi * BS + cs + c];
+        T *dst = crow + wave * SPW;
+#pragma unroll
+        for (int c = 0; c < SPW; ++c) dst[c] = v[c];
       }
-      T *rv = s.redv + (col & 1) * NW;
-      int *ri = s.redi + (col & 1) * NW;
       if (lane == 0) {
-        rv[wave] = best;
-        ri[wave] = bi;
+        s.redv[b * NW + wave] = wm;
+        s.redi[b * NW + wave] = wi;
+      }
+      if (tid == col) {
+#pragma unroll
+        for (int c = 0; c < SPW; ++c) crow[NW * SPW + c] = x0[c];
       }
       __syncthreads();
-      best = rv[0];
-      bi = ri[0];
-#pragma unroll
-      for (int w2 = 1; w2 < NW; ++w2) {
-        const T ob = rv[w2];
-        const int oi = ri[w2];
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
+      // global pivot over the waves' winners (lanes 0..NW-1 of every wave),
+      // largest magnitude, lowest row among equal ones
+      T cv = T(-1);
+      int ci = INT_MAX;
+      if (lane < NW) {
+        cv = s.redv[b * NW + lane];
+        ci = s.redi[b * NW + lane];
       }
-      const bool zero = !(best > T(0));
+      const T pv = wave_max(cv);
+      const int pi = wave_min(cv == pv ? ci : INT_MAX);
+      const unsigned long long hit = __ballot(lane < NW && cv == pv && ci == pi);
+      const bool zero = !(pv > T(0)) || hit == 0 || pi < r || pi >= np;   // (only the first can fire)
       singular |= zero;
-      const int piv = zero ? r : bi;
-      // pivot row entries of this sub-panel -> prow; if rows move, the register
-      // part of row r -> tmprow and the LDS columns outside the sub-panel swap.
-      if (has0 && r0 == piv) {
+      const int piv = zero ? r : pi;
+      pivs[jj] = piv;
+      const T *pr = crow + (zero ? NW : (int)__builtin_ctzll(hit)) * SPW;
+      const T *dr = crow + NW * SPW;
+      T prow[SPW], drow[SPW];
 #pragma unroll
-        for (int c = 0; c < SPW; ++c) prow[c] = x0[c];
+      for (int c = 0; c < SPW; ++c) {
+        prow[c] = pr[c];
+        drow[c] = dr[c];
       }
-      const bool own_lds = piv >= r1 && (piv - r1) % NT == 0;   // this thread's LDS row
-      if (own_lds) {
-#pragma unroll
-        for (int c = 0; c < SPW; ++c) prow[c] = s.blk[(size_t)piv * BS + cs + c];
-      }
-      if (piv != r) {
-        if (has0 && r0 == r) {
-#pragma unroll
-          for (int c = 0; c < SPW; ++c) tmprow[c] = x0[c];
-        }
-        if (tid < W && (tid < cs || tid >= cs + SPW)) {
-          const T t0 = s.blk[r * BS + tid];
-          s.blk[r * BS + tid] = s.blk[piv * BS + tid];
-          s.blk[piv * BS + tid] = t0;
-        }
-        if (tid == W) {
-          const int t0 = s.perm[r];
-          s.perm[r] = s.perm[piv];
-          s.perm[piv] = t0;
-        }
-        // the interchange also applies to the stored columns of the earlier panels
-        for (int c = tid; c < j0; c += NT) {
-          T *col = Fm + (size_t)c * ld;
-          const T t0 = col[r];
-          col[r] = col[piv];
-          col[piv] = t0;
-        }
-      }
-      __syncthreads();
       if (piv != r) {
         if (has0 && r0 == piv) {
 #pragma unroll
-          for (int c = 0; c < SPW; ++c) x0[c] = tmprow[c];
+          for (int c = 0; c < SPW; ++c) x0[c] = drow[c];
         } else if (has0 && r0 == r) {
 #pragma unroll
           for (int c = 0; c < SPW; ++c) x0[c] = prow[c];
         }
-        if (own_lds) {
+        if (piv >= r1 && (piv - r1) % NT == 0) {   // this thread's LDS row
 #pragma unroll
-          for (int c = 0; c < SPW; ++c) s.blk[(size_t)piv * BS + cs + c] = tmprow[c];
+          for (int c = 0; c < SPW; ++c) s.blk[(size_t)piv * BS + cs + c] = drow[c];
         }
       }
       if (!zero) {
         const T inv = T(1) / prow[jj];
         if (has0 && r0 > r) {
-          T l0 = T(0);
+          const T l0 = x0[jj] * inv;
+          x0[jj] = l0;
 #pragma unroll
-          for (int c = 0; c < SPW; ++c)
-            if (c == jj) l0 = x0[c] * inv;
-#pragma unroll
-          for (int c = 0; c < SPW; ++c) {
-            if (c == jj) x0[c] = l0;
-            else if (c > jj) x0[c] -= l0 * prow[c];
-          }
+          for (int c = jj + 1; c < SPW; ++c) x0[c] -= l0 * prow[c];
         }
         for (int rr = r1; rr < np; rr += NT) {
           T *y1 = s.blk + (size_t)rr * BS;
           const T l1 = y1[col] * inv;
           y1[col] = l1;
+#pragma unroll
           for (int c = jj + 1; c < SPW; ++c) y1[cs + c] -= l1 * prow[c];
         }
+      }
+    }
+    // the sub-panel's interchanges on the block columns outside it and on perm:
+    // position x receives the row of position t_0(t_1(...t_7(x))) (t_jj the
+    // transposition of rows j0+cs+jj and pivs[jj]); all reads before the writes
+    {
+      constexpr int NOUT = W - SPW;
+      const int m = tid / (NOUT + 1), cc = tid % (NOUT + 1);
+      int x = -1, y = -1, c = 0;
+      T val = T(0);
+      int pval = 0;
+      if (m < 2 * SPW) {
+        x = j0 + cs + m;
+#pragma unroll
+        for (int q = 0; q < SPW; ++q)
+          if (m == SPW + q) x = pivs[q];
+        y = x;
+#pragma unroll
+        for (int q = SPW - 1; q >= 0; --q) {
+          const int rq = j0 + cs + q;
+          y = (y == rq) ? pivs[q] : (y == pivs[q] ? rq : y);
+        }
+        c = cc < cs ? cc : cc + SPW;
+        if (y != x) {
+          if (cc < NOUT) val = s.blk[(size_t)y * BS + c];
+          else pval = s.perm[y];
+        }
+      }
+      __syncthreads();
+      if (y != x) {
+        if (cc < NOUT) s.blk[(size_t)x * BS + c] = val;
+        else s.perm[x] = pval;
       }
     }
     if (has0) {
@@ -418,16 +515,21 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
         for (int i = 0; i < SPW; ++i) s.blk[(rp + i) * BS + c] = u[i];
       }
       __syncthreads();
-      // rank-8 update of the rows below
+      // rank-8 update of the rows below, 4 columns at a time
       for (int i = rp + SPW + tid; i < np; i += NT) {
         T l[SPW];
 #pragma unroll
         for (int k = 0; k < SPW; ++k) l[k] = s.blk[i * BS + cs + k];
-        for (int c = cs + SPW; c < W; ++c) {
-          T acc = s.blk[i * BS + c];
+        for (int c = cs + SPW; c < W; c += 4) {
+          T acc[4];
 #pragma unroll
-          for (int k = 0; k < SPW; ++k) acc -= l[k] * s.blk[(rp + k) * BS + c];
-          s.blk[i * BS + c] = acc;
+          for (int q = 0; q < 4; ++q) acc[q] = s.blk[i * BS + c + q];
+#pragma unroll
+          for (int k = 0; k < SPW; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] -= l[k] * s.blk[(rp + k) * BS + c + q];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) s.blk[i * BS + c + q] = acc[q];
         }
       }
       __syncthreads();
@@ -436,9 +538,49 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np, T *prow, T 
   return singular;
 }
 
+// Positions x >= j0 whose row changed in the panel just factored, with the
+// position y the row came from (perm after the panel vs. invb, the inverse of perm
+// before it); at most 2W of them.
+template <typename T>
+__device__ inline void moved_rows(const Lds<T> &s, int j0, int np) {
+  for (int x = j0 + threadIdx.x; x < np; x += NT) {
+    const int y = s.invb[s.perm[x]];
+    if (y != x) {
+      const int k = atomicAdd(s.mvn, 1);
+      s.mvx[k] = x;
+      s.mvy[k] = y;
+    }
+  }
+}
+
+// The same row movement on the stored factor columns 0..j0-1:
+// col[mvx[i]] <- col[mvy[i]] (all reads of a group of columns before its writes).
+template <typename T>
+__device__ inline void move_rows(const Lds<T> &s, T *Fm, int ld, int j0) {
+  constexpr int U = 8;    // values per thread and group
+  const int m = *s.mvn;
+  if (m == 0) return;
+  const int cg = (NT * U) / m;   // whole columns per group (m <= 2W <= 64)
+  for (int c0 = 0; c0 < j0; c0 += cg) {
+    const int items = (j0 - c0 < cg ? j0 - c0 : cg) * m;
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = threadIdx.x + u * NT;
+      if (i < items) v[u] = Fm[(size_t)(c0 + i / m) * ld + s.mvy[i % m]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = threadIdx.x + u * NT;
+      if (i < items) Fm[(size_t)(c0 + i / m) * ld + s.mvx[i % m]] = v[u];
+    }
+  }
+}
+
 // LDS carve-up of k_condense_t (byte offsets, 16-byte aligned parts).
 struct LdsLayout {
-  size_t blk, prow, tmp, perm, redv, redi, dsc, total;
+  size_t blk, crow, perm, redv, redi, dsc, invb, mv, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -448,10 +590,8 @@ __host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp, i
   size_t o = 0;
   L.blk = o;
   o = al16(o + (size_t)np * (W + 1) * tsize);
-  L.prow = o;
-  o = al16(o + W * tsize);
-  L.tmp = o;
-  o = al16(o + W * tsize);
+  L.crow = o;
+  o = al16(o + 2 * (NW + 1) * 8 * tsize);
   L.perm = o;
   o = al16(o + (size_t)np * sizeof(int));
   L.redv = o;
@@ -460,6 +600,10 @@ __host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp, i
   o = al16(o + 2 * NW * sizeof(int));
   L.dsc = o;
   o = al16(o + (lp ? (size_t)np * sizeof(double) : 0));
+  L.invb = o;
+  o = al16(o + (size_t)np * sizeof(int));
+  L.mv = o;
+  o = al16(o + (4 * WMAX + 1) * sizeof(int));
   L.total = o;
   return L;
 }
@@ -490,12 +634,15 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
   const LdsLayout Lo = lds_layout(np, sizeof(T), LP, W);
   Lds<T> s;
   s.blk = reinterpret_cast<T *>(sm + Lo.blk);
-  s.prow = reinterpret_cast<T *>(sm + Lo.prow);
-  s.tmp = reinterpret_cast<T *>(sm + Lo.tmp);
+  s.crow = reinterpret_cast<T *>(sm + Lo.crow);
   s.perm = reinterpret_cast<int *>(sm + Lo.perm);
   s.redv = reinterpret_cast<T *>(sm + Lo.redv);
   s.redi = reinterpret_cast<int *>(sm + Lo.redi);
   s.dsc = LP ? reinterpret_cast<double *>(sm + Lo.dsc) : nullptr;
+  s.invb = reinterpret_cast<int *>(sm + Lo.invb);
+  s.mvx = reinterpret_cast<int *>(sm + Lo.mv);
+  s.mvy = s.mvx + 2 * WMAX;
+  s.mvn = s.mvy + 2 * WMAX;
   // factor storage and inverses of the diagonal blocks ([nJ][2][W][W])
   T *Fm;
   T *Ie;
@@ -530,10 +677,19 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
     __syncthreads();
     if (J > 0)
       run_steps<T, W>(s, Ie, Fm, np, J, [&](int i) { return Step{i * 2 * W * W, i * W, i * W + W, np}; });
-    singular |= panel_factor<T, W>(s, j0, np, s.prow, s.tmp, Fm, np);
+    if (J > 0) {
+      for (int x = j0 + tid; x < np; x += NT) s.invb[s.perm[x]] = x;
+      if (tid == 0) *s.mvn = 0;
+    }
+    singular |= panel_factor<T, W>(s, j0, np);
     __syncthreads();
+    if (J > 0) {
+      moved_rows<T>(s, j0, np);
+      __syncthreads();
+    }
     invert_diag<T, W>(s, j0, Ie + (size_t)J * 2 * W * W, Ie + (size_t)J * 2 * W * W + W * W);
     store_block<T, W>(s, Fm, np, j0, np);
+    if (J > 0) move_rows<T>(s, Fm, np, j0);
     __syncthreads();
   }
   if constexpr (LP) {

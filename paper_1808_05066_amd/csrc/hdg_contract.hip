@@ -35,7 +35,7 @@ __host__ __device__ inline int table_chunk(int Nq4) {
 
 // Dynamic LDS of the kernel in doubles: the larger of the volume phase (staged
 // tables + a 4-point coefficient slice), the gradient phase (tables if resident +
-// at least one Np x Np matrix) and the face phase.
+// a group of Np x Np matrices) and the face phase.
 template <int D, bool VISC, int NCT>
 __host__ __device__ inline size_t contract_lds_doubles(int Np, int Nq, int Nfq, int Nfp, int fsize) {
   constexpr int M = D + 2;
@@ -47,8 +47,14 @@ __host__ __device__ inline size_t contract_lds_doubles(int Np, int Nq, int Nfq, 
   const size_t facew = (size_t)Nfq * fsize + (size_t)Nfq * Nfp * Nfp + (size_t)Nfq * Nfp;
   if (facew > total) total = facew;
   if (VISC) {
+    // all D + 1 gradient/mass matrices at once when they fit in 160 KB beside
+    // resident tables (register use keeps the kernel at one workgroup per CU,
+    // so the LDS costs no occupancy), else as many as fit, at least one
     const size_t held = QC >= Nq4 ? tables : 0;
-    if (held + (size_t)Np * Np > total) total = held + (size_t)Np * Np;
+    const size_t nn = (size_t)Np * Np;
+    size_t jg = (20480 > held + nn) ? (20480 - held) / nn : 1;
+    if (jg > (size_t)(D + 1)) jg = D + 1;
+    if (held + jg * nn > total) total = held + jg * nn;
   }
   return total;
 }
