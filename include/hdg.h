@@ -122,7 +122,11 @@ int hdg_plan_dims(const hdg_plan *plan, hdg_dims *out);
 int hdg_plan_workspace_bytes(const hdg_plan *plan, size_t *bytes);
 
 /* Bind caller-owned device workspace (>= hdg_plan_workspace_bytes, 256-byte
- * aligned) and upload the tables into it (synchronous on `stream`). */
+ * aligned) and upload the tables into it (synchronous on `stream`).  The
+ * workspace belongs to the plan until it is bound again or the plan is
+ * destroyed: when all elements fit in one chunk, the plan keeps the structural
+ * zeros of its coupling blocks there between calls and clears them only on the
+ * first call after a bind. */
 int hdg_plan_bind_workspace(hdg_plan *plan, void *dev_ptr, size_t bytes, void *stream);
 
 /* Physical coordinates of the element nodes x[dim][E*Np] and of the global

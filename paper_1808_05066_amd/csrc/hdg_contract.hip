@@ -48,9 +48,10 @@ __host__ __device__ inline size_t contract_lds_doubles(int Np, int Nq, int Nfq, 
   if (facew > total) total = facew;
   if (VISC) {
     // all D + 1 gradient/mass matrices at once when they fit in 160 KB beside
-    // resident tables (register use keeps the kernel at one workgroup per CU,
-    // so the LDS costs no occupancy), else as many as fit, at least one
-    const size_t held = QC >= Nq4 ? tables : 0;
+    // resident tables and the per-point W J, W (register use keeps the kernel at
+    // one workgroup per CU, so the LDS costs no occupancy), else as many as fit,
+    // at least one
+    const size_t held = (QC >= Nq4 ? tables : 0) + (size_t)Nq * (D * D + 1);
     const size_t nn = (size_t)Np * Np;
     size_t jg = (20480 > held + nn) ? (20480 - held) / nn : 1;
     if (jg > (size_t)(D + 1)) jg = D + 1;
@@ -65,7 +66,7 @@ template <int D, bool VISC, int NCT>
 __host__ __device__ inline int grad_group(int Np, int Nq, int Nfq, int Nfp, int fsize) {
   const int Nq4 = (Nq + 3) & ~3;
   const int QC = table_chunk<D, NCT>(Nq4);
-  const size_t held = QC >= Nq4 ? (size_t)(1 + D) * QC * 16 * NCT : 0;
+  const size_t held = (QC >= Nq4 ? (size_t)(1 + D) * QC * 16 * NCT : 0) + (size_t)Nq * (D * D + 1);
   const size_t avail = contract_lds_doubles<D, VISC, NCT>(Np, Nq, Nfq, Nfp, fsize) - held;
   const size_t jg = avail / ((size_t)Np * Np);
   return jg > (size_t)(D + 1) ? D + 1 : (int)jg;
@@ -120,13 +121,16 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   if (resident) stage(0);
   // zero fill: q rows and padding of A, X, C, D, R_tr
   const int nv = M * Np;
-  for (size_t i = tid; i < (size_t)np * np; i += NT) {
-    const int col = (int)(i / np), row = (int)(i % np);
-    if (row >= nv || col >= P.n) A[i] = (row == col && row >= P.n) ? 1.0 : 0.0;
+  // (a wave per column, lanes along the rows: no index division)
+  for (int col = wave; col < np; col += NT / 64) {
+    double *Ac = A + (size_t)col * np;
+    for (int row = (col < P.n ? nv : 0) + lane; row < np; row += 64) Ac[row] = (row == col && row >= P.n) ? 1.0 : 0.0;
   }
-  for (size_t i = tid; i < (size_t)kx * np; i += NT) X[i] = 0.0;
-  for (size_t i = tid; i < (size_t)np * kp; i += NT) Cm[i] = 0.0;
-  for (size_t i = tid; i < (size_t)kp * kp; i += NT) Dm[i] = 0.0;
+  if (P.zero_xcd) {
+    for (size_t i = tid; i < (size_t)kx * np; i += NT) X[i] = 0.0;
+    for (size_t i = tid; i < (size_t)np * kp; i += NT) Cm[i] = 0.0;
+    for (size_t i = tid; i < (size_t)kp * kp; i += NT) Dm[i] = 0.0;
+  }
   for (int i = tid; i < kp; i += NT) Rt[i] = 0.0;
   __syncthreads();
 
@@ -134,51 +138,70 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   const int nrows = G * M * Np;
   const int ntiles = (nrows + 15) / 16;
   constexpr int CS = M * M + M * D * M + (VISC ? M * D * M * D : 0);  // coefficients per point
+  constexpr int CR = (4 * CS + NT - 1) / NT;                          // slice values per thread
   double *coef = work;                                                // [4][CS]
+  // the coefficient slice of points q0..q0+3, fetched into registers one slice
+  // ahead of its use so that the loads overlap the previous slice's MFMAs
+  auto fetch = [&](int q0, double (&cv)[CR]) {
+#pragma unroll
+    for (int u = 0; u < CR; ++u) {
+      const int t = tid + u * NT;
+      double val = 0.0;
+      if (t < 4 * CS) {
+        const int j = t % CS, qq = t / CS;
+        if (q0 + qq < Nq) val = pv[(size_t)(q0 + qq) * L.size + L.Mv + j];   // Mv, Kv, Kq are contiguous
+      }
+      cv[u] = val;
+    }
+  };
   for (int base = 0; base < ntiles; base += (NT / 64) * RT) {
     d4 acc[RT][NCT];
 #pragma unroll
     for (int u = 0; u < RT; ++u)
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = d4{0.0, 0.0, 0.0, 0.0};
+    // per row tile: basis function a and the coefficient offsets of row rho = (g, c, a):
+    // T = [g < M] cq[o1] phi_a + sum_r cq[o2 + r * st] dphi_{r,a}, packed in one word
+    // per tile (a: bits 0-6, o2: bits 7-18, g < M: bit 19; o1 = o2 - M * M - c * D * M
+    // + c * M is kept as the difference o2 - o1 = M * M + c * (D - 1) * M in bits 20-30)
+    int pk[RT];
+#pragma unroll
+    for (int u = 0; u < RT; ++u) {
+      const int tile = base + wave * RT + u;
+      const int rho = tile * 16 + li;
+      pk[u] = -1;
+      if (tile < ntiles && rho < nrows) {
+        const int a = rho % Np, c = (rho / Np) % M, g = rho / (Np * M);
+        if (g < M) pk[u] = a | ((M * M + c * D * M + g) << 7) | (1 << 19) | ((M * M + c * (D - 1) * M) << 20);
+        else pk[u] = a | ((M * M + M * D * M + c * D * (M * D) + (g - M)) << 7);
+      }
+    }
+    double cv[CR];
+    fetch(0, cv);
     for (int q0 = 0; q0 < Nq4; q0 += 4) {
       if (!resident && q0 % QC == 0) {
         __syncthreads();
         stage(q0);
       }
       __syncthreads();
-      for (int t = tid; t < 4 * CS; t += NT) {
-        const int j = t % CS, qq = t / CS;
-        double val = 0.0;
-        if (q0 + qq < Nq) {
-          const double *w = pv + (size_t)(q0 + qq) * L.size;
-          if (j < M * M) val = w[L.Mv + j];
-          else if (j < M * M + M * D * M) val = w[L.Kv + (j - M * M)];
-          else val = w[L.Kq + (j - M * M - M * D * M)];
-        }
-        coef[t] = val;
-      }
+#pragma unroll
+      for (int u = 0; u < CR; ++u)
+        if (tid + u * NT < 4 * CS) coef[tid + u * NT] = cv[u];
+      if (q0 + 4 < Nq4) fetch(q0 + 4, cv);
       __syncthreads();
       const int qp = q0 + lk;
       const int ql = resident ? qp : qp % QC;   // row of the staged tables
       const double *cq = coef + lk * CS;
 #pragma unroll
       for (int u = 0; u < RT; ++u) {
-        const int tile = base + wave * RT + u;
-        const int rho = tile * 16 + li;
         double tval = 0.0;
-        if (tile < ntiles && rho < nrows) {
-          const int a = rho % Np, c = (rho / Np) % M, g = rho / (Np * M);
-          if (g < M) {
-            tval = cq[c * M + g] * sphi[ql * NB + a];
+        if (pk[u] >= 0) {
+          const int a = pk[u] & 127, o2 = (pk[u] >> 7) & 4095;
+          const bool vcol = (pk[u] >> 19) & 1;
+          const int st = vcol ? M : M * D;
+          if (vcol) tval = cq[o2 - (pk[u] >> 20)] * sphi[ql * NB + a];
 #pragma unroll
-            for (int r = 0; r < D; ++r) tval += cq[M * M + (c * D + r) * M + g] * sdphi[(r * QC + ql) * NB + a];
-          } else {
-            const int s = g - M;
-#pragma unroll
-            for (int r = 0; r < D; ++r)
-              tval += cq[M * M + M * D * M + (c * D + r) * (M * D) + s] * sdphi[(r * QC + ql) * NB + a];
-          }
+          for (int r = 0; r < D; ++r) tval += cq[o2 + r * st] * sdphi[(r * QC + ql) * NB + a];
         }
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = mfma4(tval, sphi[ql * NB + ct * 16 + li], acc[u][ct]);
@@ -206,23 +229,31 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   // ---- gradient rows: G_j[a][b] = sum W dphi_j,a phi_b (physical), M[a][b] = sum W phi_a phi_b,
   // one matrix at a time (j = 0..D-1 gradients, j = D mass)
   if (VISC) {
+    constexpr int DW = D * D + 1;   // W J (D x D) and W per point
     const int JG = grad_group<D, VISC, NCT>(Np, Nq, Nfq, Nfp, L.fsize);
-    double *gm = resident ? work : lds;   // [JG][Np][Np]
+    double *swj = resident ? work : lds;   // [Nq][DW]
+    double *gm = swj + Nq * DW;            // [JG][Np][Np]
+    for (int t = tid; t < Nq * DW; t += NT) {
+      const int qp = t / DW, i = t % DW;
+      swj[t] = pv[(size_t)qp * L.size + (i < D * D ? L.WJ + i : L.W)];
+    }
+    __syncthreads();
     for (int j0 = 0; j0 <= D; j0 += JG) {
       const int nj = (D + 1 - j0) < JG ? (D + 1 - j0) : JG;
       for (int t = tid; t < nj * Np * Np; t += NT) {
         const int b = t % Np, a = (t / Np) % Np, j = j0 + t / (Np * Np);
         double acc = 0.0;
-        for (int qp = 0; qp < Nq; ++qp) {
-          const double *w = pv + (size_t)qp * L.size;
-          if (j < D) {
+        if (j < D) {
+#pragma unroll 4
+          for (int qp = 0; qp < Nq; ++qp) {
             double ta = 0.0;
 #pragma unroll
-            for (int r = 0; r < D; ++r) ta += w[L.WJ + r * D + j] * DPHI(r, qp, a);
+            for (int r = 0; r < D; ++r) ta += swj[qp * DW + r * D + j] * DPHI(r, qp, a);
             acc += ta * PHI(qp, b);
-          } else {
-            acc += w[L.W] * PHI(qp, a) * PHI(qp, b);
           }
+        } else {
+#pragma unroll 4
+          for (int qp = 0; qp < Nq; ++qp) acc += swj[qp * DW + D * D] * PHI(qp, a) * PHI(qp, b);
         }
         gm[t] = acc;
       }
@@ -250,6 +281,7 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   for (int t = tid; t < M * Np; t += NT) {
     const int a = t % Np, c = t / Np;
     double acc = 0.0;
+#pragma unroll 4
     for (int qp = 0; qp < Nq; ++qp) {
       const double *w = pv + (size_t)qp * L.size;
       double ta = w[L.Wu + c] * PHI(qp, a);
@@ -263,6 +295,7 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
     for (int t = tid; t < M * D * Np; t += NT) {
       const int a = t % Np, cj = t / Np, c = cj / D, j = cj % D;
       double acc = 0.0;
+#pragma unroll 4
       for (int qp = 0; qp < Nq; ++qp) {
         const double *w = pv + (size_t)qp * L.size;
         double ta = 0.0;
@@ -293,43 +326,74 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
     __syncthreads();
     const bool dir = fbc[f] != 0;
     const int *fn = fnodes + f * Nfp;
-    // (c, c') blocks: A_vv += Tv, C_v = Tv (flux faces), B_v = Th, D = Th or mass
-    for (int t = tid; t < M * M * NP2; t += NT) {
-      const int ib = t % Nfp, ia = (t / Nfp) % Nfp, cc = t / NP2;
-      const int c = cc / M, cp = cc % M;
-      double tv = 0.0, th = 0.0, tw = 0.0;
-      for (int fq = 0; fq < Nfq; ++fq) {
-        const double pp = spp[fq * NP2 + ia * Nfp + ib];
-        const double *w = spf + fq * L.fsize;
-        tv += w[L.fFv + c * M + cp] * pp;
-        th += w[L.fFh + c * M + cp] * pp;
-        tw += w[L.fW] * pp;
-      }
-      const int a = fn[ia], b = fn[ib];
-      A[(size_t)(cp * Np + b) * np + c * Np + a] += tv;
-      X[(size_t)(f * MF + cp * Nfp + ib) * np + c * Np + a] = th;
-      Dm[(size_t)(f * MF + cp * Nfp + ib) * kp + f * MF + c * Nfp + ia] = dir ? (c == cp ? tw : 0.0) : th;
-      if (!dir) Cm[(size_t)(cp * Np + a) * kp + f * MF + c * Nfp + ib] = tv;
-    }
-    if (VISC) {
-      // (c, s) blocks: A_vq += Tq, C_q = Tq (flux faces)
-      for (int t = tid; t < M * M * D * NP2; t += NT) {
-        const int ib = t % Nfp, ia = (t / Nfp) % Nfp, cs = t / NP2;
-        const int c = cs / (M * D), s = cs % (M * D);
-        double tq = 0.0;
-        for (int fq = 0; fq < Nfq; ++fq)
-          tq += spf[fq * L.fsize + L.fFq + c * (M * D) + s] * spp[fq * NP2 + ia * Nfp + ib];
+    // face products on MFMA: T[rho][(ia, ib)] = sum_fq coef_rho(fq) psi_ia(fq) psi_ib(fq), with
+    // rows rho: Tv (c, c') | Th (c, c') | mass | Tq (c, s) | B_q (j) (the last two viscous only)
+    {
+      constexpr int MM = M * M, RV = 2 * MM + 1;
+      constexpr int NR = RV + (VISC ? MM * D + D : 0);
+      constexpr int RTL = (NR + 15) / 16;
+      const int nct = (NP2 + 15) / 16;
+      const int Nfq4 = (Nfq + 3) & ~3;
+      for (int tt = wave; tt < RTL * nct; tt += NT / 64) {
+        const int rt = tt / nct, ct = tt % nct;
+        const int ra = rt * 16 + li;   // A-operand row of this lane
+        int off = -1;
+        if (ra < MM) off = L.fFv + ra;
+        else if (ra < 2 * MM) off = L.fFh + (ra - MM);
+        else if (ra == 2 * MM) off = L.fW;
+        else if (VISC && ra < RV + MM * D) off = L.fFq + (ra - RV);
+        else if (VISC && ra < NR) off = L.fWn + (ra - RV - MM * D);
+        const int nb = ct * 16 + li;   // B-operand column of this lane
+        // output column of this lane, n = ib * Nfp + ia (the product table is symmetric in
+        // ia, ib; with ia fastest the lanes write neighbouring rows of A, B and D), and
+        // the A entries it will add to, read before the products so that the loads overlap them
+        const int n = nb;
+        const int ib = n < NP2 ? n / Nfp : 0, ia = n < NP2 ? n % Nfp : 0;
         const int a = fn[ia], b = fn[ib];
-        A[(size_t)(nv + s * Np + b) * np + c * Np + a] += tq;
-        if (!dir) Cm[(size_t)(nv + s * Np + a) * kp + f * MF + c * Nfp + ib] = tq;
-      }
-      // B_q[(c, j, a), (f, c, b)] = -sum W n_j psi_a psi_b
-      for (int t = tid; t < D * NP2; t += NT) {
-        const int ib = t % Nfp, ia = (t / Nfp) % Nfp, j = t / NP2;
-        double tn = 0.0;
-        for (int fq = 0; fq < Nfq; ++fq) tn += spf[fq * L.fsize + L.fWn + j] * spp[fq * NP2 + ia * Nfp + ib];
-        for (int c = 0; c < M; ++c)
-          X[(size_t)(f * MF + c * Nfp + ib) * np + nv + (c * D + j) * Np + fn[ia]] = -tn;
+        double *ap[4];
+        double aold[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rho = rt * 16 + lk + 4 * r;
+          ap[r] = nullptr;
+          if (n < NP2) {
+            if (rho < MM) ap[r] = A + (size_t)((rho % M) * Np + b) * np + (rho / M) * Np + a;
+            else if (VISC && rho >= RV && rho < RV + MM * D)
+              ap[r] = A + (size_t)(nv + ((rho - RV) % (M * D)) * Np + b) * np + ((rho - RV) / (M * D)) * Np + a;
+          }
+          aold[r] = ap[r] ? *ap[r] : 0.0;
+        }
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < Nfq4; k0 += 4) {
+          const int fq = k0 + lk;
+          const double av = (off >= 0 && fq < Nfq) ? spf[fq * L.fsize + off] : 0.0;
+          const double bv = (nb < NP2 && fq < Nfq) ? spp[fq * NP2 + nb] : 0.0;
+          acc = mfma4(av, bv, acc);
+        }
+        if (n >= NP2) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rho = rt * 16 + lk + 4 * r;
+          const double v = acc[r];
+          if (ap[r]) *ap[r] = aold[r] + v;   // A_vv += Tv, A_vq += Tq
+          if (rho < MM) {                 // C_v = Tv (flux faces)
+            const int c = rho / M, cp = rho % M;
+            if (!dir) Cm[(size_t)(cp * Np + a) * kp + f * MF + c * Nfp + ib] = v;
+          } else if (rho < 2 * MM) {      // B_v = Th, D = Th (flux faces)
+            const int c = (rho - MM) / M, cp = (rho - MM) % M;
+            X[(size_t)(f * MF + cp * Nfp + ib) * np + c * Np + a] = v;
+            if (!dir) Dm[(size_t)(f * MF + cp * Nfp + ib) * kp + f * MF + c * Nfp + ia] = v;
+          } else if (rho == 2 * MM) {     // D = mass on Dirichlet faces
+            if (dir)
+              for (int c = 0; c < M; ++c) Dm[(size_t)(f * MF + c * Nfp + ib) * kp + f * MF + c * Nfp + ia] = v;
+          } else if (VISC && rho < RV + MM * D) {   // C_q = Tq (flux faces)
+            const int q = rho - RV, c = q / (M * D), sq = q % (M * D);
+            if (!dir) Cm[(size_t)(nv + sq * Np + a) * kp + f * MF + c * Nfp + ib] = v;
+          } else if (VISC && rho < NR) {  // B_q[(c, j, a), (f, c, b)] = -sum W n_j psi_a psi_b
+            const int j = rho - RV - MM * D;
+            for (int c = 0; c < M; ++c) X[(size_t)(f * MF + c * Nfp + ib) * np + nv + (c * D + j) * Np + a] = -v;
+          }
+        }
       }
     }
     // residual face terms

@@ -266,6 +266,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
     if (D.cw_lp) D.cw_lp = 16;
   }
   D.contract_threads = 1024;
+  D.zero_xcd = 1;
   P->fused = D.cw != 0;
   if (opts && (opts->flags & HDG_FLAG_SPLIT_DENSE)) P->fused = false;
   P->split_ok = lu_lds_bytes(D.n_pad) <= 160 * 1024;
@@ -488,6 +489,7 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   if (!e) e = up(l.bj_tpos, P->bj_tpos.data(), P->bj_tpos.size() * 4);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(e, "bind_workspace upload");
+  P->xcd_clean = false;
   DevPlan &D = P->dp;
   D.phi = reinterpret_cast<const double *>(base + l.phi);
   D.dphi = reinterpret_cast<const double *>(base + l.dphi);
@@ -577,9 +579,18 @@ int run_front(Plan *P, const double *v, const double *q, const double *vhat, con
   if (!e) e = launch_points(P->dp, e0, ec, v, q, vhat, ustar, vbc, status, s);
   if (!e) e = phase_end(P, PH_POINTS, s);
   if (!e) e = phase_begin(P, PH_CONTRACT, s);
+  // With one chunk every element keeps its workspace slot, so the zeros of X, C and D
+  // (a fixed pattern per element: face nodes and face boundary types do not change)
+  // survive from the previous call; only the split solve overwrites X.
+  const bool one_chunk = P->chunk >= P->n_elem;
+  P->dp.zero_xcd = (one_chunk && P->xcd_clean) ? 0 : 1;
   if (!e) e = P->contract_mfma ? launch_contract_mfma(P->dp, e0, ec, s) : launch_contract(P->dp, e0, ec, s);
   if (!e) e = phase_end(P, PH_CONTRACT, s);
-  if (e) return hip_fail(e, "assemble");
+  if (e) {
+    P->xcd_clean = false;
+    return hip_fail(e, "assemble");
+  }
+  P->xcd_clean = one_chunk;
   return HDG_OK;
 }
 
@@ -642,6 +653,7 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
     if (!e) e = launch_lu(P->dp, ec, status + e0, s);
     if (!e) e = phase_end(P, PH_LU, s);
     if (!e) e = phase_begin(P, PH_SOLVE, s);
+    P->xcd_clean = false;   // the split solve writes [Y z] over X
     if (!e) e = launch_solve(P->dp, ec, s);
     if (!e) e = phase_end(P, PH_SOLVE, s);
     if (!e) e = phase_begin(P, PH_SCHUR, s);

@@ -22,6 +22,7 @@ struct DevPlan {
   int dim, m, Np, nf, Nfp, Nq, Nfq, n, k, n_pad, k_pad, kx, viscous, n_elem, n_trace;
   int cw, cw_lp;           // column-block width of the fused FP64 / FP32 condensation (0: not available)
   int contract_threads;    // workgroup size of the block contraction (256, 512, 1024)
+  int zero_xcd;            // 1: the contraction clears X, C and D first (0: they hold the zeros already)
   double gamma, mu, Pr, alpha;
   PointLayout L;
   // tables (device)
@@ -84,6 +85,7 @@ struct Plan {
   size_t ws_bytes = 0;
   size_t off_tables_end = 0;
   bool bound = false;
+  bool xcd_clean = false;   // workspace X, C, D hold this plan's structural zeros (one chunk)
 };
 
 // plan helpers shared by the entry-point sources (hdg_plan.cpp)
