@@ -204,24 +204,26 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
           for (int r = 0; r < D; ++r) tval += cq[o2 + r * st] * sdphi[(r * QC + ql) * NB + a];
         }
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = mfma4(tval, sphi[ql * NB + ct * 16 + li], acc[u][ct]);
+        for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = mfma4(sphi[ql * NB + ct * 16 + li], tval, acc[u][ct]);
       }
     }
-    // write the tiles: rows rho = (g, c, a), columns b
+    // write the tiles.  The products are formed transposed (phi as the first operand), so
+    // that lane l holds row rho = tile * 16 + l % 16 and columns b = ct * 16 + l / 16 + 4 r:
+    // neighbouring lanes write neighbouring rows of A
 #pragma unroll
     for (int u = 0; u < RT; ++u) {
       const int tile = base + wave * RT + u;
+      const int rho = tile * 16 + li;
+      if (tile >= ntiles || rho >= nrows) continue;
+      const int a = rho % Np, c = (rho / Np) % M, g = rho / (Np * M);
+      double *Ac = A + (size_t)(g * Np) * np + c * Np + a;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rho = tile * 16 + lk + 4 * r;
-        if (tile >= ntiles || rho >= nrows) continue;
-        const int a = rho % Np, c = (rho / Np) % M, g = rho / (Np * M);
+      for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-          const int b = ct * 16 + li;
-          if (b < Np) A[(size_t)(g * Np + b) * np + c * Np + a] = acc[u][ct][r];
+        for (int r = 0; r < 4; ++r) {
+          const int b = ct * 16 + lk + 4 * r;
+          if (b < Np) Ac[(size_t)b * np] = acc[u][ct][r];
         }
-      }
     }
   }
   __syncthreads();
@@ -376,9 +378,11 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
           const int rho = rt * 16 + lk + 4 * r;
           const double v = acc[r];
           if (ap[r]) *ap[r] = aold[r] + v;   // A_vv += Tv, A_vq += Tq
+          // (C entries use T[.][ia][ib] = T[.][ib][ia]: column from node ib, row from ia, so
+          // that neighbouring lanes write neighbouring rows of C as well)
           if (rho < MM) {                 // C_v = Tv (flux faces)
             const int c = rho / M, cp = rho % M;
-            if (!dir) Cm[(size_t)(cp * Np + a) * kp + f * MF + c * Nfp + ib] = v;
+            if (!dir) Cm[(size_t)(cp * Np + b) * kp + f * MF + c * Nfp + ia] = v;
           } else if (rho < 2 * MM) {      // B_v = Th, D = Th (flux faces)
             const int c = (rho - MM) / M, cp = (rho - MM) % M;
             X[(size_t)(f * MF + cp * Nfp + ib) * np + c * Np + a] = v;
@@ -388,7 +392,7 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
               for (int c = 0; c < M; ++c) Dm[(size_t)(f * MF + c * Nfp + ib) * kp + f * MF + c * Nfp + ia] = v;
           } else if (VISC && rho < RV + MM * D) {   // C_q = Tq (flux faces)
             const int q = rho - RV, c = q / (M * D), sq = q % (M * D);
-            if (!dir) Cm[(size_t)(nv + sq * Np + a) * kp + f * MF + c * Nfp + ib] = v;
+            if (!dir) Cm[(size_t)(nv + sq * Np + b) * kp + f * MF + c * Nfp + ia] = v;
           } else if (VISC && rho < NR) {  // B_q[(c, j, a), (f, c, b)] = -sum W n_j psi_a psi_b
             const int j = rho - RV - MM * D;
             for (int c = 0; c < M; ++c) X[(size_t)(f * MF + c * Nfp + ib) * np + nv + (c * D + j) * Np + a] = -v;
