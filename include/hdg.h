@@ -180,14 +180,20 @@ int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
 
 /* ---- Kernel tuning ---------------------------------------------------------
  * Launch shapes of one plan (0 leaves a field unchanged): workgroup size of
- * the block contraction (256, 512, 1024 threads) and column-block width of
- * the fused FP64 / FP32 condensation (32 or 16; must fit in LDS).  The
- * autotuner (paper_1808_05066_amd/autotune.py) sweeps these per (n, k, dtype)
- * and caches the fastest in JSON.  Set before building a batch. */
+ * the block contraction (256, 512, 1024 threads), column-block width of the
+ * fused FP64 / FP32 condensation (32 or 16; must fit in LDS), and its number
+ * of launches: 1 (one workgroup per element factors A and works through every
+ * right-hand-side block) or 2 (default: one workgroup per element for the LU,
+ * then one per element and right-hand-side block, the workgroups of an
+ * element on one XCD so that they share its factors in L2; FP64 with 32-column
+ * blocks and FP32; the results are the same bit for bit).  The autotuner
+ * (paper_1808_05066_amd/autotune.py) sweeps these per (n, k, dtype) and caches
+ * the fastest in JSON.  Set before building a batch (batches use one launch). */
 typedef struct {
   int contract_threads;
   int condense_width;
   int condense_width_lp;
+  int condense_launches;
 } hdg_tuning;
 
 int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t);

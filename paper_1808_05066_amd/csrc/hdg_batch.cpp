@@ -257,6 +257,11 @@ extern "C" int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t) {
       return fail(HDG_EUNSUPPORTED, "condense_width_lp does not fit in LDS for this block size");
     P->dp.cw_lp = t->condense_width_lp;
   }
+  if (t->condense_launches) {
+    if (t->condense_launches != 1 && t->condense_launches != 2)
+      return fail(HDG_EINVAL, "condense_launches must be 1 or 2");
+    P->dp.condense_launches = t->condense_launches;
+  }
   return HDG_OK;
 }
 
@@ -266,5 +271,6 @@ extern "C" int hdg_plan_get_tuning(const hdg_plan *plan, hdg_tuning *t) {
   t->contract_threads = P->dp.contract_threads;
   t->condense_width = P->fused ? P->dp.cw : 0;
   t->condense_width_lp = P->dp.cw_lp;
+  t->condense_launches = P->dp.condense_launches;
   return HDG_OK;
 }

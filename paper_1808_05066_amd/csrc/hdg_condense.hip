@@ -614,22 +614,10 @@ __host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp, i
 __host__ __device__ inline size_t rec_perm_off(int np) { return (size_t)np * np + 2 * (size_t)np * WMAX; }
 __host__ __device__ inline size_t lp_rec_floats(int np) { return rec_perm_off(np) + 2 * (size_t)np; }
 
-// T = double, LP = false: FP64 condensation, factors overwrite the A scratch.
-// T = float,  LP = true : scaled FP32 condensation, factors to the record `fac`.
-// One workgroup per element (blockIdx.x = element of the chunk).
+// LDS of the condensation kernels, carved as lds_layout describes.
 template <typename T, bool LP, int W>
-__device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, int32_t *status, T *S, double *g,
-                                              T *Y, double *z, T *inv, float *fac) {
-  typedef Mfma<T> MF;
-  constexpr int BS = W + 1, TW = W / 16;
+__device__ __forceinline__ Lds<T> carve_lds(int np) {
   extern __shared__ double smem[];
-  const int e = e0 + el;
-  const int np = P.n_pad, kp = P.k_pad, kx = P.kx, n = P.n, k = P.k;
-  double *A64 = P.A + (size_t)el * np * np;
-  const double *X = P.X + (size_t)el * kx * np;
-  const double *C = P.C + (size_t)el * np * kp;
-  const double *Dm = P.D + (size_t)el * kp * kp;
-  const double *Rt = P.Rt + (size_t)el * kp;
   char *sm = reinterpret_cast<char *>(smem);
   const LdsLayout Lo = lds_layout(np, sizeof(T), LP, W);
   Lds<T> s;
@@ -643,33 +631,57 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
   s.mvx = reinterpret_cast<int *>(sm + Lo.mv);
   s.mvy = s.mvx + 2 * WMAX;
   s.mvn = s.mvy + 2 * WMAX;
-  // factor storage and inverses of the diagonal blocks ([nJ][2][W][W])
-  T *Fm;
-  T *Ie;
-  float *rec = nullptr;
-  if constexpr (LP) {
-    rec = fac + (size_t)e * lp_rec_floats(np);
-    Fm = rec;
-    Ie = rec + (size_t)np * np;
-  } else {
-    Fm = A64;
-    Ie = inv + (size_t)el * 2 * np * WMAX;
-  }
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int nJ = np / W;
+  return s;
+}
 
+// Factor storage of element el (chunk slot) / e (global index): FP64 factors
+// overwrite the A scratch, FP32 factors go to the record.
+template <typename T, bool LP>
+struct FactorPtrs {
+  T *F;     // [np][np] factors in pivot-position order
+  T *Inv;   // [np/W][2][W][W] inverses of the diagonal blocks
+  float *rec;
+};
+
+template <typename T, bool LP>
+__device__ __forceinline__ FactorPtrs<T, LP> factor_ptrs(const DevPlan &P, int e, int el, T *inv, float *fac) {
+  const int np = P.n_pad;
+  FactorPtrs<T, LP> f;
+  if constexpr (LP) {
+    f.rec = fac + (size_t)e * lp_rec_floats(np);
+    f.F = f.rec;
+    f.Inv = f.rec + (size_t)np * np;
+  } else {
+    f.rec = nullptr;
+    f.F = P.A + (size_t)el * np * np;
+    f.Inv = inv + (size_t)el * 2 * np * WMAX;
+  }
+  return f;
+}
+
+// Symmetric power-of-two scaling of the low-precision path from the diagonal of A.
+__device__ inline double diag_scale(const double *A64, int np, int i) {
+  const double a = fabs(A64[(size_t)i * np + i]);
+  return (a > 0.0 && a < 1e300) ? exp2(-rint(0.5 * log2(a))) : 1.0;
+}
+
+// LU of element el, left-looking over W-column blocks; leaves perm (and the
+// scaling) in LDS and stores the permutation (P.ipiv, or the record).
+// Returns whether a zero pivot occurred.
+template <typename T, bool LP, int W>
+__device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &s, const FactorPtrs<T, LP> &f) {
+  const int np = P.n_pad;
+  const double *A64 = P.A + (size_t)el * np * np;
+  T *Fm = f.F;
+  T *Ie = f.Inv;
+  const int tid = threadIdx.x;
+  const int nJ = np / W;
   for (int i = tid; i < np; i += NT) {
     s.perm[i] = i;
-    if constexpr (LP) {
-      const double a = fabs(A64[(size_t)i * np + i]);
-      s.dsc[i] = (a > 0.0 && a < 1e300) ? exp2(-rint(0.5 * log2(a))) : 1.0;
-    }
+    if constexpr (LP) s.dsc[i] = diag_scale(A64, np, i);
   }
   __syncthreads();
   bool singular = false;
-
-  // ---- LU, left-looking over W-column blocks
   for (int J = 0; J < nJ; ++J) {
     const int j0 = J * W;
     if constexpr (LP) load_block_scaled<T, W>(s, A64, np, j0, np, true);
@@ -693,83 +705,176 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
     __syncthreads();
   }
   if constexpr (LP) {
-    int *rp = reinterpret_cast<int *>(rec + rec_perm_off(np));
+    int *rp = reinterpret_cast<int *>(f.rec + rec_perm_off(np));
     float *rd = reinterpret_cast<float *>(rp + np);
     for (int i = tid; i < np; i += NT) {
       rp[i] = s.perm[i];
       rd[i] = (float)s.dsc[i];
     }
+  } else {
+    int *ip = P.ipiv + (size_t)el * np;
+    for (int i = tid; i < np; i += NT) ip[i] = s.perm[i];
   }
+  return singular;
+}
 
-  // ---- right-hand sides, 32 columns at a time, then the Schur product
+// Right-hand-side block c0..c0+W-1 of [B | R_loc] for element e (slot el), with
+// perm (and the scaling) in LDS: permutation gather, forward and backward
+// sweeps against the stored factors, outputs Y, z, then the Schur product
+// C * Y_block straight from LDS into S and g.
+template <typename T, bool LP, int W>
+__device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c0, const Lds<T> &s,
+                                          const FactorPtrs<T, LP> &f, T *S, double *g, T *Y, double *z) {
+  typedef Mfma<T> MF;
+  constexpr int BS = W + 1, TW = W / 16;
+  const int np = P.n_pad, kp = P.k_pad, kx = P.kx, n = P.n, k = P.k;
+  const double *X = P.X + (size_t)el * kx * np;
+  const double *C = P.C + (size_t)el * np * kp;
+  const double *Dm = P.D + (size_t)el * kp * kp;
+  const double *Rt = P.Rt + (size_t)el * kp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nJ = np / W;
   T *Se = S + (size_t)e * k * k;
   double *ge = g + (size_t)e * k;
   T *Ye = Y + (size_t)e * n * k;
   const int ntr = kp / 16;
-  for (int c0 = 0; c0 < kx; c0 += W) {
-    if constexpr (LP) load_block_scaled<T, W>(s, X, np, c0, np, false);
-    else load_block<T, W>(s, X, np, c0, np);
-    __syncthreads();
-    // forward (unit lower) then backward (upper) sweep as one pipelined sequence
-    run_steps<T, W>(s, Ie, Fm, np, 2 * nJ, [&](int i) {
-      if (i < nJ) return Step{i * 2 * W * W, i * W, i * W + W, np};
-      const int P = 2 * nJ - 1 - i;
-      return Step{P * 2 * W * W + W * W, P * W, 0, P * W};
-    });
-    if constexpr (LP) {
-      // undo the column scaling: Y = D Y_hat, z = D z_hat
-      for (int t = tid; t < np * W; t += NT) {
-        const int c = t / np, i = t - c * np;
-        s.blk[i * BS + c] = (T)((double)s.blk[i * BS + c] * s.dsc[i]);
-      }
-      __syncthreads();
-    }
-    // outputs Y, z (compact)
-    for (int t = tid; t < n * W; t += NT) {
-      const int c = t / n, i = t - c * n;
-      const int col = c0 + c;
-      if (col < k) Ye[(size_t)col * n + i] = s.blk[i * BS + c];
-      else if (col == kp) z[(size_t)e * n + i] = (double)s.blk[i * BS + c];
-    }
-    // T = C * block (k_pad x W): S = D - T, g = -R_tr + T
-    for (int t = wave; t < ntr; t += NW) {
-      const int r0 = t * 16;
-      typename MF::acc acc[TW];
-#pragma unroll
-      for (int q = 0; q < TW; ++q) acc[q] = typename MF::acc{0, 0, 0, 0};
-      const double *Cr = C + (size_t)lk * kp + r0 + li;
-      T a[8], an[8];
-#pragma unroll
-      for (int kk = 0; kk < 8; ++kk) a[kk] = (T)Cr[(size_t)(4 * kk) * kp];
-      for (int kb = 0; kb < np; kb += 32) {
-        if (kb + 32 < np) {
-#pragma unroll
-          for (int kk = 0; kk < 8; ++kk) an[kk] = (T)Cr[(size_t)(kb + 32 + 4 * kk) * kp];
-        }
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) {
-          const T *brow = s.blk + (kb + 4 * kk + lk) * BS;
-#pragma unroll
-          for (int q = 0; q < TW; ++q) acc[q] = MF::op(a[kk], brow[q * 16 + li], acc[q]);
-        }
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = r0 + MF::row(lk, r);
-        if (row >= k) continue;
-#pragma unroll
-        for (int q = 0; q < TW; ++q) {
-          const int col = c0 + q * 16 + li;
-          if (col < k) Se[(size_t)col * k + row] = (T)(Dm[(size_t)col * kp + row] - (double)acc[q][r]);
-          else if (col == kp) ge[row] = -Rt[row] + (double)acc[q][r];
-        }
-      }
+  if constexpr (LP) load_block_scaled<T, W>(s, X, np, c0, np, false);
+  else load_block<T, W>(s, X, np, c0, np);
+  __syncthreads();
+  // forward (unit lower) then backward (upper) sweep as one pipelined sequence
+  run_steps<T, W>(s, f.Inv, f.F, np, 2 * nJ, [&](int i) {
+    if (i < nJ) return Step{i * 2 * W * W, i * W, i * W + W, np};
+    const int Pb = 2 * nJ - 1 - i;
+    return Step{Pb * 2 * W * W + W * W, Pb * W, 0, Pb * W};
+  });
+  if constexpr (LP) {
+    // undo the column scaling: Y = D Y_hat, z = D z_hat
+    for (int t = tid; t < np * W; t += NT) {
+      const int c = t / np, i = t - c * np;
+      s.blk[i * BS + c] = (T)((double)s.blk[i * BS + c] * s.dsc[i]);
     }
     __syncthreads();
   }
-  if (singular && tid == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
+  // outputs Y, z (compact)
+  for (int t = tid; t < n * W; t += NT) {
+    const int c = t / n, i = t - c * n;
+    const int col = c0 + c;
+    if (col < k) Ye[(size_t)col * n + i] = s.blk[i * BS + c];
+    else if (col == kp) z[(size_t)e * n + i] = (double)s.blk[i * BS + c];
+  }
+  // T = C * block (k_pad x W): S = D - T, g = -R_tr + T
+  for (int t = wave; t < ntr; t += NW) {
+    const int r0 = t * 16;
+    typename MF::acc acc[TW];
+#pragma unroll
+    for (int q = 0; q < TW; ++q) acc[q] = typename MF::acc{0, 0, 0, 0};
+    const double *Cr = C + (size_t)lk * kp + r0 + li;
+    T a[8], an[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) a[kk] = (T)Cr[(size_t)(4 * kk) * kp];
+    for (int kb = 0; kb < np; kb += 32) {
+      if (kb + 32 < np) {
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) an[kk] = (T)Cr[(size_t)(kb + 32 + 4 * kk) * kp];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const T *brow = s.blk + (kb + 4 * kk + lk) * BS;
+#pragma unroll
+        for (int q = 0; q < TW; ++q) acc[q] = MF::op(a[kk], brow[q * 16 + li], acc[q]);
+      }
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + MF::row(lk, r);
+      if (row >= k) continue;
+#pragma unroll
+      for (int q = 0; q < TW; ++q) {
+        const int col = c0 + q * 16 + li;
+        if (col < k) Se[(size_t)col * k + row] = (T)(Dm[(size_t)col * kp + row] - (double)acc[q][r]);
+        else if (col == kp) ge[row] = -Rt[row] + (double)acc[q][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// T = double, LP = false: FP64 condensation, factors overwrite the A scratch.
+// T = float,  LP = true : scaled FP32 condensation, factors to the record `fac`.
+// One workgroup per element (the LU, then every right-hand-side block).
+template <typename T, bool LP, int W>
+__device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, int32_t *status, T *S, double *g,
+                                              T *Y, double *z, T *inv, float *fac) {
+  const int e = e0 + el;
+  const Lds<T> s = carve_lds<T, LP, W>(P.n_pad);
+  const FactorPtrs<T, LP> f = factor_ptrs<T, LP>(P, e, el, inv, fac);
+  const bool singular = lu_part<T, LP, W>(P, el, s, f);
+  for (int c0 = 0; c0 < P.kx; c0 += W) rhs_block<T, LP, W>(P, e, el, c0, s, f, S, g, Y, z);
+  if (singular && threadIdx.x == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
+}
+
+// Split condensation: the LU of one element per workgroup, then one workgroup
+// per (element, right-hand-side block).  The nRB workgroups of an element read
+// the same factors and C, so they are placed on one XCD (workgroups are handed
+// to the 8 XCDs round-robin by index: element slot el runs as indices
+// (el / 8 * nRB + j) * 8 + el % 8) and share its L2.
+template <typename T, bool LP, int W>
+__device__ __forceinline__ void lu_body(const DevPlan &P, int e0, int el, int32_t *status, T *inv, float *fac) {
+  const int e = e0 + el;
+  const Lds<T> s = carve_lds<T, LP, W>(P.n_pad);
+  const FactorPtrs<T, LP> f = factor_ptrs<T, LP>(P, e, el, inv, fac);
+  const bool singular = lu_part<T, LP, W>(P, el, s, f);
+  if (singular && threadIdx.x == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
+}
+
+constexpr int NXCD = 8;
+
+template <typename T, bool LP, int W>
+__device__ __forceinline__ void rhs_body(const DevPlan &P, int e0, int ec, T *S, double *g, T *Y, double *z, T *inv,
+                                         float *fac) {
+  const int nrb = P.kx / W;
+  const int b = blockIdx.x, xcd = b % NXCD, slot = b / NXCD;
+  const int el = (slot / nrb) * NXCD + xcd, j = slot % nrb;
+  if (el >= ec) return;   // whole workgroup
+  const int e = e0 + el;
+  const int np = P.n_pad;
+  const Lds<T> s = carve_lds<T, LP, W>(np);
+  const FactorPtrs<T, LP> f = factor_ptrs<T, LP>(P, e, el, inv, fac);
+  const int *perm = LP ? reinterpret_cast<const int *>(f.rec + rec_perm_off(np)) : P.ipiv + (size_t)el * np;
+  const double *A64 = P.A + (size_t)el * np * np;
+  for (int i = threadIdx.x; i < np; i += NT) {
+    s.perm[i] = perm[i];
+    if constexpr (LP) s.dsc[i] = diag_scale(A64, np, i);
+  }
+  __syncthreads();
+  rhs_block<T, LP, W>(P, e, el, j * W, s, f, S, g, Y, z);
+}
+
+__global__ __launch_bounds__(NT) void k_lu_f64_w32(DevPlan P, int e0, int32_t *status, double *inv) {
+  lu_body<double, false, 32>(P, e0, blockIdx.x, status, inv, nullptr);
+}
+
+__global__ __launch_bounds__(NT) void k_rhs_f64_w32(DevPlan P, int e0, int ec, double *S, double *g, double *Y,
+                                                    double *z, double *inv) {
+  rhs_body<double, false, 32>(P, e0, ec, S, g, Y, z, inv, nullptr);
+}
+
+template <int W>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_lu_f32(DevPlan P, int e0,
+                                                                                        int32_t *status,
+                                                                                        float *fac) {
+  lu_body<float, true, W>(P, e0, blockIdx.x, status, nullptr, fac);
+}
+
+template <int W>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rhs_f32(DevPlan P, int e0, int ec,
+                                                                                         float *S, double *g,
+                                                                                         float *Y, double *z,
+                                                                                         float *fac) {
+  rhs_body<float, true, W>(P, e0, ec, S, g, Y, z, nullptr, fac);
 }
 
 __global__ __launch_bounds__(NT) void k_condense_f64_w32(DevPlan P, int e0, int32_t *status, double *S, double *g,
@@ -916,9 +1021,17 @@ hipError_t launch_dyn(K kern, int ec, size_t lds, hipStream_t s, Args... args) {
   return hipGetLastError();
 }
 
+// grid of the right-hand-side launch: element slots rounded up to the XCD count, times the blocks
+static int rhs_grid(const DevPlan &P, int ec, int W) { return (ec + NXCD - 1) / NXCD * NXCD * (P.kx / W); }
+
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s) {
   const size_t lds = condense_lds_bytes(P.n_pad, P.cw);
+  if (P.cw == 32 && P.condense_launches == 2) {
+    hipError_t e = launch_dyn(k_lu_f64_w32, ec, lds, s, P, e0, status, P.inv);
+    if (!e) e = launch_dyn(k_rhs_f64_w32, rhs_grid(P, ec, 32), lds, s, P, e0, ec, S, g, Y, z, P.inv);
+    return e;
+  }
   if (P.cw == 32) return launch_dyn(k_condense_f64_w32, ec, lds, s, P, e0, status, S, g, Y, z, P.inv);
   if (P.cw == 16) return launch_dyn(k_condense_f64_w16, ec, lds, s, P, e0, status, S, g, Y, z, P.inv);
   return hipErrorInvalidValue;
@@ -927,6 +1040,17 @@ hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, do
 hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
                               double *z, float *fac, hipStream_t s) {
   const size_t lds = condense_lds_bytes_lp(P.n_pad, P.cw_lp);
+  if (P.condense_launches == 2 && (P.cw_lp == 32 || P.cw_lp == 16)) {
+    hipError_t e;
+    if (P.cw_lp == 32) {
+      e = launch_dyn(k_lu_f32<32>, ec, lds, s, P, e0, status, fac);
+      if (!e) e = launch_dyn(k_rhs_f32<32>, rhs_grid(P, ec, 32), lds, s, P, e0, ec, S, g, Y, z, fac);
+    } else {
+      e = launch_dyn(k_lu_f32<16>, ec, lds, s, P, e0, status, fac);
+      if (!e) e = launch_dyn(k_rhs_f32<16>, rhs_grid(P, ec, 16), lds, s, P, e0, ec, S, g, Y, z, fac);
+    }
+    return e;
+  }
   if (P.cw_lp == 32) return launch_dyn(k_condense_f32<32>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
   if (P.cw_lp == 16) return launch_dyn(k_condense_f32<16>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
   return hipErrorInvalidValue;

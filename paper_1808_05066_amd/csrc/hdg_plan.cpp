@@ -267,6 +267,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   }
   D.contract_threads = 1024;
   D.zero_xcd = 1;
+  D.condense_launches = 2;
   P->fused = D.cw != 0;
   if (opts && (opts->flags & HDG_FLAG_SPLIT_DENSE)) P->fused = false;
   P->split_ok = lu_lds_bytes(D.n_pad) <= 160 * 1024;

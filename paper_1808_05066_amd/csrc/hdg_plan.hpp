@@ -23,6 +23,7 @@ struct DevPlan {
   int cw, cw_lp;           // column-block width of the fused FP64 / FP32 condensation (0: not available)
   int contract_threads;    // workgroup size of the block contraction (256, 512, 1024)
   int zero_xcd;            // 1: the contraction clears X, C and D first (0: they hold the zeros already)
+  int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
   double gamma, mu, Pr, alpha;
   PointLayout L;
   // tables (device)

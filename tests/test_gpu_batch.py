@@ -9,8 +9,8 @@
 * a captured hipGraph of the whole batch, replayed several times with eager
   work and synchronizations in between, reproduces the eager outputs every
   time;
-* the tuning knobs (contraction workgroup size, condensation block width)
-  change nothing but the launch shape.
+* the tuning knobs (contraction workgroup size, condensation block width,
+  one or two condensation launches) change nothing but the launch shape.
 """
 import numpy as np
 import pytest
@@ -128,11 +128,22 @@ def test_tuning_changes_only_the_launch_shape(torch, groups):
     base = plan.assemble_condense(*args)
     torch.cuda.synchronize()
     t0 = plan.tuning()
-    for ct, cw in ((256, 32), (512, 16), (1024, 32)):
-        plan.set_tuning(contract_threads=ct, condense_width=cw)
+    for ct, cw, nl in ((256, 32, 2), (512, 16, 2), (1024, 32, 1), (1024, 32, 2)):
+        plan.set_tuning(contract_threads=ct, condense_width=cw, condense_launches=nl)
         out = plan.assemble_condense(*args)
         torch.cuda.synchronize()
         for key in ("S", "Y", "g"):
             err = float(torch.linalg.norm(out[key] - base[key]) / torch.linalg.norm(base[key]))
-            assert err <= 1e-13, (ct, cw, key, err)
+            assert err <= 1e-13, (ct, cw, nl, key, err)
+    # the split and the fused condensation do the same arithmetic in the same order
+    lp = {}
+    for nl in (1, 2):
+        plan.set_tuning(condense_launches=nl)
+        f64 = plan.assemble_condense(*args)
+        lp[nl] = plan.assemble_condense_lp(*args)
+        torch.cuda.synchronize()
+        lp[nl]["f64"] = f64
+    for key in ("S", "Y", "g", "z"):
+        assert torch.equal(lp[1][key], lp[2][key]), ("fp32", key)
+        assert torch.equal(lp[1]["f64"][key], lp[2]["f64"][key]), ("fp64", key)
     plan.set_tuning(**t0)
