@@ -399,8 +399,10 @@ int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q, const dou
  * around each kernel group: 0 points (pointwise physics), 1 contract (block
  * assembly), 2 LU, 3 triangular solves, 4 Schur product (split dense path),
  * 5 back-solve, 6 trace operator, 7 trace right-hand side, 8 fused
- * condensation (LU + solves + Schur in one kernel), 9 low-precision fused
- * condensation, 10 low-precision local solve, 11 matrix-free Jacobian action.
+ * condensation (LU + solves + Schur: one kernel, or the two below), 9
+ * low-precision fused condensation, 10 low-precision local solve, 11
+ * matrix-free Jacobian action, 12 and 13 the LU launch and the right-hand-side
+ * launch of an FP64 condensation in two launches (inside phase 8).
  * Enabling resets the totals; hdg_plan_phase_times returns accumulated
  * milliseconds and call counts (up to n entries) and synchronizes on the last
  * recorded events. */

@@ -15,7 +15,7 @@ ERROR_NAMES = {0: "HDG_OK", -1: "HDG_EINVAL", -2: "HDG_EUNSUPPORTED", -3: "HDG_E
                -4: "HDG_ESINGULAR", -5: "HDG_EHIP", -6: "HDG_ENOMEM"}
 ETYPES = {"tri": 0, "quad": 1, "tet": 2, "hex": 3}
 PHASES = ["points", "contract", "lu", "solve", "schur", "backsolve", "matvec", "rhs", "condense", "condense_lp",
-          "lp_solve", "jvp"]
+          "lp_solve", "jvp", "condense_lu", "condense_rhs"]
 FLAG_SPLIT_DENSE = 1
 FLAG_NARROW_BLOCK = 2
 

@@ -1024,12 +1024,24 @@ hipError_t launch_dyn(K kern, int ec, size_t lds, hipStream_t s, Args... args) {
 // grid of the right-hand-side launch: element slots rounded up to the XCD count, times the blocks
 static int rhs_grid(const DevPlan &P, int ec, int W) { return (ec + NXCD - 1) / NXCD * NXCD * (P.kx / W); }
 
+bool condense_two_launches(const DevPlan &P) { return P.cw == 32 && P.condense_launches == 2; }
+
+hipError_t launch_condense_lu(const DevPlan &P, int e0, int ec, int32_t *status, hipStream_t s) {
+  return launch_dyn(k_lu_f64_w32, ec, condense_lds_bytes(P.n_pad, 32), s, P, e0, status, P.inv);
+}
+
+hipError_t launch_condense_rhs(const DevPlan &P, int e0, int ec, double *S, double *g, double *Y, double *z,
+                               hipStream_t s) {
+  return launch_dyn(k_rhs_f64_w32, rhs_grid(P, ec, 32), condense_lds_bytes(P.n_pad, 32), s, P, e0, ec, S, g, Y, z,
+                    P.inv);
+}
+
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s) {
   const size_t lds = condense_lds_bytes(P.n_pad, P.cw);
-  if (P.cw == 32 && P.condense_launches == 2) {
-    hipError_t e = launch_dyn(k_lu_f64_w32, ec, lds, s, P, e0, status, P.inv);
-    if (!e) e = launch_dyn(k_rhs_f64_w32, rhs_grid(P, ec, 32), lds, s, P, e0, ec, S, g, Y, z, P.inv);
+  if (condense_two_launches(P)) {
+    hipError_t e = launch_condense_lu(P, e0, ec, status, s);
+    if (!e) e = launch_condense_rhs(P, e0, ec, S, g, Y, z, s);
     return e;
   }
   if (P.cw == 32) return launch_dyn(k_condense_f64_w32, ec, lds, s, P, e0, status, S, g, Y, z, P.inv);

@@ -645,7 +645,16 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
     if (!e && !P->fused && !P->split_ok) return fail(HDG_EUNSUPPORTED, "FP64 condensation: local block too large");
     if (!e && P->fused) {
       e = phase_begin(P, PH_CONDENSE, s);
-      if (!e) e = launch_condense(P->dp, e0, ec, status + e0, S, g, Y, z, s);
+      if (!e && condense_two_launches(P->dp)) {
+        e = phase_begin(P, PH_CONDENSE_LU, s);
+        if (!e) e = launch_condense_lu(P->dp, e0, ec, status + e0, s);
+        if (!e) e = phase_end(P, PH_CONDENSE_LU, s);
+        if (!e) e = phase_begin(P, PH_CONDENSE_RHS, s);
+        if (!e) e = launch_condense_rhs(P->dp, e0, ec, S, g, Y, z, s);
+        if (!e) e = phase_end(P, PH_CONDENSE_RHS, s);
+      } else if (!e) {
+        e = launch_condense(P->dp, e0, ec, status + e0, S, g, Y, z, s);
+      }
       if (!e) e = phase_end(P, PH_CONDENSE, s);
       if (e) return hip_fail(e, "condense");
       continue;

@@ -61,7 +61,7 @@ struct DevPlan {
 // Phases timed with HIP events when phase timing is enabled.
 enum Phase {
   PH_POINTS = 0, PH_CONTRACT, PH_LU, PH_SOLVE, PH_SCHUR, PH_BACKSOLVE, PH_MATVEC, PH_RHS, PH_CONDENSE,
-  PH_CONDENSE_LP, PH_LP_SOLVE, PH_JVP, PH_COUNT
+  PH_CONDENSE_LP, PH_LP_SOLVE, PH_JVP, PH_CONDENSE_LU, PH_CONDENSE_RHS, PH_COUNT
 };
 
 struct Plan {
@@ -151,6 +151,11 @@ bool contract_mfma_supported(const DevPlan &P);
 hipError_t launch_contract_mfma(const DevPlan &P, int e0, int ec, hipStream_t s);
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s);
+// FP64 condensation in two launches (32-column blocks, condense_launches == 2): the LU, then the right-hand sides
+bool condense_two_launches(const DevPlan &P);
+hipError_t launch_condense_lu(const DevPlan &P, int e0, int ec, int32_t *status, hipStream_t s);
+hipError_t launch_condense_rhs(const DevPlan &P, int e0, int ec, double *S, double *g, double *Y, double *z,
+                               hipStream_t s);
 hipError_t launch_bj_assemble(const DevPlan &P, const double *S, double *B, hipStream_t s);
 hipError_t launch_block_invert(const DevPlan &P, double *B, int32_t *bad, hipStream_t s);
 hipError_t launch_block_apply(const DevPlan &P, const double *Binv, const double *r, double *z, hipStream_t s);
