@@ -414,6 +414,13 @@ int hdg_plan_phase_times(hdg_plan *plan, double *ms, long *calls, int n);
  * largest absolute difference (0 expected).  Allocates 8 bytes of device memory. */
 int hdg_selftest(double *max_err);
 
+/* First element whose status is not HDG_OK: synchronizes `stream`, copies the
+ * n_elem entries of elem_status (device, as filled by an assemble call of this
+ * plan) to the host and scans them; *first_bad_elem receives the index (-1 if
+ * every element is HDG_OK) and *code its status (HDG_OK then).  Returns
+ * HDG_EHIP if the copy fails. */
+int hdg_status(const hdg_plan *plan, const int32_t *elem_status, void *stream, int *first_bad_elem, int *code);
+
 /* Last host-side error message of the calling thread. */
 const char *hdg_last_error(void);
 

@@ -126,6 +126,7 @@ SIGNATURES = {
     "hdg_selftest": (I, [ctypes.POINTER(ctypes.c_double)]),
     "hdg_plan_set_timing": (I, [P, I]),
     "hdg_plan_phase_times": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_long), I]),
+    "hdg_status": (I, [P, P, P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "hdg_last_error": (ctypes.c_char_p, []),
 }
 

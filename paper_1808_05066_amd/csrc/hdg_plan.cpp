@@ -39,6 +39,26 @@ using namespace hdg;
 
 extern "C" const char *hdg_last_error(void) { return g_err.c_str(); }
 
+extern "C" int hdg_status(const hdg_plan *plan, const int32_t *elem_status, void *stream, int *first_bad_elem,
+                          int *code) {
+  const Plan *P = reinterpret_cast<const Plan *>(plan);
+  if (!P || !elem_status || !first_bad_elem || !code) return fail(HDG_EINVAL, "null argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::vector<int32_t> h(P->n_elem);
+  hipError_t e = hipMemcpyAsync(h.data(), elem_status, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (!e) e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "status copy");
+  *first_bad_elem = -1;
+  *code = HDG_OK;
+  for (size_t i = 0; i < h.size(); ++i)
+    if (h[i] != HDG_OK) {
+      *first_bad_elem = (int)i;
+      *code = h[i];
+      break;
+    }
+  return HDG_OK;
+}
+
 extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_phys *phys,
                                const hdg_opts *opts) {
   if (!out || !mesh || !phys) return fail(HDG_EINVAL, "null argument");

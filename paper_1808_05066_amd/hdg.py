@@ -171,6 +171,13 @@ class Plan:
         check(self.lib.hdg_plan_phase_times(self.h, ms, calls, n), "hdg_plan_phase_times")
         return {name: (ms[i], calls[i]) for i, name in enumerate(_lib.PHASES)}
 
+    def status(self, elem_status):
+        """(first element whose status is not HDG_OK, its code), (-1, 0) if none; synchronizes."""
+        first, code = ctypes.c_int(), ctypes.c_int()
+        check(self.lib.hdg_status(self.h, ctypes.c_void_p(elem_status.data_ptr()), _stream(), ctypes.byref(first),
+                                  ctypes.byref(code)), "hdg_status")
+        return first.value, code.value
+
     # -- mixed precision -----------------------------------------------------
     def lp_factor_bytes(self):
         nb = ctypes.c_size_t()

@@ -159,3 +159,7 @@ def test_nonphysical_state_is_flagged(torch):
     st = out["status"].cpu().numpy()
     assert st[bad] == -3
     assert np.count_nonzero(st) == 1
+    # the status reduction of the C-ABI names the same element and code
+    assert plan.status(out["status"]) == (bad, -3)
+    good = plan.assemble_condense(*(to_dev(inp)[key] for key in ("v", "q", "vhat", "ustar", "vbc")))
+    assert plan.status(good["status"]) == (-1, 0)
