@@ -78,15 +78,15 @@ struct Lds {
 // each thread keeps LU loads in flight before writing them to LDS)
 constexpr int LU = 8;
 
-template <typename T, int W>
+template <typename T, int W, int NTT = NT>
 __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, int np) {
   constexpr int BS = W + 1;
   const int total = np * W;
-  for (int t0 = threadIdx.x; t0 < total; t0 += LU * NT) {
+  for (int t0 = threadIdx.x; t0 < total; t0 += LU * NTT) {
     T v[LU];
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
-      const int t = t0 + u * NT;
+      const int t = t0 + u * NTT;
       if (t < total) {
         const int c = t / np, i = t - c * np;
         v[u] = M[(size_t)(c0 + c) * ld + s.perm[i]];
@@ -94,7 +94,7 @@ __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, i
     }
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
-      const int t = t0 + u * NT;
+      const int t = t0 + u * NTT;
       if (t < total) {
         const int c = t / np, i = t - c * np;
         s.blk[i * BS + c] = v[u];
@@ -105,15 +105,15 @@ __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, i
 
 // Low-precision load of FP64 columns: blk[i][c] = d_row * M[c0+c][perm[i]] * d_col
 // (colscale false: right-hand sides, rows scaled only).
-template <typename T, int W>
+template <typename T, int W, int NTT = NT>
 __device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int ld, int c0, int np, bool colscale) {
   constexpr int BS = W + 1;
   const int total = np * W;
-  for (int t0 = threadIdx.x; t0 < total; t0 += LU * NT) {
+  for (int t0 = threadIdx.x; t0 < total; t0 += LU * NTT) {
     double v[LU];
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
-      const int t = t0 + u * NT;
+      const int t = t0 + u * NTT;
       if (t < total) {
         const int c = t / np, i = t - c * np;
         v[u] = M[(size_t)(c0 + c) * ld + s.perm[i]];
@@ -121,7 +121,7 @@ __device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int l
     }
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
-      const int t = t0 + u * NT;
+      const int t = t0 + u * NTT;
       if (t < total) {
         const int c = t / np, i = t - c * np;
         double x = v[u] * s.dsc[s.perm[i]];
@@ -199,102 +199,6 @@ __device__ inline void inv_apply(const Lds<T> &s, T (&ia)[W / 4], int p0, const 
   }
 }
 
-// Inverses of the diagonal W x W blocks of the freshly factored panel (block rows
-// j0..j0+W-1): wave 0 inverts the unit-lower part, wave 1 the upper part; column c
-// of each inverse is solved by lane c.  Stored column-major (W x W) in Linv / Uinv.
-template <typename T, int W>
-__device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
-  constexpr int BS = W + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane >= W || wave > 1) return;
-  const int c = lane;
-  T x[W];
-  if (wave == 0) {
-#pragma unroll
-    for (int i = 0; i < W; ++i) x[i] = (i == c) ? T(1) : T(0);
-#pragma unroll
-    for (int kk = 0; kk < W; ++kk)
-#pragma unroll
-      for (int i = kk + 1; i < W; ++i) x[i] -= s.blk[(j0 + i) * BS + kk] * x[kk];
-#pragma unroll
-    for (int i = 0; i < W; ++i) Linv[c * W + i] = x[i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < W; ++i) x[i] = (i == c) ? T(1) : T(0);
-#pragma unroll
-    for (int kk = W - 1; kk >= 0; --kk) {
-      x[kk] /= s.blk[(j0 + kk) * BS + kk];
-#pragma unroll
-      for (int i = 0; i < kk; ++i) x[i] -= s.blk[(j0 + i) * BS + kk] * x[kk];
-    }
-#pragma unroll
-    for (int i = 0; i < W; ++i) Uinv[c * W + i] = x[i];
-  }
-}
-
-// blk[r][:] -= sum_kk M[(p0+kk) * ld + r] * blk[p0+kk][:]  for rows r in [r_lo, r_hi)
-// (stored factors are in pivot-position order, so the loads are contiguous;
-// r_lo, r_hi multiples of 16, disjoint from p0..p0+W-1).  The wave's first tile
-// arrives preloaded in a; the first tile of the next step is loaded into a at
-// the end.
-template <typename T, int W>
-__device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, int ld, const Step &st,
-                                   const Step &next) {
-  typedef Mfma<T> MF;
-  constexpr int BS = W + 1, TW = W / 16, KS = W / 4;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int p0 = st.p0, r_lo = st.r_lo;
-  const int ntile = st.r_hi > r_lo ? (st.r_hi - r_lo) / 16 : 0;
-  const T *Mp = M + (size_t)(p0 + lk) * ld;
-  T an[KS];
-  for (int t = wave; t < ntile; t += NW) {
-    const int r0 = r_lo + t * 16;
-    const int tn = t + NW;
-    if (tn < ntile) {
-      const size_t grow = (size_t)(r_lo + tn * 16 + li);
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk) an[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
-    }
-    typename MF::acc c[TW];
-#pragma unroll
-    for (int q = 0; q < TW; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) c[q][r] = s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li];
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const T *brow = s.blk + (p0 + 4 * kk + lk) * BS;
-#pragma unroll
-      for (int q = 0; q < TW; ++q) c[q] = MF::op(a[kk], brow[q * 16 + li], c[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < TW; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li] = c[q][r];
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) a[kk] = an[kk];
-  }
-  load_tile<T, W>(a, M, ld, next);
-}
-
-// A sequence of steps: spec(i) for i in [0, count), each applied with its
-// operands loaded one step ahead.
-template <typename T, int W, typename Spec>
-__device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int ld, int count, Spec spec) {
-  T ia[W / 4], a[W / 4];
-  Step cur = spec(0);
-  load_inv<T, W>(ia, Ie, cur);
-  load_tile<T, W>(a, Fm, ld, cur);
-  for (int i = 0; i < count; ++i) {
-    const Step nxt = (i + 1 < count) ? spec(i + 1) : Step{-1, 0, 0, 0};
-    inv_apply<T, W>(s, ia, cur.p0, Ie, nxt);
-    __syncthreads();
-    gemm_update<T, W>(s, a, Fm, ld, cur, nxt);
-    __syncthreads();
-    cur = nxt;
-  }
-}
-
 // Wave-wide reductions on the DPP network: within each row of 16 lanes by quad
 // permutations and row rotations (every lane ends with its row's result), then
 // across the four rows by reading lanes 0, 16, 32, 48.  All 64 lanes must be active.
@@ -339,6 +243,106 @@ __device__ inline int wave_min(int v) {
   v = min(v, dpp_i32<DPP_ROW_ROR8>(v));
   return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
              min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+// Inverses of the diagonal W x W blocks of the freshly factored panel (block rows
+// j0..j0+W-1): wave 0 inverts the unit-lower part, wave 1 the upper part; column c
+// of each inverse is solved by lane c.  Stored column-major (W x W) in Linv / Uinv.
+template <typename T, int W>
+__device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
+  constexpr int BS = W + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane >= W || wave > 1) return;
+  const int c = lane;
+  T x[W];
+  if (wave == 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i) x[i] = (i == c) ? T(1) : T(0);
+#pragma unroll
+    for (int kk = 0; kk < W; ++kk)
+#pragma unroll
+      for (int i = kk + 1; i < W; ++i) x[i] -= s.blk[(j0 + i) * BS + kk] * x[kk];
+#pragma unroll
+    for (int i = 0; i < W; ++i) Linv[c * W + i] = x[i];
+  } else {
+    // reciprocal of the diagonal entry of column c, one division per lane; lane kk's
+    // reciprocal is read by every lane in the sweep (no division in the dependent chain)
+    const T rc = T(1) / s.blk[(j0 + c) * BS + c];
+#pragma unroll
+    for (int i = 0; i < W; ++i) x[i] = (i == c) ? T(1) : T(0);
+#pragma unroll
+    for (int kk = W - 1; kk >= 0; --kk) {
+      x[kk] *= lane_val(rc, kk);
+#pragma unroll
+      for (int i = 0; i < kk; ++i) x[i] -= s.blk[(j0 + i) * BS + kk] * x[kk];
+    }
+#pragma unroll
+    for (int i = 0; i < W; ++i) Uinv[c * W + i] = x[i];
+  }
+}
+
+// blk[r][:] -= sum_kk M[(p0+kk) * ld + r] * blk[p0+kk][:]  for rows r in [r_lo, r_hi)
+// (stored factors are in pivot-position order, so the loads are contiguous;
+// r_lo, r_hi multiples of 16, disjoint from p0..p0+W-1).  The wave's first tile
+// arrives preloaded in a; the first tile of the next step is loaded into a at
+// the end.
+template <typename T, int W, int NTT = NT>
+__device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, int ld, const Step &st,
+                                   const Step &next) {
+  constexpr int NWT = NTT / 64;
+  typedef Mfma<T> MF;
+  constexpr int BS = W + 1, TW = W / 16, KS = W / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int p0 = st.p0, r_lo = st.r_lo;
+  const int ntile = st.r_hi > r_lo ? (st.r_hi - r_lo) / 16 : 0;
+  const T *Mp = M + (size_t)(p0 + lk) * ld;
+  T an[KS];
+  for (int t = wave; t < ntile; t += NWT) {
+    const int r0 = r_lo + t * 16;
+    const int tn = t + NWT;
+    if (tn < ntile) {
+      const size_t grow = (size_t)(r_lo + tn * 16 + li);
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) an[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
+    }
+    typename MF::acc c[TW];
+#pragma unroll
+    for (int q = 0; q < TW; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c[q][r] = s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const T *brow = s.blk + (p0 + 4 * kk + lk) * BS;
+#pragma unroll
+      for (int q = 0; q < TW; ++q) c[q] = MF::op(a[kk], brow[q * 16 + li], c[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < TW; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li] = c[q][r];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) a[kk] = an[kk];
+  }
+  load_tile<T, W>(a, M, ld, next);
+}
+
+// A sequence of steps: spec(i) for i in [0, count), each applied with its
+// operands loaded one step ahead.
+template <typename T, int W, typename Spec, int NTT = NT>
+__device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int ld, int count, Spec spec) {
+  T ia[W / 4], a[W / 4];
+  Step cur = spec(0);
+  load_inv<T, W>(ia, Ie, cur);
+  load_tile<T, W>(a, Fm, ld, cur);
+  for (int i = 0; i < count; ++i) {
+    const Step nxt = (i + 1 < count) ? spec(i + 1) : Step{-1, 0, 0, 0};
+    inv_apply<T, W>(s, ia, cur.p0, Ie, nxt);
+    __syncthreads();
+    gemm_update<T, W, NTT>(s, a, Fm, ld, cur, nxt);
+    __syncthreads();
+    cur = nxt;
+  }
 }
 
 // LU with partial pivoting of block rows j0..np-1 (block columns 0..W-1), in
@@ -722,7 +726,7 @@ __device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &
 // perm (and the scaling) in LDS: permutation gather, forward and backward
 // sweeps against the stored factors, outputs Y, z, then the Schur product
 // C * Y_block straight from LDS into S and g.
-template <typename T, bool LP, int W>
+template <typename T, bool LP, int W, int NTT = NT>
 __device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c0, const Lds<T> &s,
                                           const FactorPtrs<T, LP> &f, T *S, double *g, T *Y, double *z) {
   typedef Mfma<T> MF;
@@ -739,32 +743,34 @@ __device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c
   double *ge = g + (size_t)e * k;
   T *Ye = Y + (size_t)e * n * k;
   const int ntr = kp / 16;
-  if constexpr (LP) load_block_scaled<T, W>(s, X, np, c0, np, false);
-  else load_block<T, W>(s, X, np, c0, np);
+  if constexpr (LP) load_block_scaled<T, W, NTT>(s, X, np, c0, np, false);
+  else load_block<T, W, NTT>(s, X, np, c0, np);
   __syncthreads();
   // forward (unit lower) then backward (upper) sweep as one pipelined sequence
-  run_steps<T, W>(s, f.Inv, f.F, np, 2 * nJ, [&](int i) {
+  const auto rhs_spec = [&](int i) {
     if (i < nJ) return Step{i * 2 * W * W, i * W, i * W + W, np};
     const int Pb = 2 * nJ - 1 - i;
     return Step{Pb * 2 * W * W + W * W, Pb * W, 0, Pb * W};
-  });
+  };
+  run_steps<T, W, decltype(rhs_spec), NTT>(s, f.Inv, f.F, np, 2 * nJ, rhs_spec);
+
   if constexpr (LP) {
     // undo the column scaling: Y = D Y_hat, z = D z_hat
-    for (int t = tid; t < np * W; t += NT) {
+    for (int t = tid; t < np * W; t += NTT) {
       const int c = t / np, i = t - c * np;
       s.blk[i * BS + c] = (T)((double)s.blk[i * BS + c] * s.dsc[i]);
     }
     __syncthreads();
   }
   // outputs Y, z (compact)
-  for (int t = tid; t < n * W; t += NT) {
+  for (int t = tid; t < n * W; t += NTT) {
     const int c = t / n, i = t - c * n;
     const int col = c0 + c;
     if (col < k) Ye[(size_t)col * n + i] = s.blk[i * BS + c];
     else if (col == kp) z[(size_t)e * n + i] = (double)s.blk[i * BS + c];
   }
   // T = C * block (k_pad x W): S = D - T, g = -R_tr + T
-  for (int t = wave; t < ntr; t += NW) {
+  for (int t = wave; t < ntr; t += NTT / 64) {
     const int r0 = t * 16;
     typename MF::acc acc[TW];
 #pragma unroll
@@ -832,7 +838,7 @@ __device__ __forceinline__ void lu_body(const DevPlan &P, int e0, int el, int32_
 
 constexpr int NXCD = 8;
 
-template <typename T, bool LP, int W>
+template <typename T, bool LP, int W, int NTT = NT>
 __device__ __forceinline__ void rhs_body(const DevPlan &P, int e0, int ec, T *S, double *g, T *Y, double *z, T *inv,
                                          float *fac) {
   const int nrb = P.kx / W;
@@ -845,21 +851,24 @@ __device__ __forceinline__ void rhs_body(const DevPlan &P, int e0, int ec, T *S,
   const FactorPtrs<T, LP> f = factor_ptrs<T, LP>(P, e, el, inv, fac);
   const int *perm = LP ? reinterpret_cast<const int *>(f.rec + rec_perm_off(np)) : P.ipiv + (size_t)el * np;
   const double *A64 = P.A + (size_t)el * np * np;
-  for (int i = threadIdx.x; i < np; i += NT) {
+  for (int i = threadIdx.x; i < np; i += NTT) {
     s.perm[i] = perm[i];
     if constexpr (LP) s.dsc[i] = diag_scale(A64, np, i);
   }
   __syncthreads();
-  rhs_block<T, LP, W>(P, e, el, j * W, s, f, S, g, Y, z);
+  rhs_block<T, LP, W, NTT>(P, e, el, j * W, s, f, S, g, Y, z);
 }
 
 __global__ __launch_bounds__(NT) void k_lu_f64_w32(DevPlan P, int e0, int32_t *status, double *inv) {
   lu_body<double, false, 32>(P, e0, blockIdx.x, status, inv, nullptr);
 }
 
-__global__ __launch_bounds__(NT) void k_rhs_f64_w32(DevPlan P, int e0, int ec, double *S, double *g, double *Y,
-                                                    double *z, double *inv) {
-  rhs_body<double, false, 32>(P, e0, ec, S, g, Y, z, inv, nullptr);
+// right-hand sides: one workgroup per CU (LDS) with few registers, so 16 waves
+constexpr int NT_RHS = 1024;
+
+__global__ __launch_bounds__(NT_RHS) void k_rhs_f64_w32(DevPlan P, int e0, int ec, double *S, double *g, double *Y,
+                                                        double *z, double *inv) {
+  rhs_body<double, false, 32, NT_RHS>(P, e0, ec, S, g, Y, z, inv, nullptr);
 }
 
 template <int W>
@@ -1014,11 +1023,16 @@ size_t condense_inv_doubles(int np) { return 2 * (size_t)np * WMAX; }
 size_t lp_record_bytes(int np) { return lp_rec_floats(np) * sizeof(float); }
 
 template <typename K, typename... Args>
-hipError_t launch_dyn(K kern, int ec, size_t lds, hipStream_t s, Args... args) {
+hipError_t launch_dyn_t(K kern, int ec, int nt, size_t lds, hipStream_t s, Args... args) {
   hipError_t e = set_dyn_lds((const void *)kern, lds);
   if (e) return e;
-  hipLaunchKernelGGL(kern, dim3(ec), dim3(NT), lds, s, args...);
+  hipLaunchKernelGGL(kern, dim3(ec), dim3(nt), lds, s, args...);
   return hipGetLastError();
+}
+
+template <typename K, typename... Args>
+hipError_t launch_dyn(K kern, int ec, size_t lds, hipStream_t s, Args... args) {
+  return launch_dyn_t(kern, ec, NT, lds, s, args...);
 }
 
 // grid of the right-hand-side launch: element slots rounded up to the XCD count, times the blocks
@@ -1032,8 +1046,8 @@ hipError_t launch_condense_lu(const DevPlan &P, int e0, int ec, int32_t *status,
 
 hipError_t launch_condense_rhs(const DevPlan &P, int e0, int ec, double *S, double *g, double *Y, double *z,
                                hipStream_t s) {
-  return launch_dyn(k_rhs_f64_w32, rhs_grid(P, ec, 32), condense_lds_bytes(P.n_pad, 32), s, P, e0, ec, S, g, Y, z,
-                    P.inv);
+  return launch_dyn_t(k_rhs_f64_w32, rhs_grid(P, ec, 32), NT_RHS, condense_lds_bytes(P.n_pad, 32), s, P, e0, ec, S,
+                      g, Y, z, P.inv);
 }
 
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
