@@ -89,7 +89,7 @@ typedef struct {
   int n_trace;             /* number of global trace nodes */
 } hdg_mesh;
 
-enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2 };
+enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2, HDG_FLAG_ELIMINATE_Q = 4 };
 
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */
@@ -98,7 +98,14 @@ typedef struct {
                               block contraction; separate LU / solve / Schur kernels)
                               instead of the matrix-core contraction and the fused
                               left-looking condensation used by default when their LDS
-                              working sets fit */
+                              working sets fit.
+                              HDG_FLAG_ELIMINATE_Q (Navier-Stokes): hdg_assemble_condense
+                              first eliminates the gradient unknowns q element by element
+                              (their block is the mass matrix times the identity), then
+                              condenses the m N_p x m N_p block of v; same outputs S, g,
+                              Y, z (to rounding) with 4x smaller dense factorizations.
+                              FP64 hdg_assemble_condense only (the FP32 path and batches
+                              condense the full block). */
 } hdg_opts;
 
 typedef struct {

@@ -18,6 +18,7 @@ PHASES = ["points", "contract", "lu", "solve", "schur", "backsolve", "matvec", "
           "lp_solve", "jvp", "condense_lu", "condense_rhs"]
 FLAG_SPLIT_DENSE = 1
 FLAG_NARROW_BLOCK = 2
+FLAG_ELIMINATE_Q = 4
 
 
 class hdg_phys(ctypes.Structure):

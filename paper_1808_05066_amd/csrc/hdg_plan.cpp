@@ -318,6 +318,20 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   L.fW = o; o += 1;
   L.fsize = o;
   P->contract_mfma = contract_mfma_supported(D) && !(opts && (opts->flags & HDG_FLAG_SPLIT_DENSE));
+  if (opts && (opts->flags & HDG_FLAG_ELIMINATE_Q)) {
+    const int nv = D.m * D.Np;
+    P->qa.nr_pad = roundup(nv, 32);
+    if (!D.viscous) {
+      delete P;
+      return fail(HDG_EINVAL, "HDG_FLAG_ELIMINATE_Q needs a Navier-Stokes plan (gradient unknowns)");
+    }
+    if (qelim_lds_bytes(D) > 160 * 1024 || D.Np + D.nf * D.Nfp > 112 || !condense_width(P->qa.nr_pad, false) ||
+        !P->fused) {
+      delete P;
+      return fail(HDG_EUNSUPPORTED, "q elimination: element too large for its LDS working sets");
+    }
+    P->qelim = true;
+  }
   *out = reinterpret_cast<hdg_plan *>(P);
   return HDG_OK;
 }
@@ -391,7 +405,8 @@ namespace {
 struct Layout {
   size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x;
   size_t bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos, tables_end;
-  size_t pv, pf, A, X, C, D, Rt, ipiv, inv, total;
+  size_t pv, pf, A, X, C, D, Rt, ipiv, inv;
+  size_t rA, rX, rC, rD, rRt, rMH, rYv, rzv, ripiv, rinv, total;
 };
 
 Layout layout(const Plan *P) {
@@ -431,6 +446,19 @@ Layout layout(const Plan *P) {
   l.Rt = take(ch * (size_t)D.k_pad * 8);
   l.ipiv = take(ch * (size_t)D.n_pad * 4);
   l.inv = take(P->fused ? ch * condense_inv_doubles(D.n_pad) * 8 : 0);
+  if (P->qelim) {
+    const size_t nr = P->qa.nr_pad, nv = (size_t)D.m * D.Np;
+    l.rA = take(ch * nr * nr * 8);
+    l.rX = take(ch * (size_t)D.kx * nr * 8);
+    l.rC = take(ch * nr * D.k_pad * 8);
+    l.rD = take(ch * (size_t)D.k_pad * D.k_pad * 8);
+    l.rRt = take(ch * (size_t)D.k_pad * 8);
+    l.rMH = take(ch * (size_t)(1 + D.dim) * D.Np * D.Np * 8);
+    l.rYv = take(ch * (size_t)D.k * nv * 8);
+    l.rzv = take(ch * nv * 8);
+    l.ripiv = take(ch * nr * 4);
+    l.rinv = take(ch * condense_inv_doubles((int)nr) * 8);
+  }
   l.total = o;
   return l;
 }
@@ -537,6 +565,19 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   D.Rt = reinterpret_cast<double *>(base + l.Rt);
   D.ipiv = reinterpret_cast<int *>(base + l.ipiv);
   D.inv = reinterpret_cast<double *>(base + l.inv);
+  if (P->qelim) {
+    QElimArgs &Q = P->qa;
+    Q.A = reinterpret_cast<double *>(base + l.rA);
+    Q.X = reinterpret_cast<double *>(base + l.rX);
+    Q.C = reinterpret_cast<double *>(base + l.rC);
+    Q.D = reinterpret_cast<double *>(base + l.rD);
+    Q.Rt = reinterpret_cast<double *>(base + l.rRt);
+    Q.MH = reinterpret_cast<double *>(base + l.rMH);
+    Q.Yv = reinterpret_cast<double *>(base + l.rYv);
+    Q.zv = reinterpret_cast<double *>(base + l.rzv);
+    P->rp.ipiv = reinterpret_cast<int *>(base + l.ripiv);
+    P->rp.inv = reinterpret_cast<double *>(base + l.rinv);
+  }
   P->ws = dev;
   P->ws_bytes = bytes;
   P->bound = true;
@@ -615,6 +656,20 @@ int run_front(Plan *P, const double *v, const double *q, const double *vhat, con
   return HDG_OK;
 }
 
+// FP64 condensation of one chunk with descriptor Dp (the plan's, or the reduced one of the q
+// elimination); outputs indexed from element e0 of Dp's numbering
+hipError_t condense_chunk(Plan *P, const DevPlan &Dp, int e0, int ec, int32_t *status, double *S, double *g,
+                          double *Y, double *z, hipStream_t s) {
+  if (!condense_two_launches(Dp)) return launch_condense(Dp, e0, ec, status, S, g, Y, z, s);
+  hipError_t e = phase_begin(P, PH_CONDENSE_LU, s);
+  if (!e) e = launch_condense_lu(Dp, e0, ec, status, s);
+  if (!e) e = phase_end(P, PH_CONDENSE_LU, s);
+  if (!e) e = phase_begin(P, PH_CONDENSE_RHS, s);
+  if (!e) e = launch_condense_rhs(Dp, e0, ec, S, g, Y, z, s);
+  if (!e) e = phase_end(P, PH_CONDENSE_RHS, s);
+  return e;
+}
+
 int check_inputs(const Plan *P, const double *v, const double *q, const double *vhat,
                  const double *ustar, int32_t *status) {
   if (!v || !vhat || !status) return fail(HDG_EINVAL, "v, vhat and elem_status are required");
@@ -665,15 +720,26 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
     if (!e && !P->fused && !P->split_ok) return fail(HDG_EUNSUPPORTED, "FP64 condensation: local block too large");
     if (!e && P->fused) {
       e = phase_begin(P, PH_CONDENSE, s);
-      if (!e && condense_two_launches(P->dp)) {
-        e = phase_begin(P, PH_CONDENSE_LU, s);
-        if (!e) e = launch_condense_lu(P->dp, e0, ec, status + e0, s);
-        if (!e) e = phase_end(P, PH_CONDENSE_LU, s);
-        if (!e) e = phase_begin(P, PH_CONDENSE_RHS, s);
-        if (!e) e = launch_condense_rhs(P->dp, e0, ec, S, g, Y, z, s);
-        if (!e) e = phase_end(P, PH_CONDENSE_RHS, s);
+      if (!e && P->qelim) {
+        // eliminate q, condense the m N_p block of v (outputs of the slots 0..ec-1), recover the q rows
+        DevPlan r = P->dp;
+        r.n = P->dp.m * P->dp.Np;
+        r.n_pad = P->qa.nr_pad;
+        r.cw = condense_width(r.n_pad, false);
+        r.A = P->qa.A;
+        r.X = P->qa.X;
+        r.C = P->qa.C;
+        r.D = P->qa.D;
+        r.Rt = P->qa.Rt;
+        r.ipiv = P->rp.ipiv;
+        r.inv = P->rp.inv;
+        const size_t k = P->dp.k;
+        e = launch_qelim(P->dp, P->qa, ec, s);
+        if (!e) e = condense_chunk(P, r, 0, ec, status + e0, S + (size_t)e0 * k * k, g + (size_t)e0 * k, P->qa.Yv,
+                                   P->qa.zv, s);
+        if (!e) e = launch_qrecover(P->dp, P->qa, e0, ec, Y, z, s);
       } else if (!e) {
-        e = launch_condense(P->dp, e0, ec, status + e0, S, g, Y, z, s);
+        e = condense_chunk(P, P->dp, e0, ec, status + e0, S, g, Y, z, s);
       }
       if (!e) e = phase_end(P, PH_CONDENSE, s);
       if (e) return hip_fail(e, "condense");

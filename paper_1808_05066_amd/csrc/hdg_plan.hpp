@@ -64,6 +64,21 @@ enum Phase {
   PH_CONDENSE_LP, PH_LP_SOLVE, PH_JVP, PH_CONDENSE_LU, PH_CONDENSE_RHS, PH_COUNT
 };
 
+// Buffers of the q elimination, per chunk slot: the reduced block (n_r = m N_p,
+// padded to nr_pad) in the layout of the condensation, M^-1 and H_j, and the v
+// rows of Y and z from the reduced condensation.
+struct QElimArgs {
+  int nr_pad;
+  double *A;    // [chunk][nr_pad][nr_pad]
+  double *X;    // [chunk][kx][nr_pad]
+  double *C;    // [chunk][nr_pad][k_pad]
+  double *D;    // [chunk][k_pad][k_pad]
+  double *Rt;   // [chunk][k_pad]
+  double *MH;   // [chunk][1 + dim][Np][Np]
+  double *Yv;   // [chunk][k][m Np]
+  double *zv;   // [chunk][m Np]
+};
+
 struct Plan {
   RefTables ref;
   bool timing = false;
@@ -87,7 +102,17 @@ struct Plan {
   size_t off_tables_end = 0;
   bool bound = false;
   bool xcd_clean = false;   // workspace X, C, D hold this plan's structural zeros (one chunk)
+  // element-local elimination of q (HDG_FLAG_ELIMINATE_Q): reduced condensation plan and buffers
+  bool qelim = false;
+  DevPlan rp{};
+  QElimArgs qa{};
 };
+
+// q elimination (hdg_qelim.hip)
+size_t qelim_lds_bytes(const DevPlan &P);
+hipError_t launch_qelim(const DevPlan &P, const QElimArgs &Q, int ec, hipStream_t s);
+hipError_t launch_qrecover(const DevPlan &P, const QElimArgs &Q, int e0, int ec, double *Y, double *z,
+                           hipStream_t s);
 
 // plan helpers shared by the entry-point sources (hdg_plan.cpp)
 Plan *checked(hdg_plan *plan);   // null or unbound plan -> nullptr with the error recorded

@@ -16,11 +16,11 @@ def oracle_case(wl):
     return disc, ostate.oracle_inputs(wl, disc)
 
 
-def gpu_plan(wl, chunk_elems=0, split_dense=False, narrow_block=False):
+def gpu_plan(wl, chunk_elems=0, split_dense=False, narrow_block=False, eliminate_q=False):
     from paper_1808_05066_amd.hdg import Plan
     return Plan(wl.mesh.etype, wl.p, wl.mesh.elem_xyz, wl.tmap, wl.n_trace, wl.face_bc, viscous=wl.viscous,
                 gamma=wl.gamma, mu=wl.mu, Pr=wl.Pr, alpha=wl.alpha, chunk_elems=chunk_elems,
-                split_dense=split_dense, narrow_block=narrow_block)
+                split_dense=split_dense, narrow_block=narrow_block, eliminate_q=eliminate_q)
 
 
 def to_dev(inp):

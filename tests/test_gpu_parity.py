@@ -163,3 +163,40 @@ def test_nonphysical_state_is_flagged(torch):
     assert plan.status(out["status"]) == (bad, -3)
     good = plan.assemble_condense(*(to_dev(inp)[key] for key in ("v", "q", "vhat", "ustar", "vbc")))
     assert plan.status(good["status"]) == (-1, 0)
+
+
+VISCOUS_CASES = [n for n in SMALL_CASES if n.startswith("ns")]
+
+
+@pytest.mark.parametrize("name", VISCOUS_CASES)
+@pytest.mark.parametrize("chunk,launches", [(0, 2), (3, 1)])
+def test_q_elimination_matches_oracle(torch, name, chunk, launches):
+    """HDG_FLAG_ELIMINATE_Q: the gradient unknowns eliminated element by element, then the
+    m N_p block of v condensed; S, Y (all rows), g, z against the oracle's dense condensation."""
+    wl, disc, inp, blocks = _case(name)
+    print("case", name, "chunk", chunk, "launches", launches, flush=True)
+    plan = gpu_plan(wl, chunk_elems=chunk, eliminate_q=True)
+    plan.set_tuning(condense_launches=launches)
+    d = to_dev(inp)
+    out = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], residuals=True)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().max()) == 0
+    errs = {
+        "S": rel_err_per_elem(out["S"].cpu().numpy(), colmajor([b["S"] for b in blocks])),
+        "Y": rel_err_per_elem(out["Y"].cpu().numpy(), colmajor([b["Y"] for b in blocks])),
+        "g": rel_err_per_elem(out["g"].cpu().numpy(), np.stack([b["g"] for b in blocks])),
+        "z_backward": max(z_backward_err(disc, inp, e, b["A"], b["R_loc"], out["z"][e].cpu().numpy())
+                          for e, b in enumerate(blocks)),
+    }
+    print(name, errs)
+    for key, err in errs.items():
+        assert err <= TOL, (key, err)
+    zf = rel_err_per_elem(out["z"].cpu().numpy(), np.stack([b["z"] for b in blocks]))
+    assert zf <= 1e-11, zf
+
+
+def test_q_elimination_needs_gradient_unknowns(torch):
+    from paper_1808_05066_amd import _lib
+    wl, _, _, _ = _case("euler2d_tri_p2")
+    with pytest.raises(_lib.HdgError):
+        gpu_plan(wl, eliminate_q=True)
