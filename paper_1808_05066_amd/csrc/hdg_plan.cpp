@@ -325,7 +325,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
       delete P;
       return fail(HDG_EINVAL, "HDG_FLAG_ELIMINATE_Q needs a Navier-Stokes plan (gradient unknowns)");
     }
-    if (qelim_lds_bytes(D) > 160 * 1024 || D.Np + D.nf * D.Nfp > 112 || !condense_width(P->qa.nr_pad, false) ||
+    if (qelim_lds_bytes(D) > 160 * 1024 || D.Np + D.nf * D.Nfp + 1 > 112 || !condense_width(P->qa.nr_pad, false) ||
         !P->fused) {
       delete P;
       return fail(HDG_EUNSUPPORTED, "q elimination: element too large for its LDS working sets");

@@ -21,12 +21,12 @@ namespace hdg {
 namespace {
 
 constexpr int QT = 512;   // threads per workgroup
-constexpr int QCB = 16;   // right-hand-side columns per pass
+constexpr int QCB = 16;   // right-hand-side columns per recovery pass
 
 // LDS carve-up (doubles): mass matrix inverse, H_j, and a region shared by the
 // Gauss-Jordan work array and the W columns of a pass.
 struct QLds {
-  int mi, hh, w, xs, total;
+  int mi, hh, w, xs, ti, total;
 };
 
 __host__ __device__ inline QLds q_lds(int Np, int D, int M, int ntc) {
@@ -36,16 +36,32 @@ __host__ __device__ inline QLds q_lds(int Np, int D, int M, int ntc) {
   L.w = L.hh + D * Np * Np;
   const int gj = Np * 2 * Np;
   const int wc = QCB * D * Np + (M * D * Np > QCB * M * Np ? M * D * Np : QCB * M * Np);
-  const int rcb = ((D * Np + 3) & ~3) * 7 * 16;   // R_c of the q elimination (QCT column tiles)
+  const int rcb = ((D * Np + 15) & ~15) * 7 * 16;   // R_c of the q elimination (up to 7 column tiles)
   int w = gj > wc ? gj : wc;
   if (rcb > w) w = rcb;
   L.xs = L.w + w;
-  // staged q rows of X: the residual (M D Np), a component's trace columns (ntc x D Np)
+  // staged q rows of X: the residual (M D Np), a component's trace columns and residual ((ntc + 1) x D Np)
   // or the columns of a recovery pass (QCB x D Np)
   int nq = M * D * Np;
-  if (ntc * D * Np > nq) nq = ntc * D * Np;
+  if ((ntc + 1) * D * Np > nq) nq = (ntc + 1) * D * Np;
   if (QCB * D * Np > nq) nq = QCB * D * Np;
-  L.total = L.xs + nq;
+  L.ti = L.xs + nq;
+  L.total = L.ti + 56;   // int table of up to 112 trace columns
+  return L;
+}
+
+// LDS of the recovery, in doubles: M^-1, H_j, W_B of a pass (or of the residual), the pass's
+// Y_v columns and B_q rows; small enough for two workgroups per CU at N_p = 27.
+struct QRecLds {
+  int hh, wb, ys, xs, total;
+};
+__host__ __device__ inline QRecLds qrec_lds(int Np, int D, int M) {
+  QRecLds L;
+  L.hh = Np * Np;
+  L.wb = L.hh + D * Np * Np;
+  L.ys = L.wb + (QCB * D * Np > M * D * Np ? QCB * D * Np : M * D * Np);
+  L.xs = L.ys + QCB * M * Np;
+  L.total = L.xs + QCB * D * Np;
   return L;
 }
 
@@ -101,12 +117,16 @@ __device__ inline d4 mfma4(double a, double b, d4 c) { return __builtin_amdgcn_m
 // Per element; for each component c the products of the q columns of c with
 // R_c = [H (v columns of c) | W_B (trace columns of c)] form one GEMM on the
 // FP64 matrix cores: rows = the v rows of A (A_vq) followed by the trace rows
-// of C (C_q), K = D N_p, N = N_p + nf N_fp.  Lane l supplies the operand row
-// tile*16 + l%16 at k = k0 + l/16 (A operand, streamed from the column-major
-// blocks) and R_c[k0 + l/16][ct*16 + l%16] (B operand, LDS); accumulator r of
-// lane l is the output (row tile*16 + l/16 + 4r, column ct*16 + l%16).
-constexpr int QCT = 7;   // column tiles of R_c (N_p + nf N_fp <= 112)
+// of C (C_q), K = D N_p, N = N_p + nf N_fp + 1 (the last column is the
+// residual).  The product is formed transposed so that outputs leave in
+// column-major runs: lane l supplies R_c[k0 + l/16][ct*16 + l%16] (MFMA A
+// operand, LDS) and the operand row tile*16 + l%16 at k = k0 + l/16 (MFMA B
+// operand, streamed from the column-major blocks); accumulator r of lane l is
+// the output (row tile*16 + l%16, column ct*16 + l/16 + 4r).
+// NCT column tiles of R_c (N_p + nf N_fp + 1 <= 16 NCT <= 112); at most QKS k-steps (D N_p <= 4 QKS)
+constexpr int QKS = 28;
 
+template <int NCT>
 __global__ __launch_bounds__(QT) void k_qelim(DevPlan P, QElimArgs Q) {
   extern __shared__ double sm[];
   const int el = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -128,24 +148,29 @@ __global__ __launch_bounds__(QT) void k_qelim(DevPlan P, QElimArgs Q) {
   double *mi = sm + L.mi, *hh = sm + L.hh, *rc = sm + L.w, *xs = sm + L.xs;
   mass_and_h(P, A, mi, hh, rc, MH);
 
-  const int ncol = Np + nf * Nfp;          // columns of R_c
+  int *tcb = reinterpret_cast<int *>(sm + L.ti);   // trace column of R_c column Np + fi, less c Nfp
+  for (int fi = tid; fi < nf * Nfp; fi += QT) tcb[fi] = (fi / Nfp) * MF + fi % Nfp;
+  const int ntc = nf * Nfp;                // trace columns of one component
+  const int ncr = Np + ntc;                // column of R_c holding the residual
   const int nrow = nv + kp;                // operand rows: A_vq then C_q
   const int nrt = (nrow + 15) / 16;
-  const int K4 = (DN + 3) & ~3;
-  const int ntc = nf * Nfp;                // trace columns of one component
+  const int K16 = (DN + 15) & ~15, KS = (DN + 3) / 4;
   for (int c = 0; c < M; ++c) {
     __syncthreads();
-    // B_q rows of component c of its trace columns, xs[fi][ja] (contiguous in the column)
-    for (int t = tid; t < ntc * DN; t += QT) {
+    // B_q rows of component c of its trace columns, xs[fi][ja] (contiguous in the column), then
+    // the R_q rows of component c
+    for (int t = tid; t < (ntc + 1) * DN; t += QT) {
       const int fi = t / DN, ja = t % DN;
-      xs[t] = X[(size_t)((fi / Nfp) * MF + c * Nfp + fi % Nfp) * np + nv + c * DN + ja];
+      const int col = fi < ntc ? (fi / Nfp) * MF + c * Nfp + fi % Nfp : kp;
+      xs[t] = X[(size_t)col * np + nv + c * DN + ja];
     }
     __syncthreads();
-    // R_c[(j, a)][col]: H_j[a][b] for col = b < Np; W_B for trace column f Nfp + ib of component c
-    for (int t = tid; t < K4 * QCT * 16; t += QT) {
-      const int col = t % (QCT * 16), ja = t / (QCT * 16);
+    // R_c[(j, a)][col]: H_j[a][b] for col = b < Np; W_B for trace column f Nfp + ib of component c;
+    // W_R (component c) in column ncr
+    for (int t = tid; t < K16 * NCT * 16; t += QT) {
+      const int col = t % (NCT * 16), ja = t / (NCT * 16);
       double val = 0.0;
-      if (ja < DN && col < ncol) {
+      if (ja < DN && col <= ncr) {
         const int j = ja / Np, a = ja % Np;
         if (col < Np) {
           val = hh[(j * Np + col) * Np + a];
@@ -154,10 +179,11 @@ __global__ __launch_bounds__(QT) void k_qelim(DevPlan P, QElimArgs Q) {
           for (int q = 0; q < Np; ++q) val += mi[q * Np + a] * xq[q];
         }
       }
-      rc[t] = val;   // rc[ja][col], row stride QCT * 16
+      rc[t] = -val;   // -R_c[ja][col], row stride NCT * 16
     }
     __syncthreads();
-    for (int rt = wave; rt < nrt; rt += QT / 64) {
+    // the operands of a row tile (all k-steps) are loaded one row tile ahead of the MFMAs
+    auto load_ops = [&](double (&ob)[QKS], int rt) {
       const int row = rt * 16 + li;   // operand row of this lane
       const double *src = nullptr;    // column (nv + c DN + ja) of A or C at this row
       size_t ld = 0;
@@ -168,65 +194,95 @@ __global__ __launch_bounds__(QT) void k_qelim(DevPlan P, QElimArgs Q) {
         src = C + (size_t)(nv + c * DN) * kp + (row - nv);
         ld = kp;
       }
-      d4 acc[QCT];
 #pragma unroll
-      for (int ct = 0; ct < QCT; ++ct) acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < K4; k0 += 4) {
-        const int ja = k0 + lk;
-        const double av = (src && ja < DN) ? src[(size_t)ja * ld] : 0.0;
-        const double *rr = rc + ja * (QCT * 16) + li;
-#pragma unroll
-        for (int ct = 0; ct < QCT; ++ct) acc[ct] = mfma4(av, rr[ct * 16], acc[ct]);
+      for (int ks = 0; ks < QKS; ++ks) {
+        const int ja = 4 * ks + lk;
+        ob[ks] = (ks < KS && src && ja < DN) ? src[(size_t)ja * ld] : 0.0;
       }
-      // outputs: original entry minus the product
+    };
+    // outputs: original entry minus the product.  The accumulators start from the original
+    // entries (the residual column accumulates over c; the same lane owns an output entry for
+    // every c) and the MFMAs add the operand times -R_c, so the results are stored as they are.
+    // (The column offset is made opaque per row tile so that the column address arithmetic is
+    // not hoisted out of the row-tile loop into registers.)
+    auto src_of = [&](int col, int orow) -> const double * {
+      const bool vrow = orow < nv;
+      const int trow = orow - nv;
+      if (col < Np) {
+        const size_t cv = c * Np + col;
+        return vrow ? A + cv * np + orow : C + cv * kp + trow;
+      }
+      if (col < ncr) {
+        const size_t tc = tcb[col - Np] + c * Nfp;
+        return vrow ? X + tc * np + orow : Dm + tc * kp + trow;
+      }
+      if (vrow) return c == 0 ? X + (size_t)kp * np + orow : Xr + (size_t)kp * nr + orow;
+      return c == 0 ? Rt + trow : Rtr + trow;
+    };
+    auto dst_of = [&](int col, int orow) -> double * {
+      const bool vrow = orow < nv;
+      const int trow = orow - nv;
+      if (col < Np) {
+        const size_t cv = c * Np + col;
+        return vrow ? Ar + cv * nr + orow : Cr + cv * kp + trow;
+      }
+      if (col < ncr) {
+        const size_t tc = tcb[col - Np] + c * Nfp;
+        return vrow ? Xr + tc * nr + orow : Dr + tc * kp + trow;
+      }
+      return vrow ? Xr + (size_t)kp * nr + orow : Rtr + trow;
+    };
+    auto init = [&](d4 (&acc)[NCT], int rt) {
+      const int orow = rt * 16 + li;
+      int cb = lk;
+      asm volatile("" : "+v"(cb));
 #pragma unroll
-      for (int ct = 0; ct < QCT; ++ct) {
-        const int col = ct * 16 + li;
-        if (col >= ncol) continue;
+      for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int orow = rt * 16 + lk + 4 * r;
-          if (orow >= nrow) continue;
-          const double v = acc[ct][r];
-          if (col < Np) {
-            const int cv = c * Np + col;
-            if (orow < nv) Ar[(size_t)cv * nr + orow] = A[(size_t)cv * np + orow] - v;
-            else Cr[(size_t)cv * kp + orow - nv] = C[(size_t)cv * kp + orow - nv] - v;
-          } else {
-            const int fi = col - Np, tc = (fi / Nfp) * MF + c * Nfp + fi % Nfp;
-            if (orow < nv) Xr[(size_t)tc * nr + orow] = X[(size_t)tc * np + orow] - v;
-            else Dr[(size_t)tc * kp + orow - nv] = Dm[(size_t)tc * kp + orow - nv] - v;
-          }
+          const int col = ct * 16 + cb + 4 * r;
+          acc[ct][r] = (orow < nrow && col <= ncr) ? *src_of(col, orow) : 0.0;
         }
+    };
+    auto mma = [&](d4 (&acc)[NCT], const double (&ob)[QKS]) {
+#pragma unroll
+      for (int ks = 0; ks < QKS; ++ks) {
+        if (ks >= KS) break;
+        const double *rr = rc + (4 * ks + lk) * (NCT * 16) + li;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[ct] = mfma4(rr[ct * 16], ob[ks], acc[ct]);
       }
+    };
+    auto store = [&](const d4 (&acc)[NCT], int rt) {
+      const int orow = rt * 16 + li;
+      if (orow >= nrow) return;
+      int cb = lk;
+      asm volatile("" : "+v"(cb));
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = ct * 16 + cb + 4 * r;
+          if (col <= ncr) *dst_of(col, orow) = acc[ct][r];
+        }
+    };
+    constexpr int NW = QT / 64;
+    double o0[QKS], o1[QKS];
+    d4 acc[NCT];
+    if (wave < nrt) load_ops(o0, wave);
+    for (int rt = wave; rt < nrt; rt += 2 * NW) {
+      init(acc, rt);
+      if (rt + NW < nrt) load_ops(o1, rt + NW);
+      mma(acc, o0);
+      store(acc, rt);
+      if (rt + NW >= nrt) break;
+      init(acc, rt + NW);
+      if (rt + 2 * NW < nrt) load_ops(o0, rt + 2 * NW);
+      mma(acc, o1);
+      store(acc, rt + NW);
     }
   }
-  // the residual column (all components): W_R = A_qq^-1 R_q
-  __syncthreads();
-  double *wr = rc;   // [M D Np]
-  for (int t = tid; t < M * DN; t += QT) xs[t] = X[(size_t)kp * np + nv + t];
-  __syncthreads();
-  for (int t = tid; t < M * DN; t += QT) {
-    const int a = t % Np, cj = t / Np;
-    const double *xq = xs + cj * Np;
-    double acc = 0.0;
-    for (int q = 0; q < Np; ++q) acc += mi[q * Np + a] * xq[q];
-    wr[t] = acc;
-  }
-  __syncthreads();
-  for (int row = tid; row < nr; row += QT) {
-    double val = 0.0;
-    if (row < nv) {
-      val = X[(size_t)kp * np + row];
-      for (int q = 0; q < M * DN; ++q) val -= A[(size_t)(nv + q) * np + row] * wr[q];
-    }
-    Xr[(size_t)kp * nr + row] = val;
-  }
-  for (int trow = tid; trow < kp; trow += QT) {
-    double val = Rt[trow];
-    for (int q = 0; q < M * DN; ++q) val -= C[(size_t)(nv + q) * kp + trow] * wr[q];
-    Rtr[trow] = val;
-  }
+  for (int row = nv + tid; row < nr; row += QT) Xr[(size_t)kp * nr + row] = 0.0;
   // padding: identity of A^ beyond n_r, zero rows of B^ and columns of C^ beyond n_r, the zero
   // columns of [B^ r^ | 0], the padding columns of D
   for (size_t t = tid; t < (size_t)nr * nr; t += QT) {
@@ -260,9 +316,11 @@ __global__ __launch_bounds__(QT) void k_qrecover(DevPlan P, QElimArgs Q, int e0,
   const double *zv = Q.zv + (size_t)el * nv;
   double *Ye = Y + (size_t)e * n * k;
   double *ze = z + (size_t)e * n;
-  double *mi = sm, *hh = sm + Np * Np, *wb = hh + D * Np * Np;   // wb [QCB][DN] or [M D Np]
-  double *ys = wb + QCB * DN;                                       // [QCB][nv] Y_v of the pass
-  double *xs = sm + q_lds(Np, D, M, P.nf * Nfp).xs;                             // [QCB][DN] B_q rows of the pass
+  const QRecLds L = qrec_lds(Np, D, M);
+  double *mi = sm, *hh = sm + L.hh;
+  double *wb = sm + L.wb;   // [QCB][DN] or [M D Np]
+  double *ys = sm + L.ys;   // [QCB][nv] Y_v of the pass
+  double *xs = sm + L.xs;   // [QCB][DN] B_q rows of the pass
   for (int t = tid; t < (1 + D) * Np * Np; t += QT) sm[t] = MH[t];
   for (int c0 = 0; c0 < k; c0 += QCB) {
     const int nc = (k - c0) < QCB ? (k - c0) : QCB;
@@ -273,6 +331,7 @@ __global__ __launch_bounds__(QT) void k_qrecover(DevPlan P, QElimArgs Q, int e0,
       xs[t] = X[(size_t)col * np + nv + trace_comp(col, M, Nfp) * DN + ja];
     }
     __syncthreads();
+    // W_B of the pass (M^-1 per direction block) and the v rows of Y
     for (int t = tid; t < nc * DN; t += QT) {
       const int cl = t / DN, ja = t % DN, j = ja / Np, a = ja % Np;
       const double *xq = xs + cl * DN + j * Np;
@@ -280,20 +339,34 @@ __global__ __launch_bounds__(QT) void k_qrecover(DevPlan P, QElimArgs Q, int e0,
       for (int q = 0; q < Np; ++q) acc += mi[q * Np + a] * xq[q];
       wb[t] = acc;
     }
+    for (int t = tid; t < nc * nv; t += QT) Ye[(size_t)(c0 + t / nv) * n + t % nv] = ys[t];
     __syncthreads();
-    for (int t = tid; t < nc * n; t += QT) {
-      const int cl = t / n, row = t % n, col = c0 + cl;
-      double val;
-      if (row < nv) {
-        val = ys[cl * nv + row];
-      } else {
-        const int cja = row - nv, cc = cja / DN, ja = cja % DN, j = ja / Np, a = ja % Np;
-        val = (cc == trace_comp(col, M, Nfp)) ? wb[cl * DN + ja] : 0.0;
-        const double *yv = ys + cl * nv + cc * Np;
-        const double *h = hh + j * Np * Np + a;   // H_j[a][b] at h[b * Np]
-        for (int b = 0; b < Np; ++b) val -= h[b * Np] * yv[b];
+    // q rows of component cc: Y_q = [cc == comp(col)] W_B - H_j Y_v(cc), one FP64 MFMA tile per
+    // (column tile, (j, a) tile, cc) with the columns as MFMA rows: lane l supplies
+    // Y_v(cc, b = k0 + l/16)[col l%16] and H_j[a][b] for (j, a) = tile + l%16; accumulator r of
+    // lane l is column l/16 + 4r, (j, a) = tile + l%16, so 16 lanes store 16 consecutive rows.
+    const int nct = (nc + 15) / 16, njt = (DN + 15) / 16;
+    for (int task = tid >> 6; task < nct * njt * M; task += QT / 64) {
+      const int ct = task % nct, jt = (task / nct) % njt, cc = task / (nct * njt);
+      const int li = tid & 15, lk = (tid >> 4) & 3;
+      const int cl = ct * 16 + li, ja = jt * 16 + li, j = ja / Np, a = ja % Np;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < Np; k0 += 4) {
+        const int b = k0 + lk;
+        const double av = (b < Np && cl < nc) ? ys[cl * nv + cc * Np + b] : 0.0;
+        const double bv = (b < Np && ja < DN) ? hh[(j * Np + b) * Np + a] : 0.0;
+        acc = mfma4(av, bv, acc);
       }
-      Ye[(size_t)col * n + row] = val;
+      if (ja < DN) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int cr = ct * 16 + lk + 4 * r;
+          if (cr >= nc) continue;
+          const int col = c0 + cr;
+          const double w = (cc == trace_comp(col, M, Nfp)) ? wb[cr * DN + ja] : 0.0;
+          Ye[(size_t)col * n + nv + cc * DN + ja] = w - acc[r];
+        }
+      }
     }
   }
   __syncthreads();
@@ -322,20 +395,34 @@ __global__ __launch_bounds__(QT) void k_qrecover(DevPlan P, QElimArgs Q, int e0,
 }  // namespace
 
 size_t qelim_lds_bytes(const DevPlan &P) {
-  return (size_t)q_lds(P.Np, P.dim, P.m, P.nf * P.Nfp).total * sizeof(double);
+  const int a = q_lds(P.Np, P.dim, P.m, P.nf * P.Nfp).total, r = qrec_lds(P.Np, P.dim, P.m).total;
+  return (size_t)(a > r ? a : r) * sizeof(double);
 }
 
 hipError_t launch_qelim(const DevPlan &P, const QElimArgs &Q, int ec, hipStream_t s) {
   const size_t lds = qelim_lds_bytes(P);
-  hipError_t e = set_dyn_lds((const void *)k_qelim, lds);
-  if (e) return e;
-  hipLaunchKernelGGL(k_qelim, dim3(ec), dim3(QT), lds, s, P, Q);
-  return hipGetLastError();
+  const int nct = (P.Np + P.nf * P.Nfp + 16) / 16;
+  auto go = [&](auto kern) -> hipError_t {
+    hipError_t e = set_dyn_lds((const void *)kern, lds);
+    if (e) return e;
+    hipLaunchKernelGGL(kern, dim3(ec), dim3(QT), lds, s, P, Q);
+    return hipGetLastError();
+  };
+  switch (nct) {
+    case 1: return go(k_qelim<1>);
+    case 2: return go(k_qelim<2>);
+    case 3: return go(k_qelim<3>);
+    case 4: return go(k_qelim<4>);
+    case 5: return go(k_qelim<5>);
+    case 6: return go(k_qelim<6>);
+    case 7: return go(k_qelim<7>);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_qrecover(const DevPlan &P, const QElimArgs &Q, int e0, int ec, double *Y, double *z,
                            hipStream_t s) {
-  const size_t lds = qelim_lds_bytes(P);
+  const size_t lds = (size_t)qrec_lds(P.Np, P.dim, P.m).total * sizeof(double);
   hipError_t e = set_dyn_lds((const void *)k_qrecover, lds);
   if (e) return e;
   hipLaunchKernelGGL(k_qrecover, dim3(ec), dim3(QT), lds, s, P, Q, e0, Y, z);
