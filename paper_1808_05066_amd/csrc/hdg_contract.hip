@@ -121,8 +121,9 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   if (resident) stage(0);
   // zero fill: q rows and padding of A, X, C, D, R_tr
   const int nv = M * Np;
-  // (a wave per column, lanes along the rows: no index division)
-  for (int col = wave; col < np; col += NT / 64) {
+  // (a wave per column, lanes along the rows: no index division).  With a_qmin the q rows
+  // and the padding of A are left unwritten: only M and G_j of the first component are read.
+  for (int col = P.a_qmin ? np : wave; col < np; col += NT / 64) {
     double *Ac = A + (size_t)col * np;
     for (int row = (col < P.n ? nv : 0) + lane; row < np; row += 64) Ac[row] = (row == col && row >= P.n) ? 1.0 : 0.0;
   }
@@ -260,15 +261,17 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
         gm[t] = acc;
       }
       __syncthreads();
-      // G_j into the (q_j, v) block, the mass matrix into every (q_j, q_j) block
-      for (int t = tid; t < M * nj * Np * Np; t += NT) {
+      // G_j into the (q_j, v) block, the mass matrix into every (q_j, q_j) block (with a_qmin
+      // into those of the first component and its first direction only)
+      const int mc = P.a_qmin ? 1 : M, mj = P.a_qmin ? 1 : D;
+      for (int t = tid; t < mc * nj * Np * Np; t += NT) {
         const int a = t % Np, b = (t / Np) % Np, jl = (t / (Np * Np)) % nj, c = t / (nj * Np * Np);
         const int j = j0 + jl;
         const double val = gm[(jl * Np + a) * Np + b];
         if (j < D) {
           A[(size_t)(c * Np + b) * np + nv + (c * D + j) * Np + a] = val;
         } else {
-          for (int jj = 0; jj < D; ++jj) {
+          for (int jj = 0; jj < mj; ++jj) {
             const int cj = c * D + jj;
             A[(size_t)(nv + cj * Np + b) * np + nv + cj * Np + a] = val;
           }

@@ -287,6 +287,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   }
   D.contract_threads = 1024;
   D.zero_xcd = 1;
+  D.a_qmin = 0;
   D.condense_launches = 2;
   P->fused = D.cw != 0;
   if (opts && (opts->flags & HDG_FLAG_SPLIT_DENSE)) P->fused = false;
@@ -636,7 +637,8 @@ hipError_t phase_end(Plan *P, int ph, hipStream_t s) {
 }
 
 int run_front(Plan *P, const double *v, const double *q, const double *vhat, const double *ustar,
-              const double *vbc, int32_t *status, int e0, int ec, hipStream_t s) {
+              const double *vbc, int32_t *status, int e0, int ec, hipStream_t s, bool q_only) {
+  P->dp.a_qmin = q_only ? 1 : 0;
   hipError_t e = phase_begin(P, PH_POINTS, s);
   if (!e) e = launch_points(P->dp, e0, ec, v, q, vhat, ustar, vbc, status, s);
   if (!e) e = phase_end(P, PH_POINTS, s);
@@ -714,7 +716,7 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
   if (e) return hip_fail(e, "status init");
   for (int e0 = 0; e0 < P->n_elem; e0 += P->chunk) {
     int ec = std::min(P->chunk, P->n_elem - e0);
-    rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s);
+    rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s, P->qelim && P->fused);
     if (rc) return rc;
     e = launch_copy_resid(P->dp, e0, ec, Rloc, Rtr, s);
     if (!e && !P->fused && !P->split_ok) return fail(HDG_EUNSUPPORTED, "FP64 condensation: local block too large");

@@ -23,6 +23,7 @@ struct DevPlan {
   int cw, cw_lp;           // column-block width of the fused FP64 / FP32 condensation (0: not available)
   int contract_threads;    // workgroup size of the block contraction (256, 512, 1024)
   int zero_xcd;            // 1: the contraction clears X, C and D first (0: they hold the zeros already)
+  int a_qmin;              // 1: of the q rows of A only M and G_j of the first component are formed
   int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
   double gamma, mu, Pr, alpha;
   PointLayout L;
@@ -119,7 +120,7 @@ Plan *checked(hdg_plan *plan);   // null or unbound plan -> nullptr with the err
 hipError_t phase_begin(Plan *P, int ph, hipStream_t s);
 hipError_t phase_end(Plan *P, int ph, hipStream_t s);
 int run_front(Plan *P, const double *v, const double *q, const double *vhat, const double *ustar,
-              const double *vbc, int32_t *status, int e0, int ec, hipStream_t s);
+              const double *vbc, int32_t *status, int e0, int ec, hipStream_t s, bool q_only = false);
 int check_inputs(const Plan *P, const double *v, const double *q, const double *vhat, const double *ustar,
                  int32_t *status);
 

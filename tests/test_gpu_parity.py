@@ -193,6 +193,12 @@ def test_q_elimination_matches_oracle(torch, name, chunk, launches):
         assert err <= TOL, (key, err)
     zf = rel_err_per_elem(out["z"].cpu().numpy(), np.stack([b["z"] for b in blocks]))
     assert zf <= 1e-11, zf
+    # the condensation forms only the parts of the q rows of A that the elimination reads; the
+    # block export of the same plan afterwards still has the whole of A
+    blk = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    torch.cuda.synchronize()
+    ea = rel_err_per_elem(blk["A"].cpu().numpy(), colmajor([b["A"] for b in blocks]))
+    assert ea <= TOL, ea
 
 
 def test_q_elimination_needs_gradient_unknowns(torch):
