@@ -132,6 +132,48 @@ def bench_mixed(plan, inp, out64, E, fp64_cond_ms, torch):
             "converged": info["converged"], "rel_err_vs_fp64_gpu": errs}
 
 
+def bench_eliminate_q(wl, inp, out_ref, full_ms, steps, torch):
+    """The same step on a plan that eliminates the gradient unknowns element by element before
+    the dense condensation (identical S, g, Y, z up to rounding), timed the same way."""
+    from paper_1808_05066_amd.hdg import Plan
+    plan = Plan(wl.mesh.etype, wl.p, wl.mesh.elem_xyz, wl.tmap, wl.n_trace, wl.face_bc, viscous=wl.viscous,
+                gamma=wl.gamma, mu=wl.mu, Pr=wl.Pr, alpha=wl.alpha, eliminate_q=True)
+    out = plan.alloc_outputs()
+    r = torch.empty(plan.m, plan.n_trace, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(r)
+    dv = torch.empty(plan.m, plan.n_nodes, dtype=torch.float64, device="cuda")
+    dq = torch.empty(plan.m * plan.dim, plan.n_nodes, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.assemble_condense(inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"], out=out)
+        plan.trace_rhs(out["g"], r)
+        plan.trace_matvec(out["S"], r, y)
+        plan.backsolve(out["Y"], out["z"], r, dv, dq)
+
+    step()
+    torch.cuda.synchronize()
+    if int((out["status"] != 0).sum()):
+        raise RuntimeError("q-eliminating condensation reported a non-OK element status")
+    ms = _timed(step, steps, torch)
+    plan.set_timing(True)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    avg = {name: (t / c if c else 0.0) for name, (t, c) in plan.phase_times().items()}
+    plan.set_timing(False)
+
+    def rel(a, b):
+        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+    E = plan.n_elem
+    res = {"value": E / (ms / 1e3), "unit": "elem/s", "ms_per_step": ms, "vs_full_block": full_ms / ms,
+           "reduced_n": plan.m * plan.Np, "phase_ms": {p: round(v, 4) for p, v in avg.items()},
+           "rel_diff_vs_full_block": {key: rel(out[key], out_ref[key]) for key in ("S", "g", "Y", "z")}}
+    del plan, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_batch(torch, tune=True):
     """Mixed batch: 20,250 Kuhn tetrahedra with orders drawn from {1,2,3,4} plus 4,096 p = 2 hexes (NS).
 
@@ -262,6 +304,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurement")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-batch measurement")
+    ap.add_argument("--no-eliminate-q", action="store_true",
+                    help="skip the measurement of the condensation that eliminates q first")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
@@ -366,6 +410,9 @@ def main():
         "condensed_GBps": E * (k * k + k) * 8 / (cond_ms / 1e3) / 1e9,
         "wall_s_timed": wall,
     }
+    if wl.viscous and not args.no_eliminate_q:
+        print("[bench] condensation with the gradient unknowns eliminated first", file=sys.stderr, flush=True)
+        res["eliminate_q"] = bench_eliminate_q(wl, inp, out, ms, args.steps, torch)
     if not args.no_mixed:
         print("[bench] mixed-precision path", file=sys.stderr, flush=True)
         res["mixed"] = bench_mixed(plan, inp, out, E, cond_ms, torch)
