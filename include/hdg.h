@@ -105,7 +105,10 @@ typedef struct {
                               condenses the m N_p x m N_p block of v; same outputs S, g,
                               Y, z (to rounding) with 4x smaller dense factorizations.
                               FP64 hdg_assemble_condense only (the FP32 path and batches
-                              condense the full block). */
+                              condense the full block). Needs N_p + nf N_fp + 1 <= 112
+                              and the elimination's LDS sets within 160 KB (hexahedra up
+                              to p = 2, tetrahedra up to p = 3); otherwise plan creation
+                              returns HDG_EUNSUPPORTED, and HDG_EINVAL for Euler. */
 } hdg_opts;
 
 typedef struct {
