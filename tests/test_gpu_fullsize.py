@@ -40,14 +40,18 @@ def full(torch):
     return wl, disc, inp, plan, out
 
 
-def test_ns3d_hex_p2_16_sampled(torch, full):
-    wl, disc, inp, plan, out = full
-    assert int((out["status"] != 0).sum()) == 0
+@pytest.fixture(scope="module")
+def sampled_ref(full):
+    wl, disc, inp, _, _ = full
     E = wl.mesh.n_elem
     rng = np.random.default_rng(2024)
     sample = [0, E - 1] + list(rng.choice(np.arange(1, E - 1), 2, replace=False))
     ref = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], None, elems=sample,
                                  keep_blocks=True)
+    return sample, ref
+
+
+def check_sampled(disc, inp, out, sample, ref):
     for e, r in zip(sample, ref):
         errs = {}
         zg = out["z"][e].cpu().numpy()
@@ -62,6 +66,35 @@ def test_ns3d_hex_p2_16_sampled(torch, full):
         print("element", e, errs, flush=True)
         for key, err in errs.items():
             assert err <= TOL, (e, key, err)
+
+
+def test_ns3d_hex_p2_16_sampled(torch, full, sampled_ref):
+    wl, disc, inp, plan, out = full
+    assert int((out["status"] != 0).sum()) == 0
+    check_sampled(disc, inp, out, *sampled_ref)
+
+
+def test_ns3d_hex_p2_16_eliminate_q(torch, full, sampled_ref):
+    """The q-eliminating condensation at full size in the launch configuration bench.py times: sampled
+    elements against the oracle, and every element against the full-block condensation."""
+    wl, disc, inp, _, out = full
+    plan = gpu_plan(wl, eliminate_q=True)
+    dev = {k: (None if inp[k] is None else torch.from_numpy(np.ascontiguousarray(inp[k])).cuda())
+           for k in ("v", "q", "vhat", "ustar")}
+    print("full-size run with q eliminated first", flush=True)
+    outq = plan.assemble_condense(dev["v"], dev["q"], dev["vhat"], dev["ustar"], None, residuals=True)
+    torch.cuda.synchronize()
+    assert int((outq["status"] != 0).sum()) == 0
+    check_sampled(disc, inp, outq, *sampled_ref)
+    E = wl.mesh.n_elem
+    for key in ("S", "Y", "g"):
+        a = outq[key].reshape(E, -1)
+        b = out[key].reshape(E, -1)
+        err = float(((a - b).norm(dim=1) / b.norm(dim=1)).max())
+        print(key, "max over elements vs full block", err, flush=True)
+        assert err <= TOL, (key, err)
+    del plan, outq, dev
+    torch.cuda.empty_cache()
 
 
 def test_ns3d_hex_p2_16_trace_solve(torch, full):
