@@ -171,7 +171,7 @@ int batch_sequence(Batch *B, hipStream_t s) {
     const hdg_batch_io &a = B->io[i];
     hipError_t e = launch_fill_int(a.elem_status, P->n_elem, HDG_OK, s);
     if (e) return hip_fail(e, "batch status init");
-    int rc = run_front(P, a.v, a.q, a.vhat, a.u_star, a.v_bc, a.elem_status, 0, P->n_elem, s);
+    int rc = run_front(P, a.v, a.q, a.vhat, a.u_star, a.v_bc, a.elem_status, 0, P->n_elem, s, P->dp.mg != nullptr);
     if (rc) return rc;
   }
   hipError_t e = launch_fill_int(B->d_counter, 1, 0, s);

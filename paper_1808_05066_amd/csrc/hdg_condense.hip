@@ -78,8 +78,8 @@ struct Lds {
 // each thread keeps LU loads in flight before writing them to LDS)
 constexpr int LU = 8;
 
-template <typename T, int W, int NTT = NT>
-__device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, int np) {
+template <typename T, int W, int NTT = NT, typename Fetch>
+__device__ inline void load_block_f(const Lds<T> &s, int np, Fetch fetch) {
   constexpr int BS = W + 1;
   const int total = np * W;
   for (int t0 = threadIdx.x; t0 < total; t0 += LU * NTT) {
@@ -89,7 +89,7 @@ __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, i
       const int t = t0 + u * NTT;
       if (t < total) {
         const int c = t / np, i = t - c * np;
-        v[u] = M[(size_t)(c0 + c) * ld + s.perm[i]];
+        v[u] = fetch(c, s.perm[i]);
       }
     }
 #pragma unroll
@@ -103,10 +103,15 @@ __device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, i
   }
 }
 
-// Low-precision load of FP64 columns: blk[i][c] = d_row * M[c0+c][perm[i]] * d_col
-// (colscale false: right-hand sides, rows scaled only).
 template <typename T, int W, int NTT = NT>
-__device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int ld, int c0, int np, bool colscale) {
+__device__ inline void load_block(const Lds<T> &s, const T *M, int ld, int c0, int np) {
+  load_block_f<T, W, NTT>(s, np, [&](int c, int o) { return M[(size_t)(c0 + c) * ld + o]; });
+}
+
+// Same with the symmetric scaling of the low-precision path (rows always, columns
+// if colscale), converting to T; fetch(c, o) returns the FP64 entry.
+template <typename T, int W, int NTT = NT, typename Fetch>
+__device__ inline void load_block_scaled_f(const Lds<T> &s, int c0, int np, bool colscale, Fetch fetch) {
   constexpr int BS = W + 1;
   const int total = np * W;
   for (int t0 = threadIdx.x; t0 < total; t0 += LU * NTT) {
@@ -116,7 +121,7 @@ __device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int l
       const int t = t0 + u * NTT;
       if (t < total) {
         const int c = t / np, i = t - c * np;
-        v[u] = M[(size_t)(c0 + c) * ld + s.perm[i]];
+        v[u] = fetch(c, s.perm[i]);
       }
     }
 #pragma unroll
@@ -129,6 +134,69 @@ __device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int l
         s.blk[i * BS + c] = (T)x;
       }
     }
+  }
+}
+
+template <typename T, int W, int NTT = NT>
+__device__ inline void load_block_scaled(const Lds<T> &s, const double *M, int ld, int c0, int np, bool colscale) {
+  load_block_scaled_f<T, W, NTT>(s, c0, np, colscale, [&](int c, int o) { return M[(size_t)(c0 + c) * ld + o]; });
+}
+
+// Entry (o, col) of the local block A of an element (A64: its stored block, mg: its compact
+// M and G_j).  Without the compact copy every entry is stored; with it only the v rows are
+// (the contraction leaves the q rows and the padding unwritten), and the rest follows from
+// the block structure: the q row (c, j, a) holds G_j[a][b] in the v column (c, b) and
+// M[a][b] in the q column (c, j, b), zero elsewhere; the padding is the identity.
+__device__ inline double a_entry(const DevPlan &P, const double *A64, const double *mg, int o, int col) {
+  const int nv = P.m * P.Np;
+  if (!mg || (o < nv && col < P.n)) return A64[(size_t)col * P.n_pad + o];
+  if (o < nv) return 0.0;
+  if (o >= P.n || col >= P.n) return o == col ? 1.0 : 0.0;
+  const int ro = P.uinfo[o], rc = P.uinfo[col];
+  if ((ro >> 12) != (rc >> 12)) return 0.0;
+  const int a = ro & 255, b = rc & 255, j = (ro >> 8) & 15;
+  if (col < nv) return mg[(j * P.Np + a) * P.Np + b];
+  return j == ((rc >> 8) & 15) ? mg[(P.dim * P.Np + a) * P.Np + b] : 0.0;
+}
+
+// Block j0 of A (gathered through perm, scaled in the low-precision path) when only its v rows
+// are stored: the v rows are read, the q rows and the padding start as zero / identity, and
+// after a barrier the nonzeros of the q rows in these columns are placed through the inverse
+// permutation (invb, formed here in full) -- at most d N_p per column.  The caller's barrier
+// follows.
+template <typename T, bool LP, int W>
+__device__ inline void load_block_formed(const Lds<T> &s, const DevPlan &P, const double *A64, const double *mg,
+                                         int j0) {
+  constexpr int BS = W + 1;
+  const int np = P.n_pad, n = P.n, Np = P.Np, D = P.dim, nv = P.m * Np, DN = D * Np;
+  for (int x = threadIdx.x; x < np; x += NT) s.invb[s.perm[x]] = x;
+  const auto fetch = [&](int c, int o) {
+    const int col = j0 + c;
+    if (o < nv) return col < n ? A64[(size_t)col * np + o] : 0.0;
+    return (o == col && o >= n) ? 1.0 : 0.0;
+  };
+  if constexpr (LP) load_block_scaled_f<T, W>(s, j0, np, true, fetch);
+  else load_block_f<T, W>(s, np, fetch);
+  __syncthreads();
+  for (int t = threadIdx.x; t < W * DN; t += NT) {
+    const int c = t / DN, r = t - c * DN, col = j0 + c;
+    if (col >= n) continue;
+    int o;
+    double val;
+    if (col < nv) {
+      // v column (cc, b): G_j[a][b] in the q rows (cc, j, a)
+      const int cc = col / Np, b = col - cc * Np, j = r / Np, a = r - j * Np;
+      o = nv + (cc * D + j) * Np + a;
+      val = mg[(j * Np + a) * Np + b];
+    } else {
+      // q column (cc, jj, b): M[a][b] in the q rows (cc, jj, a)
+      if (r >= Np) continue;
+      const int qc = col - nv, cj = qc / Np, b = qc - cj * Np;
+      o = nv + cj * Np + r;
+      val = mg[(D * Np + r) * Np + b];
+    }
+    if constexpr (LP) val *= s.dsc[o] * s.dsc[col];
+    s.blk[s.invb[o] * BS + c] = (T)val;
   }
 }
 
@@ -664,8 +732,8 @@ __device__ __forceinline__ FactorPtrs<T, LP> factor_ptrs(const DevPlan &P, int e
 }
 
 // Symmetric power-of-two scaling of the low-precision path from the diagonal of A.
-__device__ inline double diag_scale(const double *A64, int np, int i) {
-  const double a = fabs(A64[(size_t)i * np + i]);
+__device__ inline double diag_scale(const DevPlan &P, const double *A64, const double *mg, int i) {
+  const double a = fabs(a_entry(P, A64, mg, i, i));
   return (a > 0.0 && a < 1e300) ? exp2(-rint(0.5 * log2(a))) : 1.0;
 }
 
@@ -676,19 +744,21 @@ template <typename T, bool LP, int W>
 __device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &s, const FactorPtrs<T, LP> &f) {
   const int np = P.n_pad;
   const double *A64 = P.A + (size_t)el * np * np;
+  const double *mg = P.mg ? P.mg + (size_t)el * (P.dim + 1) * P.Np * P.Np : nullptr;
   T *Fm = f.F;
   T *Ie = f.Inv;
   const int tid = threadIdx.x;
   const int nJ = np / W;
   for (int i = tid; i < np; i += NT) {
     s.perm[i] = i;
-    if constexpr (LP) s.dsc[i] = diag_scale(A64, np, i);
+    if constexpr (LP) s.dsc[i] = diag_scale(P, A64, mg, i);
   }
   __syncthreads();
   bool singular = false;
   for (int J = 0; J < nJ; ++J) {
     const int j0 = J * W;
-    if constexpr (LP) load_block_scaled<T, W>(s, A64, np, j0, np, true);
+    if (mg) load_block_formed<T, LP, W>(s, P, A64, mg, j0);
+    else if constexpr (LP) load_block_scaled<T, W>(s, A64, np, j0, np, true);
     else load_block<T, W>(s, A64, np, j0, np);
     __syncthreads();
     if (J > 0)
@@ -851,9 +921,10 @@ __device__ __forceinline__ void rhs_body(const DevPlan &P, int e0, int ec, T *S,
   const FactorPtrs<T, LP> f = factor_ptrs<T, LP>(P, e, el, inv, fac);
   const int *perm = LP ? reinterpret_cast<const int *>(f.rec + rec_perm_off(np)) : P.ipiv + (size_t)el * np;
   const double *A64 = P.A + (size_t)el * np * np;
+  const double *mg = P.mg ? P.mg + (size_t)el * (P.dim + 1) * P.Np * P.Np : nullptr;
   for (int i = threadIdx.x; i < np; i += NTT) {
     s.perm[i] = perm[i];
-    if constexpr (LP) s.dsc[i] = diag_scale(A64, np, i);
+    if constexpr (LP) s.dsc[i] = diag_scale(P, A64, mg, i);
   }
   __syncthreads();
   rhs_block<T, LP, W, NTT>(P, e, el, j * W, s, f, S, g, Y, z);

@@ -122,7 +122,8 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   // zero fill: q rows and padding of A, X, C, D, R_tr
   const int nv = M * Np;
   // (a wave per column, lanes along the rows: no index division).  With a_qmin the q rows
-  // and the padding of A are left unwritten: only M and G_j of the first component are read.
+  // and the padding of A are left unwritten: the condensation forms them from the compact
+  // M and G_j, the q elimination reads M and G_j of the first component.
   for (int col = P.a_qmin ? np : wave; col < np; col += NT / 64) {
     double *Ac = A + (size_t)col * np;
     for (int row = (col < P.n ? nv : 0) + lane; row < np; row += 64) Ac[row] = (row == col && row >= P.n) ? 1.0 : 0.0;
@@ -261,6 +262,11 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
         gm[t] = acc;
       }
       __syncthreads();
+      // the compact copy the condensation forms the q rows of A from
+      if (P.mg) {
+        double *mg = P.mg + (size_t)el * (D + 1) * Np * Np + (size_t)j0 * Np * Np;
+        for (int t = tid; t < nj * Np * Np; t += NT) mg[t] = gm[t];
+      }
       // G_j into the (q_j, v) block, the mass matrix into every (q_j, q_j) block (with a_qmin
       // into those of the first component and its first direction only)
       const int mc = P.a_qmin ? 1 : M, mj = P.a_qmin ? 1 : D;

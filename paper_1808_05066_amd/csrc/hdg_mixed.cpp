@@ -83,7 +83,7 @@ extern "C" int hdg_assemble_condense_lp(hdg_plan *plan, const double *v, const d
   if (e) return hip_fail(e, "status init");
   for (int e0 = 0; e0 < P->n_elem; e0 += P->chunk) {
     const int ec = std::min(P->chunk, P->n_elem - e0);
-    rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s);
+    rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s, P->dp.mg != nullptr);
     if (rc) return rc;
     e = launch_copy_resid(P->dp, e0, ec, Rloc, Rtr, s);
     if (!e) e = phase_begin(P, PH_CONDENSE_LP, s);

@@ -319,6 +319,16 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   L.fW = o; o += 1;
   L.fsize = o;
   P->contract_mfma = contract_mfma_supported(D) && !(opts && (opts->flags & HDG_FLAG_SPLIT_DENSE));
+  if (D.viscous && P->contract_mfma) {
+    // local unknown x: v (c, a) at c Np + a, q (c, j, a) at m Np + (c d + j) Np + a, padding beyond n
+    P->uinfo.assign(D.n_pad, 0);
+    const int nv = D.m * D.Np;
+    for (int x = 0; x < D.n; ++x) {
+      const int c = x < nv ? x / D.Np : (x - nv) / (D.dim * D.Np);
+      const int j = x < nv ? 0 : ((x - nv) / D.Np) % D.dim;
+      P->uinfo[x] = x % D.Np | j << 8 | c << 12;
+    }
+  }
   if (opts && (opts->flags & HDG_FLAG_ELIMINATE_Q)) {
     const int nv = D.m * D.Np;
     P->qa.nr_pad = roundup(nv, 32);
@@ -405,8 +415,8 @@ namespace {
 
 struct Layout {
   size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x;
-  size_t bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos, tables_end;
-  size_t pv, pf, A, X, C, D, Rt, ipiv, inv;
+  size_t bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos, uinfo, tables_end;
+  size_t pv, pf, A, X, C, D, Rt, ipiv, inv, mg;
   size_t rA, rX, rC, rD, rRt, rMH, rYv, rzv, ripiv, rinv, total;
 };
 
@@ -437,6 +447,7 @@ Layout layout(const Plan *P) {
   l.bj_cf = take(P->bj_cf.size() * 4);
   l.bj_loc = take(P->bj_loc.size() * 4);
   l.bj_tpos = take(P->bj_tpos.size() * 4);
+  l.uinfo = take(P->uinfo.size() * 4);
   l.tables_end = o;
   l.pv = take(ch * D.Nq * D.L.size * 8);
   l.pf = take(ch * D.nf * D.Nfq * D.L.fsize * 8);
@@ -447,6 +458,7 @@ Layout layout(const Plan *P) {
   l.Rt = take(ch * (size_t)D.k_pad * 8);
   l.ipiv = take(ch * (size_t)D.n_pad * 4);
   l.inv = take(P->fused ? ch * condense_inv_doubles(D.n_pad) * 8 : 0);
+  l.mg = take(P->uinfo.empty() ? 0 : ch * (size_t)(1 + D.dim) * D.Np * D.Np * 8);
   if (P->qelim) {
     const size_t nr = P->qa.nr_pad, nv = (size_t)D.m * D.Np;
     l.rA = take(ch * nr * nr * 8);
@@ -537,6 +549,7 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   if (!e) e = up(l.bj_cf, P->bj_cf.data(), P->bj_cf.size() * 4);
   if (!e) e = up(l.bj_loc, P->bj_loc.data(), P->bj_loc.size() * 4);
   if (!e) e = up(l.bj_tpos, P->bj_tpos.data(), P->bj_tpos.size() * 4);
+  if (!e) e = up(l.uinfo, P->uinfo.data(), P->uinfo.size() * 4);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(e, "bind_workspace upload");
   P->xcd_clean = false;
@@ -566,6 +579,8 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   D.Rt = reinterpret_cast<double *>(base + l.Rt);
   D.ipiv = reinterpret_cast<int *>(base + l.ipiv);
   D.inv = reinterpret_cast<double *>(base + l.inv);
+  D.mg = P->uinfo.empty() ? nullptr : reinterpret_cast<double *>(base + l.mg);
+  D.uinfo = P->uinfo.empty() ? nullptr : reinterpret_cast<const int *>(base + l.uinfo);
   if (P->qelim) {
     QElimArgs &Q = P->qa;
     Q.A = reinterpret_cast<double *>(base + l.rA);
@@ -716,7 +731,7 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
   if (e) return hip_fail(e, "status init");
   for (int e0 = 0; e0 < P->n_elem; e0 += P->chunk) {
     int ec = std::min(P->chunk, P->n_elem - e0);
-    rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s, P->qelim && P->fused);
+    rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s, (P->qelim || P->dp.mg) && P->fused);
     if (rc) return rc;
     e = launch_copy_resid(P->dp, e0, ec, Rloc, Rtr, s);
     if (!e && !P->fused && !P->split_ok) return fail(HDG_EUNSUPPORTED, "FP64 condensation: local block too large");
@@ -735,6 +750,8 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
         r.Rt = P->qa.Rt;
         r.ipiv = P->rp.ipiv;
         r.inv = P->rp.inv;
+        r.mg = nullptr;   // the reduced block is stored whole
+        r.uinfo = nullptr;
         const size_t k = P->dp.k;
         e = launch_qelim(P->dp, P->qa, ec, s);
         if (!e) e = condense_chunk(P, r, 0, ec, status + e0, S + (size_t)e0 * k * k, g + (size_t)e0 * k, P->qa.Yv,

@@ -49,6 +49,10 @@ struct DevPlan {
   double *Rt;              // [chunk][k_pad]
   int *ipiv;               // [chunk][n_pad]
   double *inv;             // [chunk][n_pad/32][2][32][32] inverses of diagonal factor blocks
+  // q rows of A in compact form (Navier-Stokes with the matrix-core contraction, else null):
+  // the condensation forms the q rows and the padding of A from these instead of reading them
+  double *mg;              // [chunk][1 + dim][Np][Np]: G_j[a][b] (j < dim), M[a][b] (j = dim)
+  const int *uinfo;        // [n_pad]: node | direction << 8 | component << 12 of each local unknown
   // block-Jacobi structure of the condensed operator
   int bj_face;             // 1: one block per mesh face (HDG), 0: one m x m block per trace node
   int bj_nblk, bj_bs;
@@ -97,6 +101,7 @@ struct Plan {
   std::vector<double> geo_vol, geo_face, node_x, trace_x;
   std::vector<int> tmap, face_bc, node_face;
   std::vector<int> bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos;
+  std::vector<int> uinfo;   // see DevPlan::uinfo (empty: the q rows of A are read, not formed)
   // workspace
   void *ws = nullptr;
   size_t ws_bytes = 0;
