@@ -405,6 +405,45 @@ int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q, const dou
                      double *dlam, void *work, size_t bytes, const hdg_refine_opts *opts,
                      hdg_refine_info *info, int32_t *elem_status, void *stream);
 
+/* ---- Newton iterations on the nonlinear system (library's own driver) ----
+ * Solves R(v, q, vhat) = 0 for one implicit stage (the plan's alpha > 0 with the
+ * previous-stage state u_star) or the steady problem (alpha = 0): R is the element
+ * residual R_loc of every element together with the assembled trace residual
+ * sum_K P_K^T R_tr,K (the weak forms of Sections 3.3 and 4).  Each iteration
+ * assembles and condenses every element (hdg_assemble_condense), solves the
+ * condensed system K dlambda = sum_K P_K^T g_K with GMRES (opts->lin, block
+ * Jacobi if precond = 1; S in FP64), back-solves dx_K = -z_K - Y_K P_K dlambda
+ * and updates v += dv, q += dq (Navier-Stokes), vhat += dlambda in place (the
+ * local elimination remark after the weak forms).  Stops when
+ * ||R|| <= atol or ||R|| <= tol ||R_0|| (converged = 1), or after maxit updates.
+ * v [m][E*Np], q [m*dim][E*Np] (NULL for Euler), vhat [m][n_trace] device,
+ * updated in place; u_star, v_bc as for hdg_assemble_condense.  work: device,
+ * 256-byte aligned, at least hdg_newton_workspace_bytes (S, g, Y, z, the
+ * residuals, the updates and the solver's workspace); info on the host.
+ * Synchronizes `stream` every iteration.  An element with a non-OK status stops
+ * the iteration with its code (e.g. HDG_ENONPHYS). */
+#define HDG_NEWTON_HIST 32
+typedef struct {
+  int maxit;              /* Newton updates at most (>= 1) */
+  double tol;             /* relative stop: ||R|| <= tol ||R_0|| */
+  double atol;            /* absolute stop: ||R|| <= atol */
+  hdg_solve_opts lin;     /* linear solves; s_dtype must be HDG_FP64 */
+} hdg_newton_opts;
+
+typedef struct {
+  int iterations;         /* updates applied */
+  int converged;          /* 1 if a stop criterion was met */
+  int lin_iterations;     /* GMRES Arnoldi steps over all iterations */
+  int lin_converged;      /* 1 if every linear solve met opts->lin.tol */
+  double res[HDG_NEWTON_HIST];   /* ||R|| at the state before update i (res[iterations]: final state) */
+  double ms;              /* host wall time */
+} hdg_newton_info;
+
+int hdg_newton_workspace_bytes(const hdg_plan *plan, const hdg_newton_opts *opts, size_t *bytes);
+int hdg_newton_solve(hdg_plan *plan, double *v, double *q, double *vhat, const double *u_star,
+                     const double *v_bc, void *work, size_t bytes, const hdg_newton_opts *opts,
+                     hdg_newton_info *info, void *stream);
+
 /* Optional per-phase timing with HIP events recorded on the call's stream
  * around each kernel group: 0 points (pointwise physics), 1 contract (block
  * assembly), 2 LU, 3 triangular solves, 4 Schur product (split dense path),

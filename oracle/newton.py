@@ -1,4 +1,6 @@
-"""Steady Newton driver on the condensed trace system (oracle, small meshes).
+"""Newton driver on the condensed trace system (oracle, small meshes): the steady
+problem, or one implicit stage when the discretization's alpha > 0 and u* is given
+(the mass term alpha (u(v) - u*, w) of the stage residual).
 
 Each iteration assembles every element (complex-step Jacobian), condenses,
 solves the global trace system with a sparse direct solver and back-solves
@@ -16,7 +18,7 @@ from . import hdg
 
 
 def newton_steady(disc: hdg.Discretization, v, q, vhat, vbc=None, source=None, tol=1e-11,
-                  maxit=12, verbose=False):
+                  maxit=12, verbose=False, ustar=None):
     v, vhat = v.copy(), vhat.copy()
     q = None if q is None else q.copy()
     m, d, Np = disc.m, disc.d, disc.Np
@@ -25,7 +27,7 @@ def newton_steady(disc: hdg.Discretization, v, q, vhat, vbc=None, source=None, t
         Ys, zs, Ss, gs, rn = [], [], [], [], 0.0
         rt = np.zeros(m * disc.n_trace)
         for e in range(disc.mesh.n_elem):
-            x, lam, us, vb = disc.elem_inputs(e, v, q, vhat, None, vbc)
+            x, lam, us, vb = disc.elem_inputs(e, v, q, vhat, ustar, vbc)
             s = disc.element_system(e, x, lam, us, vb, source)
             c = hdg.condense(s)
             Ys.append(c["Y"]); zs.append(c["z"]); Ss.append(c["S"]); gs.append(c["g"])

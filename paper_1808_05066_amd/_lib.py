@@ -46,6 +46,19 @@ class hdg_refine_opts(ctypes.Structure):
                 ("gmres", hdg_solve_opts)]
 
 
+HDG_NEWTON_HIST = 32
+
+
+class hdg_newton_opts(ctypes.Structure):
+    _fields_ = [("maxit", ctypes.c_int), ("tol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("lin", hdg_solve_opts)]
+
+
+class hdg_newton_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("lin_iterations", ctypes.c_int),
+                ("lin_converged", ctypes.c_int), ("res", ctypes.c_double * HDG_NEWTON_HIST), ("ms", ctypes.c_double)]
+
+
 class hdg_refine_info(ctypes.Structure):
     _fields_ = [("outer_iterations", ctypes.c_int), ("gmres_iterations", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("total_ms", ctypes.c_double), ("gmres_ms", ctypes.c_double),
@@ -101,6 +114,9 @@ SIGNATURES = {
     "hdg_refine_workspace_bytes": (I, [P, ctypes.POINTER(hdg_refine_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "hdg_refine_solve": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t,
                              ctypes.POINTER(hdg_refine_opts), ctypes.POINTER(hdg_refine_info), P, P]),
+    "hdg_newton_workspace_bytes": (I, [P, ctypes.POINTER(hdg_newton_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_newton_solve": (I, [P, P, P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_newton_opts),
+                             ctypes.POINTER(hdg_newton_info), P]),
     "hdg_learn_nparams": (I, []),
     "hdg_learn_setup": (I, [P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),
     "hdg_learn_forward": (I, [P, P, P, P, P]),

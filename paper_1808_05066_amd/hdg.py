@@ -254,6 +254,27 @@ class Plan:
         res["history"] = [info.history[i] for i in range(min(16, info.outer_iterations))]
         return dx, dlam, res
 
+    def newton_solve(self, v, q, vhat, ustar=None, vbc=None, maxit=10, tol=1e-10, atol=0.0, lin_tol=1e-12,
+                     lin_restart=50, lin_maxit=2000, precond="block_jacobi"):
+        """Newton iterations on the nonlinear system (hdg_newton_solve): v, q, vhat updated in
+        place.  Returns the info as a dict (residual history in "res")."""
+        torch = _torch()
+        lo = _lib.hdg_solve_opts(int(lin_restart), int(lin_maxit), float(lin_tol), TraceSolver.PRECONDS[precond],
+                                 _lib.HDG_FP64)
+        opts = _lib.hdg_newton_opts(int(maxit), float(tol), float(atol), lo)
+        nb = ctypes.c_size_t()
+        check(self.lib.hdg_newton_workspace_bytes(self.h, ctypes.byref(opts), ctypes.byref(nb)),
+              "hdg_newton_workspace_bytes")
+        work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        wp = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        info = _lib.hdg_newton_info()
+        check(self.lib.hdg_newton_solve(self.h, _ptr(v), _ptr(q), _ptr(vhat), _ptr(ustar), _ptr(vbc), wp,
+                                        ctypes.c_size_t(nb.value), ctypes.byref(opts), ctypes.byref(info),
+                                        _stream()), "hdg_newton_solve")
+        res = {f: getattr(info, f) for f, _ in _lib.hdg_newton_info._fields_ if f != "res"}
+        res["res"] = [info.res[i] for i in range(min(_lib.HDG_NEWTON_HIST, info.iterations + 1))]
+        return res
+
     def trace_rhs(self, g, r=None):
         if r is None:
             r = self._empty(self.m, self.n_trace)

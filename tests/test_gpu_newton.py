@@ -1,0 +1,73 @@
+"""Newton driver (hdg_newton_solve) on small Navier-Stokes meshes, one implicit stage
+(alpha = 1/(a_ii dt), u* from the unperturbed field), started from the perturbed state.
+
+Checks: the residual norm of the starting state against the oracle's (same discrete
+equations), convergence of the iteration, and that the converged GPU state satisfies
+the oracle's discrete equations: the oracle's residual norm at that state is below
+1e-9 of the starting one."""
+import numpy as np
+import pytest
+
+from oracle import newton
+
+from cases import SMALL_CASES, gpu_plan, oracle_case, residual_term_scale, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def oracle_residual(disc, inp, v, q, vhat):
+    # newton_steady computes the residual norm of its starting state first
+    _, _, _, hist = newton.newton_steady(disc, v, q, vhat, vbc=inp["vbc"], ustar=inp["ustar"], maxit=1, tol=0.0)
+    return hist[0]
+
+
+def residual_scale(disc, inp):
+    """Floating-point scale of the residual norm: every element's quadrature terms in
+    absolute value (the rounding of ||R|| is a small multiple of eps times this)."""
+    tot = 0.0
+    for e in range(disc.mesh.n_elem):
+        x, lam, us, _ = disc.elem_inputs(e, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
+        tot += residual_term_scale(disc, e, x, lam, us) ** 2
+    return float(np.sqrt(tot))
+
+
+@pytest.mark.parametrize("name", ["ns2d_tri_p2", "ns3d_hex_p1"])
+def test_newton_converges_to_oracle_solution(torch, name):
+    wl = SMALL_CASES[name]()
+    disc, inp = oracle_case(wl)
+    print("case", name, flush=True)
+    r0 = oracle_residual(disc, inp, inp["v"], inp["q"], inp["vhat"])
+    scale = residual_scale(disc, inp)
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    v, q, vh = d["v"].clone(), d["q"].clone(), d["vhat"].clone()
+    info = plan.newton_solve(v, q, vh, d["ustar"], d["vbc"], maxit=10, tol=1e-10, lin_tol=1e-13)
+    torch.cuda.synchronize()
+    print(name, "oracle r0", r0, "scale", scale, "gpu", info, flush=True)
+    assert abs(info["res"][0] - r0) <= 1e-12 * scale
+    assert info["converged"] == 1 and info["lin_converged"] == 1
+    assert info["iterations"] <= 8
+    res = info["res"]
+    assert all(res[i + 1] < res[i] for i in range(len(res) - 1))
+    r_end = oracle_residual(disc, inp, v.cpu().numpy(), q.cpu().numpy(), vh.cpu().numpy())
+    print(name, "oracle residual at the GPU's converged state", r_end, flush=True)
+    assert r_end <= 1e-9 * r0
+
+
+def test_newton_rejects_fp32_operator(torch):
+    from paper_1808_05066_amd import _lib
+    wl = SMALL_CASES["ns2d_tri_p2"]()
+    plan = gpu_plan(wl)
+    lo = _lib.hdg_solve_opts(50, 100, 1e-10, 1, _lib.HDG_FP32)
+    opts = _lib.hdg_newton_opts(5, 1e-10, 0.0, lo)
+    import ctypes
+    nb = ctypes.c_size_t()
+    assert plan.lib.hdg_newton_workspace_bytes(plan.h, ctypes.byref(opts), ctypes.byref(nb)) == _lib.HDG_EINVAL

@@ -336,3 +336,32 @@ def test_convergence_order_k_plus_1(viscous, p):
     if viscous:
         qrate = np.log2(qerrs[0] / qerrs[1])
         assert qrate >= p + 1 - 0.3, (qerrs, qrate)
+
+
+def test_implicit_stage_newton_returns_to_uniform_flow():
+    """One implicit stage (alpha > 0) whose previous-stage state u* is a uniform flow: the
+    uniform flow (v constant, q = 0, vhat = v) solves it exactly (free-stream preservation
+    and alpha (u - u*) = 0), and it is the solution Newton finds from a perturbed start,
+    with the residual falling quadratically."""
+    mu, Pr, alpha, p = 0.01, 0.72, 5.0, 2
+    mesh = M.tri_square(2, 0.05, 7, periodic=True)
+    tmap, nt = M.trace_map(mesh, p, "hdg")
+    disc = hdg.Discretization(mesh, p, hdg.Phys(GAM, mu, Pr, alpha, True), tmap, nt,
+                              np.zeros((mesh.n_elem, 3), dtype=np.int32))
+    vc = ph.v_of_prim(np.array(1.1), np.array([0.3, -0.2]), np.array(0.9), GAM)
+    nn = mesh.n_elem * disc.Np
+    v_ex = np.repeat(vc[:, None], nn, axis=1)
+    vh_ex = np.repeat(vc[:, None], nt, axis=1)
+    ustar = ph.u_of_v(v_ex.T, GAM).T.copy()
+    rng = np.random.default_rng(11)
+    v0 = v_ex * (1 + 1e-2 * rng.standard_normal(v_ex.shape))
+    vh0 = vh_ex * (1 + 1e-2 * rng.standard_normal(vh_ex.shape))
+    q0 = 1e-3 * rng.standard_normal((4 * 2, nn))
+    v, q, vh, hist = newton.newton_steady(disc, v0, q0, vh0, ustar=ustar, tol=1e-12, maxit=8)
+    assert hist[-1] < 1e-12 * max(1.0, hist[0]), hist
+    assert len(hist) <= 6, hist
+    for i in range(1, len(hist) - 1):
+        assert hist[i + 1] <= 10 * hist[i] ** 2 / hist[0] + 1e-13, hist   # quadratic decrease
+    assert np.max(np.abs(v - v_ex)) < 1e-10 * np.max(np.abs(vc))
+    assert np.max(np.abs(q)) < 1e-9
+    assert np.max(np.abs(vh - vh_ex)) < 1e-10 * np.max(np.abs(vc))
