@@ -174,6 +174,19 @@ def bench_eliminate_q(wl, inp, out_ref, full_ms, steps, torch):
     return res
 
 
+def bench_newton(plan, inp, torch, maxit=8, tol=1e-10):
+    """Newton iterations of one implicit stage (hdg_newton_solve) from the benchmark's
+    perturbed state: assemble + condense, GMRES(50) with block Jacobi on the condensed
+    system, back-solve and update per iteration."""
+    v, vh = inp["v"].clone(), inp["vhat"].clone()
+    q = None if inp["q"] is None else inp["q"].clone()
+    info = plan.newton_solve(v, q, vh, inp["ustar"], inp["vbc"], maxit=maxit, tol=tol, lin_tol=1e-10)
+    its = max(info["iterations"], 1)
+    return {"iterations": info["iterations"], "converged": info["converged"], "residuals": info["res"],
+            "gmres_iterations": info["lin_iterations"], "ms": info["ms"], "ms_per_iteration": info["ms"] / its,
+            "tol_rel": tol}
+
+
 def bench_batch(torch, tune=True):
     """Mixed batch: 20,250 Kuhn tetrahedra with orders drawn from {1,2,3,4} plus 4,096 p = 2 hexes (NS).
 
@@ -304,6 +317,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision measurement")
     ap.add_argument("--no-solve", action="store_true", help="skip the GMRES measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed-batch measurement")
+    ap.add_argument("--no-newton", action="store_true", help="skip the Newton-iteration measurement")
     ap.add_argument("--no-eliminate-q", action="store_true",
                     help="skip the measurement of the condensation that eliminates q first")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
@@ -413,6 +427,9 @@ def main():
     if wl.viscous and not args.no_eliminate_q:
         print("[bench] condensation with the gradient unknowns eliminated first", file=sys.stderr, flush=True)
         res["eliminate_q"] = bench_eliminate_q(wl, inp, out, ms, args.steps, torch)
+    if not args.no_newton:
+        print("[bench] Newton iterations of one implicit stage", file=sys.stderr, flush=True)
+        res["newton"] = bench_newton(plan, inp, torch)
     if not args.no_mixed:
         print("[bench] mixed-precision path", file=sys.stderr, flush=True)
         res["mixed"] = bench_mixed(plan, inp, out, E, cond_ms, torch)
