@@ -444,6 +444,21 @@ int hdg_newton_solve(hdg_plan *plan, double *v, double *q, double *vhat, const d
                      const double *v_bc, void *work, size_t bytes, const hdg_newton_opts *opts,
                      hdg_newton_info *info, void *stream);
 
+/* One step of Alexander's three-stage L-stable DIRK(3,3) (the time integration of the
+ * paper's numerical examples, Section 5) around hdg_newton_solve: stage i solves
+ *   alpha (u(v_i) - u*_i, w) + s(v_i; w) = 0,  alpha = 1/(a_ii dt),
+ * s the steady residual, with (u*_i, w) = (u_n, w) - dt sum_{j<i} a_ij s(v_j; w) formed
+ * on the element L2 products b(v) = (u(v), phi_a)_K from the converged earlier stages
+ * (s(v_j; w) = -alpha (u(v_j) - u*_j, w)), and u*_i = M_K^-1 b*_i as nodal values.  The
+ * scheme is stiffly accurate: (v, q, vhat) are replaced by the last stage's solution
+ * (each stage starts from the previous one).  Sets the plan's alpha to 1/(a_ii dt) (left
+ * so afterwards).  info[3]: one hdg_newton_info per stage.  work: device, 256-byte
+ * aligned, at least hdg_dirk_workspace_bytes.  Errors as hdg_newton_solve; a stage that
+ * does not converge is reported in its info, not as an error. */
+int hdg_dirk_workspace_bytes(const hdg_plan *plan, const hdg_newton_opts *opts, size_t *bytes);
+int hdg_dirk_step(hdg_plan *plan, double *v, double *q, double *vhat, const double *v_bc, double dt,
+                  void *work, size_t bytes, const hdg_newton_opts *opts, hdg_newton_info *info, void *stream);
+
 /* Optional per-phase timing with HIP events recorded on the call's stream
  * around each kernel group: 0 points (pointwise physics), 1 contract (block
  * assembly), 2 LU, 3 triangular solves, 4 Schur product (split dense path),

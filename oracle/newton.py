@@ -61,3 +61,61 @@ def l2_error_u(disc: hdg.Discretization, v, u_exact):
         du = ph.u_of_v(vq, disc.phys.gamma) - u_exact(G.xq)
         err += np.sum(G.W[:, None] * du ** 2)
     return np.sqrt(err)
+
+
+# ---- one step of Alexander's three-stage L-stable DIRK(3,3) (the time integration of
+# the paper's numerical examples, Section 5).  Stage i solves
+#   alpha (u(v_i) - u*_i, w) + s(v_i; w) = 0,   alpha = 1 / (a_ii dt),
+# with (u*_i, w) = (u_n, w) - dt sum_{j<i} a_ij s(v_j; w).  A converged stage j gives
+# s(v_j; w) = -alpha (u(v_j) - u*_j, w); on the element L2 products b(v) = (u(v), phi_a)_K
+# this is b*_i = b(v_n) + sum_{j<i} (a_ij / a_jj) (b(v_j) - b*_j), and u*_i = M_K^-1 b*_i
+# as nodal values.  Stiffly accurate: the step ends in the last stage's state.
+
+DIRK33_G = 0.435866521508459   # root of x^3 - 3x^2 + 3x/2 - 1/6 in (1/6, 1/2)
+
+
+def dirk33_tableau():
+    g = DIRK33_G
+    return np.array([[g, 0.0, 0.0],
+                     [0.5 * (1.0 - g), g, 0.0],
+                     [-0.25 * (6 * g * g - 16 * g + 1), 0.25 * (6 * g * g - 20 * g + 5), g]])
+
+
+def weak_u(disc: hdg.Discretization, v):
+    """b[c][e Np + a] = (u_c(v_h), phi_a)_K by the element quadrature."""
+    from . import physics as ph
+    Np, phi = disc.Np, disc.ref.phi
+    b = np.zeros_like(v)
+    for e in range(disc.mesh.n_elem):
+        sl = slice(e * Np, (e + 1) * Np)
+        uq = ph.u_of_v(phi @ v[:, sl].T, disc.phys.gamma)
+        b[:, sl] = (phi.T @ (disc.geom(e).W[:, None] * uq)).T
+    return b
+
+
+def mass_solve(disc: hdg.Discretization, b):
+    """u[:, K] = M_K^-1 b[:, K], M_K the element mass matrix (phi_a, phi_b)_K."""
+    Np, phi = disc.Np, disc.ref.phi
+    u = np.zeros_like(b)
+    for e in range(disc.mesh.n_elem):
+        sl = slice(e * Np, (e + 1) * Np)
+        Mk = phi.T @ (disc.geom(e).W[:, None] * phi)
+        u[:, sl] = np.linalg.solve(Mk, b[:, sl].T).T
+    return u
+
+
+def dirk33_step(disc: hdg.Discretization, v, q, vhat, dt, vbc=None, tol=1e-11, maxit=12):
+    """One DIRK(3,3) step; the discretization's alpha must be 1 / (a_ii dt)."""
+    A = dirk33_tableau()
+    assert abs(disc.phys.alpha * A[0, 0] * dt - 1.0) < 1e-12
+    bn = weak_u(disc, v)
+    d, hists = [], []
+    for i in range(3):
+        bs = bn.copy()
+        for j in range(i):
+            bs = bs + (A[i, j] / A[j, j]) * d[j]
+        v, q, vhat, hist = newton_steady(disc, v, q, vhat, vbc=vbc, tol=tol, maxit=maxit,
+                                         ustar=mass_solve(disc, bs))
+        hists.append(hist)
+        d.append(weak_u(disc, v) - bs)
+    return v, q, vhat, hists

@@ -117,6 +117,9 @@ SIGNATURES = {
     "hdg_newton_workspace_bytes": (I, [P, ctypes.POINTER(hdg_newton_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "hdg_newton_solve": (I, [P, P, P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_newton_opts),
                              ctypes.POINTER(hdg_newton_info), P]),
+    "hdg_dirk_workspace_bytes": (I, [P, ctypes.POINTER(hdg_newton_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_dirk_step": (I, [P, P, P, P, P, ctypes.c_double, P, ctypes.c_size_t, ctypes.POINTER(hdg_newton_opts),
+                          ctypes.POINTER(hdg_newton_info), P]),
     "hdg_learn_nparams": (I, []),
     "hdg_learn_setup": (I, [P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),
     "hdg_learn_forward": (I, [P, P, P, P, P]),

@@ -158,3 +158,95 @@ extern "C" int hdg_newton_solve(hdg_plan *plan, double *v, double *q, double *vh
   info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return HDG_OK;
 }
+
+// ---- DIRK(3,3) step (Alexander's three-stage, L-stable, stiffly accurate scheme)
+//
+// Stage i solves  alpha (u(v_i) - u*_i, w) + s(v_i; w) = 0,  alpha = 1/(a_ii dt), with the
+// steady residual s and (u*_i, w) = (u_n, w) - dt sum_{j<i} a_ij s(v_j; w).  The converged
+// stage j gives s(v_j; w) = -alpha (u(v_j) - u*_j, w), so on the element L2 products
+// b(v) = (u(v), phi_a)_K:   b*_i = b(v_n) + sum_{j<i} (a_ij / a_jj) (b(v_j) - b*_j),  and the
+// nodal u*_i = M_K^-1 b*_i makes the stage's mass term exact.  The new state is the last
+// stage's (stiffly accurate).  The plan's alpha is set to 1/(a_ii dt) and left there.
+namespace {
+
+constexpr double DIRK_G = 0.435866521508459;   // a_ii, root of x^3 - 3x^2 + 3x/2 - 1/6 in (1/6, 1/2)
+
+struct DirkLayout {
+  size_t bn, bs, d0, d1, us, newton, total;
+};
+
+DirkLayout dirk_layout(const Plan *P, size_t newton_bytes) {
+  const size_t NM = (size_t)P->dp.m * P->n_elem * P->dp.Np * 8;
+  DirkLayout l{};
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    size_t r = o;
+    o = a256(o + b);
+    return r;
+  };
+  l.bn = take(NM);
+  l.bs = take(NM);
+  l.d0 = take(NM);
+  l.d1 = take(NM);
+  l.us = take(NM);
+  l.newton = take(newton_bytes);
+  l.total = o;
+  return l;
+}
+
+}  // namespace
+
+extern "C" int hdg_dirk_workspace_bytes(const hdg_plan *plan, const hdg_newton_opts *opts, size_t *bytes) {
+  size_t nb = 0;
+  int rc = hdg_newton_workspace_bytes(plan, opts, &nb);
+  if (rc) return rc;
+  *bytes = dirk_layout(reinterpret_cast<const Plan *>(plan), nb).total;
+  return HDG_OK;
+}
+
+extern "C" int hdg_dirk_step(hdg_plan *plan, double *v, double *q, double *vhat, const double *v_bc, double dt,
+                             void *work, size_t bytes, const hdg_newton_opts *opts, hdg_newton_info *info,
+                             void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  if (!v || !vhat || !work || !info || !check_opts(opts) || !(dt > 0.0)) return fail(HDG_EINVAL, "bad argument");
+  size_t nb = 0;
+  int rc = hdg_newton_workspace_bytes(plan, opts, &nb);
+  if (rc) return rc;
+  const DirkLayout l = dirk_layout(P, nb);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "DIRK workspace smaller than hdg_dirk_workspace_bytes");
+  if (reinterpret_cast<uintptr_t>(work) & 255) return fail(HDG_EINVAL, "workspace must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(work);
+  auto ptr = [&](size_t off) { return reinterpret_cast<double *>(base + off); };
+  double *bn = ptr(l.bn), *bs = ptr(l.bs), *us = ptr(l.us);
+  double *d[2] = {ptr(l.d0), ptr(l.d1)};
+  const size_t NM = (size_t)P->dp.m * P->n_elem * P->dp.Np;
+  const double g = DIRK_G;
+  const double a[3][3] = {{g, 0.0, 0.0},
+                          {0.5 * (1.0 - g), g, 0.0},
+                          {-0.25 * (6.0 * g * g - 16.0 * g + 1.0), 0.25 * (6.0 * g * g - 20.0 * g + 5.0), g}};
+  hdg_phys ph = P->phys;
+  ph.alpha = 1.0 / (g * dt);
+  rc = hdg_plan_set_phys(plan, &ph);
+  if (rc) return rc;
+  hipError_t e = launch_weak_u(P->dp, v, bn, s);
+  if (e) return hip_fail(e, "DIRK stage products");
+  for (int i = 0; i < 3; ++i) {
+    // b*_i = b_n + sum_{j<i} (a_ij / a_jj) d_j,  d_j = b(v_j) - b*_j
+    e = launch_axpby(1.0, bn, 0.0, nullptr, bs, NM, s);
+    for (int j = 0; j < i && !e; ++j) e = launch_axpby(1.0, bs, a[i][j] / a[j][j], d[j], bs, NM, s);
+    if (!e) e = launch_mass_solve(P->dp, bs, us, s);
+    if (e) return hip_fail(e, "DIRK stage state");
+    rc = hdg_newton_solve(plan, v, q, vhat, us, v_bc, base + l.newton, nb, opts, info + i, stream);
+    if (rc) return rc;
+    if (i < 2) {
+      e = launch_weak_u(P->dp, v, d[i], s);
+      if (!e) e = launch_axpby(1.0, d[i], -1.0, bs, d[i], NM, s);
+      if (e) return hip_fail(e, "DIRK stage products");
+    }
+  }
+  e = hipStreamSynchronize(s);
+  if (e) return hip_fail(e, "DIRK step");
+  return HDG_OK;
+}

@@ -206,6 +206,9 @@ hipError_t launch_backsolve(const DevPlan &P, const double *Y, const double *z, 
 hipError_t launch_trace_matvec(const DevPlan &P, const double *S, const double *x, double *y,
                                hipStream_t s);
 hipError_t launch_trace_rhs(const DevPlan &P, const double *g, double *r, hipStream_t s);
+// element L2 products of the DIRK stage combination (hdg_stage.hip)
+hipError_t launch_weak_u(const DevPlan &P, const double *v, double *b, hipStream_t s);
+hipError_t launch_mass_solve(const DevPlan &P, const double *b, double *u, hipStream_t s);
 hipError_t launch_prepare_state(const DevPlan &P, int N, const double *prim, const double *grad,
                                 double *v, double *q, double *u, hipStream_t s);
 

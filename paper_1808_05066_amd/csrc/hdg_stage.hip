@@ -1,0 +1,127 @@
+// Element L2 products for the stage combination of a DIRK step:
+//   b_K = (u(v_h), phi_a)_K        (weak form of the conserved state, quadrature)
+//   u*  = M_K^-1 b_K               (the nodal state whose L2 products are b_K)
+// so that the mass term alpha (u(v) - u*, w) of a stage sees exactly the
+// combination of previous stages formed on the b vectors.  Layouts: v, b, u
+// [m][E*Np] (structure of arrays, element-major nodes).
+#include "hdg_physics.hpp"
+#include "hdg_plan.hpp"
+
+namespace hdg {
+
+namespace {
+
+constexpr int SB = 128;
+
+// b[c][e Np + a] = sum_q W_q u_c(v(x_q)) phi_a(x_q)
+template <int D>
+__global__ __launch_bounds__(SB) void k_weak_u(DevPlan P, const double *__restrict__ v, double *b) {
+  constexpr int M = D + 2;
+  extern __shared__ double sm[];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int Np = P.Np, Nq = P.Nq;
+  const size_t NN = (size_t)P.n_elem * Np;
+  double *vs = sm;              // [M][Np]
+  double *uq = vs + M * Np;     // [Nq][M] W_q u(v(x_q))
+  for (int t = tid; t < M * Np; t += SB) vs[t] = v[(size_t)(t / Np) * NN + (size_t)e * Np + t % Np];
+  __syncthreads();
+  const int gs = 1 + D * D;
+  for (int q = tid; q < Nq; q += SB) {
+    double vq[M];
+    for (int c = 0; c < M; ++c) {
+      double acc = 0.0;
+      for (int a = 0; a < Np; ++a) acc += P.phi[(size_t)q * Np + a] * vs[c * Np + a];
+      vq[c] = acc;
+    }
+    const Prim<D, double> s = prim_of_v<D, double>(vq, P.gamma);
+    double u[M];
+    u_of_prim<D, double>(s, P.gamma, u);
+    const double W = P.geo_vol[((size_t)e * Nq + q) * gs];
+    for (int c = 0; c < M; ++c) uq[q * M + c] = W * u[c];
+  }
+  __syncthreads();
+  for (int t = tid; t < M * Np; t += SB) {
+    const int c = t / Np, a = t % Np;
+    double acc = 0.0;
+    for (int q = 0; q < Nq; ++q) acc += uq[q * M + c] * P.phi[(size_t)q * Np + a];
+    b[(size_t)c * NN + (size_t)e * Np + a] = acc;
+  }
+}
+
+// u[c][e Np + :] = M_K^-1 b[c][e Np + :],  M_K[a][a'] = sum_q W_q phi_a phi_a'
+// (Cholesky in LDS: M_K is symmetric positive definite)
+template <int D>
+__global__ __launch_bounds__(SB) void k_mass_solve(DevPlan P, const double *__restrict__ b, double *u) {
+  constexpr int M = D + 2;
+  extern __shared__ double sm[];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int Np = P.Np, Nq = P.Nq;
+  const size_t NN = (size_t)P.n_elem * Np;
+  double *L = sm;              // [Np][Np], lower triangle
+  double *x = L + Np * Np;     // [M][Np]
+  double *W = x + M * Np;      // [Nq]
+  const int gs = 1 + D * D;
+  for (int q = tid; q < Nq; q += SB) W[q] = P.geo_vol[((size_t)e * Nq + q) * gs];
+  for (int t = tid; t < M * Np; t += SB) x[t] = b[(size_t)(t / Np) * NN + (size_t)e * Np + t % Np];
+  __syncthreads();
+  for (int t = tid; t < Np * Np; t += SB) {
+    const int i = t / Np, j = t % Np;
+    double acc = 0.0;
+    if (j <= i)
+      for (int q = 0; q < Nq; ++q) acc += W[q] * P.phi[(size_t)q * Np + i] * P.phi[(size_t)q * Np + j];
+    L[t] = acc;
+  }
+  __syncthreads();
+  // right-looking Cholesky, column k per pass
+  for (int k = 0; k < Np; ++k) {
+    if (tid == 0) L[k * Np + k] = sqrt(L[k * Np + k]);
+    __syncthreads();
+    const double d = L[k * Np + k];
+    for (int i = k + 1 + tid; i < Np; i += SB) L[i * Np + k] /= d;
+    __syncthreads();
+    for (int t = tid; t < (Np - k - 1) * (Np - k - 1); t += SB) {
+      const int i = k + 1 + t / (Np - k - 1), j = k + 1 + t % (Np - k - 1);
+      if (j <= i) L[i * Np + j] -= L[i * Np + k] * L[j * Np + k];
+    }
+    __syncthreads();
+  }
+  // L L^T x = b for the M components, one thread per component
+  for (int c = tid; c < M; c += SB) {
+    double *xc = x + c * Np;
+    for (int i = 0; i < Np; ++i) {
+      double s = xc[i];
+      for (int j = 0; j < i; ++j) s -= L[i * Np + j] * xc[j];
+      xc[i] = s / L[i * Np + i];
+    }
+    for (int i = Np - 1; i >= 0; --i) {
+      double s = xc[i];
+      for (int j = i + 1; j < Np; ++j) s -= L[j * Np + i] * xc[j];
+      xc[i] = s / L[i * Np + i];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < M * Np; t += SB) u[(size_t)(t / Np) * NN + (size_t)e * Np + t % Np] = x[t];
+}
+
+}  // namespace
+
+hipError_t launch_weak_u(const DevPlan &P, const double *v, double *b, hipStream_t s) {
+  const size_t lds = (size_t)((P.dim + 2) * P.Np + P.Nq * (P.dim + 2)) * sizeof(double);
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_weak_u<2>, dim3(P.n_elem), dim3(SB), lds, s, P, v, b);
+  else
+    hipLaunchKernelGGL(k_weak_u<3>, dim3(P.n_elem), dim3(SB), lds, s, P, v, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass_solve(const DevPlan &P, const double *b, double *u, hipStream_t s) {
+  const size_t lds = (size_t)(P.Np * P.Np + (P.dim + 2) * P.Np + P.Nq) * sizeof(double);
+  if (lds > 64 * 1024) return hipErrorInvalidValue;
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_mass_solve<2>, dim3(P.n_elem), dim3(SB), lds, s, P, b, u);
+  else
+    hipLaunchKernelGGL(k_mass_solve<3>, dim3(P.n_elem), dim3(SB), lds, s, P, b, u);
+  return hipGetLastError();
+}
+
+}  // namespace hdg

@@ -275,6 +275,30 @@ class Plan:
         res["res"] = [info.res[i] for i in range(min(_lib.HDG_NEWTON_HIST, info.iterations + 1))]
         return res
 
+    def dirk_step(self, v, q, vhat, dt, vbc=None, maxit=10, tol=1e-10, atol=0.0, lin_tol=1e-12, lin_restart=50,
+                  lin_maxit=2000, precond="block_jacobi"):
+        """One DIRK(3,3) step (hdg_dirk_step): v, q, vhat replaced in place by the step's end state;
+        sets the plan's alpha to 1/(a_ii dt).  Returns one info dict per stage."""
+        torch = _torch()
+        lo = _lib.hdg_solve_opts(int(lin_restart), int(lin_maxit), float(lin_tol), TraceSolver.PRECONDS[precond],
+                                 _lib.HDG_FP64)
+        opts = _lib.hdg_newton_opts(int(maxit), float(tol), float(atol), lo)
+        nb = ctypes.c_size_t()
+        check(self.lib.hdg_dirk_workspace_bytes(self.h, ctypes.byref(opts), ctypes.byref(nb)),
+              "hdg_dirk_workspace_bytes")
+        work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        wp = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        infos = (_lib.hdg_newton_info * 3)()
+        check(self.lib.hdg_dirk_step(self.h, _ptr(v), _ptr(q), _ptr(vhat), _ptr(vbc), ctypes.c_double(dt), wp,
+                                     ctypes.c_size_t(nb.value), ctypes.byref(opts), infos, _stream()),
+              "hdg_dirk_step")
+        out = []
+        for info in infos:
+            res = {f: getattr(info, f) for f, _ in _lib.hdg_newton_info._fields_ if f != "res"}
+            res["res"] = [info.res[i] for i in range(min(_lib.HDG_NEWTON_HIST, info.iterations + 1))]
+            out.append(res)
+        return out
+
     def trace_rhs(self, g, r=None):
         if r is None:
             r = self._empty(self.m, self.n_trace)

@@ -23,6 +23,29 @@ def gpu_plan(wl, chunk_elems=0, split_dense=False, narrow_block=False, eliminate
                 split_dense=split_dense, narrow_block=narrow_block, eliminate_q=eliminate_q)
 
 
+def smooth_periodic_case(dt, n=2, p=2, mu=0.02, Pr=0.72, gamma=1.4):
+    """Smooth periodic Navier-Stokes state on an n x n triangle mesh (seeded jitter); the
+    discretization carries the DIRK(3,3) stage coefficient alpha = 1 / (a_ii dt).
+    Returns (mesh data for a GPU plan, oracle discretization, v, q = 0, vhat)."""
+    from oracle import newton, physics as ph
+    from workloads import meshes as M
+    mesh = M.tri_square(n, 0.05, 7, periodic=True)
+    tmap, nt = M.trace_map(mesh, p, "hdg")
+    alpha = 1.0 / (newton.DIRK33_G * dt)
+    face_bc = np.zeros((mesh.n_elem, 3), dtype=np.int32)
+    disc = ohdg.Discretization(mesh, p, ohdg.Phys(gamma, mu, Pr, alpha, True), tmap, nt, face_bc)
+
+    def v_of(x):
+        r = 1 + 0.1 * np.sin(2 * np.pi * x[0]) * np.cos(2 * np.pi * x[1])
+        V = np.stack([0.3 + 0.05 * np.cos(2 * np.pi * x[1]), -0.2 + 0.05 * np.sin(2 * np.pi * x[0])], axis=-1)
+        pp = 1 + 0.05 * np.cos(2 * np.pi * (x[0] + x[1]))
+        return ph.v_of_prim(r, V, pp, gamma).T.copy()
+
+    v0, vh0 = v_of(disc.node_coords()), v_of(disc.trace_coords())
+    md = dict(mesh=mesh, p=p, tmap=tmap, n_trace=nt, face_bc=face_bc, mu=mu, Pr=Pr, gamma=gamma, alpha=alpha)
+    return md, disc, v0, np.zeros((4 * 2, v0.shape[1])), vh0
+
+
 def to_dev(inp):
     import torch
     out = {}

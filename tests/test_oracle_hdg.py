@@ -18,6 +18,8 @@ from oracle import hdg, newton, physics as ph, state
 from workloads import configs as C
 from workloads import meshes as M
 
+from cases import smooth_periodic_case
+
 GAM = 1.4
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -365,3 +367,32 @@ def test_implicit_stage_newton_returns_to_uniform_flow():
     assert np.max(np.abs(v - v_ex)) < 1e-10 * np.max(np.abs(vc))
     assert np.max(np.abs(q)) < 1e-9
     assert np.max(np.abs(vh - vh_ex)) < 1e-10 * np.max(np.abs(vc))
+
+
+def test_dirk33_tableau_order_conditions():
+    """Alexander's DIRK(3,3): a_ii is the root of x^3 - 3x^2 + 3x/2 - 1/6 in (1/6, 1/2); the
+    stiffly accurate weights (last row) satisfy the third-order conditions."""
+    A = newton.dirk33_tableau()
+    g = A[0, 0]
+    assert abs(g ** 3 - 3 * g ** 2 + 1.5 * g - 1.0 / 6.0) < 1e-15
+    b, c = A[2], A.sum(axis=1)
+    assert abs(c[2] - 1.0) < 1e-15
+    for lhs, rhs in ((b.sum(), 1.0), (b @ c, 0.5), (b @ c ** 2, 1.0 / 3.0), (b @ A @ c, 1.0 / 6.0)):
+        assert abs(lhs - rhs) < 1e-14
+
+
+def test_dirk33_step_temporal_order():
+    """Self-convergence in time of the oracle's DIRK(3,3) steps on a smooth periodic flow (T = 0.2
+    in 2, 4, 8 steps): the error ratio must show third order (rate >= 2.5; a wrong stage
+    coefficient drops it to 2 or below)."""
+    out = {}
+    for nsteps in (2, 4, 8):
+        dt = 0.2 / nsteps
+        _, disc, v, q, vh = smooth_periodic_case(dt)
+        for _ in range(nsteps):
+            v, q, vh, hists = newton.dirk33_step(disc, v, q, vh, dt)
+            assert all(h[-1] < 1e-11 for h in hists), hists
+        out[nsteps] = v
+    e1 = np.linalg.norm(out[2] - out[4])
+    e2 = np.linalg.norm(out[4] - out[8])
+    assert np.log2(e1 / e2) >= 2.5, (e1, e2)
