@@ -187,6 +187,20 @@ def bench_newton(plan, inp, torch, maxit=8, tol=1e-10):
             "tol_rel": tol}
 
 
+def bench_dirk(plan, inp, dt, torch):
+    """One DIRK(3,3) step (hdg_dirk_step, three Newton-solved stages) from the benchmark's state."""
+    v, vh = inp["v"].clone(), inp["vhat"].clone()
+    q = None if inp["q"] is None else inp["q"].clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stages = plan.dirk_step(v, q, vh, dt, vbc=inp["vbc"], tol=1e-10, lin_tol=1e-10)
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"dt": dt, "ms": ms, "newton_iterations": [st["iterations"] for st in stages],
+            "gmres_iterations": [st["lin_iterations"] for st in stages],
+            "converged": all(st["converged"] for st in stages),
+            "final_residuals": [st["res"][-1] for st in stages]}
+
+
 def bench_batch(torch, tune=True):
     """Mixed batch: 20,250 Kuhn tetrahedra with orders drawn from {1,2,3,4} plus 4,096 p = 2 hexes (NS).
 
@@ -430,6 +444,9 @@ def main():
     if not args.no_newton:
         print("[bench] Newton iterations of one implicit stage", file=sys.stderr, flush=True)
         res["newton"] = bench_newton(plan, inp, torch)
+    if not args.no_newton and wl.viscous and wl.alpha > 0:
+        print("[bench] one DIRK(3,3) step", file=sys.stderr, flush=True)
+        res["dirk_step"] = bench_dirk(plan, inp, 1.0 / (wl.alpha * C.DIRK33_AII), torch)
     if not args.no_mixed:
         print("[bench] mixed-precision path", file=sys.stderr, flush=True)
         res["mixed"] = bench_mixed(plan, inp, out, E, cond_ms, torch)
