@@ -127,6 +127,22 @@ void hdg_plan_destroy(hdg_plan *plan);
  * takes effect at the next call. */
 int hdg_plan_set_phys(hdg_plan *plan, const hdg_phys *phys);
 int hdg_plan_dims(const hdg_plan *plan, hdg_dims *out);
+/* Source term of the conservation law (the right-hand side s of the Navier-Stokes
+ * equations with a source, as in the Couette problem of Section 5): nodal values
+ * src [m][E*Np] in the layout of v (device, caller-owned, read at every assemble
+ * until replaced; NULL removes it).  The element residual receives -(s_h, w) with s_h
+ * the nodal interpolant at the volume quadrature points; the Jacobian is unchanged. */
+int hdg_plan_set_source(hdg_plan *plan, const double *src);
+/* Physical coordinates of the volume quadrature points, xq [dim][E*Nq] (device),
+ * element-major (e Nq + q): the image of the reference points under the element map. */
+int hdg_quad_coords(const hdg_plan *plan, double *xq, void *stream);
+/* Element L2 errors against values at the volume quadrature points (xq order):
+ *   out[e][c] = sum_q W_q (f_c(x_q) - exact[c][e Nq + q])^2,
+ * kind 0: f = u(v_h) from v [m][E*Np], c < m (conserved variables);
+ * kind 1: f = the gradient unknowns q [m*dim][E*Np] interpolated, c < m*dim (NS only).
+ * All device; out [E][m] or [E][m*dim]. */
+int hdg_l2_error(const hdg_plan *plan, int kind, const double *f, const double *exact, double *out,
+                 void *stream);
 
 /* Bytes of device workspace the plan needs (tables + per-chunk scratch). */
 int hdg_plan_workspace_bytes(const hdg_plan *plan, size_t *bytes);

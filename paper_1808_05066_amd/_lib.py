@@ -120,6 +120,9 @@ SIGNATURES = {
     "hdg_dirk_workspace_bytes": (I, [P, ctypes.POINTER(hdg_newton_opts), ctypes.POINTER(ctypes.c_size_t)]),
     "hdg_dirk_step": (I, [P, P, P, P, P, ctypes.c_double, P, ctypes.c_size_t, ctypes.POINTER(hdg_newton_opts),
                           ctypes.POINTER(hdg_newton_info), P]),
+    "hdg_plan_set_source": (I, [P, P]),
+    "hdg_quad_coords": (I, [P, P, P]),
+    "hdg_l2_error": (I, [P, I, P, P, P, P]),
     "hdg_learn_nparams": (I, []),
     "hdg_learn_setup": (I, [P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),
     "hdg_learn_forward": (I, [P, P, P, P, P]),

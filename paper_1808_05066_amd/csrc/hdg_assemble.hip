@@ -33,15 +33,17 @@ __global__ __launch_bounds__(128) void k_vol_points(DevPlan P, int e0, int ec, c
   const size_t NN = (size_t)P.n_elem * Np;
   const double *phi = P.phi + (size_t)qp * Np;
   const size_t nb = (size_t)e * Np;
-  double vq[M], qq[VISC ? M * D : 1], us[M];
+  double vq[M], qq[VISC ? M * D : 1], us[M], sq[M];
   for (int c = 0; c < M; ++c) {
-    double s = 0.0, t = 0.0;
+    double s = 0.0, t = 0.0, f = 0.0;
     for (int a = 0; a < Np; ++a) {
       s += phi[a] * v[c * NN + nb + a];
       if (ustar) t += phi[a] * ustar[c * NN + nb + a];
+      if (P.src) f += phi[a] * P.src[c * NN + nb + a];
     }
     vq[c] = s;
     us[c] = t;
+    sq[c] = f;
   }
   if (VISC)
     for (int s = 0; s < M * D; ++s) {
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(128) void k_vol_points(DevPlan P, int e0, int ec, c
       }
     if (t == 0) {
       for (int c = 0; c < M; ++c) {
-        out[L.Wu + c] = W * alpha * (u[c].v - us[c]);
+        out[L.Wu + c] = W * (alpha * (u[c].v - us[c]) - sq[c]);
         for (int r = 0; r < D; ++r) {
           double acc = 0.0;
           for (int j = 0; j < D; ++j) acc += F[c * D + j].v * Ji[r * D + j];

@@ -287,6 +287,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   }
   D.contract_threads = 1024;
   D.zero_xcd = 1;
+  D.src = nullptr;
   D.a_qmin = 0;
   D.condense_launches = 2;
   P->fused = D.cw != 0;
@@ -358,6 +359,33 @@ extern "C" int hdg_plan_set_phys(hdg_plan *plan, const hdg_phys *phys) {
   P->dp.mu = phys->mu;
   P->dp.Pr = phys->Pr;
   P->dp.alpha = phys->alpha;
+  return HDG_OK;
+}
+
+extern "C" int hdg_plan_set_source(hdg_plan *plan, const double *src) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P) return fail(HDG_EINVAL, "null plan");
+  P->dp.src = src;
+  return HDG_OK;
+}
+
+extern "C" int hdg_quad_coords(const hdg_plan *plan, double *xq, void *stream) {
+  const Plan *P = checked(const_cast<hdg_plan *>(plan));
+  if (!P) return HDG_EINVAL;
+  if (!xq) return fail(HDG_EINVAL, "null argument");
+  hipError_t e = launch_quad_coords(P->dp, xq, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "quad_coords");
+  return HDG_OK;
+}
+
+extern "C" int hdg_l2_error(const hdg_plan *plan, int kind, const double *f, const double *exact, double *out,
+                            void *stream) {
+  const Plan *P = checked(const_cast<hdg_plan *>(plan));
+  if (!P) return HDG_EINVAL;
+  if (!f || !exact || !out || kind < 0 || kind > 1 || (kind == 1 && !P->dp.viscous))
+    return fail(HDG_EINVAL, "bad argument");
+  hipError_t e = launch_l2_error(P->dp, kind, f, exact, out, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "l2_error");
   return HDG_OK;
 }
 

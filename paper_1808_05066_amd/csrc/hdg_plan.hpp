@@ -26,6 +26,7 @@ struct DevPlan {
   int a_qmin;              // 1: of the q rows of A only M and G_j of the first component are formed
   int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
   double gamma, mu, Pr, alpha;
+  const double *src;       // [m][E*Np] nodal source of the conservation law (device, caller-owned) or null
   PointLayout L;
   // tables (device)
   const double *phi;       // [Nq][Np]
@@ -209,6 +210,9 @@ hipError_t launch_trace_rhs(const DevPlan &P, const double *g, double *r, hipStr
 // element L2 products of the DIRK stage combination (hdg_stage.hip)
 hipError_t launch_weak_u(const DevPlan &P, const double *v, double *b, hipStream_t s);
 hipError_t launch_mass_solve(const DevPlan &P, const double *b, double *u, hipStream_t s);
+hipError_t launch_quad_coords(const DevPlan &P, double *xq, hipStream_t s);
+hipError_t launch_l2_error(const DevPlan &P, int kind, const double *f, const double *ex, double *out,
+                           hipStream_t s);
 hipError_t launch_prepare_state(const DevPlan &P, int N, const double *prim, const double *grad,
                                 double *v, double *q, double *u, hipStream_t s);
 

@@ -1,4 +1,5 @@
-// Element L2 products for the stage combination of a DIRK step:
+// Element L2 products for the stage combination of a DIRK step, quadrature-point
+// coordinates and element L2 errors against values at the quadrature points:
 //   b_K = (u(v_h), phi_a)_K        (weak form of the conserved state, quadrature)
 //   u*  = M_K^-1 b_K               (the nodal state whose L2 products are b_K)
 // so that the mass term alpha (u(v) - u*, w) of a stage sees exactly the
@@ -103,7 +104,74 @@ __global__ __launch_bounds__(SB) void k_mass_solve(DevPlan P, const double *__re
   for (int t = tid; t < M * Np; t += SB) u[(size_t)(t / Np) * NN + (size_t)e * Np + t % Np] = x[t];
 }
 
+// x_q = sum_a phi_a(x_q) x_a (exact for straight-sided simplices and multilinear quads/hexes)
+__global__ void k_quad_coords(DevPlan P, double *xq) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t NQ = (size_t)P.n_elem * P.Nq, NN = (size_t)P.n_elem * P.Np;
+  if (t >= NQ) return;
+  const int e = (int)(t / P.Nq), q = (int)(t % P.Nq);
+  for (int d = 0; d < P.dim; ++d) {
+    double acc = 0.0;
+    for (int a = 0; a < P.Np; ++a) acc += P.phi[(size_t)q * P.Np + a] * P.node_x[(size_t)d * NN + (size_t)e * P.Np + a];
+    xq[(size_t)d * NQ + t] = acc;
+  }
+}
+
+// out[e][c] = sum_q W_q (f_c(x_q) - ex[c][e Nq + q])^2 with f_c = u_c(v_h) (kind 0, f = v) or
+// the interpolated gradient unknowns (kind 1, f = q)
+template <int D>
+__global__ __launch_bounds__(64) void k_l2_error(DevPlan P, int kind, const double *__restrict__ f,
+                                                 const double *__restrict__ ex, double *out) {
+  constexpr int M = D + 2, NC = M * D;
+  __shared__ double red[64][NC];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int Np = P.Np, Nq = P.Nq, nc = kind == 0 ? M : NC;
+  const size_t NN = (size_t)P.n_elem * Np, NQ = (size_t)P.n_elem * Nq;
+  double acc[NC];
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  for (int q = tid; q < Nq; q += 64) {
+    const double *phi = P.phi + (size_t)q * Np;
+    double val[NC];
+    for (int c = 0; c < nc; ++c) {
+      double s = 0.0;
+      for (int a = 0; a < Np; ++a) s += phi[a] * f[(size_t)c * NN + (size_t)e * Np + a];
+      val[c] = s;
+    }
+    if (kind == 0) {
+      const Prim<D, double> st = prim_of_v<D, double>(val, P.gamma);
+      u_of_prim<D, double>(st, P.gamma, val);
+    }
+    const double W = P.geo_vol[((size_t)e * Nq + q) * (1 + D * D)];
+    for (int c = 0; c < nc; ++c) {
+      const double d = val[c] - ex[(size_t)c * NQ + (size_t)e * Nq + q];
+      acc[c] += W * d * d;
+    }
+  }
+  for (int c = 0; c < nc; ++c) red[tid][c] = acc[c];
+  __syncthreads();
+  if (tid < nc) {
+    double s = 0.0;
+    for (int t = 0; t < 64; ++t) s += red[t][tid];
+    out[(size_t)e * nc + tid] = s;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_quad_coords(const DevPlan &P, double *xq, hipStream_t s) {
+  const size_t NQ = (size_t)P.n_elem * P.Nq;
+  hipLaunchKernelGGL(k_quad_coords, dim3((unsigned)((NQ + 255) / 256)), dim3(256), 0, s, P, xq);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2_error(const DevPlan &P, int kind, const double *f, const double *ex, double *out,
+                           hipStream_t s) {
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_l2_error<2>, dim3(P.n_elem), dim3(64), 0, s, P, kind, f, ex, out);
+  else
+    hipLaunchKernelGGL(k_l2_error<3>, dim3(P.n_elem), dim3(64), 0, s, P, kind, f, ex, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_weak_u(const DevPlan &P, const double *v, double *b, hipStream_t s) {
   const size_t lds = (size_t)((P.dim + 2) * P.Np + P.Nq * (P.dim + 2)) * sizeof(double);

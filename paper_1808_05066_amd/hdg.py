@@ -299,6 +299,27 @@ class Plan:
             out.append(res)
         return out
 
+    def set_source(self, src):
+        """Nodal source [m][E*Np] of the conservation law (a device tensor kept alive by the
+        plan), or None to remove it."""
+        self._src = src
+        check(self.lib.hdg_plan_set_source(self.h, _ptr(src)), "hdg_plan_set_source")
+
+    def quad_coords(self):
+        """Physical coordinates of the volume quadrature points [dim][E*Nq]."""
+        xq = self._empty(self.dim, self.n_elem * self.Nq)
+        check(self.lib.hdg_quad_coords(self.h, _ptr(xq), _stream()), "hdg_quad_coords")
+        return xq
+
+    def l2_error(self, f, exact, kind="u"):
+        """Per-component squared L2 errors summed over the elements (hdg_l2_error): kind "u"
+        compares u(v_h) from v with exact conserved variables, kind "q" the gradient unknowns."""
+        k = {"u": 0, "q": 1}[kind]
+        nc = self.m if k == 0 else self.m * self.dim
+        out = self._empty(self.n_elem, nc)
+        check(self.lib.hdg_l2_error(self.h, k, _ptr(f), _ptr(exact), _ptr(out), _stream()), "hdg_l2_error")
+        return out.sum(dim=0)
+
     def trace_rhs(self, g, r=None):
         if r is None:
             r = self._empty(self.m, self.n_trace)

@@ -206,3 +206,34 @@ def test_q_elimination_needs_gradient_unknowns(torch):
     wl, _, _, _ = _case("euler2d_tri_p2")
     with pytest.raises(_lib.HdgError):
         gpu_plan(wl, eliminate_q=True)
+
+
+@pytest.mark.parametrize("name", ["ns2d_tri_p2", "ns3d_hex_p1"])
+def test_source_term_matches_oracle(torch, name):
+    """hdg_plan_set_source: a source linear in x (its nodal interpolant is exact, so the GPU's
+    interpolated source and the oracle's source at the quadrature points are the same
+    function); R_loc against the oracle's element residual with that source, R_tr and the
+    Jacobian unchanged."""
+    wl, disc, inp, blocks = _case(name)
+    rng = np.random.default_rng(42)
+    coef = rng.standard_normal((disc.m, 1 + disc.d))
+
+    def src(x):   # x (Nq, d) -> (Nq, m)
+        return coef[:, 0][None, :] + x @ coef[:, 1:].T
+
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    xn = disc.node_coords()
+    plan.set_source(torch.from_numpy(np.ascontiguousarray(src(xn.T).T)).cuda())
+    out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    torch.cuda.synchronize()
+    ref_R, ref_T = [], []
+    for e in range(disc.mesh.n_elem):
+        x, lam, us, vb = disc.elem_inputs(e, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
+        R, T = disc.element_residual(e, x[None], lam[None], us, vb, src)
+        ref_R.append(R[0]), ref_T.append(T[0])
+    err_R = rloc_err(disc, inp, out["R_loc"].cpu().numpy(), np.stack(ref_R))
+    err_T = rel_err_per_elem(out["R_tr"].cpu().numpy(), np.stack(ref_T))
+    err_A = rel_err_per_elem(out["A"].cpu().numpy(), colmajor([b["A"] for b in blocks]))
+    print(name, "source: R_loc", err_R, "R_tr", err_T, "A", err_A, flush=True)
+    assert err_R <= TOL and err_T <= TOL and err_A <= TOL

@@ -48,3 +48,34 @@ def test_meshes_conforming_and_counts():
     t = M.tri_square(8, 0.1, 1)
     tm, nt = M.trace_map(t, 2, "hdg")
     assert nt == 208 * 3 and t.boundary.sum() == 32
+
+
+def test_couette_source_is_the_divergence_of_the_fluxes():
+    """The printed source of the Couette example equals div(F(v) + G(v, grad v)) of the printed
+    exact solution under the oracle's flux functions (4th-order central differences of the
+    flux divergence, gradients of v by differences as well): a check of the formula reading
+    and of the flux conventions (stress, heat flux with kappa = mu gamma c_v / Pr)."""
+    from oracle import physics as ph
+    from workloads.fields import Couette
+    c = Couette()
+    gam = c.gamma
+
+    def v_at(X):
+        pr, _ = c.prim_and_grad(X)
+        return ph.v_of_prim(pr[0], pr[1:3].T, pr[3], gam)
+
+    def d4(f, X, k, h):
+        e = np.zeros((2, 1))
+        e[k] = h
+        return (8 * (f(X + e) - f(X - e)) - (f(X + 2 * e) - f(X - 2 * e))) / (12 * h)
+
+    def flux(X):
+        v = v_at(X)
+        q = np.stack([d4(v_at, X, k, 1e-3) for k in range(2)], axis=-1)
+        return ph.flux_F(v, gam) + ph.flux_G(v, q, gam, c.mu, c.Pr)
+
+    ys = np.array([0.05, 0.3, 0.5, 0.8, 0.97])
+    X = np.stack([np.full_like(ys, 0.4), ys])
+    div = sum(d4(lambda Y: flux(Y)[:, :, k], X, k, 2e-3) for k in range(2)).T
+    s = c.source(X)
+    assert np.max(np.abs(div - s)) <= 1e-5 * np.max(np.abs(s))

@@ -15,6 +15,8 @@ Fields:
 * ``TaylorGreen`` -- the Taylor-Green initial condition of the paper's TGV
   example (constant density, pressure from the incompressible solution).
 * ``Uniform`` -- a constant state (free-stream tests).
+* ``Couette`` -- the steady compressible Couette flow with a source term of the
+  paper's Navier-Stokes convergence example (exact solution and source).
 * ``SmoothNoise`` wraps a field and perturbs it with seeded periodic
   sinusoids (relative for rho and p, scaled by a reference speed for V).
 * ``node_noise`` draws the per-node i.i.d. perturbation.
@@ -52,6 +54,42 @@ class Uniform(Field):
 
     def prim(self, x):
         return self.vals[:, None] * np.ones_like(x[0])[None, :]
+
+
+class Couette(Field):
+    """Steady compressible Couette flow on (0, L)^2 (the Navier-Stokes convergence example of
+    Section 5): V_x = V0 y' log(1 + y'), V_y = 0, p = P0,
+    T = T0 (a + y' (b - a)) + V0^2 Pr / (2 c_v gamma) y' (1 - y'), rho = p / ((gamma - 1) c_v T),
+    y' = y / L, T0 = V0^2 / ((gamma - 1) gamma M0^2 c_v).  Units: R = 1 (c_v = 1 / (gamma - 1)),
+    rho0 = V0 = L = 1, so P0 = 1 / (gamma M0^2) and mu = 1 / Re0.  ``source`` is the right-hand side
+    s of the conservation law that this field satisfies exactly (same section)."""
+
+    def __init__(self, gamma=1.4, Pr=0.71, M0=0.15, a=0.8, b=0.85, Re0=0.1):
+        self.dim = 2
+        self.gamma, self.Pr, self.M0, self.a, self.b = gamma, Pr, M0, a, b
+        self.cv = 1.0 / (gamma - 1.0)
+        self.V0, self.L = 1.0, 1.0
+        self.P0 = 1.0 / (gamma * M0 ** 2)
+        self.mu = 1.0 / Re0
+        self.T0 = self.V0 ** 2 / ((gamma - 1.0) * gamma * M0 ** 2 * self.cv)
+
+    def prim(self, x):
+        y = x[1] / self.L
+        g, cv = self.gamma, self.cv
+        T = self.T0 * (self.a + y * (self.b - self.a)) + self.V0 ** 2 * self.Pr / (2 * cv * g) * y * (1 - y)
+        p = self.P0 * np.ones_like(y)
+        rho = p / ((g - 1.0) * cv * T)
+        return np.stack([rho, self.V0 * y * np.log(1 + y), 0 * y, p])
+
+    def source(self, x):
+        """(4, N) right-hand side of the conservation law (mass, x and y momentum, energy)."""
+        y = np.asarray(x[1]) / self.L
+        lg = np.log(1 + y)
+        mu, V0, L = self.mu, self.V0, self.L
+        sx = -mu * V0 / L ** 2 * (2 + y) / (1 + y) ** 2
+        se = -mu * V0 ** 2 / L ** 2 * (lg ** 2 + y * lg / (1 + y) + (y * (3 + 2 * y) * lg - 2 * y - 1) / (1 + y) ** 2)
+        z = 0 * y
+        return np.stack([z, sx, z, se])
 
 
 class ShuVortex(Field):
