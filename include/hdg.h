@@ -89,7 +89,7 @@ typedef struct {
   int n_trace;             /* number of global trace nodes */
 } hdg_mesh;
 
-enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2, HDG_FLAG_ELIMINATE_Q = 4 };
+enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2, HDG_FLAG_ELIMINATE_Q = 4, HDG_FLAG_GHAT_INTERIOR = 8 };
 
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */
@@ -108,7 +108,11 @@ typedef struct {
                               condense the full block). Needs N_p + nf N_fp + 1 <= 112
                               and the elimination's LDS sets within 160 KB (hexahedra up
                               to p = 2, tetrahedra up to p = 3); otherwise plan creation
-                              returns HDG_EUNSUPPORTED, and HDG_EINVAL for Euler. */
+                              returns HDG_EUNSUPPORTED, and HDG_EINVAL for Euler. 
+                              HDG_FLAG_GHAT_INTERIOR (Navier-Stokes): viscous numerical
+                              flux G(v_h, q_h).n with the element's v_h (the first of the
+                              two viscous fluxes of Section 3.3) instead of G(vhat_h, q_h).n
+                              (the one of the paper's examples, the default). */
 } hdg_opts;
 
 typedef struct {

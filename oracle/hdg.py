@@ -55,6 +55,9 @@ class Phys:
     Pr: float = 0.72
     alpha: float = 0.0
     viscous: bool = False
+    # viscous numerical flux: G(v_hat, q) . n (the one used in the paper's examples) or, with
+    # ghat_interior, G(v, q) . n with the element's v (the first of the two choices of Section 3.3)
+    ghat_interior: bool = False
 
 
 class Discretization:
@@ -157,7 +160,7 @@ class Discretization:
             tf = ph.fhat(vhf, vf, nrm, gam)
             if ph_.viscous:
                 qf = np.einsum("qa,pcja->pqcj", F["phi"], qN)
-                tf = tf + ph.ghat(vhf, qf, nrm, gam, ph_.mu, ph_.Pr)
+                tf = tf + ph.ghat(vf if ph_.ghat_interior else vhf, qf, nrm, gam, ph_.mu, ph_.Pr)
                 Rq = Rq - np.einsum("q,pqc,qj,qa->pcja", F["W"], vhf, nrm, F["phi"])
             Rv = Rv + np.einsum("q,pqc,qa->pca", F["W"], tf, F["phi"])
             if self.face_bc[e, f] == 1:

@@ -19,6 +19,7 @@ PHASES = ["points", "contract", "lu", "solve", "schur", "backsolve", "matvec", "
 FLAG_SPLIT_DENSE = 1
 FLAG_NARROW_BLOCK = 2
 FLAG_ELIMINATE_Q = 4
+FLAG_GHAT_INTERIOR = 8
 
 
 class hdg_phys(ctypes.Structure):

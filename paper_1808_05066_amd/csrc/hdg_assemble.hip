@@ -183,13 +183,24 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
   for (int j = 0; j < D; ++j) vn += sh.V[j] * n[j];
   const double lam = dabs(vn) + sqrt(gam * sh.p / sh.rho);
   // trace-state directions: d(f_hat + g_hat)/d v_hat and the flux value
+  // (with ghat_v the viscous numerical flux does not depend on v_hat: it is added below)
+  const bool gh_trace = VISC && !P.ghat_v;
   for (int t = 0; t < M; ++t) {
     Dual vd[M], o[M];
     for (int c = 0; c < M; ++c) vd[c] = Dual{vh[c], c == t ? 1.0 : 0.0};
-    trace_flux<D, Dual, double>(vd, vv, Fnv, qq, n, gam, P.mu, P.Pr, VISC, o);
+    trace_flux<D, Dual, double>(vd, vv, Fnv, qq, n, gam, P.mu, P.Pr, gh_trace, o);
     for (int c = 0; c < M; ++c) out[L.fFh + c * M + t] = W * o[c].d;
     if (t == 0)
       for (int c = 0; c < M; ++c) out[L.fFf + c] = W * o[c].v;
+  }
+  if (VISC && P.ghat_v) {
+    double G[M * D];
+    flux_G<D, double, double>(sv, qq, gam, P.mu, P.Pr, G);
+    for (int c = 0; c < M; ++c) {
+      double a = 0.0;
+      for (int j = 0; j < D; ++j) a += G[c * D + j] * n[j];
+      out[L.fFf + c] += W * a;
+    }
   }
   // element-state directions: d f_hat / d v = 1/2 (A_n(v) + sigma)
   for (int t = 0; t < M; ++t) {
@@ -203,13 +214,23 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
       for (int j = 0; j < D; ++j) an += F[c * D + j].d * n[j];
       out[L.fFv + c * M + t] = W * 0.5 * (an + lam * A0h[c * M + t]);
     }
+    if (VISC && P.ghat_v) {
+      // d g_hat / d v with g_hat = G(v, q).n
+      Dual G[M * D];
+      flux_G<D, Dual, double>(s, qq, gam, P.mu, P.Pr, G);
+      for (int c = 0; c < M; ++c) {
+        double gn = 0.0;
+        for (int j = 0; j < D; ++j) gn += G[c * D + j].d * n[j];
+        out[L.fFv + c * M + t] += W * gn;
+      }
+    }
   }
   if (VISC) {
     // d g_hat / d q: g_hat is linear in q
     for (int si = 0; si < M * D; ++si) {
       double es[M * D], G[M * D];
       for (int i = 0; i < M * D; ++i) es[i] = (i == si) ? 1.0 : 0.0;
-      flux_G<D, double, double>(sh, es, gam, P.mu, P.Pr, G);
+      flux_G<D, double, double>(P.ghat_v ? sv : sh, es, gam, P.mu, P.Pr, G);
       for (int c = 0; c < M; ++c) {
         double a = 0.0;
         for (int j = 0; j < D; ++j) a += G[c * D + j] * n[j];

@@ -24,6 +24,7 @@ struct DevPlan {
   int contract_threads;    // workgroup size of the block contraction (256, 512, 1024)
   int zero_xcd;            // 1: the contraction clears X, C and D first (0: they hold the zeros already)
   int a_qmin;              // 1: of the q rows of A only M and G_j of the first component are formed
+  int ghat_v;              // 1: viscous numerical flux G(v, q).n with the element's v (else G(v_hat, q).n)
   int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
   double gamma, mu, Pr, alpha;
   const double *src;       // [m][E*Np] nodal source of the conservation law (device, caller-owned) or null

@@ -14,7 +14,7 @@ import pytest
 from oracle import hdg as ohdg
 from oracle import state as ostate
 
-from cases import (SMALL_CASES, colmajor, gpu_plan, oracle_case, rel_err_per_elem, rloc_err, to_dev,
+from cases import (SMALL_CASES, colmajor, gpu_plan, oracle_case, oracle_disc, rel_err_per_elem, rloc_err, to_dev,
                    z_backward_err)
 
 pytestmark = pytest.mark.gpu
@@ -237,3 +237,33 @@ def test_source_term_matches_oracle(torch, name):
     err_A = rel_err_per_elem(out["A"].cpu().numpy(), colmajor([b["A"] for b in blocks]))
     print(name, "source: R_loc", err_R, "R_tr", err_T, "A", err_A, flush=True)
     assert err_R <= TOL and err_T <= TOL and err_A <= TOL
+
+
+@pytest.mark.parametrize("name", ["ns2d_tri_p2", "ns3d_hex_p1"])
+def test_interior_viscous_flux_matches_oracle(torch, name):
+    """HDG_FLAG_GHAT_INTERIOR: viscous numerical flux G(v_h, q_h).n (the first of the two choices
+    of Section 3.3).  All blocks, the residuals and the condensed outputs against the oracle with
+    the same choice; the blocks must differ from the default flux's."""
+    wl = SMALL_CASES[name]()
+    disc = oracle_disc(wl, ghat_interior=True)
+    inp = ostate.oracle_inputs(wl, disc)
+    blocks = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"],
+                                    keep_blocks=True)
+    plan = gpu_plan(wl, ghat_interior=True)
+    d = to_dev(inp)
+    out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    cond = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], residuals=True)
+    torch.cuda.synchronize()
+    errs = {
+        "R_loc": rloc_err(disc, inp, out["R_loc"].cpu().numpy(), np.stack([b["R_loc"] for b in blocks])),
+        "R_tr": rel_err_per_elem(out["R_tr"].cpu().numpy(), np.stack([b["R_tr"] for b in blocks])),
+        "S": rel_err_per_elem(cond["S"].cpu().numpy(), colmajor([b["S"] for b in blocks])),
+        "Y": rel_err_per_elem(cond["Y"].cpu().numpy(), colmajor([b["Y"] for b in blocks])),
+    }
+    for key in ("A", "B", "C", "D"):
+        errs[key] = rel_err_per_elem(out[key].cpu().numpy(), colmajor([b[key] for b in blocks]))
+    print(name, errs, flush=True)
+    for key, err in errs.items():
+        assert err <= TOL, (key, err)
+    _, _, _, base = _case(name)
+    assert rel_err_per_elem(np.stack([b["C"] for b in blocks]), np.stack([b["C"] for b in base])) > 1e-6
