@@ -89,7 +89,8 @@ typedef struct {
   int n_trace;             /* number of global trace nodes */
 } hdg_mesh;
 
-enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2, HDG_FLAG_ELIMINATE_Q = 4, HDG_FLAG_GHAT_INTERIOR = 8 };
+enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2, HDG_FLAG_ELIMINATE_Q = 4, HDG_FLAG_GHAT_INTERIOR = 8,
+       HDG_FLAG_SIGMA_S = 16 };
 
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */
@@ -112,7 +113,11 @@ typedef struct {
                               HDG_FLAG_GHAT_INTERIOR (Navier-Stokes): viscous numerical
                               flux G(v_h, q_h).n with the element's v_h (the first of the
                               two viscous fluxes of Section 3.3) instead of G(vhat_h, q_h).n
-                              (the one of the paper's examples, the default). */
+                              (the one of the paper's examples, the default).
+                              HDG_FLAG_SIGMA_S: stabilization matrix sigma_S =
+                              |A_n(vhat)| A0(vhat) (the symmetric variable matrix of
+                              Section 4, v* = vhat) instead of sigma_SLF =
+                              lambda_max(vhat) A0(vhat) (the paper's examples). */
 } hdg_opts;
 
 typedef struct {

@@ -58,6 +58,9 @@ class Phys:
     # viscous numerical flux: G(v_hat, q) . n (the one used in the paper's examples) or, with
     # ghat_interior, G(v, q) . n with the element's v (the first of the two choices of Section 3.3)
     ghat_interior: bool = False
+    # stabilization matrix: "slf" (symmetric Lax-Friedrichs, the paper's examples) or "s"
+    # (symmetric variable |A_n| A0), both at v* = v_hat
+    sigma: str = "slf"
 
 
 class Discretization:
@@ -157,7 +160,7 @@ class Discretization:
             vf = np.einsum("qa,pca->pqc", F["phi"], vN)
             vhf = np.einsum("qb,pcb->pqc", F["psi"], LN[:, f])
             nrm = F["n"]
-            tf = ph.fhat(vhf, vf, nrm, gam)
+            tf = ph.fhat(vhf, vf, nrm, gam, ph_.sigma)
             if ph_.viscous:
                 qf = np.einsum("qa,pcja->pqcj", F["phi"], qN)
                 tf = tf + ph.ghat(vf if ph_.ghat_interior else vhf, qf, nrm, gam, ph_.mu, ph_.Pr)

@@ -175,9 +175,50 @@ def sigma_slf(vh, n, gamma):
     return lam_max(vh, n, gamma)[..., None, None] * A0(vh, gamma)
 
 
-def fhat(vh, v, n, gamma):
-    """Inviscid trace flux with sigma_SLF evaluated at v* = v_hat."""
+def abs_An_apply(v, n, gamma, du):
+    """|A_n(v)| du for perturbations du (..., m) of the conservation variables, from the
+    eigen-decomposition of the Euler flux Jacobian along the unit normal n: acoustic waves
+    u_n -/+ c with strengths (dp -/+ rho c du_n) / (2 c^2) on (1, V -/+ c n, H -/+ c u_n), the
+    entropy wave (speed u_n) with strength drho - dp / c^2 on (1, V, |V|^2 / 2) and the shear
+    waves (speed u_n) rho (0, dV_t, V . dV_t), dV_t = dV - du_n n; dprim linearized from du."""
+    rho, V, p = prim_of_v(v, gamma)
+    m = du.shape[-1]
+    d = m - 2
+    drho = du[..., 0]
+    dV = (du[..., 1:m - 1] - V * drho[..., None]) / rho[..., None]
+    dp = (gamma - 1.0) * (du[..., m - 1] - 0.5 * (V * V).sum(-1) * drho - rho * (V * dV).sum(-1))
+    c = np.sqrt(gamma * p / rho)
+    un = (V * n).sum(-1)
+    H = c * c / (gamma - 1.0) + 0.5 * (V * V).sum(-1)
+    dun = (dV * n).sum(-1)
+    dVt = dV - dun[..., None] * n
+    a1 = (dp - rho * c * dun) / (2 * c * c)
+    a4 = (dp + rho * c * dun) / (2 * c * c)
+    a2 = drho - dp / (c * c)
+
+    def vec(s0, sV, sE):
+        return np.concatenate([s0[..., None], sV, sE[..., None]], axis=-1)
+
+    one = np.ones_like(rho)
+    r1 = vec(one, V - c[..., None] * n, H - c * un)
+    r4 = vec(one, V + c[..., None] * n, H + c * un)
+    r2 = vec(one, V, 0.5 * (V * V).sum(-1))
+    sh = vec(0 * rho, rho[..., None] * dVt, rho * (V * dVt).sum(-1))
+    return (abs_cs(un - c)[..., None] * a1[..., None] * r1
+            + abs_cs(un)[..., None] * (a2[..., None] * r2 + sh)
+            + abs_cs(un + c)[..., None] * a4[..., None] * r4)
+
+
+def sigma_s_apply(vh, n, gamma, dv):
+    """Symmetric variable stabilization |A_n(v_hat)| A0(v_hat) applied to dv (v* = v_hat)."""
+    return abs_An_apply(vh, n, gamma, np.einsum("...ab,...b->...a", A0(vh, gamma), dv))
+
+
+def fhat(vh, v, n, gamma, sigma="slf"):
+    """Inviscid trace flux with sigma_SLF (default) or sigma_S evaluated at v* = v_hat."""
     Fn = np.einsum("...cj,...j->...c", flux_F(vh, gamma) + flux_F(v, gamma), n)
+    if sigma == "s":
+        return 0.5 * Fn + 0.5 * sigma_s_apply(vh, n, gamma, v - vh)
     sig = sigma_slf(vh, n, gamma)
     return 0.5 * Fn + 0.5 * np.einsum("...ab,...b->...a", sig, v - vh)
 

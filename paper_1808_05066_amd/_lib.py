@@ -20,6 +20,7 @@ FLAG_SPLIT_DENSE = 1
 FLAG_NARROW_BLOCK = 2
 FLAG_ELIMINATE_Q = 4
 FLAG_GHAT_INTERIOR = 8
+FLAG_SIGMA_S = 16
 
 
 class hdg_phys(ctypes.Structure):

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
   for (int t = 0; t < M; ++t) {
     Dual vd[M], o[M];
     for (int c = 0; c < M; ++c) vd[c] = Dual{vh[c], c == t ? 1.0 : 0.0};
-    trace_flux<D, Dual, double>(vd, vv, Fnv, qq, n, gam, P.mu, P.Pr, gh_trace, o);
+    trace_flux<D, Dual, double>(vd, vv, Fnv, qq, n, gam, P.mu, P.Pr, gh_trace, o, P.sigma_s != 0);
     for (int c = 0; c < M; ++c) out[L.fFh + c * M + t] = W * o[c].d;
     if (t == 0)
       for (int c = 0; c < M; ++c) out[L.fFf + c] = W * o[c].v;
@@ -203,6 +203,17 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
     }
   }
   // element-state directions: d f_hat / d v = 1/2 (A_n(v) + sigma)
+  double sig[M * M];   // sigma(v_hat), column t = sigma e_t
+  if (P.sigma_s) {
+    for (int t = 0; t < M; ++t) {
+      double et[M], col[M];
+      for (int c = 0; c < M; ++c) et[c] = c == t ? 1.0 : 0.0;
+      sigma_s_apply<D, double, double>(sh, A0h, n, gam, et, col);
+      for (int c = 0; c < M; ++c) sig[c * M + t] = col[c];
+    }
+  } else {
+    for (int i = 0; i < M * M; ++i) sig[i] = lam * A0h[i];
+  }
   for (int t = 0; t < M; ++t) {
     Dual vd[M];
     for (int c = 0; c < M; ++c) vd[c] = Dual{vv[c], c == t ? 1.0 : 0.0};
@@ -212,7 +223,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
     for (int c = 0; c < M; ++c) {
       double an = 0.0;
       for (int j = 0; j < D; ++j) an += F[c * D + j].d * n[j];
-      out[L.fFv + c * M + t] = W * 0.5 * (an + lam * A0h[c * M + t]);
+      out[L.fFv + c * M + t] = W * 0.5 * (an + sig[c * M + t]);
     }
     if (VISC && P.ghat_v) {
       // d g_hat / d v with g_hat = G(v, q).n

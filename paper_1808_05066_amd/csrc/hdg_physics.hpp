@@ -170,13 +170,53 @@ __device__ inline void A0_of_prim(const Prim<D, T> &s, double gam, T *A) {
   A[(M - 1) * M + M - 1] = (s.rho * Ht * Ht - c2 * s.p * g1) * g1;
 }
 
-// Trace flux f_hat + g_hat at one face point.  vh: trace state (type T),
+// Symmetric variable stabilization sigma_S dv = |A_n(v*)| A0(v*) dv (Section 4): du = A0 dv, its
+// primitive perturbation (linearized), then the wave decomposition of the Euler flux Jacobian
+// along the unit normal n -- acoustic speeds u_n -/+ c with strengths (dp -/+ rho c du_n)/(2c^2)
+// on (1, V -/+ c n, H -/+ c u_n), entropy (speed u_n, strength drho - dp/c^2) on (1, V, |V|^2/2)
+// and shear (speed u_n) rho (0, dV_t, V . dV_t) -- each scaled by |speed|.
+template <int D, typename T, typename U>
+__device__ inline void sigma_s_apply(const Prim<D, T> &s, const T *A0, const double *n, double gam, const U *dv,
+                                     T *out) {
+  const int M = D + 2;
+  T du[M];
+  for (int c = 0; c < M; ++c) {
+    T a = cst<T>(0.0);
+    for (int e = 0; e < M; ++e) a = a + A0[c * M + e] * dv[e];
+    du[c] = a;
+  }
+  T kin = cst<T>(0.0);
+  for (int i = 0; i < D; ++i) kin = kin + s.V[i] * s.V[i];
+  T dV[D], vdV = cst<T>(0.0), un = cst<T>(0.0), dun = cst<T>(0.0);
+  for (int i = 0; i < D; ++i) {
+    dV[i] = (du[1 + i] - s.V[i] * du[0]) / s.rho;
+    vdV = vdV + s.V[i] * dV[i];
+    un = un + s.V[i] * n[i];
+    dun = dun + dV[i] * n[i];
+  }
+  const T dp = (gam - 1.0) * (du[M - 1] - 0.5 * kin * du[0] - s.rho * vdV);
+  const T c2 = gam * s.p / s.rho, c = dsqrt(c2);
+  const T H = c2 / (gam - 1.0) + 0.5 * kin;
+  const T a1 = (dp - s.rho * c * dun) / (2.0 * c2), a4 = (dp + s.rho * c * dun) / (2.0 * c2);
+  const T a2 = du[0] - dp / c2;
+  const T l1 = dabs(un - c), l2 = dabs(un), l4 = dabs(un + c);
+  T vdVt = cst<T>(0.0);
+  for (int i = 0; i < D; ++i) vdVt = vdVt + s.V[i] * (dV[i] - dun * n[i]);
+  out[0] = l1 * a1 + l2 * a2 + l4 * a4;
+  for (int i = 0; i < D; ++i)
+    out[1 + i] = l1 * a1 * (s.V[i] - c * n[i]) + l2 * (a2 * s.V[i] + s.rho * (dV[i] - dun * n[i])) +
+                 l4 * a4 * (s.V[i] + c * n[i]);
+  out[M - 1] = l1 * a1 * (H - c * un) + l2 * (a2 * 0.5 * kin + s.rho * vdVt) + l4 * a4 * (H + c * un);
+}
+
+// Trace flux f_hat + g_hat at one face point (stabilization sigma_SLF = lambda_max A0, or
+// sigma_S with sym_s, both at v* = v_hat).  vh: trace state (type T),
 // F_n(v) of the element state precomputed (double), dv = v - v_hat evaluated
 // inside, q (type Q) the element gradient unknowns (ignored if !visc).
 template <int D, typename T, typename Q>
 __device__ inline void trace_flux(const T *vh, const double *v, const double *Fnv, const Q *q,
                                   const double *n, double gam, double mu, double Pr, bool visc,
-                                  T *out) {
+                                  T *out, bool sym_s = false) {
   const int M = D + 2;
   Prim<D, T> s = prim_of_v<D, T>(vh, gam);
   T F[M * D];
@@ -186,14 +226,20 @@ __device__ inline void trace_flux(const T *vh, const double *v, const double *Fn
   T vn = cst<T>(0.0);
   for (int j = 0; j < D; ++j) vn = vn + s.V[j] * n[j];
   T lam = dabs(vn) + dsqrt(gam * s.p / s.rho);
-  T dv[M];
+  T dv[M], ss[M];
   for (int c = 0; c < M; ++c) dv[c] = v[c] - vh[c];
+  if (sym_s) sigma_s_apply<D, T, T>(s, A, n, gam, dv, ss);
   for (int c = 0; c < M; ++c) {
     T fn = cst<T>(0.0);
     for (int j = 0; j < D; ++j) fn = fn + F[c * D + j] * n[j];
     T sd = cst<T>(0.0);
-    for (int e = 0; e < M; ++e) sd = sd + A[c * M + e] * dv[e];
-    out[c] = 0.5 * (fn + Fnv[c]) + 0.5 * lam * sd;
+    if (sym_s) {
+      sd = ss[c];
+    } else {
+      for (int e = 0; e < M; ++e) sd = sd + A[c * M + e] * dv[e];
+      sd = lam * sd;
+    }
+    out[c] = 0.5 * (fn + Fnv[c]) + 0.5 * sd;
   }
   if (visc) {
     T G[M * D];

@@ -6,9 +6,9 @@ from oracle import state as ostate
 from workloads import configs as C
 
 
-def oracle_disc(wl, nquad=None, ghat_interior=False):
+def oracle_disc(wl, nquad=None, ghat_interior=False, sigma="slf"):
     return ohdg.Discretization(wl.mesh, wl.p, ohdg.Phys(wl.gamma, wl.mu, wl.Pr, wl.alpha, wl.viscous,
-                                                        ghat_interior),
+                                                        ghat_interior, sigma),
                                wl.tmap, wl.n_trace, wl.face_bc, nquad)
 
 
@@ -17,12 +17,13 @@ def oracle_case(wl):
     return disc, ostate.oracle_inputs(wl, disc)
 
 
-def gpu_plan(wl, chunk_elems=0, split_dense=False, narrow_block=False, eliminate_q=False, ghat_interior=False):
+def gpu_plan(wl, chunk_elems=0, split_dense=False, narrow_block=False, eliminate_q=False, ghat_interior=False,
+             sigma="slf"):
     from paper_1808_05066_amd.hdg import Plan
     return Plan(wl.mesh.etype, wl.p, wl.mesh.elem_xyz, wl.tmap, wl.n_trace, wl.face_bc, viscous=wl.viscous,
                 gamma=wl.gamma, mu=wl.mu, Pr=wl.Pr, alpha=wl.alpha, chunk_elems=chunk_elems,
                 split_dense=split_dense, narrow_block=narrow_block, eliminate_q=eliminate_q,
-                ghat_interior=ghat_interior)
+                ghat_interior=ghat_interior, sigma=sigma)
 
 
 def smooth_periodic_case(dt, n=2, p=2, mu=0.02, Pr=0.72, gamma=1.4):

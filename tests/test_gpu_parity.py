@@ -267,3 +267,43 @@ def test_interior_viscous_flux_matches_oracle(torch, name):
         assert err <= TOL, (key, err)
     _, _, _, base = _case(name)
     assert rel_err_per_elem(np.stack([b["C"] for b in blocks]), np.stack([b["C"] for b in base])) > 1e-6
+
+
+@pytest.mark.parametrize("name", ["euler2d_tri_p2", "ns3d_hex_p1", "euler3d_hex_p2"])
+def test_symmetric_variable_stabilization_matches_oracle(torch, name):
+    """HDG_FLAG_SIGMA_S: stabilization sigma_S = |A_n(v_hat)| A0(v_hat) (the symmetric variable
+    matrix of Section 4).  Blocks, residuals and condensed outputs against the oracle with the
+    same matrix; the blocks must differ from the sigma_SLF ones."""
+    wl = SMALL_CASES[name]()
+    disc = oracle_disc(wl, sigma="s")
+    inp = ostate.oracle_inputs(wl, disc)
+    blocks = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"],
+                                    keep_blocks=True)
+    plan = gpu_plan(wl, sigma="s")
+    d = to_dev(inp)
+    out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    cond = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], residuals=True)
+    torch.cuda.synchronize()
+    errs = {
+        "R_loc": rloc_err(disc, inp, out["R_loc"].cpu().numpy(), np.stack([b["R_loc"] for b in blocks])),
+        "R_tr": rel_err_per_elem(out["R_tr"].cpu().numpy(), np.stack([b["R_tr"] for b in blocks])),
+    }
+    for key in ("A", "B", "C", "D"):
+        errs[key] = rel_err_per_elem(out[key].cpu().numpy(), colmajor([b[key] for b in blocks]))
+    print(name, errs, flush=True)
+    for key, err in errs.items():
+        assert err <= TOL, (key, err)
+    # S and Y come from solves with the local block, whose condition number sigma_S can raise
+    # (its entropy and shear parts vanish where u.n does): per element, forward error within
+    # 1e-12 or within 64 eps cond(A) (a backward-stable solve's bound), whichever is larger
+    Sg, Yg = cond["S"].cpu().numpy(), cond["Y"].cpu().numpy()
+    worst = 0.0
+    for e, b in enumerate(blocks):
+        bound = max(TOL, 64 * np.finfo(float).eps * np.linalg.cond(b["A"]))
+        for got, ref in ((Sg[e].T, b["S"]), (Yg[e].T, b["Y"])):
+            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+            worst = max(worst, err / bound)
+            assert err <= bound, (e, err, bound)
+    print(name, "S, Y: worst error / bound", worst, flush=True)
+    _, _, _, base = _case(name)
+    assert rel_err_per_elem(np.stack([b["A"] for b in blocks]), np.stack([b["A"] for b in base])) > 1e-6

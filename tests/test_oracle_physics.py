@@ -143,3 +143,30 @@ def test_complex_step_matches_finite_differences():
         e[i] = h
         Jf[:, :, i] = (f(vh + e) - f(vh - e)) / (2 * h)
     assert np.abs(Jc - Jf).max() <= 1e-6 * np.abs(Jc).max()
+
+
+def test_abs_An_matches_the_eigen_decomposition():
+    """|A_n| du from the closed-form wave decomposition against V |Lambda| V^-1 du, A_n = dF_n/du
+    by complex step and V, Lambda from a general eigen-solver, at random states (2D and 3D);
+    sigma_S = |A_n| A0 is symmetric positive semi-definite."""
+    rng = np.random.default_rng(3)
+    for d in (2, 3):
+        m = d + 2
+        for _ in range(4):
+            v = P.v_of_prim(np.array(1 + 0.3 * rng.random()), 0.6 * rng.standard_normal(d),
+                             np.array(1 + 0.5 * rng.random()), GAM)
+            n = rng.standard_normal(d)
+            n /= np.linalg.norm(n)
+            u = P.u_of_v(v, GAM)
+            J = np.zeros((m, m))
+            for k in range(m):
+                uc = u.astype(complex)
+                uc[k] += 1e-30j
+                J[:, k] = np.imag(np.einsum("cj,j->c", P.flux_F(P.v_of_u(uc, GAM), GAM), n)) / 1e-30
+            w, R = np.linalg.eig(J)
+            absA = np.real(R @ np.diag(np.abs(w)) @ np.linalg.inv(R))
+            du = rng.standard_normal(m)
+            assert np.max(np.abs(absA @ du - P.abs_An_apply(v, n, GAM, du))) <= 1e-12 * np.max(np.abs(absA @ du))
+            S = np.stack([P.sigma_s_apply(v, n, GAM, e) for e in np.eye(m)], axis=1)
+            assert np.max(np.abs(S - S.T)) <= 1e-12 * np.max(np.abs(S))
+            assert np.min(np.linalg.eigvalsh(0.5 * (S + S.T))) >= -1e-12 * np.max(np.abs(S))
