@@ -90,7 +90,7 @@ typedef struct {
 } hdg_mesh;
 
 enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2, HDG_FLAG_ELIMINATE_Q = 4, HDG_FLAG_GHAT_INTERIOR = 8,
-       HDG_FLAG_SIGMA_S = 16 };
+       HDG_FLAG_SIGMA_S = 16, HDG_FLAG_SIGMA_MV = 32 };
 
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */
@@ -117,7 +117,12 @@ typedef struct {
                               HDG_FLAG_SIGMA_S: stabilization matrix sigma_S =
                               |A_n(vhat)| A0(vhat) (the symmetric variable matrix of
                               Section 4, v* = vhat) instead of sigma_SLF =
-                              lambda_max(vhat) A0(vhat) (the paper's examples). */
+                              lambda_max(vhat) A0(vhat) (the paper's examples).
+                              HDG_FLAG_SIGMA_MV: the mean-value stabilization matrix of
+                              Section 4 on the straight path between vhat and v in
+                              entropy variables (its two integrals combined into one
+                              integral of sigma_S over the path, 4-point Gauss-Legendre);
+                              takes precedence over HDG_FLAG_SIGMA_S. */
 } hdg_opts;
 
 typedef struct {

@@ -58,8 +58,8 @@ class Phys:
     # viscous numerical flux: G(v_hat, q) . n (the one used in the paper's examples) or, with
     # ghat_interior, G(v, q) . n with the element's v (the first of the two choices of Section 3.3)
     ghat_interior: bool = False
-    # stabilization matrix: "slf" (symmetric Lax-Friedrichs, the paper's examples) or "s"
-    # (symmetric variable |A_n| A0), both at v* = v_hat
+    # stabilization matrix: "slf" (symmetric Lax-Friedrichs, the paper's examples), "s"
+    # (symmetric variable |A_n| A0), both at v* = v_hat, or "mv" (mean value between v_hat and v)
     sigma: str = "slf"
 
 

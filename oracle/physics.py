@@ -214,11 +214,28 @@ def sigma_s_apply(vh, n, gamma, dv):
     return abs_An_apply(vh, n, gamma, np.einsum("...ab,...b->...a", A0(vh, gamma), dv))
 
 
+# Gauss-Legendre points and weights on [0, 1] for the mean-value stabilization's theta integral
+MV_THETA = 0.5 * (1.0 + np.polynomial.legendre.leggauss(4)[0])
+MV_WEIGHT = 0.5 * np.polynomial.legendre.leggauss(4)[1]
+
+
+def sigma_mv_apply(vh, v, n, gamma, dv):
+    """Mean-value stabilization (Section 4) on the straight path in entropy variables,
+    sigma_MV(v_hat, v) = int_0^1 |A_n| A0 (v_hat + theta (v - v_hat)) dtheta (the two (1 - theta)
+    weighted integrals of the definition add up to this), applied to dv, by 4-point Gauss-Legendre."""
+    out = 0.0
+    for th, w in zip(MV_THETA, MV_WEIGHT):
+        out = out + w * sigma_s_apply(vh + th * (v - vh), n, gamma, dv)
+    return out
+
+
 def fhat(vh, v, n, gamma, sigma="slf"):
-    """Inviscid trace flux with sigma_SLF (default) or sigma_S evaluated at v* = v_hat."""
+    """Inviscid trace flux with sigma_SLF (default), sigma_S (v* = v_hat) or sigma_MV."""
     Fn = np.einsum("...cj,...j->...c", flux_F(vh, gamma) + flux_F(v, gamma), n)
     if sigma == "s":
         return 0.5 * Fn + 0.5 * sigma_s_apply(vh, n, gamma, v - vh)
+    if sigma == "mv":
+        return 0.5 * Fn + 0.5 * sigma_mv_apply(vh, v, n, gamma, v - vh)
     sig = sigma_slf(vh, n, gamma)
     return 0.5 * Fn + 0.5 * np.einsum("...ab,...b->...a", sig, v - vh)
 

@@ -21,6 +21,7 @@ FLAG_NARROW_BLOCK = 2
 FLAG_ELIMINATE_Q = 4
 FLAG_GHAT_INTERIOR = 8
 FLAG_SIGMA_S = 16
+FLAG_SIGMA_MV = 32
 
 
 class hdg_phys(ctypes.Structure):

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
   for (int t = 0; t < M; ++t) {
     Dual vd[M], o[M];
     for (int c = 0; c < M; ++c) vd[c] = Dual{vh[c], c == t ? 1.0 : 0.0};
-    trace_flux<D, Dual, double>(vd, vv, Fnv, qq, n, gam, P.mu, P.Pr, gh_trace, o, P.sigma_s != 0);
+    trace_flux<D, Dual, double>(vd, vv, Fnv, qq, n, gam, P.mu, P.Pr, gh_trace, o, P.sigma_s == 1);
     for (int c = 0; c < M; ++c) out[L.fFh + c * M + t] = W * o[c].d;
     if (t == 0)
       for (int c = 0; c < M; ++c) out[L.fFf + c] = W * o[c].v;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
   }
   // element-state directions: d f_hat / d v = 1/2 (A_n(v) + sigma)
   double sig[M * M];   // sigma(v_hat), column t = sigma e_t
-  if (P.sigma_s) {
+  if (P.sigma_s == 1) {
     for (int t = 0; t < M; ++t) {
       double et[M], col[M];
       for (int c = 0; c < M; ++c) et[c] = c == t ? 1.0 : 0.0;
@@ -234,6 +234,50 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
         for (int j = 0; j < D; ++j) gn += G[c * D + j].d * n[j];
         out[L.fFv + c * M + t] += W * gn;
       }
+    }
+  }
+  if (P.sigma_s == 2) {
+    // mean-value stabilization: sigma depends on both states, so f_hat is differentiated with
+    // respect to v_hat and to v in full (the values above are replaced)
+    double gval[M];
+    for (int c = 0; c < M; ++c) gval[c] = 0.0;
+    if (VISC) {
+      double G[M * D];
+      flux_G<D, double, double>(P.ghat_v ? sv : sh, qq, gam, P.mu, P.Pr, G);
+      for (int c = 0; c < M; ++c)
+        for (int j = 0; j < D; ++j) gval[c] += G[c * D + j] * n[j];
+    }
+    for (int t = 0; t < M; ++t) {
+      Dual a[M], b[M], o[M];
+      for (int c = 0; c < M; ++c) {
+        a[c] = Dual{vh[c], c == t ? 1.0 : 0.0};
+        b[c] = Dual{vv[c], 0.0};
+      }
+      fhat_mv<D, Dual>(a, b, n, gam, o);
+      double gd[M];
+      for (int c = 0; c < M; ++c) gd[c] = 0.0;
+      if (VISC && !P.ghat_v) {
+        Dual G[M * D];
+        flux_G<D, Dual, double>(prim_of_v<D, Dual>(a, gam), qq, gam, P.mu, P.Pr, G);
+        for (int c = 0; c < M; ++c)
+          for (int j = 0; j < D; ++j) gd[c] += G[c * D + j].d * n[j];
+      }
+      for (int c = 0; c < M; ++c) out[L.fFh + c * M + t] = W * (o[c].d + gd[c]);
+      if (t == 0)
+        for (int c = 0; c < M; ++c) out[L.fFf + c] = W * (o[c].v + gval[c]);
+      for (int c = 0; c < M; ++c) {
+        a[c] = Dual{vh[c], 0.0};
+        b[c] = Dual{vv[c], c == t ? 1.0 : 0.0};
+      }
+      fhat_mv<D, Dual>(a, b, n, gam, o);
+      for (int c = 0; c < M; ++c) gd[c] = 0.0;
+      if (VISC && P.ghat_v) {
+        Dual G[M * D];
+        flux_G<D, Dual, double>(prim_of_v<D, Dual>(b, gam), qq, gam, P.mu, P.Pr, G);
+        for (int c = 0; c < M; ++c)
+          for (int j = 0; j < D; ++j) gd[c] += G[c * D + j].d * n[j];
+      }
+      for (int c = 0; c < M; ++c) out[L.fFv + c * M + t] = W * (o[c].d + gd[c]);
     }
   }
   if (VISC) {

@@ -209,6 +209,45 @@ __device__ inline void sigma_s_apply(const Prim<D, T> &s, const T *A0, const dou
   out[M - 1] = l1 * a1 * (H - c * un) + l2 * (a2 * 0.5 * kin + s.rho * vdVt) + l4 * a4 * (H + c * un);
 }
 
+// Mean-value stabilization (Section 4) on the straight path in entropy variables:
+// sigma_MV(vh, v) dv = int_0^1 sigma_S(vh + th (v - vh)) dv dth (the definition's two (1 - th)
+// weighted integrals add up to this), 4-point Gauss-Legendre in th.
+template <int D, typename T>
+__device__ inline void sigma_mv_apply(const T *vh, const T *v, const double *n, double gam, const T *dv, T *out) {
+  const int M = D + 2;
+  const double x0 = 0.3399810435848563, x1 = 0.8611363115940526;
+  const double w0 = 0.6521451548625461, w1 = 0.3478548451374538;
+  const double th[4] = {0.5 * (1.0 - x1), 0.5 * (1.0 - x0), 0.5 * (1.0 + x0), 0.5 * (1.0 + x1)};
+  const double wt[4] = {0.5 * w1, 0.5 * w0, 0.5 * w0, 0.5 * w1};
+  for (int c = 0; c < M; ++c) out[c] = cst<T>(0.0);
+  for (int g = 0; g < 4; ++g) {
+    T vt[M];
+    for (int c = 0; c < M; ++c) vt[c] = vh[c] + th[g] * (v[c] - vh[c]);
+    const Prim<D, T> st = prim_of_v<D, T>(vt, gam);
+    T A[M * M], o[M];
+    A0_of_prim<D, T>(st, gam, A);
+    sigma_s_apply<D, T, T>(st, A, n, gam, dv, o);
+    for (int c = 0; c < M; ++c) out[c] = out[c] + wt[g] * o[c];
+  }
+}
+
+// Inviscid trace flux with the mean-value stabilization: 1/2 (F_n(vh) + F_n(v)) + 1/2 sigma_MV (v - vh),
+// both states of type T (derivatives with respect to either).
+template <int D, typename T>
+__device__ inline void fhat_mv(const T *vh, const T *v, const double *n, double gam, T *out) {
+  const int M = D + 2;
+  T Fh[M * D], Fv[M * D], dv[M], sd[M];
+  flux_F<D, T>(prim_of_v<D, T>(vh, gam), gam, Fh);
+  flux_F<D, T>(prim_of_v<D, T>(v, gam), gam, Fv);
+  for (int c = 0; c < M; ++c) dv[c] = v[c] - vh[c];
+  sigma_mv_apply<D, T>(vh, v, n, gam, dv, sd);
+  for (int c = 0; c < M; ++c) {
+    T fn = cst<T>(0.0);
+    for (int j = 0; j < D; ++j) fn = fn + (Fh[c * D + j] + Fv[c * D + j]) * n[j];
+    out[c] = 0.5 * fn + 0.5 * sd[c];
+  }
+}
+
 // Trace flux f_hat + g_hat at one face point (stabilization sigma_SLF = lambda_max A0, or
 // sigma_S with sym_s, both at v* = v_hat).  vh: trace state (type T),
 // F_n(v) of the element state precomputed (double), dv = v - v_hat evaluated

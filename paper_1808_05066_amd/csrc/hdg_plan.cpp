@@ -289,7 +289,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   D.zero_xcd = 1;
   D.src = nullptr;
   D.ghat_v = (opts && (opts->flags & HDG_FLAG_GHAT_INTERIOR)) ? 1 : 0;
-  D.sigma_s = (opts && (opts->flags & HDG_FLAG_SIGMA_S)) ? 1 : 0;
+  D.sigma_s = (opts && (opts->flags & HDG_FLAG_SIGMA_MV)) ? 2 : (opts && (opts->flags & HDG_FLAG_SIGMA_S)) ? 1 : 0;
   D.a_qmin = 0;
   D.condense_launches = 2;
   P->fused = D.cw != 0;

@@ -25,7 +25,8 @@ struct DevPlan {
   int zero_xcd;            // 1: the contraction clears X, C and D first (0: they hold the zeros already)
   int a_qmin;              // 1: of the q rows of A only M and G_j of the first component are formed
   int ghat_v;              // 1: viscous numerical flux G(v, q).n with the element's v (else G(v_hat, q).n)
-  int sigma_s;             // 1: stabilization sigma_S = |A_n| A0 (else sigma_SLF = lambda_max A0), at v_hat
+  int sigma_s;             // stabilization: 0 sigma_SLF = lambda_max A0, 1 sigma_S = |A_n| A0 (both at v_hat),
+                           // 2 sigma_MV (mean value between v_hat and v)
   int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
   double gamma, mu, Pr, alpha;
   const double *src;       // [m][E*Np] nodal source of the conservation law (device, caller-owned) or null

@@ -269,17 +269,18 @@ def test_interior_viscous_flux_matches_oracle(torch, name):
     assert rel_err_per_elem(np.stack([b["C"] for b in blocks]), np.stack([b["C"] for b in base])) > 1e-6
 
 
+@pytest.mark.parametrize("sigma", ["s", "mv"])
 @pytest.mark.parametrize("name", ["euler2d_tri_p2", "ns3d_hex_p1", "euler3d_hex_p2"])
-def test_symmetric_variable_stabilization_matches_oracle(torch, name):
-    """HDG_FLAG_SIGMA_S: stabilization sigma_S = |A_n(v_hat)| A0(v_hat) (the symmetric variable
-    matrix of Section 4).  Blocks, residuals and condensed outputs against the oracle with the
-    same matrix; the blocks must differ from the sigma_SLF ones."""
+def test_symmetric_variable_stabilization_matches_oracle(torch, name, sigma):
+    """HDG_FLAG_SIGMA_S / HDG_FLAG_SIGMA_MV: stabilization sigma_S = |A_n(v_hat)| A0(v_hat) or the
+    mean-value matrix between v_hat and v (Section 4).  Blocks, residuals and condensed outputs
+    against the oracle with the same matrix; the blocks must differ from the sigma_SLF ones."""
     wl = SMALL_CASES[name]()
-    disc = oracle_disc(wl, sigma="s")
+    disc = oracle_disc(wl, sigma=sigma)
     inp = ostate.oracle_inputs(wl, disc)
     blocks = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"],
                                     keep_blocks=True)
-    plan = gpu_plan(wl, sigma="s")
+    plan = gpu_plan(wl, sigma=sigma)
     d = to_dev(inp)
     out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
     cond = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], residuals=True)

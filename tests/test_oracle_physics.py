@@ -170,3 +170,26 @@ def test_abs_An_matches_the_eigen_decomposition():
             S = np.stack([P.sigma_s_apply(v, n, GAM, e) for e in np.eye(m)], axis=1)
             assert np.max(np.abs(S - S.T)) <= 1e-12 * np.max(np.abs(S))
             assert np.min(np.linalg.eigvalsh(0.5 * (S + S.T))) >= -1e-12 * np.max(np.abs(S))
+
+
+def test_mean_value_stabilization():
+    """sigma_MV: equal to sigma_S when v = v_hat (the path is a point), symmetric positive
+    semi-definite, and its 4-point theta rule reproduces a fine (64-point) rule of the same
+    integral between nearby states where no wave speed changes sign along the path (the
+    integrand is then smooth; n along the velocity keeps V.n > 0)."""
+    rng = np.random.default_rng(5)
+    for d in (2, 3):
+        m = d + 2
+        Vh = np.array([0.4, -0.2, 0.1][:d])
+        vh = P.v_of_prim(np.array(1.1), Vh, np.array(0.9), GAM)
+        v = P.v_of_prim(np.array(1.15), np.array([0.45, -0.15, 0.12][:d]), np.array(0.95), GAM)
+        n = Vh / np.linalg.norm(Vh)
+        dv = rng.standard_normal(m)
+        assert np.allclose(P.sigma_mv_apply(vh, vh, n, GAM, dv), P.sigma_s_apply(vh, n, GAM, dv), rtol=1e-13,
+                           atol=1e-13)
+        S = np.stack([P.sigma_mv_apply(vh, v, n, GAM, e) for e in np.eye(m)], axis=1)
+        assert np.max(np.abs(S - S.T)) <= 1e-12 * np.max(np.abs(S))
+        assert np.min(np.linalg.eigvalsh(0.5 * (S + S.T))) >= -1e-12 * np.max(np.abs(S))
+        th, w = np.polynomial.legendre.leggauss(64)
+        fine = sum(0.5 * wi * P.sigma_s_apply(vh + 0.5 * (1 + ti) * (v - vh), n, GAM, dv) for ti, wi in zip(th, w))
+        assert np.max(np.abs(P.sigma_mv_apply(vh, v, n, GAM, dv) - fine)) <= 1e-9 * np.max(np.abs(fine))
