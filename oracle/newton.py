@@ -63,6 +63,31 @@ def l2_error_u(disc: hdg.Discretization, v, u_exact):
     return np.sqrt(err)
 
 
+def l2_error_v(disc: hdg.Discretization, v, v_exact):
+    """sqrt(sum_K int |v_h - v_exact|^2) with the element quadrature."""
+    err = 0.0
+    for e in range(disc.mesh.n_elem):
+        G = disc.geom(e)
+        dv = disc.ref.phi @ v[:, e * disc.Np:(e + 1) * disc.Np].T - v_exact(G.xq)
+        err += np.sum(G.W[:, None] * dv ** 2)
+    return np.sqrt(err)
+
+
+def entropy_integral(disc: hdg.Discretization, v):
+    """Per element (int_K rho s, int_K rho) with s = ln(p / rho^gamma) at u(v_h), by the
+    element quadrature: the total thermodynamic entropy, the negative of the integral of
+    the generalized entropy H = -rho s that Proposition 1 follows (entropy-variable section)."""
+    from . import physics as ph
+    out = np.zeros((disc.mesh.n_elem, 2))
+    for e in range(disc.mesh.n_elem):
+        G = disc.geom(e)
+        vq = disc.ref.phi @ v[:, e * disc.Np:(e + 1) * disc.Np].T
+        H, _ = ph.entropy_pair(vq, disc.phys.gamma)
+        rho = ph.prim_of_v(vq, disc.phys.gamma)[0]
+        out[e] = (np.sum(G.W * -H), np.sum(G.W * rho))
+    return out
+
+
 # ---- one step of Alexander's three-stage L-stable DIRK(3,3) (the time integration of
 # the paper's numerical examples, Section 5).  Stage i solves
 #   alpha (u(v_i) - u*_i, w) + s(v_i; w) = 0,   alpha = 1 / (a_ii dt),
