@@ -153,10 +153,18 @@ int hdg_quad_coords(const hdg_plan *plan, double *xq, void *stream);
 /* Element L2 errors against values at the volume quadrature points (xq order):
  *   out[e][c] = sum_q W_q (f_c(x_q) - exact[c][e Nq + q])^2,
  * kind 0: f = u(v_h) from v [m][E*Np], c < m (conserved variables);
- * kind 1: f = the gradient unknowns q [m*dim][E*Np] interpolated, c < m*dim (NS only).
+ * kind 1: f = the gradient unknowns q [m*dim][E*Np] interpolated, c < m*dim (NS only);
+ * kind 2: f = the entropy variables v_h [m][E*Np] interpolated, c < m.
  * All device; out [E][m] or [E][m*dim]. */
 int hdg_l2_error(const hdg_plan *plan, int kind, const double *f, const double *exact, double *out,
                  void *stream);
+/* Total thermodynamic entropy and mass of each element (the quantities whose evolution
+ * Proposition 1 and the Shu vortex example of Section 5 follow):
+ *   out[e][0] = int_K rho s,  out[e][1] = int_K rho,  s = ln(p / rho^gamma),
+ * at the states u(v_h) of v [m][E*Np], by the volume quadrature.  -out[e][0] is the
+ * element integral of the generalized entropy H = -rho s of the entropy-variable section;
+ * a baseline s0 enters as -s0 out[e][1].  Device pointers; out [E][2]. */
+int hdg_entropy_integral(const hdg_plan *plan, const double *v, double *out, void *stream);
 
 /* Bytes of device workspace the plan needs (tables + per-chunk scratch). */
 int hdg_plan_workspace_bytes(const hdg_plan *plan, size_t *bytes);

@@ -384,10 +384,19 @@ extern "C" int hdg_l2_error(const hdg_plan *plan, int kind, const double *f, con
                             void *stream) {
   const Plan *P = checked(const_cast<hdg_plan *>(plan));
   if (!P) return HDG_EINVAL;
-  if (!f || !exact || !out || kind < 0 || kind > 1 || (kind == 1 && !P->dp.viscous))
+  if (!f || !exact || !out || kind < 0 || kind > 2 || (kind == 1 && !P->dp.viscous))
     return fail(HDG_EINVAL, "bad argument");
   hipError_t e = launch_l2_error(P->dp, kind, f, exact, out, reinterpret_cast<hipStream_t>(stream));
   if (e) return hip_fail(e, "l2_error");
+  return HDG_OK;
+}
+
+extern "C" int hdg_entropy_integral(const hdg_plan *plan, const double *v, double *out, void *stream) {
+  const Plan *P = checked(const_cast<hdg_plan *>(plan));
+  if (!P) return HDG_EINVAL;
+  if (!v || !out) return fail(HDG_EINVAL, "null argument");
+  hipError_t e = launch_entropy(P->dp, v, out, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "entropy_integral");
   return HDG_OK;
 }
 

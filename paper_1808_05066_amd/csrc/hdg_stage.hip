@@ -117,15 +117,16 @@ __global__ void k_quad_coords(DevPlan P, double *xq) {
   }
 }
 
-// out[e][c] = sum_q W_q (f_c(x_q) - ex[c][e Nq + q])^2 with f_c = u_c(v_h) (kind 0, f = v) or
-// the interpolated gradient unknowns (kind 1, f = q)
+// out[e][c] = sum_q W_q (f_c(x_q) - ex[c][e Nq + q])^2 with f_c = u_c(v_h) (kind 0, f = v),
+// the interpolated gradient unknowns (kind 1, f = q) or the interpolated entropy variables
+// (kind 2, f = v)
 template <int D>
 __global__ __launch_bounds__(64) void k_l2_error(DevPlan P, int kind, const double *__restrict__ f,
                                                  const double *__restrict__ ex, double *out) {
   constexpr int M = D + 2, NC = M * D;
   __shared__ double red[64][NC];
   const int e = blockIdx.x, tid = threadIdx.x;
-  const int Np = P.Np, Nq = P.Nq, nc = kind == 0 ? M : NC;
+  const int Np = P.Np, Nq = P.Nq, nc = kind == 1 ? NC : M;
   const size_t NN = (size_t)P.n_elem * Np, NQ = (size_t)P.n_elem * Nq;
   double acc[NC];
   for (int c = 0; c < NC; ++c) acc[c] = 0.0;
@@ -156,7 +157,49 @@ __global__ __launch_bounds__(64) void k_l2_error(DevPlan P, int kind, const doub
   }
 }
 
+// out[e] = (sum_q W_q rho s, sum_q W_q rho) at the states v_h(x_q), s = ln(p / rho^gamma):
+// the element's total thermodynamic entropy (minus the generalized entropy H = -rho s of the
+// entropy-variable section) and its mass
+template <int D>
+__global__ __launch_bounds__(64) void k_entropy(DevPlan P, const double *__restrict__ v, double *out) {
+  constexpr int M = D + 2;
+  __shared__ double red[2][64];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int Np = P.Np, Nq = P.Nq;
+  const size_t NN = (size_t)P.n_elem * Np;
+  double rs = 0.0, rm = 0.0;
+  for (int q = tid; q < Nq; q += 64) {
+    const double *phi = P.phi + (size_t)q * Np;
+    double val[M];
+    for (int c = 0; c < M; ++c) {
+      double s = 0.0;
+      for (int a = 0; a < Np; ++a) s += phi[a] * v[(size_t)c * NN + (size_t)e * Np + a];
+      val[c] = s;
+    }
+    const Prim<D, double> st = prim_of_v<D, double>(val, P.gamma);
+    const double W = P.geo_vol[((size_t)e * Nq + q) * (1 + D * D)];
+    rs += W * st.rho * (log(st.p) - P.gamma * log(st.rho));
+    rm += W * st.rho;
+  }
+  red[0][tid] = rs;
+  red[1][tid] = rm;
+  __syncthreads();
+  if (tid < 2) {
+    double s = 0.0;
+    for (int t = 0; t < 64; ++t) s += red[tid][t];
+    out[(size_t)e * 2 + tid] = s;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_entropy(const DevPlan &P, const double *v, double *out, hipStream_t s) {
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_entropy<2>, dim3(P.n_elem), dim3(64), 0, s, P, v, out);
+  else
+    hipLaunchKernelGGL(k_entropy<3>, dim3(P.n_elem), dim3(64), 0, s, P, v, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_quad_coords(const DevPlan &P, double *xq, hipStream_t s) {
   const size_t NQ = (size_t)P.n_elem * P.Nq;

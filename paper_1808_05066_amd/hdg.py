@@ -314,12 +314,20 @@ class Plan:
 
     def l2_error(self, f, exact, kind="u"):
         """Per-component squared L2 errors summed over the elements (hdg_l2_error): kind "u"
-        compares u(v_h) from v with exact conserved variables, kind "q" the gradient unknowns."""
-        k = {"u": 0, "q": 1}[kind]
-        nc = self.m if k == 0 else self.m * self.dim
+        compares u(v_h) from v with exact conserved variables, kind "q" the gradient unknowns,
+        kind "v" the entropy variables."""
+        k = {"u": 0, "q": 1, "v": 2}[kind]
+        nc = self.m * self.dim if k == 1 else self.m
         out = self._empty(self.n_elem, nc)
         check(self.lib.hdg_l2_error(self.h, k, _ptr(f), _ptr(exact), _ptr(out), _stream()), "hdg_l2_error")
         return out.sum(dim=0)
+
+    def entropy_integral(self, v):
+        """Per-element (int_K rho s, int_K rho), s = ln(p / rho^gamma), as [E][2]
+        (hdg_entropy_integral)."""
+        out = self._empty(self.n_elem, 2)
+        check(self.lib.hdg_entropy_integral(self.h, _ptr(v), _ptr(out), _stream()), "hdg_entropy_integral")
+        return out
 
     def trace_rhs(self, g, r=None):
         if r is None:

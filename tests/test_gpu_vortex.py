@@ -1,0 +1,76 @@
+"""Entropy integrals and the Shu vortex of Section 5 on the GPU.
+
+* hdg_entropy_integral and the v-norm error (hdg_l2_error kind 2) against the oracle's
+  entropy_integral and l2_error_v on a perturbed vortex state (200 triangles, p = 4):
+  every element to 1e-12 relative.
+* The Shu vortex set-up (psi = 5, M = gamma^-1/2, 200 triangles, k = 4, dt = 0.05) for
+  40 DIRK(3,3) steps (t = 2): every stage's Newton iteration converges, the mass stays
+  constant to 1e-12 relative, the total thermodynamic entropy int rho s never decreases
+  from one step to the next (beyond 1e-12 of its scale: the semi-discrete entropy balance
+  of Proposition 1, observed through the time discretization as the paper reports), and
+  the errors in u and v stay at the level of the spatial discretization: within 1.5x and
+  2.5x the error of the initial nodal state (0.022 in u, 0.0089 in v; 0.022 and 0.016
+  measured at t = 2)."""
+import numpy as np
+import pytest
+
+from oracle import hdg as ohdg, newton, physics as ph
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def test_entropy_integral_and_v_error_match_oracle(torch):
+    from paper_1808_05066_amd.hdg import Plan
+    from workloads import fields as F, meshes as M
+    gamma, p = 1.4, 4
+    f = F.ShuVortex(mach=gamma ** -0.5, L=1.0, center=(0.3, -0.2), gamma=gamma)
+    mesh = M.tri_square(10, 0.05, 11, periodic=True, lo=-5.0, length=10.0)
+    tmap, nt = M.trace_map(mesh, p, "hdg")
+    fbc = np.zeros((mesh.n_elem, 3), dtype=np.int32)
+    disc = ohdg.Discretization(mesh, p, ohdg.Phys(gamma, 0.0, 0.72, 0.0, False), tmap, nt, fbc)
+    x = disc.node_coords()
+    prim = f.prim(x)
+    prim[3] *= 1.0 + 0.05 * np.sin(x[0]) * np.cos(0.7 * x[1])   # not homentropic
+    v = ph.v_of_prim(prim[0], prim[1:3].T, prim[3], gamma).T.copy()
+
+    def vex(xq):
+        pr = f.prim(xq.T)
+        return ph.v_of_prim(pr[0], pr[1:3].T, pr[3], gamma)
+
+    ref = newton.entropy_integral(disc, v)
+    ref_ev = newton.l2_error_v(disc, v, vex)
+    plan = Plan("tri", p, mesh.elem_xyz, tmap, nt, fbc, viscous=False, gamma=gamma)
+    dv = torch.from_numpy(v).cuda()
+    got = plan.entropy_integral(dv).cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())
+    xq = plan.quad_coords().cpu().numpy()
+    pr = torch.from_numpy(np.ascontiguousarray(f.prim(xq))).cuda()
+    vq, _, _ = plan.prepare_state(pr)
+    ev = float(torch.sqrt(plan.l2_error(dv, vq, "v").sum()))
+    print("entropy", got.sum(0), "v error", ev, ref_ev, flush=True)
+    assert abs(ev - ref_ev) <= 1e-12 * ref_ev
+
+
+def test_shu_vortex_entropy_history(torch):
+    from paper_1808_05066_amd.vortex import shu_vortex_run
+    r = shu_vortex_run(40)
+    h = r["history"]
+    for row in h[:3] + h[-3:]:
+        print(row, flush=True)
+    print("seconds", r["seconds"], "S0", r["S0"], flush=True)
+    assert len(h) == 41 and all(row["converged"] for row in h)
+    dS = np.array([row["dS"] for row in h])
+    mass = np.array([row["mass"] for row in h])
+    scale = abs(r["S0"]) + r["mass0"]
+    assert np.all(np.diff(dS) >= -1e-12 * scale), np.diff(dS).min()
+    assert np.abs(mass / r["mass0"] - 1.0).max() < 1e-12
+    assert max(row["err_u"] for row in h) <= 1.5 * h[0]["err_u"]
+    assert max(row["err_v"] for row in h) <= 2.5 * h[0]["err_v"]
