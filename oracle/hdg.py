@@ -18,6 +18,13 @@ and the element's share of the trace equation is
 
     R_tr[f,c,b] = <f_hat + g_hat, mu_b>_F       (interior / periodic faces)
     R_tr[f,c,b] = <v_hat - v_bc, mu_b>_F        (Dirichlet-trace faces)
+    R_tr[f,c,b] = 0                             (other faces at a node of a Dirichlet face)
+
+The last case only arises with a continuous trace (EDG): a trace node shared by a
+Dirichlet face and interior faces keeps the Dirichlet condition alone, so the
+boundary value is imposed at the node rather than mixed with flux balances of
+other faces (the paper leaves the boundary operator open; HDG and IEDG traces
+never share a node across a Dirichlet face).
 
 The mass term alpha (u(v_h) - u*, w) stands in for the time derivative of a
 backward-Euler or DIRK stage (alpha = 1 / (a_ii dt); alpha = 0 is steady);
@@ -77,6 +84,9 @@ class Discretization:
         self.n_trace = n_trace
         self.face_bc = (np.zeros((mesh.n_elem, self.nf), dtype=np.int32)
                         if face_bc is None else np.asarray(face_bc))
+        # trace nodes of Dirichlet-trace faces
+        self.dir_node = np.zeros(n_trace, dtype=bool)
+        self.dir_node[self.tmap[self.face_bc == 1].ravel()] = True
         self.n = m * self.Np * (1 + d) if phys.viscous else m * self.Np
         self.k = self.nf * m * self.Nfp
         self._geo = {}
@@ -171,7 +181,8 @@ class Discretization:
                 vbq = F["psi"] @ vb.T
                 Rtr.append(np.einsum("q,pqc,qb->pcb", F["W"], vhf - vbq[None], F["psi"]))
             else:
-                Rtr.append(np.einsum("q,pqc,qb->pcb", F["W"], tf, F["psi"]))
+                keep = ~self.dir_node[self.tmap[e, f]]
+                Rtr.append(np.einsum("q,pqc,qb->pcb", F["W"], tf, F["psi"]) * keep)
         Rloc = Rv.reshape(P, -1)
         if ph_.viscous:
             Rloc = np.concatenate([Rloc, Rq.reshape(P, -1)], axis=1)

@@ -79,3 +79,38 @@ def test_couette_source_is_the_divergence_of_the_fluxes():
     div = sum(d4(lambda Y: flux(Y)[:, :, k], X, k, 2e-3) for k in range(2)).T
     s = c.source(X)
     assert np.max(np.abs(div - s)) <= 1e-5 * np.max(np.abs(s))
+
+
+def test_ringleb_field_is_a_steady_euler_solution():
+    """The Ringleb field, read with (x - A/2)^2 + y^2 = 1/(4 c^10 V^4) and the 1/(3c^3) term of A
+    (both printed garbled), is a steady Euler solution on the example's square: the central
+    difference divergence of its inviscid fluxes (written out here) falls as h^2 (below 1e-7
+    at h = 1e-3, 100x smaller at h = 1e-4), while the mirrored flow angle leaves an O(1)
+    residual; the root solves the hodograph relation, the flow is subsonic, and p = rho^gamma / gamma
+    (the hodograph flow is homentropic)."""
+    from workloads.fields import Ringleb
+    f = Ringleb()
+    g = f.gamma
+    rng = np.random.default_rng(0)
+    pts = np.stack([rng.uniform(-4.9, -1.1, 60), rng.uniform(1.1, 4.9, 60)])
+
+    def fluxes(X, flip=1.0):
+        r, u, v, p = f.prim(X)
+        v = flip * v
+        E = p / (g - 1) + 0.5 * r * (u * u + v * v)
+        return (np.stack([r * u, r * u * u + p, r * u * v, u * (E + p)]),
+                np.stack([r * v, r * u * v, r * v * v + p, v * (E + p)]))
+
+    def div(h, flip=1.0):
+        ex, ey = np.array([[h], [0.0]]), np.array([[0.0], [h]])
+        return np.abs((fluxes(pts + ex, flip)[0] - fluxes(pts - ex, flip)[0]) / (2 * h)
+                      + (fluxes(pts + ey, flip)[1] - fluxes(pts - ey, flip)[1]) / (2 * h)).max()
+
+    r3, r4 = div(1e-3), div(1e-4)
+    assert r3 < 1e-7 and r4 < r3 / 50
+    assert div(1e-4, flip=-1.0) > 0.1
+    c = f.speed_of_sound(pts)
+    assert np.abs(f._f(c, pts[0], pts[1])).max() < 1e-9
+    r, u, v, p = f.prim(pts)
+    assert np.all(np.hypot(u, v) < np.sqrt(g * p / r))
+    np.testing.assert_allclose(p, r ** g / g, rtol=1e-13)

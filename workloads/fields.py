@@ -17,6 +17,9 @@ Fields:
 * ``Uniform`` -- a constant state (free-stream tests).
 * ``Couette`` -- the steady compressible Couette flow with a source term of the
   paper's Navier-Stokes convergence example (exact solution and source).
+* ``Ringleb`` -- the Ringleb flow of the paper's steady Euler convergence
+  example (hodograph solution; speed of sound from a scalar root find per point,
+  written with the corrected forms of two garbled formulas, see tests).
 * ``SmoothNoise`` wraps a field and perturbs it with seeded periodic
   sinusoids (relative for rho and p, scaled by a reference speed for V).
 * ``node_noise`` draws the per-node i.i.d. perturbation.
@@ -90,6 +93,51 @@ class Couette(Field):
         se = -mu * V0 ** 2 / L ** 2 * (lg ** 2 + y * lg / (1 + y) + (y * (3 + 2 * y) * lg - 2 * y - 1) / (1 + y) ** 2)
         z = 0 * y
         return np.stack([z, sx, z, se])
+
+
+class Ringleb(Field):
+    """Steady Ringleb flow (real points only; gamma = 1.4 is built into its hodograph).
+
+    With c the speed of sound and V the speed, c^2 = 1 - V^2 / 5 and
+    A(c) = 1/c + 1/(3c^3) + 1/(5c^5) - ln((1 + c) / (1 - c)) / 2, the point (x, y) lies on
+    (x - A/2)^2 + y^2 = 1 / (4 c^10 V^4); its streamline parameter is
+    psi^2 = 1 / (2V^2) - c^5 (x - A/2) and the flow angle theta = arcsin(psi V).  Then
+    rho = c^5, p = c^7 / gamma and V = V (cos theta, sin theta).  The root in c is unique
+    in (1/2, 1) on the example's square (-5, -1) x (1, 5) (subsonic there, c > 0.95) and is
+    found by bisection."""
+
+    gamma = 1.4
+
+    def __init__(self):
+        self.dim = 2
+
+    @staticmethod
+    def _A(c):
+        return 1.0 / c + 1.0 / (3.0 * c ** 3) + 1.0 / (5.0 * c ** 5) - 0.5 * np.log((1.0 + c) / (1.0 - c))
+
+    def _f(self, c, x, y):
+        V2 = 5.0 * (1.0 - c * c)
+        return (x - 0.5 * self._A(c)) ** 2 + y * y - 1.0 / (4.0 * c ** 10 * V2 * V2)
+
+    def speed_of_sound(self, x):
+        x0, y0 = np.asarray(x[0], float), np.asarray(x[1], float)
+        lo = np.full(x0.shape, 0.5)
+        hi = np.full(x0.shape, 1.0 - 1e-14)
+        if np.any(self._f(lo, x0, y0) <= 0.0) or np.any(self._f(hi, x0, y0) >= 0.0):
+            raise ValueError("point outside the bracketed Ringleb region")
+        for _ in range(64):
+            mid = 0.5 * (lo + hi)
+            pos = self._f(mid, x0, y0) > 0.0
+            lo = np.where(pos, mid, lo)
+            hi = np.where(pos, hi, mid)
+        return 0.5 * (lo + hi)
+
+    def prim(self, x):
+        c = self.speed_of_sound(x)
+        V = np.sqrt(5.0 * (1.0 - c * c))
+        psi = np.sqrt(1.0 / (2.0 * V * V) - c ** 5 * (np.asarray(x[0], float) - 0.5 * self._A(c)))
+        th = np.arcsin(np.clip(psi * V, -1.0, 1.0))
+        return np.stack([c ** 5, V * np.cos(th), V * np.sin(th), c ** 7 / self.gamma])
 
 
 class ShuVortex(Field):
