@@ -84,7 +84,12 @@ typedef struct {
   int order;               /* polynomial degree p (1..4) */
   int n_elem;
   const double *elem_xyz;  /* [n_elem][n_vertices][dim]: straight-sided or multilinear */
-  const int32_t *face_bc;  /* [n_elem][nf]: 0 flux face, 1 Dirichlet-trace face; NULL: all 0 */
+  const int32_t *face_bc;  /* [n_elem][nf]: 0 flux face, 1 Dirichlet-trace face; NULL: all 0.
+                              The trace rows of a Dirichlet-trace face are <v_hat - v_bc, mu>
+                              (the boundary operator of the trace equation, left open by the
+                              paper); a trace node that a Dirichlet face shares with flux faces
+                              (a continuous, EDG trace) keeps only those rows: the flux faces'
+                              rows at that node are dropped, so the node takes the boundary value */
   const int32_t *trace_map;/* [n_elem][nf][Nfp] global trace node; encodes HDG/EDG/IEDG */
   int n_trace;             /* number of global trace nodes */
 } hdg_mesh;

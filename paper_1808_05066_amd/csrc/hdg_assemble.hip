@@ -540,6 +540,29 @@ __global__ __launch_bounds__(BLK) void k_contract(DevPlan P, int e0, int ec) {
   }
 }
 
+// Zero the trace rows (f, c, b) of C, D and R_tr of the face nodes marked in row_drop, one
+// workgroup per element of the chunk; index i runs over (row, column) with the row fastest
+// (columns n of C, then k of D, then R_tr), matching the column-major blocks.
+__global__ __launch_bounds__(256) void k_drop_rows(DevPlan P, int e0) {
+  const int el = blockIdx.x, e = e0 + el;
+  const int n = P.n, k = P.k, kp = P.k_pad, Nfp = P.Nfp, MF = P.m * P.Nfp;
+  const int *drop = P.row_drop + (size_t)e * P.nf * Nfp;
+  double *C = P.C + (size_t)el * P.n_pad * kp;
+  double *Dm = P.D + (size_t)el * kp * kp;
+  double *Rt = P.Rt + (size_t)el * kp;
+  const size_t total = (size_t)k * (n + k + 1);
+  for (size_t i = threadIdx.x; i < total; i += 256) {
+    const int row = (int)(i % k), col = (int)(i / k);
+    if (!drop[(row / MF) * Nfp + row % Nfp]) continue;
+    if (col < n)
+      C[(size_t)col * kp + row] = 0.0;
+    else if (col < n + k)
+      Dm[(size_t)(col - n) * kp + row] = 0.0;
+    else
+      Rt[row] = 0.0;
+  }
+}
+
 __global__ void k_export(DevPlan P, int e0, int ec, double *A, double *B, double *C, double *Dm, double *Rl,
                          double *Rtr) {
   const int el = blockIdx.x, e = e0 + el;
@@ -632,6 +655,12 @@ hipError_t launch_contract(const DevPlan &P, int e0, int ec, hipStream_t s) {
 hipError_t launch_export_blocks(const DevPlan &P, int e0, int ec, double *A, double *B, double *C, double *D,
                                 double *Rloc, double *Rtr, hipStream_t s) {
   hipLaunchKernelGGL(k_export, dim3(ec), dim3(256), 0, s, P, e0, ec, A, B, C, D, Rloc, Rtr);
+  return hipGetLastError();
+}
+
+hipError_t launch_drop_rows(const DevPlan &P, int e0, int ec, hipStream_t s) {
+  if (!P.row_drop) return hipSuccess;
+  hipLaunchKernelGGL(k_drop_rows, dim3(ec), dim3(256), 0, s, P, e0);
   return hipGetLastError();
 }
 

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(JB) void k_jvp(DevPlan P, int e0, const double *__r
         acc += mu * o[c];
       }
     }
-    yt[row] = acc;
+    yt[row] = (P.row_drop && P.row_drop[((size_t)e * nf + f) * Nfp + ib]) ? 0.0 : acc;
   }
 }
 

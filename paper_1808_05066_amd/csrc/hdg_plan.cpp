@@ -94,6 +94,21 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   P->face_bc.assign((size_t)E * R.nf, 0);
   if (mesh->face_bc)
     for (size_t i = 0; i < P->face_bc.size(); ++i) P->face_bc[i] = mesh->face_bc[i] ? 1 : 0;
+  // A continuous (EDG) trace node on a Dirichlet face keeps the Dirichlet condition alone: the
+  // flux rows that other faces contribute at that node are dropped.
+  {
+    std::vector<char> dir_node(mesh->n_trace, 0);
+    for (size_t ef = 0; ef < P->face_bc.size(); ++ef)
+      if (P->face_bc[ef])
+        for (int b = 0; b < R.Nfp; ++b) dir_node[P->tmap[ef * R.Nfp + b]] = 1;
+    std::vector<int> drop(P->tmap.size(), 0);
+    bool any = false;
+    for (size_t ef = 0; ef < P->face_bc.size(); ++ef)
+      if (!P->face_bc[ef])
+        for (int b = 0; b < R.Nfp; ++b)
+          if (dir_node[P->tmap[ef * R.Nfp + b]]) drop[ef * R.Nfp + b] = 1, any = true;
+    if (any) P->row_drop.swap(drop);
+  }
   P->node_face.assign(R.Np * R.nf, -1);
   for (int f = 0; f < R.nf; ++f)
     for (int b = 0; b < R.Nfp; ++b) P->node_face[R.fnodes[f * R.Nfp + b] * R.nf + f] = b;
@@ -288,6 +303,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   D.contract_threads = 1024;
   D.zero_xcd = 1;
   D.src = nullptr;
+  D.row_drop = nullptr;
   D.ghat_v = (opts && (opts->flags & HDG_FLAG_GHAT_INTERIOR)) ? 1 : 0;
   D.sigma_s = (opts && (opts->flags & HDG_FLAG_SIGMA_MV)) ? 2 : (opts && (opts->flags & HDG_FLAG_SIGMA_S)) ? 1 : 0;
   D.a_qmin = 0;
@@ -454,7 +470,7 @@ namespace {
 
 struct Layout {
   size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x;
-  size_t bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos, uinfo, tables_end;
+  size_t bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos, uinfo, row_drop, tables_end;
   size_t pv, pf, A, X, C, D, Rt, ipiv, inv, mg;
   size_t rA, rX, rC, rD, rRt, rMH, rYv, rzv, ripiv, rinv, total;
 };
@@ -487,6 +503,7 @@ Layout layout(const Plan *P) {
   l.bj_loc = take(P->bj_loc.size() * 4);
   l.bj_tpos = take(P->bj_tpos.size() * 4);
   l.uinfo = take(P->uinfo.size() * 4);
+  l.row_drop = take(P->row_drop.size() * 4);
   l.tables_end = o;
   l.pv = take(ch * D.Nq * D.L.size * 8);
   l.pf = take(ch * D.nf * D.Nfq * D.L.fsize * 8);
@@ -589,6 +606,7 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   if (!e) e = up(l.bj_loc, P->bj_loc.data(), P->bj_loc.size() * 4);
   if (!e) e = up(l.bj_tpos, P->bj_tpos.data(), P->bj_tpos.size() * 4);
   if (!e) e = up(l.uinfo, P->uinfo.data(), P->uinfo.size() * 4);
+  if (!e) e = up(l.row_drop, P->row_drop.data(), P->row_drop.size() * 4);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(e, "bind_workspace upload");
   P->xcd_clean = false;
@@ -620,6 +638,7 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   D.inv = reinterpret_cast<double *>(base + l.inv);
   D.mg = P->uinfo.empty() ? nullptr : reinterpret_cast<double *>(base + l.mg);
   D.uinfo = P->uinfo.empty() ? nullptr : reinterpret_cast<const int *>(base + l.uinfo);
+  D.row_drop = P->row_drop.empty() ? nullptr : reinterpret_cast<const int *>(base + l.row_drop);
   if (P->qelim) {
     QElimArgs &Q = P->qa;
     Q.A = reinterpret_cast<double *>(base + l.rA);
@@ -703,6 +722,7 @@ int run_front(Plan *P, const double *v, const double *q, const double *vhat, con
   const bool one_chunk = P->chunk >= P->n_elem;
   P->dp.zero_xcd = (one_chunk && P->xcd_clean) ? 0 : 1;
   if (!e) e = P->contract_mfma ? launch_contract_mfma(P->dp, e0, ec, s) : launch_contract(P->dp, e0, ec, s);
+  if (!e && P->dp.row_drop) e = launch_drop_rows(P->dp, e0, ec, s);
   if (!e) e = phase_end(P, PH_CONTRACT, s);
   if (e) {
     P->xcd_clean = false;

@@ -41,6 +41,8 @@ struct DevPlan {
   const double *geo_face;  // [E][nf][Nfq][1 + dim]: W_f, n
   const int *tmap;         // [E][nf][Nfp]
   const int *face_bc;      // [E][nf]
+  const int *row_drop;     // [E][nf][Nfp] 1: the trace rows of this face node are dropped (a continuous
+                           // trace node of a Dirichlet face seen from another face), or null when none is
   const double *node_x;    // [dim][E*Np]
   const double *trace_x;   // [dim][n_trace]
   // per-chunk scratch (device)
@@ -104,6 +106,7 @@ struct Plan {
   // host copies
   std::vector<double> geo_vol, geo_face, node_x, trace_x;
   std::vector<int> tmap, face_bc, node_face;
+  std::vector<int> row_drop;  // see DevPlan::row_drop (empty: no row is dropped)
   std::vector<int> bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos;
   std::vector<int> uinfo;   // see DevPlan::uinfo (empty: the q rows of A are read, not formed)
   // workspace
@@ -216,6 +219,7 @@ hipError_t launch_mass_solve(const DevPlan &P, const double *b, double *u, hipSt
 hipError_t launch_quad_coords(const DevPlan &P, double *xq, hipStream_t s);
 hipError_t launch_l2_error(const DevPlan &P, int kind, const double *f, const double *ex, double *out,
                            hipStream_t s);
+hipError_t launch_drop_rows(const DevPlan &P, int e0, int ec, hipStream_t s);
 hipError_t launch_entropy(const DevPlan &P, const double *v, double *out, hipStream_t s);
 hipError_t launch_prepare_state(const DevPlan &P, int N, const double *prim, const double *grad,
                                 double *v, double *q, double *u, hipStream_t s);
