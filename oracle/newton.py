@@ -88,6 +88,35 @@ def entropy_integral(disc: hdg.Discretization, v):
     return out
 
 
+def flow_statistics(disc: hdg.Discretization, v):
+    """Per element the integrals of (rho s, rho, rho |V|^2 / 2, |omega|^2, theta, theta^2, T,
+    T^2) by the element quadrature, at u(v_h) and the velocity gradient of v_h: the quantities
+    whose means and variances the Taylor-Green example of Section 5 follows.  s = ln(p/rho^gamma),
+    omega = curl V (a scalar in 2D), theta = div V, T = p / rho.  The velocity gradient comes from
+    V(v) = -v_{2..d+1} / v_m differentiated by the chain rule."""
+    from . import physics as ph
+    d, m, g = disc.d, disc.m, disc.phys.gamma
+    out = np.zeros((disc.mesh.n_elem, 8))
+    for e in range(disc.mesh.n_elem):
+        G = disc.geom(e)
+        ve = v[:, e * disc.Np:(e + 1) * disc.Np]              # (m, Np)
+        vq = disc.ref.phi @ ve.T                              # (nq, m)
+        gv = np.einsum("naj,ca->ncj", G.gphi, ve)              # (nq, m, d): d v_c / d x_j
+        rho, V, p = ph.prim_of_v(vq, g)
+        vm = vq[:, m - 1]
+        dV = -(gv[:, 1:d + 1, :] + V[:, :, None] * gv[:, None, m - 1, :]) / vm[:, None, None]   # [q, i, j]
+        if d == 2:
+            om2 = (dV[:, 1, 0] - dV[:, 0, 1]) ** 2
+        else:
+            om = np.stack([dV[:, 2, 1] - dV[:, 1, 2], dV[:, 0, 2] - dV[:, 2, 0], dV[:, 1, 0] - dV[:, 0, 1]], axis=1)
+            om2 = np.sum(om ** 2, axis=1)
+        th = np.trace(dV, axis1=1, axis2=2)
+        T = p / rho
+        cols = [rho * np.log(p / rho ** g), rho, 0.5 * rho * np.sum(V ** 2, axis=1), om2, th, th ** 2, T, T ** 2]
+        out[e] = [np.sum(G.W * c) for c in cols]
+    return out
+
+
 # ---- one step of Alexander's three-stage L-stable DIRK(3,3) (the time integration of
 # the paper's numerical examples, Section 5).  Stage i solves
 #   alpha (u(v_i) - u*_i, w) + s(v_i; w) = 0,   alpha = 1 / (a_ii dt),
