@@ -170,6 +170,14 @@ int hdg_l2_error(const hdg_plan *plan, int kind, const double *f, const double *
  * element integral of the generalized entropy H = -rho s of the entropy-variable section;
  * a baseline s0 enters as -s0 out[e][1].  Device pointers; out [E][2]. */
 int hdg_entropy_integral(const hdg_plan *plan, const double *v, double *out, void *stream);
+/* Element integrals of the flow statistics followed in the Taylor-Green example of
+ * Section 5, by the volume quadrature at the states u(v_h) of v [m][E*Np] and the
+ * velocity gradients of v_h (V = -w / v_m, w = the middle entropy variables):
+ *   out[e][0..7] = int_K (rho s, rho, rho |V|^2 / 2, |omega|^2, theta, theta^2, T, T^2),
+ * s = ln(p / rho^gamma), omega = curl V (the scalar dV_y/dx - dV_x/dy in 2D), theta = div V,
+ * T = p / rho (temperature up to the gas constant).  Means and variances follow by
+ * dividing by the domain volume.  Device pointers; out [E][8]. */
+int hdg_flow_statistics(const hdg_plan *plan, const double *v, double *out, void *stream);
 
 /* Bytes of device workspace the plan needs (tables + per-chunk scratch). */
 int hdg_plan_workspace_bytes(const hdg_plan *plan, size_t *bytes);

@@ -127,6 +127,7 @@ SIGNATURES = {
     "hdg_quad_coords": (I, [P, P, P]),
     "hdg_l2_error": (I, [P, I, P, P, P, P]),
     "hdg_entropy_integral": (I, [P, P, P, P]),
+    "hdg_flow_statistics": (I, [P, P, P, P]),
     "hdg_learn_nparams": (I, []),
     "hdg_learn_setup": (I, [P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),
     "hdg_learn_forward": (I, [P, P, P, P, P]),

@@ -416,6 +416,15 @@ extern "C" int hdg_entropy_integral(const hdg_plan *plan, const double *v, doubl
   return HDG_OK;
 }
 
+extern "C" int hdg_flow_statistics(const hdg_plan *plan, const double *v, double *out, void *stream) {
+  const Plan *P = checked(const_cast<hdg_plan *>(plan));
+  if (!P) return HDG_EINVAL;
+  if (!v || !out) return fail(HDG_EINVAL, "null argument");
+  hipError_t e = launch_flow_stats(P->dp, v, out, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "flow_statistics");
+  return HDG_OK;
+}
+
 extern "C" void hdg_plan_destroy(hdg_plan *plan) {
   Plan *P = reinterpret_cast<Plan *>(plan);
   if (!P) return;

@@ -220,6 +220,7 @@ hipError_t launch_quad_coords(const DevPlan &P, double *xq, hipStream_t s);
 hipError_t launch_l2_error(const DevPlan &P, int kind, const double *f, const double *ex, double *out,
                            hipStream_t s);
 hipError_t launch_drop_rows(const DevPlan &P, int e0, int ec, hipStream_t s);
+hipError_t launch_flow_stats(const DevPlan &P, const double *v, double *out, hipStream_t s);
 hipError_t launch_entropy(const DevPlan &P, const double *v, double *out, hipStream_t s);
 hipError_t launch_prepare_state(const DevPlan &P, int N, const double *prim, const double *grad,
                                 double *v, double *q, double *u, hipStream_t s);

@@ -191,7 +191,86 @@ __global__ __launch_bounds__(64) void k_entropy(DevPlan P, const double *__restr
   }
 }
 
+// Element integrals of the flow statistics of the Taylor-Green example (Section 5) at the
+// states u(v_h) and velocity gradients of v_h by the volume quadrature:
+//   out[e] = (rho s, rho, rho |V|^2 / 2, |omega|^2, theta, theta^2, T, T^2),
+// s = ln(p / rho^gamma), omega = curl V (scalar in 2D), theta = div V, T = p / rho (the
+// temperature up to the gas constant).  V = -w / v_m with w = v_2..v_{d+1}, so
+// dV_i = -(dw_i + V_i dv_m) / v_m.
+template <int D>
+__global__ __launch_bounds__(64) void k_flow_stats(DevPlan P, const double *__restrict__ v, double *out) {
+  constexpr int M = D + 2, NS = 8;
+  __shared__ double red[NS][64];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int Np = P.Np, Nq = P.Nq;
+  const size_t NN = (size_t)P.n_elem * Np;
+  double acc[NS];
+  for (int i = 0; i < NS; ++i) acc[i] = 0.0;
+  for (int q = tid; q < Nq; q += 64) {
+    const double *phi = P.phi + (size_t)q * Np;
+    const double *g = P.geo_vol + ((size_t)e * Nq + q) * (1 + D * D);
+    double val[M], gr[M][D];
+    for (int c = 0; c < M; ++c) {
+      double s = 0.0, dr[D];
+      for (int r = 0; r < D; ++r) dr[r] = 0.0;
+      const double *vc = v + (size_t)c * NN + (size_t)e * Np;
+      for (int a = 0; a < Np; ++a) {
+        const double va = vc[a];
+        s += phi[a] * va;
+        for (int r = 0; r < D; ++r) dr[r] += P.dphi[((size_t)r * Nq + q) * Np + a] * va;
+      }
+      val[c] = s;
+      for (int j = 0; j < D; ++j) {
+        double t = 0.0;
+        for (int r = 0; r < D; ++r) t += dr[r] * g[1 + r * D + j];
+        gr[c][j] = t;
+      }
+    }
+    const Prim<D, double> st = prim_of_v<D, double>(val, P.gamma);
+    const double vm = val[M - 1];
+    double dV[D][D];   // dV[i][j] = dV_i / dx_j
+    for (int i = 0; i < D; ++i)
+      for (int j = 0; j < D; ++j) dV[i][j] = -(gr[1 + i][j] + st.V[i] * gr[M - 1][j]) / vm;
+    double ke = 0.0, th = 0.0, om2 = 0.0;
+    for (int i = 0; i < D; ++i) {
+      ke += st.V[i] * st.V[i];
+      th += dV[i][i];
+    }
+    if constexpr (D == 2) {
+      const double w3 = dV[1][0] - dV[0][1];
+      om2 = w3 * w3;
+    } else {
+      const double w1 = dV[2][1] - dV[1][2], w2 = dV[0][2] - dV[2][0], w3 = dV[1][0] - dV[0][1];
+      om2 = w1 * w1 + w2 * w2 + w3 * w3;
+    }
+    const double W = g[0], T = st.p / st.rho;
+    acc[0] += W * st.rho * (log(st.p) - P.gamma * log(st.rho));
+    acc[1] += W * st.rho;
+    acc[2] += W * 0.5 * st.rho * ke;
+    acc[3] += W * om2;
+    acc[4] += W * th;
+    acc[5] += W * th * th;
+    acc[6] += W * T;
+    acc[7] += W * T * T;
+  }
+  for (int i = 0; i < NS; ++i) red[i][tid] = acc[i];
+  __syncthreads();
+  if (tid < NS) {
+    double s = 0.0;
+    for (int t = 0; t < 64; ++t) s += red[tid][t];
+    out[(size_t)e * NS + tid] = s;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_flow_stats(const DevPlan &P, const double *v, double *out, hipStream_t s) {
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_flow_stats<2>, dim3(P.n_elem), dim3(64), 0, s, P, v, out);
+  else
+    hipLaunchKernelGGL(k_flow_stats<3>, dim3(P.n_elem), dim3(64), 0, s, P, v, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_entropy(const DevPlan &P, const double *v, double *out, hipStream_t s) {
   if (P.dim == 2)

@@ -329,6 +329,13 @@ class Plan:
         check(self.lib.hdg_entropy_integral(self.h, _ptr(v), _ptr(out), _stream()), "hdg_entropy_integral")
         return out
 
+    def flow_statistics(self, v):
+        """Per-element integrals [E][8] of (rho s, rho, rho |V|^2 / 2, |omega|^2, theta,
+        theta^2, T, T^2) (hdg_flow_statistics)."""
+        out = self._empty(self.n_elem, 8)
+        check(self.lib.hdg_flow_statistics(self.h, _ptr(v), _ptr(out), _stream()), "hdg_flow_statistics")
+        return out
+
     def trace_rhs(self, g, r=None):
         if r is None:
             r = self._empty(self.m, self.n_trace)

@@ -77,9 +77,11 @@ def tgv_run(steps, dt=5.71e-2, p=2, n=16, scheme="edg", sigma="slf", mach=0.8, r
             atol=1e-12, lin_tol=1e-12, gamma=1.4, progress=False):
     """Inviscid Taylor-Green vortex of Section 5 (the periodic cube (-pi L, pi L)^3 in n^3
     hexahedra, degree p, M0 = 0.8, dt = 0.0571 L / V0, entropy-variable EDG by default;
-    the paper uses n = 32).  Recorded: the change of the mean thermodynamic entropy
-    (int rho s - int rho s at t = 0) / |Omega| and the mass drift, with the stages' Newton
-    iteration counts and convergence flags."""
+    the paper uses n = 32).  Recorded (hdg_flow_statistics): the change of the mean
+    thermodynamic entropy (int rho s - int rho s at t = 0) / |Omega|, the mass drift, the mean
+    kinetic energy, the mean-square vorticity <omega . omega>, the dilatation variance
+    <theta' theta'> and the temperature variance <T' T'> / T0^2 (T = p / rho, T0 = P0 / rho0),
+    with the stages' Newton and GMRES iteration counts and convergence flags."""
     import torch
 
     from workloads import meshes as M
@@ -101,11 +103,15 @@ def tgv_run(steps, dt=5.71e-2, p=2, n=16, scheme="edg", sigma="slf", mach=0.8, r
 
     v, vhat = state(xn), state(xt)
     vol = (2 * np.pi) ** 3
+    T0 = f.p0 / f.rho0
     S0, m0 = (float(a) for a in plan.entropy_integral(v).sum(0).cpu())
 
     def record(t, infos):
-        S, mass = (float(a) for a in plan.entropy_integral(v).sum(0).cpu())
+        st = plan.flow_statistics(v).sum(0).cpu().numpy() / vol
+        S, mass = st[0] * vol, st[1] * vol
         return {"t": t, "ds_mean": (S - S0) / vol, "mass_drift": mass / m0 - 1.0,
+                "kinetic_energy": float(st[2]), "vorticity_ms": float(st[3]),
+                "dilatation_var": float(st[5] - st[4] ** 2), "temperature_var": float((st[7] - st[6] ** 2) / T0 ** 2),
                 "newton": [i["iterations"] for i in infos], "gmres": [i["lin_iterations"] for i in infos],
                 "converged": all(i["converged"] for i in infos)}
 

@@ -2,7 +2,8 @@
 
 * hdg_entropy_integral and the v-norm error (hdg_l2_error kind 2) against the oracle's
   entropy_integral and l2_error_v on a perturbed vortex state (200 triangles, p = 4):
-  every element to 1e-12 relative.
+  every element to 1e-12 relative; hdg_flow_statistics against the oracle's flow_statistics
+  on a perturbed vortex (triangles) and Taylor-Green state (hexahedra), p = 2, to 1e-11.
 * The Shu vortex set-up (psi = 5, M = gamma^-1/2, 200 triangles, k = 4, dt = 0.05) for
   40 DIRK(3,3) steps (t = 2): every stage's Newton iteration converges, the mass stays
   constant to 1e-12 relative, the total thermodynamic entropy int rho s never decreases
@@ -57,6 +58,32 @@ def test_entropy_integral_and_v_error_match_oracle(torch):
     ev = float(torch.sqrt(plan.l2_error(dv, vq, "v").sum()))
     print("entropy", got.sum(0), "v error", ev, ref_ev, flush=True)
     assert abs(ev - ref_ev) <= 1e-12 * ref_ev
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_flow_statistics_match_oracle(torch, dim):
+    from paper_1808_05066_amd.hdg import Plan
+    from workloads import fields as F, meshes as M
+    gamma, p = 1.4, 2
+    if dim == 2:
+        f = F.ShuVortex(mach=0.5, L=0.1, gamma=gamma)
+        mesh, et, nfc = M.tri_square(6, 0.08, 2, periodic=True), "tri", 3
+    else:
+        f = F.TaylorGreen(mach=0.8, gamma=gamma)
+        mesh, et, nfc = M.hex_cube(3, 0.05, 4, periodic=True), "hex", 6
+    tmap, nt = M.trace_map(mesh, p, "hdg")
+    fbc = np.zeros((mesh.n_elem, nfc), dtype=np.int32)
+    disc = ohdg.Discretization(mesh, p, ohdg.Phys(gamma, 0.0, 0.72, 0.0, False), tmap, nt, fbc)
+    x = disc.node_coords()
+    prim = f.prim(x)
+    prim[0] *= 1.0 + 0.03 * np.sin(3 * x[0] + 1.0) * np.cos(2 * x[1])
+    v = ph.v_of_prim(prim[0], prim[1:dim + 1].T, prim[dim + 1], gamma).T.copy()
+    ref = newton.flow_statistics(disc, v)
+    plan = Plan(et, p, mesh.elem_xyz, tmap, nt, fbc, viscous=False, gamma=gamma)
+    got = plan.flow_statistics(torch.from_numpy(v).cuda()).cpu().numpy()
+    print("flow statistics", got.sum(0), flush=True)
+    bound = 1e-11 * np.abs(ref) + 1e-13 * np.abs(ref).max(axis=0)[None, :]
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
 
 
 def test_shu_vortex_entropy_history(torch):
