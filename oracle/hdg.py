@@ -68,6 +68,9 @@ class Phys:
     # stabilization matrix: "slf" (symmetric Lax-Friedrichs, the paper's examples), "s"
     # (symmetric variable |A_n| A0), both at v* = v_hat, or "mv" (mean value between v_hat and v)
     sigma: str = "slf"
+    # projection viscous numerical flux of Section 4: (Pi G(v_h, q_h)) . n with Pi the element L2
+    # projection onto the polynomial space of q_h (overrides ghat_interior)
+    ghat_proj: bool = False
 
 
 class Discretization:
@@ -157,6 +160,12 @@ class Discretization:
             qq = np.einsum("qa,pcja->pqcj", phi, qN)
             flux = flux + ph.flux_G(vq, qq, gam, ph_.mu, ph_.Pr)
         Rv = -np.einsum("q,pqcj,qaj->pca", W, flux, gphi)
+        if ph_.viscous and ph_.ghat_proj:
+            # nodal coefficients of the element L2 projection of G(v_h, q_h): M Gpi = (phi_a, G)_K
+            Gq = ph.flux_G(vq, qq, gam, ph_.mu, ph_.Pr)
+            Mk = phi.T @ (W[:, None] * phi)
+            rhs = np.einsum("q,qa,pqcj->apcj", W, phi, Gq)
+            Gpi = np.linalg.solve(Mk, rhs.reshape(Np, -1)).reshape(Np, P, m, d).transpose(1, 0, 2, 3)
         if ph_.alpha != 0.0:
             us = np.zeros((phi.shape[0], m)) if ustar_nodes is None else phi @ ustar_nodes.T
             Rv = Rv + ph_.alpha * np.einsum("q,pqc,qa->pca", W, ph.u_of_v(vq, gam) - us, phi)
@@ -172,8 +181,11 @@ class Discretization:
             nrm = F["n"]
             tf = ph.fhat(vhf, vf, nrm, gam, ph_.sigma)
             if ph_.viscous:
-                qf = np.einsum("qa,pcja->pqcj", F["phi"], qN)
-                tf = tf + ph.ghat(vf if ph_.ghat_interior else vhf, qf, nrm, gam, ph_.mu, ph_.Pr)
+                if ph_.ghat_proj:
+                    tf = tf + np.einsum("qa,pacj,qj->pqc", F["phi"], Gpi, nrm)
+                else:
+                    qf = np.einsum("qa,pcja->pqcj", F["phi"], qN)
+                    tf = tf + ph.ghat(vf if ph_.ghat_interior else vhf, qf, nrm, gam, ph_.mu, ph_.Pr)
                 Rq = Rq - np.einsum("q,pqc,qj,qa->pcja", F["W"], vhf, nrm, F["phi"])
             Rv = Rv + np.einsum("q,pqc,qa->pca", F["W"], tf, F["phi"])
             if self.face_bc[e, f] == 1:

@@ -436,3 +436,67 @@ def test_ringleb_errors_match_tables_3_to_5():
         assert ref / 1.4 < err < ref * 1.4, (scheme, err, ref)
     err = _ringleb_oracle_error(16, 1, "hdg")
     assert abs(err / tab["error"]["hdg"][0][1] - 1.0) < 0.05, err
+
+
+def _proj_case(seed, const_v):
+    """A 2x2 jittered periodic triangle mesh, p = 2, Navier-Stokes; v either one constant state or
+    a smooth field, q seeded random nodal values."""
+    mesh = M.tri_square(2, 0.1, seed, periodic=True)
+    tmap, nt = M.trace_map(mesh, 2, "hdg")
+    fbc = np.zeros((mesh.n_elem, 3), dtype=np.int32)
+    rng = np.random.default_rng(seed)
+    discs = {k: hdg.Discretization(mesh, 2, hdg.Phys(1.4, 0.05, 0.72, 0.0, True, k == "int", "slf", k == "proj"),
+                                   tmap, nt, fbc) for k in ("int", "proj")}
+    d0 = discs["int"]
+    x = d0.node_coords()
+    rho = np.ones(x.shape[1]) if const_v else 1.0 + 0.2 * np.sin(2 * np.pi * x[0]) * np.cos(2 * np.pi * x[1])
+    V = np.stack([0.3 + (0 if const_v else 0.2) * np.cos(2 * np.pi * x[1]), -0.2 + 0 * x[0]], axis=1)
+    v = ph.v_of_prim(rho, V, 1.0 + 0 * x[0], 1.4).T.copy()
+    q = rng.standard_normal((8, x.shape[1]))
+    vh = rng.standard_normal((4, nt)) * 0.01 + v[:, :1]
+    return discs, v, q, vh
+
+
+def test_projection_viscous_flux_reduces_to_interior_flux():
+    """With one constant state v_h, G(v_h, q_h) is linear in q_h with constant coefficients, so it
+    lies in the polynomial space of q_h and its projection is itself: the projection viscous flux
+    (Section 4) equals the interior flux G(v_h, q_h).n, element residuals to 1e-13."""
+    discs, v, q, vh = _proj_case(3, True)
+    for e in range(discs["int"].mesh.n_elem):
+        out = []
+        for k in ("int", "proj"):
+            dk = discs[k]
+            xl, lam = dk.pack_local(v, q, e), dk.gather_trace(vh, e)
+            out.append(dk.element_residual(e, xl[None], lam[None]))
+        for a, b in zip(*out):
+            assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+
+
+def test_projection_viscous_flux_against_least_squares_projection():
+    """With a varying v_h the projection flux differs from the interior one by
+    <(Pi G - G) . n, phi_i> on the element boundary; Pi is computed here independently as the
+    weighted least-squares fit of G(v_h, q_h) at the volume quadrature points (numpy lstsq), and
+    the face integrals with the face quadrature: R_v(proj) - R_v(int) matches to 1e-11."""
+    discs, v, q, vh = _proj_case(5, False)
+    di, dp = discs["int"], discs["proj"]
+    Np, m, d = di.Np, di.m, di.d
+    for e in range(di.mesh.n_elem):
+        xl, lam = di.pack_local(v, q, e), di.gather_trace(vh, e)
+        Ri = di.element_residual(e, xl[None], lam[None])[0][0][:m * Np].reshape(m, Np)
+        Rp = dp.element_residual(e, xl[None], lam[None])[0][0][:m * Np].reshape(m, Np)
+        G = di.geom(e)
+        sl = slice(e * Np, (e + 1) * Np)
+        vq = di.ref.phi @ v[:, sl].T
+        qq = np.einsum("qa,cja->qcj", di.ref.phi, q[:, sl].reshape(m, d, Np))
+        Gq = ph.flux_G(vq, qq, 1.4, 0.05, 0.72).reshape(len(G.W), m * d)
+        sw = np.sqrt(G.W)[:, None]
+        coef = np.linalg.lstsq(sw * di.ref.phi, sw * Gq, rcond=None)[0]          # (Np, m d)
+        diff = np.zeros((m, Np))
+        for F in G.faces:
+            vf = F["phi"] @ v[:, sl].T
+            qf = np.einsum("qa,cja->qcj", F["phi"], q[:, sl].reshape(m, d, Np))
+            Gf = ph.flux_G(vf, qf, 1.4, 0.05, 0.72)
+            Pf = (F["phi"] @ coef).reshape(-1, m, d)
+            diff += np.einsum("q,qcj,qj,qa->ca", F["W"], Pf - Gf, F["n"], F["phi"])
+        assert np.abs(diff).max() > 1e-4
+        assert np.abs((Rp - Ri) - diff).max() <= 1e-11 * np.abs(diff).max()
