@@ -95,7 +95,7 @@ typedef struct {
 } hdg_mesh;
 
 enum { HDG_FLAG_SPLIT_DENSE = 1, HDG_FLAG_NARROW_BLOCK = 2, HDG_FLAG_ELIMINATE_Q = 4, HDG_FLAG_GHAT_INTERIOR = 8,
-       HDG_FLAG_SIGMA_S = 16, HDG_FLAG_SIGMA_MV = 32 };
+       HDG_FLAG_SIGMA_S = 16, HDG_FLAG_SIGMA_MV = 32, HDG_FLAG_GHAT_PROJ = 64 };
 
 typedef struct {
   int chunk_elems;         /* elements per internal wave (0: all) */
@@ -127,7 +127,14 @@ typedef struct {
                               Section 4 on the straight path between vhat and v in
                               entropy variables (its two integrals combined into one
                               integral of sigma_S over the path, 4-point Gauss-Legendre);
-                              takes precedence over HDG_FLAG_SIGMA_S. */
+                              takes precedence over HDG_FLAG_SIGMA_S.
+                              HDG_FLAG_GHAT_PROJ: the projection viscous numerical flux
+                              of Section 4, (Pi G(v_h, q_h)).n on every face with Pi the
+                              element L2 projection onto the space of q_h (volume
+                              quadrature); Navier-Stokes only, element blocks and
+                              residuals (not the matrix-free Jacobian of the FP32 path,
+                              which refuses it); takes precedence over
+                              HDG_FLAG_GHAT_INTERIOR. */
 } hdg_opts;
 
 typedef struct {

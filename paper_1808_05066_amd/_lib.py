@@ -22,6 +22,7 @@ FLAG_ELIMINATE_Q = 4
 FLAG_GHAT_INTERIOR = 8
 FLAG_SIGMA_S = 16
 FLAG_SIGMA_MV = 32
+FLAG_GHAT_PROJ = 64
 
 
 class hdg_phys(ctypes.Structure):

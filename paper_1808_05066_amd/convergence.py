@@ -15,7 +15,7 @@ from __future__ import annotations
 import numpy as np
 
 
-def couette_run(n, p, scheme="hdg", tol=1e-9, atol=1e-10, maxit=20, lin_tol=1e-13):
+def couette_run(n, p, scheme="hdg", tol=1e-9, atol=1e-10, maxit=20, lin_tol=1e-13, ghat_proj=False):
     """Solve the Couette problem on an n x n mesh of order p; returns the error dict."""
     import torch
 
@@ -28,7 +28,7 @@ def couette_run(n, p, scheme="hdg", tol=1e-9, atol=1e-10, maxit=20, lin_tol=1e-1
     mesh = M.tri_square(n, 0.0, 0, periodic=False)
     tmap, nt = M.trace_map(mesh, p, scheme)
     plan = Plan(mesh.etype, p, mesh.elem_xyz, tmap, nt, mesh.boundary.astype(np.int32), viscous=True,
-                gamma=f.gamma, mu=f.mu, Pr=f.Pr, alpha=0.0)
+                gamma=f.gamma, mu=f.mu, Pr=f.Pr, alpha=0.0, ghat_proj=ghat_proj)
     dev = plan.device
     xn, xt = (t.cpu().numpy() for t in plan.node_coords())
 

@@ -184,7 +184,10 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
   const double lam = dabs(vn) + sqrt(gam * sh.p / sh.rho);
   // trace-state directions: d(f_hat + g_hat)/d v_hat and the flux value
   // (with ghat_v the viscous numerical flux does not depend on v_hat: it is added below)
-  const bool gh_trace = VISC && !P.ghat_v;
+  // with the projection viscous flux the face points carry no viscous flux: it is added from
+  // the volume points by the projection kernels
+  const bool gface = VISC && !P.ghat_proj;
+  const bool gh_trace = gface && !P.ghat_v;
   for (int t = 0; t < M; ++t) {
     Dual vd[M], o[M];
     for (int c = 0; c < M; ++c) vd[c] = Dual{vh[c], c == t ? 1.0 : 0.0};
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
     if (t == 0)
       for (int c = 0; c < M; ++c) out[L.fFf + c] = W * o[c].v;
   }
-  if (VISC && P.ghat_v) {
+  if (gface && P.ghat_v) {
     double G[M * D];
     flux_G<D, double, double>(sv, qq, gam, P.mu, P.Pr, G);
     for (int c = 0; c < M; ++c) {
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
       for (int j = 0; j < D; ++j) an += F[c * D + j].d * n[j];
       out[L.fFv + c * M + t] = W * 0.5 * (an + sig[c * M + t]);
     }
-    if (VISC && P.ghat_v) {
+    if (gface && P.ghat_v) {
       // d g_hat / d v with g_hat = G(v, q).n
       Dual G[M * D];
       flux_G<D, Dual, double>(s, qq, gam, P.mu, P.Pr, G);
@@ -241,7 +244,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
     // respect to v_hat and to v in full (the values above are replaced)
     double gval[M];
     for (int c = 0; c < M; ++c) gval[c] = 0.0;
-    if (VISC) {
+    if (gface) {
       double G[M * D];
       flux_G<D, double, double>(P.ghat_v ? sv : sh, qq, gam, P.mu, P.Pr, G);
       for (int c = 0; c < M; ++c)
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
       fhat_mv<D, Dual>(a, b, n, gam, o);
       double gd[M];
       for (int c = 0; c < M; ++c) gd[c] = 0.0;
-      if (VISC && !P.ghat_v) {
+      if (gface && !P.ghat_v) {
         Dual G[M * D];
         flux_G<D, Dual, double>(prim_of_v<D, Dual>(a, gam), qq, gam, P.mu, P.Pr, G);
         for (int c = 0; c < M; ++c)
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
       }
       fhat_mv<D, Dual>(a, b, n, gam, o);
       for (int c = 0; c < M; ++c) gd[c] = 0.0;
-      if (VISC && P.ghat_v) {
+      if (gface && P.ghat_v) {
         Dual G[M * D];
         flux_G<D, Dual, double>(prim_of_v<D, Dual>(b, gam), qq, gam, P.mu, P.Pr, G);
         for (int c = 0; c < M; ++c)
@@ -285,10 +288,11 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
     for (int si = 0; si < M * D; ++si) {
       double es[M * D], G[M * D];
       for (int i = 0; i < M * D; ++i) es[i] = (i == si) ? 1.0 : 0.0;
-      flux_G<D, double, double>(P.ghat_v ? sv : sh, es, gam, P.mu, P.Pr, G);
+      if (gface) flux_G<D, double, double>(P.ghat_v ? sv : sh, es, gam, P.mu, P.Pr, G);
       for (int c = 0; c < M; ++c) {
         double a = 0.0;
-        for (int j = 0; j < D; ++j) a += G[c * D + j] * n[j];
+        if (gface)
+          for (int j = 0; j < D; ++j) a += G[c * D + j] * n[j];
         out[L.fFq + c * (M * D) + si] = W * a;
       }
     }

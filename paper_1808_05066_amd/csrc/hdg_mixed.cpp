@@ -113,6 +113,7 @@ extern "C" int hdg_jacobian_apply(hdg_plan *plan, const double *v, const double 
   Plan *P = checked(plan);
   if (!P) return HDG_EINVAL;
   if (!dx || !dlam || !y_loc || !y_tr) return fail(HDG_EINVAL, "dx, dlam, y_loc and y_tr are required");
+  if (P->dp.ghat_proj) return fail(HDG_EUNSUPPORTED, "the matrix-free Jacobian has no projection viscous flux");
   const bool reuse = reuse_points && P->chunk >= P->n_elem;
   if (!reuse) {
     int rc = check_inputs(P, v, q, vhat, ustar, status);
@@ -155,6 +156,7 @@ extern "C" int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q
   if (!S || !Y || !factors || !Rloc || !Rtr || !dx || !dlam || !work || !opts || !info || !status)
     return fail(HDG_EINVAL, "null argument");
   if (opts->max_outer < 1 || !(opts->tol > 0.0)) return fail(HDG_EINVAL, "bad refinement options");
+  if (P->dp.ghat_proj) return fail(HDG_EUNSUPPORTED, "the matrix-free Jacobian has no projection viscous flux");
   hdg_solve_opts go = opts->gmres;
   go.s_dtype = HDG_FP32;
   size_t sb = 0;

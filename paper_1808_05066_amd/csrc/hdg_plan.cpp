@@ -305,6 +305,13 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   D.src = nullptr;
   D.row_drop = nullptr;
   D.ghat_v = (opts && (opts->flags & HDG_FLAG_GHAT_INTERIOR)) ? 1 : 0;
+  D.ghat_proj = (opts && (opts->flags & HDG_FLAG_GHAT_PROJ)) ? 1 : 0;
+  D.gp = D.gz = nullptr;
+  if (D.ghat_proj && (!D.viscous || gproj_lift_lds(D) > 64 * 1024)) {
+    delete P;
+    return fail(D.viscous ? HDG_EUNSUPPORTED : HDG_EINVAL,
+                "projection viscous flux: Navier-Stokes only, element mass inverse and lift within 64 KB of LDS");
+  }
   D.sigma_s = (opts && (opts->flags & HDG_FLAG_SIGMA_MV)) ? 2 : (opts && (opts->flags & HDG_FLAG_SIGMA_S)) ? 1 : 0;
   D.a_qmin = 0;
   D.condense_launches = 2;
@@ -480,7 +487,7 @@ namespace {
 struct Layout {
   size_t phi, dphi, fphi, fnodes, node_face, geo_vol, geo_face, tmap, face_bc, node_x, trace_x;
   size_t bj_nodes, bj_ce, bj_cf, bj_loc, bj_tpos, uinfo, row_drop, tables_end;
-  size_t pv, pf, A, X, C, D, Rt, ipiv, inv, mg;
+  size_t pv, pf, A, X, C, D, Rt, ipiv, inv, mg, gp, gz;
   size_t rA, rX, rC, rD, rRt, rMH, rYv, rzv, ripiv, rinv, total;
 };
 
@@ -524,6 +531,11 @@ Layout layout(const Plan *P) {
   l.ipiv = take(ch * (size_t)D.n_pad * 4);
   l.inv = take(P->fused ? ch * condense_inv_doubles(D.n_pad) * 8 : 0);
   l.mg = take(P->uinfo.empty() ? 0 : ch * (size_t)(1 + D.dim) * D.Np * D.Np * 8);
+  {
+    const size_t MD = (size_t)D.m * D.dim;
+    l.gp = take(D.ghat_proj ? ch * D.Nq * (MD + MD * D.m + MD * MD) * 8 : 0);
+    l.gz = take(D.ghat_proj ? ch * (size_t)D.nf * D.dim * D.Nfp * D.Nq * 8 : 0);
+  }
   if (P->qelim) {
     const size_t nr = P->qa.nr_pad, nv = (size_t)D.m * D.Np;
     l.rA = take(ch * nr * nr * 8);
@@ -646,6 +658,8 @@ extern "C" int hdg_plan_bind_workspace(hdg_plan *plan, void *dev, size_t bytes, 
   D.ipiv = reinterpret_cast<int *>(base + l.ipiv);
   D.inv = reinterpret_cast<double *>(base + l.inv);
   D.mg = P->uinfo.empty() ? nullptr : reinterpret_cast<double *>(base + l.mg);
+  D.gp = D.ghat_proj ? reinterpret_cast<double *>(base + l.gp) : nullptr;
+  D.gz = D.ghat_proj ? reinterpret_cast<double *>(base + l.gz) : nullptr;
   D.uinfo = P->uinfo.empty() ? nullptr : reinterpret_cast<const int *>(base + l.uinfo);
   D.row_drop = P->row_drop.empty() ? nullptr : reinterpret_cast<const int *>(base + l.row_drop);
   if (P->qelim) {
@@ -731,13 +745,15 @@ int run_front(Plan *P, const double *v, const double *q, const double *vhat, con
   const bool one_chunk = P->chunk >= P->n_elem;
   P->dp.zero_xcd = (one_chunk && P->xcd_clean) ? 0 : 1;
   if (!e) e = P->contract_mfma ? launch_contract_mfma(P->dp, e0, ec, s) : launch_contract(P->dp, e0, ec, s);
+  if (!e && P->dp.ghat_proj) e = launch_gproj(P->dp, e0, ec, v, q, s);
   if (!e && P->dp.row_drop) e = launch_drop_rows(P->dp, e0, ec, s);
   if (!e) e = phase_end(P, PH_CONTRACT, s);
   if (e) {
     P->xcd_clean = false;
     return hip_fail(e, "assemble");
   }
-  P->xcd_clean = one_chunk;
+  // the projection terms fill entries of C outside the contraction's pattern: clear every call
+  P->xcd_clean = one_chunk && !P->dp.ghat_proj;
   return HDG_OK;
 }
 

@@ -25,6 +25,7 @@ struct DevPlan {
   int zero_xcd;            // 1: the contraction clears X, C and D first (0: they hold the zeros already)
   int a_qmin;              // 1: of the q rows of A only M and G_j of the first component are formed
   int ghat_v;              // 1: viscous numerical flux G(v, q).n with the element's v (else G(v_hat, q).n)
+  int ghat_proj;           // 1: projection viscous numerical flux (Pi G(v, q)).n, added by the projection kernels
   int sigma_s;             // stabilization: 0 sigma_SLF = lambda_max A0, 1 sigma_S = |A_n| A0 (both at v_hat),
                            // 2 sigma_MV (mean value between v_hat and v)
   int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
@@ -59,6 +60,10 @@ struct DevPlan {
   // the condensation forms the q rows and the padding of A from these instead of reading them
   double *mg;              // [chunk][1 + dim][Np][Np]: G_j[a][b] (j < dim), M[a][b] (j = dim)
   const int *uinfo;        // [n_pad]: node | direction << 8 | component << 12 of each local unknown
+  // projection viscous flux scratch (null unless ghat_proj): W (G, dG/dv, dG/dq) at the volume
+  // points [chunk][Nq][MD + MD M + MD MD], and the face lift Z [chunk][nf][dim][Nfp][Nq]
+  double *gp;
+  double *gz;
   // block-Jacobi structure of the condensed operator
   int bj_face;             // 1: one block per mesh face (HDG), 0: one m x m block per trace node
   int bj_nblk, bj_bs;
@@ -221,6 +226,8 @@ hipError_t launch_l2_error(const DevPlan &P, int kind, const double *f, const do
                            hipStream_t s);
 hipError_t launch_drop_rows(const DevPlan &P, int e0, int ec, hipStream_t s);
 hipError_t launch_flow_stats(const DevPlan &P, const double *v, double *out, hipStream_t s);
+hipError_t launch_gproj(const DevPlan &P, int e0, int ec, const double *v, const double *q, hipStream_t s);
+size_t gproj_lift_lds(const DevPlan &P);
 hipError_t launch_entropy(const DevPlan &P, const double *v, double *out, hipStream_t s);
 hipError_t launch_prepare_state(const DevPlan &P, int N, const double *prim, const double *grad,
                                 double *v, double *q, double *u, hipStream_t s);

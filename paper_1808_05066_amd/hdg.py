@@ -36,7 +36,7 @@ class Plan:
 
     def __init__(self, etype, order, elem_xyz, trace_map, n_trace, face_bc=None, *, viscous=False,
                  gamma=1.4, mu=0.0, Pr=0.72, alpha=0.0, chunk_elems=0, split_dense=False, narrow_block=False,
-                 eliminate_q=False, ghat_interior=False, sigma="slf",
+                 eliminate_q=False, ghat_interior=False, sigma="slf", ghat_proj=False,
                  device="cuda"):
         torch = _torch()
         self.lib = _lib.load()
@@ -50,7 +50,8 @@ class Plan:
         phys = _lib.hdg_phys(int(bool(viscous)), float(gamma), float(mu), float(Pr), float(alpha))
         flags = ((_lib.FLAG_SPLIT_DENSE if split_dense else 0) | (_lib.FLAG_NARROW_BLOCK if narrow_block else 0) |
                  (_lib.FLAG_ELIMINATE_Q if eliminate_q else 0) | (_lib.FLAG_GHAT_INTERIOR if ghat_interior else 0) |
-                 (_lib.FLAG_SIGMA_S if sigma == "s" else 0) | (_lib.FLAG_SIGMA_MV if sigma == "mv" else 0))
+                 (_lib.FLAG_SIGMA_S if sigma == "s" else 0) | (_lib.FLAG_SIGMA_MV if sigma == "mv" else 0) |
+                 (_lib.FLAG_GHAT_PROJ if ghat_proj else 0))
         opts = _lib.hdg_opts(int(chunk_elems), 0, flags)
         h = ctypes.c_void_p()
         check(self.lib.hdg_plan_create(ctypes.byref(h), ctypes.byref(mesh), ctypes.byref(phys),

@@ -6,9 +6,9 @@ from oracle import state as ostate
 from workloads import configs as C
 
 
-def oracle_disc(wl, nquad=None, ghat_interior=False, sigma="slf"):
+def oracle_disc(wl, nquad=None, ghat_interior=False, sigma="slf", ghat_proj=False):
     return ohdg.Discretization(wl.mesh, wl.p, ohdg.Phys(wl.gamma, wl.mu, wl.Pr, wl.alpha, wl.viscous,
-                                                        ghat_interior, sigma),
+                                                        ghat_interior, sigma, ghat_proj),
                                wl.tmap, wl.n_trace, wl.face_bc, nquad)
 
 
@@ -18,12 +18,12 @@ def oracle_case(wl):
 
 
 def gpu_plan(wl, chunk_elems=0, split_dense=False, narrow_block=False, eliminate_q=False, ghat_interior=False,
-             sigma="slf"):
+             sigma="slf", ghat_proj=False):
     from paper_1808_05066_amd.hdg import Plan
     return Plan(wl.mesh.etype, wl.p, wl.mesh.elem_xyz, wl.tmap, wl.n_trace, wl.face_bc, viscous=wl.viscous,
                 gamma=wl.gamma, mu=wl.mu, Pr=wl.Pr, alpha=wl.alpha, chunk_elems=chunk_elems,
                 split_dense=split_dense, narrow_block=narrow_block, eliminate_q=eliminate_q,
-                ghat_interior=ghat_interior, sigma=sigma)
+                ghat_interior=ghat_interior, sigma=sigma, ghat_proj=ghat_proj)
 
 
 def smooth_periodic_case(dt, n=2, p=2, mu=0.02, Pr=0.72, gamma=1.4):

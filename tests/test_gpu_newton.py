@@ -71,3 +71,15 @@ def test_newton_rejects_fp32_operator(torch):
     import ctypes
     nb = ctypes.c_size_t()
     assert plan.lib.hdg_newton_workspace_bytes(plan.h, ctypes.byref(opts), ctypes.byref(nb)) == _lib.HDG_EINVAL
+
+
+def test_newton_with_projection_viscous_flux(torch):
+    """Steady Newton iteration with the projection viscous flux (Section 4) on the Couette problem
+    (4 x 4 triangles, p = 2): quadratic convergence from the interpolated exact state, and the
+    momentum error at the level of the default flux's (within 2x)."""
+    from paper_1808_05066_amd.convergence import couette_run
+    r0 = couette_run(4, 2)
+    rp = couette_run(4, 2, ghat_proj=True)
+    print("default", r0, "projection", rp, flush=True)
+    assert rp["converged"] == 1 and rp["newton_iterations"] <= 6
+    assert rp["momentum"] <= 2.0 * r0["momentum"] and rp["rho"] <= 2.0 * r0["rho"]

@@ -269,6 +269,40 @@ def test_interior_viscous_flux_matches_oracle(torch, name):
     assert rel_err_per_elem(np.stack([b["C"] for b in blocks]), np.stack([b["C"] for b in base])) > 1e-6
 
 
+@pytest.mark.parametrize("eliminate_q", [False, True])
+@pytest.mark.parametrize("name", ["ns2d_tri_p2", "ns3d_hex_p1"])
+def test_projection_viscous_flux_matches_oracle(torch, name, eliminate_q):
+    """HDG_FLAG_GHAT_PROJ: projection viscous flux (Pi G(v_h, q_h)).n of Section 4 (added from the
+    volume points after the contraction).  Blocks, residuals and condensed outputs against the
+    oracle with the same flux, also through the q-eliminating condensation; the blocks must
+    differ from the default flux's."""
+    wl = SMALL_CASES[name]()
+    disc = oracle_disc(wl, ghat_proj=True)
+    inp = ostate.oracle_inputs(wl, disc)
+    blocks = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"],
+                                    keep_blocks=True)
+    plan = gpu_plan(wl, ghat_proj=True, eliminate_q=eliminate_q)
+    d = to_dev(inp)
+    out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    errs = {}
+    for rep in range(2):   # the second call runs on the workspace the first one left
+        cond = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], residuals=True)
+        torch.cuda.synchronize()
+        errs["S%d" % rep] = rel_err_per_elem(cond["S"].cpu().numpy(), colmajor([b["S"] for b in blocks]))
+        errs["Y%d" % rep] = rel_err_per_elem(cond["Y"].cpu().numpy(), colmajor([b["Y"] for b in blocks]))
+        errs["g%d" % rep] = rel_err_per_elem(cond["g"].cpu().numpy(), np.stack([b["g"] for b in blocks]))
+    errs["R_loc"] = rloc_err(disc, inp, out["R_loc"].cpu().numpy(), np.stack([b["R_loc"] for b in blocks]))
+    errs["R_tr"] = rel_err_per_elem(out["R_tr"].cpu().numpy(), np.stack([b["R_tr"] for b in blocks]))
+    for key in ("A", "B", "C", "D"):
+        errs[key] = rel_err_per_elem(out[key].cpu().numpy(), colmajor([b[key] for b in blocks]))
+    print(name, eliminate_q, errs, flush=True)
+    for key, err in errs.items():
+        assert err <= TOL, (key, err)
+    _, _, _, base = _case(name)
+    # (4.6e-7 on the nearly uniform hexahedron state, whose G is close to its projection)
+    assert rel_err_per_elem(np.stack([b["A"] for b in blocks]), np.stack([b["A"] for b in base])) > 1e-8
+
+
 @pytest.mark.parametrize("sigma", ["s", "mv"])
 @pytest.mark.parametrize("name", ["euler2d_tri_p2", "ns3d_hex_p1", "euler3d_hex_p2"])
 def test_symmetric_variable_stabilization_matches_oracle(torch, name, sigma):
