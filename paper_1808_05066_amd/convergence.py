@@ -53,14 +53,15 @@ def couette_run(n, p, scheme="hdg", tol=1e-9, atol=1e-10, maxit=20, lin_tol=1e-1
             "q": float(np.sqrt(np.sum(eq ** 2)))}
 
 
-def couette_table(ns=(4, 8, 16), ps=(1, 2), scheme="hdg"):
+def couette_table(ns=(4, 8, 16), ps=(1, 2), scheme="hdg", ghat_proj=False):
     """Errors and rates for every (p, n); rates against the next finer mesh."""
     rows = []
     for p in ps:
         prev = None
         for n in ns:
-            r = couette_run(n, p, scheme)
+            r = couette_run(n, p, scheme, ghat_proj=ghat_proj)
             r["scheme"] = scheme
+            r["ghat_proj"] = ghat_proj
             if prev is not None:
                 for key in ("rho", "momentum", "rhoE", "q"):
                     r["rate_" + key] = float(np.log2(prev[key] / r[key]))
@@ -126,6 +127,7 @@ def main(argv=None):
     ap.add_argument("--ns", default=None, help="comma-separated n (default 8,16,32,64 / 4,8,16)")
     ap.add_argument("--ps", default="1,2,3,4")
     ap.add_argument("--schemes", default="hdg,iedg,edg")
+    ap.add_argument("--ghat-proj", action="store_true", help="couette: projection viscous flux")
     a = ap.parse_args(argv)
     ps = tuple(int(x) for x in a.ps.split(","))
     if a.problem == "ringleb":
@@ -136,7 +138,7 @@ def main(argv=None):
     else:
         ns = tuple(int(x) for x in (a.ns or "4,8,16").split(","))
         for scheme in a.schemes.split(","):
-            for r in couette_table(ns, ps, scheme):
+            for r in couette_table(ns, ps, scheme, a.ghat_proj):
                 print(json.dumps(r), flush=True)
 
 
