@@ -15,6 +15,9 @@ namespace {
 
 constexpr int BLK = 256;
 
+// one row of S_K per thread in a single pass: whole waves covering the k rows (at most 1024)
+inline int matvec_threads(int k) { return k >= 1024 ? 1024 : ((k + 63) / 64) * 64; }
+
 // gather the element trace vector (k) of a [m][n_trace] field into LDS
 __device__ inline void gather_trace(const DevPlan &P, int e, const double *x, double *xl) {
   const int Nfp = P.Nfp, M = P.m, nf = P.nf;
@@ -64,8 +67,8 @@ __global__ __launch_bounds__(BLK) void k_backsolve_local(DevPlan P, const T *__r
 }
 
 template <typename T>
-__global__ __launch_bounds__(BLK) void k_trace_matvec(DevPlan P, const T *__restrict__ S,
-                                                       const double *__restrict__ x, double *y) {
+__global__ __launch_bounds__(1024) void k_trace_matvec(DevPlan P, const T *__restrict__ S,
+                                                        const double *__restrict__ x, double *y) {
   extern __shared__ double xl[];
   const int e = blockIdx.x;
   const int k = P.k, Nfp = P.Nfp, M = P.m, nf = P.nf;
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(BLK) void k_trace_matvec(DevPlan P, const T *__rest
   __syncthreads();
   const T *Se = S + (size_t)e * k * k;
   const int *tm = P.tmap + (size_t)e * nf * Nfp;
-  for (int row = threadIdx.x; row < k; row += BLK) {
+  for (int row = threadIdx.x; row < k; row += blockDim.x) {
     double acc = 0.0;
     for (int col = 0; col < k; ++col) acc += (double)Se[(size_t)col * k + row] * xl[col];
     const int b = row % Nfp, c = (row / Nfp) % M, f = row / (Nfp * M);
@@ -149,14 +152,16 @@ hipError_t launch_backsolve(const DevPlan &P, const double *Y, const double *z, 
 hipError_t launch_trace_matvec(const DevPlan &P, const double *S, const double *x, double *y, hipStream_t s) {
   hipError_t e = launch_fill_double(y, (size_t)P.m * P.n_trace, 0.0, s);
   if (e) return e;
-  hipLaunchKernelGGL(k_trace_matvec<double>, dim3(P.n_elem), dim3(BLK), P.k * sizeof(double), s, P, S, x, y);
+  hipLaunchKernelGGL(k_trace_matvec<double>, dim3(P.n_elem), dim3(matvec_threads(P.k)), P.k * sizeof(double), s, P, S,
+                     x, y);
   return hipGetLastError();
 }
 
 hipError_t launch_trace_matvec_f32(const DevPlan &P, const float *S, const double *x, double *y, hipStream_t s) {
   hipError_t e = launch_fill_double(y, (size_t)P.m * P.n_trace, 0.0, s);
   if (e) return e;
-  hipLaunchKernelGGL(k_trace_matvec<float>, dim3(P.n_elem), dim3(BLK), P.k * sizeof(double), s, P, S, x, y);
+  hipLaunchKernelGGL(k_trace_matvec<float>, dim3(P.n_elem), dim3(matvec_threads(P.k)), P.k * sizeof(double), s, P, S,
+                     x, y);
   return hipGetLastError();
 }
 
