@@ -15,7 +15,7 @@ namespace {
 
 constexpr int BLK = 256;
 
-// one row of S_K per thread in a single pass: whole waves covering the k rows (at most 1024)
+// one row per thread in a single pass: whole waves covering the rows (at most 1024; more rows loop)
 inline int matvec_threads(int k) { return k >= 1024 ? 1024 : ((k + 63) / 64) * 64; }
 
 // gather the element trace vector (k) of a [m][n_trace] field into LDS
@@ -28,7 +28,7 @@ __device__ inline void gather_trace(const DevPlan &P, int e, const double *x, do
   }
 }
 
-__global__ __launch_bounds__(BLK) void k_backsolve(DevPlan P, const double *__restrict__ Y,
+__global__ __launch_bounds__(1024) void k_backsolve(DevPlan P, const double *__restrict__ Y,
                                                     const double *__restrict__ z,
                                                     const double *__restrict__ dvhat, double *dv, double *dq) {
   extern __shared__ double xl[];
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(BLK) void k_backsolve(DevPlan P, const double *__re
   __syncthreads();
   const double *Ye = Y + (size_t)e * n * k;
   const size_t NN = (size_t)P.n_elem * Np;
-  for (int row = threadIdx.x; row < n; row += BLK) {
+  for (int row = threadIdx.x; row < n; row += blockDim.x) {
     double acc = -z[(size_t)e * n + row];
     for (int col = 0; col < k; ++col) acc -= Ye[(size_t)col * n + row] * xl[col];
     const int a = row % Np, cs = row / Np;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(BLK) void k_backsolve(DevPlan P, const double *__re
 // out[e] = a[e] - Y_e P_e dlambda on element-local vectors [E][n] (refinement
 // loop of the mixed-precision path; Y in FP64 or FP32, arithmetic in FP64).
 template <typename T>
-__global__ __launch_bounds__(BLK) void k_backsolve_local(DevPlan P, const T *__restrict__ Y,
+__global__ __launch_bounds__(1024) void k_backsolve_local(DevPlan P, const T *__restrict__ Y,
                                                           const double *__restrict__ a,
                                                           const double *__restrict__ dvhat, double *out) {
   extern __shared__ double xl[];
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(BLK) void k_backsolve_local(DevPlan P, const T *__r
   gather_trace(P, e, dvhat, xl);
   __syncthreads();
   const T *Ye = Y + (size_t)e * n * k;
-  for (int row = threadIdx.x; row < n; row += BLK) {
+  for (int row = threadIdx.x; row < n; row += blockDim.x) {
     double acc = a[(size_t)e * n + row];
     for (int col = 0; col < k; ++col) acc -= (double)Ye[(size_t)col * n + row] * xl[col];
     out[(size_t)e * n + row] = acc;
@@ -145,7 +145,8 @@ __global__ void k_prepare(int N, double gam, const double *__restrict__ prim, co
 
 hipError_t launch_backsolve(const DevPlan &P, const double *Y, const double *z, const double *dvhat, double *dv,
                             double *dq, hipStream_t s) {
-  hipLaunchKernelGGL(k_backsolve, dim3(P.n_elem), dim3(BLK), P.k * sizeof(double), s, P, Y, z, dvhat, dv, dq);
+  hipLaunchKernelGGL(k_backsolve, dim3(P.n_elem), dim3(matvec_threads(P.n)), P.k * sizeof(double), s, P, Y, z, dvhat,
+                     dv, dq);
   return hipGetLastError();
 }
 
@@ -167,7 +168,8 @@ hipError_t launch_trace_matvec_f32(const DevPlan &P, const float *S, const doubl
 
 hipError_t launch_backsolve_local_f32(const DevPlan &P, const float *Y, const double *a, const double *dvhat,
                                       double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_backsolve_local<float>, dim3(P.n_elem), dim3(BLK), P.k * sizeof(double), s, P, Y, a, dvhat,
+  hipLaunchKernelGGL(k_backsolve_local<float>, dim3(P.n_elem), dim3(matvec_threads(P.n)), P.k * sizeof(double), s, P,
+                     Y, a, dvhat,
                      out);
   return hipGetLastError();
 }
