@@ -73,6 +73,65 @@ def l2_error_v(disc: hdg.Discretization, v, v_exact):
     return np.sqrt(err)
 
 
+def l2_error_components(disc: hdg.Discretization, v, u_exact):
+    """Per conserved component c: sqrt(sum_K int_K (u(v_h) - u_exact)_c^2), element quadrature."""
+    from . import physics as ph
+    err = np.zeros(disc.m)
+    for e in range(disc.mesh.n_elem):
+        G = disc.geom(e)
+        vq = disc.ref.phi @ v[:, e * disc.Np:(e + 1) * disc.Np].T
+        du = ph.u_of_v(vq, disc.phys.gamma) - u_exact(G.xq)
+        err += np.sum(G.W[:, None] * du ** 2, axis=0)
+    return np.sqrt(err)
+
+
+def l2_error_stress_heat(disc: hdg.Discretization, v, q, v_exact, q_exact):
+    """L2(Omega) norms of the errors in the viscous stress and the heat flux formed from
+    (v_h, q_h) against those formed from the exact state and its gradient (the quantities of
+    the Couette example of Section 5: the approximate stresses and heat fluxes come from the
+    approximate solution and the approximate gradients).  v_exact: x (N, d) -> (N, m),
+    q_exact: x (N, d) -> (N, m, d).  Returns (||tau_h - tau||, ||f_h - f||)."""
+    from . import physics as ph
+    ph_, d, m = disc.phys, disc.d, disc.m
+    et = ef = 0.0
+    for e in range(disc.mesh.n_elem):
+        G = disc.geom(e)
+        sl = slice(e * disc.Np, (e + 1) * disc.Np)
+        vq = disc.ref.phi @ v[:, sl].T
+        qq = (disc.ref.phi @ q[:, sl].T).reshape(len(G.W), m, d)
+        th, fh = ph.stress_heat_flux(vq, qq, ph_.gamma, ph_.mu, ph_.Pr)
+        te, fe = ph.stress_heat_flux(v_exact(G.xq), q_exact(G.xq), ph_.gamma, ph_.mu, ph_.Pr)
+        et += np.sum(G.W[:, None, None] * (th - te) ** 2)
+        ef += np.sum(G.W[:, None] * (fh - fe) ** 2)
+    return np.sqrt(et), np.sqrt(ef)
+
+
+def project_boundary_data(disc: hdg.Discretization, v_exact):
+    """Dirichlet data of the trace equation <v_hat - v_bc, mu>_F = 0 on the boundary faces as
+    the L2(F) projection of the boundary function onto the face's trace space: per Dirichlet
+    face, M_F c = <v_exact, mu>_F with M_F the face mass matrix of the trace basis, by the face
+    quadrature.  (Testing the trace equation against every mu with the boundary function itself
+    gives exactly this projection; a nodal interpolant of it is a different, O(h^{k+1}) nearby
+    datum.)  v_exact: x (N, d) -> (N, m).  Returns (m, n_trace): the projection on the nodes of
+    Dirichlet faces, zero elsewhere.  A trace node shared by two Dirichlet faces (a continuous
+    trace at a boundary corner) has no face-local projection and raises ValueError."""
+    out = np.zeros((disc.m, disc.n_trace))
+    seen = np.zeros(disc.n_trace, dtype=bool)
+    for e in range(disc.mesh.n_elem):
+        for f in range(disc.nf):
+            if disc.face_bc[e, f] != 1:
+                continue
+            nodes = disc.tmap[e, f]
+            if np.any(seen[nodes]):
+                raise ValueError("trace node shared by two Dirichlet faces")
+            seen[nodes] = True
+            F = disc.geom(e).faces[f]
+            Mf = F["psi"].T @ (F["W"][:, None] * F["psi"])
+            rhs = F["psi"].T @ (F["W"][:, None] * v_exact(F["x"]))
+            out[:, nodes] = np.linalg.solve(Mf, rhs).T
+    return out
+
+
 def entropy_integral(disc: hdg.Discretization, v):
     """Per element (int_K rho s, int_K rho) with s = ln(p / rho^gamma) at u(v_h), by the
     element quadrature: the total thermodynamic entropy, the negative of the integral of

@@ -137,11 +137,12 @@ def flux_F(v, gamma):
     return F
 
 
-def flux_G(v, q, gamma, mu, Pr):
-    """Viscous flux G(v, q), shape (..., m, d); q has shape (..., m, d).
+def stress_heat_flux(v, q, gamma, mu, Pr):
+    """Viscous stress tau (..., d, d) and heat flux f (..., d) of the state v with gradient
+    unknowns q (..., m, d) (the Navier-Stokes section: Newtonian stress with beta = 0, Fourier
+    heat flux f = -kappa grad T, kappa = c_p mu / Pr).
 
-    grad u = A0(v) q per direction, then velocity and temperature gradients
-    from grad u, stress tau with beta = 0 and heat flux f = -kappa grad T.
+    grad u = A0(v) q per direction, then the velocity and temperature gradients from grad u.
     """
     rho, V, p = prim_of_v(v, gamma)
     d = V.shape[-1]
@@ -156,7 +157,16 @@ def flux_G(v, q, gamma, mu, Pr):
     div = np.einsum("...ii->...", gV)
     tau = mu * (gV + np.swapaxes(gV, -1, -2) - (2.0 / 3.0) * div[..., None, None] * np.eye(d))
     kappa = gamma / (gamma - 1.0) * mu / Pr
-    f = -kappa * gT
+    return tau, -kappa * gT
+
+
+def flux_G(v, q, gamma, mu, Pr):
+    """Viscous flux G(v, q), shape (..., m, d); q has shape (..., m, d):
+    G = -(0, tau, V.tau - f) with the stress and heat flux of ``stress_heat_flux``."""
+    rho, V, p = prim_of_v(v, gamma)
+    d = V.shape[-1]
+    m = d + 2
+    tau, f = stress_heat_flux(v, q, gamma, mu, Pr)
     G = np.zeros(v.shape[:-1] + (m, d), dtype=np.result_type(v, q, float))
     G[..., 1:m - 1, :] = -tau
     G[..., m - 1, :] = -(np.einsum("...i,...ij->...j", V, tau) - f)

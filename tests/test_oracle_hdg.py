@@ -306,9 +306,13 @@ def test_convergence_order_k_plus_1(viscous, p):
     """Euler: L2 error of u at rate >= k+1-0.3.  NS (mu = 0.05): u at >= k+1-0.45 and the
     temperature-gradient component of q (the last entropy variable) at >= k+1-0.3.
 
-    The momentum components of q converge below k+1 in this diffusion-dominated
-    regime with sigma_SLF as the only stabilization; the measured rates are
-    recorded with the design notes, not asserted here.
+    The other components of q are not pinned at k+1: the viscous flux sees q only through
+    K~(v) q, whose null space holds the density gradient at fixed velocity and temperature and
+    the skew part of the velocity gradient; the scheme controls those directions of q only
+    through the inviscid stabilization, and they converge at about k (Couette, k = 1: first
+    component 0.98, momentum components 0.7 to 1.6, last component 2.0).  What Table 6 prints,
+    the stress and heat flux formed from (v_h, q_h), lies in the range of K~ and converges at
+    k+1: test_couette_against_table_6.
     """
     mu = 0.05 if viscous else 0.0
     Pr = 0.72
@@ -500,3 +504,115 @@ def test_projection_viscous_flux_against_least_squares_projection():
             diff += np.einsum("q,qcj,qj,qa->ca", F["W"], Pf - Gf, F["n"], F["phi"])
         assert np.abs(diff).max() > 1e-4
         assert np.abs((Rp - Ri) - diff).max() <= 1e-11 * np.abs(diff).max()
+
+
+# ------------------------------------------------- Dirichlet data, Table 6 (Couette)
+def _couette_exact():
+    from workloads.fields import Couette
+    f = Couette()
+
+    def v_ex(x):                                   # x (N, d) -> (N, m)
+        pr = f.prim(x.T)
+        return ph.v_of_prim(pr[0], pr[1:3].T, pr[3], f.gamma)
+
+    def q_ex(x):                                   # grad v by complex step: (N, m, d)
+        cols = []
+        for j in range(2):
+            xc = x.astype(complex)
+            xc[:, j] += 1e-30j
+            pr = f.prim(xc.T)
+            cols.append(np.imag(ph.v_of_prim(pr[0], pr[1:3].T, pr[3], f.gamma)) / 1e-30)
+        return np.stack(cols, -1)
+
+    def u_ex(x):
+        pr = f.prim(x.T)
+        return ph.u_of_prim(pr[0], pr[1:3].T, pr[3], f.gamma)
+
+    return f, v_ex, q_ex, u_ex
+
+
+def test_boundary_projection_reproduces_face_polynomials_and_is_best():
+    """The face L2 projection of the Dirichlet data reproduces, at the trace nodes, a field that
+    is a polynomial of degree <= k along every boundary face (here one of total degree k on
+    straight faces), and for a non-polynomial field its L2(F) error is no larger than that of the
+    nodal interpolant, measured with an independent 12-point Gauss rule on each face."""
+    for p in (1, 2, 3):
+        mesh = M.tri_square(3, 0.08, 4, periodic=False)
+        tmap, nt = M.trace_map(mesh, p, "hdg")
+        disc = hdg.Discretization(mesh, p, hdg.Phys(GAM, 0.0, 0.72, 0.0, False), tmap, nt,
+                                  mesh.boundary.astype(np.int32))
+        xt = disc.trace_coords().T
+        bnd = disc.dir_node
+        c = np.random.default_rng(p).normal(size=(4, 3))
+        poly = lambda x: np.stack([(c[i, 0] + c[i, 1] * x[:, 0] + c[i, 2] * x[:, 1]) ** p
+                                   for i in range(4)], -1)
+        vb = newton.project_boundary_data(disc, poly)
+        assert np.allclose(vb[:, bnd], poly(xt[bnd]).T, rtol=1e-12, atol=1e-12)
+        smooth = lambda x: np.stack([np.sin(3 * x[:, 0] + 2 * x[:, 1] + i) for i in range(4)], -1)
+        vb = newton.project_boundary_data(disc, smooth)
+        vi = smooth(xt).T
+        s, t = np.polynomial.legendre.leggauss(12)
+        worse = 0
+        for e in range(mesh.n_elem):
+            xyz = mesh.elem_xyz[e]
+            for f in range(3):
+                if disc.face_bc[e, f] != 1:
+                    continue
+                a, b = xyz[(f + 1) % 3], xyz[(f + 2) % 3]   # the face opposite vertex f
+                nodes = tmap[e, f]
+                xn = xt[nodes]
+                # 1D Lagrange basis in the face's arc parameter through its nodes
+                tn = (xn - a) @ (b - a) / ((b - a) @ (b - a))
+                tq = 0.5 * (s + 1.0)
+                L = np.ones((len(tq), len(tn)))
+                for i in range(len(tn)):
+                    for j in range(len(tn)):
+                        if j != i:
+                            L[:, i] *= (tq - tn[j]) / (tn[i] - tn[j])
+                gq = smooth(a + tq[:, None] * (b - a))
+                ep = np.sum(t[:, None] * (L @ vb[:, nodes].T - gq) ** 2)
+                ei = np.sum(t[:, None] * (L @ vi[:, nodes].T - gq) ** 2)
+                worse += ep > ei * (1 + 1e-9)
+        assert worse == 0
+
+
+def _couette_oracle_errors(n, p):
+    f, v_ex, q_ex, u_ex = _couette_exact()
+    mesh = M.tri_square(n, 0.0, 0, periodic=False)
+    tmap, nt = M.trace_map(mesh, p, "hdg")
+    disc = hdg.Discretization(mesh, p, hdg.Phys(f.gamma, f.mu, f.Pr, 0.0, True), tmap, nt,
+                              mesh.boundary.astype(np.int32))
+    xn, xt = disc.node_coords().T, disc.trace_coords().T
+    vbc = newton.project_boundary_data(disc, v_ex)
+    vh0 = v_ex(xt).T.copy()
+    vh0[:, disc.dir_node] = vbc[:, disc.dir_node]
+    q0 = q_ex(xn).transpose(1, 2, 0).reshape(-1, xn.shape[0]).copy()
+    v, q, vh, hist = newton.newton_steady(disc, v_ex(xn).T.copy(), q0, vh0, vbc=vbc,
+                                          source=lambda x: f.source(x.T).T, tol=1e-11)
+    assert hist[-1] < 1e-10, hist
+    eu = newton.l2_error_components(disc, v, u_ex)
+    et, ef = newton.l2_error_stress_heat(disc, v, q, v_ex, q_ex)
+    # non-dimensional as printed: rho0 = V0 = L = 1, so tau* = tau / mu and f* = f / mu
+    return {"rho": eu[0], "momentum": np.hypot(eu[1], eu[2]), "rhoE": eu[3],
+            "tau": et / f.mu, "f": ef / f.mu}
+
+
+@pytest.mark.parametrize("p,ns", [(1, (16, 32)), (2, (8, 16))])
+def test_couette_against_table_6(p, ns):
+    """Table 6 (Couette flow, entropy-variable HDG, Dirichlet data = the exact solution, tested
+    on each boundary face, i.e. its face L2 projection): the density, momentum, total energy,
+    stress tau* and heat flux f* (formed from v_h and q_h) errors within a factor 6 of the printed
+    ones, and every rate on the mesh pair within 0.3 of the printed rate.  The factor covers what
+    the paper leaves unstated (the diagonal of the split, the quadrature, the nodes); the rate
+    window the scatter of the printed rates themselves."""
+    tab = json.load(open(os.path.join(HERE, "golden", "paper_table_6_couette.json")))
+    hs = tab["L_over_h"]
+    i0, i1 = hs.index(ns[0]), hs.index(ns[1])
+    e0, e1 = _couette_oracle_errors(ns[0], p), _couette_oracle_errors(ns[1], p)
+    for key in tab["quantities"]:
+        for e, i in ((e0, i0), (e1, i1)):
+            ref = tab["error"][key][p - 1][i]
+            assert ref / 6 <= e[key] <= 6 * ref, (key, p, hs[i], e[key], ref)
+        rate = np.log2(e0[key] / e1[key])
+        ref_rate = tab["rate"][key][p - 1][i1 - 1]
+        assert abs(rate - ref_rate) <= 0.3, (key, p, rate, ref_rate)

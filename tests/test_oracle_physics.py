@@ -193,3 +193,33 @@ def test_mean_value_stabilization():
         th, w = np.polynomial.legendre.leggauss(64)
         fine = sum(0.5 * wi * P.sigma_s_apply(vh + 0.5 * (1 + ti) * (v - vh), n, GAM, dv) for ti, wi in zip(th, w))
         assert np.max(np.abs(P.sigma_mv_apply(vh, v, n, GAM, dv) - fine)) <= 1e-9 * np.max(np.abs(fine))
+
+
+def test_stress_and_heat_flux_closed_form():
+    """tau and f formed from (v, q = grad v) equal the Newtonian stress (beta = 0) and the Fourier
+    heat flux of a flow with a given affine velocity, density and pressure, written in closed form
+    from the primitive gradients (the Navier-Stokes section)."""
+    gam, mu, Pr = 1.4, 0.03, 0.72
+    rng = np.random.default_rng(5)
+    for d in (2, 3):
+        x0 = rng.normal(size=d)
+        gV = rng.normal(size=(d, d))                     # dV_i / dx_j
+        grho, gp = rng.normal(size=d) * 0.1, rng.normal(size=d) * 0.2
+        rho0, p0, V0 = 1.1, 0.9, rng.normal(size=d) * 0.3
+
+        def prim(x):
+            dx = x - x0
+            return rho0 + grho @ dx, V0 + gV @ dx, p0 + gp @ dx
+
+        def v_at(x):
+            r, V, p = prim(x)
+            return P.v_of_prim(np.asarray(r), V, np.asarray(p), gam)
+
+        q = np.stack([np.imag(v_at(x0 + 1e-30j * np.eye(d)[j])) / 1e-30 for j in range(d)], -1)
+        tau, f = P.stress_heat_flux(v_at(x0)[None].real, q[None], gam, mu, Pr)
+        div = np.trace(gV)
+        tau_ex = mu * (gV + gV.T - 2.0 / 3.0 * div * np.eye(d))
+        gT = (gp - p0 / rho0 * grho) / rho0               # T = p / rho
+        f_ex = -gam / (gam - 1.0) * mu / Pr * gT
+        assert np.allclose(tau[0], tau_ex, rtol=1e-12, atol=1e-14)
+        assert np.allclose(f[0], f_ex, rtol=1e-12, atol=1e-14)
