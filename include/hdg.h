@@ -166,10 +166,29 @@ int hdg_quad_coords(const hdg_plan *plan, double *xq, void *stream);
  *   out[e][c] = sum_q W_q (f_c(x_q) - exact[c][e Nq + q])^2,
  * kind 0: f = u(v_h) from v [m][E*Np], c < m (conserved variables);
  * kind 1: f = the gradient unknowns q [m*dim][E*Np] interpolated, c < m*dim (NS only);
- * kind 2: f = the entropy variables v_h [m][E*Np] interpolated, c < m.
- * All device; out [E][m] or [E][m*dim]. */
+ * kind 2: f = the entropy variables v_h [m][E*Np] interpolated, c < m;
+ * kind 3 (NS only): the viscous stress and heat flux formed from the state and its gradient
+ *   unknowns, as the Couette example of Section 5 measures them: f = [v; q] stacked
+ *   [(m + m*dim)][E*Np] (v_h, q_h), exact = [v; q] stacked [(m + m*dim)][E*Nq] at the
+ *   quadrature points; c < dim*dim + dim (tau[i][j] row-major, then f[j]); tau and f are those
+ *   of the plan's viscous flux G = -(0, tau, V.tau - f).
+ * All device; out [E][m], [E][m*dim] or [E][dim*dim + dim]. */
 int hdg_l2_error(const hdg_plan *plan, int kind, const double *f, const double *exact, double *out,
                  void *stream);
+/* Physical coordinates of the face quadrature points of every element face,
+ * xf [dim][E*nf*Nfq] (device), ordered (e nf + f) Nfq + q: the face's image under the element
+ * map.  Where Dirichlet data is known as a function, evaluate it here for hdg_trace_project. */
+int hdg_face_quad_coords(const hdg_plan *plan, double *xf, void *stream);
+/* Dirichlet data of the trace equation as the face L2 projection (Section 3: the trace equation
+ * is tested against every trace function mu, so <v_hat - v_bc, mu>_F = 0 with v_bc the boundary
+ * function makes v_hat its L2(F) projection): for every Dirichlet-trace face, the nodal trace
+ * coefficients c solving M_F c = <g, mu>_F (M_F the face mass matrix of the trace basis, face
+ * quadrature) are written to v_bc [m][n_trace] at that face's trace nodes; other entries are left
+ * as they are.  g [m][E*nf*Nfq]: entropy variables of the boundary state at the face quadrature
+ * points (hdg_face_quad_coords order; only Dirichlet faces are read).  Device pointers, caller
+ * owned.  HDG_EUNSUPPORTED when a trace node is shared by two Dirichlet faces (a continuous
+ * trace at a boundary corner has no face-local projection) or a face has more than 25 nodes. */
+int hdg_trace_project(const hdg_plan *plan, const double *g, double *v_bc, void *stream);
 /* Total thermodynamic entropy and mass of each element (the quantities whose evolution
  * Proposition 1 and the Shu vortex example of Section 5 follow):
  *   out[e][0] = int_K rho s,  out[e][1] = int_K rho,  s = ln(p / rho^gamma),

@@ -127,6 +127,8 @@ SIGNATURES = {
     "hdg_plan_set_source": (I, [P, P]),
     "hdg_quad_coords": (I, [P, P, P]),
     "hdg_l2_error": (I, [P, I, P, P, P, P]),
+    "hdg_face_quad_coords": (I, [P, P, P]),
+    "hdg_trace_project": (I, [P, P, P, P]),
     "hdg_entropy_integral": (I, [P, P, P, P]),
     "hdg_flow_statistics": (I, [P, P, P, P]),
     "hdg_learn_nparams": (I, []),

@@ -3,9 +3,11 @@
 as Dirichlet data on the whole boundary, then element L2 errors at the volume quadrature
 points (hdg_quad_coords, hdg_l2_error).
 
-* Couette flow with a source term (Navier-Stokes, Table 6): reported with rho0 = V0 = L = 1,
-  the conserved variables (rho, momentum, rho E) and the gradient unknowns q (the
-  entropy-variable gradients from which the stresses and heat fluxes are formed).
+* Couette flow with a source term (Navier-Stokes, Table 6): reported as the table reports it,
+  with rho0 = V0 = L = 1: the conserved variables (rho, momentum, rho E) and the stress and heat
+  flux formed from v_h and q_h (tau* = tau / mu, f* = f / mu), besides the raw gradient
+  unknowns q.  The Dirichlet data is the exact solution tested on each boundary face (its face
+  L2 projection, hdg_trace_project); bc="nodal" takes its nodal interpolant instead.
 * Ringleb flow (Euler, Tables 3-5): the square (-5, -1) x (1, 5), h = 4 / n, the
   [L2(Omega)]^m norm of the error in the conserved variables, for HDG, IEDG and EDG traces.
 
@@ -15,7 +17,8 @@ from __future__ import annotations
 import numpy as np
 
 
-def couette_run(n, p, scheme="hdg", tol=1e-9, atol=1e-10, maxit=20, lin_tol=1e-13, ghat_proj=False):
+def couette_run(n, p, scheme="hdg", tol=1e-9, atol=1e-10, maxit=20, lin_tol=1e-13, ghat_proj=False,
+                bc="projection"):
     """Solve the Couette problem on an n x n mesh of order p; returns the error dict."""
     import torch
 
@@ -41,29 +44,39 @@ def couette_run(n, p, scheme="hdg", tol=1e-9, atol=1e-10, maxit=20, lin_tol=1e-1
     v, q, _ = state(xn, True)
     vhat, _, _ = state(xt, False)
     vbc = vhat.clone()
+    if bc == "projection":
+        gf, _, _ = state(plan.face_quad_coords().cpu().numpy(), False)
+        plan.trace_project(gf, vbc)
+        vhat = vbc.clone()
     plan.set_source(torch.from_numpy(np.ascontiguousarray(f.source(xn))).to(dev))
     info = plan.newton_solve(v, q, vhat, None, vbc, maxit=maxit, tol=tol, atol=atol, lin_tol=lin_tol)
     xq = plan.quad_coords().cpu().numpy()
-    _, qex, uex = state(xq, True)
+    vex, qex, uex = state(xq, True)
     eu = torch.sqrt(plan.l2_error(v, uex, "u")).cpu().numpy()
     eq = torch.sqrt(plan.l2_error(q, qex, "q")).cpu().numpy()
-    return {"n": n, "p": p, "elements": mesh.n_elem, "newton_iterations": info["iterations"],
+    es = plan.l2_error(torch.cat([v, q]), torch.cat([vex, qex]), "stress").cpu().numpy()
+    d = 2
+    return {"n": n, "p": p, "bc": bc, "elements": mesh.n_elem, "newton_iterations": info["iterations"],
             "converged": info["converged"], "res": info["res"][-1],
             "rho": float(eu[0]), "momentum": float(np.hypot(eu[1], eu[2])), "rhoE": float(eu[3]),
+            "tau": float(np.sqrt(es[:d * d].sum())) / f.mu, "f": float(np.sqrt(es[d * d:].sum())) / f.mu,
             "q": float(np.sqrt(np.sum(eq ** 2)))}
 
 
-def couette_table(ns=(4, 8, 16), ps=(1, 2), scheme="hdg", ghat_proj=False):
+COUETTE_KEYS = ("rho", "momentum", "rhoE", "tau", "f", "q")
+
+
+def couette_table(ns=(4, 8, 16), ps=(1, 2), scheme="hdg", ghat_proj=False, bc="projection"):
     """Errors and rates for every (p, n); rates against the next finer mesh."""
     rows = []
     for p in ps:
         prev = None
         for n in ns:
-            r = couette_run(n, p, scheme, ghat_proj=ghat_proj)
+            r = couette_run(n, p, scheme, ghat_proj=ghat_proj, bc=bc)
             r["scheme"] = scheme
             r["ghat_proj"] = ghat_proj
             if prev is not None:
-                for key in ("rho", "momentum", "rhoE", "q"):
+                for key in COUETTE_KEYS:
                     r["rate_" + key] = float(np.log2(prev[key] / r[key]))
             rows.append(r)
             prev = r
@@ -128,6 +141,8 @@ def main(argv=None):
     ap.add_argument("--ps", default="1,2,3,4")
     ap.add_argument("--schemes", default="hdg,iedg,edg")
     ap.add_argument("--ghat-proj", action="store_true", help="couette: projection viscous flux")
+    ap.add_argument("--bc", default="projection", choices=("projection", "nodal"),
+                    help="couette: Dirichlet data as the face L2 projection or the nodal interpolant")
     a = ap.parse_args(argv)
     ps = tuple(int(x) for x in a.ps.split(","))
     if a.problem == "ringleb":
@@ -138,7 +153,7 @@ def main(argv=None):
     else:
         ns = tuple(int(x) for x in (a.ns or "4,8,16").split(","))
         for scheme in a.schemes.split(","):
-            for r in couette_table(ns, ps, scheme, a.ghat_proj):
+            for r in couette_table(ns, ps, scheme, a.ghat_proj, a.bc):
                 print(json.dumps(r), flush=True)
 
 

@@ -237,10 +237,10 @@ __device__ inline void load_tile(T (&a)[W / 4], const T *M, int ld, const Step &
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   if (st.inv < 0 || st.r_lo + wave * 16 >= st.r_hi) return;
-  const T *Mp = M + (size_t)(st.p0 + lk) * ld;
-  const size_t grow = (size_t)(st.r_lo + wave * 16 + li);
+  const T *Mb = M + (size_t)st.p0 * ld;
+  const int o0 = lk * ld + st.r_lo + wave * 16 + li;
 #pragma unroll
-  for (int kk = 0; kk < W / 4; ++kk) a[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
+  for (int kk = 0; kk < W / 4; ++kk) a[kk] = -Mb[o0 + 4 * kk * ld];
 }
 
 // Rows p0..p0+W-1 of the block <- Inv * rows, Inv (preloaded in ia) the stored
@@ -321,7 +321,10 @@ __device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
   constexpr int BS = W + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane >= W || wave > 1) return;
-  const int c = lane;
+  // c is made opaque to the optimizer: otherwise the identity columns below are hoisted
+  // out of the caller's block loop and stay live (2W registers) through every phase
+  int c = lane;
+  asm volatile("" : "+v"(c));
   T x[W];
   if (wave == 0) {
 #pragma unroll
@@ -351,10 +354,13 @@ __device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
 
 // blk[r][:] -= sum_kk M[(p0+kk) * ld + r] * blk[p0+kk][:]  for rows r in [r_lo, r_hi)
 // (stored factors are in pivot-position order, so the loads are contiguous;
-// r_lo, r_hi multiples of 16, disjoint from p0..p0+W-1).  The wave's first tile
-// arrives preloaded in a; the first tile of the next step is loaded into a at
-// the end.
-template <typename T, int W, int NTT = NT>
+// r_lo, r_hi multiples of 16, disjoint from p0..p0+W-1).  Wave w updates the row
+// tiles w, w + NWT, ...; its first tile arrives preloaded in a, and the factor
+// tiles of its next MT - 1 tiles and the first tile of the next step are all
+// requested before the first MFMA, so one memory latency is exposed per step
+// rather than one per tile (a step is short next to a load from memory).  Tiles
+// beyond the first MT of a wave (large blocks) are fetched one tile ahead.
+template <typename T, int W, int NTT = NT, int MT = 5>
 __device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, int ld, const Step &st,
                                    const Step &next) {
   constexpr int NWT = NTT / 64;
@@ -364,16 +370,24 @@ __device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, i
   const int li = lane & 15, lk = lane >> 4;
   const int p0 = st.p0, r_lo = st.r_lo;
   const int ntile = st.r_hi > r_lo ? (st.r_hi - r_lo) / 16 : 0;
-  const T *Mp = M + (size_t)(p0 + lk) * ld;
-  T an[KS];
-  for (int t = wave; t < ntile; t += NWT) {
-    const int r0 = r_lo + t * 16;
-    const int tn = t + NWT;
-    if (tn < ntile) {
-      const size_t grow = (size_t)(r_lo + tn * 16 + li);
+  // uniform base, 32-bit lane offsets (a block has fewer than 2^31 entries)
+  const T *Mb = M + (size_t)p0 * ld;
+  const int o0 = lk * ld + r_lo + li;
+  T ab[MT][KS];
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) an[kk] = -Mp[(size_t)(4 * kk) * ld + grow];
+  for (int u = 1; u < MT; ++u) {
+    const int t = wave + u * NWT;
+    if (t < ntile) {
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) ab[u][kk] = -Mb[o0 + 4 * kk * ld + t * 16];
     }
+  }
+  T an[KS];
+  load_tile<T, W>(an, M, ld, next);
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) ab[0][kk] = a[kk];
+  const auto tile = [&](int t, const T (&op)[KS]) {
+    const int r0 = r_lo + t * 16;
     typename MF::acc c[TW];
 #pragma unroll
     for (int q = 0; q < TW; ++q)
@@ -383,21 +397,42 @@ __device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, i
     for (int kk = 0; kk < KS; ++kk) {
       const T *brow = s.blk + (p0 + 4 * kk + lk) * BS;
 #pragma unroll
-      for (int q = 0; q < TW; ++q) c[q] = MF::op(a[kk], brow[q * 16 + li], c[q]);
+      for (int q = 0; q < TW; ++q) c[q] = MF::op(op[kk], brow[q * 16 + li], c[q]);
     }
 #pragma unroll
     for (int q = 0; q < TW; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li] = c[q][r];
+  };
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) a[kk] = an[kk];
+  for (int u = 0; u < MT; ++u) {
+    const int t = wave + u * NWT;
+    if (t < ntile) tile(t, ab[u]);
   }
-  load_tile<T, W>(a, M, ld, next);
+  // remaining tiles of the wave, one tile ahead
+  int t = wave + MT * NWT;
+  if (t < ntile) {
+    T cur[KS], nx[KS];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) cur[kk] = -Mb[o0 + 4 * kk * ld + t * 16];
+    for (; t < ntile; t += NWT) {
+      const int tn = t + NWT;
+      if (tn < ntile) {
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) nx[kk] = -Mb[o0 + 4 * kk * ld + tn * 16];
+      }
+      tile(t, cur);
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) cur[kk] = nx[kk];
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) a[kk] = an[kk];
 }
 
 // A sequence of steps: spec(i) for i in [0, count), each applied with its
 // operands loaded one step ahead.
-template <typename T, int W, typename Spec, int NTT = NT>
+template <typename T, int W, typename Spec, int NTT = NT, int MT = 5>
 __device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int ld, int count, Spec spec) {
   T ia[W / 4], a[W / 4];
   Step cur = spec(0);
@@ -407,7 +442,7 @@ __device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int 
     const Step nxt = (i + 1 < count) ? spec(i + 1) : Step{-1, 0, 0, 0};
     inv_apply<T, W>(s, ia, cur.p0, Ie, nxt);
     __syncthreads();
-    gemm_update<T, W, NTT>(s, a, Fm, ld, cur, nxt);
+    gemm_update<T, W, NTT, MT>(s, a, Fm, ld, cur, nxt);
     __syncthreads();
     cur = nxt;
   }
@@ -737,6 +772,20 @@ __device__ inline double diag_scale(const DevPlan &P, const double *A64, const d
   return (a > 0.0 && a < 1e300) ? exp2(-rint(0.5 * log2(a))) : 1.0;
 }
 
+// Update steps of the left-looking LU: step i applies factor block i to the rows below it.
+struct StepSpec {
+  int W, np;
+  __device__ Step operator()(int i) const { return Step{i * 2 * W * W, i * W, i * W + W, np}; }
+};
+
+// Factor tiles a wave requests ahead per update step: five where the kernel runs at two
+// waves per SIMD (FP64, 32 columns; the register file has room), two or three in the kernels
+// whose registers are capped for four waves per SIMD.
+template <typename T, int W>
+__host__ __device__ constexpr int lu_prefetch_tiles() {
+  return (sizeof(T) == 8 && W == 32) ? 5 : (sizeof(T) == 4 ? 3 : 2);
+}
+
 // LU of element el, left-looking over W-column blocks; leaves perm (and the
 // scaling) in LDS and stores the permutation (P.ipiv, or the record).
 // Returns whether a zero pivot occurred.
@@ -762,7 +811,7 @@ __device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &
     else load_block<T, W>(s, A64, np, j0, np);
     __syncthreads();
     if (J > 0)
-      run_steps<T, W>(s, Ie, Fm, np, J, [&](int i) { return Step{i * 2 * W * W, i * W, i * W + W, np}; });
+      run_steps<T, W, StepSpec, NT, lu_prefetch_tiles<T, W>()>(s, Ie, Fm, np, J, StepSpec{W, np});
     if (J > 0) {
       for (int x = j0 + tid; x < np; x += NT) s.invb[s.perm[x]] = x;
       if (tid == 0) *s.mvn = 0;
@@ -822,7 +871,7 @@ __device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c
     const int Pb = 2 * nJ - 1 - i;
     return Step{Pb * 2 * W * W + W * W, Pb * W, 0, Pb * W};
   };
-  run_steps<T, W, decltype(rhs_spec), NTT>(s, f.Inv, f.F, np, 2 * nJ, rhs_spec);
+  run_steps<T, W, decltype(rhs_spec), NTT, (NTT >= 1024 ? 1 : lu_prefetch_tiles<T, W>())>(s, f.Inv, f.F, np, 2 * nJ, rhs_spec);
 
   if constexpr (LP) {
     // undo the column scaling: Y = D Y_hat, z = D z_hat

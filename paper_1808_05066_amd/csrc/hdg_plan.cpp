@@ -407,10 +407,41 @@ extern "C" int hdg_l2_error(const hdg_plan *plan, int kind, const double *f, con
                             void *stream) {
   const Plan *P = checked(const_cast<hdg_plan *>(plan));
   if (!P) return HDG_EINVAL;
-  if (!f || !exact || !out || kind < 0 || kind > 2 || (kind == 1 && !P->dp.viscous))
+  if (!f || !exact || !out || kind < 0 || kind > 3 || (kind >= 1 && kind != 2 && !P->dp.viscous))
     return fail(HDG_EINVAL, "bad argument");
-  hipError_t e = launch_l2_error(P->dp, kind, f, exact, out, reinterpret_cast<hipStream_t>(stream));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = kind == 3 ? launch_l2_error_visc(P->dp, f, exact, out, s) : launch_l2_error(P->dp, kind, f, exact, out, s);
   if (e) return hip_fail(e, "l2_error");
+  return HDG_OK;
+}
+
+extern "C" int hdg_face_quad_coords(const hdg_plan *plan, double *xf, void *stream) {
+  const Plan *P = checked(const_cast<hdg_plan *>(plan));
+  if (!P) return HDG_EINVAL;
+  if (!xf) return fail(HDG_EINVAL, "null argument");
+  hipError_t e = launch_face_quad_coords(P->dp, xf, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "face_quad_coords");
+  return HDG_OK;
+}
+
+extern "C" int hdg_trace_project(const hdg_plan *plan, const double *g, double *vbc, void *stream) {
+  const Plan *P = checked(const_cast<hdg_plan *>(plan));
+  if (!P) return HDG_EINVAL;
+  if (!g || !vbc) return fail(HDG_EINVAL, "null argument");
+  // every trace node of a Dirichlet face must belong to that face alone
+  const int nf = P->dp.nf, Nfp = P->dp.Nfp;
+  std::vector<char> seen(P->n_trace, 0);
+  for (int ef = 0; ef < P->n_elem * nf; ++ef) {
+    if (P->face_bc[ef] != 1) continue;
+    for (int b = 0; b < Nfp; ++b) {
+      const int t = P->tmap[(size_t)ef * Nfp + b];
+      if (seen[t]) return fail(HDG_EUNSUPPORTED, "trace node shared by two Dirichlet faces (continuous trace)");
+      seen[t] = 1;
+    }
+  }
+  hipError_t e = launch_trace_project(P->dp, g, vbc, reinterpret_cast<hipStream_t>(stream));
+  if (e == hipErrorInvalidValue) return fail(HDG_EUNSUPPORTED, "face too large for the projection kernel");
+  if (e) return hip_fail(e, "trace_project");
   return HDG_OK;
 }
 

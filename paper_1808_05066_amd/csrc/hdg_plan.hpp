@@ -222,6 +222,9 @@ hipError_t launch_trace_rhs(const DevPlan &P, const double *g, double *r, hipStr
 hipError_t launch_weak_u(const DevPlan &P, const double *v, double *b, hipStream_t s);
 hipError_t launch_mass_solve(const DevPlan &P, const double *b, double *u, hipStream_t s);
 hipError_t launch_quad_coords(const DevPlan &P, double *xq, hipStream_t s);
+hipError_t launch_l2_error_visc(const DevPlan &P, const double *f, const double *ex, double *out, hipStream_t s);
+hipError_t launch_face_quad_coords(const DevPlan &P, double *xf, hipStream_t s);
+hipError_t launch_trace_project(const DevPlan &P, const double *g, double *vbc, hipStream_t s);
 hipError_t launch_l2_error(const DevPlan &P, int kind, const double *f, const double *ex, double *out,
                            hipStream_t s);
 hipError_t launch_drop_rows(const DevPlan &P, int e0, int ec, hipStream_t s);

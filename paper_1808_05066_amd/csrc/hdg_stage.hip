@@ -157,6 +157,132 @@ __global__ __launch_bounds__(64) void k_l2_error(DevPlan P, int kind, const doub
   }
 }
 
+// Viscous stress tau[i][j] and heat flux f[j] of the state with entropy variables v[M] and
+// gradient unknowns q[c D + k] (G = -(0, tau, V.tau - f) of the viscous flux), into out[D D + D].
+template <int D>
+__device__ inline void stress_heat(const double *v, const double *q, const DevPlan &P, double *out) {
+  constexpr int M = D + 2;
+  const Prim<D, double> st = prim_of_v<D, double>(v, P.gamma);
+  double G[M * D];
+  flux_G<D, double, double>(st, q, P.gamma, P.mu, P.Pr, G);
+  for (int i = 0; i < D; ++i)
+    for (int j = 0; j < D; ++j) out[i * D + j] = -G[(1 + i) * D + j];
+  for (int j = 0; j < D; ++j) {
+    double vt = 0.0;
+    for (int i = 0; i < D; ++i) vt += st.V[i] * out[i * D + j];
+    out[D * D + j] = G[(D + 1) * D + j] + vt;
+  }
+}
+
+// out[e][c] = sum_q W_q (s_c(v_h, q_h)(x_q) - s_c(v, q)(x_q))^2 for the stress and heat flux s of
+// the viscous flux: f = [v; q] stacked [(M + M D)][E*Np] (nodal, interpolated), ex the same
+// stacked [(M + M D)][E*Nq] at the volume quadrature points; c < D D + D
+template <int D>
+__global__ __launch_bounds__(64) void k_l2_error_visc(DevPlan P, const double *__restrict__ f,
+                                                      const double *__restrict__ ex, double *out) {
+  constexpr int M = D + 2, NV = M + M * D, NS = D * D + D;
+  __shared__ double red[64][NS];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  const int Np = P.Np, Nq = P.Nq;
+  const size_t NN = (size_t)P.n_elem * Np, NQ = (size_t)P.n_elem * Nq;
+  double acc[NS];
+  for (int c = 0; c < NS; ++c) acc[c] = 0.0;
+  for (int q = tid; q < Nq; q += 64) {
+    const double *phi = P.phi + (size_t)q * Np;
+    double h[NV], x[NV];
+    for (int c = 0; c < NV; ++c) {
+      double s = 0.0;
+      for (int a = 0; a < Np; ++a) s += phi[a] * f[(size_t)c * NN + (size_t)e * Np + a];
+      h[c] = s;
+      x[c] = ex[(size_t)c * NQ + (size_t)e * Nq + q];
+    }
+    double sh[NS], sx[NS];
+    stress_heat<D>(h, h + M, P, sh);
+    stress_heat<D>(x, x + M, P, sx);
+    const double W = P.geo_vol[((size_t)e * Nq + q) * (1 + D * D)];
+    for (int c = 0; c < NS; ++c) acc[c] += W * (sh[c] - sx[c]) * (sh[c] - sx[c]);
+  }
+  for (int c = 0; c < NS; ++c) red[tid][c] = acc[c];
+  __syncthreads();
+  if (tid < NS) {
+    double s = 0.0;
+    for (int t = 0; t < 64; ++t) s += red[t][tid];
+    out[(size_t)e * NS + tid] = s;
+  }
+}
+
+// Physical coordinates of the face quadrature points, xf[c][(e nf + f) Nfq + q] =
+// sum_b psi_b(x_q) x_c(face node b): the face's image under the element map (affine and
+// multilinear faces are reproduced by the face-node interpolant)
+__global__ void k_face_quad_coords(DevPlan P, double *xf) {
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t NF = (size_t)P.n_elem * P.nf * P.Nfq, NN = (size_t)P.n_elem * P.Np;
+  if (t >= NF) return;
+  const int q = (int)(t % P.Nfq);
+  const size_t ef = t / P.Nfq;
+  const int f = (int)(ef % P.nf), e = (int)(ef / P.nf);
+  const double *psi = P.fphi + ((size_t)f * P.Nfq + q) * P.Nfp;
+  for (int d = 0; d < P.dim; ++d) {
+    double acc = 0.0;
+    for (int b = 0; b < P.Nfp; ++b)
+      acc += psi[b] * P.node_x[(size_t)d * NN + (size_t)e * P.Np + P.fnodes[f * P.Nfp + b]];
+    xf[(size_t)d * NF + t] = acc;
+  }
+}
+
+// Face L2 projection of Dirichlet data: for every Dirichlet-trace face, M_F c = <g, mu>_F with
+// M_F[b][b'] = sum_q W_q psi_b psi_b' and g given at the face quadrature points,
+// g[c][(e nf + f) Nfq + q]; c (Nfp x m) written to the face's trace nodes of vbc [m][n_trace].
+// One 64-thread workgroup per element face; Gauss-Jordan on the SPD face mass matrix in LDS.
+constexpr int PJ_NFP = 25;   // face nodes of a p = 4 quadrilateral face
+__global__ __launch_bounds__(64) void k_trace_project(DevPlan P, const double *__restrict__ g, double *vbc) {
+  __shared__ double Mf[PJ_NFP][PJ_NFP];
+  __shared__ double R[PJ_NFP][8];
+  const int ef = blockIdx.x, tid = threadIdx.x;
+  if (P.face_bc[ef] != 1) return;   // whole workgroup
+  const int f = ef % P.nf, m = P.m, Nfp = P.Nfp, Nfq = P.Nfq;
+  const size_t NF = (size_t)P.n_elem * P.nf * Nfq;
+  const double *psi = P.fphi + (size_t)f * Nfq * Nfp;
+  const double *gf = P.geo_face + (size_t)ef * Nfq * (1 + P.dim);
+  for (int t = tid; t < Nfp * Nfp; t += 64) {
+    const int b = t / Nfp, c = t % Nfp;
+    double s = 0.0;
+    for (int q = 0; q < Nfq; ++q) s += gf[(size_t)q * (1 + P.dim)] * psi[q * Nfp + b] * psi[q * Nfp + c];
+    Mf[b][c] = s;
+  }
+  for (int t = tid; t < Nfp * m; t += 64) {
+    const int b = t / m, c = t % m;
+    double s = 0.0;
+    for (int q = 0; q < Nfq; ++q)
+      s += gf[(size_t)q * (1 + P.dim)] * psi[q * Nfp + b] * g[(size_t)c * NF + (size_t)ef * Nfq + q];
+    R[b][c] = s;
+  }
+  __syncthreads();
+  for (int i = 0; i < Nfp; ++i) {
+    const double inv = 1.0 / Mf[i][i];
+    __syncthreads();
+    // rows other than i: subtract their multiple of row i (row i itself is scaled after)
+    for (int t = tid; t < Nfp * (Nfp + m); t += 64) {
+      const int r = t / (Nfp + m), c = t % (Nfp + m);
+      if (r == i) continue;
+      const double l = Mf[r][i] * inv;
+      if (c < Nfp) {
+        if (c != i) Mf[r][c] -= l * Mf[i][c];
+      } else {
+        R[r][c - Nfp] -= l * R[i][c - Nfp];
+      }
+    }
+    __syncthreads();
+    for (int r = tid; r < Nfp; r += 64)
+      if (r != i) Mf[r][i] = 0.0;
+    __syncthreads();
+  }
+  for (int t = tid; t < Nfp * m; t += 64) {
+    const int b = t / m, c = t % m;
+    vbc[(size_t)c * P.n_trace + P.tmap[(size_t)ef * Nfp + b]] = R[b][c] / Mf[b][b];
+  }
+}
+
 // out[e] = (sum_q W_q rho s, sum_q W_q rho) at the states v_h(x_q), s = ln(p / rho^gamma):
 // the element's total thermodynamic entropy (minus the generalized entropy H = -rho s of the
 // entropy-variable section) and its mass
@@ -292,6 +418,26 @@ hipError_t launch_l2_error(const DevPlan &P, int kind, const double *f, const do
     hipLaunchKernelGGL(k_l2_error<2>, dim3(P.n_elem), dim3(64), 0, s, P, kind, f, ex, out);
   else
     hipLaunchKernelGGL(k_l2_error<3>, dim3(P.n_elem), dim3(64), 0, s, P, kind, f, ex, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_l2_error_visc(const DevPlan &P, const double *f, const double *ex, double *out, hipStream_t s) {
+  if (P.dim == 2)
+    hipLaunchKernelGGL(k_l2_error_visc<2>, dim3(P.n_elem), dim3(64), 0, s, P, f, ex, out);
+  else
+    hipLaunchKernelGGL(k_l2_error_visc<3>, dim3(P.n_elem), dim3(64), 0, s, P, f, ex, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_quad_coords(const DevPlan &P, double *xf, hipStream_t s) {
+  const size_t NF = (size_t)P.n_elem * P.nf * P.Nfq;
+  hipLaunchKernelGGL(k_face_quad_coords, dim3((unsigned)((NF + 255) / 256)), dim3(256), 0, s, P, xf);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_project(const DevPlan &P, const double *g, double *vbc, hipStream_t s) {
+  if (P.Nfp > PJ_NFP || P.m > 8) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trace_project, dim3((unsigned)((size_t)P.n_elem * P.nf)), dim3(64), 0, s, P, g, vbc);
   return hipGetLastError();
 }
 

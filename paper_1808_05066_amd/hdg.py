@@ -313,12 +313,25 @@ class Plan:
         check(self.lib.hdg_quad_coords(self.h, _ptr(xq), _stream()), "hdg_quad_coords")
         return xq
 
+    def face_quad_coords(self):
+        """Physical coordinates of the face quadrature points [dim][E*nf*Nfq]."""
+        xf = self._empty(self.dim, self.n_elem * self.nf * self.Nfq)
+        check(self.lib.hdg_face_quad_coords(self.h, _ptr(xf), _stream()), "hdg_face_quad_coords")
+        return xf
+
+    def trace_project(self, g, vbc):
+        """Face L2 projection of Dirichlet data g [m][E*nf*Nfq] (entropy variables at the face
+        quadrature points) into the Dirichlet faces' nodes of vbc [m][n_trace] (in place)."""
+        check(self.lib.hdg_trace_project(self.h, _ptr(g), _ptr(vbc), _stream()), "hdg_trace_project")
+        return vbc
+
     def l2_error(self, f, exact, kind="u"):
         """Per-component squared L2 errors summed over the elements (hdg_l2_error): kind "u"
         compares u(v_h) from v with exact conserved variables, kind "q" the gradient unknowns,
-        kind "v" the entropy variables."""
-        k = {"u": 0, "q": 1, "v": 2}[kind]
-        nc = self.m * self.dim if k == 1 else self.m
+        kind "v" the entropy variables, kind "stress" the viscous stress and heat flux formed
+        from f = [v; q] stacked against exact = [v; q] stacked at the quadrature points."""
+        k = {"u": 0, "q": 1, "v": 2, "stress": 3}[kind]
+        nc = self.m * self.dim if k == 1 else (self.dim * self.dim + self.dim if k == 3 else self.m)
         out = self._empty(self.n_elem, nc)
         check(self.lib.hdg_l2_error(self.h, k, _ptr(f), _ptr(exact), _ptr(out), _stream()), "hdg_l2_error")
         return out.sum(dim=0)
