@@ -159,6 +159,11 @@ int hdg_plan_dims(const hdg_plan *plan, hdg_dims *out);
  * until replaced; NULL removes it).  The element residual receives -(s_h, w) with s_h
  * the nodal interpolant at the volume quadrature points; the Jacobian is unchanged. */
 int hdg_plan_set_source(hdg_plan *plan, const double *src);
+/* The same source given by its values at the volume quadrature points, src [m][E*Nq]
+ * (hdg_quad_coords order; device, caller-owned, read at every assemble until replaced; NULL
+ * removes it): the element residual receives -sum_q W_q s(x_q) phi_a(x_q), the quadrature of
+ * (s, w) with s itself, as the oracle forms it. */
+int hdg_plan_set_source_points(hdg_plan *plan, const double *src);
 /* Physical coordinates of the volume quadrature points, xq [dim][E*Nq] (device),
  * element-major (e Nq + q): the image of the reference points under the element map. */
 int hdg_quad_coords(const hdg_plan *plan, double *xq, void *stream);

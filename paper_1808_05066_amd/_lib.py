@@ -125,6 +125,7 @@ SIGNATURES = {
     "hdg_dirk_step": (I, [P, P, P, P, P, ctypes.c_double, P, ctypes.c_size_t, ctypes.POINTER(hdg_newton_opts),
                           ctypes.POINTER(hdg_newton_info), P]),
     "hdg_plan_set_source": (I, [P, P]),
+    "hdg_plan_set_source_points": (I, [P, P]),
     "hdg_quad_coords": (I, [P, P, P]),
     "hdg_l2_error": (I, [P, I, P, P, P, P]),
     "hdg_face_quad_coords": (I, [P, P, P]),

@@ -7,7 +7,8 @@ points (hdg_quad_coords, hdg_l2_error).
   with rho0 = V0 = L = 1: the conserved variables (rho, momentum, rho E) and the stress and heat
   flux formed from v_h and q_h (tau* = tau / mu, f* = f / mu), besides the raw gradient
   unknowns q.  The Dirichlet data is the exact solution tested on each boundary face (its face
-  L2 projection, hdg_trace_project); bc="nodal" takes its nodal interpolant instead.
+  L2 projection, hdg_trace_project) and the source is evaluated at the volume quadrature points;
+  bc="nodal" takes the nodal interpolants of both instead.
 * Ringleb flow (Euler, Tables 3-5): the square (-5, -1) x (1, 5), h = 4 / n, the
   [L2(Omega)]^m norm of the error in the conserved variables, for HDG, IEDG and EDG traces.
 
@@ -48,9 +49,12 @@ def couette_run(n, p, scheme="hdg", tol=1e-9, atol=1e-10, maxit=20, lin_tol=1e-1
         gf, _, _ = state(plan.face_quad_coords().cpu().numpy(), False)
         plan.trace_project(gf, vbc)
         vhat = vbc.clone()
-    plan.set_source(torch.from_numpy(np.ascontiguousarray(f.source(xn))).to(dev))
-    info = plan.newton_solve(v, q, vhat, None, vbc, maxit=maxit, tol=tol, atol=atol, lin_tol=lin_tol)
     xq = plan.quad_coords().cpu().numpy()
+    if bc == "projection":
+        plan.set_source_points(torch.from_numpy(np.ascontiguousarray(f.source(xq))).to(dev))
+    else:
+        plan.set_source(torch.from_numpy(np.ascontiguousarray(f.source(xn))).to(dev))
+    info = plan.newton_solve(v, q, vhat, None, vbc, maxit=maxit, tol=tol, atol=atol, lin_tol=lin_tol)
     vex, qex, uex = state(xq, True)
     eu = torch.sqrt(plan.l2_error(v, uex, "u")).cpu().numpy()
     eq = torch.sqrt(plan.l2_error(q, qex, "q")).cpu().numpy()

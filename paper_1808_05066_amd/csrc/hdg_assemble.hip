@@ -39,11 +39,11 @@ __global__ __launch_bounds__(128) void k_vol_points(DevPlan P, int e0, int ec, c
     for (int a = 0; a < Np; ++a) {
       s += phi[a] * v[c * NN + nb + a];
       if (ustar) t += phi[a] * ustar[c * NN + nb + a];
-      if (P.src) f += phi[a] * P.src[c * NN + nb + a];
+      if (P.src && !P.src_qp) f += phi[a] * P.src[c * NN + nb + a];
     }
     vq[c] = s;
     us[c] = t;
-    sq[c] = f;
+    sq[c] = (P.src && P.src_qp) ? P.src[c * (size_t)P.n_elem * P.Nq + (size_t)e * P.Nq + qp] : f;
   }
   if (VISC)
     for (int s = 0; s < M * D; ++s) {

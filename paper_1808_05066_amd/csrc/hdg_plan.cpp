@@ -303,6 +303,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   D.contract_threads = 1024;
   D.zero_xcd = 1;
   D.src = nullptr;
+  D.src_qp = 0;
   D.row_drop = nullptr;
   D.ghat_v = (opts && (opts->flags & HDG_FLAG_GHAT_INTERIOR)) ? 1 : 0;
   D.ghat_proj = (opts && (opts->flags & HDG_FLAG_GHAT_PROJ)) ? 1 : 0;
@@ -391,6 +392,15 @@ extern "C" int hdg_plan_set_source(hdg_plan *plan, const double *src) {
   Plan *P = reinterpret_cast<Plan *>(plan);
   if (!P) return fail(HDG_EINVAL, "null plan");
   P->dp.src = src;
+  P->dp.src_qp = 0;
+  return HDG_OK;
+}
+
+extern "C" int hdg_plan_set_source_points(hdg_plan *plan, const double *src) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P) return fail(HDG_EINVAL, "null plan");
+  P->dp.src = src;
+  P->dp.src_qp = src ? 1 : 0;
   return HDG_OK;
 }
 

@@ -30,7 +30,8 @@ struct DevPlan {
                            // 2 sigma_MV (mean value between v_hat and v)
   int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
   double gamma, mu, Pr, alpha;
-  const double *src;       // [m][E*Np] nodal source of the conservation law (device, caller-owned) or null
+  const double *src;       // source of the conservation law (device, caller-owned) or null: nodal [m][E*Np],
+  int src_qp;              // or (src_qp = 1) its values at the volume quadrature points [m][E*Nq]
   PointLayout L;
   // tables (device)
   const double *phi;       // [Nq][Np]

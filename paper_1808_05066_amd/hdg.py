@@ -307,6 +307,12 @@ class Plan:
         self._src = src
         check(self.lib.hdg_plan_set_source(self.h, _ptr(src)), "hdg_plan_set_source")
 
+    def set_source_points(self, src):
+        """Source [m][E*Nq] at the volume quadrature points (quad_coords order), a device tensor
+        kept alive by the plan, or None to remove it."""
+        self._src = src
+        check(self.lib.hdg_plan_set_source_points(self.h, _ptr(src)), "hdg_plan_set_source_points")
+
     def quad_coords(self):
         """Physical coordinates of the volume quadrature points [dim][E*Nq]."""
         xq = self._empty(self.dim, self.n_elem * self.Nq)

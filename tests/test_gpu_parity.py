@@ -242,6 +242,34 @@ def test_source_term_matches_oracle(torch, name):
 
 
 @pytest.mark.parametrize("name", ["ns2d_tri_p2", "ns3d_hex_p1"])
+def test_source_at_quadrature_points_matches_oracle(torch, name):
+    """hdg_plan_set_source_points: a non-polynomial source given by its values at the GPU's volume
+    quadrature points; R_loc against the oracle's element residual with the same function
+    evaluated at its own quadrature points."""
+    wl, disc, inp, blocks = _case(name)
+    rng = np.random.default_rng(43)
+    coef = rng.standard_normal((disc.m, disc.d))
+
+    def src(x):   # x (Nq, d) -> (Nq, m)
+        return np.sin(x @ coef.T + np.arange(disc.m)[None, :])
+
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    xq = plan.quad_coords().cpu().numpy()
+    plan.set_source_points(torch.from_numpy(np.ascontiguousarray(src(xq.T).T)).cuda())
+    out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    torch.cuda.synchronize()
+    ref_R = []
+    for e in range(disc.mesh.n_elem):
+        x, lam, us, vb = disc.elem_inputs(e, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
+        R, _ = disc.element_residual(e, x[None], lam[None], us, vb, src)
+        ref_R.append(R[0])
+    err_R = rloc_err(disc, inp, out["R_loc"].cpu().numpy(), np.stack(ref_R))
+    print(name, "source at points: R_loc", err_R, flush=True)
+    assert err_R <= TOL
+
+
+@pytest.mark.parametrize("name", ["ns2d_tri_p2", "ns3d_hex_p1"])
 def test_interior_viscous_flux_matches_oracle(torch, name):
     """HDG_FLAG_GHAT_INTERIOR: viscous numerical flux G(v_h, q_h).n (the first of the two choices
     of Section 3.3).  All blocks, the residuals and the condensed outputs against the oracle with
