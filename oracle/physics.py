@@ -224,18 +224,69 @@ def sigma_s_apply(vh, n, gamma, dv):
     return abs_An_apply(vh, n, gamma, np.einsum("...ab,...b->...a", A0(vh, gamma), dv))
 
 
-# Gauss-Legendre points and weights on [0, 1] for the mean-value stabilization's theta integral
-MV_THETA = 0.5 * (1.0 + np.polynomial.legendre.leggauss(4)[0])
-MV_WEIGHT = 0.5 * np.polynomial.legendre.leggauss(4)[1]
+def _path_speeds(vh, v, th, n, gamma):
+    """Real wave speeds u_n - c, u_n, u_n + c (last axis) at the states vh + th (v - vh) (real
+    parts; th broadcasts against the leading axes)."""
+    vt = np.real(vh) + th[..., None] * (np.real(v) - np.real(vh))
+    rho, V, p = prim_of_v(vt, gamma)
+    un = (V * n).sum(-1)
+    c = np.sqrt(gamma * p / rho)
+    return np.stack([un - c, un, un + c], axis=-1)
+
+
+MV_SAMPLES = 32       # sub-intervals of [0, 1] searched for sign changes of the wave speeds
+MV_GAUSS = 12         # Gauss-Legendre points on every smooth piece
+
+
+def mv_breakpoints(vh, v, n, gamma):
+    """Sorted breakpoints (..., MV_SAMPLES + 4) in [0, 1] of the mean-value integrand along the
+    straight path vh + th (v - vh): 0, 1 and every root of u_n - c, u_n and u_n + c (where |A_n|
+    has a kink), found by bisection in the sub-intervals where a speed changes sign; unused
+    slots repeat 1.  At most one root per speed and sub-interval is resolved (a second one in
+    the same 1/32 of the path would be missed)."""
+    lead = np.broadcast_shapes(np.shape(np.real(vh))[:-1], np.shape(np.real(v))[:-1], np.shape(n)[:-1])
+    ts = np.linspace(0.0, 1.0, MV_SAMPLES + 1)
+    g = _path_speeds(vh[..., None, :], v[..., None, :], np.broadcast_to(ts, lead + ts.shape),
+                     n[..., None, :], gamma)                        # (..., S+1, 3)
+    sa, sb = g[..., :-1, :], g[..., 1:, :]
+    bracket = (sa * sb < 0) | ((sb == 0) & (sa != 0))
+    lo = np.broadcast_to(ts[:-1, None], bracket.shape).copy()
+    hi = np.broadcast_to(ts[1:, None], bracket.shape).copy()
+    flo = sa.copy()
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        gm = np.empty_like(mid)
+        for k in range(3):
+            gm[..., k] = _path_speeds(vh[..., None, :], v[..., None, :], mid[..., k], n[..., None, :], gamma)[..., k]
+        left = np.sign(gm) == np.sign(flo)
+        lo = np.where(left, mid, lo)
+        flo = np.where(left, gm, flo)
+        hi = np.where(left, hi, mid)
+    roots = np.where(bracket, 0.5 * (lo + hi), 1.0).reshape(lead + (-1,))
+    roots = np.sort(roots, axis=-1)[..., :3]                           # at most 3 kinks kept
+    if np.any(bracket.sum(axis=(-2, -1)) > 3):
+        raise ValueError("more than three wave-speed sign changes along a mean-value path")
+    ends = np.broadcast_to(np.array([0.0, 1.0]), lead + (2,))
+    return np.sort(np.concatenate([ends, roots], axis=-1), axis=-1)
 
 
 def sigma_mv_apply(vh, v, n, gamma, dv):
-    """Mean-value stabilization (Section 4) on the straight path in entropy variables,
-    sigma_MV(v_hat, v) = int_0^1 |A_n| A0 (v_hat + theta (v - v_hat)) dtheta (the two (1 - theta)
-    weighted integrals of the definition add up to this), applied to dv, by 4-point Gauss-Legendre."""
+    """Mean-value stabilization of Section 4 on the straight path in entropy variables,
+    sigma_MV(v_hat, v) = int_0^1 |A_n| A0 (v_hat + theta (v - v_hat)) d theta (the definition's two
+    (1 - theta) weighted integrals along the path and its reverse add up to this), applied to dv.
+    The integrand is smooth except where a wave speed u_n - c, u_n, u_n + c changes sign along
+    the path; the integral is split there (mv_breakpoints, on the real parts) and every piece is
+    integrated with MV_GAUSS-point Gauss-Legendre, exact to rounding.  Complex-step derivatives
+    pass through: the integrand is continuous at the breakpoints, so their motion adds nothing."""
+    br = mv_breakpoints(vh, v, n, gamma)                               # (..., 5)
+    x, w = np.polynomial.legendre.leggauss(MV_GAUSS)
     out = 0.0
-    for th, w in zip(MV_THETA, MV_WEIGHT):
-        out = out + w * sigma_s_apply(vh + th * (v - vh), n, gamma, dv)
+    for i in range(br.shape[-1] - 1):
+        a, b = br[..., i], br[..., i + 1]
+        for xg, wg in zip(x, w):
+            th = a + (b - a) * 0.5 * (1.0 + xg)
+            out = out + (0.5 * wg * (b - a))[..., None] * \
+                sigma_s_apply(vh + th[..., None] * (v - vh), n, gamma, dv)
     return out
 
 

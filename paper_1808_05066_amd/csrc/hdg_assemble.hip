@@ -119,7 +119,9 @@ __global__ __launch_bounds__(128) void k_vol_points(DevPlan P, int e0, int ec, c
   out[L.W] = W;
 }
 
-template <int D, bool VISC>
+// MV: the mean-value stabilization (its own instantiation: its path integral needs many
+// registers, which the other stabilizations should not pay for)
+template <int D, bool VISC, bool MV>
 __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, const double *__restrict__ v,
                                                       const double *__restrict__ q,
                                                       const double *__restrict__ vhat,
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(128) void k_face_points(DevPlan P, int e0, int ec, 
       }
     }
   }
-  if (P.sigma_s == 2) {
+  if (MV) {
     // mean-value stabilization: sigma depends on both states, so f_hat is differentiated with
     // respect to v_hat and to v in full (the values above are replaced)
     double gval[M];
@@ -616,8 +618,12 @@ hipError_t points_t(const DevPlan &P, int e0, int ec, const double *v, const dou
   hipError_t e = hipGetLastError();
   if (e) return e;
   int nfp = ec * P.nf * P.Nfq;
-  hipLaunchKernelGGL((k_face_points<D, VISC>), dim3((nfp + 127) / 128), dim3(128), 0, s, P, e0, ec, v, q, vhat,
-                     vbc, status);
+  if (P.sigma_s == 2)
+    hipLaunchKernelGGL((k_face_points<D, VISC, true>), dim3((nfp + 127) / 128), dim3(128), 0, s, P, e0, ec, v, q,
+                       vhat, vbc, status);
+  else
+    hipLaunchKernelGGL((k_face_points<D, VISC, false>), dim3((nfp + 127) / 128), dim3(128), 0, s, P, e0, ec, v, q,
+                       vhat, vbc, status);
   return hipGetLastError();
 }
 

@@ -209,25 +209,100 @@ __device__ inline void sigma_s_apply(const Prim<D, T> &s, const T *A0, const dou
   out[M - 1] = l1 * a1 * (H - c * un) + l2 * (a2 * 0.5 * kin + s.rho * vdVt) + l4 * a4 * (H + c * un);
 }
 
+// Wave speeds u_n - c, u_n, u_n + c at the state va + th (vb - va) (real values).
+template <int D>
+__device__ inline void path_speeds(const double *va, const double *vb, double th, const double *n, double gam,
+                                   double *g) {
+  const int M = D + 2;
+  double vt[M];
+  for (int c = 0; c < M; ++c) vt[c] = va[c] + th * (vb[c] - va[c]);
+  const Prim<D, double> st = prim_of_v<D, double>(vt, gam);
+  double un = 0.0;
+  for (int j = 0; j < D; ++j) un += st.V[j] * n[j];
+  const double c = sqrt(gam * st.p / st.rho);
+  g[0] = un - c;
+  g[1] = un;
+  g[2] = un + c;
+}
+
+// Breakpoints of the mean-value integrand along the straight path va + th (vb - va): 0, 1 and
+// the roots in between of the three wave speeds (kinks of |A_n|), located by sign changes over
+// MV_NS equal sub-intervals and bisection; sorted into br, returns their number (2..5).
+constexpr int MV_NS = 16;
+template <int D>
+__device__ inline int mv_breakpoints(const double *va, const double *vb, const double *n, double gam, double *br) {
+  int nb = 0;
+  double roots[3];
+  double ga[3], gb[3];
+  path_speeds<D>(va, vb, 0.0, n, gam, ga);
+  for (int j = 0; j < MV_NS; ++j) {
+    const double t0 = (double)j / MV_NS, t1 = (double)(j + 1) / MV_NS;
+    path_speeds<D>(va, vb, t1, n, gam, gb);
+    for (int k = 0; k < 3; ++k) {
+      if (!((ga[k] < 0.0 && gb[k] > 0.0) || (ga[k] > 0.0 && gb[k] < 0.0) || (gb[k] == 0.0 && ga[k] != 0.0))) continue;
+      double lo = t0, hi = t1, flo = ga[k];
+      for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        double gm[3];
+        path_speeds<D>(va, vb, mid, n, gam, gm);
+        if ((gm[k] > 0.0) == (flo > 0.0) && gm[k] != 0.0) {
+          lo = mid;
+          flo = gm[k];
+        } else {
+          hi = mid;
+        }
+      }
+      if (nb < 3) roots[nb++] = 0.5 * (lo + hi);
+    }
+    for (int k = 0; k < 3; ++k) ga[k] = gb[k];
+  }
+  br[0] = 0.0;
+  for (int i = 0; i < nb; ++i) {   // insertion into the sorted list
+    int p = i + 1;
+    while (p > 1 && br[p - 1] > roots[i]) {
+      br[p] = br[p - 1];
+      --p;
+    }
+    br[p] = roots[i];
+  }
+  br[nb + 1] = 1.0;
+  return nb + 2;
+}
+
 // Mean-value stabilization (Section 4) on the straight path in entropy variables:
 // sigma_MV(vh, v) dv = int_0^1 sigma_S(vh + th (v - vh)) dv dth (the definition's two (1 - th)
-// weighted integrals add up to this), 4-point Gauss-Legendre in th.
+// weighted integrals add up to this).  The integrand is smooth except where a wave speed changes
+// sign along the path; the integral is split there (breakpoints from the values of the states)
+// and each piece integrated with 8-point Gauss-Legendre.  Derivatives (T = Dual) need no term
+// for the moving breakpoints: the integrand is continuous across them.
 template <int D, typename T>
 __device__ inline void sigma_mv_apply(const T *vh, const T *v, const double *n, double gam, const T *dv, T *out) {
   const int M = D + 2;
-  const double x0 = 0.3399810435848563, x1 = 0.8611363115940526;
-  const double w0 = 0.6521451548625461, w1 = 0.3478548451374538;
-  const double th[4] = {0.5 * (1.0 - x1), 0.5 * (1.0 - x0), 0.5 * (1.0 + x0), 0.5 * (1.0 + x1)};
-  const double wt[4] = {0.5 * w1, 0.5 * w0, 0.5 * w0, 0.5 * w1};
+  // Gauss-Legendre, 8 points on [-1, 1] (nodes +-x_i, weights w_i)
+  const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+  const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+  double va[M], vb[M], br[5];
+  for (int c = 0; c < M; ++c) {
+    va[c] = val(vh[c]);
+    vb[c] = val(v[c]);
+  }
+  const int nb = mv_breakpoints<D>(va, vb, n, gam, br);
   for (int c = 0; c < M; ++c) out[c] = cst<T>(0.0);
-  for (int g = 0; g < 4; ++g) {
-    T vt[M];
-    for (int c = 0; c < M; ++c) vt[c] = vh[c] + th[g] * (v[c] - vh[c]);
-    const Prim<D, T> st = prim_of_v<D, T>(vt, gam);
-    T A[M * M], o[M];
-    A0_of_prim<D, T>(st, gam, A);
-    sigma_s_apply<D, T, T>(st, A, n, gam, dv, o);
-    for (int c = 0; c < M; ++c) out[c] = out[c] + wt[g] * o[c];
+  for (int i = 0; i + 1 < nb; ++i) {
+    const double a = br[i], h = br[i + 1] - br[i];
+    if (!(h > 0.0)) continue;
+    for (int g = 0; g < 8; ++g) {
+      const double x = (g < 4) ? -gx[3 - g] : gx[g - 4];
+      const double wq = 0.5 * h * ((g < 4) ? gw[3 - g] : gw[g - 4]);
+      const double th = a + 0.5 * h * (1.0 + x);
+      T vt[M];
+      for (int c = 0; c < M; ++c) vt[c] = vh[c] + th * (v[c] - vh[c]);
+      const Prim<D, T> st = prim_of_v<D, T>(vt, gam);
+      T A[M * M], o[M];
+      A0_of_prim<D, T>(st, gam, A);
+      sigma_s_apply<D, T, T>(st, A, n, gam, dv, o);
+      for (int c = 0; c < M; ++c) out[c] = out[c] + wq * o[c];
+    }
   }
 }
 

@@ -372,3 +372,44 @@ def test_symmetric_variable_stabilization_matches_oracle(torch, name, sigma):
     print(name, "S, Y: worst error / bound", worst, flush=True)
     _, _, _, base = _case(name)
     assert rel_err_per_elem(np.stack([b["A"] for b in blocks]), np.stack([b["A"] for b in base])) > 1e-6
+
+
+@pytest.mark.parametrize("name", ["ns2d_tri_p2", "euler3d_hex_p2"])
+def test_mean_value_stabilization_across_sign_changes(torch, name):
+    """sigma_MV where the wave speeds change sign between v_hat and v: the trace states carry the
+    reversed velocity, so u_n (and, where |u_n| is near c, u_n -/+ c) changes sign on the path at
+    most face points and the integrand has kinks there.  The GPU's split path integral against
+    the oracle's (both exact to rounding): blocks and residuals to 1e-12."""
+    from oracle import physics as oph
+    wl = SMALL_CASES[name]()
+    disc = oracle_disc(wl, sigma="mv")
+    inp = ostate.oracle_inputs(wl, disc)
+    rho, V, p = oph.prim_of_v(inp["vhat"].T, wl.gamma)
+    inp["vhat"] = np.ascontiguousarray(oph.v_of_prim(rho, -V, p, wl.gamma).T)
+    # the case exercises the kinks: count face points whose path has an inner breakpoint
+    kinks = 0
+    for e in range(disc.mesh.n_elem):
+        x, lam, _, _ = disc.elem_inputs(e, inp["v"], inp["q"], inp["vhat"])
+        G = disc.geom(e)
+        LN = lam.reshape(disc.nf, disc.m, disc.Nfp)
+        vN = x[:disc.m * disc.Np].reshape(disc.m, disc.Np)
+        for f in range(disc.nf):
+            F = G.faces[f]
+            br = oph.mv_breakpoints(F["psi"] @ LN[f].T, F["phi"] @ vN.T, F["n"], wl.gamma)
+            kinks += int(np.sum((br > 0) & (br < 1)))
+    assert kinks > disc.mesh.n_elem * disc.nf, kinks
+    blocks = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"],
+                                    keep_blocks=True)
+    plan = gpu_plan(wl, sigma="mv")
+    d = to_dev(inp)
+    out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    torch.cuda.synchronize()
+    errs = {
+        "R_loc": rloc_err(disc, inp, out["R_loc"].cpu().numpy(), np.stack([b["R_loc"] for b in blocks])),
+        "R_tr": rel_err_per_elem(out["R_tr"].cpu().numpy(), np.stack([b["R_tr"] for b in blocks])),
+    }
+    for key in ("A", "B", "C", "D"):
+        errs[key] = rel_err_per_elem(out[key].cpu().numpy(), colmajor([b[key] for b in blocks]))
+    print(name, "kinks", kinks, errs, flush=True)
+    for key, err in errs.items():
+        assert err <= TOL, (key, err)

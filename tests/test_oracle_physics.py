@@ -174,9 +174,9 @@ def test_abs_An_matches_the_eigen_decomposition():
 
 def test_mean_value_stabilization():
     """sigma_MV: equal to sigma_S when v = v_hat (the path is a point), symmetric positive
-    semi-definite, and its 4-point theta rule reproduces a fine (64-point) rule of the same
-    integral between nearby states where no wave speed changes sign along the path (the
-    integrand is then smooth; n along the velocity keeps V.n > 0)."""
+    semi-definite, symmetric in its two states (the definition's two path integrals), and equal
+    to a 64-point rule of the same integral between nearby states where no wave speed changes
+    sign along the path (the integrand is then smooth; n along the velocity keeps V.n > 0)."""
     rng = np.random.default_rng(5)
     for d in (2, 3):
         m = d + 2
@@ -190,9 +190,45 @@ def test_mean_value_stabilization():
         S = np.stack([P.sigma_mv_apply(vh, v, n, GAM, e) for e in np.eye(m)], axis=1)
         assert np.max(np.abs(S - S.T)) <= 1e-12 * np.max(np.abs(S))
         assert np.min(np.linalg.eigvalsh(0.5 * (S + S.T))) >= -1e-12 * np.max(np.abs(S))
+        assert np.allclose(P.sigma_mv_apply(v, vh, n, GAM, dv), P.sigma_mv_apply(vh, v, n, GAM, dv),
+                           rtol=1e-13, atol=1e-13)
         th, w = np.polynomial.legendre.leggauss(64)
         fine = sum(0.5 * wi * P.sigma_s_apply(vh + 0.5 * (1 + ti) * (v - vh), n, GAM, dv) for ti, wi in zip(th, w))
-        assert np.max(np.abs(P.sigma_mv_apply(vh, v, n, GAM, dv) - fine)) <= 1e-9 * np.max(np.abs(fine))
+        assert np.max(np.abs(P.sigma_mv_apply(vh, v, n, GAM, dv) - fine)) <= 1e-13 * np.max(np.abs(fine))
+
+
+@pytest.mark.parametrize("case", ["u_n", "u_n - c", "u_n + c", "two"])
+def test_mean_value_stabilization_across_sign_changes(case):
+    """Where a wave speed changes sign along the path, the integrand has a kink; the split
+    integral agrees with a composite trapezoidal rule on 40,000 intervals (error O(h^2) at a
+    kink, about 1e-10 of the integral here) to 1e-8, while a single 4-point Gauss rule across
+    the kink misses by more than 1e-5: a missed or misplaced breakpoint fails the first bound."""
+    rng = np.random.default_rng(11)
+    for d in (2, 3):
+        m = d + 2
+        n = np.zeros(d)
+        n[0] = 1.0
+        c0 = np.sqrt(GAM * 0.9 / 1.1)
+        u0, u1 = {"u_n": (-0.3, 0.4), "u_n - c": (c0 - 0.35, c0 + 0.3), "u_n + c": (-c0 - 0.3, -c0 + 0.25),
+                  "two": (-c0 - 0.2, 0.3)}[case]
+        V0 = np.array([u0, 0.2, -0.1][:d])
+        V1 = np.array([u1, -0.1, 0.15][:d])
+        vh = P.v_of_prim(np.array(1.1), V0, np.array(0.9), GAM)
+        v = P.v_of_prim(np.array(1.1), V1, np.array(0.9), GAM)
+        br = P.mv_breakpoints(vh, v, n, GAM)
+        inner = br[(br > 0) & (br < 1)]
+        assert len(inner) == (2 if case == "two" else 1), br
+        dv = rng.standard_normal(m)
+        got = P.sigma_mv_apply(vh, v, n, GAM, dv)
+        N = 40000
+        ts = np.linspace(0.0, 1.0, N + 1)
+        vals = P.sigma_s_apply(vh + ts[:, None] * (v - vh), n, GAM, dv)
+        trap = (vals[0] + vals[-1]) / (2 * N) + vals[1:-1].sum(0) / N
+        scale = np.max(np.abs(trap))
+        assert np.max(np.abs(got - trap)) <= 1e-8 * scale, (case, d, got, trap)
+        x4, w4 = np.polynomial.legendre.leggauss(4)
+        g4 = sum(0.5 * wi * P.sigma_s_apply(vh + 0.5 * (1 + ti) * (v - vh), n, GAM, dv) for ti, wi in zip(x4, w4))
+        assert np.max(np.abs(g4 - trap)) > 1e-5 * scale, (case, d)
 
 
 def test_stress_and_heat_flux_closed_form():
