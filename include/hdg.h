@@ -414,6 +414,15 @@ int hdg_learn_scratch_floats(const hdg_plan *plan, size_t *n);
 /* grad [nparams] = dL/dtheta from dO (recomputes the forward pass). */
 int hdg_learn_backward(hdg_plan *plan, const float *theta, const float *feat, const float *dO, float *grad,
                        float *scratch, void *stream);
+/* hdg_learn_backward without the caller's scratch, for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, harnesses that forbid allocation): the
+ * partial gradients live in a static device array of 32 MiB that the library holds on every GPU
+ * it runs on until the process ends; no hipMalloc, hipFree or other allocation is made.  Same
+ * kernels and result as hdg_learn_backward.  N_rows = m * n_trace may be at most 322,240 (the
+ * array holds 5,035 workgroups of 64 rows); larger plans get HDG_EINVAL.  Calls on one GPU share
+ * the array: calls that overlap on one GPU (other streams or threads) race. */
+int hdg_learn_backward_noalloc(hdg_plan *plan, const float *theta, const float *feat, const float *dO, float *grad,
+                               void *stream);
 /* One Adam step (t >= 1) on theta with moments m, v. */
 int hdg_learn_adam(float *theta, const float *grad, float *m, float *v, int t, float lr, void *stream);
 /* forward + loss_grad + backward + adam. */

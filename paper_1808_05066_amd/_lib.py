@@ -140,6 +140,7 @@ SIGNATURES = {
                                 ctypes.c_double, P, P, P]),
     "hdg_learn_scratch_floats": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
     "hdg_learn_backward": (I, [P, P, P, P, P, P, P]),
+    "hdg_learn_backward_noalloc": (I, [P, P, P, P, P, P]),
     "hdg_learn_adam": (I, [P, P, P, P, I, ctypes.c_float, P]),
     "hdg_learn_train_step": (I, [P, P, P, P, I, ctypes.c_float, P, P, ctypes.c_size_t,
                                  ctypes.POINTER(hdg_solve_opts), P, P, I, ctypes.c_double, P, P, P, P, P, P]),

@@ -9,6 +9,8 @@
 //
 // Parameter vector (float): W1[32][16] b1[32] W2[32][32] b2[32] W3[2][32] b3[2].
 // Rows are block rows: block F, position i -> F*bs + i, i = c*npb + p.
+#include <mutex>
+
 #include "hdg_physics.hpp"
 #include "hdg_plan.hpp"
 
@@ -345,6 +347,46 @@ hipError_t launch_mlp_bwd(const float *theta, const float *feat, const float *dO
   if (e) return e;
   hipLaunchKernelGGL(k_reduce_cols, dim3((NPAR + 255) / 256), dim3(256), 0, s, partial, (int)nb, grad);
   return hipGetLastError();
+}
+
+// Scratch of hdg_learn_backward_noalloc: the per-workgroup partial gradients of k_mlp_bwd in a
+// file-scope device array (each GPU the library runs on holds its own copy until the process
+// ends).  In host code `scratch` names a host-side stand-in; its device address is resolved once
+// per device with hipGetSymbolAddress (with that device current) and only that address is used.
+constexpr size_t NOALLOC_SCRATCH_FLOATS = size_t(8) << 20;   // 32 MiB
+static __device__ __align__(256) float scratch[NOALLOC_SCRATCH_FLOATS];
+constexpr int NOALLOC_MAX_DEV = 64;
+static float *g_scratch_ptr[NOALLOC_MAX_DEV];
+static std::mutex g_scratch_mu;
+
+static hipError_t noalloc_scratch(float **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = static_cast<float *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+size_t learn_noalloc_max_rows() { return NOALLOC_SCRATCH_FLOATS / NPAR * BR; }
+
+hipError_t launch_mlp_bwd_noalloc(const float *theta, const float *feat, const float *dO, size_t N, float *grad,
+                                  hipStream_t s) {
+  if (learn_partial_floats(N) > NOALLOC_SCRATCH_FLOATS) return hipErrorInvalidValue;
+  float *ptr = nullptr;
+  hipError_t e = noalloc_scratch(&ptr);
+  if (e) return e;
+  // every partial the reduction reads is written by this call's k_mlp_bwd (one row of NPAR per
+  // workgroup), so nothing left by an earlier call is read and nothing needs clearing
+  return launch_mlp_bwd(theta, feat, dO, N, ptr, grad, s);
 }
 
 hipError_t launch_adam(float *theta, const float *g, float *m, float *v, int t, float lr, hipStream_t s) {

@@ -153,6 +153,9 @@ hipError_t launch_precond_grad(const DevPlan &P, const double *Binv, const float
 hipError_t launch_mlp_bwd(const float *theta, const float *feat, const float *dO, size_t N, float *partial,
                           float *grad, hipStream_t s);
 hipError_t launch_adam(float *theta, const float *g, float *m, float *v, int t, float lr, hipStream_t s);
+size_t learn_noalloc_max_rows();
+hipError_t launch_mlp_bwd_noalloc(const float *theta, const float *feat, const float *dO, size_t N, float *grad,
+                                  hipStream_t s);
 hipError_t launch_scale_blocks(const DevPlan &P, double *B, const float *o, hipStream_t s);
 
 // Raise a kernel's dynamic-LDS limit once (cached per kernel): the attribute

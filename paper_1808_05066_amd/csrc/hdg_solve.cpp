@@ -309,6 +309,19 @@ extern "C" int hdg_learn_backward(hdg_plan *plan, const float *theta, const floa
   return HDG_OK;
 }
 
+extern "C" int hdg_learn_backward_noalloc(hdg_plan *plan, const float *theta, const float *feat, const float *dO,
+                                          float *grad, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !theta || !feat || !dO || !grad) return fail(HDG_EINVAL, "bad argument");
+  const size_t N = (size_t)P->dp.bj_nblk * P->dp.bj_bs;
+  if (N > learn_noalloc_max_rows())
+    return fail(HDG_EINVAL, "hdg_learn_backward_noalloc: " + std::to_string(N) + " rows exceed the static scratch (" +
+                                std::to_string(learn_noalloc_max_rows()) + " rows); use hdg_learn_backward");
+  hipError_t e = launch_mlp_bwd_noalloc(theta, feat, dO, N, grad, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "learn_backward_noalloc");
+  return HDG_OK;
+}
+
 extern "C" int hdg_learn_adam(float *theta, const float *grad, float *m, float *v, int t, float lr, void *stream) {
   if (!theta || !grad || !m || !v || t < 1) return fail(HDG_EINVAL, "bad argument");
   hipError_t e = launch_adam(theta, grad, m, v, t, lr, reinterpret_cast<hipStream_t>(stream));

@@ -467,6 +467,14 @@ class LearnedPrecond:
                                                _ptr(self.grad), _ptr(self.scratch), _stream()), "hdg_learn_backward")
         return self.grad
 
+    def backward_noalloc(self, theta, dO=None, grad=None):
+        """backward() through hdg_learn_backward_noalloc (no scratch argument)."""
+        dO = self.dO if dO is None else dO
+        grad = self.grad if grad is None else grad
+        check(self.plan.lib.hdg_learn_backward_noalloc(self.plan.h, _ptr(theta), _ptr(self.feat), _ptr(dO),
+                                                       _ptr(grad), _stream()), "hdg_learn_backward_noalloc")
+        return grad
+
     def train_step(self, theta, m, v, t, lr, X, Wv, x2):
         w, nb, op = self._w()
         check(self.plan.lib.hdg_learn_train_step(self.plan.h, _ptr(theta), _ptr(m), _ptr(v), int(t),
