@@ -25,6 +25,14 @@ __device__ inline d4 mfma4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Rows of a 16-column panel held in LDS (the rest of a taller panel stays in A itself).
+constexpr int LU_LDS_CAP = 160 * 1024 - 4 * 1024;
+constexpr int LU_RL = (LU_LDS_CAP / (PS * (int)sizeof(double))) / 16 * 16;   // 1168
+
+// BIG: panels taller than LU_RL rows keep their rows from LU_RL on in A (global memory, in
+// place): every panel access then goes through a generic pointer, which the LDS-only
+// instantiation avoids.
+template <bool BIG>
 __global__ __launch_bounds__(BLK) void k_lu(DevPlan P, int32_t *status) {
   extern __shared__ double sm[];
   __shared__ double redv[BLK];
@@ -37,8 +45,14 @@ __global__ __launch_bounds__(BLK) void k_lu(DevPlan P, int32_t *status) {
   bool singular = false;
   for (int j0 = 0; j0 < np; j0 += 16) {
     const int rows = np - j0;
-    for (int t = tid; t < rows * 16; t += BLK) {
-      const int i = t % rows, jj = t / rows;
+    const int rl = BIG ? (rows < LU_RL ? rows : LU_RL) : rows;   // rows of the panel in LDS
+    // entry (i, jj) of the panel: LDS below rl, A itself from rl on
+    const auto pe = [&](int i, int jj) -> double & {
+      if (BIG && i >= rl) return A[(size_t)(j0 + jj) * np + j0 + i];
+      return sm[i * PS + jj];
+    };
+    for (int t = tid; t < rl * 16; t += BLK) {
+      const int i = t % rl, jj = t / rl;
       sm[i * PS + jj] = A[(size_t)(j0 + jj) * np + j0 + i];
     }
     __syncthreads();
@@ -46,7 +60,7 @@ __global__ __launch_bounds__(BLK) void k_lu(DevPlan P, int32_t *status) {
       double best = -1.0;
       int bi = jj;
       for (int i = jj + tid; i < rows; i += BLK) {
-        const double a = fabs(sm[i * PS + jj]);
+        const double a = fabs(pe(i, jj));
         if (a > best) {
           best = a;
           bi = i;
@@ -71,23 +85,23 @@ __global__ __launch_bounds__(BLK) void k_lu(DevPlan P, int32_t *status) {
       if (zero) singular = true;
       if (!zero && piv != jj && tid < 16) {
         const double t0 = sm[jj * PS + tid];
-        sm[jj * PS + tid] = sm[piv * PS + tid];
-        sm[piv * PS + tid] = t0;
+        sm[jj * PS + tid] = pe(piv, tid);
+        pe(piv, tid) = t0;
       }
       if (tid == 0) ipiv[j0 + jj] = zero ? j0 + jj : j0 + piv;
       __syncthreads();
       if (!zero) {
         const double inv = 1.0 / sm[jj * PS + jj];
         for (int i = jj + 1 + tid; i < rows; i += BLK) {
-          const double l = sm[i * PS + jj] * inv;
-          sm[i * PS + jj] = l;
-          for (int c = jj + 1; c < 16; ++c) sm[i * PS + c] -= l * sm[jj * PS + c];
+          const double l = pe(i, jj) * inv;
+          pe(i, jj) = l;
+          for (int c = jj + 1; c < 16; ++c) pe(i, c) -= l * sm[jj * PS + c];
         }
       }
       __syncthreads();
     }
-    for (int t = tid; t < rows * 16; t += BLK) {
-      const int i = t % rows, jj = t / rows;
+    for (int t = tid; t < rl * 16; t += BLK) {
+      const int i = t % rl, jj = t / rl;
       A[(size_t)(j0 + jj) * np + j0 + i] = sm[i * PS + jj];
     }
     // row interchanges on the columns outside the panel
@@ -133,7 +147,8 @@ __global__ __launch_bounds__(BLK) void k_lu(DevPlan P, int32_t *status) {
       acc[3] = Ct[12];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const double a = -sm[(16 + ti * 16 + li) * PS + 4 * kk + lk];
+        const int pr = 16 + ti * 16 + li;   // panel row of the L21 entry
+        const double a = -(BIG && pr >= rl ? A[(size_t)(j0 + 4 * kk + lk) * np + j0 + pr] : sm[pr * PS + 4 * kk + lk]);
         const double b = A[(size_t)(col0 + li) * np + j0 + 4 * kk + lk];
         acc = mfma4(a, b, acc);
       }
@@ -306,13 +321,18 @@ __global__ void k_copy_resid(DevPlan P, int e0, double *Rl, double *Rtr) {
 
 }  // namespace
 
-size_t lu_lds_bytes(int np) { return (size_t)np * PS * sizeof(double); }
+// LDS of the split LU: the whole first panel where it fits, else LU_RL of its rows
+size_t lu_lds_bytes(int np) { return (size_t)(np < LU_RL ? np : LU_RL) * PS * sizeof(double); }
 
 hipError_t launch_lu(const DevPlan &P, int ec, int32_t *status, hipStream_t s) {
   const size_t lds = lu_lds_bytes(P.n_pad);
-  hipError_t e = set_dyn_lds((const void *)k_lu, lds);
+  const bool big = P.n_pad > LU_RL;
+  hipError_t e = set_dyn_lds(big ? (const void *)k_lu<true> : (const void *)k_lu<false>, lds);
   if (e) return e;
-  hipLaunchKernelGGL(k_lu, dim3(ec), dim3(BLK), lds, s, P, status);
+  if (big)
+    hipLaunchKernelGGL(k_lu<true>, dim3(ec), dim3(BLK), lds, s, P, status);
+  else
+    hipLaunchKernelGGL(k_lu<false>, dim3(ec), dim3(BLK), lds, s, P, status);
   return hipGetLastError();
 }
 

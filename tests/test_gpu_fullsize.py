@@ -145,3 +145,24 @@ def test_ns3d_hex_p2_16_trace_solve(torch, full):
     y = plan.trace_matvec(out["S"], x)
     res = float(torch.linalg.norm(rhs - y) / torch.linalg.norm(rhs))
     assert res <= 1.01e-10
+
+
+def test_p3_hex_fp64_condensation_sampled(torch):
+    """FP64 condensation of p = 3 hexahedra (n = 1280, k = 480, the block of the 32^3 mesh): the local
+    block does not fit the left-looking kernels' LDS, so the right-looking kernels run, with the
+    rows of the first panels beyond 1168 kept in the block itself; S, Y, g and R_tr of sampled
+    elements against the oracle to 1e-12, z by its backward error (1e-12) and forward error (1e-11)."""
+    wl = C.ns3d_hex(n=2, p=3, eps=0.05, jitter=0.05)
+    disc = oracle_disc(wl)
+    inp = ostate.oracle_inputs(wl, disc)
+    plan = gpu_plan(wl)
+    assert plan.dims["n"] == 1280 and plan.tuning()["condense_width"] == 0
+    dev = {k: (None if inp[k] is None else torch.from_numpy(np.ascontiguousarray(inp[k])).cuda())
+           for k in ("v", "q", "vhat", "ustar", "vbc")}
+    out = plan.assemble_condense(dev["v"], dev["q"], dev["vhat"], dev["ustar"], dev["vbc"], residuals=True)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().max()) == 0
+    sample = [0, 5]
+    ref = ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"], elems=sample,
+                                 keep_blocks=True)
+    check_sampled(disc, inp, out, sample, ref)
