@@ -249,6 +249,95 @@ def bench_batch(torch, tune=True):
     return res
 
 
+def c4_slabs(nslab=8):
+    """The 32^3 mesh of p = 3 hexahedra (32,768 elements, n = 1280, k = 480; Taylor-Green at Re 1600,
+    Mach 0.1, 5% noise, jitter 5%) cut into nslab slabs of whole cell layers along z: per-element
+    work (assembly, Jacobian, condensation) does not depend on the neighbours, so the slabs
+    together are the whole mesh's step; faces between slabs are trace faces of one element."""
+    import dataclasses
+
+    from workloads import meshes as M
+    full = C.ns3d_hex(n=32, p=3, eps=0.05, jitter=0.05, config_id=4)
+    zc = full.mesh.elem_lat[:, :, 2].min(axis=1)
+    per = 32 // nslab
+    out = []
+    for sl in range(nslab):
+        idx = np.nonzero((zc >= sl * per) & (zc < (sl + 1) * per))[0]
+        sub = M.subset_mesh(full.mesh, idx)
+        out.append(dataclasses.replace(full, name="%s_slab%d" % (full.name, sl), mesh=sub,
+                                       face_bc=np.zeros((len(idx), 6), dtype=np.int32), tmap=None, n_trace=0))
+    return out
+
+
+def bench_c4(torch, nslab=8, process=None, chunk=2048, tol=1e-10):
+    """FP64 against mixed precision on the 32^3 p = 3 mesh (all 32,768 elements, slab by slab).
+
+    FP64: hdg_assemble_condense (the right-looking kernels: the 1280-row block does not fit the
+    left-looking kernels' LDS).  Mixed: hdg_assemble_condense_lp (FP32 condensation on the matrix
+    cores after power-of-two scaling), then the element-level FP64 refinement hdg_refine_local of
+    A dx = -(R_loc + B P dvhat) for a seeded trace update dvhat to a per-element relative residual
+    <= tol.  Mixed elem/s = E / (t_factor_lp + t_refine_local).  Errors: FP32 outputs against the
+    FP64 GPU outputs (S, Y, g, z) and the refined dx against the FP64 back-solve -z - Y P dvhat."""
+    from paper_1808_05066_amd.inputs import device_inputs, plan_for
+    tot = {"fp64_ms": 0.0, "lp_ms": 0.0, "refine_ms": 0.0}
+    E = 0
+    worst = {"S": 0.0, "Y": 0.0, "g": 0.0, "z": 0.0, "dx": 0.0}
+    refine = {"steps_max": 0, "rel_residual_max": 0.0, "converged": True}
+    rng = np.random.default_rng([4, 9])
+
+    def rel(a, b):
+        return float(torch.linalg.norm(a.double() - b) / torch.linalg.norm(b))
+
+    slabs = c4_slabs(nslab)[:process]
+    for i, wl in enumerate(slabs):
+        print("[bench] c4 slab %d/%d: %d elements" % (i + 1, len(slabs), wl.mesh.n_elem), file=sys.stderr, flush=True)
+        plan = plan_for(wl, chunk_elems=chunk)
+        inp = device_inputs(plan, wl)
+        args = (inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
+        out = plan.alloc_outputs()
+        plan.assemble_condense(*args, out=out)
+        torch.cuda.synchronize()
+        if int((out["status"] != 0).sum()):
+            return {"error": "non-OK element status in the FP64 condensation (slab %d)" % i}
+        tot["fp64_ms"] += _timed(lambda: plan.assemble_condense(*args, out=out), 1, torch)
+        lp = plan.alloc_outputs_lp()
+        plan.assemble_condense_lp(*args, out=lp)
+        torch.cuda.synchronize()
+        if int((lp["status"] != 0).sum()):
+            return {"error": "non-OK element status in the FP32 condensation (slab %d)" % i}
+        tot["lp_ms"] += _timed(lambda: plan.assemble_condense_lp(*args, out=lp), 1, torch)
+        dl = torch.from_numpy(1e-3 * rng.standard_normal((plan.m, plan.n_trace))).cuda() * inp["vhat"].abs()
+        dx, info = plan.refine_local(*args[:3], lp, dl, ustar=inp["ustar"], vbc=inp["vbc"], tol=tol)
+        dx64 = plan.backsolve_elements(out["Y"], out["z"], dl)
+        torch.cuda.synchronize()
+        tot["refine_ms"] += info["total_ms"]
+        refine["steps_max"] = max(refine["steps_max"], info["outer_iterations"])
+        refine["rel_residual_max"] = max(refine["rel_residual_max"], info["rel_residual"])
+        refine["converged"] = refine["converged"] and bool(info["converged"])
+        for key in ("S", "Y", "g", "z"):
+            worst[key] = max(worst[key], rel(lp[key], out[key]))
+        worst["dx"] = max(worst["dx"], rel(dx, dx64))
+        E += plan.n_elem
+        n, k = plan.n, plan.k
+        del plan, inp, out, lp, dx, dx64, dl
+        torch.cuda.empty_cache()
+    fl = flops_per_elem(n, k, 64, 125, 5, 3, True)
+    dense = fl["lu"] + fl["solve"] + fl["schur"]
+    v64 = E / (tot["fp64_ms"] / 1e3)
+    vmix = E / ((tot["lp_ms"] + tot["refine_ms"]) / 1e3)
+    return {"workload": "ns3d_hex_p3_32: 32^3 periodic trilinear hexes, p = 3 (n = 1280, k = 480), Taylor-Green "
+                        "Re 1600 Mach 0.1, 5%% noise, jitter 5%%; %d of its %d slabs of %d elements" % (len(slabs), nslab, E // len(slabs)),
+            "elements": E, "n": n, "k": k,
+            "fp64": {"value": v64, "unit": "elem/s", "ms": tot["fp64_ms"],
+                     "dense_tflops": dense * E / (tot["fp64_ms"] / 1e3) / 1e12},
+            "mixed": {"value": vmix, "unit": "elem/s", "dtype": "f32 condensation + f64 element refinement",
+                      "t_factor_lp_ms": tot["lp_ms"], "t_refine_local_ms": tot["refine_ms"],
+                      "refine_tol": tol, **refine},
+            "speedup_mixed_vs_fp64": vmix / v64,
+            "rel_err_fp32_vs_fp64_gpu": worst,
+            "bf16": "not built: see the design notes"}
+
+
 def bench_learned(torch):
     """Held-out 24^3 p = 2 system: GMRES(50) to 1e-10 with plain and learned block Jacobi."""
     ck = os.path.join(ROOT, "paper_1808_05066_amd", "data", "learned_bj.npz")
@@ -335,6 +424,9 @@ def main():
     ap.add_argument("--no-eliminate-q", action="store_true",
                     help="skip the measurement of the condensation that eliminates q first")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 32^3 p = 3 FP64 / mixed comparison")
+    ap.add_argument("--c4-slabs", type=int, default=8, help="slabs of the 32^3 p = 3 mesh to process (of 8)")
+    ap.add_argument("--only-c4", action="store_true", help="run only the 32^3 p = 3 comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration under rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -348,6 +440,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.only_c4:
+        print(json.dumps({"c4": bench_c4(torch, nslab=8, process=args.c4_slabs)}))
         return
     from paper_1808_05066_amd.hdg import Plan
 

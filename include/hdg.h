@@ -496,6 +496,26 @@ int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q, const dou
                      double *dlam, void *work, size_t bytes, const hdg_refine_opts *opts,
                      hdg_refine_info *info, int32_t *elem_status, void *stream);
 
+/* Element-local back-solve dx [E][n] = -z - Y P dvhat in the element-local ordering (the
+ * layout of hdg_refine_solve / hdg_refine_local), FP64 Y [E][k][n] and z [E][n] of
+ * hdg_assemble_condense; dvhat [m][n_trace].  Device pointers. */
+int hdg_backsolve_elements(hdg_plan *plan, const double *Y, const double *z, const double *dvhat, double *dx,
+                           void *stream);
+
+/* Element-level refinement with a fixed trace update (the element version of the mixed-precision
+ * criterion, for meshes processed without a global solve): with the low-precision factors of
+ * hdg_assemble_condense_lp, solve per element  A dx = -(R_loc + B P dvhat)  by dx = 0; repeat
+ * dx += A_lp^-1 r, r = -(R_loc + A dx + B P dvhat) with A and B applied matrix-free in FP64
+ * (hdg_jacobian_apply), until max_K ||r_K|| / ||R_loc,K + B_K P_K dvhat|| <= tol or max_iter
+ * steps.  dx [E][n] element-local; info->rel_residual is that maximum, history[] per step,
+ * gmres fields 0.  reuse_points: the pointwise data of the last assembly of this plan are
+ * current (one chunk only).  Workspace: hdg_refine_local_workspace_bytes, 256-byte aligned. */
+int hdg_refine_local_workspace_bytes(const hdg_plan *plan, size_t *bytes);
+int hdg_refine_local(hdg_plan *plan, const double *v, const double *q, const double *vhat, const double *u_star,
+                     const double *v_bc, const float *factors, const double *R_loc, const double *dvhat, double *dx,
+                     void *work, size_t bytes, int max_iter, double tol, int reuse_points, hdg_refine_info *info,
+                     int32_t *elem_status, void *stream);
+
 /* ---- Newton iterations on the nonlinear system (library's own driver) ----
  * Solves R(v, q, vhat) = 0 for one implicit stage (the plan's alpha > 0 with the
  * previous-stage state u_star) or the steady problem (alpha = 0): R is the element

@@ -116,6 +116,10 @@ SIGNATURES = {
     "hdg_lp_solve": (I, [P, P, P, P, P]),
     "hdg_jacobian_apply": (I, [P, P, P, P, P, P, I, P, P, P, P, P, P]),
     "hdg_refine_workspace_bytes": (I, [P, ctypes.POINTER(hdg_refine_opts), ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_backsolve_elements": (I, [P, P, P, P, P, P]),
+    "hdg_refine_local_workspace_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_refine_local": (I, [P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, I, ctypes.c_double, I,
+                             ctypes.POINTER(hdg_refine_info), P, P]),
     "hdg_refine_solve": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t,
                              ctypes.POINTER(hdg_refine_opts), ctypes.POINTER(hdg_refine_info), P, P]),
     "hdg_newton_workspace_bytes": (I, [P, ctypes.POINTER(hdg_newton_opts), ctypes.POINTER(ctypes.c_size_t)]),

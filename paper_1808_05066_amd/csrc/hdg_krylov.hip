@@ -216,6 +216,35 @@ __global__ void k_scale_by(const double *__restrict__ x, const double *__restric
   out[t] = x[t] / s[0];
 }
 
+// Largest per-element ratio ||r_e|| / ||b_e|| over elements (r, b element-local [E][n]): one
+// workgroup per element, the ratio (non-negative, so its bits order as unsigned integers) merged
+// into *out by an atomic maximum; *out must start at 0.
+__global__ __launch_bounds__(RB) void k_elem_ratio_max(const double *__restrict__ r, const double *__restrict__ b, int n,
+                                                       unsigned long long *out) {
+  __shared__ double sr[RB], sb[RB];
+  const int e = blockIdx.x, tid = threadIdx.x;
+  double ar = 0.0, ab = 0.0;
+  for (int i = tid; i < n; i += RB) {
+    const double x = r[(size_t)e * n + i], y = b[(size_t)e * n + i];
+    ar += x * x;
+    ab += y * y;
+  }
+  sr[tid] = ar;
+  sb[tid] = ab;
+  __syncthreads();
+  for (int w = RB / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      sr[tid] += sr[tid + w];
+      sb[tid] += sb[tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double ratio = sb[0] > 0.0 ? sqrt(sr[0] / sb[0]) : (sr[0] > 0.0 ? INFINITY : 0.0);
+    atomicMax(out, (unsigned long long)__double_as_longlong(ratio));
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -252,6 +281,12 @@ hipError_t launch_block_apply(const DevPlan &P, const double *Binv, const double
   const int npb = P.bj_face ? P.Nfp : 1;
   hipLaunchKernelGGL(k_block_apply, dim3(P.bj_nblk), dim3(bs <= 64 ? 64 : 128), bs * sizeof(double), s, P, Binv, r,
                      z, bs, npb);
+  return hipGetLastError();
+}
+
+hipError_t launch_elem_ratio_max(const double *r, const double *b, int E, int n, unsigned long long *out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_elem_ratio_max, dim3(E), dim3(RB), 0, s, r, b, n, out);
   return hipGetLastError();
 }
 

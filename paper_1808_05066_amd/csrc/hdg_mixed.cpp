@@ -10,6 +10,7 @@
 // then delta += c and r = -R - J delta with J applied matrix-free in FP64.
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "hdg_plan.hpp"
@@ -266,5 +267,117 @@ extern "C" int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q
   }
   info->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   info->gmres_ms = gmres_ms;
+  return HDG_OK;
+}
+
+// ---- element-level refinement with a fixed trace update -------------------------------------
+namespace {
+
+struct LocalLayout {
+  size_t b, r, c, y, ytr, zero, ratio, total;
+};
+
+LocalLayout local_layout(const Plan *P) {
+  const size_t E = P->n_elem, n = P->dp.n, k = P->dp.k;
+  LocalLayout l{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o = a256(o + bytes);
+    return r;
+  };
+  l.b = take(E * n * 8);
+  l.r = take(E * n * 8);
+  l.c = take(E * n * 8);
+  l.y = take(E * n * 8);
+  l.ytr = take(E * k * 8);
+  l.zero = take(E * n * 8);
+  l.ratio = take(64);
+  l.total = o;
+  return l;
+}
+
+}  // namespace
+
+extern "C" int hdg_backsolve_elements(hdg_plan *plan, const double *Y, const double *z, const double *dvhat,
+                                      double *dx, void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  if (!Y || !z || !dvhat || !dx) return fail(HDG_EINVAL, "Y, z, dvhat and dx are required");
+  hipError_t e = launch_backsolve_elements(P->dp, Y, z, dvhat, dx, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "backsolve_elements");
+  return HDG_OK;
+}
+
+extern "C" int hdg_refine_local_workspace_bytes(const hdg_plan *plan, size_t *bytes) {
+  const Plan *P = reinterpret_cast<const Plan *>(plan);
+  if (!P || !bytes) return fail(HDG_EINVAL, "bad argument");
+  *bytes = local_layout(P).total;
+  return HDG_OK;
+}
+
+extern "C" int hdg_refine_local(hdg_plan *plan, const double *v, const double *q, const double *vhat,
+                                const double *ustar, const double *vbc, const float *factors, const double *Rloc,
+                                const double *dvhat, double *dx, void *work, size_t bytes, int max_iter, double tol,
+                                int reuse_points, hdg_refine_info *info, int32_t *status, void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  if (!factors || !Rloc || !dvhat || !dx || !work || !info || !status) return fail(HDG_EINVAL, "null argument");
+  if (max_iter < 1 || !(tol > 0.0)) return fail(HDG_EINVAL, "bad refinement options");
+  if (P->dp.ghat_proj) return fail(HDG_EUNSUPPORTED, "the matrix-free Jacobian has no projection viscous flux");
+  const LocalLayout l = local_layout(P);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "local refinement workspace too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char *base = static_cast<char *>(work);
+  double *b = reinterpret_cast<double *>(base + l.b);
+  double *r = reinterpret_cast<double *>(base + l.r);
+  double *c = reinterpret_cast<double *>(base + l.c);
+  double *y = reinterpret_cast<double *>(base + l.y);
+  double *ytr = reinterpret_cast<double *>(base + l.ytr);
+  double *zero = reinterpret_cast<double *>(base + l.zero);
+  unsigned long long *ratio = reinterpret_cast<unsigned long long *>(base + l.ratio);
+  const size_t E = P->n_elem, n = P->dp.n, NL = E * n;
+  const int reuse = reuse_points ? 1 : 0;
+  auto t0 = std::chrono::steady_clock::now();
+  // b = -(R_loc + B P dvhat)
+  hipError_t e = launch_fill_double(zero, NL, 0.0, s);
+  if (e) return hip_fail(e, "refine_local init");
+  int rc = hdg_jacobian_apply(plan, v, q, vhat, ustar, vbc, reuse, zero, dvhat, y, ytr, status, stream);
+  if (rc) return rc;
+  e = launch_axpby(-1.0, Rloc, -1.0, y, b, NL, s);
+  if (!e) e = launch_fill_double(dx, NL, 0.0, s);
+  if (!e) e = launch_axpby(1.0, b, 0.0, nullptr, r, NL, s);
+  if (e) return hip_fail(e, "refine_local init");
+  info->outer_iterations = 0;
+  info->gmres_iterations = 0;
+  info->converged = 0;
+  info->rel_residual = 1.0;
+  info->gmres_ms = 0.0;
+  for (int i = 0; i < 16; ++i) info->history[i] = 0.0;
+  for (int it = 0; it < max_iter; ++it) {
+    rc = hdg_lp_solve(plan, factors, r, c, stream);   // c = A_lp^-1 r
+    if (rc) return rc;
+    e = launch_axpby(1.0, dx, 1.0, c, dx, NL, s);
+    if (e) return hip_fail(e, "refine_local update");
+    rc = hdg_jacobian_apply(plan, v, q, vhat, ustar, vbc, 1, dx, dvhat, y, ytr, status, stream);
+    if (rc) return rc;
+    e = launch_axpby(-1.0, Rloc, -1.0, y, r, NL, s);   // r = -R_loc - (A dx + B P dvhat)
+    if (!e) e = launch_fill_double(reinterpret_cast<double *>(ratio), 1, 0.0, s);
+    if (!e) e = launch_elem_ratio_max(r, b, (int)E, (int)n, ratio, s);
+    unsigned long long hb = 0;
+    if (!e) e = hipMemcpyAsync(&hb, ratio, 8, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return hip_fail(e, "refine_local residual");
+    double rel;
+    std::memcpy(&rel, &hb, 8);
+    if (it < 16) info->history[it] = rel;
+    info->outer_iterations = it + 1;
+    info->rel_residual = rel;
+    if (rel <= tol) {
+      info->converged = 1;
+      break;
+    }
+  }
+  info->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return HDG_OK;
 }

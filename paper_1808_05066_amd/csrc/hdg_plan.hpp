@@ -192,6 +192,10 @@ hipError_t launch_jvp(const DevPlan &P, int e0, int ec, const double *dx, const 
 hipError_t launch_trace_matvec_f32(const DevPlan &P, const float *S, const double *x, double *y, hipStream_t s);
 hipError_t launch_backsolve_local_f32(const DevPlan &P, const float *Y, const double *a, const double *dvhat,
                                       double *out, hipStream_t s);
+hipError_t launch_backsolve_elements(const DevPlan &P, const double *Y, const double *z, const double *dvhat,
+                                     double *dx, hipStream_t s);
+hipError_t launch_elem_ratio_max(const double *r, const double *b, int E, int n, unsigned long long *out,
+                                 hipStream_t s);
 hipError_t launch_bj_assemble_f32(const DevPlan &P, const float *S, double *B, hipStream_t s);
 size_t condense_inv_doubles(int np);
 bool contract_mfma_supported(const DevPlan &P);

@@ -47,12 +47,14 @@ __global__ __launch_bounds__(1024) void k_backsolve(DevPlan P, const double *__r
   }
 }
 
-// out[e] = a[e] - Y_e P_e dlambda on element-local vectors [E][n] (refinement
-// loop of the mixed-precision path; Y in FP64 or FP32, arithmetic in FP64).
+// out[e] = sa a[e] - Y_e P_e dlambda on element-local vectors [E][n] (refinement
+// loop of the mixed-precision path with sa = 1; the back-solve dx = -z - Y P dlambda in the
+// element-local ordering with sa = -1; Y in FP64 or FP32, arithmetic in FP64).
 template <typename T>
 __global__ __launch_bounds__(1024) void k_backsolve_local(DevPlan P, const T *__restrict__ Y,
                                                           const double *__restrict__ a,
-                                                          const double *__restrict__ dvhat, double *out) {
+                                                          const double *__restrict__ dvhat, double *out,
+                                                          double sa) {
   extern __shared__ double xl[];
   const int e = blockIdx.x;
   const int n = P.n, k = P.k;
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(1024) void k_backsolve_local(DevPlan P, const T *__
   __syncthreads();
   const T *Ye = Y + (size_t)e * n * k;
   for (int row = threadIdx.x; row < n; row += blockDim.x) {
-    double acc = a[(size_t)e * n + row];
+    double acc = sa * a[(size_t)e * n + row];
     for (int col = 0; col < k; ++col) acc -= (double)Ye[(size_t)col * n + row] * xl[col];
     out[(size_t)e * n + row] = acc;
   }
@@ -169,8 +171,14 @@ hipError_t launch_trace_matvec_f32(const DevPlan &P, const float *S, const doubl
 hipError_t launch_backsolve_local_f32(const DevPlan &P, const float *Y, const double *a, const double *dvhat,
                                       double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_backsolve_local<float>, dim3(P.n_elem), dim3(matvec_threads(P.n)), P.k * sizeof(double), s, P,
-                     Y, a, dvhat,
-                     out);
+                     Y, a, dvhat, out, 1.0);
+  return hipGetLastError();
+}
+
+hipError_t launch_backsolve_elements(const DevPlan &P, const double *Y, const double *z, const double *dvhat,
+                                     double *dx, hipStream_t s) {
+  hipLaunchKernelGGL(k_backsolve_local<double>, dim3(P.n_elem), dim3(matvec_threads(P.n)), P.k * sizeof(double), s,
+                     P, Y, z, dvhat, dx, -1.0);
   return hipGetLastError();
 }
 

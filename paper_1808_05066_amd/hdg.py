@@ -256,6 +256,34 @@ class Plan:
         res["history"] = [info.history[i] for i in range(min(16, info.outer_iterations))]
         return dx, dlam, res
 
+    def backsolve_elements(self, Y, z, dvhat, dx=None):
+        """dx [E][n] = -z - Y P dvhat in the element-local ordering (FP64 Y, z)."""
+        if dx is None:
+            dx = self._empty(self.n_elem, self.n)
+        check(self.lib.hdg_backsolve_elements(self.h, _ptr(Y), _ptr(z), _ptr(dvhat), _ptr(dx), _stream()),
+              "hdg_backsolve_elements")
+        return dx
+
+    def refine_local(self, v, q, vhat, lp, dvhat, ustar=None, vbc=None, tol=1e-10, max_iter=10,
+                     reuse_points=False):
+        """Element-level refinement A dx = -(R_loc + B P dvhat) with the low-precision factors of
+        `lp` (hdg_refine_local).  Returns (dx [E][n], info dict)."""
+        torch = _torch()
+        nb = ctypes.c_size_t()
+        check(self.lib.hdg_refine_local_workspace_bytes(self.h, ctypes.byref(nb)), "hdg_refine_local_workspace_bytes")
+        work = torch.empty(int(nb.value) + 256, dtype=torch.uint8, device=self.device)
+        wp = ctypes.c_void_p(work.data_ptr() + (-work.data_ptr()) % 256)
+        dx = self._empty(self.n_elem, self.n)
+        info = _lib.hdg_refine_info()
+        status = torch.zeros(self.n_elem, dtype=torch.int32, device=self.device)
+        check(self.lib.hdg_refine_local(self.h, _ptr(v), _ptr(q), _ptr(vhat), _ptr(ustar), _ptr(vbc),
+                                        _ptr(lp["factors"]), _ptr(lp["R_loc"]), _ptr(dvhat), _ptr(dx), wp,
+                                        ctypes.c_size_t(nb.value), int(max_iter), float(tol), int(bool(reuse_points)),
+                                        ctypes.byref(info), _ptr(status), _stream()), "hdg_refine_local")
+        res = {f: getattr(info, f) for f, _ in _lib.hdg_refine_info._fields_ if f != "history"}
+        res["history"] = [info.history[i] for i in range(min(16, info.outer_iterations))]
+        return dx, res
+
     def newton_solve(self, v, q, vhat, ustar=None, vbc=None, maxit=10, tol=1e-10, atol=0.0, lin_tol=1e-12,
                      lin_restart=50, lin_maxit=2000, precond="block_jacobi"):
         """Newton iterations on the nonlinear system (hdg_newton_solve): v, q, vhat updated in

@@ -194,3 +194,26 @@ def test_large_block_p3_hex_fp32_and_refinement(torch):
                                        max_outer=12, gmres_tol=1e-8)
     print("p=3 hex refinement", info)
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["ns3d_hex_p2", "ns3d_hex_p3"])
+def test_element_refinement_with_fixed_trace_update(torch, name):
+    """hdg_refine_local (the element version of the mixed-precision criterion): with the FP32
+    factors, A dx = -(R_loc + B P dvhat) for a seeded dvhat converges to a per-element relative
+    residual <= 1e-10, and dx equals the FP64 element back-solve -z - Y P dvhat
+    (hdg_backsolve_elements) to 1e-9."""
+    wl = SMALL_CASES[name]() if name in SMALL_CASES else C.ns3d_hex(n=2, p=3, eps=0.05, jitter=0.05)
+    disc, inp = oracle_case(wl)
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    f64 = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    lp = plan.assemble_condense_lp(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    rng = np.random.default_rng(41)
+    dl = torch.from_numpy(1e-3 * rng.standard_normal((disc.m, wl.n_trace)) * np.abs(inp["vhat"])).cuda()
+    dx, info = plan.refine_local(d["v"], d["q"], d["vhat"], lp, dl, ustar=d["ustar"], vbc=d["vbc"], tol=1e-10)
+    dx64 = plan.backsolve_elements(f64["Y"], f64["z"], dl)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.norm(dx - dx64) / torch.linalg.norm(dx64))
+    print(name, info, "dx vs FP64 back-solve", err, flush=True)
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert err <= 1e-9
