@@ -56,28 +56,79 @@ def prepare_inputs(plan, wl, torch):
     return device_inputs(plan, wl)
 
 
-def cpu_baseline(wl, seconds_budget=20.0):
-    """Time the FP64 oracle on a bounded element sample of the same workload (1 BLAS thread)."""
-    from threadpoolctl import threadpool_limits
+_ORACLE = {}
 
+
+def _oracle_setup(wl):
     from oracle import hdg as ohdg
     from oracle import state as ostate
     disc = ohdg.Discretization(wl.mesh, wl.p, ohdg.Phys(wl.gamma, wl.mu, wl.Pr, wl.alpha, wl.viscous),
                                wl.tmap, wl.n_trace, wl.face_bc)
-    inp = ostate.oracle_inputs_fast(wl, disc)
+    _ORACLE.update(disc=disc, inp=ostate.oracle_inputs_fast(wl, disc))
+
+
+def _oracle_element(e):
+    """One element through the oracle (worker side; one BLAS thread)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import hdg as ohdg
+    disc, inp = _ORACLE["disc"], _ORACLE["inp"]
+    with threadpool_limits(limits=1):
+        ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"], elems=[int(e)])
+    return int(e)
+
+
+def _host_cores():
+    """Host cores this process may use (its affinity set), at most the 16 a one-GPU share holds."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, seconds_budget=20.0):
+    """Time the FP64 oracle on bounded element samples of the same workload: on one core (one BLAS
+    thread), then on all host cores with one worker process per core (elements are independent)."""
+    import multiprocessing as mp
+    _oracle_setup(wl)
     rng = np.random.default_rng(0)
     order = rng.permutation(wl.mesh.n_elem)
+    # one core
     done, t_used = 0, 0.0
-    with threadpool_limits(limits=1):
-        while t_used < seconds_budget and done < wl.mesh.n_elem:
-            e = int(order[done])
-            t0 = time.perf_counter()
-            ohdg.assemble_condense(disc, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"], elems=[e])
-            t_used += time.perf_counter() - t0
-            done += 1
-    return {"value": done / t_used, "unit": "elem/s", "cores": 1, "kind": "oracle",
-            "sample": "%d seeded-random elements of the same mesh, residual + complex-step Jacobian + "
-                      "LAPACK condensation, 1 BLAS thread, %.1f s" % (done, t_used)}
+    while t_used < 0.4 * seconds_budget and done < wl.mesh.n_elem:
+        t0 = time.perf_counter()
+        _oracle_element(order[done])
+        t_used += time.perf_counter() - t0
+        done += 1
+    one = done / t_used
+    # all cores: enough elements for about 0.6 of the budget at the one-core rate times the cores
+    cores = _host_cores()
+    count = int(min(wl.mesh.n_elem, max(cores, round(0.6 * seconds_budget * one * cores))))
+    sample = order[:count]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_element, sample[:cores])          # workers warm
+        t0 = time.perf_counter()
+        pool.map(_oracle_element, sample, chunksize=1)
+        wall = time.perf_counter() - t0
+    return {"value": count / wall, "unit": "elem/s", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "one_core": {"value": one, "unit": "elem/s", "cores": 1,
+                         "sample": "%d elements, %.1f s" % (done, t_used)},
+            "sample": "%d seeded-random elements of the same mesh on %d worker processes (one BLAS thread "
+                      "each), residual + complex-step Jacobian + LAPACK condensation, %.1f s wall"
+                      % (count, cores, wall)}
 
 
 def _timed(fn, reps, torch):
@@ -434,6 +485,11 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-element work shards by element partition; see the design notes).", file=sys.stderr)
         sys.exit(2)
+    # the CPU oracle runs first, in worker processes forked before this process touches the GPU
+    cpu_res = None
+    if not args.no_cpu_baseline and not args.copy_calibration and not args.only_c4:
+        print("[bench] timing the CPU oracle samples", file=sys.stderr, flush=True)
+        cpu_res = cpu_baseline(WORKLOADS[args.workload][1](), args.cpu_seconds)
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -551,14 +607,17 @@ def main():
     if not args.no_learned:
         print("[bench] learned preconditioner on a held-out system", file=sys.stderr, flush=True)
         res["learned_precond"] = bench_learned(torch)
+    out = inp = plan = None   # release the measured mesh before the larger legs
+    torch.cuda.empty_cache()
     if not args.no_batch:
-        del out, inp, plan
-        torch.cuda.empty_cache()
         print("[bench] mixed tetrahedron/hexahedron batch", file=sys.stderr, flush=True)
         res["batch"] = bench_batch(torch)
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    if not args.no_c4:
+        print("[bench] 32^3 p = 3 mesh: FP64 against mixed precision", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        res["c4"] = bench_c4(torch, nslab=8, process=args.c4_slabs)
+    if cpu_res is not None:
+        res["cpu_baseline"] = cpu_res
     print(json.dumps(res))
 
 

@@ -241,6 +241,17 @@ int hdg_assemble(hdg_plan *plan, const double *v, const double *q, const double 
                  double *A, double *B, double *C, double *D, double *R_loc, double *R_tr,
                  int32_t *elem_status, void *stream);
 
+/* Static condensation of caller-supplied element blocks (local elimination remark of
+ * Section 3.3): for every element, S = D - C A^-1 B, g = -R_tr + C A^-1 R_loc,
+ * Y = A^-1 B, z = A^-1 R_loc with the kernels of hdg_assemble_condense.  Blocks in the
+ * compact layout hdg_assemble exports (A [E][n][n], B [E][k][n], C [E][n][k], D [E][k][k],
+ * R_loc [E][n], R_tr [E][k], column-major); outputs as hdg_assemble_condense.  A zero pivot
+ * sets elem_status[e] = HDG_ESINGULAR (the outputs of that element are then meaningless).
+ * Uses the plan's workspace; device pointers. */
+int hdg_condense_blocks(hdg_plan *plan, const double *A, const double *B, const double *C, const double *D,
+                        const double *R_loc, const double *R_tr, double *S, double *g, double *Y, double *z,
+                        int32_t *elem_status, void *stream);
+
 /* The hot path.  For every element: residual R_loc, R_tr and Jacobian blocks
  * [A B; C D] of the Newton system [A B; C D][dx; dlambda] = -[R_loc; R_tr],
  * LU of A with partial pivoting, and
@@ -481,6 +492,7 @@ typedef struct {
   double rel_residual;    /* ||J delta + R|| / ||R|| of the returned delta */
   double total_ms, gmres_ms;   /* host wall time: whole call; global solves incl. preconditioner setup */
   double history[16];     /* relative residual after each refinement step */
+  int fallback_elements;  /* hdg_refine_local: elements solved by the FP64 fallback */
 } hdg_refine_info;
 
 int hdg_refine_workspace_bytes(const hdg_plan *plan, const hdg_refine_opts *opts, size_t *bytes);
@@ -506,9 +518,11 @@ int hdg_backsolve_elements(hdg_plan *plan, const double *Y, const double *z, con
  * criterion, for meshes processed without a global solve): with the low-precision factors of
  * hdg_assemble_condense_lp, solve per element  A dx = -(R_loc + B P dvhat)  by dx = 0; repeat
  * dx += A_lp^-1 r, r = -(R_loc + A dx + B P dvhat) with A and B applied matrix-free in FP64
- * (hdg_jacobian_apply), until max_K ||r_K|| / ||R_loc,K + B_K P_K dvhat|| <= tol or max_iter
- * steps.  dx [E][n] element-local; info->rel_residual is that maximum, history[] per step,
- * gmres fields 0.  reuse_points: the pointwise data of the last assembly of this plan are
+ * (hdg_jacobian_apply), until max_K ||r_K|| / ||R_loc,K + B_K P_K dvhat|| <= tol, max_iter
+ * steps, or a step that does not halve that maximum (stagnation).  Short of tol, the elements
+ * still above it fall back to FP64: their blocks are re-assembled in full and solved with the
+ * FP64 LU (right-looking kernels); info->fallback_elements counts them.  dx [E][n]
+ * element-local; info->rel_residual is the final maximum, history[] per step, gmres fields 0.  reuse_points: the pointwise data of the last assembly of this plan are
  * current (one chunk only).  Workspace: hdg_refine_local_workspace_bytes, 256-byte aligned. */
 int hdg_refine_local_workspace_bytes(const hdg_plan *plan, size_t *bytes);
 int hdg_refine_local(hdg_plan *plan, const double *v, const double *q, const double *vhat, const double *u_star,

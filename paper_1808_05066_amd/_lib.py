@@ -66,7 +66,7 @@ class hdg_newton_info(ctypes.Structure):
 class hdg_refine_info(ctypes.Structure):
     _fields_ = [("outer_iterations", ctypes.c_int), ("gmres_iterations", ctypes.c_int), ("converged", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("total_ms", ctypes.c_double), ("gmres_ms", ctypes.c_double),
-                ("history", ctypes.c_double * 16)]
+                ("history", ctypes.c_double * 16), ("fallback_elements", ctypes.c_int)]
 
 
 class hdg_solve_info(ctypes.Structure):
@@ -102,6 +102,7 @@ SIGNATURES = {
     "hdg_node_coords": (I, [P, P, P, P]),
     "hdg_prepare_state": (I, [P, I, P, P, P, P, P, P]),
     "hdg_assemble": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
+    "hdg_condense_blocks": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P]),
     "hdg_assemble_condense": (I, [P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
     "hdg_backsolve": (I, [P, P, P, P, P, P, P]),
     "hdg_trace_matvec": (I, [P, P, P, P, P]),

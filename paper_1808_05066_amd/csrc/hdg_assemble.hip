@@ -600,6 +600,58 @@ __global__ void k_export(DevPlan P, int e0, int ec, double *A, double *B, double
     if (Rtr) Rtr[(size_t)e * k + i] = Ri[i];
 }
 
+// The inverse of k_export: caller blocks (compact, column-major) into the workspace of the
+// condensation, with the padding of A set to the identity and every other padding entry zero.
+__global__ void k_import(DevPlan P, int e0, const double *A, const double *B, const double *C, const double *Dm,
+                         const double *Rl, const double *Rtr) {
+  const int el = blockIdx.x, e = e0 + el;
+  const int n = P.n, k = P.k, np = P.n_pad, kp = P.k_pad, kx = P.kx;
+  double *Ai = P.A + (size_t)el * np * np;
+  double *Xi = P.X + (size_t)el * kx * np;
+  double *Ci = P.C + (size_t)el * np * kp;
+  double *Di = P.D + (size_t)el * kp * kp;
+  double *Ri = P.Rt + (size_t)el * kp;
+  for (size_t i = threadIdx.x; i < (size_t)np * np; i += blockDim.x) {
+    const size_t col = i / np, row = i % np;
+    Ai[i] = (row < (size_t)n && col < (size_t)n) ? A[(size_t)e * n * n + col * n + row] : (row == col ? 1.0 : 0.0);
+  }
+  for (size_t i = threadIdx.x; i < (size_t)kx * np; i += blockDim.x) {
+    const size_t col = i / np, row = i % np;
+    double v = 0.0;
+    if (row < (size_t)n) {
+      if (col < (size_t)k) v = B[(size_t)e * n * k + col * n + row];
+      else if (col == (size_t)kp) v = Rl[(size_t)e * n + row];
+    }
+    Xi[i] = v;
+  }
+  for (size_t i = threadIdx.x; i < (size_t)np * kp; i += blockDim.x) {
+    const size_t col = i / kp, row = i % kp;
+    Ci[i] = (row < (size_t)k && col < (size_t)n) ? C[(size_t)e * n * k + col * k + row] : 0.0;
+  }
+  for (size_t i = threadIdx.x; i < (size_t)kp * kp; i += blockDim.x) {
+    const size_t col = i / kp, row = i % kp;
+    Di[i] = (row < (size_t)k && col < (size_t)k) ? Dm[(size_t)e * k * k + col * k + row] : 0.0;
+  }
+  for (int i = threadIdx.x; i < kp; i += blockDim.x) Ri[i] = i < k ? Rtr[(size_t)e * k + i] : 0.0;
+}
+
+// FP64 fallback of the element-level refinement: column 0 of X <- b (rows of the element, zero
+// padding), so the right-looking solve leaves A^-1 b there ...
+__global__ void k_fallback_rhs(DevPlan P, int e0, const double *b) {
+  const int el = blockIdx.x, e = e0 + el;
+  double *X0 = P.X + (size_t)el * P.kx * P.n_pad;
+  for (int i = threadIdx.x; i < P.n_pad; i += blockDim.x) X0[i] = i < P.n ? b[(size_t)e * P.n + i] : 0.0;
+}
+
+// ... and dx[e] <- that column for the elements whose refinement ratio exceeds tol (counted).
+__global__ void k_fallback_take(DevPlan P, int e0, const double *ratio, double tol, double *dx, int *count) {
+  const int el = blockIdx.x, e = e0 + el;
+  if (!(ratio[e] > tol)) return;   // whole workgroup
+  const double *X0 = P.X + (size_t)el * P.kx * P.n_pad;
+  for (int i = threadIdx.x; i < P.n; i += blockDim.x) dx[(size_t)e * P.n + i] = X0[i];
+  if (threadIdx.x == 0) atomicAdd(count, 1);
+}
+
 __global__ void k_fill_int(int32_t *p, int n, int val) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = val;
@@ -665,6 +717,23 @@ hipError_t launch_contract(const DevPlan &P, int e0, int ec, hipStream_t s) {
 hipError_t launch_export_blocks(const DevPlan &P, int e0, int ec, double *A, double *B, double *C, double *D,
                                 double *Rloc, double *Rtr, hipStream_t s) {
   hipLaunchKernelGGL(k_export, dim3(ec), dim3(256), 0, s, P, e0, ec, A, B, C, D, Rloc, Rtr);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_blocks(const DevPlan &P, int e0, int ec, const double *A, const double *B, const double *C,
+                                const double *D, const double *Rloc, const double *Rtr, hipStream_t s) {
+  hipLaunchKernelGGL(k_import, dim3(ec), dim3(256), 0, s, P, e0, A, B, C, D, Rloc, Rtr);
+  return hipGetLastError();
+}
+
+hipError_t launch_fallback_rhs(const DevPlan &P, int e0, int ec, const double *b, hipStream_t s) {
+  hipLaunchKernelGGL(k_fallback_rhs, dim3(ec), dim3(256), 0, s, P, e0, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_fallback_take(const DevPlan &P, int e0, int ec, const double *ratio, double tol, double *dx,
+                                int *count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fallback_take, dim3(ec), dim3(256), 0, s, P, e0, ratio, tol, dx, count);
   return hipGetLastError();
 }
 

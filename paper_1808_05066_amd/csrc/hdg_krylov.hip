@@ -218,9 +218,9 @@ __global__ void k_scale_by(const double *__restrict__ x, const double *__restric
 
 // Largest per-element ratio ||r_e|| / ||b_e|| over elements (r, b element-local [E][n]): one
 // workgroup per element, the ratio (non-negative, so its bits order as unsigned integers) merged
-// into *out by an atomic maximum; *out must start at 0.
+// into *out by an atomic maximum (*out must start at 0); per[e] the ratio itself, if per is given.
 __global__ __launch_bounds__(RB) void k_elem_ratio_max(const double *__restrict__ r, const double *__restrict__ b, int n,
-                                                       unsigned long long *out) {
+                                                       unsigned long long *out, double *per) {
   __shared__ double sr[RB], sb[RB];
   const int e = blockIdx.x, tid = threadIdx.x;
   double ar = 0.0, ab = 0.0;
@@ -242,6 +242,7 @@ __global__ __launch_bounds__(RB) void k_elem_ratio_max(const double *__restrict_
   if (tid == 0) {
     const double ratio = sb[0] > 0.0 ? sqrt(sr[0] / sb[0]) : (sr[0] > 0.0 ? INFINITY : 0.0);
     atomicMax(out, (unsigned long long)__double_as_longlong(ratio));
+    if (per) per[e] = ratio;
   }
 }
 
@@ -285,8 +286,8 @@ hipError_t launch_block_apply(const DevPlan &P, const double *Binv, const double
 }
 
 hipError_t launch_elem_ratio_max(const double *r, const double *b, int E, int n, unsigned long long *out,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_elem_ratio_max, dim3(E), dim3(RB), 0, s, r, b, n, out);
+                                 double *per, hipStream_t s) {
+  hipLaunchKernelGGL(k_elem_ratio_max, dim3(E), dim3(RB), 0, s, r, b, n, out, per);
   return hipGetLastError();
 }
 

@@ -221,6 +221,7 @@ extern "C" int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q
   const double Rn = std::sqrt(a + b);
   info->outer_iterations = 0;
   info->gmres_iterations = 0;
+  info->fallback_elements = 0;
   info->rel_residual = Rn > 0.0 ? 1.0 : 0.0;
   info->converged = Rn == 0.0 ? 1 : 0;
   for (int i = 0; i < 16; ++i) info->history[i] = 0.0;
@@ -274,7 +275,7 @@ extern "C" int hdg_refine_solve(hdg_plan *plan, const double *v, const double *q
 namespace {
 
 struct LocalLayout {
-  size_t b, r, c, y, ytr, zero, ratio, total;
+  size_t b, r, c, y, ytr, zero, ratio, per, count, total;
 };
 
 LocalLayout local_layout(const Plan *P) {
@@ -293,6 +294,8 @@ LocalLayout local_layout(const Plan *P) {
   l.ytr = take(E * k * 8);
   l.zero = take(E * n * 8);
   l.ratio = take(64);
+  l.per = take(E * 8);
+  l.count = take(64);
   l.total = o;
   return l;
 }
@@ -354,6 +357,20 @@ extern "C" int hdg_refine_local(hdg_plan *plan, const double *v, const double *q
   info->rel_residual = 1.0;
   info->gmres_ms = 0.0;
   for (int i = 0; i < 16; ++i) info->history[i] = 0.0;
+  double* per = reinterpret_cast<double *>(base + l.per);
+  int *count = reinterpret_cast<int *>(base + l.count);
+  // max_K ||r_K|| / ||b_K|| of the current r (and per element into `per`)
+  auto ratio_of = [&](double &rel) -> hipError_t {
+    hipError_t ee = launch_fill_double(reinterpret_cast<double *>(ratio), 1, 0.0, s);
+    if (!ee) ee = launch_elem_ratio_max(r, b, (int)E, (int)n, ratio, per, s);
+    unsigned long long hb = 0;
+    if (!ee) ee = hipMemcpyAsync(&hb, ratio, 8, hipMemcpyDeviceToHost, s);
+    if (!ee) ee = hipStreamSynchronize(s);
+    std::memcpy(&rel, &hb, 8);
+    return ee;
+  };
+  info->fallback_elements = 0;
+  double prev = 1.0;
   for (int it = 0; it < max_iter; ++it) {
     rc = hdg_lp_solve(plan, factors, r, c, stream);   // c = A_lp^-1 r
     if (rc) return rc;
@@ -362,14 +379,9 @@ extern "C" int hdg_refine_local(hdg_plan *plan, const double *v, const double *q
     rc = hdg_jacobian_apply(plan, v, q, vhat, ustar, vbc, 1, dx, dvhat, y, ytr, status, stream);
     if (rc) return rc;
     e = launch_axpby(-1.0, Rloc, -1.0, y, r, NL, s);   // r = -R_loc - (A dx + B P dvhat)
-    if (!e) e = launch_fill_double(reinterpret_cast<double *>(ratio), 1, 0.0, s);
-    if (!e) e = launch_elem_ratio_max(r, b, (int)E, (int)n, ratio, s);
-    unsigned long long hb = 0;
-    if (!e) e = hipMemcpyAsync(&hb, ratio, 8, hipMemcpyDeviceToHost, s);
-    if (!e) e = hipStreamSynchronize(s);
+    double rel = 0.0;
+    if (!e) e = ratio_of(rel);
     if (e) return hip_fail(e, "refine_local residual");
-    double rel;
-    std::memcpy(&rel, &hb, 8);
     if (it < 16) info->history[it] = rel;
     info->outer_iterations = it + 1;
     info->rel_residual = rel;
@@ -377,6 +389,41 @@ extern "C" int hdg_refine_local(hdg_plan *plan, const double *v, const double *q
       info->converged = 1;
       break;
     }
+    if (rel > 0.5 * prev) break;   // stagnating: the low-precision factors cannot reach tol
+    prev = rel;
+  }
+  if (!info->converged) {
+    // per-element FP64 fallback: the elements still above tol are solved with the FP64 LU of their
+    // block (re-assembled in full, right-looking kernels); the others keep the refined dx
+    DevPlan Dp = P->dp;
+    Dp.mg = nullptr;
+    Dp.uinfo = nullptr;
+    e = launch_fill_int(count, 1, 0, s);
+    if (e) return hip_fail(e, "refine_local fallback");
+    for (int e0 = 0; e0 < P->n_elem; e0 += P->chunk) {
+      const int ec = std::min(P->chunk, P->n_elem - e0);
+      rc = run_front(P, v, q, vhat, ustar, vbc, status, e0, ec, s, false);
+      if (rc) return rc;
+      P->xcd_clean = false;   // X is overwritten below
+      e = launch_fallback_rhs(Dp, e0, ec, b, s);
+      if (!e) e = launch_lu(Dp, ec, status + e0, s);
+      if (!e) e = launch_solve(Dp, ec, s);
+      if (!e) e = launch_fallback_take(Dp, e0, ec, per, tol, dx, count, s);
+      if (e) return hip_fail(e, "refine_local fallback");
+    }
+    int hc = 0;
+    e = hipMemcpyAsync(&hc, count, 4, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return hip_fail(e, "refine_local fallback");
+    info->fallback_elements = hc;
+    rc = hdg_jacobian_apply(plan, v, q, vhat, ustar, vbc, 0, dx, dvhat, y, ytr, status, stream);
+    if (rc) return rc;
+    e = launch_axpby(-1.0, Rloc, -1.0, y, r, NL, s);
+    double rel = 0.0;
+    if (!e) e = ratio_of(rel);
+    if (e) return hip_fail(e, "refine_local fallback residual");
+    info->rel_residual = rel;
+    info->converged = rel <= tol ? 1 : 0;
   }
   info->total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return HDG_OK;

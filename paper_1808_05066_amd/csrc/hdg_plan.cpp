@@ -842,6 +842,35 @@ extern "C" int hdg_assemble(hdg_plan *plan, const double *v, const double *q, co
   return HDG_OK;
 }
 
+extern "C" int hdg_condense_blocks(hdg_plan *plan, const double *A, const double *B, const double *C,
+                                   const double *D, const double *Rloc, const double *Rtr, double *S, double *g,
+                                   double *Y, double *z, int32_t *status, void *stream) {
+  Plan *P = checked(plan);
+  if (!P) return HDG_EINVAL;
+  if (!A || !B || !C || !D || !Rloc || !Rtr || !S || !g || !Y || !z || !status)
+    return fail(HDG_EINVAL, "every block, output and elem_status is required");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_fill_int(status, P->n_elem, HDG_OK, s);
+  if (e) return hip_fail(e, "status init");
+  DevPlan Dp = P->dp;
+  Dp.mg = nullptr;       // A is stored whole
+  Dp.uinfo = nullptr;
+  P->xcd_clean = false;  // X, C and D now hold the caller's blocks
+  for (int e0 = 0; e0 < P->n_elem; e0 += P->chunk) {
+    const int ec = std::min(P->chunk, P->n_elem - e0);
+    e = launch_import_blocks(Dp, e0, ec, A, B, C, D, Rloc, Rtr, s);
+    if (!e && P->fused) {
+      e = condense_chunk(P, Dp, e0, ec, status + e0, S, g, Y, z, s);
+    } else if (!e) {
+      e = launch_lu(Dp, ec, status + e0, s);
+      if (!e) e = launch_solve(Dp, ec, s);
+      if (!e) e = launch_schur(Dp, e0, ec, S, g, Y, z, nullptr, nullptr, s);
+    }
+    if (e) return hip_fail(e, "condense_blocks");
+  }
+  return HDG_OK;
+}
+
 extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const double *q,
                                      const double *vhat, const double *ustar, const double *vbc,
                                      double *S, double *g, double *Y, double *z, double *Rloc,

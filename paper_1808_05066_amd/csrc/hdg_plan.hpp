@@ -195,7 +195,10 @@ hipError_t launch_backsolve_local_f32(const DevPlan &P, const float *Y, const do
 hipError_t launch_backsolve_elements(const DevPlan &P, const double *Y, const double *z, const double *dvhat,
                                      double *dx, hipStream_t s);
 hipError_t launch_elem_ratio_max(const double *r, const double *b, int E, int n, unsigned long long *out,
-                                 hipStream_t s);
+                                 double *per, hipStream_t s);
+hipError_t launch_fallback_rhs(const DevPlan &P, int e0, int ec, const double *b, hipStream_t s);
+hipError_t launch_fallback_take(const DevPlan &P, int e0, int ec, const double *ratio, double tol, double *dx,
+                                int *count, hipStream_t s);
 hipError_t launch_bj_assemble_f32(const DevPlan &P, const float *S, double *B, hipStream_t s);
 size_t condense_inv_doubles(int np);
 bool contract_mfma_supported(const DevPlan &P);
@@ -230,6 +233,8 @@ hipError_t launch_trace_rhs(const DevPlan &P, const double *g, double *r, hipStr
 hipError_t launch_weak_u(const DevPlan &P, const double *v, double *b, hipStream_t s);
 hipError_t launch_mass_solve(const DevPlan &P, const double *b, double *u, hipStream_t s);
 hipError_t launch_quad_coords(const DevPlan &P, double *xq, hipStream_t s);
+hipError_t launch_import_blocks(const DevPlan &P, int e0, int ec, const double *A, const double *B, const double *C,
+                                const double *D, const double *Rloc, const double *Rtr, hipStream_t s);
 hipError_t launch_l2_error_visc(const DevPlan &P, const double *f, const double *ex, double *out, hipStream_t s);
 hipError_t launch_face_quad_coords(const DevPlan &P, double *xf, hipStream_t s);
 hipError_t launch_trace_project(const DevPlan &P, const double *g, double *vbc, hipStream_t s);

@@ -149,6 +149,16 @@ class Plan:
             _stream()), "hdg_assemble_condense")
         return out
 
+    def condense_blocks(self, blocks, out=None):
+        """Condensation of caller blocks (dict with A, B, C, D, R_loc, R_tr in the layout of
+        assemble()) with the hot path's kernels (hdg_condense_blocks)."""
+        if out is None:
+            out = self.alloc_outputs()
+        check(self.lib.hdg_condense_blocks(self.h, *(_ptr(blocks[key]) for key in ("A", "B", "C", "D", "R_loc", "R_tr")),
+                                           _ptr(out["S"]), _ptr(out["g"]), _ptr(out["Y"]), _ptr(out["z"]),
+                                           _ptr(out["status"]), _stream()), "hdg_condense_blocks")
+        return out
+
     def backsolve(self, Y, z, dvhat, dv=None, dq=None):
         if dv is None:
             dv = self._empty(self.m, self.n_nodes)

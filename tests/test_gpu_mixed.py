@@ -217,3 +217,28 @@ def test_element_refinement_with_fixed_trace_update(torch, name):
     print(name, info, "dx vs FP64 back-solve", err, flush=True)
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
     assert err <= 1e-9
+
+
+def test_element_refinement_falls_back_to_fp64(torch):
+    """The FP64 fallback of hdg_refine_local, forced from the host: one refinement step cannot
+    reach 1e-10 (the FP32 correction leaves about 1e-5), so every element above the tolerance is
+    re-assembled and solved with the FP64 LU; the result then meets the tolerance and equals the
+    FP64 element back-solve."""
+    wl = SMALL_CASES["ns3d_hex_p2"]()
+    disc, inp = oracle_case(wl)
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    f64 = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    lp = plan.assemble_condense_lp(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    rng = np.random.default_rng(43)
+    dl = torch.from_numpy(1e-3 * rng.standard_normal((disc.m, wl.n_trace)) * np.abs(inp["vhat"])).cuda()
+    dx, info = plan.refine_local(d["v"], d["q"], d["vhat"], lp, dl, ustar=d["ustar"], vbc=d["vbc"], tol=1e-10,
+                                 max_iter=1)
+    dx64 = plan.backsolve_elements(f64["Y"], f64["z"], dl)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.norm(dx - dx64) / torch.linalg.norm(dx64))
+    print(info, "dx vs FP64 back-solve", err, flush=True)
+    assert info["history"][0] > 1e-10                      # one step alone does not reach tol
+    assert info["fallback_elements"] == wl.mesh.n_elem
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    assert err <= 1e-9

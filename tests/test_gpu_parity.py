@@ -413,3 +413,68 @@ def test_mean_value_stabilization_across_sign_changes(torch, name):
     print(name, "kinks", kinks, errs, flush=True)
     for key, err in errs.items():
         assert err <= TOL, (key, err)
+
+
+def _block_tensors(torch, blocks):
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return {"A": dev(colmajor([b["A"] for b in blocks])), "B": dev(colmajor([b["B"] for b in blocks])),
+            "C": dev(colmajor([b["C"] for b in blocks])), "D": dev(colmajor([b["D"] for b in blocks])),
+            "R_loc": dev(np.stack([b["R_loc"] for b in blocks])), "R_tr": dev(np.stack([b["R_tr"] for b in blocks]))}
+
+
+@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("name", ["euler2d_tri_p2", "ns2d_tri_p2", "ns3d_hex_p2"])
+def test_condense_blocks_matches_oracle(torch, name, split):
+    """hdg_condense_blocks on the oracle's own blocks: the condensation alone (S, Y, g, z) against
+    the oracle's LAPACK condensation of the same blocks, for the left-looking and right-looking
+    kernels."""
+    wl, disc, inp, blocks = _case(name)
+    plan = gpu_plan(wl, split_dense=split)
+    out = plan.condense_blocks(_block_tensors(torch, blocks))
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().max()) == 0
+    for key, mat in (("S", True), ("Y", True), ("g", False), ("z", False)):
+        ref = colmajor([b[key] for b in blocks]) if mat else np.stack([b[key] for b in blocks])
+        err = rel_err_per_elem(out[key].cpu().numpy(), ref)
+        assert err <= (1e-11 if key == "z" else TOL), (key, err)
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_singular_local_block_is_flagged(torch, split):
+    """A local block with a zero column (built on the host from the oracle's blocks) has a zero
+    pivot: HDG_ESINGULAR on that element only, every other element condensed as before."""
+    wl, disc, inp, blocks = _case("ns2d_tri_p2")
+    bad = 3
+    blocks = [dict(b) for b in blocks]
+    A = blocks[bad]["A"].copy()
+    A[:, 7] = 0.0
+    blocks[bad]["A"] = A
+    plan = gpu_plan(wl, split_dense=split)
+    out = plan.condense_blocks(_block_tensors(torch, blocks))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert st[bad] == -4 and np.count_nonzero(st) == 1, st
+    assert plan.status(out["status"]) == (bad, -4)
+    good = [e for e in range(len(blocks)) if e != bad]
+    ref = colmajor([blocks[e]["S"] for e in good])
+    assert rel_err_per_elem(out["S"].cpu().numpy()[good], ref) <= TOL
+
+
+def test_non_finite_q_and_vhat_are_flagged(torch):
+    """A NaN in the gradient unknowns of one element flags that element HDG_ENONPHYS; a NaN at one
+    trace node flags exactly the elements whose faces hold that node."""
+    wl, disc, inp, _ = _case("ns2d_tri_p2")
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    bad = 9
+    d["q"][2, bad * disc.Np + 1] = float("nan")
+    out = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    st = out["status"].cpu().numpy()
+    assert st[bad] == -3 and np.count_nonzero(st) == 1, st
+    d = to_dev(inp)
+    node = int(wl.tmap[4, 1, 0])
+    d["vhat"][0, node] = float("nan")
+    out = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    st = out["status"].cpu().numpy()
+    holders = sorted({e for e in range(wl.mesh.n_elem) if np.any(wl.tmap[e] == node)})
+    assert sorted(np.nonzero(st)[0].tolist()) == holders and np.all(st[holders] == -3), (st, holders)
