@@ -291,12 +291,21 @@ int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
  * element on one XCD so that they share its factors in L2; FP64 with 32-column
  * blocks and FP32; the results are the same bit for bit).  The autotuner
  * (paper_1808_05066_amd/autotune.py) sweeps these per (n, k, dtype) and caches
- * the fastest in JSON.  Set before building a batch (batches use one launch). */
+ * the fastest in JSON.  Set before building a batch (batches use one launch).
+ * lu_waves selects the LU of the two-launch FP64 condensation: 1 keeps its
+ * 32-column working block in LDS (one workgroup per CU), 4 or 8 keep it in
+ * the registers of that many waves (LDS for staging only: with 4 waves two
+ * elements share a CU; 4 for n_pad <= 192, 8 for n_pad <= 640).  Default: 4
+ * where it applies, else 1.  The factors are stored the same way, so S, g, Y,
+ * z agree to rounding (the register kernels pick a pivot whose magnitude is
+ * within a relative 2^-11 of the column's largest).  HDG_EUNSUPPORTED if the
+ * block is too large for the choice. */
 typedef struct {
   int contract_threads;
   int condense_width;
   int condense_width_lp;
   int condense_launches;
+  int lu_waves;
 } hdg_tuning;
 
 int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t);

@@ -262,6 +262,17 @@ extern "C" int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t) {
       return fail(HDG_EINVAL, "condense_launches must be 1 or 2");
     P->dp.condense_launches = t->condense_launches;
   }
+  if (t->lu_waves) {
+    if (t->lu_waves == 1) {
+      P->dp.lu_waves = 0;
+    } else {
+      if (t->lu_waves != 4 && t->lu_waves != 8) return fail(HDG_EINVAL, "lu_waves must be 1, 4 or 8");
+      if (!lu_reg_supported(P->dp.n_pad, t->lu_waves))
+        return fail(HDG_EUNSUPPORTED, "register-resident LU not available for this block size");
+      P->dp.lu_waves = t->lu_waves;
+    }
+    P->dp.lu_waves_set = 1;
+  }
   return HDG_OK;
 }
 
@@ -272,5 +283,6 @@ extern "C" int hdg_plan_get_tuning(const hdg_plan *plan, hdg_tuning *t) {
   t->condense_width = P->fused ? P->dp.cw : 0;
   t->condense_width_lp = P->dp.cw_lp;
   t->condense_launches = P->dp.condense_launches;
+  t->lu_waves = P->dp.lu_waves ? P->dp.lu_waves : 1;
   return HDG_OK;
 }

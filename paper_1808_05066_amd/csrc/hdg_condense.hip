@@ -25,6 +25,8 @@
 // (FP32 accumulation); Y = D Y_hat and z = D z_hat are unscaled on output and
 // the factors, pivots, scales and diagonal-block inverses are kept for the
 // refinement solves.
+#include <utility>
+
 #include "hdg_plan.hpp"
 
 namespace hdg {
@@ -210,6 +212,13 @@ __device__ inline void store_block(const Lds<T> &s, T *M, int ld, int c0, int np
   }
 }
 
+// Barrier for exchanges through LDS only: waits for this wave's LDS operations, not for its
+// global loads.  __syncthreads() also waits for every outstanding global load, which in the
+// blocked sweeps below would expose the full memory latency of the operands prefetched for
+// the next step at every step; here those loads stay in flight across the barrier (each
+// wave consumes only its own loads, and the compiler waits for them where they are used).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // One step "apply diagonal-block inverse, then update the other rows" of a
 // blocked triangular sweep.  Both global operands of a step (the W x W inverse
 // and the first row tile of the factor panel) are loaded one step ahead into
@@ -260,7 +269,7 @@ __device__ inline void inv_apply(const Lds<T> &s, T (&ia)[W / 4], int p0, const 
     for (int kk = 0; kk < W / 4; ++kk) acc = MF::op(ia[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
   }
   load_inv<T, W>(ia, Ie, next);
-  __syncthreads();
+  lds_barrier();
   if (wave < TW * TW) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) s.blk[(p0 + ti * 16 + MF::row(lk, r)) * BS + tj * 16 + li] = acc[r];
@@ -441,9 +450,9 @@ __device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int 
   for (int i = 0; i < count; ++i) {
     const Step nxt = (i + 1 < count) ? spec(i + 1) : Step{-1, 0, 0, 0};
     inv_apply<T, W>(s, ia, cur.p0, Ie, nxt);
-    __syncthreads();
+    lds_barrier();
     gemm_update<T, W, NTT, MT>(s, a, Fm, ld, cur, nxt);
-    __syncthreads();
+    lds_barrier();
     cur = nxt;
   }
 }
@@ -660,28 +669,26 @@ __device__ inline void moved_rows(const Lds<T> &s, int j0, int np) {
   }
 }
 
-// The same row movement on the stored factor columns 0..j0-1:
-// col[mvx[i]] <- col[mvy[i]] (all reads of a group of columns before its writes).
-template <typename T>
-__device__ inline void move_rows(const Lds<T> &s, T *Fm, int ld, int j0) {
-  constexpr int U = 8;    // values per thread and group
-  const int m = *s.mvn;
+
+// The row movement of one block's pivots on the stored factor columns 0..j0-1:
+// col[mvx[i]] <- col[mvy[i]] for the m (<= 64) moved positions.  Each wave moves whole columns,
+// lane i the position i: the lane's read precedes its write, and the reads of a column are
+// the same wave's, so no barrier is needed between them.  Four columns per wave in flight.
+template <int NWV, typename T>
+__device__ inline void move_rows_waves(const int *mvx, const int *mvy, int m, T *Fm, int ld, int j0) {
   if (m == 0) return;
-  const int cg = (NT * U) / m;   // whole columns per group (m <= 2W <= 64)
-  for (int c0 = 0; c0 < j0; c0 += cg) {
-    const int items = (j0 - c0 < cg ? j0 - c0 : cg) * m;
-    T v[U];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool act = lane < m;
+  const int y = act ? mvy[lane] : 0, x = act ? mvx[lane] : 0;
+  constexpr int CU = 4;
+  for (int c0 = w * CU; c0 < j0; c0 += NWV * CU) {
+    T v[CU];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = threadIdx.x + u * NT;
-      if (i < items) v[u] = Fm[(size_t)(c0 + i / m) * ld + s.mvy[i % m]];
-    }
-    __syncthreads();
+    for (int u = 0; u < CU; ++u)
+      if (act && c0 + u < j0) v[u] = Fm[(size_t)(c0 + u) * ld + y];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = threadIdx.x + u * NT;
-      if (i < items) Fm[(size_t)(c0 + i / m) * ld + s.mvx[i % m]] = v[u];
-    }
+    for (int u = 0; u < CU; ++u)
+      if (act && c0 + u < j0) Fm[(size_t)(c0 + u) * ld + x] = v[u];
   }
 }
 
@@ -824,7 +831,7 @@ __device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &
     }
     invert_diag<T, W>(s, j0, Ie + (size_t)J * 2 * W * W, Ie + (size_t)J * 2 * W * W + W * W);
     store_block<T, W>(s, Fm, np, j0, np);
-    if (J > 0) move_rows<T>(s, Fm, np, j0);
+    if (J > 0) move_rows_waves<NW>(s.mvx, s.mvy, *s.mvn, Fm, np, j0);
     __syncthreads();
   }
   if constexpr (LP) {
@@ -1124,6 +1131,521 @@ __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, int W, const flo
   for (int i = tid; i < n; i += SB) x[(size_t)e * n + i] = (double)dsc[i] * y[i];
 }
 
+
+// ---------------------------------------------------------------------------
+// LU with the working block in registers (two elements per CU).
+//
+// The left-looking LU above keeps its 32-column working block in LDS
+// (n_pad x 33 doubles, 143 KB at n_pad = 544), which leaves room for one
+// workgroup per CU: the latency of the pivot searches and barriers then has
+// nothing to hide behind.  Here the 32 columns live in the registers of NWV
+// waves as matrix-core accumulators: row tile t (16 rows) belongs to wave
+// t % NWV, whose lane (li, lk) holds rows lk + 4r (r = 0..3) of columns li and
+// 16 + li.  LDS holds only staging (an 8-column sub-panel, the rows that feed a
+// step, the permutations), about 66 KB at n_pad = 544, so with four waves two
+// elements share a CU and one's panel factorization overlaps the other's
+// updates.  The factors, their ordering and the diagonal-block inverses are
+// stored exactly as the LDS kernel stores them, so the right-hand-side launch
+// is the same.
+//
+// * Update of block J by the stored factors, in steps of 16 columns: the wave
+//   that owns tile s applies the inverse of the unit-lower 16 x 16 diagonal
+//   block to it on the matrix cores, its own accumulators serving as the B
+//   operand (the accumulator layout of a 16-row tile is the B layout of its
+//   four 4-row k-steps), and writes the result to LDS; after one barrier every
+//   wave subtracts F(tile rows, step columns) times those rows from its tiles
+//   below.  The owner of the next step's tile updates that tile first and
+//   applies the next inverse before its other tiles, so one barrier per step
+//   suffices (the staging is double-buffered).
+// * Panel factorization of block J in four 8-column sub-panels with partial
+//   pivoting: the sub-panel's rows are copied to LDS and each thread keeps up
+//   to MR of them in registers; per column one wave-wide maximum of a 64-bit
+//   key (the magnitude's leading 48 bits, then the lowest row) and one barrier.
+//   Rows are not moved in the registers: sig[p] records the position that the
+//   row held in physical slot p has reached, and every access goes through it.
+//   After a sub-panel its 8 pivot rows are solved against the remaining
+//   columns (unit-lower 8 x 8, per wave) and the rows below receive the rank-8
+//   update on the matrix cores.
+// ---------------------------------------------------------------------------
+
+typedef unsigned long long u64;
+
+// 32-bit pivot key of relative row i (< 1024): the magnitude's exponent and leading 11
+// mantissa bits, then the lower row (the choice is that of exact partial pivoting up to a
+// relative 2^-11, which keeps the multipliers below 1 + 2^-10 in magnitude); 0 marks "no
+// candidate"
+__device__ inline unsigned pivot_key32(double x, int i) {
+  const u64 b = __builtin_bit_cast(u64, fabs(x));
+  return ((unsigned)(b >> 41) << 10) | (unsigned)(1023 - i);
+}
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)dpp_i32<DPP_QUAD_1032>((int)v));
+  v = max(v, (unsigned)dpp_i32<DPP_QUAD_2301>((int)v));
+  v = max(v, (unsigned)dpp_i32<DPP_ROW_ROR4>((int)v));
+  v = max(v, (unsigned)dpp_i32<DPP_ROW_ROR8>((int)v));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
+}
+
+constexpr int RG_SS = 9;     // LDS row stride of the 8-column sub-panel
+constexpr int RG_ST = 34;    // LDS row stride of the 16 x 32 / 8 x 32 staging
+
+struct RegLayout {
+  size_t sub, stage, ust, wst, crow, redk, perm, sig, invb, mv, total;
+};
+
+__host__ __device__ inline RegLayout reg_layout(int np, int nwv) {
+  RegLayout L;
+  size_t o = 0;
+  const size_t subd = (size_t)np * RG_SS > 32 * 33 ? (size_t)np * RG_SS : 32 * 33;
+  L.sub = o;   o = al16(o + subd * 8);
+  L.stage = o; o = al16(o + 2 * 16 * RG_ST * 8);
+  L.ust = o;   o = al16(o + 8 * RG_ST * 8);
+  L.wst = o;   o = al16(o + (size_t)nwv * 8 * RG_ST * 8);
+  L.crow = o;  o = al16(o + 2 * (size_t)(nwv + 1) * 8 * 8);
+  L.redk = o;  o = al16(o + (2 * (size_t)nwv + 8) * 4);
+  L.perm = o;  o = al16(o + (size_t)np * 4);
+  L.sig = o;   o = al16(o + (size_t)np * 4);
+  L.invb = o;  o = al16(o + (size_t)np * 4);
+  L.mv = o;    o = al16(o + (4 * WMAX + 1) * 4);
+  L.total = o;
+  return L;
+}
+
+template <typename F, int... I>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F &&f) {
+  sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <int NWV, int TPW>
+__device__ __forceinline__ void lu_reg_body(const DevPlan &P, int el, int32_t *status, double *inv) {
+  constexpr int NTR = 64 * NWV;
+  constexpr int MR = (TPW + 3) / 4;   // sub-panel rows per thread: ceil(16 TPW NWV / NTR)
+  extern __shared__ double smem[];
+  char *sm = reinterpret_cast<char *>(smem);
+  const int np = P.n_pad, NTILE = np / 16, nJ = np / 32;
+  const int n = P.n, Np = P.Np, Dm = P.dim, nv = P.m * Np, DN = Dm * Np;
+  const RegLayout Lo = reg_layout(np, NWV);
+  double *sub = reinterpret_cast<double *>(sm + Lo.sub);
+  double *stage = reinterpret_cast<double *>(sm + Lo.stage);
+  double *ust = reinterpret_cast<double *>(sm + Lo.ust);
+  double *crow = reinterpret_cast<double *>(sm + Lo.crow);
+  unsigned *redk = reinterpret_cast<unsigned *>(sm + Lo.redk);
+  int *pivl = reinterpret_cast<int *>(sm + Lo.redk) + 2 * NWV;
+  int *perm = reinterpret_cast<int *>(sm + Lo.perm);
+  int *sig = reinterpret_cast<int *>(sm + Lo.sig);
+  int *invb = reinterpret_cast<int *>(sm + Lo.invb);
+  int *mvx = reinterpret_cast<int *>(sm + Lo.mv);
+  int *mvy = mvx + 2 * WMAX;
+  int *mvn = mvy + 2 * WMAX;
+  double *Fm = P.A + (size_t)el * np * np;   // factors overwrite A (columns of block J are read before)
+  const double *mg = P.mg ? P.mg + (size_t)el * (P.dim + 1) * P.Np * P.Np : nullptr;
+  double *Ie = inv + (size_t)el * 2 * np * WMAX;
+  typedef Mfma<double> MF;
+
+  for (int i = threadIdx.x; i < np; i += NTR) perm[i] = i;
+  bool singular = false;
+  d4 acc[TPW][2];
+  __syncthreads();
+
+  for (int J = 0; J < nJ; ++J) {
+    const int j0 = J * 32;
+    // Thread coordinates are redefined opaquely in every block: whatever is formed from them
+    // (addresses, lane predicates) is recomputed inside the block loop instead of being hoisted
+    // out of it and held in (spilled) registers.  The wave index is made uniform again.
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, li = lane & 15, lk = lane >> 4;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double *wst = reinterpret_cast<double *>(sm + Lo.wst) + (size_t)w * 8 * RG_ST;
+
+  // operands of the update steps: F(tile t rows, step s columns), negated (uniform base,
+  // 32-bit lane offset made opaque: otherwise the compiler hoists a 64-bit address per tile
+  // and k-step out of the block loop and spills them), and the inverse of step s's 16 x 16
+  // unit-lower diagonal block
+  const auto load_f = [&](int s, int t, double (&f)[4]) {
+    const double *base = Fm + (size_t)(16 * s) * np;
+    unsigned o = lk * np + 16 * t + li;
+    asm volatile("" : "+v"(o));
+    sfor<4>([&](auto kk) { f[kk] = -base[o + 4u * kk * np]; });
+  };
+  const auto load_la = [&](int s, double (&la)[4]) {
+    const int off = 16 * (s & 1);
+    const double *Li = Ie + (size_t)(s >> 1) * 2 * WMAX * WMAX;
+    sfor<4>([&](auto kk) { la[kk] = Li[(off + 4 * kk + lk) * WMAX + off + li]; });
+  };
+  // rows <- (16 x 16 inverse, operands la) x rows for the tile in at; result to the staging
+  const auto inv_rows = [&](d4 (&at)[2], const double (&la)[4], double *stn) {
+    d4 nw[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    sfor<2>([&](auto q) { sfor<4>([&](auto kk) { nw[q] = MF::op(la[kk], at[q][(int)kk], nw[q]); }); });
+    sfor<2>([&](auto q) {
+      at[q] = nw[q];
+      sfor<4>([&](auto r) { stn[(lk + 4 * r) * RG_ST + 16 * q + li] = nw[q][(int)r]; });
+    });
+  };
+  // the accumulator column half q (0 or 1, uniform) of slot (u, r), as selects of values (a
+  // select of the two addresses would keep acc out of the registers)
+  const auto acc_get = [&](auto u, auto r, int q) {
+    const double v0 = acc[u][0][(int)r], v1 = acc[u][1][(int)r];
+    return q ? v1 : v0;
+  };
+  const auto acc_set = [&](auto u, auto r, int q, double v) {
+    const double v0 = acc[u][0][(int)r], v1 = acc[u][1][(int)r];
+    acc[u][0][(int)r] = q ? v0 : v;
+    acc[u][1][(int)r] = q ? v : v1;
+  };
+
+    for (int x = tid; x < np; x += NTR) {
+      sig[x] = x;
+      invb[perm[x]] = x;
+    }
+    if (tid == 0) *mvn = 0;
+    __syncthreads();
+    // gather block J through the permutation, 8 columns at a time through LDS: the stored
+    // rows directly (all of A, or only its v rows when the q rows are formed from the compact
+    // M and G_j), then the nonzeros of the formed q rows placed through the inverse permutation
+    for (int h = 0; h < 4; ++h) {
+      const int c0 = j0 + 8 * h;
+      constexpr int GU = 4;   // entries per thread with their loads in flight together
+      for (int x0 = tid; x0 < np * 8; x0 += GU * NTR) {
+        double v[GU];
+        sfor<GU>([&](auto g) {
+          const int x = x0 + g * NTR;
+          v[g] = 0.0;
+          if (x < np * 8) {
+            const int c = x / np, o = perm[x - c * np], col = c0 + c;
+            if (!mg) v[g] = Fm[(size_t)col * np + o];
+            else if (o < nv) v[g] = col < n ? Fm[(size_t)col * np + o] : 0.0;
+            else v[g] = (o == col && o >= n) ? 1.0 : 0.0;
+          }
+        });
+        sfor<GU>([&](auto g) {
+          const int x = x0 + g * NTR;
+          if (x < np * 8) {
+            const int c = x / np;
+            sub[(x - c * np) * RG_SS + c] = v[g];
+          }
+        });
+      }
+      if (mg) {
+        __syncthreads();
+        // v column (cc, b): G_j[a][b] in the q rows (cc, j, a); q column (cc, jj, b): M[a][b]
+        // in the q rows (cc, jj, a)
+        for (int x = tid; x < 8 * DN; x += NTR) {
+          const int c = x / DN, r = x - c * DN, col = c0 + c;
+          if (col >= n) continue;
+          int o;
+          double val;
+          if (col < nv) {
+            const int cc = col / Np, bb = col - cc * Np, j = r / Np, aa = r - j * Np;
+            o = nv + (cc * Dm + j) * Np + aa;
+            val = mg[(j * Np + aa) * Np + bb];
+          } else {
+            if (r >= Np) continue;
+            const int qc = col - nv, cj = qc / Np, bb = qc - cj * Np;
+            o = nv + cj * Np + r;
+            val = mg[(Dm * Np + r) * Np + bb];
+          }
+          sub[invb[o] * RG_SS + c] = val;
+        }
+      }
+      __syncthreads();
+      const int qh = h >> 1, lo = 8 * (h & 1);
+      if (li >= lo && li < lo + 8) {
+        sfor<TPW>([&](auto u) {
+          const int t = w + NWV * u;
+          if (t < NTILE) sfor<4>([&](auto r) { acc_set(u, r, qh, sub[(16 * t + lk + 4 * r) * RG_SS + li - lo]); });
+        });
+      }
+      __syncthreads();
+    }
+
+    // ---- update by the stored factors, 16 columns per step ----
+    // Every register that carries an operand into a later step is loaded unconditionally
+    // (inactive slots re-read an active tile's address, a cache hit): a conditional load into
+    // a loop-carried register becomes a load into a temporary and a copy, and the copy waits
+    // for the load at once.  Loads complete in issue order, so the inverse operands of a step
+    // are requested before the operand ring.
+    const int ns = 2 * J;
+    if (ns > 0) {
+      double fr[TPW][4], L0[4], L1[4];
+      // operand ring: fr[u] holds F(tile of slot u, columns of the coming step)
+      const auto ring = [&](int s2) {
+        const int tmin = s2 + 1 < NTILE ? s2 + 1 : NTILE - 1;
+        sfor<TPW>([&](auto u) {
+          int t = w + NWV * u;
+          t = t < tmin ? tmin : (t > NTILE - 1 ? NTILE - 1 : t);
+          load_f(s2, t, fr[u]);
+        });
+      };
+      if (w == 0) {
+        // step 0: rows 0..15 (tile 0 of wave 0) <- inverse of the first diagonal block times them
+        load_la(0, L0);
+        inv_rows(acc[0], L0, stage);
+      }
+      load_la(ns > 1 ? 1 : 0, L1);
+      ring(0);
+      // step s: the owner of tile s + 1 applies the inverse of step s + 1 (operands Ln); the
+      // inverse of step s + 2 is requested into Lq (free: its last use was in step s - 1)
+      const auto step = [&](int s, double (&Ln)[4], double (&Lq)[4]) {
+        lds_barrier();
+        const double *stg = stage + (s & 1) * 16 * RG_ST;
+        double b[4][2];
+        sfor<4>([&](auto kk) { sfor<2>([&](auto q) { b[kk][q] = stg[(4 * kk + lk) * RG_ST + 16 * q + li]; }); });
+        load_la(s + 2 < ns ? s + 2 : ns - 1, Lq);
+        const bool own = s + 1 < ns && w == (s + 1) % NWV;
+        const auto update = [&](auto u) {
+          sfor<4>([&](auto kk) { sfor<2>([&](auto q) { acc[u][q] = MF::op(fr[u][kk], b[kk][q], acc[u][q]); }); });
+        };
+        if (own) {
+          // tile s + 1: its last update, then the inverse of step s + 1; rows to the staging
+          const int us = (s + 1) / NWV;
+          double *stn = stage + ((s + 1) & 1) * 16 * RG_ST;
+          sfor<TPW>([&](auto u) {
+            if (u == us) {
+              update(u);
+              inv_rows(acc[u], Ln, stn);
+            }
+          });
+        }
+        // the wave's other tiles below the step
+        sfor<TPW>([&](auto u) {
+          const int t = w + NWV * u;
+          if (t > s + (own ? 1 : 0) && t < NTILE) update(u);
+        });
+        ring(s + 1 < ns ? s + 1 : s);
+      };
+      for (int s = 0; s < ns; s += 2) {
+        step(s, L1, L0);
+        if (s + 1 < ns) step(s + 1, L0, L1);
+      }
+    }
+    __syncthreads();
+
+    // ---- panel factorization of block J: four 8-column sub-panels ----
+    for (int sp = 0; sp < 4; ++sp) {
+      const int cs = 8 * sp, qs = sp >> 1, lo = 8 * (sp & 1);
+      const int P0 = j0 + cs, R = np - P0;
+      const bool mine = li >= lo && li < lo + 8;
+      // (a) the sub-panel's rows from position P0 on into LDS
+      if (mine) {
+        sfor<TPW>([&](auto u) {
+          const int t = w + NWV * u;
+          if (t < NTILE) {
+            sfor<4>([&](auto r) {
+              const int sg = sig[16 * t + lk + 4 * r];
+              if (sg >= P0) sub[(sg - P0) * RG_SS + li - lo] = acc_get(u, r, qs);
+            });
+          }
+        });
+      }
+      __syncthreads();
+      // (b) partial pivoting over the 8 columns; thread rows i = tid + NTR m.  The columns
+      // are kept rotated so that the current one is x[m][0] (one copy of the column code):
+      // at column jj, x[m][c] holds column jj + c for c < 8 - jj and the finished column
+      // jj + c - 8 after that; after 8 rotations the order is the original one.
+      double x[MR][8];
+      int sgl[MR];   // positions reached by the rows of this thread's physical slots
+      sfor<MR>([&](auto m) {
+        const int i = tid + NTR * m;
+        sfor<8>([&](auto c) { x[m][c] = i < R ? sub[i * RG_SS + c] : 0.0; });
+        sgl[m] = tid + NTR * m < np ? sig[tid + NTR * m] : -1;
+      });
+      for (int jj = 0; jj < 8; ++jj) {
+        unsigned best = 0;
+        int bm = -1;
+        sfor<MR>([&](auto m) {
+          const int i = tid + NTR * m;
+          if (i < R && i >= jj) {
+            const unsigned kx = pivot_key32(x[m][0], i);
+            if (kx > best) {
+              best = kx;
+              bm = m;
+            }
+          }
+        });
+        const unsigned wb = wave_max_u32(best);
+        const int bs = jj & 1;
+        double *cr = crow + (size_t)bs * (NWV + 1) * 8;
+        if (bm >= 0 && best == wb) {
+          sfor<MR>([&](auto m) {
+            if (m == bm) sfor<8>([&](auto c) { cr[w * 8 + c] = x[m][c]; });
+          });
+        }
+        if (lane == 0) redk[bs * NWV + w] = wb;
+        if (tid == jj) sfor<8>([&](auto c) { cr[NWV * 8 + c] = x[0][c]; });
+        lds_barrier();
+        unsigned kb = 0;
+        int wv = 0;
+        sfor<NWV>([&](auto v) {
+          const unsigned kv = redk[bs * NWV + v];
+          if (kv > kb) {
+            kb = kv;
+            wv = v;
+          }
+        });
+        double prow[8];
+        sfor<8>([&](auto c) { prow[c] = cr[wv * 8 + c]; });
+        const bool zero = kb == 0 || !(fabs(prow[0]) > 0.0);
+        singular |= zero;
+        const int piv = zero ? jj : 1023 - (int)(kb & 1023u);
+        if (tid == 0) pivl[jj] = piv;
+        if (piv != jj) {
+          sfor<MR>([&](auto m) {
+            if (tid + NTR * m == piv) sfor<8>([&](auto c) { x[m][c] = cr[NWV * 8 + c]; });
+          });
+          if (tid == jj) sfor<8>([&](auto c) { x[0][c] = prow[c]; });
+          const int a = P0 + jj, bp = P0 + piv;
+          sfor<MR>([&](auto m) { sgl[m] = sgl[m] == a ? bp : (sgl[m] == bp ? a : sgl[m]); });
+        }
+        // reciprocal of the pivot: hardware estimate and two Newton steps
+        double rinv = 0.0;
+        if (!zero) {
+          rinv = __builtin_amdgcn_rcp(prow[0]);
+          rinv = fma(rinv, fma(-prow[0], rinv, 1.0), rinv);
+          rinv = fma(rinv, fma(-prow[0], rinv, 1.0), rinv);
+        }
+        sfor<MR>([&](auto m) {
+          const int i = tid + NTR * m;
+          if (!zero && i < R && i > jj) {
+            const double l = x[m][0] * rinv;
+            x[m][0] = l;
+            sfor<7>([&](auto cm) {
+              constexpr int c = cm + 1;
+              if (c < 8 - jj) x[m][c] -= l * prow[c];
+            });
+          }
+          const double t0 = x[m][0];
+          sfor<7>([&](auto c) { x[m][c] = x[m][c + 1]; });
+          x[m][7] = t0;
+        });
+      }
+      sfor<MR>([&](auto m) {
+        const int i = tid + NTR * m;
+        if (i < R) sfor<8>([&](auto c) { sub[i * RG_SS + c] = x[m][c]; });
+        if (tid + NTR * m < np) sig[tid + NTR * m] = sgl[m];
+      });
+      if (tid == 0) {
+        // the sub-panel's interchanges on the permutation, in order
+        for (int jj = 0; jj < 8; ++jj) {
+          const int a = P0 + jj, bp = P0 + pivl[jj];
+          if (a != bp) {
+            const int tmp = perm[a];
+            perm[a] = perm[bp];
+            perm[bp] = tmp;
+          }
+        }
+      }
+      __syncthreads();
+      // (d) factored sub-panel back into the registers; the 8 pivot rows to the staging
+      // (their columns from cs + 8 on; zero before, so that they leave those columns unchanged)
+      sfor<TPW>([&](auto u) {
+        const int t = w + NWV * u;
+        if (t < NTILE) {
+          sfor<4>([&](auto r) {
+            const int sg = sig[16 * t + lk + 4 * r];
+            if (mine && sg >= P0) acc_set(u, r, qs, sub[(sg - P0) * RG_SS + li - lo]);
+            if (sg >= P0 && sg < P0 + 8) {
+              sfor<2>([&](auto q) {
+                const int c = 16 * q + li;
+                ust[(sg - P0) * RG_ST + c] = c >= cs + 8 ? acc[u][q][(int)r] : 0.0;
+              });
+            }
+          });
+        }
+      });
+      __syncthreads();
+      // (e) pivot rows against the unit-lower 8 x 8 block (every wave, lane = column), into
+      // the wave's own staging
+      if (lane < 32) {
+        double uu[8];
+        sfor<8>([&](auto i) { uu[i] = ust[i * RG_ST + lane]; });
+        sfor<8>([&](auto i) {
+          sfor<8>([&](auto k2) {
+            if constexpr (k2 < i) uu[i] -= sub[i * RG_SS + k2] * uu[k2];
+          });
+        });
+        sfor<8>([&](auto i) { wst[i * RG_ST + lane] = uu[i]; });
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // (f) holders of the pivot rows take the solved values; rank-8 update of the rows below
+      double bw[2][2];
+      sfor<2>([&](auto kk) { sfor<2>([&](auto q) { bw[kk][q] = wst[(4 * kk + lk) * RG_ST + 16 * q + li]; }); });
+      sfor<TPW>([&](auto u) {
+        const int t = w + NWV * u;
+        if (t < NTILE) {
+          sfor<4>([&](auto r) {
+            const int sg = sig[16 * t + lk + 4 * r];
+            if (sg >= P0 && sg < P0 + 8) {
+              sfor<2>([&](auto q) {
+                const int c = 16 * q + li;
+                if (c >= cs + 8) acc[u][q][(int)r] = wst[(sg - P0) * RG_ST + c];
+              });
+            }
+          });
+          const int sa = sig[16 * t + li];
+          sfor<2>([&](auto kk) {
+            const double a = sa >= P0 + 8 ? -sub[(sa - P0) * RG_SS + 4 * kk + lk] : 0.0;
+            sfor<2>([&](auto q) { acc[u][q] = MF::op(a, bw[kk][q], acc[u][q]); });
+          });
+        }
+      });
+      __syncthreads();
+    }
+
+    // ---- store block J (pivot-position order), diagonal-block inverses, row movement ----
+    double *dst = sub;   // 32 x 33 diagonal block
+    sfor<TPW>([&](auto u) {
+      const int t = w + NWV * u;
+      if (t < NTILE) {
+        sfor<4>([&](auto r) {
+          const int sg = sig[16 * t + lk + 4 * r];
+          sfor<2>([&](auto q) {
+            Fm[(size_t)(j0 + 16 * q + li) * np + sg] = acc[u][q][(int)r];
+            if (sg >= j0 && sg < j0 + 32) dst[(sg - j0) * 33 + 16 * q + li] = acc[u][q][(int)r];
+          });
+        });
+      }
+    });
+    __syncthreads();
+    {
+      Lds<double> sd;
+      sd.blk = dst;
+      invert_diag<double, 32>(sd, 0, Ie + (size_t)J * 2 * WMAX * WMAX, Ie + (size_t)J * 2 * WMAX * WMAX + WMAX * WMAX);
+    }
+    if (J > 0) {
+      for (int xp = j0 + tid; xp < np; xp += NTR) {
+        const int y = invb[perm[xp]];
+        if (y != xp) {
+          const int kq = atomicAdd(mvn, 1);
+          mvx[kq] = xp;
+          mvy[kq] = y;
+        }
+      }
+    }
+    __syncthreads();
+    if (J > 0) move_rows_waves<NWV>(mvx, mvy, *mvn, Fm, np, j0);
+    __syncthreads();
+  }
+  int *ip = P.ipiv + (size_t)el * np;
+  for (int i = threadIdx.x; i < np; i += NTR) ip[i] = perm[i];
+  if (singular && threadIdx.x == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
+}
+
+template <int NWV, int TPW>
+__global__ __launch_bounds__(64 * NWV) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_lu_reg(DevPlan P,
+                                                                                               int32_t *status,
+                                                                                               double *inv) {
+  lu_reg_body<NWV, TPW>(P, blockIdx.x, status, inv);
+}
+
 }  // namespace
 
 int condense_width(int np, bool lp) {
@@ -1160,7 +1682,36 @@ static int rhs_grid(const DevPlan &P, int ec, int W) { return (ec + NXCD - 1) / 
 
 bool condense_two_launches(const DevPlan &P) { return P.cw == 32 && P.condense_launches == 2; }
 
+size_t lu_reg_lds_bytes(int np, int nwv) { return reg_layout(np, nwv).total; }
+
+// Register-resident LU (P.lu_waves waves per workgroup): 4 waves (two elements per CU, all
+// registers of a wave within 256) for n_pad <= 192, 8 waves for n_pad <= 640.
+bool lu_reg_supported(int np, int nwv) {
+  const int tpw = (np / 16 + nwv - 1) / nwv;
+  if (nwv == 4) return tpw <= 3 && reg_layout(np, 4).total <= 80 * 1024;
+  if (nwv == 8) return tpw <= 5 && reg_layout(np, 8).total <= 160 * 1024;
+  return false;
+}
+
+// Default LU of the two-launch FP64 condensation: the register-resident kernel with two
+// elements per CU where it applies (measured 1.7x the LDS kernel at n_pad = 160), else the
+// LDS kernel (at n_pad = 544 the register kernel streams the same factors and is slower).
+int default_lu_waves(int np) { return lu_reg_supported(np, 4) ? 4 : 0; }
+
+hipError_t launch_condense_lu_reg(const DevPlan &P, int ec, int32_t *status, hipStream_t s) {
+  const int np = P.n_pad, nwv = P.lu_waves, tpw = (np / 16 + nwv - 1) / nwv;
+  const size_t lds = reg_layout(np, nwv).total;
+  if (nwv == 4 && tpw <= 3) return launch_dyn_t(k_lu_reg<4, 3>, ec, 256, lds, s, P, status, P.inv);
+  if (nwv == 8) {
+    if (tpw <= 2) return launch_dyn_t(k_lu_reg<8, 2>, ec, 512, lds, s, P, status, P.inv);
+    if (tpw <= 3) return launch_dyn_t(k_lu_reg<8, 3>, ec, 512, lds, s, P, status, P.inv);
+    if (tpw <= 5) return launch_dyn_t(k_lu_reg<8, 5>, ec, 512, lds, s, P, status, P.inv);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_condense_lu(const DevPlan &P, int e0, int ec, int32_t *status, hipStream_t s) {
+  if (P.lu_waves) return launch_condense_lu_reg(P, ec, status, s);
   return launch_dyn(k_lu_f64_w32, ec, condense_lds_bytes(P.n_pad, 32), s, P, e0, status, P.inv);
 }
 

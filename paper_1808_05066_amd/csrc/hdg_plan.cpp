@@ -316,6 +316,8 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   D.sigma_s = (opts && (opts->flags & HDG_FLAG_SIGMA_MV)) ? 2 : (opts && (opts->flags & HDG_FLAG_SIGMA_S)) ? 1 : 0;
   D.a_qmin = 0;
   D.condense_launches = 2;
+  D.lu_waves = default_lu_waves(D.n_pad);
+  D.lu_waves_set = 0;
   P->fused = D.cw != 0;
   if (opts && (opts->flags & HDG_FLAG_SPLIT_DENSE)) P->fused = false;
   P->split_ok = lu_lds_bytes(D.n_pad) <= 160 * 1024;
@@ -897,6 +899,8 @@ extern "C" int hdg_assemble_condense(hdg_plan *plan, const double *v, const doub
         r.n = P->dp.m * P->dp.Np;
         r.n_pad = P->qa.nr_pad;
         r.cw = condense_width(r.n_pad, false);
+        if (!r.lu_waves_set) r.lu_waves = default_lu_waves(r.n_pad);
+        if (r.lu_waves && !lu_reg_supported(r.n_pad, r.lu_waves)) r.lu_waves = 0;
         r.A = P->qa.A;
         r.X = P->qa.X;
         r.C = P->qa.C;

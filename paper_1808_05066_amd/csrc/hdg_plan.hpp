@@ -29,6 +29,9 @@ struct DevPlan {
   int sigma_s;             // stabilization: 0 sigma_SLF = lambda_max A0, 1 sigma_S = |A_n| A0 (both at v_hat),
                            // 2 sigma_MV (mean value between v_hat and v)
   int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
+  int lu_waves;            // LU of the two-launch FP64 condensation: 0 working block in LDS (k_lu_f64_w32),
+                           // 4 or 8: in the registers of that many waves (k_lu_reg)
+  int lu_waves_set;        // 1: lu_waves chosen by hdg_plan_set_tuning (else the default per block size)
   double gamma, mu, Pr, alpha;
   const double *src;       // source of the conservation law (device, caller-owned) or null: nodal [m][E*Np],
   int src_qp;              // or (src_qp = 1) its values at the volume quadrature points [m][E*Nq]
@@ -208,6 +211,9 @@ hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, do
 // FP64 condensation in two launches (32-column blocks, condense_launches == 2): the LU, then the right-hand sides
 bool condense_two_launches(const DevPlan &P);
 hipError_t launch_condense_lu(const DevPlan &P, int e0, int ec, int32_t *status, hipStream_t s);
+bool lu_reg_supported(int np, int nwv);
+int default_lu_waves(int np);
+size_t lu_reg_lds_bytes(int np, int nwv);
 hipError_t launch_condense_rhs(const DevPlan &P, int e0, int ec, double *S, double *g, double *Y, double *z,
                                hipStream_t s);
 hipError_t launch_bj_assemble(const DevPlan &P, const double *S, double *B, hipStream_t s);

@@ -81,9 +81,10 @@ class Plan:
         check(self.lib.hdg_plan_get_tuning(self.h, ctypes.byref(t)), "hdg_plan_get_tuning")
         return {f: getattr(t, f) for f, _ in _lib.hdg_tuning._fields_}
 
-    def set_tuning(self, contract_threads=0, condense_width=0, condense_width_lp=0, condense_launches=0):
+    def set_tuning(self, contract_threads=0, condense_width=0, condense_width_lp=0, condense_launches=0,
+                   lu_waves=0):
         t = _lib.hdg_tuning(int(contract_threads), int(condense_width), int(condense_width_lp),
-                            int(condense_launches))
+                            int(condense_launches), int(lu_waves))
         check(self.lib.hdg_plan_set_tuning(self.h, ctypes.byref(t)), "hdg_plan_set_tuning")
 
     def __del__(self):

@@ -96,6 +96,45 @@ def test_condense_matches_oracle(torch, name, chunk, split, narrow):
     assert zf <= 1e-11, zf
 
 
+@pytest.mark.parametrize("name", list(SMALL_CASES))
+@pytest.mark.parametrize("lu_waves,chunk", [(4, 0), (8, 0), (4, 3)])
+def test_register_lu_matches_oracle(torch, name, lu_waves, chunk):
+    """The LU with its working block in registers (4 or 8 waves) in front of the same
+    right-hand-side launch: S, Y, g, z against the oracle at the bar of the LDS kernel, and
+    against the LDS kernel's outputs on the same plan.  Four waves take n_pad <= 192 only;
+    a larger block must be refused."""
+    wl, disc, inp, blocks = _case(name)
+    print("case", name, "lu_waves", lu_waves, "chunk", chunk, flush=True)
+    plan = gpu_plan(wl, chunk_elems=chunk)
+    d = to_dev(inp)
+    if lu_waves == 4 and plan.n_pad > 192:
+        with pytest.raises(RuntimeError):
+            plan.set_tuning(lu_waves=4)
+        return
+    plan.set_tuning(lu_waves=1)
+    ref = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    plan.set_tuning(lu_waves=lu_waves)
+    assert plan.tuning()["lu_waves"] == lu_waves
+    out = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"], residuals=True)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().max()) == 0
+    errs = {
+        "S": rel_err_per_elem(out["S"].cpu().numpy(), colmajor([b["S"] for b in blocks])),
+        "Y": rel_err_per_elem(out["Y"].cpu().numpy(), colmajor([b["Y"] for b in blocks])),
+        "g": rel_err_per_elem(out["g"].cpu().numpy(), np.stack([b["g"] for b in blocks])),
+        "z_backward": max(z_backward_err(disc, inp, e, b["A"], b["R_loc"], out["z"][e].cpu().numpy())
+                          for e, b in enumerate(blocks)),
+    }
+    print(name, errs)
+    for key, err in errs.items():
+        assert err <= TOL, (key, err)
+    zf = rel_err_per_elem(out["z"].cpu().numpy(), np.stack([b["z"] for b in blocks]))
+    assert zf <= 1e-11, zf
+    for key in ("S", "Y", "g"):
+        diff = rel_err_per_elem(out[key].cpu().numpy(), ref[key].cpu().numpy())
+        assert diff <= TOL, (key, diff)
+
+
 @pytest.mark.parametrize("name", ["euler2d_tri_p2", "ns2d_tri_p2", "ns3d_hex_p1", "ns3d_hex_p2"])
 def test_trace_operator_backsolve_and_brute_force(torch, name):
     """Condensed solve with GPU S, g + GPU back-solve == oracle brute-force full solve.  The p = 2
