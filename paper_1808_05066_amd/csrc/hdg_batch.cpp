@@ -1,6 +1,7 @@
 // Batches of plans (element types and orders with uneven block sizes)
-// condensed in one persistent launch, and hipGraph capture of the whole
-// assemble + condense sequence of a batch.
+// condensed by two persistent launches (the LU items, then the right-hand-side
+// items in per-XCD queues), and hipGraph capture of the whole assemble +
+// condense sequence of a batch.
 #include <algorithm>
 #include <numeric>
 #include <vector>
@@ -11,8 +12,9 @@ using namespace hdg;
 
 namespace hdg {
 size_t batch_item_args_bytes();
-hipError_t launch_condense_batch(const DevPlan *plans_dev, const void *io_dev, const int *queue, int n_items,
-                                 int *counter, int n_groups, size_t lds, hipStream_t s);
+hipError_t launch_condense_batch(const DevPlan *plans_dev, const void *io_dev, const int *lu_queue, int n_lu,
+                                 const void *rhs_queue, const int *rhs_xoff, int *counters, int lu_groups,
+                                 int rhs_groups, size_t lds, hipStream_t s);
 }  // namespace hdg
 
 namespace {
@@ -22,16 +24,22 @@ struct ItemArgs {   // device layout of the per-plan outputs read by the persist
   int32_t *status;
 };
 
+constexpr int NXCD = 8;
+
 struct Batch {
   std::vector<Plan *> plans;
-  std::vector<int> queue;
+  std::vector<int> queue;       // LU items: plan << 24 | element
+  std::vector<int> rhs;         // right-hand-side items: (plan << 24 | element, block), by XCD
+  int xoff[NXCD + 1] = {0};     // start of each XCD's items in rhs (in items)
   size_t lds = 0;
-  int groups = 0;
+  int groups = 0, rhs_groups = 0;
   bool bound = false;
   DevPlan *d_plans = nullptr;
   ItemArgs *d_io = nullptr;
   int *d_queue = nullptr;
-  int *d_counter = nullptr;
+  int *d_rhs = nullptr;
+  int *d_xoff = nullptr;
+  int *d_counter = nullptr;     // [1 + NXCD]
   std::vector<hdg_batch_io> io;
   bool io_set = false;
   hipGraph_t graph = nullptr;
@@ -41,7 +49,7 @@ struct Batch {
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct BatchLayout {
-  size_t plans, io, queue, counter, total;
+  size_t plans, io, queue, rhs, xoff, counter, total;
 };
 
 BatchLayout batch_layout(const Batch *B) {
@@ -53,6 +61,10 @@ BatchLayout batch_layout(const Batch *B) {
   o = a256(o + B->plans.size() * sizeof(ItemArgs));
   l.queue = o;
   o = a256(o + B->queue.size() * sizeof(int));
+  l.rhs = o;
+  o = a256(o + B->rhs.size() * sizeof(int));
+  l.xoff = o;
+  o = a256(o + (NXCD + 1) * sizeof(int));
   l.counter = o;
   o = a256(o + 64);
   l.total = o;
@@ -77,7 +89,7 @@ extern "C" int hdg_batch_create(hdg_batch **out, hdg_plan *const *plans, int n_p
     double cost;
     int plan, el;
   };
-  std::vector<Item> items;
+  std::vector<Item> items, ritems;
   for (int i = 0; i < n_plans; ++i) {
     Plan *P = reinterpret_cast<Plan *>(plans[i]);
     if (!P || !P->bound || !P->fused || P->chunk < P->n_elem || P->n_elem >= (1 << 24)) {
@@ -87,15 +99,36 @@ extern "C" int hdg_batch_create(hdg_batch **out, hdg_plan *const *plans, int n_p
     B->plans.push_back(P);
     B->lds = std::max(B->lds, condense_lds_bytes(P->dp.n_pad, P->dp.cw));
     const double np = P->dp.n_pad, kp = P->dp.k_pad;
-    const double cost = np * np * np / 3.0 + np * np * kp + np * kp * kp;   // LU + solves + Schur
-    for (int e = 0; e < P->n_elem; ++e) items.push_back({cost, i, e});
+    const double lu = np * np * np / 3.0, rhs = np * np * kp + np * kp * kp;   // LU; solves + Schur
+    for (int e = 0; e < P->n_elem; ++e) {
+      items.push_back({lu, i, e});
+      ritems.push_back({rhs, i, e});
+    }
   }
-  if (order == 0)   // longest processing time first
-    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) { return a.cost > b.cost; });
+  const auto by_cost = [](const Item &a, const Item &b) { return a.cost > b.cost; };
+  if (order == 0) {   // longest processing time first
+    std::stable_sort(items.begin(), items.end(), by_cost);
+    std::stable_sort(ritems.begin(), ritems.end(), by_cost);
+  }
   for (const Item &it : items) B->queue.push_back((it.plan << 24) | it.el);
+  // right-hand-side items: the k-th element (in queue order) to XCD k mod 8, its blocks together
+  std::vector<std::vector<int>> xq(NXCD);
+  for (size_t k = 0; k < ritems.size(); ++k) {
+    const Item &it = ritems[k];
+    const DevPlan &D = B->plans[it.plan]->dp;
+    for (int j = 0; j < D.kx / D.cw; ++j) {
+      xq[k % NXCD].push_back((it.plan << 24) | it.el);
+      xq[k % NXCD].push_back(j);
+    }
+  }
+  for (int x = 0; x < NXCD; ++x) {
+    B->xoff[x + 1] = B->xoff[x] + (int)xq[x].size() / 2;
+    B->rhs.insert(B->rhs.end(), xq[x].begin(), xq[x].end());
+  }
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) cus = 256;
   B->groups = std::max(1, std::min<int>(cus, (int)B->queue.size()));
+  B->rhs_groups = NXCD * std::max(1, cus / NXCD);
   *out = reinterpret_cast<hdg_batch *>(B);
   return HDG_OK;
 }
@@ -123,12 +156,16 @@ extern "C" int hdg_batch_bind_workspace(hdg_batch *batch, void *ptr, size_t byte
   B->d_plans = reinterpret_cast<DevPlan *>(base + l.plans);
   B->d_io = reinterpret_cast<ItemArgs *>(base + l.io);
   B->d_queue = reinterpret_cast<int *>(base + l.queue);
+  B->d_rhs = reinterpret_cast<int *>(base + l.rhs);
+  B->d_xoff = reinterpret_cast<int *>(base + l.xoff);
   B->d_counter = reinterpret_cast<int *>(base + l.counter);
   std::vector<DevPlan> dp;
   for (Plan *P : B->plans) dp.push_back(P->dp);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(B->d_plans, dp.data(), dp.size() * sizeof(DevPlan), hipMemcpyHostToDevice, s);
   if (!e) e = hipMemcpyAsync(B->d_queue, B->queue.data(), B->queue.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(B->d_rhs, B->rhs.data(), B->rhs.size() * sizeof(int), hipMemcpyHostToDevice, s);
+  if (!e) e = hipMemcpyAsync(B->d_xoff, B->xoff, sizeof(B->xoff), hipMemcpyHostToDevice, s);
   if (!e) e = hipStreamSynchronize(s);
   if (e) return hip_fail(e, "batch_bind");
   B->bound = true;
@@ -140,6 +177,7 @@ extern "C" int hdg_batch_set_groups(hdg_batch *batch, int groups) {
   Batch *B = reinterpret_cast<Batch *>(batch);
   if (!B || groups < 1) return fail(HDG_EINVAL, "bad argument");
   B->groups = std::min<int>(groups, (int)B->queue.size());
+  B->rhs_groups = NXCD * ((groups + NXCD - 1) / NXCD);
   drop_graph(B);
   return HDG_OK;
 }
@@ -174,10 +212,10 @@ int batch_sequence(Batch *B, hipStream_t s) {
     int rc = run_front(P, a.v, a.q, a.vhat, a.u_star, a.v_bc, a.elem_status, 0, P->n_elem, s, P->dp.mg != nullptr);
     if (rc) return rc;
   }
-  hipError_t e = launch_fill_int(B->d_counter, 1, 0, s);
+  hipError_t e = launch_fill_int(B->d_counter, 1 + NXCD, 0, s);
   if (!e)
-    e = launch_condense_batch(B->d_plans, B->d_io, B->d_queue, (int)B->queue.size(), B->d_counter, B->groups, B->lds,
-                              s);
+    e = launch_condense_batch(B->d_plans, B->d_io, B->d_queue, (int)B->queue.size(), B->d_rhs, B->d_xoff,
+                              B->d_counter, B->groups, B->rhs_groups, B->lds, s);
   if (e) return hip_fail(e, "batch condense");
   return HDG_OK;
 }

@@ -1032,18 +1032,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
   condense_body<float, true, W>(P, e0, blockIdx.x, status, S, g, Y, z, nullptr, fac);
 }
 
-// Persistent condensation over a batch of plans (element types / orders with
-// uneven n, k): every workgroup takes work items from a queue ordered by
-// decreasing block size (longest processing time first) until it is empty.
-// Item i = (plan index, element) packed as plan << 24 | element.
+// Persistent condensation over a batch of plans (element types / orders with uneven n, k), in
+// two launches as the per-plan path: every workgroup takes work items from a queue until it
+// is empty.
+// * LU items (plan << 24 | element), longest processing time first: the LU of the element.
+// * Right-hand-side items (plan << 24 | element, block j): one 32- (or 16-) column block of
+//   [B | R_loc] against the element's factors.  Eight queues, one per XCD: the items of an
+//   element sit together in the queue of one XCD, and a workgroup takes items from the queue
+//   of the XCD it runs on (workgroups are handed to the XCDs round-robin by index), so the
+//   workgroups working on an element share its factors and C in that XCD's L2.
 struct BatchItemArgs {
   double *S, *g, *Y, *z;
   int32_t *status;
 };
 
-__global__ __launch_bounds__(NT) void k_condense_batch(const DevPlan *__restrict__ plans,
-                                                       const BatchItemArgs *__restrict__ io,
-                                                       const int *__restrict__ queue, int n_items, int *counter) {
+__global__ __launch_bounds__(NT) void k_lu_batch(const DevPlan *__restrict__ plans,
+                                                 const BatchItemArgs *__restrict__ io,
+                                                 const int *__restrict__ queue, int n_items, int *counter) {
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
@@ -1054,11 +1059,41 @@ __global__ __launch_bounds__(NT) void k_condense_batch(const DevPlan *__restrict
     const int code = queue[it];
     const int pi = code >> 24, el = code & 0xFFFFFF;
     const DevPlan &P = plans[pi];
-    const BatchItemArgs &a = io[pi];
-    if (P.cw == 32)
-      condense_body<double, false, 32>(P, 0, el, a.status, a.S, a.g, a.Y, a.z, P.inv, nullptr);
-    else
-      condense_body<double, false, 16>(P, 0, el, a.status, a.S, a.g, a.Y, a.z, P.inv, nullptr);
+    if (P.cw == 32) lu_body<double, false, 32>(P, 0, el, io[pi].status, P.inv, nullptr);
+    else lu_body<double, false, 16>(P, 0, el, io[pi].status, P.inv, nullptr);
+    __syncthreads();
+  }
+}
+
+template <int W>
+__device__ __forceinline__ void rhs_item(const DevPlan &P, int el, int j, const BatchItemArgs &a) {
+  const int np = P.n_pad;
+  const Lds<double> s = carve_lds<double, false, W>(np);
+  const FactorPtrs<double, false> f = factor_ptrs<double, false>(P, el, el, P.inv, nullptr);
+  const int *perm = P.ipiv + (size_t)el * np;
+  for (int i = threadIdx.x; i < np; i += NT_RHS) s.perm[i] = perm[i];
+  __syncthreads();
+  rhs_block<double, false, W, NT_RHS>(P, el, el, j * W, s, f, a.S, a.g, a.Y, a.z);
+}
+
+__global__ __launch_bounds__(NT_RHS) void k_rhs_batch(const DevPlan *__restrict__ plans,
+                                                      const BatchItemArgs *__restrict__ io,
+                                                      const int2 *__restrict__ queue, const int *__restrict__ xoff,
+                                                      int *counters) {
+  __shared__ int s_item;
+  const int x = blockIdx.x % NXCD;
+  const int n_items = xoff[x + 1] - xoff[x];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&counters[x], 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const int2 c = queue[xoff[x] + it];
+    const int pi = c.x >> 24, el = c.x & 0xFFFFFF;
+    const DevPlan &P = plans[pi];
+    if (P.cw == 32) rhs_item<32>(P, el, c.y, io[pi]);
+    else rhs_item<16>(P, el, c.y, io[pi]);
     __syncthreads();
   }
 }
@@ -1755,12 +1790,18 @@ hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status,
 
 size_t batch_item_args_bytes() { return sizeof(BatchItemArgs); }
 
-hipError_t launch_condense_batch(const DevPlan *plans_dev, const void *io_dev, const int *queue, int n_items,
-                                 int *counter, int n_groups, size_t lds, hipStream_t s) {
-  hipError_t e = set_dyn_lds((const void *)k_condense_batch, lds);
+hipError_t launch_condense_batch(const DevPlan *plans_dev, const void *io_dev, const int *lu_queue, int n_lu,
+                                 const void *rhs_queue, const int *rhs_xoff, int *counters, int lu_groups,
+                                 int rhs_groups, size_t lds, hipStream_t s) {
+  hipError_t e = set_dyn_lds((const void *)k_lu_batch, lds);
+  if (!e) e = set_dyn_lds((const void *)k_rhs_batch, lds);
   if (e) return e;
-  hipLaunchKernelGGL(k_condense_batch, dim3(n_groups), dim3(NT), lds, s, plans_dev,
-                     static_cast<const BatchItemArgs *>(io_dev), queue, n_items, counter);
+  const BatchItemArgs *io = static_cast<const BatchItemArgs *>(io_dev);
+  hipLaunchKernelGGL(k_lu_batch, dim3(lu_groups), dim3(NT), lds, s, plans_dev, io, lu_queue, n_lu, counters);
+  e = hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_rhs_batch, dim3(rhs_groups), dim3(NT_RHS), lds, s, plans_dev, io,
+                     static_cast<const int2 *>(rhs_queue), rhs_xoff, counters + 1);
   return hipGetLastError();
 }
 
