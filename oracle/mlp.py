@@ -1,13 +1,18 @@
 """NumPy reference of the learned block-Jacobi correction (oracle; test infrastructure only).
 
-Not in the paper.  The learned preconditioner rescales every block-Jacobi
-inverse B_F of the condensed trace operator K row- and column-wise,
+Not in the paper.  The learned preconditioner corrects every block-Jacobi
+inverse B_F of the condensed trace operator K by a row and column rescaling
+and a rank-R term,
 
-    M_F^-1 = diag(e^a) B_F diag(e^b),    (a_i, b_i) = 0.5 tanh(o_i),
+    M_F^-1 = diag(e^a) (B_F + (c U)(c V)^T) diag(e^b),
+    a_i = 0.5 tanh(o_i0),  b_i = 0.5 tanh(o_i1),
+    U_ik = tanh(o_i,2+k),  V_ik = tanh(o_i,2+R+k),  c_i = |B_F,ii|^(1/2),
 
-with o_i the output of a small multilayer perceptron applied to per-unknown
-features (16 -> 32 -> 32 -> 2, tanh hidden layers, linear output).  It is
-trained to make M^-1 K close to the identity on random vectors,
+(c U meaning diag(c) U), with o_i the output of a small multilayer perceptron
+applied to per-unknown features (16 -> 32 -> 32 -> 2 + 2R, tanh hidden layers,
+linear output).  Row i of U and V comes from row i's own features, so the
+rank-R term couples the unknowns of a block with one another.  It is trained
+to make M^-1 K close to the identity on random vectors,
 
     L = sum_v ||x_v - M^-1 K x_v||^2 / sum_v ||x_v||^2,
 
@@ -15,13 +20,14 @@ with Adam (Kingma & Ba).  Everything here is FP64 and written for checking:
 plain loops over blocks, explicit chain rule, no fusion.
 
 Parameter vector layout (shared with the device kernels):
-    W1 [32][16], b1 [32], W2 [32][32], b2 [32], W3 [2][32], b3 [2].
+    W1 [32][16], b1 [32], W2 [32][32], b2 [32], W3 [2+2R][32], b3 [2+2R].
 """
 from __future__ import annotations
 
 import numpy as np
 
-NF, NH, NO = 16, 32, 2
+NF, NH, R = 16, 32, 4
+NO = 2 + 2 * R
 SHAPES = [("W1", (NH, NF)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)), ("W3", (NO, NH)), ("b3", (NO,))]
 N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
 
@@ -92,38 +98,69 @@ def scalings(o):
     return 0.5 * np.tanh(o[:, 0]), 0.5 * np.tanh(o[:, 1])
 
 
+def low_rank(o):
+    """U, V (rows x R) of the rank-R term."""
+    return np.tanh(o[:, 2:2 + R]), np.tanh(o[:, 2 + R:2 + 2 * R])
+
+
+def corrected_block(BF, oF):
+    """M_F^-1 of one block (bs x bs) from its inverse BF and the outputs oF (bs x NO)."""
+    a, b = scalings(oF)
+    U, V = low_rank(oF)
+    c = np.sqrt(np.abs(np.diag(BF)))
+    return np.exp(a)[:, None] * (BF + (c[:, None] * U) @ (c[:, None] * V).T) * np.exp(b)[None, :]
+
+
 def precond_loss(Binv, o, X, Wv):
-    """Loss L and dL/do for block inverses Binv (nblk x bs x bs), outputs o (nblk*bs x 2).
+    """Loss L and dL/do for block inverses Binv (nblk x bs x bs), outputs o (nblk*bs x NO).
 
     X, Wv: (nvec, nblk*bs) random vectors and their images w = K x, both in the
-    block-row order (block F, position i -> row F*bs + i).
+    block-row order (block F, position i -> row F*bs + i).  Per block and vector,
+    with e = e^b w, t = (cV)^T e, u = B e + (cU) t, y = e^a u, r = x - y:
+    dL/dy = -2 r / |X|^2, and the chain rule back through u, t, e to a, b, U, V.
     """
     nblk, bs, _ = Binv.shape
     a, b = scalings(o)
+    U, V = low_rank(o)
     ea, eb = np.exp(a), np.exp(b)
     x2 = float(np.sum(X ** 2))
     loss = 0.0
     ga, gb = np.zeros_like(a), np.zeros_like(b)
-    for v in range(X.shape[0]):
-        for F in range(nblk):
-            rows = slice(F * bs, (F + 1) * bs)
-            u = Binv[F] @ (eb[rows] * Wv[v, rows])
+    gU, gV = np.zeros_like(U), np.zeros_like(V)
+    for F in range(nblk):
+        rows = slice(F * bs, (F + 1) * bs)
+        BF = Binv[F]
+        c = np.sqrt(np.abs(np.diag(BF)))
+        cU, cV = c[:, None] * U[rows], c[:, None] * V[rows]
+        for v in range(X.shape[0]):
+            e = eb[rows] * Wv[v, rows]
+            t = cV.T @ e
+            u = BF @ e + cU @ t
             y = ea[rows] * u
             r = X[v, rows] - y
             loss += float(r @ r)
             dy = -2.0 * r / x2
             ga[rows] += dy * y
-            gb[rows] += (Binv[F].T @ (ea[rows] * dy)) * eb[rows] * Wv[v, rows]
-    dO = np.stack([ga * 0.5 * (1.0 - np.tanh(o[:, 0]) ** 2), gb * 0.5 * (1.0 - np.tanh(o[:, 1]) ** 2)], 1)
+            du = ea[rows] * dy
+            gU[rows] += np.outer(du, t) * c[:, None]
+            dt = cU.T @ du
+            gV[rows] += np.outer(e, dt) * c[:, None]
+            de = BF.T @ du + cV @ dt
+            gb[rows] += de * e
+    th = np.tanh(o)
+    dO = np.zeros_like(o)
+    dO[:, 0] = ga * 0.5 * (1.0 - th[:, 0] ** 2)
+    dO[:, 1] = gb * 0.5 * (1.0 - th[:, 1] ** 2)
+    dO[:, 2:2 + R] = gU * (1.0 - th[:, 2:2 + R] ** 2)
+    dO[:, 2 + R:] = gV * (1.0 - th[:, 2 + R:] ** 2)
     return loss / x2, dO
 
 
 def apply_scaled(Binv, o, w):
-    """M^-1 w with the scaled blocks (block-row order)."""
+    """M^-1 w with the corrected blocks (block-row order)."""
     nblk, bs, _ = Binv.shape
-    a, b = scalings(o)
     out = np.zeros_like(w)
     for F in range(nblk):
         rows = slice(F * bs, (F + 1) * bs)
-        out[rows] = np.exp(a[rows]) * (Binv[F] @ (np.exp(b[rows]) * w[rows]))
+        out[rows] = corrected_block(Binv[F], o[rows]) @ w[rows]
     return out

@@ -37,9 +37,10 @@ def test_backward_matches_finite_differences():
 def test_constant_network_and_block_jacobi_start():
     X = np.random.default_rng(3).normal(size=(5, mlp.NF))
     parts = mlp.unpack(np.zeros(mlp.N_PARAMS))
-    parts["b3"] = np.array([0.7, -0.2])
+    b3 = np.linspace(-0.7, 0.7, mlp.NO)
+    parts["b3"] = b3
     o, _ = mlp.forward(mlp.pack(parts), X)
-    assert np.allclose(o, [[0.7, -0.2]] * 5, rtol=0, atol=0)
+    assert np.allclose(o, [b3] * 5, rtol=0, atol=0)
     theta = mlp.init_params(0)
     o, _ = mlp.forward(theta, X)
     assert np.all(o == 0.0)
@@ -61,11 +62,11 @@ def test_loss_gradient_matches_finite_differences():
     rng = np.random.default_rng(5)
     X = rng.normal(size=(3, K.shape[0]))
     Wv = X @ K.T
-    o = rng.normal(scale=0.5, size=(K.shape[0], 2))
+    o = rng.normal(scale=0.5, size=(K.shape[0], mlp.NO))
     L, dO = mlp.precond_loss(Binv, o, X, Wv)
     h = 1e-6
     for i in range(0, K.shape[0], 3):
-        for j in range(2):
+        for j in range(mlp.NO):
             op, om = o.copy(), o.copy()
             op[i, j] += h
             om[i, j] -= h
@@ -80,8 +81,27 @@ def test_exact_inverse_gives_zero_loss_and_zero_output_is_block_jacobi():
     K, Binv = _block_system(6, coupling=0.0)
     X = np.random.default_rng(7).normal(size=(2, K.shape[0]))
     Wv = X @ K.T
-    L, dO = mlp.precond_loss(Binv, np.zeros((K.shape[0], 2)), X, Wv)
+    L, dO = mlp.precond_loss(Binv, np.zeros((K.shape[0], mlp.NO)), X, Wv)
     assert L <= 1e-24 and np.max(np.abs(dO)) <= 1e-12
+
+
+def test_corrected_block_is_scaling_plus_rank_r():
+    """The corrected block against its definition written out entry by entry: row and column
+    rescaling of B + sum_k c_i c_j U_ik V_jk, of rank at most R in the correction."""
+    rng = np.random.default_rng(9)
+    bs = 6
+    BF = rng.normal(size=(bs, bs)) + 3 * np.eye(bs)
+    oF = rng.normal(scale=0.7, size=(bs, mlp.NO))
+    M = mlp.corrected_block(BF, oF)
+    for i in range(bs):
+        for j in range(bs):
+            ai, bj = 0.5 * np.tanh(oF[i, 0]), 0.5 * np.tanh(oF[j, 1])
+            ci, cj = np.sqrt(abs(BF[i, i])), np.sqrt(abs(BF[j, j]))
+            corr = sum(ci * cj * np.tanh(oF[i, 2 + k]) * np.tanh(oF[j, 2 + mlp.R + k]) for k in range(mlp.R))
+            assert abs(M[i, j] - np.exp(ai) * (BF[i, j] + corr) * np.exp(bj)) <= 1e-13 * (1 + abs(M[i, j]))
+    a, b = mlp.scalings(oF)
+    D = np.exp(-a)[:, None] * M * np.exp(-b)[None, :] - BF
+    assert np.linalg.matrix_rank(D, tol=1e-10) <= mlp.R
 
 
 def test_adam_first_step_is_lr_times_sign():
