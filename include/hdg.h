@@ -406,32 +406,39 @@ int hdg_trace_solve(hdg_plan *plan, const void *S, const double *rhs, double *x,
                     size_t bytes, const hdg_solve_opts *opts, hdg_solve_info *info, void *stream);
 
 /* ---- Learned block-Jacobi correction ---------------------------------------
- * Not in the paper.  A small network rescales every block-Jacobi inverse B_F:
- *   M_F^-1 = diag(e^a) B_F diag(e^b),  (a_i, b_i) = 0.5 tanh(o_i),
- *   o_i = W3 tanh(W2 tanh(W1 f_i + b1) + b2) + b3   (16 -> 32 -> 32 -> 2, FP32)
+ * Not in the paper.  A small network corrects every block-Jacobi inverse B_F by
+ * a row and column rescaling and a rank-R term (R = 4) that couples the block's
+ * unknowns:
+ *   M_F^-1 = diag(e^a) (B_F + (c U)(c V)^T) diag(e^b),  c_i = |B_F,ii|^(1/2),
+ *   a_i = 0.5 tanh(o_i,0), b_i = 0.5 tanh(o_i,1),
+ *   U_ik = tanh(o_i,2+k), V_ik = tanh(o_i,2+R+k)   (k < R),
+ *   o_i = W3 tanh(W2 tanh(W1 f_i + b1) + b2) + b3   (16 -> 32 -> 32 -> NO = 2 + 2R, FP32)
  * with f_i 16 features of block row i (log10 |D_ii| and ||D_i,:|| of the
  * assembled block, log10 of the coupling of the row to other blocks and its
  * ratio to the row norm, one-hot component, node position on the face, local
  * Mach number, log10 p and log10 rho of the trace state, a constant 1; logs
  * scaled by 1/4).  Rows are in block order (block F, position i -> F*bs + i,
  * i = c * nodes_per_block + p); N_rows = m * n_trace.  Parameters (float,
- * hdg_learn_nparams of them): W1[32][16] b1[32] W2[32][32] b2[32] W3[2][32] b3[2].
+ * hdg_learn_nparams of them): W1[32][16] b1[32] W2[32][32] b2[32] W3[NO][32] b3[NO].
  * Training loss over random vectors x_v with w_v = K x_v:
  *   L = sum_v ||x_v - M^-1 w_v||^2 / x2,  x2 = sum_v ||x_v||^2,
  * minimized with Adam (beta 0.9, 0.999, eps 1e-8).  All pointers device. */
 int hdg_learn_nparams(void);
+/* NO, the network outputs per row. */
+int hdg_learn_outputs(void);
 
 /* Block-Jacobi setup as hdg_precond_setup (inverses into `work`) plus the
  * features feat [N_rows][16] from S (type per opts->s_dtype) and vhat [m][n_trace]. */
 int hdg_learn_setup(hdg_plan *plan, const void *S, const double *vhat, float *feat, void *work, size_t bytes,
                     const hdg_solve_opts *opts, void *stream);
-/* out [N_rows][2] = network outputs o. */
+/* out [N_rows][NO] = network outputs o. */
 int hdg_learn_forward(hdg_plan *plan, const float *theta, const float *feat, float *out, void *stream);
-/* Rescale the inverses held in `work` with the outputs; hdg_trace_solve with
- * precond 1 then applies the learned preconditioner (same cost as block Jacobi). */
+/* Replace the inverses held in `work` by the corrected blocks M_F^-1 (formed
+ * whole, bs <= 256); hdg_trace_solve with precond 1 then applies the learned
+ * preconditioner (same cost as block Jacobi). */
 int hdg_learn_apply(hdg_plan *plan, const float *out, void *work, size_t bytes, const hdg_solve_opts *opts,
                     void *stream);
-/* Loss (into *loss, device double) and dL/do [N_rows][2] for nvec vectors X, Wv
+/* Loss (into *loss, device double) and dL/do [N_rows][NO] for nvec vectors X, Wv
  * [nvec][m][n_trace] with the UNSCALED inverses in `work`. */
 int hdg_learn_loss_grad(hdg_plan *plan, const void *work, size_t bytes, const hdg_solve_opts *opts,
                         const float *out, const double *X, const double *Wv, int nvec, double x2, float *dO,
@@ -445,8 +452,8 @@ int hdg_learn_backward(hdg_plan *plan, const float *theta, const float *feat, co
  * memory (code under stream capture, serving loops, harnesses that forbid allocation): the
  * partial gradients live in a static device array of 32 MiB that the library holds on every GPU
  * it runs on until the process ends; no hipMalloc, hipFree or other allocation is made.  Same
- * kernels and result as hdg_learn_backward.  N_rows = m * n_trace may be at most 322,240 (the
- * array holds 5,035 workgroups of 64 rows); larger plans get HDG_EINVAL.  Calls on one GPU share
+ * kernels and result as hdg_learn_backward.  N_rows = m * n_trace may be at most 278,144 (the
+ * array holds 4,346 workgroups of 64 rows); larger plans get HDG_EINVAL.  Calls on one GPU share
  * the array: calls that overlap on one GPU (other streams or threads) race. */
 int hdg_learn_backward_noalloc(hdg_plan *plan, const float *theta, const float *feat, const float *dO, float *grad,
                                void *stream);
@@ -457,6 +464,27 @@ int hdg_learn_train_step(hdg_plan *plan, float *theta, float *m, float *v, int t
                          const void *work, size_t bytes, const hdg_solve_opts *opts, const double *X,
                          const double *Wv, int nvec, double x2, float *out, float *dO, float *grad, float *scratch,
                          double *loss, void *stream);
+/* Training on face blocks sampled from many systems (a pool; blocks of equal size bs).
+ * hdg_learn_extract copies, after hdg_learn_setup of a system, the blocks sel[q] (device int
+ * array, nsel entries, q < nsel) to pool block b0 + q: the unscaled inverse into pool_B
+ * [blocks][bs][bs] (column-major), the rows' features into pool_feat [blocks * bs][16], and x and
+ * w = K x of the rows for the nvec vectors X, Wv [nvec][m][n_trace] into pool_X, pool_W
+ * [nvec][ld] (block-row order; ld >= (b0 + nsel) * bs, else HDG_EINVAL).  The caller owns the
+ * pool and picks the blocks. */
+int hdg_learn_extract(hdg_plan *plan, const void *work, size_t bytes, const hdg_solve_opts *opts, const float *feat,
+                      const double *X, const double *Wv, int nvec, const int *sel, int nsel, size_t b0, size_t ld,
+                      double *pool_B, float *pool_feat, double *pool_X, double *pool_W, void *stream);
+/* Network forward / backward on N rows of features (no plan); scratch of backward_rows:
+ * hdg_learn_rows_scratch_floats(N) floats. */
+int hdg_learn_forward_rows(const float *theta, const float *feat, size_t N, float *out, void *stream);
+int hdg_learn_rows_scratch_floats(size_t N, size_t *n);
+int hdg_learn_backward_rows(const float *theta, const float *feat, const float *dO, size_t N, float *grad,
+                            float *scratch, void *stream);
+/* Loss (into *loss, cleared first) and dL/do [nblk * bs][NO] over the first nblk pool blocks
+ * (bs <= 256), x2 the squared norm of the pool's x over those rows and vectors. */
+int hdg_learn_pool_loss_grad(int nblk, int bs, const double *pool_B, const float *out, const double *X,
+                             const double *Wv, size_t ld, int nvec, double x2, float *dO, double *loss,
+                             void *stream);
 
 /* ---- Mixed precision ------------------------------------------------------
  * Low-precision condensation with FP64 refinement of the full Newton linear

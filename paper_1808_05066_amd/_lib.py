@@ -139,6 +139,13 @@ SIGNATURES = {
     "hdg_entropy_integral": (I, [P, P, P, P]),
     "hdg_flow_statistics": (I, [P, P, P, P]),
     "hdg_learn_nparams": (I, []),
+    "hdg_learn_outputs": (I, []),
+    "hdg_learn_extract": (I, [P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P, P, P, I, P, I,
+                              ctypes.c_size_t, ctypes.c_size_t, P, P, P, P, P]),
+    "hdg_learn_forward_rows": (I, [P, P, ctypes.c_size_t, P, P]),
+    "hdg_learn_rows_scratch_floats": (I, [ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "hdg_learn_backward_rows": (I, [P, P, P, ctypes.c_size_t, P, P, P]),
+    "hdg_learn_pool_loss_grad": (I, [I, I, P, P, P, P, ctypes.c_size_t, I, ctypes.c_double, P, P, P]),
     "hdg_learn_setup": (I, [P, P, P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),
     "hdg_learn_forward": (I, [P, P, P, P, P]),
     "hdg_learn_apply": (I, [P, P, P, ctypes.c_size_t, ctypes.POINTER(hdg_solve_opts), P]),

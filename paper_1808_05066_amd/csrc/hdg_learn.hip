@@ -1,13 +1,17 @@
 // Learned correction of the block-Jacobi preconditioner (not in the paper).
 //
-// Every block-Jacobi inverse B_F of the condensed operator is rescaled as
-//   M_F^-1 = diag(e^a) B_F diag(e^b),   (a_i, b_i) = 0.5 tanh(o_i),
-// o_i = MLP(features of unknown i): 16 -> 32 (tanh) -> 32 (tanh) -> 2, FP32.
-// Training minimizes L = sum_v ||x_v - M^-1 K x_v||^2 / sum_v ||x_v||^2 over
-// random vectors with Adam; these kernels are the features, the network's
-// forward and backward passes, the loss gradient and the Adam update.
+// Every block-Jacobi inverse B_F of the condensed operator is corrected as
+//   M_F^-1 = diag(e^a) (B_F + (c U)(c V)^T) diag(e^b),
+//   a_i = 0.5 tanh(o_i0), b_i = 0.5 tanh(o_i1), U_ik = tanh(o_i,2+k), V_ik = tanh(o_i,2+R+k),
+//   c_i = |B_F,ii|^(1/2),
+// o_i = MLP(features of unknown i): 16 -> 32 (tanh) -> 32 (tanh) -> 2 + 2R, FP32, R = 4: a
+// rescaling of rows and columns and a rank-R term that couples the unknowns of the block.
+// Training minimizes L = sum_v ||x_v - M^-1 K x_v||^2 / sum_v ||x_v||^2 over random vectors
+// with Adam, either on a whole system or on a pool of face blocks sampled from many systems;
+// these kernels are the features, the network's forward and backward passes, the loss
+// gradient, the Adam update, the sampling into a pool and the correction of the inverses.
 //
-// Parameter vector (float): W1[32][16] b1[32] W2[32][32] b2[32] W3[2][32] b3[2].
+// Parameter vector (float): W1[32][16] b1[32] W2[32][32] b2[32] W3[NO][32] b3[NO], NO = 2 + 2R.
 // Rows are block rows: block F, position i -> F*bs + i, i = c*npb + p.
 #include <mutex>
 
@@ -18,7 +22,7 @@ namespace hdg {
 
 namespace {
 
-constexpr int NF = 16, NH = 32, NO = 2;
+constexpr int NF = 16, NH = 32, RK = 4, NO = 2 + 2 * RK;
 constexpr int OW1 = 0, OB1 = OW1 + NH * NF, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
               OB3 = OW3 + NO * NH, NPAR = OB3 + NO;
 constexpr float LOGS = 0.25f;   // scale of log10 features
@@ -131,62 +135,83 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ theta
   float x[NF], h1[NH], h2[NH], o[NO];
   for (int i = 0; i < NF; ++i) x[i] = feat[r * NF + i];
   mlp_fwd_row(th, x, h1, h2, o);
-  out[r * 2] = o[0];
-  out[r * 2 + 1] = o[1];
+  for (int j = 0; j < NO; ++j) out[r * NO + j] = o[j];
 }
 
-// Loss and dL/do per block: y = e^a (B (e^b w)), r = x - y over nvec vectors.
-__global__ void k_precond_grad(DevPlan P, const double *__restrict__ Binv, const float *__restrict__ o,
-                               const double *__restrict__ X, const double *__restrict__ Wv, int nvec, double x2,
-                               float *dO, double *loss) {
-  extern __shared__ double sm[];
-  const int blk = blockIdx.x, bs = P.bj_bs, npb = npb_of(P);
-  const size_t NT = (size_t)P.n_trace, NV = (size_t)P.m * NT;
-  double *ea = sm, *eb = ea + bs, *ew = eb + bs, *dy = ew + bs, *red = dy + bs;
-  const double *Bb = Binv + (size_t)blk * bs * bs;
+// Loss and dL/do of one block (bs <= blockDim.x <= 256, thread i = row i): per vector, with
+// e = e^b w, t = (cV)^T e, u = B e + (cU) t, y = e^a u, r = x - y, dL/dy = -2 r / x2, then
+// du = e^a dy, dt = (cU)^T du, de = B^T du + (cV) dt and dL/da = dy y, dL/dU = du t^T c,
+// dL/dV = e dt^T c, dL/db = de e.  xw(v, i) returns (x, w) of row i for vector v.
+template <typename XW>
+__device__ inline void precond_grad_block(const double *__restrict__ Bb, int bs, const float *__restrict__ ob,
+                                          int nvec, double x2, XW xw, float *dOb, double *loss, double *sm) {
+  double *ea = sm, *eb = ea + bs, *ew = eb + bs, *du = ew + bs, *c = du + bs, *cU = c + bs, *cV = cU + bs * RK,
+         *tt = cV + bs * RK, *dt = tt + RK, *red = dt + RK;
   const int tid = threadIdx.x;
-  double ga = 0.0, gb = 0.0, lsum = 0.0;
-  int gidx = -1;
-  double ta = 0.0, tb = 0.0;
+  double ga = 0.0, gb = 0.0, lsum = 0.0, gU[RK], gV[RK], th[NO];
+  for (int k = 0; k < RK; ++k) gU[k] = gV[k] = 0.0;
   if (tid < bs) {
-    const size_t r = (size_t)blk * bs + tid;
-    ta = tanh((double)o[r * 2]);
-    tb = tanh((double)o[r * 2 + 1]);
-    ea[tid] = exp(0.5 * ta);
-    eb[tid] = exp(0.5 * tb);
-    const int c = tid / npb, p = tid % npb;
-    gidx = (int)(c * NT) + P.bj_nodes[(size_t)blk * npb + p];
+    for (int j = 0; j < NO; ++j) th[j] = tanh((double)ob[tid * NO + j]);
+    ea[tid] = exp(0.5 * th[0]);
+    eb[tid] = exp(0.5 * th[1]);
+    c[tid] = sqrt(fabs(Bb[(size_t)tid * bs + tid]));
+    for (int k = 0; k < RK; ++k) {
+      cU[tid * RK + k] = c[tid] * th[2 + k];
+      cV[tid * RK + k] = c[tid] * th[2 + RK + k];
+    }
   }
   for (int v = 0; v < nvec; ++v) {
     __syncthreads();
     double xv = 0.0;
     if (tid < bs) {
-      ew[tid] = eb[tid] * Wv[(size_t)v * NV + gidx];
-      xv = X[(size_t)v * NV + gidx];
+      const double2 q = xw(v, tid);
+      xv = q.x;
+      ew[tid] = eb[tid] * q.y;
     }
     __syncthreads();
-    double y = 0.0;
+    if (tid < RK) {
+      double t = 0.0;
+      for (int j = 0; j < bs; ++j) t += cV[j * RK + tid] * ew[j];
+      tt[tid] = t;
+    }
+    __syncthreads();
     if (tid < bs) {
       double u = 0.0;
       for (int j = 0; j < bs; ++j) u += Bb[(size_t)j * bs + tid] * ew[j];
-      y = ea[tid] * u;
+      for (int k = 0; k < RK; ++k) u += cU[tid * RK + k] * tt[k];
+      const double y = ea[tid] * u;
       const double r = xv - y;
       lsum += r * r;
       const double d = -2.0 * r / x2;
       ga += d * y;
-      dy[tid] = ea[tid] * d;
+      du[tid] = ea[tid] * d;
+      for (int k = 0; k < RK; ++k) gU[k] += du[tid] * tt[k] * c[tid];
+    }
+    __syncthreads();
+    if (tid < RK) {
+      double t = 0.0;
+      for (int i = 0; i < bs; ++i) t += cU[i * RK + tid] * du[i];
+      dt[tid] = t;
     }
     __syncthreads();
     if (tid < bs) {
-      double t = 0.0;
-      for (int i = 0; i < bs; ++i) t += Bb[(size_t)tid * bs + i] * dy[i];
-      gb += t * ew[tid];
+      double de = 0.0;
+      for (int i = 0; i < bs; ++i) de += Bb[(size_t)tid * bs + i] * du[i];
+      for (int k = 0; k < RK; ++k) {
+        de += cV[tid * RK + k] * dt[k];
+        gV[k] += ew[tid] * dt[k] * c[tid];
+      }
+      gb += de * ew[tid];
     }
   }
   if (tid < bs) {
-    const size_t r = (size_t)blk * bs + tid;
-    dO[r * 2] = (float)(ga * 0.5 * (1.0 - ta * ta));
-    dO[r * 2 + 1] = (float)(gb * 0.5 * (1.0 - tb * tb));
+    float *o = dOb + (size_t)tid * NO;
+    o[0] = (float)(ga * 0.5 * (1.0 - th[0] * th[0]));
+    o[1] = (float)(gb * 0.5 * (1.0 - th[1] * th[1]));
+    for (int k = 0; k < RK; ++k) {
+      o[2 + k] = (float)(gU[k] * (1.0 - th[2 + k] * th[2 + k]));
+      o[2 + RK + k] = (float)(gV[k] * (1.0 - th[2 + RK + k] * th[2 + RK + k]));
+    }
   }
   // block sum of the loss
   red[tid] = lsum;
@@ -196,6 +221,61 @@ __global__ void k_precond_grad(DevPlan P, const double *__restrict__ Binv, const
     __syncthreads();
   }
   if (tid == 0) atomicAdd(loss, red[0] / x2);
+}
+
+__host__ __device__ inline size_t precond_grad_lds(int bs, int nt) {
+  return ((size_t)5 * bs + 2 * (size_t)bs * RK + 2 * RK + nt) * sizeof(double);
+}
+
+// whole system: x and w of a row through its global trace unknown
+__global__ void k_precond_grad(DevPlan P, const double *__restrict__ Binv, const float *__restrict__ o,
+                               const double *__restrict__ X, const double *__restrict__ Wv, int nvec, double x2,
+                               float *dO, double *loss) {
+  extern __shared__ double sm[];
+  const int blk = blockIdx.x, bs = P.bj_bs, npb = npb_of(P);
+  const size_t NT = (size_t)P.n_trace, NV = (size_t)P.m * NT;
+  int gidx = 0;
+  if ((int)threadIdx.x < bs) {
+    const int c = threadIdx.x / npb, p = threadIdx.x % npb;
+    gidx = (int)(c * NT) + P.bj_nodes[(size_t)blk * npb + p];
+  }
+  const auto xw = [&](int v, int) { return make_double2(X[(size_t)v * NV + gidx], Wv[(size_t)v * NV + gidx]); };
+  precond_grad_block(Binv + (size_t)blk * bs * bs, bs, o + (size_t)blk * bs * NO, nvec, x2, xw,
+                     dO + (size_t)blk * bs * NO, loss, sm);
+}
+
+// pool of sampled blocks: x and w in block-row order, vector v at v * ld
+__global__ void k_pool_grad(int bs, const double *__restrict__ Binv, const float *__restrict__ o,
+                            const double *__restrict__ X, const double *__restrict__ Wv, size_t ld, int nvec,
+                            double x2, float *dO, double *loss) {
+  extern __shared__ double sm[];
+  const size_t blk = blockIdx.x;
+  const auto xw = [&](int v, int i) {
+    const size_t r = (size_t)v * ld + blk * bs + i;
+    return make_double2(X[r], Wv[r]);
+  };
+  precond_grad_block(Binv + blk * bs * bs, bs, o + blk * bs * NO, nvec, x2, xw, dO + blk * bs * NO, loss, sm);
+}
+
+// sampled blocks of a system into a pool (block q of the sample -> pool block b0 + q): the
+// block inverse, the rows' features, and x and w of its rows for every vector
+__global__ void k_pool_extract(DevPlan P, const double *__restrict__ Binv, const float *__restrict__ feat,
+                               const double *__restrict__ X, const double *__restrict__ Wv, int nvec,
+                               const int *__restrict__ sel, size_t b0, size_t ld, double *pB, float *pfeat,
+                               double *pX, double *pW) {
+  const int q = blockIdx.x, blk = sel[q], bs = P.bj_bs, npb = npb_of(P);
+  const size_t NT = (size_t)P.n_trace, NV = (size_t)P.m * NT, dstb = b0 + q;
+  for (int t = threadIdx.x; t < bs * bs; t += blockDim.x)
+    pB[dstb * bs * bs + t] = Binv[(size_t)blk * bs * bs + t];
+  for (int t = threadIdx.x; t < bs * NF; t += blockDim.x)
+    pfeat[dstb * bs * NF + t] = feat[(size_t)blk * bs * NF + t];
+  for (int t = threadIdx.x; t < bs * nvec; t += blockDim.x) {
+    const int i = t % bs, v = t / bs;
+    const int c = i / npb, p = i % npb;
+    const size_t g = c * NT + P.bj_nodes[(size_t)blk * npb + p];
+    pX[(size_t)v * ld + dstb * bs + i] = X[(size_t)v * NV + g];
+    pW[(size_t)v * ld + dstb * bs + i] = Wv[(size_t)v * NV + g];
+  }
 }
 
 // Backward: 64 rows per workgroup; activations and deltas in LDS, then every
@@ -214,11 +294,10 @@ __global__ __launch_bounds__(BR) void k_mlp_bwd(const float *__restrict__ theta,
   float x[NF], h1[NH], h2[NH], o[NO], g[NO];
   if (r < N) {
     for (int i = 0; i < NF; ++i) x[i] = feat[r * NF + i];
-    g[0] = dO[r * 2];
-    g[1] = dO[r * 2 + 1];
+    for (int q = 0; q < NO; ++q) g[q] = dO[r * NO + q];
   } else {
     for (int i = 0; i < NF; ++i) x[i] = 0.f;
-    g[0] = g[1] = 0.f;
+    for (int q = 0; q < NO; ++q) g[q] = 0.f;
   }
   mlp_fwd_row(th, x, h1, h2, o);
   float d2[NH], d1[NH];
@@ -239,8 +318,7 @@ __global__ __launch_bounds__(BR) void k_mlp_bwd(const float *__restrict__ theta,
     sd1[tid][j] = d1[j];
     sd2[tid][j] = d2[j];
   }
-  so[tid][0] = g[0];
-  so[tid][1] = g[1];
+  for (int q = 0; q < NO; ++q) so[tid][q] = g[q];
   __syncthreads();
   float *out = partial + (size_t)blockIdx.x * NPAR;
   for (int p = tid; p < NPAR; p += BR) {
@@ -288,19 +366,36 @@ __global__ void k_adam(float *theta, const float *__restrict__ g, float *m, floa
   theta[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
-__global__ void k_scale_blocks(DevPlan P, double *B, const float *__restrict__ o) {
+// M_F^-1 in place of B_F: entry (i, j) <- e^(a_i) (B_ij + c_i c_j sum_k U_ik V_jk) e^(b_j)
+// (column-major blocks; the diagonal, for c, is read before any entry changes)
+__global__ void k_correct_blocks(DevPlan P, double *B, const float *__restrict__ o) {
+  __shared__ double c[256], ea[256], eb[256], cu[256 * RK], cv[256 * RK];
   const int blk = blockIdx.x, bs = P.bj_bs;
   double *Bb = B + (size_t)blk * bs * bs;
-  const float *ob = o + (size_t)blk * bs * 2;
+  const float *ob = o + (size_t)blk * bs * NO;
+  for (int i = threadIdx.x; i < bs; i += blockDim.x) {
+    c[i] = sqrt(fabs(Bb[(size_t)i * bs + i]));
+    ea[i] = exp(0.5 * tanh((double)ob[i * NO]));
+    eb[i] = exp(0.5 * tanh((double)ob[i * NO + 1]));
+    for (int k = 0; k < RK; ++k) {
+      cu[i * RK + k] = c[i] * tanh((double)ob[i * NO + 2 + k]);
+      cv[i * RK + k] = c[i] * tanh((double)ob[i * NO + 2 + RK + k]);
+    }
+  }
+  __syncthreads();
   for (int t = threadIdx.x; t < bs * bs; t += blockDim.x) {
     const int i = t % bs, j = t / bs;
-    Bb[t] *= exp(0.5 * tanh((double)ob[i * 2]) + 0.5 * tanh((double)ob[j * 2 + 1]));
+    double corr = 0.0;
+    for (int k = 0; k < RK; ++k) corr += cu[i * RK + k] * cv[j * RK + k];
+    Bb[t] = ea[i] * (Bb[t] + corr) * eb[j];
   }
 }
 
 }  // namespace
 
 int learn_nparams() { return NPAR; }
+
+int learn_outputs() { return NO; }
 
 hipError_t launch_feat(const DevPlan &P, const double *Bd, const void *S, int s_f32, const double *vhat,
                        const int *tpos, double *coup, float *feat, hipStream_t s) {
@@ -327,13 +422,31 @@ hipError_t launch_mlp_fwd(const float *theta, const float *feat, size_t N, float
   return hipGetLastError();
 }
 
+static int grad_threads(int bs) { return bs <= 64 ? 64 : (bs <= 128 ? 128 : 256); }
+
 hipError_t launch_precond_grad(const DevPlan &P, const double *Binv, const float *o, const double *X,
                                const double *Wv, int nvec, double x2, float *dO, double *loss, hipStream_t s) {
-  const int bs = P.bj_bs;
-  const int nt = bs <= 64 ? 64 : (bs <= 128 ? 128 : 256);
+  const int bs = P.bj_bs, nt = grad_threads(bs);
   if (bs > 256) return hipErrorInvalidValue;
-  const size_t lds = ((size_t)4 * bs + nt) * sizeof(double);
-  hipLaunchKernelGGL(k_precond_grad, dim3(P.bj_nblk), dim3(nt), lds, s, P, Binv, o, X, Wv, nvec, x2, dO, loss);
+  hipLaunchKernelGGL(k_precond_grad, dim3(P.bj_nblk), dim3(nt), precond_grad_lds(bs, nt), s, P, Binv, o, X, Wv,
+                     nvec, x2, dO, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_grad(int nblk, int bs, const double *Binv, const float *o, const double *X, const double *Wv,
+                            size_t ld, int nvec, double x2, float *dO, double *loss, hipStream_t s) {
+  const int nt = grad_threads(bs);
+  if (bs > 256 || nblk < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pool_grad, dim3(nblk), dim3(nt), precond_grad_lds(bs, nt), s, bs, Binv, o, X, Wv, ld, nvec,
+                     x2, dO, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_extract(const DevPlan &P, const double *Binv, const float *feat, const double *X,
+                               const double *Wv, int nvec, const int *sel, int nsel, size_t b0, size_t ld,
+                               double *pB, float *pfeat, double *pX, double *pW, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_extract, dim3(nsel), dim3(256), 0, s, P, Binv, feat, X, Wv, nvec, sel, b0, ld, pB, pfeat,
+                     pX, pW);
   return hipGetLastError();
 }
 
@@ -397,7 +510,8 @@ hipError_t launch_adam(float *theta, const float *g, float *m, float *v, int t, 
 }
 
 hipError_t launch_scale_blocks(const DevPlan &P, double *B, const float *o, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_blocks, dim3(P.bj_nblk), dim3(256), 0, s, P, B, o);
+  if (P.bj_bs > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_correct_blocks, dim3(P.bj_nblk), dim3(256), 0, s, P, B, o);
   return hipGetLastError();
 }
 

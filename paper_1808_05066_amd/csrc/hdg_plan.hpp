@@ -147,6 +147,12 @@ int check_inputs(const Plan *P, const double *v, const double *q, const double *
 
 // learned block-Jacobi correction (hdg_learn.hip)
 int learn_nparams();
+int learn_outputs();
+hipError_t launch_pool_grad(int nblk, int bs, const double *Binv, const float *o, const double *X, const double *Wv,
+                            size_t ld, int nvec, double x2, float *dO, double *loss, hipStream_t s);
+hipError_t launch_pool_extract(const DevPlan &P, const double *Binv, const float *feat, const double *X,
+                               const double *Wv, int nvec, const int *sel, int nsel, size_t b0, size_t ld,
+                               double *pB, float *pfeat, double *pX, double *pW, hipStream_t s);
 size_t learn_partial_floats(size_t N);
 hipError_t launch_feat(const DevPlan &P, const double *Bd, const void *S, int s_f32, const double *vhat,
                        const int *tpos, double *coup, float *feat, hipStream_t s);

@@ -228,6 +228,60 @@ extern "C" int hdg_trace_solve(hdg_plan *plan, const void *S, const double *rhs,
 
 extern "C" int hdg_learn_nparams(void) { return learn_nparams(); }
 
+extern "C" int hdg_learn_outputs(void) { return learn_outputs(); }
+
+extern "C" int hdg_learn_extract(hdg_plan *plan, const void *work, size_t bytes, const hdg_solve_opts *opts,
+                                 const float *feat, const double *X, const double *Wv, int nvec, const int *sel,
+                                 int nsel, size_t b0, size_t ld, double *pool_B, float *pool_feat, double *pool_X,
+                                 double *pool_W, void *stream) {
+  Plan *P = reinterpret_cast<Plan *>(plan);
+  if (!P || !P->bound || !work || !opts || !feat || !X || !Wv || nvec < 1 || !sel || nsel < 1 || !pool_B ||
+      !pool_feat || !pool_X || !pool_W)
+    return fail(HDG_EINVAL, "bad argument");
+  if ((b0 + (size_t)nsel) * P->dp.bj_bs > ld) return fail(HDG_EINVAL, "pool rows (ld) too small for b0 + nsel blocks");
+  SolveLayout l = solve_layout(P, opts->restart);
+  if (bytes < l.total) return fail(HDG_ENOMEM, "solver workspace too small");
+  const double *B = reinterpret_cast<const double *>(static_cast<const char *>(work) + l.binv);
+  hipError_t e = launch_pool_extract(P->dp, B, feat, X, Wv, nvec, sel, nsel, b0, ld, pool_B, pool_feat, pool_X,
+                                     pool_W, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "learn_extract");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_forward_rows(const float *theta, const float *feat, size_t N, float *out, void *stream) {
+  if (!theta || !feat || !out || N == 0) return fail(HDG_EINVAL, "bad argument");
+  hipError_t e = launch_mlp_fwd(theta, feat, N, out, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "learn_forward_rows");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_rows_scratch_floats(size_t N, size_t *n) {
+  if (!n) return fail(HDG_EINVAL, "bad argument");
+  *n = learn_partial_floats(N);
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_backward_rows(const float *theta, const float *feat, const float *dO, size_t N, float *grad,
+                                       float *scratch, void *stream) {
+  if (!theta || !feat || !dO || !grad || !scratch || N == 0) return fail(HDG_EINVAL, "bad argument");
+  hipError_t e = launch_mlp_bwd(theta, feat, dO, N, scratch, grad, reinterpret_cast<hipStream_t>(stream));
+  if (e) return hip_fail(e, "learn_backward_rows");
+  return HDG_OK;
+}
+
+extern "C" int hdg_learn_pool_loss_grad(int nblk, int bs, const double *pool_B, const float *out, const double *X,
+                                        const double *Wv, size_t ld, int nvec, double x2, float *dO, double *loss,
+                                        void *stream) {
+  if (nblk < 1 || bs < 1 || bs > 256 || !pool_B || !out || !X || !Wv || nvec < 1 || !(x2 > 0.0) || !dO || !loss ||
+      ld < (size_t)nblk * bs)
+    return fail(HDG_EINVAL, "bad argument");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = launch_fill_double(loss, 1, 0.0, s);
+  if (!e) e = launch_pool_grad(nblk, bs, pool_B, out, X, Wv, ld, nvec, x2, dO, loss, s);
+  if (e) return hip_fail(e, "learn_pool_loss_grad");
+  return HDG_OK;
+}
+
 extern "C" int hdg_learn_setup(hdg_plan *plan, const void *S, const double *vhat, float *feat, void *work,
                                size_t bytes, const hdg_solve_opts *opts, void *stream) {
   Plan *P = reinterpret_cast<Plan *>(plan);

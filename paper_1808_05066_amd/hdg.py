@@ -462,11 +462,12 @@ class LearnedPrecond:
         self.plan = solver.plan
         lib = self.plan.lib
         self.nparams = lib.hdg_learn_nparams()
+        self.no = lib.hdg_learn_outputs()
         self.N = self.plan.m * self.plan.n_trace
         dev = self.plan.device
         self.feat = torch.empty(self.N, 16, dtype=torch.float32, device=dev)
-        self.out = torch.zeros(self.N, 2, dtype=torch.float32, device=dev)
-        self.dO = torch.empty(self.N, 2, dtype=torch.float32, device=dev)
+        self.out = torch.zeros(self.N, self.no, dtype=torch.float32, device=dev)
+        self.dO = torch.empty(self.N, self.no, dtype=torch.float32, device=dev)
         self.grad = torch.empty(self.nparams, dtype=torch.float32, device=dev)
         n = ctypes.c_size_t()
         check(lib.hdg_learn_scratch_floats(self.plan.h, ctypes.byref(n)), "hdg_learn_scratch_floats")
@@ -514,6 +515,14 @@ class LearnedPrecond:
                                                        _ptr(grad), _stream()), "hdg_learn_backward_noalloc")
         return grad
 
+    def extract(self, X, Wv, sel, pool, b0):
+        """Blocks sel (device int32) of this system into pool (a LearnPool) from block b0 on."""
+        w, nb, op = self._w()
+        check(self.plan.lib.hdg_learn_extract(self.plan.h, w, nb, op, _ptr(self.feat), _ptr(X), _ptr(Wv), X.shape[0],
+                                              _ptr(sel), int(sel.numel()), int(b0), int(pool.ld), _ptr(pool.B),
+                                              _ptr(pool.feat), _ptr(pool.X), _ptr(pool.W), _stream()),
+              "hdg_learn_extract")
+
     def train_step(self, theta, m, v, t, lr, X, Wv, x2):
         w, nb, op = self._w()
         check(self.plan.lib.hdg_learn_train_step(self.plan.h, _ptr(theta), _ptr(m), _ptr(v), int(t),
@@ -522,6 +531,64 @@ class LearnedPrecond:
                                                  _ptr(self.grad), _ptr(self.scratch), _ptr(self.loss), _stream()),
               "hdg_learn_train_step")
         return self.loss
+
+
+class LearnPool:
+    """Face blocks sampled from many systems for training the learned correction (caller-owned
+    device arrays of the library's pool layout; see hdg_learn_extract in include/hdg.h)."""
+
+    def __init__(self, capacity, bs, nvec, device="cuda"):
+        torch = _torch()
+        lib = _lib.load()
+        self.lib, self.cap, self.bs, self.nvec = lib, int(capacity), int(bs), int(nvec)
+        self.no, self.nparams = lib.hdg_learn_outputs(), lib.hdg_learn_nparams()
+        self.ld = self.cap * self.bs
+        self.n = 0                                    # blocks filled
+        self.B = torch.empty(self.cap, bs, bs, dtype=torch.float64, device=device)
+        self.feat = torch.empty(self.ld, 16, dtype=torch.float32, device=device)
+        self.X = torch.empty(nvec, self.ld, dtype=torch.float64, device=device)
+        self.W = torch.empty(nvec, self.ld, dtype=torch.float64, device=device)
+        self.out = torch.zeros(self.ld, self.no, dtype=torch.float32, device=device)
+        self.dO = torch.empty(self.ld, self.no, dtype=torch.float32, device=device)
+        self.grad = torch.empty(self.nparams, dtype=torch.float32, device=device)
+        n = ctypes.c_size_t()
+        check(lib.hdg_learn_rows_scratch_floats(self.ld, ctypes.byref(n)), "hdg_learn_rows_scratch_floats")
+        self.scratch = torch.empty(int(n.value), dtype=torch.float32, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def add(self, lp, X, Wv, sel):
+        """Append blocks sel of the system behind LearnedPrecond lp (after lp.setup)."""
+        k = int(sel.numel())
+        if self.n + k > self.cap:
+            raise ValueError("pool full")
+        lp.extract(X, Wv, sel, self, self.n)
+        self.n += k
+
+    def _rows(self, b0, nb):
+        return b0 * self.bs, nb * self.bs
+
+    def loss_grad(self, theta, b0, nb):
+        """Forward, loss and dL/do over pool blocks b0 .. b0 + nb - 1; returns the loss tensor."""
+        r0, nr = self._rows(b0, nb)
+        feat, out, dO = self.feat[r0:r0 + nr], self.out[r0:r0 + nr], self.dO[r0:r0 + nr]
+        X, W = self.X[:, r0:], self.W[:, r0:]
+        x2 = float((self.X[:, r0:r0 + nr] ** 2).sum())
+        check(self.lib.hdg_learn_forward_rows(_ptr(theta), _ptr(feat), nr, _ptr(out), _stream()),
+              "hdg_learn_forward_rows")
+        check(self.lib.hdg_learn_pool_loss_grad(nb, self.bs, _ptr(self.B[b0]), _ptr(out), _ptr(X), _ptr(W),
+                                                self.ld, self.nvec, x2, _ptr(dO), _ptr(self.loss), _stream()),
+              "hdg_learn_pool_loss_grad")
+        return self.loss
+
+    def train_step(self, theta, m, v, t, lr, b0, nb):
+        """One Adam step on pool blocks b0 .. b0 + nb - 1; returns the loss before the step."""
+        loss = self.loss_grad(theta, b0, nb).clone()
+        r0, nr = self._rows(b0, nb)
+        check(self.lib.hdg_learn_backward_rows(_ptr(theta), _ptr(self.feat[r0:r0 + nr]), _ptr(self.dO[r0:r0 + nr]),
+                                               nr, _ptr(self.grad), _ptr(self.scratch), _stream()),
+              "hdg_learn_backward_rows")
+        adam(theta, self.grad, m, v, t, lr)
+        return loss
 
 
 def adam(theta, grad, m, v, t, lr):

@@ -5,9 +5,13 @@
 * Adam step against the NumPy step on the same FP32-rounded inputs: <= 2e-5
   relative (beta2 = 0.999 is not exact in FP32: 1 - beta2 carries a 1.3e-5
   relative representation error into the second moment);
-* loss and dL/do with the GPU block inverses against the oracle's inverses of
-  the oracle's assembled operator on identical vectors: <= 1e-9 relative
-  (the inverses agree to cond * 1e-12);
+* loss and dL/do (row and column rescaling and rank-R term) with the GPU block
+  inverses against the oracle's inverses of the oracle's assembled operator on
+  identical vectors: <= 1e-9 relative (the inverses agree to cond * 1e-12);
+* the pool of sampled blocks: extracting every block of a system gives the
+  same loss and dL/do as the whole-system kernel; the corrected blocks that
+  hdg_learn_apply forms act as the oracle's corrected blocks of the extracted
+  inverses;
 * features: the block-statistics columns against the oracle operator;
 * a short training run lowers the proxy loss below its block-Jacobi start, the
   learned GMRES solve reaches the true 1e-10 residual, and the comparison with
@@ -64,7 +68,7 @@ def test_forward_backward_match_numpy(torch, case):
     o = lp.forward(th).cpu().numpy()
     o_ref, cache = omlp.forward(theta.astype(np.float64), feat.astype(np.float64))
     assert _rel(o, o_ref) <= 1e-5
-    dO = rng.normal(size=(lp.N, 2)).astype(np.float32)
+    dO = rng.normal(size=(lp.N, omlp.NO)).astype(np.float32)
     g = lp.backward(th, torch.from_numpy(dO).cuda()).cpu().numpy()
     g_ref = omlp.backward(theta.astype(np.float64), cache, dO.astype(np.float64))
     assert _rel(g, g_ref) <= 1e-5
@@ -96,7 +100,7 @@ def test_loss_gradient_matches_numpy(torch, case):
     nvec = 3
     X = rng.normal(size=(nvec, K.shape[0]))
     Wv = np.stack([K @ X[v] for v in range(nvec)])
-    o = rng.normal(scale=0.5, size=(len(order), 2)).astype(np.float32)
+    o = rng.normal(scale=0.5, size=(len(order), omlp.NO)).astype(np.float32)
     L_ref, dO_ref = omlp.precond_loss(Binv, o.astype(np.float64), X[:, order], Wv[:, order])
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     loss, dO = lp.loss_grad(dev(X.reshape(nvec, disc.m, -1)), dev(Wv.reshape(nvec, disc.m, -1)), out=dev(o))
@@ -104,6 +108,56 @@ def test_loss_gradient_matches_numpy(torch, case):
     print("loss", loss, L_ref, "cond", cond)
     assert abs(loss - L_ref) <= max(1e-9, 1e-12 * cond) * abs(L_ref)
     assert _rel(dO, dO_ref) <= max(1e-6, 1e-12 * cond)
+
+
+def test_pool_matches_whole_system_and_correction_matches_oracle(torch, case):
+    from paper_1808_05066_amd.hdg import LearnPool
+    disc, lp, plan, ts = case["disc"], case["lp"], case["plan"], case["ts"]
+    bs = plan.m * plan.dims["Nfp"]
+    nblk = lp.N // bs
+    rng = np.random.default_rng(24)
+    nvec = 2
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    X = dev(rng.normal(size=(nvec, plan.m, plan.n_trace)))
+    Wv = torch.stack([plan.trace_matvec(case["out"]["S"], X[v]) for v in range(nvec)])
+    o = dev(rng.normal(scale=0.5, size=(lp.N, omlp.NO)).astype(np.float32))
+    loss_w, dO_w = lp.loss_grad(X, Wv, out=o)
+    loss_w, dO_w = float(loss_w), dO_w.cpu().numpy().copy()
+    # every block into a pool, in two parts, in reverse block order
+    pool = LearnPool(nblk, bs, nvec)
+    perm = np.arange(nblk)[::-1].copy()
+    half = nblk // 2
+    pool.add(lp, X, Wv, dev(perm[:half].astype(np.int32)))
+    pool.add(lp, X, Wv, dev(perm[half:].astype(np.int32)))
+    assert pool.n == nblk
+    rows = (perm[:, None] * bs + np.arange(bs)[None, :]).reshape(-1)   # pool row -> system block row
+    pool.out.copy_(o[dev(rows)])
+    x2 = float((X * X).sum())
+    from paper_1808_05066_amd.hdg import _ptr, _stream
+    from paper_1808_05066_amd._lib import check
+    check(pool.lib.hdg_learn_pool_loss_grad(nblk, bs, _ptr(pool.B), _ptr(pool.out), _ptr(pool.X), _ptr(pool.W),
+                                            pool.ld, nvec, x2, _ptr(pool.dO), _ptr(pool.loss), _stream()), "pool")
+    torch.cuda.synchronize()
+    assert abs(float(pool.loss) - loss_w) <= 1e-12 * abs(loss_w)
+    assert _rel(pool.dO.cpu().numpy(), dO_w[rows]) <= 1e-6
+    # the corrected blocks of hdg_learn_apply against the oracle's on the extracted inverses:
+    # a pool of the index vector maps every block row to its global unknown
+    Bsys = np.empty_like(pool.B.cpu().numpy())
+    Bsys[perm] = pool.B.cpu().numpy()                        # pool block q = system block perm[q]
+    idx = dev(np.arange(plan.m * plan.n_trace, dtype=np.float64).reshape(1, plan.m, plan.n_trace))
+    imap = LearnPool(nblk, bs, 1)
+    imap.add(lp, idx, idx, dev(np.arange(nblk, dtype=np.int32)))
+    gidx = imap.X.cpu().numpy()[0].astype(np.int64)          # block row r -> global unknown
+    lp.apply(dev(rng.normal(scale=0.3, size=omlp.N_PARAMS).astype(np.float32)))
+    out_sys = lp.out.cpu().numpy().astype(np.float64)
+    w_sys = rng.normal(size=(plan.m, plan.n_trace))
+    z = ts.apply(dev(w_sys)).cpu().numpy().reshape(-1)
+    # stored blocks are column-major: pool block [j][i] is entry (i, j)
+    zr = omlp.apply_scaled(Bsys.transpose(0, 2, 1), out_sys, w_sys.reshape(-1)[gidx])
+    print("corrected apply vs oracle", _rel(z[gidx], zr))
+    assert _rel(z[gidx], zr) <= 1e-12
+    # restore the plain inverses and features for the other tests
+    lp.setup(case["out"]["S"], case["d"]["vhat"])
 
 
 def test_features_match_oracle_block_statistics(torch, case):
