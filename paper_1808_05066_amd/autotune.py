@@ -2,8 +2,13 @@
 
 For a plan it times hdg_assemble_condense (FP64) or hdg_assemble_condense_lp
 (FP32) with every admissible combination of
-  contract_threads in (256, 512, 1024)   block-contraction workgroup size
-  condense_width   in (16, 32)           condensation column-block width
+  contract_threads  in (256, 512, 1024)  block-contraction workgroup size
+  condense_width    in (16, 32)          condensation column-block width
+  condense_launches in (1, 2)            one workgroup per element, or the LU and then
+                                         one workgroup per right-hand-side block (32 only)
+  lu_waves          in (1, 4, 8)         FP64 two-launch LU: working block in LDS (one
+                                         element per CU) or in the registers of 4 waves
+                                         (two elements per CU) or 8 waves
 (median of HIP-event timings after a warm-up), keeps the fastest, and stores
 it in a JSON cache; apply() sets a cached choice on a new plan.  Batches are
 tuned over the queue order (largest first or plan order) and the persistent
@@ -46,20 +51,38 @@ def _time(fn, reps):
     return float(np.median(ts))
 
 
-def candidates(plan, dtype):
+def _admissible(plan, **kw):
     base = plan.tuning()
-    widths = []
+    try:
+        plan.set_tuning(**kw)
+        return True
+    except H._lib.HdgError:
+        return False
+    finally:
+        plan.set_tuning(**base)
+
+
+def candidates(plan, dtype):
+    """Admissible (contract_threads, width, launches, lu_waves) tuples; lu_waves 1 = LDS block."""
+    shapes = []
     for w in (32, 16):
-        try:
-            if dtype == "fp64":
-                plan.set_tuning(condense_width=w)
-            else:
-                plan.set_tuning(condense_width_lp=w)
-            widths.append(w)
-        except H._lib.HdgError:
-            pass
-    plan.set_tuning(**base)
-    return [(ct, w) for ct in (256, 512, 1024) for w in widths]
+        if dtype == "fp64":
+            if not _admissible(plan, condense_width=w):
+                continue
+            shapes.append((w, 1, 1))
+            if w == 32:
+                shapes += [(32, 2, lw) for lw in (1, 4, 8)
+                           if _admissible(plan, condense_width=32, condense_launches=2, lu_waves=lw)]
+        elif _admissible(plan, condense_width_lp=w):
+            shapes += [(w, nl, 1) for nl in (1, 2)]
+    return [(ct, w, nl, lw) for ct in (256, 512, 1024) for (w, nl, lw) in shapes]
+
+
+def _set(plan, dtype, ct, w, nl, lw):
+    if dtype == "fp64":
+        plan.set_tuning(contract_threads=ct, condense_width=w, condense_launches=nl, lu_waves=lw)
+    else:
+        plan.set_tuning(contract_threads=ct, condense_width_lp=w, condense_launches=nl)
 
 
 def tune_plan(plan, inputs, dtype="fp64", reps=3, cache=DEFAULT_CACHE, log=print):
@@ -69,19 +92,15 @@ def tune_plan(plan, inputs, dtype="fp64", reps=3, cache=DEFAULT_CACHE, log=print
     run = (lambda: plan.assemble_condense(*args, out=out)) if dtype == "fp64" else \
         (lambda: plan.assemble_condense_lp(*args, out=out))
     results = []
-    for ct, w in candidates(plan, dtype):
-        if dtype == "fp64":
-            plan.set_tuning(contract_threads=ct, condense_width=w)
-        else:
-            plan.set_tuning(contract_threads=ct, condense_width_lp=w)
+    for ct, w, nl, lw in candidates(plan, dtype):
+        _set(plan, dtype, ct, w, nl, lw)
         ms = _time(run, reps)
-        results.append({"contract_threads": ct, "condense_width": w, "ms": ms})
-        log("[autotune] %s ct=%d w=%d: %.2f ms" % (key(plan, dtype), ct, w, ms))
+        results.append({"contract_threads": ct, "condense_width": w, "condense_launches": nl, "lu_waves": lw,
+                        "ms": ms})
+        log("[autotune] %s ct=%d w=%d launches=%d lu_waves=%d: %.2f ms" % (key(plan, dtype), ct, w, nl, lw, ms))
     best = min(results, key=lambda r: r["ms"])
-    if dtype == "fp64":
-        plan.set_tuning(contract_threads=best["contract_threads"], condense_width=best["condense_width"])
-    else:
-        plan.set_tuning(contract_threads=best["contract_threads"], condense_width_lp=best["condense_width"])
+    _set(plan, dtype, best["contract_threads"], best["condense_width"], best.get("condense_launches", 1),
+         best.get("lu_waves", 1))
     entry = {"best": best, "all": results, "elements": plan.n_elem}
     if cache:
         store(cache, key(plan, dtype), entry)
@@ -125,10 +144,15 @@ def apply(plan, dtype="fp64", cache=DEFAULT_CACHE):
         return None
     b = e["best"]
     try:
+        # entries written before the launch count and LU variant were swept carry neither:
+        # they leave the plan's defaults
+        nl, lw = b.get("condense_launches", 0), b.get("lu_waves", 0)
         if dtype == "fp64":
-            plan.set_tuning(contract_threads=b["contract_threads"], condense_width=b["condense_width"])
+            plan.set_tuning(contract_threads=b["contract_threads"], condense_width=b["condense_width"],
+                            condense_launches=nl, lu_waves=lw)
         else:
-            plan.set_tuning(contract_threads=b["contract_threads"], condense_width_lp=b["condense_width"])
+            plan.set_tuning(contract_threads=b["contract_threads"], condense_width_lp=b["condense_width"],
+                            condense_launches=nl)
     except H._lib.HdgError:
         return None
     return b
