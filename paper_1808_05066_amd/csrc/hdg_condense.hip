@@ -67,8 +67,7 @@ struct Lds {
   T *blk;        // [np][BS]
   T *crow;       // [2][NW + 1][8] pivot candidate rows and diagonal row, by column parity
   int *perm;     // [np]
-  T *redv;       // [2][NW]
-  int *redi;     // [2][NW]
+  int *redi;     // [2][NW] pivot keys of the waves
   double *dsc;   // [np] symmetric scaling (low-precision path only)
   int *invb;     // [np] original row -> position before the current panel
   int *mvx;      // [2W] positions changed by the panel's interchanges
@@ -283,17 +282,6 @@ template <int CTRL>
 __device__ inline int dpp_i32(int v) {
   return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
 }
-template <int CTRL>
-__device__ inline double dpp_val(double v) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)dpp_i32<CTRL>((int)(unsigned)u);
-  const unsigned hi = (unsigned)dpp_i32<CTRL>((int)(unsigned)(u >> 32));
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-template <int CTRL>
-__device__ inline float dpp_val(float v) {
-  return __builtin_bit_cast(float, dpp_i32<CTRL>(__builtin_bit_cast(int, v)));
-}
 __device__ inline double lane_val(double v, int l) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
@@ -305,21 +293,37 @@ __device__ inline float lane_val(float v, int l) {
 }
 constexpr int DPP_QUAD_1032 = 0xB1, DPP_QUAD_2301 = 0x4E, DPP_ROW_ROR4 = 0x124, DPP_ROW_ROR8 = 0x128;
 
-template <typename T>
-__device__ inline T wave_max(T v) {
-  v = fmax(v, dpp_val<DPP_QUAD_1032>(v));
-  v = fmax(v, dpp_val<DPP_QUAD_2301>(v));
-  v = fmax(v, dpp_val<DPP_ROW_ROR4>(v));
-  v = fmax(v, dpp_val<DPP_ROW_ROR8>(v));
-  return fmax(fmax(lane_val(v, 0), lane_val(v, 16)), fmax(lane_val(v, 32), lane_val(v, 48)));
+__device__ inline unsigned wave_max_u32(unsigned v) {
+  v = max(v, (unsigned)dpp_i32<DPP_QUAD_1032>((int)v));
+  v = max(v, (unsigned)dpp_i32<DPP_QUAD_2301>((int)v));
+  v = max(v, (unsigned)dpp_i32<DPP_ROW_ROR4>((int)v));
+  v = max(v, (unsigned)dpp_i32<DPP_ROW_ROR8>((int)v));
+  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return max(max(a, b), max(c, d));
 }
-__device__ inline int wave_min(int v) {
-  v = min(v, dpp_i32<DPP_QUAD_1032>(v));
-  v = min(v, dpp_i32<DPP_QUAD_2301>(v));
-  v = min(v, dpp_i32<DPP_ROW_ROR4>(v));
-  v = min(v, dpp_i32<DPP_ROW_ROR8>(v));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+
+// Pivot key of row `row` (< 2048) in the LDS kernels: the magnitude's exponent and leading
+// mantissa bits (10 of FP64, 13 of FP32), then the lower row; exact partial pivoting up to a
+// relative 2^-10 (FP64) / 2^-13 (FP32) between near-equal candidates.  One wave maximum and one
+// maximum over the waves' winners replace a maximum of the value and a minimum of the row.
+__device__ inline unsigned mag_key(double a, int row) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, fabs(a));
+  return ((unsigned)(b >> 42) << 11) | (unsigned)(2047 - row);
+}
+__device__ inline unsigned mag_key(float a, int row) {
+  const unsigned b = __builtin_bit_cast(unsigned, fabsf(a));
+  return ((b >> 10) << 11) | (unsigned)(2047 - row);
+}
+// 1 / x from the hardware estimate and Newton steps (two in FP64, one in FP32)
+__device__ inline double rcp_newton(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline float rcp_newton(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
 // Inverses of the diagonal W x W blocks of the freshly factored panel (block rows
@@ -460,17 +464,17 @@ __device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int 
 // LU with partial pivoting of block rows j0..np-1 (block columns 0..W-1), in
 // sub-panels of 8 columns.  Inside a sub-panel thread t keeps the 8 entries of
 // row j0+t in registers (its rows j0+t+NT, j0+t+2NT, ... stay in LDS).  One
-// barrier per column: each wave reduces its pivot candidates (largest magnitude,
-// lowest row among equal ones) on the DPP network and publishes the winner's
-// value, row index and 8 sub-panel entries, next to the entries of the diagonal
-// row; after the barrier every wave reduces the NW winners the same way and
-// applies the interchange and the rank-1 update to its own rows (the interchanges
-// of the columns outside the sub-panel and of perm wait for the sub-panel's
-// end, where they are applied as one row movement).  The publication slots are
-// double-buffered by column parity, so the next column's writes cannot overtake
-// this column's reads.  After a sub-panel, its 8 pivot rows are solved against
-// the remaining columns (unit-lower 8 x 8) and the rows below receive the
-// rank-8 update.
+// barrier per column: each wave takes the maximum of its candidates' pivot keys
+// (magnitude, then the lowest row; mag_key) on the DPP network and the winning
+// lane publishes the key with its row's 8 sub-panel entries, next to the entries
+// of the diagonal row; after the barrier every wave takes the largest of the NW
+// keys and applies the interchange and the rank-1 update to its own rows (the
+// interchanges of the columns outside the sub-panel and of perm wait for the
+// sub-panel's end, where they are applied as one row movement).  The publication
+// slots are double-buffered by column parity, so the next column's writes cannot
+// overtake this column's reads.  After a sub-panel, its 8 pivot rows are solved
+// against the remaining columns (unit-lower 8 x 8) and the rows below receive
+// the rank-8 update.
 constexpr int SPW = 8;   // sub-panel width
 
 template <typename T, int W>
@@ -492,23 +496,16 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np) {
       const int r = j0 + col;   // diagonal row, always thread col's register row
       const int b = jj & 1;
       T *crow = s.crow + b * (NW + 1) * SPW;   // [NW candidate rows | diagonal row][SPW]
-      // this thread's candidate
-      T best = T(-1);
-      int bi = np;
-      if (has0 && r0 >= r) {
-        best = fabs(x0[jj]);
-        bi = r0;
-      }
+      // this thread's candidate key (0: none)
+      unsigned best = 0;
+      if (has0 && r0 >= r) best = mag_key(x0[jj], r0);
       for (int rr = r1; rr < np; rr += NT) {
-        const T v1 = fabs(s.blk[(size_t)rr * BS + col]);
-        if (v1 > best) {
-          best = v1;
-          bi = rr;
-        }
+        const unsigned k1 = mag_key(s.blk[(size_t)rr * BS + col], rr);
+        if (k1 > best) best = k1;
       }
-      const T wm = wave_max(best);
-      const int wi = wave_min(best == wm ? bi : INT_MAX);
-      if (best >= T(0) && best == wm && bi == wi) {
+      const unsigned wb = wave_max_u32(best);
+      if (best != 0 && best == wb) {   // one lane: keys differ by row
+        const int bi = 2047 - (int)(best & 2047u);
         T v[SPW];
 #pragma unroll
         for (int c = 0; c < SPW; ++c) v[c] = (bi == r0) ? x0[c] : s.blk[(size_t)bi * BS + cs + c];
@@ -516,31 +513,24 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np) {
 #pragma unroll
         for (int c = 0; c < SPW; ++c) dst[c] = v[c];
       }
-      if (lane == 0) {
-        s.redv[b * NW + wave] = wm;
-        s.redi[b * NW + wave] = wi;
-      }
+      if (lane == 0) s.redi[b * NW + wave] = (int)wb;
       if (tid == col) {
 #pragma unroll
         for (int c = 0; c < SPW; ++c) crow[NW * SPW + c] = x0[c];
       }
       __syncthreads();
-      // global pivot over the waves' winners (lanes 0..NW-1 of every wave),
-      // largest magnitude, lowest row among equal ones
-      T cv = T(-1);
-      int ci = INT_MAX;
-      if (lane < NW) {
-        cv = s.redv[b * NW + lane];
-        ci = s.redi[b * NW + lane];
+      // global pivot: the largest of the waves' keys
+      unsigned kb = 0;
+      int wv = 0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) {
+        const unsigned kv = (unsigned)s.redi[b * NW + v];
+        if (kv > kb) {
+          kb = kv;
+          wv = v;
+        }
       }
-      const T pv = wave_max(cv);
-      const int pi = wave_min(cv == pv ? ci : INT_MAX);
-      const unsigned long long hit = __ballot(lane < NW && cv == pv && ci == pi);
-      const bool zero = !(pv > T(0)) || hit == 0 || pi < r || pi >= np;   // (only the first can fire)
-      singular |= zero;
-      const int piv = zero ? r : pi;
-      pivs[jj] = piv;
-      const T *pr = crow + (zero ? NW : (int)__builtin_ctzll(hit)) * SPW;
+      const T *pr = crow + wv * SPW;
       const T *dr = crow + NW * SPW;
       T prow[SPW], drow[SPW];
 #pragma unroll
@@ -548,6 +538,10 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np) {
         prow[c] = pr[c];
         drow[c] = dr[c];
       }
+      const bool zero = kb == 0 || !(fabs(prow[jj]) > T(0));
+      singular |= zero;
+      const int piv = zero ? r : 2047 - (int)(kb & 2047u);
+      pivs[jj] = piv;
       if (piv != r) {
         if (has0 && r0 == piv) {
 #pragma unroll
@@ -562,7 +556,7 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np) {
         }
       }
       if (!zero) {
-        const T inv = T(1) / prow[jj];
+        const T inv = rcp_newton(prow[jj]);
         if (has0 && r0 > r) {
           const T l0 = x0[jj] * inv;
           x0[jj] = l0;
@@ -694,7 +688,7 @@ __device__ inline void move_rows_waves(const int *mvx, const int *mvy, int m, T 
 
 // LDS carve-up of k_condense_t (byte offsets, 16-byte aligned parts).
 struct LdsLayout {
-  size_t blk, crow, perm, redv, redi, dsc, invb, mv, total;
+  size_t blk, crow, perm, redi, dsc, invb, mv, total;
 };
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -708,8 +702,6 @@ __host__ __device__ inline LdsLayout lds_layout(int np, size_t tsize, bool lp, i
   o = al16(o + 2 * (NW + 1) * 8 * tsize);
   L.perm = o;
   o = al16(o + (size_t)np * sizeof(int));
-  L.redv = o;
-  o = al16(o + 2 * NW * tsize);
   L.redi = o;
   o = al16(o + 2 * NW * sizeof(int));
   L.dsc = o;
@@ -738,7 +730,6 @@ __device__ __forceinline__ Lds<T> carve_lds(int np) {
   s.blk = reinterpret_cast<T *>(sm + Lo.blk);
   s.crow = reinterpret_cast<T *>(sm + Lo.crow);
   s.perm = reinterpret_cast<int *>(sm + Lo.perm);
-  s.redv = reinterpret_cast<T *>(sm + Lo.redv);
   s.redi = reinterpret_cast<int *>(sm + Lo.redi);
   s.dsc = LP ? reinterpret_cast<double *>(sm + Lo.dsc) : nullptr;
   s.invb = reinterpret_cast<int *>(sm + Lo.invb);
@@ -1212,15 +1203,6 @@ typedef unsigned long long u64;
 __device__ inline unsigned pivot_key32(double x, int i) {
   const u64 b = __builtin_bit_cast(u64, fabs(x));
   return ((unsigned)(b >> 41) << 10) | (unsigned)(1023 - i);
-}
-__device__ inline unsigned wave_max_u32(unsigned v) {
-  v = max(v, (unsigned)dpp_i32<DPP_QUAD_1032>((int)v));
-  v = max(v, (unsigned)dpp_i32<DPP_QUAD_2301>((int)v));
-  v = max(v, (unsigned)dpp_i32<DPP_ROW_ROR4>((int)v));
-  v = max(v, (unsigned)dpp_i32<DPP_ROW_ROR8>((int)v));
-  const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0), b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
-  const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32), d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
-  return max(max(a, b), max(c, d));
 }
 
 constexpr int RG_SS = 9;     // LDS row stride of the 8-column sub-panel
