@@ -288,8 +288,8 @@ int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
  * of launches: 1 (one workgroup per element factors A and works through every
  * right-hand-side block) or 2 (default: one workgroup per element for the LU,
  * then one per element and right-hand-side block, the workgroups of an
- * element on one XCD so that they share its factors in L2; FP64 with 32-column
- * blocks and FP32; the results are the same bit for bit).  The autotuner
+ * element on one XCD so that they share its factors in L2; the results are
+ * the same bit for bit).  The autotuner
  * (paper_1808_05066_amd/autotune.py) sweeps these per (n, k, dtype) and caches
  * the fastest in JSON.  Set before building a batch (batches run their own
  * two persistent launches with the LDS-block LU).

@@ -5,8 +5,8 @@ For a plan it times hdg_assemble_condense (FP64) or hdg_assemble_condense_lp
   contract_threads  in (256, 512, 1024)  block-contraction workgroup size
   condense_width    in (16, 32)          condensation column-block width
   condense_launches in (1, 2)            one workgroup per element, or the LU and then
-                                         one workgroup per right-hand-side block (32 only)
-  lu_waves          in (1, 4, 8)         FP64 two-launch LU: working block in LDS (one
+                                         one workgroup per right-hand-side block
+  lu_waves          in (1, 4, 8)         FP64 two-launch LU with 32-column blocks: in LDS (one
                                          element per CU) or in the registers of 4 waves
                                          (two elements per CU) or 8 waves
 (median of HIP-event timings after a warm-up), keeps the fastest, and stores
@@ -69,9 +69,9 @@ def candidates(plan, dtype):
         if dtype == "fp64":
             if not _admissible(plan, condense_width=w):
                 continue
-            shapes.append((w, 1, 1))
+            shapes += [(w, 1, 1), (w, 2, 1)]
             if w == 32:
-                shapes += [(32, 2, lw) for lw in (1, 4, 8)
+                shapes += [(32, 2, lw) for lw in (4, 8)
                            if _admissible(plan, condense_width=32, condense_launches=2, lu_waves=lw)]
         elif _admissible(plan, condense_width_lp=w):
             shapes += [(w, nl, 1) for nl in (1, 2)]

@@ -989,6 +989,19 @@ __global__ __launch_bounds__(NT_RHS) void k_rhs_f64_w32(DevPlan P, int e0, int e
   rhs_body<double, false, 32, NT_RHS>(P, e0, ec, S, g, Y, z, inv, nullptr);
 }
 
+// 16-column blocks (a 32-column block of n_pad > 704 rows does not fit in LDS): the LU, then one
+// workgroup per (element, 16-column block), the blocks of an element on one XCD
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_lu_f64_w16(DevPlan P, int e0,
+                                                                                            int32_t *status,
+                                                                                            double *inv) {
+  lu_body<double, false, 16>(P, e0, blockIdx.x, status, inv, nullptr);
+}
+
+__global__ __launch_bounds__(NT_RHS) void k_rhs_f64_w16(DevPlan P, int e0, int ec, double *S, double *g, double *Y,
+                                                        double *z, double *inv) {
+  rhs_body<double, false, 16, NT_RHS>(P, e0, ec, S, g, Y, z, inv, nullptr);
+}
+
 template <int W>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_lu_f32(DevPlan P, int e0,
                                                                                         int32_t *status,
@@ -1697,7 +1710,7 @@ hipError_t launch_dyn(K kern, int ec, size_t lds, hipStream_t s, Args... args) {
 // grid of the right-hand-side launch: element slots rounded up to the XCD count, times the blocks
 static int rhs_grid(const DevPlan &P, int ec, int W) { return (ec + NXCD - 1) / NXCD * NXCD * (P.kx / W); }
 
-bool condense_two_launches(const DevPlan &P) { return P.cw == 32 && P.condense_launches == 2; }
+bool condense_two_launches(const DevPlan &P) { return (P.cw == 32 || P.cw == 16) && P.condense_launches == 2; }
 
 size_t lu_reg_lds_bytes(int np, int nwv) { return reg_layout(np, nwv).total; }
 
@@ -1727,13 +1740,18 @@ hipError_t launch_condense_lu_reg(const DevPlan &P, int ec, int32_t *status, hip
   return hipErrorInvalidValue;
 }
 
+// (the register-resident LU stores 32 x 32 diagonal-block inverses: 32-column plans only)
 hipError_t launch_condense_lu(const DevPlan &P, int e0, int ec, int32_t *status, hipStream_t s) {
+  if (P.cw == 16) return launch_dyn(k_lu_f64_w16, ec, condense_lds_bytes(P.n_pad, 16), s, P, e0, status, P.inv);
   if (P.lu_waves) return launch_condense_lu_reg(P, ec, status, s);
   return launch_dyn(k_lu_f64_w32, ec, condense_lds_bytes(P.n_pad, 32), s, P, e0, status, P.inv);
 }
 
 hipError_t launch_condense_rhs(const DevPlan &P, int e0, int ec, double *S, double *g, double *Y, double *z,
                                hipStream_t s) {
+  if (P.cw == 16)
+    return launch_dyn_t(k_rhs_f64_w16, rhs_grid(P, ec, 16), NT_RHS, condense_lds_bytes(P.n_pad, 16), s, P, e0, ec, S,
+                        g, Y, z, P.inv);
   return launch_dyn_t(k_rhs_f64_w32, rhs_grid(P, ec, 32), NT_RHS, condense_lds_bytes(P.n_pad, 32), s, P, e0, ec, S,
                       g, Y, z, P.inv);
 }

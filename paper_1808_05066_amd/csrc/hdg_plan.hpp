@@ -214,7 +214,7 @@ bool contract_mfma_supported(const DevPlan &P);
 hipError_t launch_contract_mfma(const DevPlan &P, int e0, int ec, hipStream_t s);
 hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, double *S, double *g, double *Y,
                            double *z, hipStream_t s);
-// FP64 condensation in two launches (32-column blocks, condense_launches == 2): the LU, then the right-hand sides
+// FP64 condensation in two launches (condense_launches == 2): the LU, then the right-hand sides
 bool condense_two_launches(const DevPlan &P);
 hipError_t launch_condense_lu(const DevPlan &P, int e0, int ec, int32_t *status, hipStream_t s);
 bool lu_reg_supported(int np, int nwv);
