@@ -292,7 +292,7 @@ int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
  * the same bit for bit).  The autotuner
  * (paper_1808_05066_amd/autotune.py) sweeps these per (n, k, dtype) and caches
  * the fastest in JSON.  Set before building a batch (batches run their own
- * two persistent launches with the LDS-block LU).
+ * two launches with the LDS-block LU).
  * lu_waves selects the LU of the two-launch FP64 condensation: 1 keeps its
  * 32-column working block in LDS (one workgroup per CU), 4 or 8 keep it in
  * the registers of that many waves (LDS for staging only: with 4 waves two
@@ -314,13 +314,15 @@ int hdg_plan_get_tuning(const hdg_plan *plan, hdg_tuning *t);
 
 /* ---- Batches ----------------------------------------------------------------
  * Several plans (element types / orders with uneven n, k, e.g. tetrahedra of
- * orders 1..4 next to hexahedra) condensed by two persistent launches: each
- * workgroup of the first takes LU items (plan, element) from a queue in
- * decreasing order of block cost (order 0, longest processing time first) or
- * plan order (order 1) until it is empty; each workgroup of the second takes
- * right-hand-side items (plan, element, column block) from the queue of the
- * XCD it runs on (an element's items lie together in one XCD's queue, so its
- * workgroups share the factors in that XCD's L2).  Outputs equal the per-plan
+ * orders 1..4 next to hexahedra) condensed by two launches over item lists:
+ * LU items (plan, element) in decreasing order of block cost (order 0, longest
+ * processing time first) or plan order (order 1), then right-hand-side items
+ * (plan, element, column block) in eight lists, one per XCD (an element's
+ * items lie together in one XCD's list, so its workgroups share the factors
+ * in that XCD's L2).  By default each item gets a workgroup of its own, in
+ * list order (the hardware starts them in index order as CUs free up);
+ * hdg_batch_set_groups selects a persistent grid instead, whose workgroups
+ * take items from atomic counters until the lists are empty.  Outputs equal the per-plan
  * two-launch condensation with the LDS-block LU bit for bit.  Every plan must
  * be bound, use the fused condensation and process all its elements in one
  * chunk; its pointwise and contraction kernels run first, per plan.  The
@@ -339,14 +341,15 @@ void hdg_batch_destroy(hdg_batch *batch);
 /* Caller-owned device workspace (descriptors, queues, counters). */
 int hdg_batch_workspace_bytes(const hdg_batch *batch, size_t *bytes);
 int hdg_batch_bind_workspace(hdg_batch *batch, void *dev_ptr, size_t bytes, void *stream);
-/* Persistent grid size of the LU launch (default: number of compute units);
- * the right-hand-side launch takes it rounded up to a multiple of 8. */
+/* 0 (default): one workgroup per item.  groups > 0: persistent grids, the LU
+ * launch with `groups` workgroups (at most one per item), the right-hand-side
+ * launch with `groups` rounded up to a multiple of 8.  HDG_EINVAL if < 0. */
 int hdg_batch_set_groups(hdg_batch *batch, int groups);
 /* Inputs / outputs of every plan (array of n_plans); synchronous upload. */
 int hdg_batch_set_io(hdg_batch *batch, const hdg_batch_io *io, void *stream);
 /* Run once: per plan status reset + pointwise + contraction, then the two
- * persistent launches of the condensation.  n_items of hdg_batch_info counts
- * the LU items (one per element). */
+ * launches of the condensation.  n_items of hdg_batch_info counts the LU
+ * items (one per element); its groups is the value of hdg_batch_set_groups. */
 int hdg_batch_run(hdg_batch *batch, void *stream);
 /* Capture the sequence of hdg_batch_run in a graph (after one eager run on the
  * same stream); hdg_batch_replay launches it.  Phase timing must be off. */

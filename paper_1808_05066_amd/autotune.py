@@ -11,8 +11,8 @@ For a plan it times hdg_assemble_condense (FP64) or hdg_assemble_condense_lp
                                          (two elements per CU) or 8 waves
 (median of HIP-event timings after a warm-up), keeps the fastest, and stores
 it in a JSON cache; apply() sets a cached choice on a new plan.  Batches are
-tuned over the queue order (largest first or plan order) and the persistent
-grid size.
+tuned over their grid: one workgroup per item, or a persistent grid of one or
+two workgroups per CU.
 """
 from __future__ import annotations
 
@@ -108,11 +108,12 @@ def tune_plan(plan, inputs, dtype="fp64", reps=3, cache=DEFAULT_CACHE, log=print
 
 
 def tune_batch(batch, reps=3, log=print):
-    """Queue order and persistent grid size of a batch whose io is set (returns the timings)."""
+    """Grid of a batch whose io is set: one workgroup per item (0) or a persistent grid of one or
+    two workgroups per CU (returns the timings)."""
     import torch
     res = []
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    for groups in (cus, 2 * cus):
+    for groups in (0, cus, 2 * cus):
         batch.set_groups(groups)
         ms = _time(batch.run, reps)
         res.append({"groups": groups, "ms": ms})

@@ -1,7 +1,7 @@
 // Batches of plans (element types and orders with uneven block sizes)
-// condensed by two persistent launches (the LU items, then the right-hand-side
-// items in per-XCD queues), and hipGraph capture of the whole assemble +
-// condense sequence of a batch.
+// condensed by two launches (the LU items, then the right-hand-side items in
+// per-XCD lists; one workgroup per item, or a persistent grid), and hipGraph
+// capture of the whole assemble + condense sequence of a batch.
 #include <algorithm>
 #include <numeric>
 #include <vector>
@@ -14,12 +14,12 @@ namespace hdg {
 size_t batch_item_args_bytes();
 hipError_t launch_condense_batch(const DevPlan *plans_dev, const void *io_dev, const int *lu_queue, int n_lu,
                                  const void *rhs_queue, const int *rhs_xoff, int *counters, int lu_groups,
-                                 int rhs_groups, size_t lds, hipStream_t s);
+                                 int rhs_groups, bool persistent, size_t lds, hipStream_t s);
 }  // namespace hdg
 
 namespace {
 
-struct ItemArgs {   // device layout of the per-plan outputs read by the persistent kernel
+struct ItemArgs {   // device layout of the per-plan outputs read by the batch kernels
   double *S, *g, *Y, *z;
   int32_t *status;
 };
@@ -32,7 +32,8 @@ struct Batch {
   std::vector<int> rhs;         // right-hand-side items: (plan << 24 | element, block), by XCD
   int xoff[NXCD + 1] = {0};     // start of each XCD's items in rhs (in items)
   size_t lds = 0;
-  int groups = 0, rhs_groups = 0;
+  int groups = 0, rhs_groups = 0;   // persistent grid sizes; groups == 0: one workgroup per item
+  int rhs_max = 0;                  // longest per-XCD right-hand-side list
   bool bound = false;
   DevPlan *d_plans = nullptr;
   ItemArgs *d_io = nullptr;
@@ -125,10 +126,7 @@ extern "C" int hdg_batch_create(hdg_batch **out, hdg_plan *const *plans, int n_p
     B->xoff[x + 1] = B->xoff[x] + (int)xq[x].size() / 2;
     B->rhs.insert(B->rhs.end(), xq[x].begin(), xq[x].end());
   }
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) cus = 256;
-  B->groups = std::max(1, std::min<int>(cus, (int)B->queue.size()));
-  B->rhs_groups = NXCD * std::max(1, cus / NXCD);
+  for (int x = 0; x < NXCD; ++x) B->rhs_max = std::max(B->rhs_max, B->xoff[x + 1] - B->xoff[x]);
   *out = reinterpret_cast<hdg_batch *>(B);
   return HDG_OK;
 }
@@ -175,7 +173,7 @@ extern "C" int hdg_batch_bind_workspace(hdg_batch *batch, void *ptr, size_t byte
 
 extern "C" int hdg_batch_set_groups(hdg_batch *batch, int groups) {
   Batch *B = reinterpret_cast<Batch *>(batch);
-  if (!B || groups < 1) return fail(HDG_EINVAL, "bad argument");
+  if (!B || groups < 0) return fail(HDG_EINVAL, "bad argument");
   B->groups = std::min<int>(groups, (int)B->queue.size());
   B->rhs_groups = NXCD * ((groups + NXCD - 1) / NXCD);
   drop_graph(B);
@@ -212,10 +210,12 @@ int batch_sequence(Batch *B, hipStream_t s) {
     int rc = run_front(P, a.v, a.q, a.vhat, a.u_star, a.v_bc, a.elem_status, 0, P->n_elem, s, P->dp.mg != nullptr);
     if (rc) return rc;
   }
-  hipError_t e = launch_fill_int(B->d_counter, 1 + NXCD, 0, s);
+  const bool persistent = B->groups > 0;
+  hipError_t e = persistent ? launch_fill_int(B->d_counter, 1 + NXCD, 0, s) : hipSuccess;
   if (!e)
     e = launch_condense_batch(B->d_plans, B->d_io, B->d_queue, (int)B->queue.size(), B->d_rhs, B->d_xoff,
-                              B->d_counter, B->groups, B->rhs_groups, B->lds, s);
+                              B->d_counter, persistent ? B->groups : (int)B->queue.size(),
+                              persistent ? B->rhs_groups : NXCD * B->rhs_max, persistent, B->lds, s);
   if (e) return hip_fail(e, "batch condense");
   return HDG_OK;
 }

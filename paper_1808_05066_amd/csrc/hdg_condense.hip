@@ -75,6 +75,18 @@ struct Lds {
   int *mvn;      // [1] number of changed positions
 };
 
+// Thread index of the helpers below, by workgroup size.  The 256-thread kernels run the LU's
+// loop over column blocks (and the batch's loop over elements) with a large live state: they
+// read it through cur_tid, so that index arithmetic is recomputed inside each helper instead of
+// being held, and spilled, across the loop.  The 1024-thread right-hand-side kernels hold few
+// registers per thread and read threadIdx.x directly: cur_tid's volatile asm also fixes the
+// order of the loads around it, which these load-bound kernels pay for.
+template <int NTT>
+__device__ __forceinline__ int tid_of() {
+  if constexpr (NTT >= 1024) return (int)threadIdx.x;
+  else return cur_tid();
+}
+
 // blk[i][c] = M[(c0 + c) * ld + perm[i]]  (gathered through the permutation;
 // each thread keeps LU loads in flight before writing them to LDS)
 constexpr int LU = 8;
@@ -83,7 +95,7 @@ template <typename T, int W, int NTT = NT, typename Fetch>
 __device__ inline void load_block_f(const Lds<T> &s, int np, Fetch fetch) {
   constexpr int BS = W + 1;
   const int total = np * W;
-  for (int t0 = threadIdx.x; t0 < total; t0 += LU * NTT) {
+  for (int t0 = tid_of<NTT>(); t0 < total; t0 += LU * NTT) {
     T v[LU];
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
@@ -115,7 +127,7 @@ template <typename T, int W, int NTT = NT, typename Fetch>
 __device__ inline void load_block_scaled_f(const Lds<T> &s, int c0, int np, bool colscale, Fetch fetch) {
   constexpr int BS = W + 1;
   const int total = np * W;
-  for (int t0 = threadIdx.x; t0 < total; t0 += LU * NTT) {
+  for (int t0 = tid_of<NTT>(); t0 < total; t0 += LU * NTT) {
     double v[LU];
 #pragma unroll
     for (int u = 0; u < LU; ++u) {
@@ -170,7 +182,7 @@ __device__ inline void load_block_formed(const Lds<T> &s, const DevPlan &P, cons
                                          int j0) {
   constexpr int BS = W + 1;
   const int np = P.n_pad, n = P.n, Np = P.Np, D = P.dim, nv = P.m * Np, DN = D * Np;
-  for (int x = threadIdx.x; x < np; x += NT) s.invb[s.perm[x]] = x;
+  for (int x = cur_tid(); x < np; x += NT) s.invb[s.perm[x]] = x;
   const auto fetch = [&](int c, int o) {
     const int col = j0 + c;
     if (o < nv) return col < n ? A64[(size_t)col * np + o] : 0.0;
@@ -179,7 +191,7 @@ __device__ inline void load_block_formed(const Lds<T> &s, const DevPlan &P, cons
   if constexpr (LP) load_block_scaled_f<T, W>(s, j0, np, true, fetch);
   else load_block_f<T, W>(s, np, fetch);
   __syncthreads();
-  for (int t = threadIdx.x; t < W * DN; t += NT) {
+  for (int t = cur_tid(); t < W * DN; t += NT) {
     const int c = t / DN, r = t - c * DN, col = j0 + c;
     if (col >= n) continue;
     int o;
@@ -205,7 +217,7 @@ __device__ inline void load_block_formed(const Lds<T> &s, const DevPlan &P, cons
 template <typename T, int W>
 __device__ inline void store_block(const Lds<T> &s, T *M, int ld, int c0, int np) {
   constexpr int BS = W + 1;
-  for (int t = threadIdx.x; t < np * W; t += NT) {
+  for (int t = cur_tid(); t < np * W; t += NT) {
     const int c = t / np, i = t - c * np;
     M[(size_t)(c0 + c) * ld + i] = s.blk[i * BS + c];
   }
@@ -228,10 +240,10 @@ struct Step {
   int r_lo, r_hi;   // rows updated by the panel p0..p0+W-1 (empty if r_lo >= r_hi)
 };
 
-template <typename T, int W>
+template <typename T, int W, int NTT = NT>
 __device__ inline void load_inv(T (&ia)[W / 4], const T *Ie, const Step &st) {
   constexpr int TW = W / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = tid_of<NTT>(), lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   if (st.inv < 0 || wave >= TW * TW) return;
   const T *Inv = Ie + st.inv;
@@ -240,9 +252,9 @@ __device__ inline void load_inv(T (&ia)[W / 4], const T *Ie, const Step &st) {
   for (int kk = 0; kk < W / 4; ++kk) ia[kk] = Inv[(4 * kk + lk) * W + ti * 16 + li];
 }
 
-template <typename T, int W>
+template <typename T, int W, int NTT = NT>
 __device__ inline void load_tile(T (&a)[W / 4], const T *M, int ld, const Step &st) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = tid_of<NTT>(), lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   if (st.inv < 0 || st.r_lo + wave * 16 >= st.r_hi) return;
   const T *Mb = M + (size_t)st.p0 * ld;
@@ -255,11 +267,11 @@ __device__ inline void load_tile(T (&a)[W / 4], const T *M, int ld, const Step &
 // inverse of the unit-lower (L) or upper (U) W x W diagonal block of the factors;
 // (W/16)^2 waves each form one 16 x 16 tile on MFMA, then write back after a
 // barrier.  The inverse of the next step is loaded into ia meanwhile.
-template <typename T, int W>
+template <typename T, int W, int NTT = NT>
 __device__ inline void inv_apply(const Lds<T> &s, T (&ia)[W / 4], int p0, const T *Ie, const Step &next) {
   typedef Mfma<T> MF;
   constexpr int BS = W + 1, TW = W / 16;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = tid_of<NTT>(), lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   typename MF::acc acc = {0, 0, 0, 0};
   const int ti = wave % TW, tj = wave / TW;
@@ -267,7 +279,7 @@ __device__ inline void inv_apply(const Lds<T> &s, T (&ia)[W / 4], int p0, const 
 #pragma unroll
     for (int kk = 0; kk < W / 4; ++kk) acc = MF::op(ia[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
   }
-  load_inv<T, W>(ia, Ie, next);
+  load_inv<T, W, NTT>(ia, Ie, next);
   lds_barrier();
   if (wave < TW * TW) {
 #pragma unroll
@@ -332,7 +344,7 @@ __device__ inline float rcp_newton(float x) {
 template <typename T, int W>
 __device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
   constexpr int BS = W + 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = cur_tid(), lane = tid & 63, wave = tid >> 6;
   if (lane >= W || wave > 1) return;
   // c is made opaque to the optimizer: otherwise the identity columns below are hoisted
   // out of the caller's block loop and stay live (2W registers) through every phase
@@ -379,7 +391,7 @@ __device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, i
   constexpr int NWT = NTT / 64;
   typedef Mfma<T> MF;
   constexpr int BS = W + 1, TW = W / 16, KS = W / 4;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = tid_of<NTT>(), lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int p0 = st.p0, r_lo = st.r_lo;
   const int ntile = st.r_hi > r_lo ? (st.r_hi - r_lo) / 16 : 0;
@@ -396,7 +408,7 @@ __device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, i
     }
   }
   T an[KS];
-  load_tile<T, W>(an, M, ld, next);
+  load_tile<T, W, NTT>(an, M, ld, next);
 #pragma unroll
   for (int kk = 0; kk < KS; ++kk) ab[0][kk] = a[kk];
   const auto tile = [&](int t, const T (&op)[KS]) {
@@ -449,11 +461,11 @@ template <typename T, int W, typename Spec, int NTT = NT, int MT = 5>
 __device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int ld, int count, Spec spec) {
   T ia[W / 4], a[W / 4];
   Step cur = spec(0);
-  load_inv<T, W>(ia, Ie, cur);
-  load_tile<T, W>(a, Fm, ld, cur);
+  load_inv<T, W, NTT>(ia, Ie, cur);
+  load_tile<T, W, NTT>(a, Fm, ld, cur);
   for (int i = 0; i < count; ++i) {
     const Step nxt = (i + 1 < count) ? spec(i + 1) : Step{-1, 0, 0, 0};
-    inv_apply<T, W>(s, ia, cur.p0, Ie, nxt);
+    inv_apply<T, W, NTT>(s, ia, cur.p0, Ie, nxt);
     lds_barrier();
     gemm_update<T, W, NTT, MT>(s, a, Fm, ld, cur, nxt);
     lds_barrier();
@@ -480,7 +492,7 @@ constexpr int SPW = 8;   // sub-panel width
 template <typename T, int W>
 __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np) {
   constexpr int BS = W + 1;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = cur_tid(), lane = tid & 63, wave = tid >> 6;
   const int r0 = j0 + tid, r1 = j0 + tid + NT;   // rows r1, r1 + NT, ... stay in LDS
   const bool has0 = r0 < np;
   T *y0 = s.blk + (size_t)r0 * BS;
@@ -653,7 +665,7 @@ __device__ inline bool panel_factor(const Lds<T> &s, int j0, int np) {
 // before it); at most 2W of them.
 template <typename T>
 __device__ inline void moved_rows(const Lds<T> &s, int j0, int np) {
-  for (int x = j0 + threadIdx.x; x < np; x += NT) {
+  for (int x = j0 + cur_tid(); x < np; x += NT) {
     const int y = s.invb[s.perm[x]];
     if (y != x) {
       const int k = atomicAdd(s.mvn, 1);
@@ -671,7 +683,7 @@ __device__ inline void moved_rows(const Lds<T> &s, int j0, int np) {
 template <int NWV, typename T>
 __device__ inline void move_rows_waves(const int *mvx, const int *mvy, int m, T *Fm, int ld, int j0) {
   if (m == 0) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tid = cur_tid(), lane = tid & 63, w = tid >> 6;
   const bool act = lane < m;
   const int y = act ? mvy[lane] : 0, x = act ? mvx[lane] : 0;
   constexpr int CU = 4;
@@ -794,7 +806,7 @@ __device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &
   const double *mg = P.mg ? P.mg + (size_t)el * (P.dim + 1) * P.Np * P.Np : nullptr;
   T *Fm = f.F;
   T *Ie = f.Inv;
-  const int tid = threadIdx.x;
+  const int tid = cur_tid();
   const int nJ = np / W;
   for (int i = tid; i < np; i += NT) {
     s.perm[i] = i;
@@ -853,7 +865,7 @@ __device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c
   const double *C = P.C + (size_t)el * np * kp;
   const double *Dm = P.D + (size_t)el * kp * kp;
   const double *Rt = P.Rt + (size_t)el * kp;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = tid_of<NTT>(), lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int nJ = np / W;
   T *Se = S + (size_t)e * k * k;
@@ -936,7 +948,7 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
   const FactorPtrs<T, LP> f = factor_ptrs<T, LP>(P, e, el, inv, fac);
   const bool singular = lu_part<T, LP, W>(P, el, s, f);
   for (int c0 = 0; c0 < P.kx; c0 += W) rhs_block<T, LP, W>(P, e, el, c0, s, f, S, g, Y, z);
-  if (singular && threadIdx.x == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
+  if (singular && cur_tid() == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
 }
 
 // Split condensation: the LU of one element per workgroup, then one workgroup
@@ -950,7 +962,7 @@ __device__ __forceinline__ void lu_body(const DevPlan &P, int e0, int el, int32_
   const Lds<T> s = carve_lds<T, LP, W>(P.n_pad);
   const FactorPtrs<T, LP> f = factor_ptrs<T, LP>(P, e, el, inv, fac);
   const bool singular = lu_part<T, LP, W>(P, el, s, f);
-  if (singular && threadIdx.x == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
+  if (singular && cur_tid() == 0 && status[el] == HDG_OK) status[el] = HDG_ESINGULAR;
 }
 
 constexpr int NXCD = 8;
@@ -969,7 +981,7 @@ __device__ __forceinline__ void rhs_body(const DevPlan &P, int e0, int ec, T *S,
   const int *perm = LP ? reinterpret_cast<const int *>(f.rec + rec_perm_off(np)) : P.ipiv + (size_t)el * np;
   const double *A64 = P.A + (size_t)el * np * np;
   const double *mg = P.mg ? P.mg + (size_t)el * (P.dim + 1) * P.Np * P.Np : nullptr;
-  for (int i = threadIdx.x; i < np; i += NTT) {
+  for (int i = tid_of<NTT>(); i < np; i += NTT) {
     s.perm[i] = perm[i];
     if constexpr (LP) s.dsc[i] = diag_scale(P, A64, mg, i);
   }
@@ -1036,68 +1048,101 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
   condense_body<float, true, W>(P, e0, blockIdx.x, status, S, g, Y, z, nullptr, fac);
 }
 
-// Persistent condensation over a batch of plans (element types / orders with uneven n, k), in
-// two launches as the per-plan path: every workgroup takes work items from a queue until it
-// is empty.
+// Condensation of a batch of plans (element types / orders with uneven n, k), in two launches
+// as the per-plan path, over two item lists:
 // * LU items (plan << 24 | element), longest processing time first: the LU of the element.
 // * Right-hand-side items (plan << 24 | element, block j): one 32- (or 16-) column block of
-//   [B | R_loc] against the element's factors.  Eight queues, one per XCD: the items of an
-//   element sit together in the queue of one XCD, and a workgroup takes items from the queue
-//   of the XCD it runs on (workgroups are handed to the XCDs round-robin by index), so the
-//   workgroups working on an element share its factors and C in that XCD's L2.
+//   [B | R_loc] against the element's factors.  Eight lists, one per XCD: the items of an
+//   element sit together in the list of one XCD, and run on workgroups of that XCD
+//   (workgroups are handed to the XCDs round-robin by index), so the workgroups working on an
+//   element share its factors and C in that XCD's L2.
+// Default: one workgroup per item (workgroup b of the right-hand-side launch takes item b / 8
+// of XCD b % 8's list); the hardware dispatches workgroups in index order as slots free up,
+// which is the longest-processing-time list schedule.  Persistent (a fixed grid of workgroups
+// taking items from atomic counters until the lists are empty) is kept as an option.
 struct BatchItemArgs {
   double *S, *g, *Y, *z;
   int32_t *status;
 };
 
+__device__ __forceinline__ void lu_item(const DevPlan *__restrict__ plans, const BatchItemArgs *__restrict__ io,
+                                        int code) {
+  const int pi = code >> 24, el = code & 0xFFFFFF;
+  const DevPlan &P = plans[pi];
+  if (P.cw == 32) lu_body<double, false, 32>(P, 0, el, io[pi].status, P.inv, nullptr);
+  else lu_body<double, false, 16>(P, 0, el, io[pi].status, P.inv, nullptr);
+}
+
 __global__ __launch_bounds__(NT) void k_lu_batch(const DevPlan *__restrict__ plans,
                                                  const BatchItemArgs *__restrict__ io,
-                                                 const int *__restrict__ queue, int n_items, int *counter) {
+                                                 const int *__restrict__ queue, int n_items) {
+  if ((int)blockIdx.x >= n_items) return;   // whole workgroup
+  lu_item(plans, io, __builtin_amdgcn_readfirstlane(queue[blockIdx.x]));
+}
+
+__global__ __launch_bounds__(NT) void k_lu_batch_persistent(const DevPlan *__restrict__ plans,
+                                                            const BatchItemArgs *__restrict__ io,
+                                                            const int *__restrict__ queue, int n_items,
+                                                            int *counter) {
   __shared__ int s_item;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = s_item;
+    // the item is the same for the whole workgroup: keep it (and the plan fields read through
+    // it) in scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n_items) break;
-    const int code = queue[it];
-    const int pi = code >> 24, el = code & 0xFFFFFF;
-    const DevPlan &P = plans[pi];
-    if (P.cw == 32) lu_body<double, false, 32>(P, 0, el, io[pi].status, P.inv, nullptr);
-    else lu_body<double, false, 16>(P, 0, el, io[pi].status, P.inv, nullptr);
+    lu_item(plans, io, __builtin_amdgcn_readfirstlane(queue[it]));
     __syncthreads();
   }
 }
 
-template <int W>
-__device__ __forceinline__ void rhs_item(const DevPlan &P, int el, int j, const BatchItemArgs &a) {
+__device__ __forceinline__ void rhs_item(const DevPlan *__restrict__ plans, const BatchItemArgs *__restrict__ io,
+                                         int code, int j) {
+  const int pi = code >> 24, el = code & 0xFFFFFF;
+  const DevPlan &P = plans[pi];
   const int np = P.n_pad;
-  const Lds<double> s = carve_lds<double, false, W>(np);
-  const FactorPtrs<double, false> f = factor_ptrs<double, false>(P, el, el, P.inv, nullptr);
   const int *perm = P.ipiv + (size_t)el * np;
-  for (int i = threadIdx.x; i < np; i += NT_RHS) s.perm[i] = perm[i];
-  __syncthreads();
-  rhs_block<double, false, W, NT_RHS>(P, el, el, j * W, s, f, a.S, a.g, a.Y, a.z);
+  const FactorPtrs<double, false> f = factor_ptrs<double, false>(P, el, el, P.inv, nullptr);
+  const BatchItemArgs &a = io[pi];
+  if (P.cw == 32) {
+    const Lds<double> s = carve_lds<double, false, 32>(np);
+    for (int i = tid_of<NT_RHS>(); i < np; i += NT_RHS) s.perm[i] = perm[i];
+    __syncthreads();
+    rhs_block<double, false, 32, NT_RHS>(P, el, el, j * 32, s, f, a.S, a.g, a.Y, a.z);
+  } else {
+    const Lds<double> s = carve_lds<double, false, 16>(np);
+    for (int i = tid_of<NT_RHS>(); i < np; i += NT_RHS) s.perm[i] = perm[i];
+    __syncthreads();
+    rhs_block<double, false, 16, NT_RHS>(P, el, el, j * 16, s, f, a.S, a.g, a.Y, a.z);
+  }
 }
 
 __global__ __launch_bounds__(NT_RHS) void k_rhs_batch(const DevPlan *__restrict__ plans,
                                                       const BatchItemArgs *__restrict__ io,
-                                                      const int2 *__restrict__ queue, const int *__restrict__ xoff,
-                                                      int *counters) {
+                                                      const int2 *__restrict__ queue, const int *__restrict__ xoff) {
+  const int x = blockIdx.x % NXCD, it = blockIdx.x / NXCD;
+  if (it >= xoff[x + 1] - xoff[x]) return;   // whole workgroup
+  const int2 c = queue[xoff[x] + it];
+  rhs_item(plans, io, __builtin_amdgcn_readfirstlane(c.x), __builtin_amdgcn_readfirstlane(c.y));
+}
+
+__global__ __launch_bounds__(NT_RHS) void k_rhs_batch_persistent(const DevPlan *__restrict__ plans,
+                                                                 const BatchItemArgs *__restrict__ io,
+                                                                 const int2 *__restrict__ queue,
+                                                                 const int *__restrict__ xoff, int *counters) {
   __shared__ int s_item;
   const int x = blockIdx.x % NXCD;
   const int n_items = xoff[x + 1] - xoff[x];
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&counters[x], 1);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n_items) break;
     const int2 c = queue[xoff[x] + it];
-    const int pi = c.x >> 24, el = c.x & 0xFFFFFF;
-    const DevPlan &P = plans[pi];
-    if (P.cw == 32) rhs_item<32>(P, el, c.y, io[pi]);
-    else rhs_item<16>(P, el, c.y, io[pi]);
+    rhs_item(plans, io, __builtin_amdgcn_readfirstlane(c.x), __builtin_amdgcn_readfirstlane(c.y));
     __syncthreads();
   }
 }
@@ -1792,16 +1837,29 @@ size_t batch_item_args_bytes() { return sizeof(BatchItemArgs); }
 
 hipError_t launch_condense_batch(const DevPlan *plans_dev, const void *io_dev, const int *lu_queue, int n_lu,
                                  const void *rhs_queue, const int *rhs_xoff, int *counters, int lu_groups,
-                                 int rhs_groups, size_t lds, hipStream_t s) {
-  hipError_t e = set_dyn_lds((const void *)k_lu_batch, lds);
+                                 int rhs_groups, bool persistent, size_t lds, hipStream_t s) {
+  const BatchItemArgs *io = static_cast<const BatchItemArgs *>(io_dev);
+  const int2 *rq = static_cast<const int2 *>(rhs_queue);
+  hipError_t e;
+  if (persistent) {
+    e = set_dyn_lds((const void *)k_lu_batch_persistent, lds);
+    if (!e) e = set_dyn_lds((const void *)k_rhs_batch_persistent, lds);
+    if (e) return e;
+    hipLaunchKernelGGL(k_lu_batch_persistent, dim3(lu_groups), dim3(NT), lds, s, plans_dev, io, lu_queue, n_lu,
+                       counters);
+    e = hipGetLastError();
+    if (e) return e;
+    hipLaunchKernelGGL(k_rhs_batch_persistent, dim3(rhs_groups), dim3(NT_RHS), lds, s, plans_dev, io, rq, rhs_xoff,
+                       counters + 1);
+    return hipGetLastError();
+  }
+  e = set_dyn_lds((const void *)k_lu_batch, lds);
   if (!e) e = set_dyn_lds((const void *)k_rhs_batch, lds);
   if (e) return e;
-  const BatchItemArgs *io = static_cast<const BatchItemArgs *>(io_dev);
-  hipLaunchKernelGGL(k_lu_batch, dim3(lu_groups), dim3(NT), lds, s, plans_dev, io, lu_queue, n_lu, counters);
+  hipLaunchKernelGGL(k_lu_batch, dim3(lu_groups), dim3(NT), lds, s, plans_dev, io, lu_queue, n_lu);
   e = hipGetLastError();
   if (e) return e;
-  hipLaunchKernelGGL(k_rhs_batch, dim3(rhs_groups), dim3(NT_RHS), lds, s, plans_dev, io,
-                     static_cast<const int2 *>(rhs_queue), rhs_xoff, counters + 1);
+  hipLaunchKernelGGL(k_rhs_batch, dim3(rhs_groups), dim3(NT_RHS), lds, s, plans_dev, io, rq, rhs_xoff);
   return hipGetLastError();
 }
 

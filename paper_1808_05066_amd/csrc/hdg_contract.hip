@@ -145,9 +145,10 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   // the coefficient slice of points q0..q0+3, fetched into registers one slice
   // ahead of its use so that the loads overlap the previous slice's MFMAs
   auto fetch = [&](int q0, double (&cv)[CR]) {
+    const int ft = cur_tid();
 #pragma unroll
     for (int u = 0; u < CR; ++u) {
-      const int t = tid + u * NT;
+      const int t = ft + u * NT;
       double val = 0.0;
       if (t < 4 * CS) {
         const int j = t % CS, qq = t / CS;
@@ -157,6 +158,9 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
     }
   };
   for (int base = 0; base < ntiles; base += (NT / 64) * RT) {
+    // thread indices re-read per pass (cur_tid): derived offsets stay inside the loop body
+    const int tid = cur_tid(), lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
     d4 acc[RT][NCT];
 #pragma unroll
     for (int u = 0; u < RT; ++u)
@@ -191,6 +195,7 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
         if (tid + u * NT < 4 * CS) coef[tid + u * NT] = cv[u];
       if (q0 + 4 < Nq4) fetch(q0 + 4, cv);
       __syncthreads();
+      const int lk = (cur_tid() & 63) >> 4, li = cur_tid() & 15;
       const int qp = q0 + lk;
       const int ql = resident ? qp : qp % QC;   // row of the staged tables
       const double *cq = coef + lk * CS;
@@ -326,6 +331,8 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
   double *spp = spf + Nfq * L.fsize;            // [Nfq][Nfp][Nfp]
   double *sps = spp + Nfq * NP2;                // [Nfq][Nfp]
   for (int f = 0; f < nf; ++f) {
+    const int tid = cur_tid(), lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
     const double *pff = pf + (size_t)f * Nfq * L.fsize;
     for (int t = tid; t < Nfq * L.fsize; t += NT) spf[t] = pff[t];
     const double *fp = P.fphi + (size_t)f * Nfq * Nfp;
@@ -346,6 +353,7 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
       const int nct = (NP2 + 15) / 16;
       const int Nfq4 = (Nfq + 3) & ~3;
       for (int tt = wave; tt < RTL * nct; tt += NT / 64) {
+        const int lane = cur_tid() & 63, li = lane & 15, lk = lane >> 4;
         const int rt = tt / nct, ct = tt % nct;
         const int ra = rt * 16 + li;   // A-operand row of this lane
         int off = -1;

@@ -171,6 +171,17 @@ hipError_t launch_scale_blocks(const DevPlan &P, double *B, const float *o, hipS
 // call is not repeated inside stream capture.
 hipError_t set_dyn_lds(const void *kernel, size_t bytes);
 
+// The thread index, read through an empty volatile asm.  The compiler can neither hoist what
+// is derived from it out of a loop nor merge two reads: a kernel that re-reads it at the top of
+// a long loop body (or in every helper such a loop calls) keeps its index arithmetic inside
+// the body, where it is cheap to recompute, instead of holding it live across the loop, where
+// it spills to scratch memory.
+__device__ __forceinline__ int cur_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // error channel of hdg_last_error(): records the message, returns the code
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *where);

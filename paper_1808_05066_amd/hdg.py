@@ -599,7 +599,8 @@ def adam(theta, grad, m, v, t, lr):
 
 
 class Batch:
-    """Persistent condensation of several plans in one launch, optionally replayed from a hipGraph.
+    """Condensation of several plans in two launches (LU items, then right-hand-side items),
+    optionally replayed from a hipGraph.
 
     io: list (one per plan) of dicts with v, q, vhat, ustar, vbc and outputs S, g, Y, z, status.
     order: "lpt" (largest blocks first) or "plan".
@@ -628,6 +629,7 @@ class Batch:
         return {"items": n.value, "groups": g.value, "lds_bytes": lds.value}
 
     def set_groups(self, groups):
+        """0 (default): one workgroup per item; > 0: a persistent grid of that many workgroups."""
         check(self.lib.hdg_batch_set_groups(self.h, int(groups)), "hdg_batch_set_groups")
 
     def set_io(self, io):

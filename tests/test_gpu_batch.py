@@ -3,9 +3,9 @@
 * every group (one element type and order) condensed on the GPU matches the
   oracle on sampled elements (S, Y, g relative <= 1e-12; z backward error
   <= 1e-12 in the summation scale of R_loc);
-* the persistent batched launch (largest blocks first, and plan order)
-  produces the same outputs as the per-plan launches, bit for bit (same
-  arithmetic in the same order);
+* the batched launches (one workgroup per item, largest blocks first and
+  plan order; a persistent grid) produce the same outputs as the per-plan
+  launches, bit for bit (same arithmetic in the same order);
 * a captured hipGraph of the whole batch, replayed several times with eager
   work and synchronizations in between, reproduces the eager outputs every
   time;
@@ -81,11 +81,12 @@ def _io(groups, torch):
     return io
 
 
-@pytest.mark.parametrize("order", ["lpt", "plan"])
-def test_persistent_batch_equals_per_plan(torch, groups, order):
+@pytest.mark.parametrize("order,grid", [("lpt", 0), ("plan", 0), ("lpt", 256)])
+def test_batch_equals_per_plan(torch, groups, order, grid):
     """Bit for bit against per-plan launches of the same arithmetic (the LU with its working
-    block in LDS, which the batch runs); the per-plan default (the register-resident LU for
-    the small tetrahedra) agrees to rounding."""
+    block in LDS, which the batch runs), with one workgroup per item (grid 0) and with a
+    persistent grid; the per-plan default (the register-resident LU for the small tetrahedra)
+    agrees to rounding."""
     from paper_1808_05066_amd.hdg import Batch
     saved = [g["plan"].tuning()["lu_waves"] for g in groups]
     dflt = [g["plan"].assemble_condense(g["d"]["v"], g["d"]["q"], g["d"]["vhat"], g["d"]["ustar"], g["d"]["vbc"])
@@ -97,6 +98,7 @@ def test_persistent_batch_equals_per_plan(torch, groups, order):
     for g, lw in zip(groups, saved):
         g["plan"].set_tuning(lu_waves=lw)
     b = Batch([g["plan"] for g in groups], order=order)
+    b.set_groups(grid)
     print(b.info())
     io = _io(groups, torch)
     b.set_io(io)
