@@ -257,7 +257,8 @@ def bench_batch(torch, tune=True):
 
     Times the per-plan launches one after another, the batched launches with one workgroup
     per item (largest blocks first, and plan order), with a persistent grid of one workgroup
-    per CU, and the hipGraph replay of the first.
+    per CU, the hipGraph replay of the first, and the stream mode (every plan's own
+    condensation on 2 or 4 concurrent streams; graph replay with 4).
     """
     from paper_1808_05066_amd import autotune
     from paper_1808_05066_amd.hdg import Batch
@@ -299,7 +300,18 @@ def bench_batch(torch, tune=True):
     b.set_io(io)
     res["batch_persistent_ms"] = _timed(b.run, 3, torch)
     del b
-    best = min(res["batch_lpt_ms"], res["graph_replay_ms"])
+    for ns in (2, 4):
+        b = Batch(plans, order="lpt")
+        b.set_streams(ns)
+        b.set_io(io)
+        res["batch_streams%d_ms" % ns] = _timed(b.run, 3, torch)
+        if ns == 4:
+            b.capture()
+            res["graph_replay_streams4_ms"] = _timed(b.replay, 3, torch)
+            res["bad_elements_streams4"] = sum(int((d["status"] != 0).sum()) for d in io)
+        del b
+    best = min(res["batch_lpt_ms"], res["graph_replay_ms"], res["batch_streams4_ms"],
+               res["graph_replay_streams4_ms"])
     res["value"] = E / (best / 1e3)
     res["unit"] = "elem/s"
     res["dense_tflops"] = flops / (best / 1e3) / 1e12

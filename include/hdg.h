@@ -341,6 +341,17 @@ void hdg_batch_destroy(hdg_batch *batch);
 /* Caller-owned device workspace (descriptors, queues, counters). */
 int hdg_batch_workspace_bytes(const hdg_batch *batch, size_t *bytes);
 int hdg_batch_bind_workspace(hdg_batch *batch, void *dev_ptr, size_t bytes, void *stream);
+/* Stream mode (n = 1..8; 0, the default, returns to the item lists): instead
+ * of the two batched launches, every plan runs its own hdg_assemble_condense
+ * (its own tuning: block width, launch count, LU variant, LDS size) on one of
+ * n streams the batch creates (default priority, non-blocking), forked from
+ * the caller's stream and joined back into it, so that the plans' kernels run
+ * concurrently and the small blocks fill the LDS and wave slots the large
+ * ones leave free.  Plans go to streams largest first (order 0) or in plan
+ * order, each to the stream with the least work so far.  Outputs equal the
+ * plans' own hdg_assemble_condense bit for bit.  A captured graph holds the
+ * fork and join. */
+int hdg_batch_set_streams(hdg_batch *batch, int n);
 /* 0 (default): one workgroup per item.  groups > 0: persistent grids, the LU
  * launch with `groups` workgroups (at most one per item), the right-hand-side
  * launch with `groups` rounded up to a multiple of 8.  HDG_EINVAL if < 0. */

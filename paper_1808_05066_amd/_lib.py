@@ -164,6 +164,7 @@ SIGNATURES = {
     "hdg_batch_workspace_bytes": (I, [P, ctypes.POINTER(ctypes.c_size_t)]),
     "hdg_batch_bind_workspace": (I, [P, P, ctypes.c_size_t, P]),
     "hdg_batch_set_groups": (I, [P, I]),
+    "hdg_batch_set_streams": (I, [P, I]),
     "hdg_batch_set_io": (I, [P, ctypes.POINTER(hdg_batch_io), P]),
     "hdg_batch_run": (I, [P, P]),
     "hdg_batch_capture": (I, [P, P]),

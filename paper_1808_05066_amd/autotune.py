@@ -11,8 +11,8 @@ For a plan it times hdg_assemble_condense (FP64) or hdg_assemble_condense_lp
                                          (two elements per CU) or 8 waves
 (median of HIP-event timings after a warm-up), keeps the fastest, and stores
 it in a JSON cache; apply() sets a cached choice on a new plan.  Batches are
-tuned over their grid: one workgroup per item, or a persistent grid of one or
-two workgroups per CU.
+tuned over their mode: item lists with one workgroup per item or a persistent
+grid, or the plans' own condensations on concurrent streams.
 """
 from __future__ import annotations
 
@@ -108,17 +108,20 @@ def tune_plan(plan, inputs, dtype="fp64", reps=3, cache=DEFAULT_CACHE, log=print
 
 
 def tune_batch(batch, reps=3, log=print):
-    """Grid of a batch whose io is set: one workgroup per item (0) or a persistent grid of one or
-    two workgroups per CU (returns the timings)."""
+    """Mode of a batch whose io is set: item lists with one workgroup per item (groups 0) or a
+    persistent grid of one or two workgroups per CU, or every plan's own condensation on 2 or 4
+    concurrent streams (returns the timings)."""
     import torch
     res = []
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    for groups in (0, cus, 2 * cus):
+    for streams, groups in [(0, 0), (0, cus), (0, 2 * cus), (2, 0), (4, 0)]:
+        batch.set_streams(streams)
         batch.set_groups(groups)
         ms = _time(batch.run, reps)
-        res.append({"groups": groups, "ms": ms})
-        log("[autotune] batch groups=%d: %.2f ms" % (groups, ms))
+        res.append({"streams": streams, "groups": groups, "ms": ms})
+        log("[autotune] batch streams=%d groups=%d: %.2f ms" % (streams, groups, ms))
     best = min(res, key=lambda r: r["ms"])
+    batch.set_streams(best["streams"])
     batch.set_groups(best["groups"])
     return {"best": best, "all": res}
 

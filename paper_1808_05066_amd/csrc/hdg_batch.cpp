@@ -45,6 +45,13 @@ struct Batch {
   bool io_set = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // stream mode (nstreams > 0): every plan's own condensation on one of nstreams streams
+  int nstreams = 0;
+  std::vector<double> cost;          // per plan: n_elem * (LU + solves + Schur) work
+  int order = 0;
+  std::vector<hipStream_t> side;     // created on first use, default priority
+  std::vector<hipEvent_t> ev;        // [0] fork, [1 + t] join of stream t
+  std::vector<int> stream_of;        // per plan
 };
 
 size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -79,6 +86,13 @@ void drop_graph(Batch *B) {
   B->graph = nullptr;
 }
 
+void drop_streams(Batch *B) {
+  for (hipEvent_t e : B->ev) (void)hipEventDestroy(e);
+  for (hipStream_t s : B->side) (void)hipStreamDestroy(s);
+  B->ev.clear();
+  B->side.clear();
+}
+
 }  // namespace
 
 extern "C" int hdg_batch_create(hdg_batch **out, hdg_plan *const *plans, int n_plans, int order) {
@@ -101,11 +115,13 @@ extern "C" int hdg_batch_create(hdg_batch **out, hdg_plan *const *plans, int n_p
     B->lds = std::max(B->lds, condense_lds_bytes(P->dp.n_pad, P->dp.cw));
     const double np = P->dp.n_pad, kp = P->dp.k_pad;
     const double lu = np * np * np / 3.0, rhs = np * np * kp + np * kp * kp;   // LU; solves + Schur
+    B->cost.push_back((lu + rhs) * P->n_elem);
     for (int e = 0; e < P->n_elem; ++e) {
       items.push_back({lu, i, e});
       ritems.push_back({rhs, i, e});
     }
   }
+  B->order = order;
   const auto by_cost = [](const Item &a, const Item &b) { return a.cost > b.cost; };
   if (order == 0) {   // longest processing time first
     std::stable_sort(items.begin(), items.end(), by_cost);
@@ -135,6 +151,7 @@ extern "C" void hdg_batch_destroy(hdg_batch *batch) {
   Batch *B = reinterpret_cast<Batch *>(batch);
   if (!B) return;
   drop_graph(B);
+  drop_streams(B);
   delete B;
 }
 
@@ -180,6 +197,48 @@ extern "C" int hdg_batch_set_groups(hdg_batch *batch, int groups) {
   return HDG_OK;
 }
 
+extern "C" int hdg_batch_set_streams(hdg_batch *batch, int n) {
+  Batch *B = reinterpret_cast<Batch *>(batch);
+  if (!B || n < 0 || n > 8) return fail(HDG_EINVAL, "streams: 0 (item lists) or 1..8");
+  drop_graph(B);
+  drop_streams(B);
+  B->nstreams = n;
+  if (n == 0) return HDG_OK;
+  for (int t = 0; t < n; ++t) {
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e) {
+      drop_streams(B);
+      B->nstreams = 0;
+      return hip_fail(e, "batch stream");
+    }
+    B->side.push_back(st);
+  }
+  for (int t = 0; t <= n; ++t) {
+    hipEvent_t ev = nullptr;
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e) {
+      drop_streams(B);
+      B->nstreams = 0;
+      return hip_fail(e, "batch event");
+    }
+    B->ev.push_back(ev);
+  }
+  // plans to streams: largest first (order 0) or in plan order, each to the stream with the
+  // least work so far
+  std::vector<int> idx(B->plans.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  if (B->order == 0) std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return B->cost[a] > B->cost[b]; });
+  std::vector<double> load(n, 0.0);
+  B->stream_of.assign(B->plans.size(), 0);
+  for (int i : idx) {
+    const int t = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    B->stream_of[i] = t;
+    load[t] += B->cost[i];
+  }
+  return HDG_OK;
+}
+
 extern "C" int hdg_batch_set_io(hdg_batch *batch, const hdg_batch_io *io, void *stream) {
   Batch *B = reinterpret_cast<Batch *>(batch);
   if (!B || !B->bound || !io) return fail(HDG_EINVAL, "bad argument or unbound batch");
@@ -201,7 +260,34 @@ extern "C" int hdg_batch_set_io(hdg_batch *batch, const hdg_batch_io *io, void *
 }
 
 namespace {
+// Stream mode: fork the side streams from s, run every plan's own assemble + condense on its
+// stream (in the assignment order, so a stream runs its plans largest first), join back into s.
+int batch_streams(Batch *B, hipStream_t s) {
+  const int n = B->nstreams;
+  hipError_t e = hipEventRecord(B->ev[0], s);
+  for (int t = 0; t < n && !e; ++t) e = hipStreamWaitEvent(B->side[t], B->ev[0], 0);
+  if (e) return hip_fail(e, "batch fork");
+  std::vector<int> idx(B->plans.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  if (B->order == 0) std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return B->cost[a] > B->cost[b]; });
+  int rc = HDG_OK;
+  for (int i : idx) {
+    const hdg_batch_io &a = B->io[i];
+    rc = hdg_assemble_condense(reinterpret_cast<hdg_plan *>(B->plans[i]), a.v, a.q, a.vhat, a.u_star, a.v_bc, a.S,
+                               a.g, a.Y, a.z, nullptr, nullptr, a.elem_status, B->side[B->stream_of[i]]);
+    if (rc) break;
+  }
+  // join every side stream, also after an error, so that none is left forked
+  for (int t = 0; t < n; ++t) {
+    hipError_t ej = hipEventRecord(B->ev[1 + t], B->side[t]);
+    if (!ej) ej = hipStreamWaitEvent(s, B->ev[1 + t], 0);
+    if (ej && !rc) rc = hip_fail(ej, "batch join");
+  }
+  return rc;
+}
+
 int batch_sequence(Batch *B, hipStream_t s) {
+  if (B->nstreams > 0) return batch_streams(B, s);
   for (size_t i = 0; i < B->plans.size(); ++i) {
     Plan *P = B->plans[i];
     const hdg_batch_io &a = B->io[i];

@@ -632,6 +632,10 @@ class Batch:
         """0 (default): one workgroup per item; > 0: a persistent grid of that many workgroups."""
         check(self.lib.hdg_batch_set_groups(self.h, int(groups)), "hdg_batch_set_groups")
 
+    def set_streams(self, n):
+        """n >= 1: every plan's own assemble + condense on n concurrent streams; 0: item lists."""
+        check(self.lib.hdg_batch_set_streams(self.h, int(n)), "hdg_batch_set_streams")
+
     def set_io(self, io):
         arr = (_lib.hdg_batch_io * len(io))()
         for i, d in enumerate(io):

@@ -5,7 +5,8 @@
   <= 1e-12 in the summation scale of R_loc);
 * the batched launches (one workgroup per item, largest blocks first and
   plan order; a persistent grid) produce the same outputs as the per-plan
-  launches, bit for bit (same arithmetic in the same order);
+  launches, bit for bit (same arithmetic in the same order), and so does the
+  stream mode (every plan's own condensation on concurrent streams);
 * a captured hipGraph of the whole batch, replayed several times with eager
   work and synchronizations in between, reproduces the eager outputs every
   time;
@@ -113,9 +114,30 @@ def test_batch_equals_per_plan(torch, groups, order, grid):
             assert err <= 1e-13, (key, err)
 
 
-def test_graph_replay_reproduces_eager(torch, groups):
+@pytest.mark.parametrize("nstreams", [1, 4])
+def test_stream_batch_equals_per_plan(torch, groups, nstreams):
+    """Stream mode runs every plan's own condensation (its own tuning) concurrently: bit for bit
+    the plans' own outputs."""
+    from paper_1808_05066_amd.hdg import Batch
+    ref = [g["plan"].assemble_condense(g["d"]["v"], g["d"]["q"], g["d"]["vhat"], g["d"]["ustar"], g["d"]["vbc"])
+           for g in groups]
+    b = Batch([g["plan"] for g in groups])
+    b.set_streams(nstreams)
+    io = _io(groups, torch)
+    b.set_io(io)
+    b.run()
+    torch.cuda.synchronize()
+    for r, o in zip(ref, io):
+        assert int(o["status"].abs().max()) == 0
+        for key in ("S", "Y", "g", "z"):
+            assert torch.equal(r[key], o[key]), key
+
+
+@pytest.mark.parametrize("nstreams", [0, 4])
+def test_graph_replay_reproduces_eager(torch, groups, nstreams):
     from paper_1808_05066_amd.hdg import Batch
     b = Batch([g["plan"] for g in groups])
+    b.set_streams(nstreams)
     io = _io(groups, torch)
     b.set_io(io)
     b.run()
