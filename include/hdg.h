@@ -294,9 +294,10 @@ int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
  * the fastest in JSON.  Set before building a batch (batches run their own
  * two launches with the LDS-block LU).
  * lu_waves selects the LU of the two-launch FP64 condensation: 1 keeps its
- * 32-column working block in LDS (one workgroup per CU), 4 or 8 keep it in
- * the registers of that many waves (LDS for staging only: with 4 waves two
- * elements share a CU; 4 for n_pad <= 192, 8 for n_pad <= 640).  Default: 4
+ * 32-column working block in LDS (one workgroup per CU), 2, 4 or 8 keep it in
+ * the registers of that many waves (LDS for staging only: with 2 waves four
+ * elements share a CU, with 4 waves two; 2 for n_pad <= 160, 4 for
+ * n_pad <= 192, 8 for n_pad <= 640).  Default: 2 where it applies, else 4
  * where it applies, else 1.  The factors are stored the same way, so S, g, Y,
  * z agree to rounding (the register kernels pick a pivot whose magnitude is
  * within a relative 2^-11 of the column's largest).  HDG_EUNSUPPORTED if the

@@ -6,9 +6,9 @@ For a plan it times hdg_assemble_condense (FP64) or hdg_assemble_condense_lp
   condense_width    in (16, 32)          condensation column-block width
   condense_launches in (1, 2)            one workgroup per element, or the LU and then
                                          one workgroup per right-hand-side block
-  lu_waves          in (1, 4, 8)         FP64 two-launch LU with 32-column blocks: in LDS (one
-                                         element per CU) or in the registers of 4 waves
-                                         (two elements per CU) or 8 waves
+  lu_waves          in (1, 2, 4, 8)      FP64 two-launch LU with 32-column blocks: in LDS (one
+                                         element per CU) or in the registers of 2 waves (four
+                                         elements per CU), 4 waves (two) or 8 waves
 (median of HIP-event timings after a warm-up), keeps the fastest, and stores
 it in a JSON cache; apply() sets a cached choice on a new plan.  Batches are
 tuned over their mode: item lists with one workgroup per item or a persistent
@@ -71,7 +71,7 @@ def candidates(plan, dtype):
                 continue
             shapes += [(w, 1, 1), (w, 2, 1)]
             if w == 32:
-                shapes += [(32, 2, lw) for lw in (4, 8)
+                shapes += [(32, 2, lw) for lw in (2, 4, 8)
                            if _admissible(plan, condense_width=32, condense_launches=2, lu_waves=lw)]
         elif _admissible(plan, condense_width_lp=w):
             shapes += [(w, nl, 1) for nl in (1, 2)]

@@ -390,7 +390,8 @@ extern "C" int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t) {
     if (t->lu_waves == 1) {
       P->dp.lu_waves = 0;
     } else {
-      if (t->lu_waves != 4 && t->lu_waves != 8) return fail(HDG_EINVAL, "lu_waves must be 1, 4 or 8");
+      if (t->lu_waves != 2 && t->lu_waves != 4 && t->lu_waves != 8)
+        return fail(HDG_EINVAL, "lu_waves must be 1, 2, 4 or 8");
       if (!lu_reg_supported(P->dp.n_pad, t->lu_waves))
         return fail(HDG_EUNSUPPORTED, "register-resident LU not available for this block size");
       P->dp.lu_waves = t->lu_waves;

@@ -1243,8 +1243,9 @@ __global__ __launch_bounds__(SB) void k_lp_solve(int n, int np, int W, const flo
 //   suffices (the staging is double-buffered).
 // * Panel factorization of block J in four 8-column sub-panels with partial
 //   pivoting: the sub-panel's rows are copied to LDS and each thread keeps up
-//   to MR of them in registers; per column one wave-wide maximum of a 64-bit
-//   key (the magnitude's leading 48 bits, then the lowest row) and one barrier.
+//   to MR of them in registers; per column one wave-wide maximum of a 32-bit
+//   key (the magnitude's exponent and leading 11 mantissa bits, then the lowest
+//   row; pivot_key32) and one barrier.
 //   Rows are not moved in the registers: sig[p] records the position that the
 //   row held in physical slot p has reached, and every access goes through it.
 //   After a sub-panel its 8 pivot rows are solved against the remaining
@@ -1759,23 +1760,33 @@ bool condense_two_launches(const DevPlan &P) { return (P.cw == 32 || P.cw == 16)
 
 size_t lu_reg_lds_bytes(int np, int nwv) { return reg_layout(np, nwv).total; }
 
-// Register-resident LU (P.lu_waves waves per workgroup): 4 waves (two elements per CU, all
-// registers of a wave within 256) for n_pad <= 192, 8 waves for n_pad <= 640.
+// Register-resident LU (P.lu_waves waves per workgroup): 2 waves (four elements per CU) for
+// n_pad <= 160, 4 waves (two elements per CU, all registers of a wave within 256) for
+// n_pad <= 192, 8 waves for n_pad <= 640.
 bool lu_reg_supported(int np, int nwv) {
   const int tpw = (np / 16 + nwv - 1) / nwv;
+  if (nwv == 2) return tpw <= 5 && reg_layout(np, 2).total <= 40 * 1024;
   if (nwv == 4) return tpw <= 3 && reg_layout(np, 4).total <= 80 * 1024;
   if (nwv == 8) return tpw <= 5 && reg_layout(np, 8).total <= 160 * 1024;
   return false;
 }
 
-// Default LU of the two-launch FP64 condensation: the register-resident kernel with two
-// elements per CU where it applies (measured 1.7x the LDS kernel at n_pad = 160), else the
-// LDS kernel (at n_pad = 544 the register kernel streams the same factors and is slower).
-int default_lu_waves(int np) { return lu_reg_supported(np, 4) ? 4 : 0; }
+// Default LU of the two-launch FP64 condensation: the register-resident kernel with the most
+// elements per CU that applies (at n_pad = 160, 32,768 elements: LDS kernel 28.0 ms, 4 waves
+// 23.3 ms, 2 waves 17.5 ms), else the LDS kernel (at n_pad = 544 the register kernel streams
+// the same factors and is slower).
+int default_lu_waves(int np) {
+  if (lu_reg_supported(np, 2)) return 2;
+  return lu_reg_supported(np, 4) ? 4 : 0;
+}
 
 hipError_t launch_condense_lu_reg(const DevPlan &P, int ec, int32_t *status, hipStream_t s) {
   const int np = P.n_pad, nwv = P.lu_waves, tpw = (np / 16 + nwv - 1) / nwv;
   const size_t lds = reg_layout(np, nwv).total;
+  if (nwv == 2) {
+    if (tpw <= 3) return launch_dyn_t(k_lu_reg<2, 3>, ec, 128, lds, s, P, status, P.inv);
+    if (tpw <= 5) return launch_dyn_t(k_lu_reg<2, 5>, ec, 128, lds, s, P, status, P.inv);
+  }
   if (nwv == 4 && tpw <= 3) return launch_dyn_t(k_lu_reg<4, 3>, ec, 256, lds, s, P, status, P.inv);
   if (nwv == 8) {
     if (tpw <= 2) return launch_dyn_t(k_lu_reg<8, 2>, ec, 512, lds, s, P, status, P.inv);

@@ -97,19 +97,19 @@ def test_condense_matches_oracle(torch, name, chunk, split, narrow):
 
 
 @pytest.mark.parametrize("name", list(SMALL_CASES))
-@pytest.mark.parametrize("lu_waves,chunk", [(4, 0), (8, 0), (4, 3)])
+@pytest.mark.parametrize("lu_waves,chunk", [(2, 0), (4, 0), (8, 0), (4, 3)])
 def test_register_lu_matches_oracle(torch, name, lu_waves, chunk):
-    """The LU with its working block in registers (4 or 8 waves) in front of the same
+    """The LU with its working block in registers (2, 4 or 8 waves) in front of the same
     right-hand-side launch: S, Y, g, z against the oracle at the bar of the LDS kernel, and
-    against the LDS kernel's outputs on the same plan.  Four waves take n_pad <= 192 only;
-    a larger block must be refused."""
+    against the LDS kernel's outputs on the same plan.  Two waves take n_pad <= 160 only,
+    four n_pad <= 192; a larger block must be refused."""
     wl, disc, inp, blocks = _case(name)
     print("case", name, "lu_waves", lu_waves, "chunk", chunk, flush=True)
     plan = gpu_plan(wl, chunk_elems=chunk)
     d = to_dev(inp)
-    if lu_waves == 4 and plan.n_pad > 192:
+    if plan.n_pad > {2: 160, 4: 192, 8: 640}[lu_waves]:
         with pytest.raises(RuntimeError):
-            plan.set_tuning(lu_waves=4)
+            plan.set_tuning(lu_waves=lu_waves)
         return
     plan.set_tuning(lu_waves=1)
     ref = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
