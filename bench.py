@@ -145,42 +145,53 @@ def _timed(fn, reps, torch):
 
 
 def bench_mixed(plan, inp, out64, E, fp64_cond_ms, torch):
-    """FP32 condensation + FP64 refinement of the full Newton system to 1e-10.
+    """Low-precision condensation + FP64 refinement of the full Newton system to 1e-10, with FP32
+    operands on the matrix cores (the main figures) and with BF16 operands (`bf16`).
 
     Mixed elem/s = E / (t_factor_lp + n_ref * t_refine_local): t_factor_lp the
     low-precision assemble + condense, t_refine_local the per-step local work
-    of the refinement (FP32 local solves, matrix-free FP64 Jacobian actions,
+    of the refinement (low-precision local solves, matrix-free FP64 Jacobian actions,
     back-solve, norms; host wall time of the loop minus its GMRES time), n_ref
     the refinement steps to reach the tolerance.  GMRES time is reported apart.
     """
     lp = plan.alloc_outputs_lp()
     args = (inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
-    plan.assemble_condense_lp(*args, out=lp)
-    torch.cuda.synchronize()
-    if int((lp["status"] != 0).sum()):
-        return {"error": "non-OK element status in the low-precision path"}
-    t_lp = _timed(lambda: plan.assemble_condense_lp(*args, out=lp), 5, torch)
-    plan.assemble_condense(*args, out=out64)
-    plan.assemble_condense_lp(*args, out=lp)
-    torch.cuda.synchronize()
-    dx, dlam, info = plan.refine_solve(*args[:3], lp, ustar=inp["ustar"], vbc=inp["vbc"], tol=1e-10,
-                                       max_outer=10, reuse_points=True, gmres_restart=50, gmres_tol=1e-8)
-    n_ref = max(1, info["outer_iterations"])
-    t_local = (info["total_ms"] - info["gmres_ms"]) / n_ref
-    value = E / ((t_lp + n_ref * t_local) / 1e3)
 
     def rel(a, b):
         a = a.double()
         return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
 
-    errs = {"S": rel(lp["S"], out64["S"]), "Y": rel(lp["Y"], out64["Y"]), "g": rel(lp["g"], out64["g"]),
-            "z": rel(lp["z"], out64["z"])}
-    return {"value": value, "unit": "elem/s", "dtype": "f32 condensation + f64 refinement",
-            "speedup_vs_fp64": value / (E / (fp64_cond_ms / 1e3)),
-            "t_factor_lp_ms": t_lp, "refine_steps": info["outer_iterations"], "t_refine_local_ms": t_local,
-            "refine_rel_residual": info["rel_residual"], "refine_history": info["history"],
-            "gmres_iterations": info["gmres_iterations"], "gmres_ms": info["gmres_ms"],
-            "converged": info["converged"], "rel_err_vs_fp64_gpu": errs}
+    def run(ops, max_outer):
+        plan.set_tuning(lp_operands=ops)
+        plan.assemble_condense_lp(*args, out=lp)
+        torch.cuda.synchronize()
+        if int((lp["status"] != 0).sum()):
+            return {"error": "non-OK element status in the low-precision path"}
+        t_lp = _timed(lambda: plan.assemble_condense_lp(*args, out=lp), 5, torch)
+        plan.assemble_condense(*args, out=out64)
+        plan.assemble_condense_lp(*args, out=lp)
+        torch.cuda.synchronize()
+        dx, dlam, info = plan.refine_solve(*args[:3], lp, ustar=inp["ustar"], vbc=inp["vbc"], tol=1e-10,
+                                           max_outer=max_outer, reuse_points=True, gmres_restart=50,
+                                           gmres_tol=1e-8)
+        n_ref = max(1, info["outer_iterations"])
+        t_local = (info["total_ms"] - info["gmres_ms"]) / n_ref
+        value = E / ((t_lp + n_ref * t_local) / 1e3)
+        errs = {"S": rel(lp["S"], out64["S"]), "Y": rel(lp["Y"], out64["Y"]), "g": rel(lp["g"], out64["g"]),
+                "z": rel(lp["z"], out64["z"])}
+        return {"value": value, "unit": "elem/s",
+                "dtype": "%s operands (FP32 condensation) + f64 refinement" % ("bf16" if ops == 2 else "f32"),
+                "speedup_vs_fp64": value / (E / (fp64_cond_ms / 1e3)),
+                "t_factor_lp_ms": t_lp, "refine_steps": info["outer_iterations"], "t_refine_local_ms": t_local,
+                "refine_rel_residual": info["rel_residual"],
+                "refine_history": info["history"][:max(1, info["outer_iterations"])],
+                "gmres_iterations": info["gmres_iterations"], "gmres_ms": info["gmres_ms"],
+                "converged": info["converged"], "rel_err_vs_fp64_gpu": errs}
+
+    res = run(1, 10)
+    res["bf16"] = run(2, 16)
+    plan.set_tuning(lp_operands=1)
+    return res
 
 
 def bench_eliminate_q(wl, inp, out_ref, full_ms, steps, torch):
@@ -346,12 +357,16 @@ def bench_c4(torch, nslab=8, process=None, chunk=2048, tol=1e-10):
     cores after power-of-two scaling), then the element-level FP64 refinement hdg_refine_local of
     A dx = -(R_loc + B P dvhat) for a seeded trace update dvhat to a per-element relative residual
     <= tol.  Mixed elem/s = E / (t_factor_lp + t_refine_local).  Errors: FP32 outputs against the
-    FP64 GPU outputs (S, Y, g, z) and the refined dx against the FP64 back-solve -z - Y P dvhat."""
+    FP64 GPU outputs (S, Y, g, z) and the refined dx against the FP64 back-solve -z - Y P dvhat.
+    `bf16`: the same with BF16 operands on the matrix cores (FP32 data and accumulation), up to 16
+    refinement steps (elements that stagnate fall back to FP64 and are counted)."""
     from paper_1808_05066_amd.inputs import device_inputs, plan_for
-    tot = {"fp64_ms": 0.0, "lp_ms": 0.0, "refine_ms": 0.0}
+    tot = {"fp64_ms": 0.0, "lp_ms": 0.0, "refine_ms": 0.0, "bf_ms": 0.0, "bf_refine_ms": 0.0}
     E = 0
     worst = {"S": 0.0, "Y": 0.0, "g": 0.0, "z": 0.0, "dx": 0.0}
+    worst_bf = dict(worst)
     refine = {"steps_max": 0, "rel_residual_max": 0.0, "converged": True}
+    refine_bf = {"steps_max": 0, "rel_residual_max": 0.0, "converged": True, "fallback_elements": 0}
     rng = np.random.default_rng([4, 9])
 
     def rel(a, b):
@@ -386,6 +401,24 @@ def bench_c4(torch, nslab=8, process=None, chunk=2048, tol=1e-10):
         for key in ("S", "Y", "g", "z"):
             worst[key] = max(worst[key], rel(lp[key], out[key]))
         worst["dx"] = max(worst["dx"], rel(dx, dx64))
+        # the same with BF16 operands on the matrix cores
+        plan.set_tuning(lp_operands=2)
+        plan.assemble_condense_lp(*args, out=lp)
+        torch.cuda.synchronize()
+        if int((lp["status"] != 0).sum()):
+            return {"error": "non-OK element status in the BF16-operand condensation (slab %d)" % i}
+        tot["bf_ms"] += _timed(lambda: plan.assemble_condense_lp(*args, out=lp), 1, torch)
+        dxb, ib = plan.refine_local(*args[:3], lp, dl, ustar=inp["ustar"], vbc=inp["vbc"], tol=tol, max_iter=16)
+        torch.cuda.synchronize()
+        tot["bf_refine_ms"] += ib["total_ms"]
+        refine_bf["steps_max"] = max(refine_bf["steps_max"], ib["outer_iterations"])
+        refine_bf["rel_residual_max"] = max(refine_bf["rel_residual_max"], ib["rel_residual"])
+        refine_bf["converged"] = refine_bf["converged"] and bool(ib["converged"])
+        refine_bf["fallback_elements"] += ib["fallback_elements"]
+        for key in ("S", "Y", "g", "z"):
+            worst_bf[key] = max(worst_bf[key], rel(lp[key], out[key]))
+        worst_bf["dx"] = max(worst_bf["dx"], rel(dxb, dx64))
+        del dxb
         E += plan.n_elem
         n, k = plan.n, plan.k
         del plan, inp, out, lp, dx, dx64, dl
@@ -394,6 +427,7 @@ def bench_c4(torch, nslab=8, process=None, chunk=2048, tol=1e-10):
     dense = fl["lu"] + fl["solve"] + fl["schur"]
     v64 = E / (tot["fp64_ms"] / 1e3)
     vmix = E / ((tot["lp_ms"] + tot["refine_ms"]) / 1e3)
+    vbf = E / ((tot["bf_ms"] + tot["bf_refine_ms"]) / 1e3)
     return {"workload": "ns3d_hex_p3_32: 32^3 periodic trilinear hexes, p = 3 (n = 1280, k = 480), Taylor-Green "
                         "Re 1600 Mach 0.1, 5%% noise, jitter 5%%; %d of its %d slabs of %d elements" % (len(slabs), nslab, E // len(slabs)),
             "elements": E, "n": n, "k": k,
@@ -404,7 +438,11 @@ def bench_c4(torch, nslab=8, process=None, chunk=2048, tol=1e-10):
                       "refine_tol": tol, **refine},
             "speedup_mixed_vs_fp64": vmix / v64,
             "rel_err_fp32_vs_fp64_gpu": worst,
-            "bf16": "not built: see the design notes"}
+            "bf16": {"value": vbf, "unit": "elem/s",
+                     "dtype": "bf16 operands (FP32 condensation) + f64 element refinement",
+                     "t_factor_lp_ms": tot["bf_ms"], "t_refine_local_ms": tot["bf_refine_ms"],
+                     "refine_tol": tol, **refine_bf, "speedup_vs_fp64": vbf / v64,
+                     "rel_err_vs_fp64_gpu": worst_bf}}
 
 
 def bench_learned(torch):

@@ -298,7 +298,12 @@ int hdg_trace_rhs(hdg_plan *plan, const double *g, double *r, void *stream);
  * the registers of that many waves (LDS for staging only: with 2 waves four
  * elements share a CU, with 4 waves two; 2 for n_pad <= 160, 4 for
  * n_pad <= 192, 8 for n_pad <= 640).  Default: 2 where it applies, else 4
- * where it applies, else 1.  The factors are stored the same way, so S, g, Y,
+ * where it applies, else 1.
+ * lp_operands selects the matrix-core operands of hdg_assemble_condense_lp:
+ * 1 (default) FP32, 2 BF16 (rounded to nearest, FP32 accumulation; the data,
+ * the panel factorizations, the stored factors and the outputs stay FP32).
+ * With BF16 the factors and S, Y carry BF16-level errors (relative ~1e-3
+ * times the growth), so the FP64 refinement needs more steps.  The factors are stored the same way, so S, g, Y,
  * z agree to rounding (the register kernels pick a pivot whose magnitude is
  * within a relative 2^-11 of the column's largest).  HDG_EUNSUPPORTED if the
  * block is too large for the choice. */
@@ -308,6 +313,7 @@ typedef struct {
   int condense_width_lp;
   int condense_launches;
   int lu_waves;
+  int lp_operands;
 } hdg_tuning;
 
 int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t);

@@ -77,7 +77,7 @@ class hdg_solve_info(ctypes.Structure):
 class hdg_tuning(ctypes.Structure):
     _fields_ = [("contract_threads", ctypes.c_int), ("condense_width", ctypes.c_int),
                 ("condense_width_lp", ctypes.c_int), ("condense_launches", ctypes.c_int),
-                ("lu_waves", ctypes.c_int)]
+                ("lu_waves", ctypes.c_int), ("lp_operands", ctypes.c_int)]
 
 
 class hdg_batch_io(ctypes.Structure):

@@ -398,6 +398,10 @@ extern "C" int hdg_plan_set_tuning(hdg_plan *plan, const hdg_tuning *t) {
     }
     P->dp.lu_waves_set = 1;
   }
+  if (t->lp_operands) {
+    if (t->lp_operands != 1 && t->lp_operands != 2) return fail(HDG_EINVAL, "lp_operands must be 1 (FP32) or 2 (BF16)");
+    P->dp.lp_bf16 = t->lp_operands == 2;
+  }
   return HDG_OK;
 }
 
@@ -409,5 +413,6 @@ extern "C" int hdg_plan_get_tuning(const hdg_plan *plan, hdg_tuning *t) {
   t->condense_width_lp = P->dp.cw_lp;
   t->condense_launches = P->dp.condense_launches;
   t->lu_waves = P->dp.lu_waves ? P->dp.lu_waves : 1;
+  t->lp_operands = P->dp.lp_bf16 ? 2 : 1;
   return HDG_OK;
 }

@@ -62,6 +62,60 @@ template <> struct Mfma<float> {
   __device__ static inline int row(int lk, int r) { return 4 * lk + r; }
 };
 
+// BF16 operands, FP32 accumulation (the low-precision path with LP == 2).  A panel of 4 KS
+// k values is held as the 16x16x4 instructions take it: lane (li, lk) has a[kk] = A[li][lk + 4 kk]
+// and b[kk] = B[lk + 4 kk][li], kk < KS.  The 16x16x(4 KS) BF16 instruction sums, for every
+// lane group g = lk, over its KS slots i the products of slot i of the A lane (row li, group g)
+// and slot i of the B lane (column li, group g): putting the lane's own kk into slot i = kk gives
+// every k of the panel exactly once, the panel's product summed in another order.  The
+// accumulators keep the FP32 16x16 layout.  Operands are rounded to BF16 (nearest, ties even).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+template <int KS>
+struct BfPanel;
+template <>
+struct BfPanel<8> {
+  typedef bf16x8 op;
+  template <typename F>
+  __device__ static inline op pack(F f) {
+    op v;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (__bf16)f(i);
+    return v;
+  }
+  __device__ static inline f4 mma(op a, op b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct BfPanel<4> {
+  typedef bf16x4 op;
+  template <typename F>
+  __device__ static inline op pack(F f) {
+    op v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = (__bf16)f(i);
+    return v;
+  }
+  __device__ static inline f4 mma(op a, op b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(i16x4, a), __builtin_bit_cast(i16x4, b), c,
+                                                     0, 0, 0);
+  }
+};
+
+// acc + sum over the panel's k of a[k] b[k] for this lane's operands (see above): KS 16x16x4
+// instructions in the operands' precision, or with BF one BF16 instruction
+template <typename T, bool BF, int KS, typename Fb>
+__device__ __forceinline__ typename Mfma<T>::acc mma_panel(const T (&a)[KS], Fb b, typename Mfma<T>::acc c) {
+  if constexpr (BF) {
+    typedef BfPanel<KS> BP;
+    return BP::mma(BP::pack([&](int i) { return a[i]; }), BP::pack(b), c);
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) c = Mfma<T>::op(a[kk], b(kk), c);
+    return c;
+  }
+}
+
 template <typename T>
 struct Lds {
   T *blk;        // [np][BS]
@@ -177,7 +231,7 @@ __device__ inline double a_entry(const DevPlan &P, const double *A64, const doub
 // after a barrier the nonzeros of the q rows in these columns are placed through the inverse
 // permutation (invb, formed here in full) -- at most d N_p per column.  The caller's barrier
 // follows.
-template <typename T, bool LP, int W>
+template <typename T, int LP, int W>
 __device__ inline void load_block_formed(const Lds<T> &s, const DevPlan &P, const double *A64, const double *mg,
                                          int j0) {
   constexpr int BS = W + 1;
@@ -267,7 +321,7 @@ __device__ inline void load_tile(T (&a)[W / 4], const T *M, int ld, const Step &
 // inverse of the unit-lower (L) or upper (U) W x W diagonal block of the factors;
 // (W/16)^2 waves each form one 16 x 16 tile on MFMA, then write back after a
 // barrier.  The inverse of the next step is loaded into ia meanwhile.
-template <typename T, int W, int NTT = NT>
+template <typename T, int W, int NTT = NT, bool BF = false>
 __device__ inline void inv_apply(const Lds<T> &s, T (&ia)[W / 4], int p0, const T *Ie, const Step &next) {
   typedef Mfma<T> MF;
   constexpr int BS = W + 1, TW = W / 16;
@@ -275,10 +329,8 @@ __device__ inline void inv_apply(const Lds<T> &s, T (&ia)[W / 4], int p0, const 
   const int li = lane & 15, lk = lane >> 4;
   typename MF::acc acc = {0, 0, 0, 0};
   const int ti = wave % TW, tj = wave / TW;
-  if (wave < TW * TW) {
-#pragma unroll
-    for (int kk = 0; kk < W / 4; ++kk) acc = MF::op(ia[kk], s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li], acc);
-  }
+  if (wave < TW * TW)
+    acc = mma_panel<T, BF, W / 4>(ia, [&](int kk) { return s.blk[(p0 + 4 * kk + lk) * BS + tj * 16 + li]; }, acc);
   load_inv<T, W, NTT>(ia, Ie, next);
   lds_barrier();
   if (wave < TW * TW) {
@@ -385,7 +437,7 @@ __device__ inline void invert_diag(const Lds<T> &s, int j0, T *Linv, T *Uinv) {
 // requested before the first MFMA, so one memory latency is exposed per step
 // rather than one per tile (a step is short next to a load from memory).  Tiles
 // beyond the first MT of a wave (large blocks) are fetched one tile ahead.
-template <typename T, int W, int NTT = NT, int MT = 5>
+template <typename T, int W, int NTT = NT, int MT = 5, bool BF = false>
 __device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, int ld, const Step &st,
                                    const Step &next) {
   constexpr int NWT = NTT / 64;
@@ -419,11 +471,8 @@ __device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, i
 #pragma unroll
       for (int r = 0; r < 4; ++r) c[q][r] = s.blk[(r0 + MF::row(lk, r)) * BS + q * 16 + li];
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const T *brow = s.blk + (p0 + 4 * kk + lk) * BS;
-#pragma unroll
-      for (int q = 0; q < TW; ++q) c[q] = MF::op(op[kk], brow[q * 16 + li], c[q]);
-    }
+    for (int q = 0; q < TW; ++q)
+      c[q] = mma_panel<T, BF, KS>(op, [&](int kk) { return s.blk[(p0 + 4 * kk + lk) * BS + q * 16 + li]; }, c[q]);
 #pragma unroll
     for (int q = 0; q < TW; ++q)
 #pragma unroll
@@ -457,7 +506,7 @@ __device__ inline void gemm_update(const Lds<T> &s, T (&a)[W / 4], const T *M, i
 
 // A sequence of steps: spec(i) for i in [0, count), each applied with its
 // operands loaded one step ahead.
-template <typename T, int W, typename Spec, int NTT = NT, int MT = 5>
+template <typename T, int W, typename Spec, int NTT = NT, int MT = 5, bool BF = false>
 __device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int ld, int count, Spec spec) {
   T ia[W / 4], a[W / 4];
   Step cur = spec(0);
@@ -465,9 +514,9 @@ __device__ inline void run_steps(const Lds<T> &s, const T *Ie, const T *Fm, int 
   load_tile<T, W, NTT>(a, Fm, ld, cur);
   for (int i = 0; i < count; ++i) {
     const Step nxt = (i + 1 < count) ? spec(i + 1) : Step{-1, 0, 0, 0};
-    inv_apply<T, W, NTT>(s, ia, cur.p0, Ie, nxt);
+    inv_apply<T, W, NTT, BF>(s, ia, cur.p0, Ie, nxt);
     lds_barrier();
-    gemm_update<T, W, NTT, MT>(s, a, Fm, ld, cur, nxt);
+    gemm_update<T, W, NTT, MT, BF>(s, a, Fm, ld, cur, nxt);
     lds_barrier();
     cur = nxt;
   }
@@ -733,7 +782,7 @@ __host__ __device__ inline size_t rec_perm_off(int np) { return (size_t)np * np 
 __host__ __device__ inline size_t lp_rec_floats(int np) { return rec_perm_off(np) + 2 * (size_t)np; }
 
 // LDS of the condensation kernels, carved as lds_layout describes.
-template <typename T, bool LP, int W>
+template <typename T, int LP, int W>
 __device__ __forceinline__ Lds<T> carve_lds(int np) {
   extern __shared__ double smem[];
   char *sm = reinterpret_cast<char *>(smem);
@@ -753,14 +802,14 @@ __device__ __forceinline__ Lds<T> carve_lds(int np) {
 
 // Factor storage of element el (chunk slot) / e (global index): FP64 factors
 // overwrite the A scratch, FP32 factors go to the record.
-template <typename T, bool LP>
+template <typename T, int LP>
 struct FactorPtrs {
   T *F;     // [np][np] factors in pivot-position order
   T *Inv;   // [np/W][2][W][W] inverses of the diagonal blocks
   float *rec;
 };
 
-template <typename T, bool LP>
+template <typename T, int LP>
 __device__ __forceinline__ FactorPtrs<T, LP> factor_ptrs(const DevPlan &P, int e, int el, T *inv, float *fac) {
   const int np = P.n_pad;
   FactorPtrs<T, LP> f;
@@ -799,7 +848,7 @@ __host__ __device__ constexpr int lu_prefetch_tiles() {
 // LU of element el, left-looking over W-column blocks; leaves perm (and the
 // scaling) in LDS and stores the permutation (P.ipiv, or the record).
 // Returns whether a zero pivot occurred.
-template <typename T, bool LP, int W>
+template <typename T, int LP, int W>
 __device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &s, const FactorPtrs<T, LP> &f) {
   const int np = P.n_pad;
   const double *A64 = P.A + (size_t)el * np * np;
@@ -821,7 +870,7 @@ __device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &
     else load_block<T, W>(s, A64, np, j0, np);
     __syncthreads();
     if (J > 0)
-      run_steps<T, W, StepSpec, NT, lu_prefetch_tiles<T, W>()>(s, Ie, Fm, np, J, StepSpec{W, np});
+      run_steps<T, W, StepSpec, NT, lu_prefetch_tiles<T, W>(), LP == 2>(s, Ie, Fm, np, J, StepSpec{W, np});
     if (J > 0) {
       for (int x = j0 + tid; x < np; x += NT) s.invb[s.perm[x]] = x;
       if (tid == 0) *s.mvn = 0;
@@ -855,7 +904,7 @@ __device__ __forceinline__ bool lu_part(const DevPlan &P, int el, const Lds<T> &
 // perm (and the scaling) in LDS: permutation gather, forward and backward
 // sweeps against the stored factors, outputs Y, z, then the Schur product
 // C * Y_block straight from LDS into S and g.
-template <typename T, bool LP, int W, int NTT = NT>
+template <typename T, int LP, int W, int NTT = NT>
 __device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c0, const Lds<T> &s,
                                           const FactorPtrs<T, LP> &f, T *S, double *g, T *Y, double *z) {
   typedef Mfma<T> MF;
@@ -881,7 +930,8 @@ __device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c
     const int Pb = 2 * nJ - 1 - i;
     return Step{Pb * 2 * W * W + W * W, Pb * W, 0, Pb * W};
   };
-  run_steps<T, W, decltype(rhs_spec), NTT, (NTT >= 1024 ? 1 : lu_prefetch_tiles<T, W>())>(s, f.Inv, f.F, np, 2 * nJ, rhs_spec);
+  run_steps<T, W, decltype(rhs_spec), NTT, (NTT >= 1024 ? 1 : lu_prefetch_tiles<T, W>()), LP == 2>(s, f.Inv, f.F, np,
+                                                                                               2 * nJ, rhs_spec);
 
   if constexpr (LP) {
     // undo the column scaling: Y = D Y_hat, z = D z_hat
@@ -914,11 +964,9 @@ __device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c
         for (int kk = 0; kk < 8; ++kk) an[kk] = (T)Cr[(size_t)(kb + 32 + 4 * kk) * kp];
       }
 #pragma unroll
-      for (int kk = 0; kk < 8; ++kk) {
-        const T *brow = s.blk + (kb + 4 * kk + lk) * BS;
-#pragma unroll
-        for (int q = 0; q < TW; ++q) acc[q] = MF::op(a[kk], brow[q * 16 + li], acc[q]);
-      }
+      for (int q = 0; q < TW; ++q)
+        acc[q] = mma_panel<T, LP == 2, 8>(a, [&](int kk) { return s.blk[(kb + 4 * kk + lk) * BS + q * 16 + li]; },
+                                          acc[q]);
 #pragma unroll
       for (int kk = 0; kk < 8; ++kk) a[kk] = an[kk];
     }
@@ -940,7 +988,7 @@ __device__ __forceinline__ void rhs_block(const DevPlan &P, int e, int el, int c
 // T = double, LP = false: FP64 condensation, factors overwrite the A scratch.
 // T = float,  LP = true : scaled FP32 condensation, factors to the record `fac`.
 // One workgroup per element (the LU, then every right-hand-side block).
-template <typename T, bool LP, int W>
+template <typename T, int LP, int W>
 __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, int32_t *status, T *S, double *g,
                                               T *Y, double *z, T *inv, float *fac) {
   const int e = e0 + el;
@@ -956,7 +1004,7 @@ __device__ __forceinline__ void condense_body(const DevPlan &P, int e0, int el, 
 // the same factors and C, so they are placed on one XCD (workgroups are handed
 // to the 8 XCDs round-robin by index: element slot el runs as indices
 // (el / 8 * nRB + j) * 8 + el % 8) and share its L2.
-template <typename T, bool LP, int W>
+template <typename T, int LP, int W>
 __device__ __forceinline__ void lu_body(const DevPlan &P, int e0, int el, int32_t *status, T *inv, float *fac) {
   const int e = e0 + el;
   const Lds<T> s = carve_lds<T, LP, W>(P.n_pad);
@@ -967,7 +1015,7 @@ __device__ __forceinline__ void lu_body(const DevPlan &P, int e0, int el, int32_
 
 constexpr int NXCD = 8;
 
-template <typename T, bool LP, int W, int NTT = NT>
+template <typename T, int LP, int W, int NTT = NT>
 __device__ __forceinline__ void rhs_body(const DevPlan &P, int e0, int ec, T *S, double *g, T *Y, double *z, T *inv,
                                          float *fac) {
   const int nrb = P.kx / W;
@@ -1014,19 +1062,20 @@ __global__ __launch_bounds__(NT_RHS) void k_rhs_f64_w16(DevPlan P, int e0, int e
   rhs_body<double, false, 16, NT_RHS>(P, e0, ec, S, g, Y, z, inv, nullptr);
 }
 
-template <int W>
+// LPM: 1 FP32 operands, 2 BF16 operands (FP32 data and accumulation either way)
+template <int W, int LPM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_lu_f32(DevPlan P, int e0,
                                                                                         int32_t *status,
                                                                                         float *fac) {
-  lu_body<float, true, W>(P, e0, blockIdx.x, status, nullptr, fac);
+  lu_body<float, LPM, W>(P, e0, blockIdx.x, status, nullptr, fac);
 }
 
-template <int W>
+template <int W, int LPM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_rhs_f32(DevPlan P, int e0, int ec,
                                                                                          float *S, double *g,
                                                                                          float *Y, double *z,
                                                                                          float *fac) {
-  rhs_body<float, true, W>(P, e0, ec, S, g, Y, z, nullptr, fac);
+  rhs_body<float, LPM, W>(P, e0, ec, S, g, Y, z, nullptr, fac);
 }
 
 __global__ __launch_bounds__(NT) void k_condense_f64_w32(DevPlan P, int e0, int32_t *status, double *S, double *g,
@@ -1042,10 +1091,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 
 // Two workgroups per CU where the FP32 working block fits twice in LDS:
 // registers are capped so that 16 waves fit.
-template <int W>
+template <int W, int LPM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_condense_f32(
     DevPlan P, int e0, int32_t *status, float *S, double *g, float *Y, double *z, float *fac) {
-  condense_body<float, true, W>(P, e0, blockIdx.x, status, S, g, Y, z, nullptr, fac);
+  condense_body<float, LPM, W>(P, e0, blockIdx.x, status, S, g, Y, z, nullptr, fac);
 }
 
 // Condensation of a batch of plans (element types / orders with uneven n, k), in two launches
@@ -1825,23 +1874,31 @@ hipError_t launch_condense(const DevPlan &P, int e0, int ec, int32_t *status, do
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
-                              double *z, float *fac, hipStream_t s) {
+template <int LPM>
+hipError_t launch_condense_lp_t(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
+                                double *z, float *fac, hipStream_t s) {
   const size_t lds = condense_lds_bytes_lp(P.n_pad, P.cw_lp);
   if (P.condense_launches == 2 && (P.cw_lp == 32 || P.cw_lp == 16)) {
     hipError_t e;
     if (P.cw_lp == 32) {
-      e = launch_dyn(k_lu_f32<32>, ec, lds, s, P, e0, status, fac);
-      if (!e) e = launch_dyn(k_rhs_f32<32>, rhs_grid(P, ec, 32), lds, s, P, e0, ec, S, g, Y, z, fac);
+      e = launch_dyn(k_lu_f32<32, LPM>, ec, lds, s, P, e0, status, fac);
+      if (!e) e = launch_dyn(k_rhs_f32<32, LPM>, rhs_grid(P, ec, 32), lds, s, P, e0, ec, S, g, Y, z, fac);
     } else {
-      e = launch_dyn(k_lu_f32<16>, ec, lds, s, P, e0, status, fac);
-      if (!e) e = launch_dyn(k_rhs_f32<16>, rhs_grid(P, ec, 16), lds, s, P, e0, ec, S, g, Y, z, fac);
+      e = launch_dyn(k_lu_f32<16, LPM>, ec, lds, s, P, e0, status, fac);
+      if (!e) e = launch_dyn(k_rhs_f32<16, LPM>, rhs_grid(P, ec, 16), lds, s, P, e0, ec, S, g, Y, z, fac);
     }
     return e;
   }
-  if (P.cw_lp == 32) return launch_dyn(k_condense_f32<32>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
-  if (P.cw_lp == 16) return launch_dyn(k_condense_f32<16>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
+  if (P.cw_lp == 32) return launch_dyn(k_condense_f32<32, LPM>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
+  if (P.cw_lp == 16) return launch_dyn(k_condense_f32<16, LPM>, ec, lds, s, P, e0, status, S, g, Y, z, fac);
   return hipErrorInvalidValue;
+}
+
+// FP32 or (P.lp_bf16) BF16 operands on the matrix cores
+hipError_t launch_condense_lp(const DevPlan &P, int e0, int ec, int32_t *status, float *S, double *g, float *Y,
+                              double *z, float *fac, hipStream_t s) {
+  if (P.lp_bf16) return launch_condense_lp_t<2>(P, e0, ec, status, S, g, Y, z, fac, s);
+  return launch_condense_lp_t<1>(P, e0, ec, status, S, g, Y, z, fac, s);
 }
 
 size_t batch_item_args_bytes() { return sizeof(BatchItemArgs); }

@@ -318,6 +318,7 @@ extern "C" int hdg_plan_create(hdg_plan **out, const hdg_mesh *mesh, const hdg_p
   D.condense_launches = 2;
   D.lu_waves = default_lu_waves(D.n_pad);
   D.lu_waves_set = 0;
+  D.lp_bf16 = 0;
   P->fused = D.cw != 0;
   if (opts && (opts->flags & HDG_FLAG_SPLIT_DENSE)) P->fused = false;
   P->split_ok = lu_lds_bytes(D.n_pad) <= 160 * 1024;

@@ -30,8 +30,9 @@ struct DevPlan {
                            // 2 sigma_MV (mean value between v_hat and v)
   int condense_launches;   // 1: fused condensation; 2: LU, then one workgroup per right-hand-side block
   int lu_waves;            // LU of the two-launch FP64 condensation: 0 working block in LDS (k_lu_f64_w32),
-                           // 4 or 8: in the registers of that many waves (k_lu_reg)
+                           // 2, 4 or 8: in the registers of that many waves (k_lu_reg)
   int lu_waves_set;        // 1: lu_waves chosen by hdg_plan_set_tuning (else the default per block size)
+  int lp_bf16;             // low-precision condensation: 0 FP32 operands, 1 BF16 operands (FP32 accumulation)
   double gamma, mu, Pr, alpha;
   const double *src;       // source of the conservation law (device, caller-owned) or null: nodal [m][E*Np],
   int src_qp;              // or (src_qp = 1) its values at the volume quadrature points [m][E*Nq]

@@ -82,9 +82,9 @@ class Plan:
         return {f: getattr(t, f) for f, _ in _lib.hdg_tuning._fields_}
 
     def set_tuning(self, contract_threads=0, condense_width=0, condense_width_lp=0, condense_launches=0,
-                   lu_waves=0):
+                   lu_waves=0, lp_operands=0):
         t = _lib.hdg_tuning(int(contract_threads), int(condense_width), int(condense_width_lp),
-                            int(condense_launches), int(lu_waves))
+                            int(condense_launches), int(lu_waves), int(lp_operands))
         check(self.lib.hdg_plan_set_tuning(self.h, ctypes.byref(t)), "hdg_plan_set_tuning")
 
     def __del__(self):

@@ -242,3 +242,57 @@ def test_element_refinement_falls_back_to_fp64(torch):
     assert info["fallback_elements"] == wl.mesh.n_elem
     assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
     assert err <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["ns3d_hex_p1", "ns3d_hex_p2"])
+def test_bf16_operands_condensation_and_refinement(torch, name):
+    """BF16 operands on the matrix cores (lp_operands = 2; FP32 data, panels and accumulation):
+    S, Y, g, z against the oracle carry BF16-level errors.  To first order an output's error is
+    its condition times the unit roundoff of the operands, so against the FP32 operands' errors
+    on the same blocks it grows by at most the ratio of the unit roundoffs, 2^-9 / 2^-24 = 2^15
+    (asserted with a factor 4 of slack), and by at least 10 (evidence that the BF16 instructions
+    run); S within 5e-2.  FP64 refinement then reaches 1e-10 on the full Newton system and on the
+    element systems, where dx equals the FP64 element back-solve to 1e-9."""
+    wl, disc, inp, blocks = _case(name)
+    print("case", name, flush=True)
+    plan = gpu_plan(wl)
+    d = to_dev(inp)
+    E = wl.mesh.n_elem
+
+    def errs(lp):
+        out = {}
+        for key, mat in (("S", True), ("Y", True), ("g", False), ("z", False)):
+            got = lp[key].cpu().numpy()
+            out[key] = max(np.linalg.norm((got[e].astype(np.float64).T if mat else got[e]) - blocks[e][key]) /
+                           np.linalg.norm(blocks[e][key]) for e in range(E))
+        return out
+
+    plan.set_tuning(lp_operands=1)
+    e32 = errs(plan.assemble_condense_lp(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"]))
+    plan.set_tuning(lp_operands=2)
+    assert plan.tuning()["lp_operands"] == 2
+    lp = plan.assemble_condense_lp(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    torch.cuda.synchronize()
+    assert int(lp["status"].abs().max()) == 0
+    ebf = errs(lp)
+    print(name, "FP32 operands", e32, "BF16 operands", ebf, flush=True)
+    assert ebf["S"] <= 5e-2, ebf["S"]
+    for key in ("S", "Y", "g", "z"):
+        assert 10 * e32[key] <= ebf[key] <= 4 * 2.0 ** 15 * e32[key], (key, ebf[key], e32[key])
+    dx, dlam, info = plan.refine_solve(d["v"], d["q"], d["vhat"], lp, ustar=d["ustar"], vbc=d["vbc"], tol=1e-10,
+                                       max_outer=16, gmres_tol=1e-8)
+    torch.cuda.synchronize()
+    print(name, "BF16 full-system refinement", info, flush=True)
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    f64 = plan.assemble_condense(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
+    rng = np.random.default_rng(47)
+    dl = torch.from_numpy(1e-3 * rng.standard_normal((disc.m, wl.n_trace)) * np.abs(inp["vhat"])).cuda()
+    dxl, linfo = plan.refine_local(d["v"], d["q"], d["vhat"], lp, dl, ustar=d["ustar"], vbc=d["vbc"], tol=1e-10,
+                                   max_iter=12)
+    dx64 = plan.backsolve_elements(f64["Y"], f64["z"], dl)
+    torch.cuda.synchronize()
+    err = float(torch.linalg.norm(dxl - dx64) / torch.linalg.norm(dx64))
+    print(name, "BF16 element refinement", linfo, "dx vs FP64 back-solve", err, flush=True)
+    assert linfo["converged"] == 1 and linfo["rel_residual"] <= 1e-10
+    assert linfo["fallback_elements"] == 0
+    assert err <= 1e-9
