@@ -244,18 +244,21 @@ def test_element_refinement_falls_back_to_fp64(torch):
     assert err <= 1e-9
 
 
-@pytest.mark.parametrize("name", ["ns3d_hex_p1", "ns3d_hex_p2"])
-def test_bf16_operands_condensation_and_refinement(torch, name):
+@pytest.mark.parametrize("name,narrow", [("ns3d_hex_p1", False), ("ns3d_hex_p2", False), ("ns3d_hex_p2", True)])
+def test_bf16_operands_condensation_and_refinement(torch, name, narrow):
     """BF16 operands on the matrix cores (lp_operands = 2; FP32 data, panels and accumulation):
     S, Y, g, z against the oracle carry BF16-level errors.  To first order an output's error is
     its condition times the unit roundoff of the operands, so against the FP32 operands' errors
     on the same blocks it grows by at most the ratio of the unit roundoffs, 2^-9 / 2^-24 = 2^15
     (asserted with a factor 4 of slack), and by at least 10 (evidence that the BF16 instructions
     run); S within 5e-2.  FP64 refinement then reaches 1e-10 on the full Newton system and on the
-    element systems, where dx equals the FP64 element back-solve to 1e-9."""
+    element systems, where dx equals the FP64 element back-solve to 1e-9.  narrow: 16-column
+    panels (one 16x16x16 BF16 instruction per k-panel instead of 16x16x32)."""
     wl, disc, inp, blocks = _case(name)
-    print("case", name, flush=True)
-    plan = gpu_plan(wl)
+    print("case", name, "narrow", narrow, flush=True)
+    plan = gpu_plan(wl, narrow_block=narrow)
+    if narrow:
+        assert plan.tuning()["condense_width_lp"] == 16
     d = to_dev(inp)
     E = wl.mesh.n_elem
 
