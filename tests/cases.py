@@ -92,6 +92,11 @@ def residual_term_scale(disc, e, x, lam, ustar=None):
     bounded by eps times this sum of magnitudes, so parity of R_loc is stated
     relative to it.
     """
+    return float(np.linalg.norm(residual_term_magnitudes(disc, e, x, lam, ustar)))
+
+
+def residual_term_magnitudes(disc, e, x, lam, ustar=None):
+    """Per row of R_loc, the sum of its quadrature contributions in absolute value."""
     from oracle import physics as ph
     G = disc.geom(e)
     m, d, Np, Nfp, nf = disc.m, disc.d, disc.Np, disc.Nfp, disc.nf
@@ -126,7 +131,7 @@ def residual_term_scale(disc, e, x, lam, ustar=None):
     out = Tv.reshape(-1)
     if P.viscous:
         out = np.concatenate([out, Tq.reshape(-1)])
-    return float(np.linalg.norm(out))
+    return out
 
 
 def rloc_err(disc, inp, gpu_R, ref_R):
@@ -149,3 +154,36 @@ def z_backward_err(disc, inp, e, A, R_loc, z_gpu):
     x, lam, us, _ = disc.elem_inputs(e, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
     s = residual_term_scale(disc, e, x, lam, us)
     return float(np.linalg.norm(A @ z_gpu - R_loc)) / s
+
+
+def z_forward_bound(disc, inp, e, A, R_loc, z):
+    """Forward-error bound of z = A^-1 R_loc for element e, derived from the element's own data.
+
+    Both codes form R_loc with a componentwise rounding error of at most about m eps t, t the
+    per-row sum of magnitudes of its m quadrature contributions (residual_term_magnitudes), and
+    solve with LU and partial pivoting, whose backward error is componentwise at most about
+    3 n eps |A| (for moderate growth).  To first order the two solutions then differ by at most
+        eps (2 * 3n |A^-1| |A| |z| + 2 m |A^-1| t)
+    per component (Skeel's componentwise condition, insensitive to the row and column scaling
+    that makes the normwise kappa(A) large on these blocks).  Returned relative to ||z||."""
+    x, lam, us, _ = disc.elem_inputs(e, inp["v"], inp["q"], inp["vhat"], inp["ustar"], inp["vbc"])
+    t = residual_term_magnitudes(disc, e, x, lam, us)
+    n = A.shape[0]
+    m = disc.ref.phi.shape[0] + disc.nf * disc.geom(e).faces[0]["W"].shape[0]
+    Ai = np.abs(np.linalg.inv(A))
+    dz = np.finfo(float).eps * (6 * n * (Ai @ (np.abs(A) @ np.abs(z))) + 2 * m * (Ai @ t))
+    return float(np.linalg.norm(dz) / np.linalg.norm(z))
+
+
+def z_forward_report(disc, inp, elems, A, R_loc, z_ref, z_gpu):
+    """Forward errors ||z_gpu - z_oracle|| / ||z_oracle|| of the given elements and their ratios to
+    the elements' derived bounds (z_forward_bound).  Returns (largest error, largest ratio) and
+    prints the distribution."""
+    errs, ratios = [], []
+    for e, a, r, zr, zg in zip(elems, A, R_loc, z_ref, z_gpu):
+        err = float(np.linalg.norm(zg - zr) / np.linalg.norm(zr))
+        errs.append(err)
+        ratios.append(err / z_forward_bound(disc, inp, e, a, r, zr))
+    print("z forward error: max %.2e median %.2e; error / derived bound: max %.2e median %.2e"
+          % (max(errs), float(np.median(errs)), max(ratios), float(np.median(ratios))))
+    return max(errs), max(ratios)

@@ -4,7 +4,8 @@ oracle on sampled elements (first, last and seeded random ones).
 
 S, Y, g, R_tr: relative Frobenius error <= 1e-12.  z: backward error
 ||A z_gpu - R_loc|| <= 1e-12 times the summation scale of R_loc, and forward
-relative error <= 1e-11 (see cases.z_backward_err)."""
+relative error <= 1e-11 and within the element's derived first-order bound
+(see cases.z_backward_err, cases.z_forward_bound)."""
 import numpy as np
 import pytest
 
@@ -12,7 +13,7 @@ from oracle import hdg as ohdg
 from oracle import state as ostate
 from workloads import configs as C
 
-from cases import gpu_plan, oracle_disc, z_backward_err
+from cases import gpu_plan, oracle_disc, z_backward_err, z_forward_report
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -55,8 +56,8 @@ def check_sampled(disc, inp, out, sample, ref):
     for e, r in zip(sample, ref):
         errs = {}
         zg = out["z"][e].cpu().numpy()
-        zf = np.linalg.norm(zg - r["z"]) / np.linalg.norm(r["z"])
-        assert zf <= 1e-11, (e, zf)
+        zf, zr = z_forward_report(disc, inp, [e], [r["A"]], [r["R_loc"]], [r["z"]], [zg])
+        assert zf <= 1e-11 and zr <= 1.0, (e, zf, zr)
         errs["z_backward"] = z_backward_err(disc, inp, e, r["A"], r["R_loc"], zg)
         for key, mat in (("S", True), ("Y", True), ("g", False)):
             got = out[key][e].cpu().numpy()
