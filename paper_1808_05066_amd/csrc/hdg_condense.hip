@@ -1049,6 +1049,15 @@ __global__ __launch_bounds__(NT_RHS) void k_rhs_f64_w32(DevPlan P, int e0, int e
   rhs_body<double, false, 32, NT_RHS>(P, e0, ec, S, g, Y, z, inv, nullptr);
 }
 
+// Small blocks (two or more working blocks fit in a CU's LDS): 4 waves per workgroup, so that
+// the workgroups of several (element, block) items share a CU instead of one item's 16 waves
+// outnumbering its row tiles.  Same arithmetic in the same order as k_rhs_f64_w32.
+constexpr int NT_RHS_SMALL = 256;
+__global__ __launch_bounds__(NT_RHS_SMALL) void k_rhs_f64_w32_small(DevPlan P, int e0, int ec, double *S, double *g,
+                                                                    double *Y, double *z, double *inv) {
+  rhs_body<double, false, 32, NT_RHS_SMALL>(P, e0, ec, S, g, Y, z, inv, nullptr);
+}
+
 // 16-column blocks (a 32-column block of n_pad > 704 rows does not fit in LDS): the LU, then one
 // workgroup per (element, 16-column block), the blocks of an element on one XCD
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_lu_f64_w16(DevPlan P, int e0,
@@ -1852,8 +1861,16 @@ hipError_t launch_condense_lu(const DevPlan &P, int e0, int ec, int32_t *status,
   return launch_dyn(k_lu_f64_w32, ec, condense_lds_bytes(P.n_pad, 32), s, P, e0, status, P.inv);
 }
 
+// 32-column right-hand sides with 4-wave workgroups where at least two working blocks fit in a
+// CU's 160 KB of LDS (at n_pad = 160, 32,768 elements: 39.9 ms against 47.8 ms with 16 waves;
+// at n_pad = 96: 0.68 against 1.10 ms per 5,062 elements; 8 waves were slower than either)
+static bool rhs_small(const DevPlan &P) { return 2 * condense_lds_bytes(P.n_pad, 32) <= 160 * 1024; }
+
 hipError_t launch_condense_rhs(const DevPlan &P, int e0, int ec, double *S, double *g, double *Y, double *z,
                                hipStream_t s) {
+  if (P.cw == 32 && rhs_small(P))
+    return launch_dyn_t(k_rhs_f64_w32_small, rhs_grid(P, ec, 32), NT_RHS_SMALL, condense_lds_bytes(P.n_pad, 32), s, P,
+                        e0, ec, S, g, Y, z, P.inv);
   if (P.cw == 16)
     return launch_dyn_t(k_rhs_f64_w16, rhs_grid(P, ec, 16), NT_RHS, condense_lds_bytes(P.n_pad, 16), s, P, e0, ec, S,
                         g, Y, z, P.inv);
