@@ -249,22 +249,36 @@ __global__ __launch_bounds__(NTH) void k_contract_mfma(DevPlan P, int e0, int ec
     __syncthreads();
     for (int j0 = 0; j0 <= D; j0 += JG) {
       const int nj = (D + 1 - j0) < JG ? (D + 1 - j0) : JG;
-      for (int t = tid; t < nj * Np * Np; t += NT) {
-        const int b = t % Np, a = (t / Np) % Np, j = j0 + t / (Np * Np);
-        double acc = 0.0;
-        if (j < D) {
-#pragma unroll 4
-          for (int qp = 0; qp < Nq; ++qp) {
-            double ta = 0.0;
+      // G_j = U_j Phi on the matrix cores, U_j[a][qp] = sum_r W J_rj dphi_r,a(qp) (j < D) or
+      // W phi_a(qp) (the mass matrix, j = D), Phi[qp][b] = phi_b(qp): one 16 x 16 output tile
+      // (a, b) per wave, K = N_q in steps of 4 points; lane (li, lk) forms the A operand
+      // U_j[16 ta + li][q0 + lk] and reads the B operand phi_{16 tb + li}(q0 + lk), and holds
+      // rows 16 ta + lk + 4 r of the result (padding rows, columns and points are zero)
+      for (int tt = wave; tt < nj * NCT * NCT; tt += NT / 64) {
+        const int jl = tt / (NCT * NCT), ta = (tt / NCT) % NCT, tb = tt % NCT;
+        const int j = j0 + jl, a = 16 * ta + li, b = 16 * tb + li;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int q0 = 0; q0 < Nq; q0 += 4) {
+          const int qp = q0 + lk;
+          double u = 0.0, v = 0.0;
+          if (qp < Nq) {
+            if (a < Np) {
+              if (j < D) {
 #pragma unroll
-            for (int r = 0; r < D; ++r) ta += swj[qp * DW + r * D + j] * DPHI(r, qp, a);
-            acc += ta * PHI(qp, b);
+                for (int r = 0; r < D; ++r) u += swj[qp * DW + r * D + j] * DPHI(r, qp, a);
+              } else {
+                u = swj[qp * DW + D * D] * PHI(qp, a);
+              }
+            }
+            if (b < Np) v = PHI(qp, b);
           }
-        } else {
-#pragma unroll 4
-          for (int qp = 0; qp < Nq; ++qp) acc += swj[qp * DW + D * D] * PHI(qp, a) * PHI(qp, b);
+          acc = mfma4(u, v, acc);
         }
-        gm[t] = acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ar = 16 * ta + lk + 4 * r;
+          if (ar < Np && b < Np) gm[(jl * Np + ar) * Np + b] = acc[r];
+        }
       }
       __syncthreads();
       // the compact copy the condensation forms the q rows of A from
