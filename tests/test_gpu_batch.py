@@ -184,3 +184,23 @@ def test_tuning_changes_only_the_launch_shape(torch, groups):
         assert torch.equal(lp[1][key], lp[2][key]), ("fp32", key)
         assert torch.equal(lp[1]["f64"][key], lp[2]["f64"][key]), ("fp64", key)
     plan.set_tuning(**t0)
+
+
+def test_batch_mode_arguments_are_checked(torch, groups):
+    """hdg_batch_set_streams takes 0..8 and hdg_batch_set_groups a non-negative grid: anything else is
+    HDG_EINVAL, and the batch still runs afterwards."""
+    from paper_1808_05066_amd.hdg import Batch
+    b = Batch([g["plan"] for g in groups])
+    for bad in (-1, 9):
+        with pytest.raises(RuntimeError):
+            b.set_streams(bad)
+    with pytest.raises(RuntimeError):
+        b.set_groups(-1)
+    b.set_streams(2)
+    b.set_streams(0)
+    b.set_groups(0)
+    io = _io(groups, torch)
+    b.set_io(io)
+    b.run()
+    torch.cuda.synchronize()
+    assert all(int(o["status"].abs().max()) == 0 for o in io)
