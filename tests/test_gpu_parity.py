@@ -50,11 +50,16 @@ def _case(name):
     return _cache[name]
 
 
-@pytest.mark.parametrize("name", list(SMALL_CASES))
-def test_assemble_blocks_match_oracle(torch, name):
+@pytest.mark.parametrize("name,ct", [(c, 1024) for c in SMALL_CASES] +
+                         [(c, t) for c in ("ns2d_tri_p2", "ns3d_hex_p1", "ns3d_hex_p2", "euler3d_hex_p2")
+                          for t in (256, 512)])
+def test_assemble_blocks_match_oracle(torch, name, ct):
+    """Every block of the element against the oracle, at each workgroup size of the block
+    contraction (each size is its own kernel instantiation)."""
     wl, disc, inp, blocks = _case(name)
-    print("case", name, flush=True)
+    print("case", name, "contract_threads", ct, flush=True)
     plan = gpu_plan(wl)
+    plan.set_tuning(contract_threads=ct)
     d = to_dev(inp)
     out = plan.assemble(d["v"], d["q"], d["vhat"], d["ustar"], d["vbc"])
     torch.cuda.synchronize()
